@@ -1,0 +1,197 @@
+"""CPU oracle for the string-network evolver -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package. The product library (libsemipar) never
+loads it. It shares no code with the HIP path: the C source ``oracle.c`` is
+compiled by gcc with ``-O2 -ffp-contract=off`` and driven through ctypes.
+
+Record and event layouts are restated here (they are the data format of the
+initial and final surfaces, not shared code).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "oracle.c")
+LIB = os.path.join(_HERE, "liboracle.so")
+
+REC = np.dtype([
+    ("id", "<i8"), ("next_id", "<i8"), ("prev_id", "<i8"),
+    ("step", "<i4"), ("flags", "<i4"),
+    ("x", "<f8", (4,)), ("x_prev", "<f8", (4,)),
+    ("r", "<f8", (4,)), ("r_prev", "<f8", (4,)),
+])
+EVT = np.dtype([
+    ("step", "<i4"), ("kind", "<i4"), ("id_a", "<i8"), ("id_b", "<i8"),
+    ("t_star", "<f8"), ("x_star", "<f8", (3,)),
+])
+
+GRID, BRUTE = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, OpenMP for the per-point loops)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.orc_create.argtypes = [P, i64, dbl, ctypes.c_int, dbl, ctypes.POINTER(P)]
+        L.orc_create.restype = ctypes.c_int
+        L.orc_evolve.argtypes = [P, i64, dbl, ctypes.c_int, ctypes.c_int]
+        L.orc_evolve.restype = ctypes.c_int
+        L.orc_destroy.argtypes = [P]
+        L.orc_destroy.restype = None
+        L.orc_n.argtypes = [P]
+        L.orc_n.restype = i64
+        L.orc_step.argtypes = [P]
+        L.orc_step.restype = i32
+        L.orc_event_count.argtypes = [P]
+        L.orc_event_count.restype = i64
+        L.orc_events.argtypes = [P, P]
+        L.orc_events.restype = ctypes.c_int
+        L.orc_read.argtypes = [P, P]
+        L.orc_read.restype = ctypes.c_int
+        L.orc_stats.argtypes = [P, P]
+        L.orc_stats.restype = None
+        L.orc_band_candidates.argtypes = [P, ctypes.c_int, P, i64]
+        L.orc_band_candidates.restype = i64
+        L.orc_top.argtypes = [ctypes.c_int, dbl, dbl, P, P, P, P]
+        L.orc_top.restype = None
+        L.orc_det4.argtypes = [P, P, P, P]
+        L.orc_det4.restype = dbl
+        L.orc_tri_tri.argtypes = [P, P, P, P, P, P, P, P]
+        L.orc_tri_tri.restype = ctypes.c_int
+        L.orc_last_confirmed.argtypes = [P, P, P, P]
+        L.orc_last_confirmed.restype = i64
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleRegion:
+    """Whole-volume region evolved by the oracle (lockstep lattice, periodic box)."""
+
+    def __init__(self, recs, box, cosmology, hcoef):
+        recs = np.ascontiguousarray(recs, dtype=REC)
+        self._keep = recs
+        h = ctypes.c_void_p()
+        rc = lib().orc_create(_ptr(recs), len(recs), float(box), int(cosmology), float(hcoef),
+                              ctypes.byref(h))
+        if rc != 0:
+            raise ValueError(f"oracle rejected the surface (code {rc})")
+        self.h = h
+
+    def evolve(self, max_steps, t_end=float("inf"), search=GRID, intercommute=True):
+        rc = lib().orc_evolve(self.h, int(max_steps), float(t_end), int(search),
+                              int(bool(intercommute)))
+        if rc != 0:
+            raise RuntimeError(f"oracle evolve failed (code {rc})")
+
+    def read(self):
+        n = lib().orc_n(self.h)
+        out = np.zeros(n, dtype=REC)
+        lib().orc_read(self.h, _ptr(out))
+        return out
+
+    def events(self):
+        n = lib().orc_event_count(self.h)
+        out = np.zeros(n, dtype=EVT)
+        if n:
+            lib().orc_events(self.h, _ptr(out))
+        return out
+
+    def stats(self):
+        s = np.zeros(5, dtype=np.int64)
+        lib().orc_stats(self.h, _ptr(s))
+        return dict(point_steps=int(s[0]), candidates=int(s[1]), confirmed=int(s[2]),
+                    accepted=int(s[3]), steps=int(s[4]))
+
+    def last_confirmed(self):
+        """Confirmed events of the most recent step, sorted by (t*, id_a, id_b)."""
+        n = lib().orc_last_confirmed(self.h, None, None, None)
+        t = np.zeros(max(n, 1)); ids = np.zeros((max(n, 1), 2), np.int64); x = np.zeros((max(n, 1), 3))
+        lib().orc_last_confirmed(self.h, _ptr(t), _ptr(ids), _ptr(x))
+        return t[:n], ids[:n], x[:n]
+
+    @property
+    def step(self):
+        return lib().orc_step(self.h)
+
+    def band_candidates(self, search=GRID):
+        """Exact-overlap candidate id pairs of the current band (no state change)."""
+        n = lib().orc_band_candidates(self.h, int(search), None, 0)
+        out = np.zeros((max(n, 1), 2), dtype=np.int64)
+        lib().orc_band_candidates(self.h, int(search), _ptr(out), n)
+        return out[:n]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run(net, steps, t_end=float("inf"), search=GRID, intercommute=True):
+    """Convenience: evolve a generated network and return (records, events, stats)."""
+    hc = {0: 0.0, 1: 2.0, 2: 1.0}[net["cosmology"]]
+    r = OracleRegion(net["recs"], net["box"], net["cosmology"], hc)
+    r.evolve(steps, t_end, search, intercommute)
+    out = (r.read(), r.events(), r.stats())
+    r.close()
+    return out
+
+
+def top(cosmology, hcoef, box, L, R, B):
+    T = np.zeros(4)
+    Lr, Rr, Br = (np.ascontiguousarray(v, dtype=np.float64) for v in (L, R, B))
+    lib().orc_top(int(cosmology), float(hcoef), float(box), _ptr(Lr), _ptr(Rr), _ptr(Br), _ptr(T))
+    return T
+
+
+def det4(a, b, c, d):
+    a, b, c, d = (np.ascontiguousarray(v, dtype=np.float64) for v in (a, b, c, d))
+    return lib().orc_det4(_ptr(a), _ptr(b), _ptr(c), _ptr(d))
+
+
+def tri_tri(P, Q):
+    """P, Q: 3 x 4 vertex arrays. Returns (hit, t*, X*)."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    t = np.zeros(1)
+    x = np.zeros(3)
+    hit = lib().orc_tri_tri(_ptr(P[0]), _ptr(P[1]), _ptr(P[2]), _ptr(Q[0]), _ptr(Q[1]),
+                            _ptr(Q[2]), _ptr(t), _ptr(x))
+    return bool(hit), float(t[0]), x
+
+
+def threads():
+    return lib().orc_threads()

@@ -1,0 +1,358 @@
+"""Seeded synthetic inputs: initial surfaces of cosmic-string networks.
+
+This module is shared by the HIP path (tests, bench) and by the CPU oracle. It holds
+none of the evolution, intersection or reconnection arithmetic. It only samples
+string shapes and writes them out as initial-surface point records.
+
+Representation (the staggered diamond lattice of the piecewise-linear solution
+x = [a(t - sigma) + b(t + sigma)]/2, Section "Semi-parallel cosmic string
+simulation", equation for x(sigma, t) and the diamond construction that follows):
+
+* A chain of N points is described by samples A_k = a(-k*delta) and
+  B_m = b(m*delta), delta being the sigma spacing.
+* Point k on lattice slice n is the world-sheet vertex X_n[k] = (A_k + B_{k+n})/2,
+  at time t_n = t0 + n*delta/2.
+* The initial surface therefore holds X_0 and X_1. Each record carries X_1 as
+  ``x`` (slice ``step`` = 1) and X_0 as ``x_prev``.
+* A chain that winds the periodic box carries shift vectors: A_{k+N} = A_k + wA
+  and B_{k+N} = B_k + wB. Positions are stored unwrapped along each chain.
+
+Generators:
+
+* :func:`kt_loops`: closed loops with a few Fourier modes, arc-length
+  reparametrized to unit speed (flat-space workload).
+* :func:`vv_network`: a Vachaspati-Vilenkin-style network from random Z3 phases
+  on a periodic cubic lattice, traced through pierced plaquettes, at rest
+  (matter-era workload).
+* :func:`straight_string`, :func:`circular_loop`, :func:`crossing_strings`:
+  analytic shapes used to pin the oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# One point record of an initial or final surface (160 bytes, matches the C ABI).
+REC_DTYPE = np.dtype([
+    ("id", "<i8"), ("next_id", "<i8"), ("prev_id", "<i8"),
+    ("step", "<i4"), ("flags", "<i4"),
+    ("x", "<f8", (4,)), ("x_prev", "<f8", (4,)),
+    ("r", "<f8", (4,)), ("r_prev", "<f8", (4,)),
+])
+assert REC_DTYPE.itemsize == 160
+
+# Event record of the C ABI (56 bytes).
+EVENT_DTYPE = np.dtype([
+    ("step", "<i4"), ("kind", "<i4"), ("id_a", "<i8"), ("id_b", "<i8"),
+    ("t_star", "<f8"), ("x_star", "<f8", (3,)),
+])
+assert EVENT_DTYPE.itemsize == 56
+
+FLAT, MATTER, RADIATION = 0, 1, 2
+# H = HCOEF / eta in conformal time for a ∝ eta^HCOEF (matter: a ∝ eta^2).
+HCOEF = {FLAT: 0.0, MATTER: 2.0, RADIATION: 1.0}
+
+
+class Network(dict):
+    """Initial surface plus the samples it was built from.
+
+    Keys: ``recs`` (REC_DTYPE array), ``box`` (periodic length L), ``delta``,
+    ``t0``, ``cosmology``, ``chains`` (list of dicts with A, B, wA, wB, id0).
+    """
+
+
+def records_from_chains(chains, t0, delta):
+    """Build the initial surface (slices 0 and 1) for a list of chains.
+
+    Each chain is a dict with ``A`` and ``B`` (N x 3 samples), ``wA`` and ``wB``
+    (shift per period; zero for a loop that does not wind the box).
+    """
+    total = sum(len(c["A"]) for c in chains)
+    recs = np.zeros(total, dtype=REC_DTYPE)
+    t1 = t0 + 0.5 * delta
+    base = 0
+    for c in chains:
+        A = np.asarray(c["A"], dtype=np.float64)
+        B = np.asarray(c["B"], dtype=np.float64)
+        n = len(A)
+        Bn = np.concatenate([B[1:], (B[0] + np.asarray(c["wB"], np.float64))[None]], axis=0)
+        x0 = 0.5 * (A + B)
+        x1 = 0.5 * (A + Bn)
+        ids = base + np.arange(n, dtype=np.int64)
+        sl = slice(base, base + n)
+        recs["id"][sl] = ids
+        recs["next_id"][sl] = base + (np.arange(n) + 1) % n
+        recs["prev_id"][sl] = base + (np.arange(n) - 1) % n
+        recs["step"][sl] = 1
+        recs["x"][sl, :3] = x1
+        recs["x"][sl, 3] = t1
+        recs["x_prev"][sl, :3] = x0
+        recs["x_prev"][sl, 3] = t0
+        c["id0"] = base
+        base += n
+    return recs
+
+
+# --------------------------------------------------------------------------------------
+# Flat space: closed loops with a few Fourier modes
+# --------------------------------------------------------------------------------------
+
+def _fourier_closed_curve(rng, n_modes, n_pts, dense):
+    """Closed curve sum_m A_m cos(2 pi m s) + B_m sin(2 pi m s), resampled at n_pts
+    equal-arc points after scaling its length to 1 (unit speed in sigma)."""
+    coef = rng.standard_normal((2, n_modes, 3))
+    s = np.arange(dense, dtype=np.float64) / dense
+    m = np.arange(1, n_modes + 1, dtype=np.float64)
+    ph = 2.0 * np.pi * np.outer(s, m)                  # dense x modes
+    C = np.cos(ph) @ coef[0] + np.sin(ph) @ coef[1]     # dense x 3
+    Cc = np.concatenate([C, C[:1]], axis=0)
+    seg = np.linalg.norm(np.diff(Cc, axis=0), axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    total = cum[-1]
+    u = np.arange(n_pts, dtype=np.float64) * (total / n_pts)
+    i = np.clip(np.searchsorted(cum, u, side="right") - 1, 0, dense - 1)
+    f = (u - cum[i]) / np.where(seg[i] > 0, seg[i], 1.0)
+    P = Cc[i] + f[:, None] * (Cc[i + 1] - Cc[i])
+    P = P / total
+    return P - P.mean(axis=0)
+
+
+def kt_loops(n_loops=8, n_pts=256, n_modes=5, box=1.0, seed=0, t0=0.0, dense=1 << 16):
+    """Flat-space workload: closed loops of invariant length 1 in a periodic box.
+
+    Per loop, in this rng order: a-curve coefficients, b-curve coefficients
+    (each 2 x n_modes x 3 iid N(0,1)), loop centre uniform in [0, box)^3.
+    delta = 1/n_pts, so dt = delta/2.
+    """
+    rng = np.random.default_rng(seed)
+    chains = []
+    for _ in range(n_loops):
+        a = _fourier_closed_curve(rng, n_modes, n_pts, dense)
+        b = _fourier_closed_curve(rng, n_modes, n_pts, dense)
+        c = rng.uniform(0.0, box, 3)
+        a = a + c
+        b = b + c
+        k = np.arange(n_pts)
+        A = a[(-k) % n_pts]          # A_k = a(-k delta)
+        B = b[k]                     # B_m = b(m delta)
+        chains.append(dict(A=A, B=B, wA=np.zeros(3), wB=np.zeros(3)))
+    delta = 1.0 / n_pts
+    recs = records_from_chains(chains, t0, delta)
+    return Network(recs=recs, box=float(box), delta=delta, t0=float(t0),
+                   cosmology=FLAT, chains=chains)
+
+
+# --------------------------------------------------------------------------------------
+# Matter era: Vachaspati-Vilenkin-style network from Z3 phases
+# --------------------------------------------------------------------------------------
+
+def _zdiff(a, b):
+    """Minimal Z3 phase difference b - a in {-1, 0, 1} (units of 2 pi / 3)."""
+    return ((b - a + 1) % 3) - 1
+
+
+def vv_faces(phase):
+    """Windings (in {-1,0,1}) of the three families of plaquettes of a periodic lattice.
+
+    Face (axis, i, j, k) is the plaquette at coordinate i (resp. j, k) along ``axis``
+    with the lower corner at site (i, j, k); its normal is +axis and the winding is
+    taken counterclockwise about that normal.
+    """
+    p = phase
+    r = lambda a, ax: np.roll(a, -1, ax)
+    pi, pj, pk = r(p, 0), r(p, 1), r(p, 2)
+    # normal +x: (j,k) -> (j+1,k) -> (j+1,k+1) -> (j,k+1)
+    pjk = r(pj, 2)
+    wx = _zdiff(p, pj) + _zdiff(pj, pjk) + _zdiff(pjk, pk) + _zdiff(pk, p)
+    # normal +y: (k,i) -> (k+1,i) -> (k+1,i+1) -> (k,i+1)
+    pki = r(pk, 0)
+    wy = _zdiff(p, pk) + _zdiff(pk, pki) + _zdiff(pki, pi) + _zdiff(pi, p)
+    # normal +z: (i,j) -> (i+1,j) -> (i+1,j+1) -> (i,j+1)
+    pij = r(pi, 1)
+    wz = _zdiff(p, pi) + _zdiff(pi, pij) + _zdiff(pij, pj) + _zdiff(pj, p)
+    w = np.stack([wx, wy, wz])
+    assert np.all(w % 3 == 0)
+    return w // 3
+
+
+def vv_chains(m, rng, xi=1.0, pts_per_xi=8, jitter=0.15):
+    """Trace strings through pierced plaquettes of an m^3 periodic Z3 lattice.
+
+    Path: face centre -> (cube centre + offset) -> face centre. The offset is drawn
+    per cube traversal, uniform in [-jitter, jitter]^3 * xi, so that the 2 or 3
+    strings crossing one cube do not touch. The closed polyline is sampled every
+    delta = xi/pts_per_xi of arc length from its first face centre; the closing
+    chord is the remainder (< delta). Cubes with 2 or 3 strings pair their entry
+    and exit faces by a seeded random permutation (cubes in index order).
+    rng order: phases, pairings, offsets (tracing order).
+    Returns a list of (P, winding) with P the unwrapped points (n x 3).
+    """
+    phase = rng.integers(0, 3, size=(m, m, m))
+    w = vv_faces(phase)
+    M3 = m * m * m
+    fid = lambda ax, i, j, k: ax * M3 + ((i % m) * m + (j % m)) * m + (k % m)
+    succ = {}
+    for i in range(m):
+        for j in range(m):
+            for k in range(m):
+                ins, outs = [], []
+                for ax in range(3):
+                    lo = (i, j, k)
+                    hi = [i, j, k]
+                    hi[ax] += 1
+                    wl = w[ax, lo[0] % m, lo[1] % m, lo[2] % m]
+                    wh = w[ax, hi[0] % m, hi[1] % m, hi[2] % m]
+                    if wl == 1:
+                        ins.append(fid(ax, *lo))
+                    elif wl == -1:
+                        outs.append((fid(ax, *lo), ax, -1))
+                    if wh == -1:
+                        ins.append(fid(ax, *hi))
+                    elif wh == 1:
+                        outs.append((fid(ax, *hi), ax, +1))
+                assert len(ins) == len(outs)
+                if len(ins) == 0:
+                    continue
+                perm = rng.permutation(len(outs)) if len(outs) > 1 else [0]
+                for a, f in enumerate(ins):
+                    succ[f] = outs[perm[a]]
+
+    def face_centre(f):
+        ax, rest = divmod(f, M3)
+        i, rest = divmod(rest, m * m)
+        j, k = divmod(rest, m)
+        c = np.array([i + 0.5, j + 0.5, k + 0.5])
+        c[ax] -= 0.5
+        return c
+
+    def flux_dir(f):
+        ax = f // M3
+        a = f % M3
+        i, rest = divmod(a, m * m)
+        j, k = divmod(rest, m)
+        d = np.zeros(3)
+        d[ax] = float(w[ax, i, j, k])
+        return d
+
+    delta = 1.0 / pts_per_xi
+    chains = []
+    visited = set()
+    for f0 in sorted(succ.keys()):
+        if f0 in visited:
+            continue
+        F = face_centre(f0)
+        start = F.copy()
+        din = flux_dir(f0)
+        verts = [F.copy()]
+        f = f0
+        while True:
+            visited.add(f)
+            nf, ax, sgn = succ[f]
+            dout = np.zeros(3)
+            dout[ax] = float(sgn)
+            C = F + 0.5 * din
+            verts.append(C + rng.uniform(-jitter, jitter, 3))
+            F = C + 0.5 * dout
+            verts.append(F.copy())
+            din = dout
+            f = nf
+            if f == f0:
+                break
+        V = np.array(verts)                      # closed: V[-1] = V[0] + m * winding
+        seg = np.linalg.norm(np.diff(V, axis=0), axis=1)
+        cum = np.concatenate([[0.0], np.cumsum(seg)])
+        n = int(np.floor(cum[-1] / delta))
+        if cum[-1] - n * delta < 1e-9:
+            n -= 1
+        u = np.arange(n + 1, dtype=np.float64) * delta
+        i = np.clip(np.searchsorted(cum, u, side="right") - 1, 0, len(seg) - 1)
+        fr = (u - cum[i]) / seg[i]
+        P = V[i] + fr[:, None] * (V[i + 1] - V[i])
+        wind = np.rint((V[-1] - start) / m).astype(np.int64)
+        chains.append((P * xi, wind))
+    return chains
+
+
+def vv_network(m=32, xi=1.0, pts_per_xi=8, seed=0, t0=8.0, cosmology=MATTER, jitter=0.15):
+    """Matter-era workload: a VV-style network at rest in a periodic box L = m*xi.
+
+    Zero initial velocity: a(-sigma) = b(sigma) = x0(sigma), i.e. A = B = P.
+    delta = xi / pts_per_xi. Ids are chain-major in tracing order.
+    A jitter of 0 gives the undisplaced face-centre / cube-centre path.
+    """
+    rng = np.random.default_rng(seed)
+    L = m * xi
+    raw = vv_chains(m, rng, xi, pts_per_xi, jitter)
+    chains = []
+    for P, wind in raw:
+        wv = wind.astype(np.float64) * L
+        chains.append(dict(A=P, B=P, wA=wv, wB=wv))
+    delta = xi / pts_per_xi
+    recs = records_from_chains(chains, t0, delta)
+    return Network(recs=recs, box=float(L), delta=delta, t0=float(t0),
+                   cosmology=cosmology, chains=chains)
+
+
+# --------------------------------------------------------------------------------------
+# Analytic shapes
+# --------------------------------------------------------------------------------------
+
+def straight_string(n_pts, box, v=0.0, origin=(0.0, 0.0, 0.0), axis=0, vdir=1):
+    """A straight string along ``axis`` winding the box once, moving with speed v
+    along ``vdir``. x(sigma,t) = sigma*sqrt(1-v^2) e_axis + v t e_vdir, hence
+    a(u) = -u*sqrt(1-v^2) e_axis + v u e_vdir and b(u) = u*sqrt(1-v^2) e_axis + v u e_vdir.
+    delta = box / (n_pts*sqrt(1-v^2)), so the chain closes on the box period."""
+    g = np.sqrt(1.0 - v * v)
+    delta = box / (n_pts * g)
+    k = np.arange(n_pts, dtype=np.float64)
+    ea = np.zeros(3); ea[axis] = 1.0
+    ev = np.zeros(3); ev[vdir] = 1.0
+    o = np.asarray(origin, np.float64)
+    # A_k = a(-k delta), B_m = b(m delta)
+    A = o + np.outer(k * delta * g, ea) + np.outer(-v * k * delta, ev)
+    B = o + np.outer(k * delta * g, ea) + np.outer(v * k * delta, ev)
+    wA = n_pts * delta * g * ea - v * n_pts * delta * ev
+    wB = n_pts * delta * g * ea + v * n_pts * delta * ev
+    return dict(A=A, B=B, wA=wA, wB=wB), delta
+
+
+def circular_loop(n_pts, radius, centre=(0.0, 0.0, 0.0)):
+    """A static regular polygon inscribed in a circle (A = B = P, zero velocity).
+    The sigma spacing is the chord length, so the lattice edges are null."""
+    th = 2.0 * np.pi * np.arange(n_pts) / n_pts
+    P = np.asarray(centre, np.float64) + radius * np.stack([np.cos(th), np.sin(th), np.zeros(n_pts)], 1)
+    delta = 2.0 * radius * np.sin(np.pi / n_pts)
+    return dict(A=P, B=P, wA=np.zeros(3), wB=np.zeros(3)), delta
+
+
+def make_network(chains, box, delta, t0, cosmology):
+    recs = records_from_chains(chains, t0, delta)
+    return Network(recs=recs, box=float(box), delta=float(delta), t0=float(t0),
+                   cosmology=cosmology, chains=chains)
+
+
+def crossing_strings(n_pts=64, box=1.0, v=0.5, y0=0.1, x0=0.30078125, z_off=0.0057):
+    """Two straight strings in flat space whose world sheets meet at one point.
+
+    String 1 lies along x at rest through (., 0, 0). String 2 lies along z through
+    (x0, y0, .) moving with speed v in -y. They cross at t* = y0/v at X* = (x0, 0, 0).
+    """
+    s1, d1 = straight_string(n_pts, box, v=0.0, origin=(0.0, 0.0, 0.0), axis=0, vdir=1)
+    g = np.sqrt(1.0 - v * v)
+    # string 2 must share the same delta: choose its point count so that it closes
+    n2 = int(round(box / (d1 * g)))
+    # pick v so that n2 * d1 * g == box exactly as far as possible: recompute g from n2
+    g2 = box / (n2 * d1)
+    v2 = np.sqrt(1.0 - g2 * g2)
+    k = np.arange(n2, dtype=np.float64)
+    ez = np.array([0.0, 0.0, 1.0]); ey = np.array([0.0, 1.0, 0.0])
+    o = np.array([x0, y0, z_off])
+    A = o + np.outer(k * d1 * g2, ez) + np.outer(v2 * k * d1, ey)
+    B = o + np.outer(k * d1 * g2, ez) - np.outer(v2 * k * d1, ey)
+    wA = n2 * d1 * g2 * ez + v2 * n2 * d1 * ey
+    wB = n2 * d1 * g2 * ez - v2 * n2 * d1 * ey
+    s2 = dict(A=A, B=B, wA=wA, wB=wB)
+    net = make_network([s1, s2], box, d1, 0.0, FLAT)
+    net["v2"] = v2
+    net["t_star"] = y0 / v2
+    net["x_star"] = np.array([x0, 0.0, 0.0])
+    return net
