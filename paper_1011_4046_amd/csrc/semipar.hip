@@ -1,0 +1,1669 @@
+// semipar.hip -- libsemipar: evolution of one globally hyperbolic region of a
+// cosmic-string network on an MI355X (gfx950).
+//
+// Paper: Blanco-Pillado, Olum, Shlaer, "A new parallel simulation technique",
+// Section "Semi-parallel cosmic string simulation": construct all diamonds of the
+// world sheet, look for intersections between different pieces of string, and
+// reconnect the strings at the intersections.
+//
+// One lattice step n of a whole-volume region is six kernels on one stream:
+//   k_evolve      diamond tops X[n+1] (flat or first-order FRW) fused with the
+//                 element of band n (vertices, FP64 box, cell, bucket count)
+//   k_scan        exclusive scan of bucket counts (counts reset to 0)
+//   k_scatter     cell-sorted copies of element cell, slot and screen box
+//   k_screen      half-shell bounding-box screen (FP64 or FP32) -> candidate pairs
+//   k_confirm     exact FP64 box overlap + four triangle pairs -> events
+//   k_resolve     one event per element by iterated local minima of (t*, id_a, id_b),
+//                 partner exchange, event log, step bookkeeping (one workgroup)
+// A device control block carries the step index, the stop rule and the counters,
+// so a block of steps can be issued (or graph-replayed) without host round trips.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <type_traits>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "semipar.h"
+#include "geom.h"
+
+#pragma clang fp contract(off)
+
+using sp::Box4;
+using sp::Elem;
+using sp::V4;
+
+namespace {
+
+constexpr int TS_LOG = 12;  // buckets per scan tile = 4096
+constexpr int TS = 1 << TS_LOG;
+constexpr int NT = 256;        // threads per block of the per-point kernels
+constexpr int RESOLVE_NT = 1024;
+constexpr uint64_t KEY_MAX = ~0ull;
+
+// ---------------------------------------------------------------------------------
+// device data
+// ---------------------------------------------------------------------------------
+// Cell grid of the current step (chosen at the end of the previous step).
+struct Cells {
+  int32_t nc;      // cells per dimension (>= 3), 0 = every element is large
+  int32_t fixed;   // 1: keep this grid; 0: follow the largest element of each step
+  double h;        // cell edge = box / nc
+  double inv_h;    // 1 / h
+  double hlim;     // elements with a larger spatial extent are large
+  float h32;       // h in FP32
+  float marg32;    // slack of FP32 spatial comparisons
+};
+
+struct Ctrl {
+  int32_t step;        // lattice index of the current slice
+  int32_t step_limit;  // a step is taken only while step < step_limit
+  int32_t done;        // set: every kernel of a step returns at once
+  int32_t defer;       // step not taken: 1 candidates, 2 events, 4 log overflowed
+  int32_t n_cand;      // candidate appends this step (may exceed the buffer)
+  int32_t n_evt;       // confirmed crossings this step (may exceed the buffer)
+  int32_t n_large;     // elements of this step outside the hash
+  int32_t stamp;       // resolve iteration stamp
+  uint64_t tmin_key;   // order key of the smallest t of the slice being written
+  double t_end;
+  int64_t point_steps, cand_total, conf_total, acc_total, large_total, steps_taken;
+  int64_t log_n;
+  int64_t n_points;
+  int32_t err;
+  int32_t pad;
+  uint64_t ext_key;    // init: order key of an element-size estimate
+  Cells cells;         // grid of the current step
+  double box;          // periodic length (for the grid choice)
+  double grow;         // next cell = grow * largest element extent of this step
+  double tol;          // slack of FP64 spatial comparisons
+};
+
+struct Slices {
+  double* p[3][4];  // [slice mod 3][x, y, z, t]
+};
+
+struct EvCand {
+  double t;
+  int64_t ida, idb;
+  int32_t sa, sb;
+  double x, y, z;
+};
+
+struct LargeBox {
+  double wl[3];   // wrapped lower corner
+  double ext[3];  // extents
+  double tlo, thi;
+  int32_t slot;
+  int32_t pad;
+};
+
+struct HashCfg {   // fixed for a configuration
+  uint32_t bmask;  // buckets - 1
+  int32_t B;       // buckets (power of two, >= TS)
+  double tol;      // slack of FP64 spatial comparisons
+  double tolL;     // slack of the large-element (wrapped) comparisons
+  double tref;     // time origin of FP32 boxes
+  double tol_t;    // slack of FP32 time conversion
+};
+
+__device__ __forceinline__ V4 ld(const Slices& X, int s, int k) {
+  return V4{X.p[s][0][k], X.p[s][1][k], X.p[s][2][k], X.p[s][3][k]};
+}
+__device__ __forceinline__ void st(const Slices& X, int s, int k, const V4& v) {
+  X.p[s][0][k] = v.x;
+  X.p[s][1][k] = v.y;
+  X.p[s][2][k] = v.z;
+  X.p[s][3][k] = v.t;
+}
+
+__host__ __device__ __forceinline__ uint64_t order_key(double v) {
+  uint64_t b;
+  memcpy(&b, &v, 8);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double from_key(uint64_t k) {
+  uint64_t b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  double v;
+  memcpy(&v, &b, 8);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t pack_cell(int x, int y, int z) {
+  return (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+}
+
+// Bucket of a cell: its row-major index modulo the (power-of-two) bucket count. Cells
+// adjacent in z map to adjacent buckets, so the lists a wave reads are close in memory;
+// when nc^3 <= buckets every cell has a bucket of its own.
+__device__ __forceinline__ uint32_t bucket_of(int nc, uint32_t bmask, int x, int y, int z) {
+  return (uint32_t)((x * nc + y) * nc + z) & bmask;
+}
+
+// Exclusive scan of the tile totals into LDS: s_toff[t] = first sorted position of
+// tile t, s_toff[ntiles] = number of hashed elements. Called by every thread.
+__device__ __forceinline__ void block_tile_offsets(const int32_t* __restrict__ tile_tot,
+                                                   int ntiles, int32_t* s_toff, int32_t* s_tmp) {
+  const int t = threadIdx.x;
+  const int nth = blockDim.x;
+  const int per = (ntiles + nth - 1) / nth;
+  const int beg = t * per;
+  int sum = 0;
+  for (int i = 0; i < per; ++i)
+    if (beg + i < ntiles) sum += tile_tot[beg + i];
+  s_tmp[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < nth; o <<= 1) {
+    const int add = t >= o ? s_tmp[t - o] : 0;
+    __syncthreads();
+    s_tmp[t] += add;
+    __syncthreads();
+  }
+  int run = s_tmp[t] - sum;
+  for (int i = 0; i < per; ++i)
+    if (beg + i < ntiles) {
+      s_toff[beg + i] = run;
+      run += tile_tot[beg + i];
+    }
+  if (t == nth - 1) s_toff[ntiles] = s_tmp[nth - 1];
+  __syncthreads();
+}
+
+// Grid for elements no larger than `ext`: the finest grid of cubic cells of edge >= ext
+// that tiles the box (3 <= nc <= 1023); nc = 0 (no grid) when fewer than 3 fit.
+__host__ __device__ inline Cells choose_cells(double box, double ext, double tol) {
+  Cells c{};
+  double h = ext > box / 1023.0 ? ext : box / 1023.0;
+  int nc = (int)floor(box / h);
+  if (nc > 1023) nc = 1023;
+  if (nc < 3) nc = 0;
+  c.nc = nc;
+  c.fixed = 0;
+  c.h = nc ? box / nc : box;
+  c.inv_h = 1.0 / c.h;
+  c.hlim = c.h - 4.0 * tol;
+  c.h32 = (float)c.h;
+  c.marg32 = (float)(c.h * 0x1p-16);
+  return c;
+}
+
+// ---------------------------------------------------------------------------------
+// step kernels
+// ---------------------------------------------------------------------------------
+
+// SCR: 0 = evolution only, 1 = FP64 screen data, 2 = FP32 screen data.
+template <bool FRW, int SCR>
+__global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restrict__ nxt, int n,
+                                               sp::Period P, double hcoef, Ctrl* ctrl, HashCfg hc,
+                                               void* __restrict__ ebox,
+                                               int32_t* __restrict__ ecell,
+                                               int32_t* __restrict__ epos,
+                                               int32_t* __restrict__ cnt,
+                                               LargeBox* __restrict__ large,
+                                               uint64_t* __restrict__ blkred) {
+  if (ctrl->done) return;
+  const int s = ctrl->step;
+  const Cells cs = ctrl->cells;
+  const int ic = s % 3, ip = (s + 2) % 3, in = (s + 1) % 3;
+  const int k = blockIdx.x * NT + threadIdx.x;
+  uint64_t tkey = KEY_MAX;
+  uint64_t xkey = 0;
+  if (k < n) {
+    const int j = nxt[k];
+    const V4 L = ld(X, ic, k);
+    const V4 R = ld(X, ic, j);
+    const V4 B = ld(X, ip, j);
+    const V4 T = sp::top<FRW>(L, R, B, P, hcoef);
+    st(X, in, k, T);
+    tkey = order_key(T.t);
+    if constexpr (SCR != 0) {
+      const int jj = nxt[j];
+      const V4 Rj = ld(X, ic, jj);
+      const V4 Bj = ld(X, ip, jj);
+      const V4 Tj = sp::top<FRW>(R, Rj, Bj, P, hcoef);
+      const Elem e = sp::make_elem(L, R, T, Tj, P);
+      const Box4 b = sp::elem_box(e);
+      double ext = b.hi[0] - b.lo[0];
+      ext = fmax(ext, b.hi[1] - b.lo[1]);
+      ext = fmax(ext, b.hi[2] - b.lo[2]);
+      xkey = order_key(ext);
+      double W[3], w[3];
+      for (int c = 0; c < 3; ++c) {
+        W[c] = P.box * floor(b.lo[c] * P.inv);
+        w[c] = b.lo[c] - W[c];
+      }
+      if (cs.nc == 0 || !(ext <= cs.hlim)) {
+        const int li = atomicAdd(&ctrl->n_large, 1);
+        LargeBox lb;
+        for (int c = 0; c < 3; ++c) {
+          lb.wl[c] = w[c];
+          lb.ext[c] = b.hi[c] - b.lo[c];
+        }
+        lb.tlo = b.lo[3];
+        lb.thi = b.hi[3];
+        lb.slot = k;
+        lb.pad = 0;
+        large[li] = lb;
+        ecell[k] = -1 - li;
+      } else {
+        int ci[3];
+        double lor[3], hir[3];
+        for (int c = 0; c < 3; ++c) {
+          int q = (int)floor(w[c] * cs.inv_h);
+          q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
+          ci[c] = q;
+          lor[c] = w[c] - (double)q * cs.h;
+          hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
+        }
+        if constexpr (SCR == 1) {
+          double4* o = (double4*)ebox + (size_t)k * 2;
+          o[0] = make_double4(lor[0], lor[1], lor[2], b.lo[3]);
+          o[1] = make_double4(hir[0], hir[1], hir[2], b.hi[3]);
+        } else {
+          float4* o = (float4*)ebox + (size_t)k * 2;
+          o[0] = make_float4(__double2float_rd(lor[0] - hc.tol), __double2float_rd(lor[1] - hc.tol),
+                             __double2float_rd(lor[2] - hc.tol),
+                             __double2float_rd((b.lo[3] - hc.tref) - hc.tol_t));
+          o[1] = make_float4(__double2float_ru(hir[0] + hc.tol), __double2float_ru(hir[1] + hc.tol),
+                             __double2float_ru(hir[2] + hc.tol),
+                             __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
+        }
+        const uint32_t bk = bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
+        epos[k] = atomicAdd(&cnt[bk], 1);
+        ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
+      }
+    }
+  }
+  // per-block minimum of the new slice's t and maximum element extent, reduced by
+  // k_resolve (no same-address atomics across the grid)
+  __shared__ uint64_t wmin[NT / 64], wmax[NT / 64];
+  tkey = wave_min_u64(tkey);
+  xkey = wave_max_u64(xkey);
+  if ((threadIdx.x & 63) == 0) {
+    wmin[threadIdx.x >> 6] = tkey;
+    wmax[threadIdx.x >> 6] = xkey;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t m = wmin[0], x = wmax[0];
+    for (int w = 1; w < NT / 64; ++w) {
+      m = wmin[w] < m ? wmin[w] : m;
+      x = wmax[w] > x ? wmax[w] : x;
+    }
+    blkred[2 * blockIdx.x] = m;
+    blkred[2 * blockIdx.x + 1] = x;
+  }
+}
+
+// Per-tile exclusive scan of the bucket counts (counts are reset for the next step);
+// tile totals go to tile_tot. Consumers scan the tile totals themselves, in LDS.
+__global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t* __restrict__ loc,
+                                              int32_t* __restrict__ tile_tot, const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  __shared__ int32_t sh[256];
+  const int t = threadIdx.x;
+  const size_t base = (size_t)blockIdx.x * TS + (size_t)t * 16;
+  int4* c4 = (int4*)(cnt + base);
+  int v[16];
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int4 q = c4[i];
+    v[4 * i] = q.x;
+    v[4 * i + 1] = q.y;
+    v[4 * i + 2] = q.z;
+    v[4 * i + 3] = q.w;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) sum += v[i];
+  sh[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int add = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int run = sh[t] - sum;
+  int out[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    out[i] = run;
+    run += v[i];
+  }
+  int4* l4 = (int4*)(loc + base);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    l4[i] = make_int4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+    c4[i] = make_int4(0, 0, 0, 0);
+  }
+  if (t == 255) tile_tot[blockIdx.x] = sh[255];
+}
+
+constexpr int MAX_TILES = 2048;  // buckets <= 2^23
+
+__device__ __forceinline__ int bucket_start(const int32_t* loc, const int32_t* s_toff, uint32_t b) {
+  return loc[b] + s_toff[b >> TS_LOG];
+}
+
+// Cell-sorted copies of each hashed element: cell, slot and screen box.
+template <int SCR>
+__global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict__ ecell,
+                                                const int32_t* __restrict__ epos,
+                                                const int32_t* __restrict__ loc,
+                                                const int32_t* __restrict__ tile_tot, int ntiles,
+                                                const void* __restrict__ ebox,
+                                                int32_t* __restrict__ scell,
+                                                int32_t* __restrict__ sid,
+                                                void* __restrict__ sbox, HashCfg hc,
+                                                const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  __shared__ int32_t s_toff[MAX_TILES + 1];
+  __shared__ int32_t s_tmp[NT];
+  block_tile_offsets(tile_tot, ntiles, s_toff, s_tmp);
+  const int nc = ctrl->cells.nc;
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const int32_t c = ecell[k];
+  if (c < 0) return;
+  const uint32_t b = bucket_of(nc, hc.bmask, c & 1023, (c >> 10) & 1023, (c >> 20) & 1023);
+  const int pos = bucket_start(loc, s_toff, b) + epos[k];
+  scell[pos] = c;
+  sid[pos] = k;
+  if constexpr (SCR == 1) {
+    const double4* src = (const double4*)ebox + (size_t)k * 2;
+    double4* dst = (double4*)sbox + (size_t)pos * 2;
+    dst[0] = src[0];
+    dst[1] = src[1];
+  } else {
+    const float4* src = (const float4*)ebox + (size_t)k * 2;
+    float4* dst = (float4*)sbox + (size_t)pos * 2;
+    dst[0] = src[0];
+    dst[1] = src[1];
+  }
+}
+
+__device__ __forceinline__ void push_cand(Ctrl* ctrl, int2* cand, int cap, int k, int m) {
+  const int i = atomicAdd(&ctrl->n_cand, 1);
+  if (i < cap) cand[i] = make_int2(k, m);
+}
+
+// Periodic 1-D overlap of [a, a + ea] and [b, b + eb] on a circle of length box.
+__device__ __forceinline__ bool wrap_overlap(double a, double ea, double b, double eb,
+                                             const sp::Period& P, double tol) {
+  const double box = P.box;
+  double d = b - a;
+  d = d - box * floor(d * P.inv);
+  return d <= ea + tol || (box - d) <= eb + tol;
+}
+
+// Screen box of a sorted entry (lo xyz t, hi xyz t), loaded as two 16/32-byte vectors.
+template <class T>
+struct SBox {
+  T v[8];
+};
+template <class T>
+__device__ __forceinline__ SBox<T> load_sbox(const void* sbox, int q) {
+  SBox<T> b;
+  if constexpr (sizeof(T) == 8) {
+    const double4* p = (const double4*)sbox + (size_t)q * 2;
+    const double4 a = p[0], c = p[1];
+    b.v[0] = a.x; b.v[1] = a.y; b.v[2] = a.z; b.v[3] = a.w;
+    b.v[4] = c.x; b.v[5] = c.y; b.v[6] = c.z; b.v[7] = c.w;
+  } else {
+    const float4* p = (const float4*)sbox + (size_t)q * 2;
+    const float4 a = p[0], c = p[1];
+    b.v[0] = a.x; b.v[1] = a.y; b.v[2] = a.z; b.v[3] = a.w;
+    b.v[4] = c.x; b.v[5] = c.y; b.v[6] = c.z; b.v[7] = c.w;
+  }
+  return b;
+}
+
+// Overlap of box a with box b shifted by (sx, sy, sz), spatial slack tl, exact in t.
+template <class T>
+__device__ __forceinline__ bool box_overlap(const SBox<T>& a, const SBox<T>& b, T sx, T sy, T sz,
+                                            T tl) {
+  return a.v[0] <= b.v[4] + sx + tl && b.v[0] + sx <= a.v[4] + tl && a.v[1] <= b.v[5] + sy + tl &&
+         b.v[1] + sy <= a.v[5] + tl && a.v[2] <= b.v[6] + sz + tl && b.v[2] + sz <= a.v[6] + tl &&
+         a.v[3] <= b.v[7] && b.v[3] <= a.v[7];
+}
+
+constexpr int SBUF = 2048;  // candidates staged in LDS per block
+
+// Half-shell screen over the cell-sorted elements: thread q takes the element at
+// sorted position q and tests the later entries of its own cell and every entry of the
+// 13 forward neighbour cells; threads past the hashed elements take one large element
+// each. Every normal element also tests every large element; two large elements are
+// tested by the one of smaller slot. Each unordered pair is therefore tested once.
+template <int SCR>
+__global__ __launch_bounds__(NT) void k_screen(int n, const int32_t* __restrict__ scell,
+                                               const int32_t* __restrict__ sid,
+                                               const void* __restrict__ sbox,
+                                               const int32_t* __restrict__ nxt,
+                                               const int32_t* __restrict__ prv,
+                                               const int32_t* __restrict__ loc,
+                                               const int32_t* __restrict__ tile_tot, int ntiles,
+                                               const LargeBox* __restrict__ large, HashCfg hc,
+                                               sp::Period P, int2* __restrict__ cand, int cap,
+                                               Ctrl* ctrl) {
+  if (ctrl->done) return;
+  using T = typename std::conditional<SCR == 1, double, float>::type;
+  __shared__ int2 sbuf[SBUF];
+  __shared__ int32_t s_toff[MAX_TILES + 1];
+  __shared__ int32_t s_tmp[NT];
+  __shared__ int s_cnt, s_base;
+  if (threadIdx.x == 0) s_cnt = 0;
+  block_tile_offsets(tile_tot, ntiles, s_toff, s_tmp);
+  const Cells cs = ctrl->cells;
+  const int q = blockIdx.x * NT + threadIdx.x;
+  const int n_norm = s_toff[ntiles];
+  const int nl = ctrl->n_large;
+  auto push = [&](int a, int b) {
+    const int i = atomicAdd(&s_cnt, 1);
+    if (i < SBUF)
+      sbuf[i] = make_int2(a, b);
+    else
+      push_cand(ctrl, cand, cap, a, b);
+  };
+  if (q < n_norm + nl) {
+    int k;
+    bool own_large;
+    double wl[3], ex[3], tlo, thi;  // wrapped box of the element (for large partners)
+    if (q < n_norm) {
+      own_large = false;
+      const int32_t c = scell[q];
+      k = sid[q];
+      const int nk = nxt[k], pk = prv[k];
+      const SBox<T> me = load_sbox<T>(sbox, q);
+      const int cx = c & 1023, cy = (c >> 10) & 1023, cz = (c >> 20) & 1023;
+      const int ccx[3] = {cx, cy, cz};
+      for (int i = 0; i < 3; ++i) {
+        wl[i] = (double)ccx[i] * cs.h + (double)me.v[i];
+        ex[i] = (double)me.v[4 + i] - (double)me.v[i];
+      }
+      if constexpr (SCR == 1) {
+        tlo = me.v[3];
+        thi = me.v[7];
+      } else {
+        tlo = (double)me.v[3] + hc.tref;
+        thi = (double)me.v[7] + hc.tref;
+      }
+      const T tl = SCR == 1 ? (T)hc.tol : (T)cs.marg32;
+      const T hh = SCR == 1 ? (T)cs.h : (T)cs.h32;
+      for (int o = 0; o < 14; ++o) {
+        int dx, dy, dz;
+        if (o == 0) {
+          dx = dy = dz = 0;
+        } else if (o < 10) {
+          dx = 1;
+          dy = (o - 1) / 3 - 1;
+          dz = (o - 1) % 3 - 1;
+        } else if (o < 13) {
+          dx = 0;
+          dy = 1;
+          dz = o - 11;
+        } else {
+          dx = 0;
+          dy = 0;
+          dz = 1;
+        }
+        int x = cx + dx, y = cy + dy, z = cz + dz;
+        x = x < 0 ? x + cs.nc : (x >= cs.nc ? x - cs.nc : x);
+        y = y < 0 ? y + cs.nc : (y >= cs.nc ? y - cs.nc : y);
+        z = z < 0 ? z + cs.nc : (z >= cs.nc ? z - cs.nc : z);
+        const uint32_t b = bucket_of(cs.nc, hc.bmask, x, y, z);
+        int beg = bucket_start(loc, s_toff, b);
+        const int end = bucket_start(loc, s_toff, b + 1);
+        if (o == 0) beg = q + 1;
+        const int32_t pc = (int32_t)pack_cell(x, y, z);
+        const T sx = (T)dx * hh, sy = (T)dy * hh, sz = (T)dz * hh;
+        int q2 = beg;
+        for (; q2 + 4 <= end; q2 += 4) {
+          int32_t c4[4], m4[4];
+          SBox<T> b4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            c4[u] = scell[q2 + u];
+            m4[u] = sid[q2 + u];
+            b4[u] = load_sbox<T>(sbox, q2 + u);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (c4[u] == pc && m4[u] != nk && m4[u] != pk && box_overlap(me, b4[u], sx, sy, sz, tl))
+              push(k, m4[u]);
+        }
+        for (; q2 < end; ++q2) {
+          if (scell[q2] != pc) continue;
+          const int m = sid[q2];
+          if (m == nk || m == pk) continue;
+          if (box_overlap(me, load_sbox<T>(sbox, q2), sx, sy, sz, tl)) push(k, m);
+        }
+      }
+    } else {
+      own_large = true;
+      const LargeBox own = large[q - n_norm];
+      k = own.slot;
+      for (int i = 0; i < 3; ++i) {
+        wl[i] = own.wl[i];
+        ex[i] = own.ext[i];
+      }
+      tlo = own.tlo;
+      thi = own.thi;
+    }
+    const int nk = nxt[k], pk = prv[k];
+    for (int a = 0; a < nl; ++a) {
+      const LargeBox lb = large[a];
+      const int m = lb.slot;
+      if (m == k) continue;
+      if (own_large && m < k) continue;
+      if (m == nk || m == pk) continue;
+      const double tt = hc.tol_t;
+      bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
+      for (int i = 0; i < 3 && ov; ++i) ov = wrap_overlap(wl[i], ex[i], lb.wl[i], lb.ext[i], P, hc.tolL);
+      if (ov) push(k, m);
+    }
+  }
+  __syncthreads();
+  const int cnt = min(s_cnt, SBUF);
+  if (threadIdx.x == 0 && cnt > 0) s_base = atomicAdd(&ctrl->n_cand, cnt);
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += NT) {
+    const int idx = s_base + i;
+    if (idx < cap) cand[idx] = sbuf[i];
+  }
+}
+
+__device__ __forceinline__ Elem load_elem(const Slices& X, int ic, int in, int a, int ja,
+                                          const sp::Period& P) {
+  return sp::make_elem(ld(X, ic, a), ld(X, ic, ja), ld(X, in, a), ld(X, in, ja), P);
+}
+
+// Exact FP64 box overlap and the four triangle pairs of each candidate.
+__global__ __launch_bounds__(NT) void k_confirm(Slices X, const int32_t* __restrict__ nxt,
+                                                const int64_t* __restrict__ id, sp::Period P,
+                                                const int2* __restrict__ cand, int cap_cand,
+                                                EvCand* __restrict__ ev, int cap_evt, Ctrl* ctrl) {
+  if (ctrl->done) return;
+  const int nc = min(ctrl->n_cand, cap_cand);
+  const int s = ctrl->step;
+  const int ic = s % 3, in = (s + 1) % 3;
+  for (int i = blockIdx.x * NT + threadIdx.x; i < nc; i += gridDim.x * NT) {
+    const int2 pr = cand[i];
+    int a = pr.x, b = pr.y;
+    int64_t ia = id[a], ib = id[b];
+    if (ib < ia) {
+      const int tmp = a;
+      a = b;
+      b = tmp;
+      const int64_t ti = ia;
+      ia = ib;
+      ib = ti;
+    }
+    const Elem ea = load_elem(X, ic, in, a, nxt[a], P);
+    Elem eb = load_elem(X, ic, in, b, nxt[b], P);
+    const Box4 ba = sp::elem_box(ea);
+    const Box4 bb = sp::elem_box(eb);
+    const V4 Aa = ea.v[0], Ab = eb.v[0];
+    const double S[3] = {P.box * P.nearest(Ab.x - Aa.x), P.box * P.nearest(Ab.y - Aa.y),
+                         P.box * P.nearest(Ab.z - Aa.z)};
+    bool ov = true;
+    for (int c = 0; c < 3; ++c)
+      ov = ov && (ba.lo[c] <= bb.hi[c] - S[c]) && (bb.lo[c] - S[c] <= ba.hi[c]);
+    ov = ov && (ba.lo[3] <= bb.hi[3]) && (bb.lo[3] <= ba.hi[3]);
+    if (!ov) continue;
+    for (int v = 0; v < 4; ++v) {
+      eb.v[v].x = eb.v[v].x - S[0];
+      eb.v[v].y = eb.v[v].y - S[1];
+      eb.v[v].z = eb.v[v].z - S[2];
+    }
+    bool found = false;
+    double bt = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+    for (int ipq = 0; ipq < 4; ++ipq) {
+      const int ipp = ipq >> 1, iq = ipq & 1;
+      const V4& P0 = ipp ? ea.v[2] : ea.v[0];
+      const V4& P1 = ea.v[1];
+      const V4& P2 = ipp ? ea.v[3] : ea.v[2];
+      const V4& Q0 = iq ? eb.v[2] : eb.v[0];
+      const V4& Q1 = eb.v[1];
+      const V4& Q2 = iq ? eb.v[3] : eb.v[2];
+      double t, x, y, z;
+      if (sp::tri_tri(P0, P1, P2, Q0, Q1, Q2, t, x, y, z)) {
+        if (!found || t < bt) {
+          found = true;
+          bt = t;
+          bx = x;
+          by = y;
+          bz = z;
+        }
+      }
+    }
+    if (!found) continue;
+    const int e = atomicAdd(&ctrl->n_evt, 1);
+    if (e < cap_evt) {
+      EvCand c;
+      c.t = bt;
+      c.ida = ia;
+      c.idb = ib;
+      c.sa = a;
+      c.sb = b;
+      c.x = bx;
+      c.y = by;
+      c.z = bz;
+      ev[e] = c;
+    }
+  }
+}
+
+__device__ __forceinline__ bool key_less(const EvCand& p, const EvCand& q) {
+  if (p.t < q.t) return true;
+  if (p.t > q.t) return false;
+  if (p.ida != q.ida) return p.ida < q.ida;
+  return p.idb < q.idb;
+}
+
+__device__ __forceinline__ uint64_t aload64(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t aload32(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void astore32(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claim `slot` for event e in iteration `st` unless an event of smaller key holds it.
+__device__ __forceinline__ void propose(uint64_t* best, int slot, uint32_t st, int e,
+                                       const EvCand* ev) {
+  const uint64_t tag = ((uint64_t)st << 32) | (uint32_t)e;
+  uint64_t old = aload64(&best[slot]);
+  for (;;) {
+    if ((uint32_t)(old >> 32) == st) {
+      const int oe = (int)(uint32_t)old;
+      if (key_less(ev[oe], ev[e])) return;
+    }
+    const unsigned long long prev =
+        atomicCAS((unsigned long long*)&best[slot], (unsigned long long)old, (unsigned long long)tag);
+    if (prev == old) return;
+    old = prev;
+  }
+}
+
+// One workgroup: the greedy matching of the step's events in (t*, id_a, id_b) order,
+// computed as iterated local minima; partner exchange; log; step bookkeeping.
+__global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
+    int32_t* __restrict__ nxt, int32_t* __restrict__ prv, const EvCand* __restrict__ ev,
+    int cap_evt, int cap_cand, uint64_t* __restrict__ best, int32_t* __restrict__ used,
+    int8_t* __restrict__ evs, semipar_event* __restrict__ log, int64_t log_cap,
+    const uint64_t* __restrict__ blkred, int nblk, Ctrl* ctrl) {
+  __shared__ int s_live;
+  __shared__ int s_nacc;
+  __shared__ uint64_t s_min[RESOLVE_NT / 64], s_max[RESOLVE_NT / 64];
+  if (ctrl->done) return;
+  const int t = threadIdx.x;
+  const int ncand = ctrl->n_cand;
+  const int ne = ctrl->n_evt;
+  int defer = 0;
+  if (ncand > cap_cand) defer |= 1;
+  if (ne > cap_evt) defer |= 2;
+  if (ctrl->log_n + (int64_t)ne > log_cap) defer |= 4;
+  if (defer) {
+    __syncthreads();
+    if (t == 0) {
+      ctrl->defer = defer;
+      ctrl->done = 1;
+      ctrl->n_cand = 0;
+      ctrl->n_evt = 0;
+      ctrl->n_large = 0;
+      ctrl->tmin_key = KEY_MAX;
+    }
+    return;
+  }
+  const int32_t step_stamp = ctrl->step + 1;
+  const uint32_t base = (uint32_t)ctrl->stamp;
+  for (int e = t; e < ne; e += RESOLVE_NT) evs[e] = 1;
+  if (t == 0) s_nacc = 0;
+  __syncthreads();
+  uint32_t iter = 0;
+  if (ne > 0) {
+    for (;;) {
+      const uint32_t stp = base + 1 + iter;
+      for (int e = t; e < ne; e += RESOLVE_NT)
+        if (evs[e] == 1) {
+          propose(best, ev[e].sa, stp, e, ev);
+          propose(best, ev[e].sb, stp, e, ev);
+        }
+      __syncthreads();
+      const uint64_t tag0 = (uint64_t)stp << 32;
+      for (int e = t; e < ne; e += RESOLVE_NT)
+        if (evs[e] == 1) {
+          const uint64_t tag = tag0 | (uint32_t)e;
+          if (aload64(&best[ev[e].sa]) == tag && aload64(&best[ev[e].sb]) == tag) {
+            evs[e] = 2;
+            astore32(&used[ev[e].sa], step_stamp);
+            astore32(&used[ev[e].sb], step_stamp);
+          }
+        }
+      if (t == 0) s_live = 0;
+      __syncthreads();
+      int live = 0;
+      for (int e = t; e < ne; e += RESOLVE_NT)
+        if (evs[e] == 1) {
+          if (aload32(&used[ev[e].sa]) == step_stamp || aload32(&used[ev[e].sb]) == step_stamp)
+            evs[e] = 0;
+          else
+            live++;
+        }
+      if (live) atomicAdd(&s_live, live);
+      __syncthreads();
+      const int remaining = s_live;
+      __syncthreads();
+      ++iter;
+      if (remaining == 0) break;
+    }
+    // partner exchange (accepted events touch disjoint elements) and log
+    const int32_t n_step = ctrl->step;
+    const int64_t log0 = ctrl->log_n;
+    for (int e = t; e < ne; e += RESOLVE_NT)
+      if (evs[e] == 2) {
+        const int a = ev[e].sa, b = ev[e].sb;
+        const int ja = nxt[a], jb = nxt[b];
+        nxt[a] = jb;
+        nxt[b] = ja;
+        prv[jb] = a;
+        prv[ja] = b;
+        const int i = atomicAdd(&s_nacc, 1);
+        semipar_event o;
+        o.step = n_step;
+        o.kind = 0;
+        o.id_a = ev[e].ida;
+        o.id_b = ev[e].idb;
+        o.t_star = ev[e].t;
+        o.x_star[0] = ev[e].x;
+        o.x_star[1] = ev[e].y;
+        o.x_star[2] = ev[e].z;
+        log[log0 + i] = o;
+      }
+  }
+  // smallest t of the slice written by this step's k_evolve, largest element extent
+  uint64_t mk = KEY_MAX, xk = 0;
+  for (int b = t; b < nblk; b += RESOLVE_NT) {
+    mk = blkred[2 * b] < mk ? blkred[2 * b] : mk;
+    xk = blkred[2 * b + 1] > xk ? blkred[2 * b + 1] : xk;
+  }
+  mk = wave_min_u64(mk);
+  xk = wave_max_u64(xk);
+  if ((t & 63) == 0) {
+    s_min[t >> 6] = mk;
+    s_max[t >> 6] = xk;
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint64_t m = s_min[0], x = s_max[0];
+    for (int w = 1; w < RESOLVE_NT / 64; ++w) {
+      m = s_min[w] < m ? s_min[w] : m;
+      x = s_max[w] > x ? s_max[w] : x;
+    }
+    if (!ctrl->cells.fixed && x != 0)
+      ctrl->cells = choose_cells(ctrl->box, ctrl->grow * from_key(x), ctrl->tol);
+    ctrl->log_n += s_nacc;
+    ctrl->acc_total += s_nacc;
+    ctrl->conf_total += ne;
+    ctrl->cand_total += ncand;
+    ctrl->large_total += ctrl->n_large;
+    ctrl->n_cand = 0;
+    ctrl->n_evt = 0;
+    ctrl->n_large = 0;
+    ctrl->stamp = (int32_t)(base + iter);
+    ctrl->step += 1;
+    ctrl->steps_taken += 1;
+    ctrl->point_steps += ctrl->n_points;
+    const double tmin = from_key(m);
+    ctrl->done = (ctrl->step >= ctrl->step_limit || tmin >= ctrl->t_end) ? 1 : 0;
+  }
+}
+
+// Start of an evolve call: smallest t on the current slice.
+__global__ __launch_bounds__(NT) void k_begin_min(Slices X, int n, Ctrl* ctrl) {
+  const int s = ctrl->step;
+  const int k = blockIdx.x * NT + threadIdx.x;
+  uint64_t key = KEY_MAX;
+  if (k < n) key = order_key(X.p[s % 3][3][k]);
+  key = wave_min_u64(key);
+  if ((threadIdx.x & 63) == 0 && key != KEY_MAX)
+    atomicMin((unsigned long long*)&ctrl->tmin_key, (unsigned long long)key);
+}
+
+__global__ void k_begin_set(Ctrl* ctrl, int32_t step_limit, double t_end, int n, Cells cells,
+                            int set_cells) {
+  if (threadIdx.x != 0) return;
+  if (set_cells) ctrl->cells = cells;
+  ctrl->step_limit = step_limit;
+  ctrl->t_end = t_end;
+  ctrl->defer = 0;
+  ctrl->n_cand = 0;
+  ctrl->n_evt = 0;
+  ctrl->n_large = 0;
+  const double tmin = from_key(ctrl->tmin_key);
+  ctrl->tmin_key = KEY_MAX;
+  ctrl->done = (n == 0 || ctrl->step >= step_limit || tmin >= t_end) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------------
+// init / emit kernels
+// ---------------------------------------------------------------------------------
+constexpr int64_t ID_EMPTY = INT64_MIN;
+
+__device__ __forceinline__ uint32_t id_hash(int64_t id, uint32_t mask) {
+  uint64_t z = (uint64_t)id + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (uint32_t)z & mask;
+}
+
+__global__ __launch_bounds__(NT) void k_init_insert(const semipar_point_rec* __restrict__ rec,
+                                                    int n, int64_t* __restrict__ hkey,
+                                                    int32_t* __restrict__ hval, uint32_t hmask,
+                                                    Ctrl* ctrl) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const int64_t id = rec[k].id;
+  if (id == ID_EMPTY) {
+    atomicOr(&ctrl->err, 1);
+    return;
+  }
+  uint32_t h = id_hash(id, hmask);
+  for (uint32_t probe = 0; probe <= hmask; ++probe) {
+    const unsigned long long prev = atomicCAS((unsigned long long*)&hkey[h],
+                                              (unsigned long long)ID_EMPTY, (unsigned long long)id);
+    if ((int64_t)prev == ID_EMPTY) {
+      hval[h] = k;
+      return;
+    }
+    if ((int64_t)prev == id) {
+      atomicOr(&ctrl->err, 2);  // duplicate id
+      return;
+    }
+    h = (h + 1) & hmask;
+  }
+  atomicOr(&ctrl->err, 4);
+}
+
+__global__ __launch_bounds__(NT) void k_fill_i64(int64_t* p, uint64_t m, int64_t v) {
+  const uint64_t i = blockIdx.x * (uint64_t)NT + threadIdx.x;
+  if (i < m) p[i] = v;
+}
+
+__device__ __forceinline__ int id_lookup(const int64_t* hkey, const int32_t* hval, uint32_t hmask,
+                                         int64_t id) {
+  if (id < 0) return -1;
+  uint32_t h = id_hash(id, hmask);
+  for (uint32_t probe = 0; probe <= hmask; ++probe) {
+    const int64_t key = hkey[h];
+    if (key == id) return hval[h];
+    if (key == ID_EMPTY) return -1;
+    h = (h + 1) & hmask;
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(NT) void k_init_links(const semipar_point_rec* __restrict__ rec, int n,
+                                                   const int64_t* __restrict__ hkey,
+                                                   const int32_t* __restrict__ hval,
+                                                   uint32_t hmask, Slices X, int32_t* nxt,
+                                                   int32_t* prv, int64_t* id, Ctrl* ctrl) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const semipar_point_rec r = rec[k];
+  const int s = r.step;
+  if (s != rec[0].step || s < 1) atomicOr(&ctrl->err, 8);
+  const int a = id_lookup(hkey, hval, hmask, r.next_id);
+  const int b = id_lookup(hkey, hval, hmask, r.prev_id);
+  if (a < 0 || b < 0) atomicOr(&ctrl->err, 16);
+  nxt[k] = a < 0 ? k : a;
+  prv[k] = b < 0 ? k : b;
+  id[k] = r.id;
+  const int ic = ((s % 3) + 3) % 3, ip = (ic + 2) % 3;
+  st(X, ic, k, V4{r.x[0], r.x[1], r.x[2], r.x[3]});
+  st(X, ip, k, V4{r.x_prev[0], r.x_prev[1], r.x_prev[2], r.x_prev[3]});
+}
+
+// next/prev pairing and an estimate of the element size for the automatic cell.
+__global__ __launch_bounds__(NT) void k_init_check(Slices X, int n, const int32_t* nxt,
+                                                   const int32_t* prv, sp::Period P, int s,
+                                                   Ctrl* ctrl) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  uint64_t key = 0;
+  if (k < n) {
+    const int j = nxt[k];
+    if (prv[j] != k) atomicOr(&ctrl->err, 32);
+    const int ic = s % 3, ip = (s + 2) % 3;
+    const V4 a = ld(X, ic, k), b = ld(X, ic, j), c = ld(X, ip, k);
+    double e1 = fabs(sp::min_image(b.x - a.x, P));
+    e1 = fmax(e1, fabs(sp::min_image(b.y - a.y, P)));
+    e1 = fmax(e1, fabs(sp::min_image(b.z - a.z, P)));
+    double e2 = fmax(fmax(fabs(a.x - c.x), fabs(a.y - c.y)), fabs(a.z - c.z));
+    key = order_key(e1 + e2);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t w = __shfl_xor(key, o, 64);
+    key = w > key ? w : key;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&ctrl->ext_key, (unsigned long long)key);
+}
+
+__global__ __launch_bounds__(NT) void k_emit_all(Slices X, int n, const int32_t* nxt,
+                                                 const int32_t* prv, const int64_t* id, int s,
+                                                 semipar_point_rec* __restrict__ out) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const int ic = s % 3, ip = (s + 2) % 3;
+  semipar_point_rec r;
+  r.id = id[k];
+  r.next_id = id[nxt[k]];
+  r.prev_id = id[prv[k]];
+  r.step = s;
+  r.flags = 0;
+  const V4 a = ld(X, ic, k), b = ld(X, ip, k);
+  r.x[0] = a.x;
+  r.x[1] = a.y;
+  r.x[2] = a.z;
+  r.x[3] = a.t;
+  r.x_prev[0] = b.x;
+  r.x_prev[1] = b.y;
+  r.x_prev[2] = b.z;
+  r.x_prev[3] = b.t;
+  for (int c = 0; c < 4; ++c) {
+    r.r[c] = 0.0;
+    r.r_prev[c] = 0.0;
+  }
+  out[k] = r;
+}
+
+// ---------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------
+thread_local char g_last_error[256] = "";
+
+inline int hip_fail(hipError_t e, const char* what, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s failed at semipar.hip:%d: %s", what, line,
+           hipGetErrorString(e));
+  return SEMIPAR_E_HIP;
+}
+
+#define RCCHK(x)              \
+  do {                        \
+    int rc_ = (x);            \
+    if (rc_ != 0) return rc_; \
+  } while (0)
+
+#define HIPCHK(x)                                          \
+  do {                                                     \
+    hipError_t e_ = (x);                                   \
+    if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__); \
+  } while (0)
+
+inline void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, sizeof(T) * count);
+}
+
+inline int blocks(int64_t n, int nt = NT) { return (int)((n + nt - 1) / nt); }
+
+}  // namespace
+
+struct semipar_region {
+  int64_t n = 0, cap = 0;
+  int cosmology = 0;
+  double hcoef = 0.0, box = 1.0;
+  hipStream_t stream = nullptr;
+  sp::Period P{};
+  uint64_t* blkred = nullptr;  // per block: min t of the slice being written, max extent
+  Slices X{};
+  int32_t *nxt = nullptr, *prv = nullptr;
+  int64_t* id = nullptr;
+  Ctrl* ctrl = nullptr;
+  Ctrl* ctrl_h = nullptr;  // pinned mirror
+  double ext0 = 0.0;       // initial element-size estimate
+  // step buffers (configured per evolve parameters)
+  int screen = -1;
+  void* ebox = nullptr;
+  int32_t *ecell = nullptr, *epos = nullptr;
+  LargeBox* large = nullptr;
+  HashCfg hc{};
+  int32_t *cnt = nullptr, *loc = nullptr, *tile_tot = nullptr;
+  int32_t *scell = nullptr, *sid = nullptr;  // cell-sorted element cells and slots
+  void* sbox = nullptr;                      // cell-sorted screen boxes
+  int ntiles = 0;
+  int2* cand = nullptr;
+  int64_t cap_cand = 0;
+  EvCand* ev = nullptr;
+  int64_t cap_evt = 0;
+  uint64_t* best = nullptr;
+  int32_t* used = nullptr;
+  int8_t* evs = nullptr;
+  semipar_event* log = nullptr;
+  int64_t log_cap = 0;
+  bool broken = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool own_stream = false;
+  hipGraphExec_t gexec = nullptr;
+  int g_steps = 0;
+  int g_timed = -1;
+  bool cells_set = false;  // the device grid has been chosen (adaptive runs keep it)
+  bool cells_fixed = false;
+  // measurement: HIP events around every launch of one kernel (timed_kernel)
+  int timed = -1;
+  std::vector<hipEvent_t> tev;
+};
+
+namespace {
+
+void free_step_buffers(semipar_region* r) {
+  dfree(r->ebox);
+  dfree(r->ecell);
+  dfree(r->epos);
+  dfree(r->large);
+  dfree(r->cnt);
+  dfree(r->loc);
+  dfree(r->tile_tot);
+  dfree(r->scell);
+  dfree(r->sid);
+  dfree(r->sbox);
+  dfree(r->cand);
+  dfree(r->ev);
+  dfree(r->best);
+  dfree(r->used);
+  dfree(r->evs);
+  r->ebox = nullptr;
+  r->ecell = r->epos = r->cnt = r->loc = r->tile_tot = r->scell = r->sid = r->used = nullptr;
+  r->sbox = nullptr;
+  r->large = nullptr;
+  r->cand = nullptr;
+  r->ev = nullptr;
+  r->best = nullptr;
+  r->evs = nullptr;
+  r->screen = -1;
+  r->cap_cand = r->cap_evt = 0;
+}
+
+void drop_graph(semipar_region* r) {
+  if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
+  r->gexec = nullptr;
+  r->g_steps = 0;
+  r->g_timed = -1;
+}
+
+int ensure_timing_events(semipar_region* r, int K) {
+  while ((int)r->tev.size() < 2 * K) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    r->tev.push_back(e);
+  }
+  return SEMIPAR_OK;
+}
+
+inline void mark(semipar_region* r, int kid, int slot) {
+  if (r->timed == kid) (void)hipEventRecord(r->tev[slot], r->stream);
+}
+
+uint64_t next_pow2(uint64_t v) {
+  uint64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+HashCfg make_hash(const semipar_region* r) {
+  HashCfg hc{};
+  const double box = r->box;
+  uint64_t B = next_pow2(std::max<uint64_t>(2 * (uint64_t)std::max<int64_t>(r->cap, 1), TS));
+  if (B > (uint64_t)TS * MAX_TILES) B = (uint64_t)TS * MAX_TILES;
+  hc.B = (int32_t)B;
+  hc.bmask = (uint32_t)(B - 1);
+  hc.tol = box * std::ldexp(1.0, -30);
+  hc.tolL = box * std::ldexp(1.0, -24);
+  hc.tref = 0.0;
+  hc.tol_t = std::ldexp(1.0, -30) * 64.0;
+  return hc;
+}
+
+int configure(semipar_region* r, const semipar_evolve_params* p) {
+  const int screen = p->screen == SEMIPAR_SCREEN_F32 ? 2 : 1;
+  const double capd = (double)std::max<int64_t>(r->cap, 1);
+  const int64_t want_cand = p->cand_per_point > 0
+                                ? (int64_t)std::ceil(p->cand_per_point * capd) + 64
+                                : (int64_t)(4.0 * capd) + 65536;
+  const int64_t want_evt = p->events_per_point > 0
+                               ? (int64_t)std::ceil(p->events_per_point * capd) + 64
+                               : (int64_t)(0.5 * capd) + 65536;
+  if (r->screen == screen && r->cap_cand >= want_cand && r->cap_evt >= want_evt)
+    return SEMIPAR_OK;
+  const int64_t old_cand = r->cap_cand, old_evt = r->cap_evt;
+  drop_graph(r);
+  free_step_buffers(r);
+  const int64_t cap = std::max<int64_t>(r->cap, 1);
+  r->hc = make_hash(r);
+  r->ntiles = r->hc.B / TS;
+  HIPCHK(hipMalloc(&r->ebox, (size_t)cap * 8 * (screen == 1 ? sizeof(double) : sizeof(float))));
+  HIPCHK(dalloc(&r->ecell, cap));
+  HIPCHK(dalloc(&r->epos, cap));
+  HIPCHK(dalloc(&r->large, cap));
+  HIPCHK(dalloc(&r->cnt, r->hc.B));
+  HIPCHK(dalloc(&r->loc, (size_t)r->hc.B + 1));
+  HIPCHK(dalloc(&r->tile_tot, r->ntiles));
+  HIPCHK(dalloc(&r->scell, cap));
+  HIPCHK(dalloc(&r->sid, cap));
+  HIPCHK(hipMalloc(&r->sbox, (size_t)cap * 8 * (screen == 1 ? sizeof(double) : sizeof(float))));
+  HIPCHK(hipMemset(r->cnt, 0, sizeof(int32_t) * r->hc.B));
+  HIPCHK(hipMemset(r->loc, 0, sizeof(int32_t) * ((size_t)r->hc.B + 1)));
+  r->cap_cand = std::max(want_cand, old_cand);
+  r->cap_evt = std::max(want_evt, old_evt);
+  if (r->cap_cand > INT32_MAX / 2) r->cap_cand = INT32_MAX / 2;
+  if (r->cap_evt > INT32_MAX / 2) r->cap_evt = INT32_MAX / 2;
+  HIPCHK(dalloc(&r->cand, r->cap_cand));
+  HIPCHK(dalloc(&r->ev, r->cap_evt));
+  HIPCHK(dalloc(&r->evs, r->cap_evt));
+  HIPCHK(dalloc(&r->best, cap));
+  HIPCHK(dalloc(&r->used, cap));
+  HIPCHK(hipMemset(r->best, 0, sizeof(uint64_t) * cap));
+  HIPCHK(hipMemset(r->used, 0, sizeof(int32_t) * cap));
+  r->screen = screen;
+  HIPCHK(hipDeviceSynchronize());
+  return SEMIPAR_OK;
+}
+
+int ensure_log(semipar_region* r, int64_t need) {
+  if (r->log_cap >= need) return SEMIPAR_OK;
+  int64_t nc = std::max<int64_t>(need, std::max<int64_t>(2 * r->log_cap, 1 << 16));
+  semipar_event* nl = nullptr;
+  HIPCHK(hipMalloc(&nl, sizeof(semipar_event) * nc));
+  if (r->log && r->ctrl_h->log_n > 0)
+    HIPCHK(hipMemcpyAsync(nl, r->log, sizeof(semipar_event) * r->ctrl_h->log_n,
+                          hipMemcpyDeviceToDevice, r->stream));
+  HIPCHK(hipStreamSynchronize(r->stream));
+  dfree(r->log);
+  r->log = nl;
+  r->log_cap = nc;
+  drop_graph(r);
+  return SEMIPAR_OK;
+}
+
+// A deferred step reported that the candidate (bit 1) or event (bit 2) buffer was too
+// small: double it. The step is then taken again from the same state.
+int grow_step_caps(semipar_region* r, int defer) {
+  drop_graph(r);
+  HIPCHK(hipStreamSynchronize(r->stream));
+  if (defer & 1) {
+    if (r->cap_cand >= INT32_MAX / 4) return SEMIPAR_E_OVERFLOW;
+    dfree(r->cand);
+    r->cand = nullptr;
+    r->cap_cand *= 2;
+    HIPCHK(dalloc(&r->cand, r->cap_cand));
+  }
+  if (defer & 2) {
+    if (r->cap_evt >= INT32_MAX / 4) return SEMIPAR_E_OVERFLOW;
+    dfree(r->ev);
+    dfree(r->evs);
+    r->ev = nullptr;
+    r->evs = nullptr;
+    r->cap_evt *= 2;
+    HIPCHK(dalloc(&r->ev, r->cap_evt));
+    HIPCHK(dalloc(&r->evs, r->cap_evt));
+  }
+  return SEMIPAR_OK;
+}
+
+// Issue one lattice step (all kernels) on the region's stream. i: index of the step in
+// its block (selects the timing-event pair when a kernel is timed).
+void issue_step(semipar_region* r, bool intercommute, int i) {
+  const int n = (int)r->n;
+  const int nb = blocks(n);
+  hipStream_t s = r->stream;
+  const bool frw = r->cosmology != SEMIPAR_FLAT;
+  mark(r, SEMIPAR_K_EVOLVE, 2 * i);
+  if (!intercommute) {
+    if (frw)
+      k_evolve<true, 0><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
+                                          r->ecell, r->epos, r->cnt, r->large, r->blkred);
+    else
+      k_evolve<false, 0><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
+                                           r->ecell, r->epos, r->cnt, r->large, r->blkred);
+  } else if (r->screen == 1) {
+    if (frw)
+      k_evolve<true, 1><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
+                                          r->ecell, r->epos, r->cnt, r->large, r->blkred);
+    else
+      k_evolve<false, 1><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
+                                           r->ecell, r->epos, r->cnt, r->large, r->blkred);
+  } else {
+    if (frw)
+      k_evolve<true, 2><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
+                                          r->ecell, r->epos, r->cnt, r->large, r->blkred);
+    else
+      k_evolve<false, 2><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
+                                           r->ecell, r->epos, r->cnt, r->large, r->blkred);
+  }
+  mark(r, SEMIPAR_K_EVOLVE, 2 * i + 1);
+  if (intercommute) {
+    mark(r, SEMIPAR_K_SCAN, 2 * i);
+    k_scan<<<r->ntiles, 256, 0, s>>>(r->cnt, r->loc, r->tile_tot, r->ctrl);
+    mark(r, SEMIPAR_K_SCAN, 2 * i + 1);
+    mark(r, SEMIPAR_K_SCATTER, 2 * i);
+    if (r->screen == 1)
+      k_scatter<1><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->tile_tot, r->ntiles, r->ebox, r->scell,
+                                     r->sid, r->sbox, r->hc, r->ctrl);
+    else
+      k_scatter<2><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->tile_tot, r->ntiles, r->ebox, r->scell,
+                                     r->sid, r->sbox, r->hc, r->ctrl);
+    mark(r, SEMIPAR_K_SCATTER, 2 * i + 1);
+    mark(r, SEMIPAR_K_SCREEN, 2 * i);
+    if (r->screen == 1)
+      k_screen<1><<<nb, NT, 0, s>>>(n, r->scell, r->sid, r->sbox, r->nxt, r->prv, r->loc, r->tile_tot,
+                                    r->ntiles, r->large, r->hc, r->P, r->cand, (int)r->cap_cand,
+                                    r->ctrl);
+    else
+      k_screen<2><<<nb, NT, 0, s>>>(n, r->scell, r->sid, r->sbox, r->nxt, r->prv, r->loc, r->tile_tot,
+                                    r->ntiles, r->large, r->hc, r->P, r->cand, (int)r->cap_cand,
+                                    r->ctrl);
+    mark(r, SEMIPAR_K_SCREEN, 2 * i + 1);
+    mark(r, SEMIPAR_K_CONFIRM, 2 * i);
+    k_confirm<<<512, NT, 0, s>>>(r->X, r->nxt, r->id, r->P, r->cand, (int)r->cap_cand, r->ev,
+                                 (int)r->cap_evt, r->ctrl);
+    mark(r, SEMIPAR_K_CONFIRM, 2 * i + 1);
+  }
+  mark(r, SEMIPAR_K_RESOLVE, 2 * i);
+  k_resolve<<<1, RESOLVE_NT, 0, s>>>(r->nxt, r->prv, r->ev, (int)r->cap_evt, (int)r->cap_cand,
+                                     r->best, r->used, r->evs, r->log, r->log_cap, r->blkred, nb,
+                                     r->ctrl);
+  mark(r, SEMIPAR_K_RESOLVE, 2 * i + 1);
+}
+
+int read_ctrl(semipar_region* r) {
+  HIPCHK(hipMemcpyAsync(r->ctrl_h, r->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, r->stream));
+  HIPCHK(hipStreamSynchronize(r->stream));
+  return SEMIPAR_OK;
+}
+
+__global__ void k_clear_defer(Ctrl* ctrl) {
+  if (threadIdx.x == 0) {
+    ctrl->defer = 0;
+    ctrl->done = 0;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* semipar_strerror(int code) {
+  switch (code) {
+    case SEMIPAR_OK: return "ok";
+    case SEMIPAR_E_ARG: return "invalid argument";
+    case SEMIPAR_E_SURFACE: return "inconsistent surface (duplicate id, dangling link, mixed slices)";
+    case SEMIPAR_E_OOM: return "out of memory";
+    case SEMIPAR_E_HIP: return "HIP runtime error";
+    case SEMIPAR_E_OVERFLOW: return "per-step buffer overflow";
+    case SEMIPAR_E_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+const char* semipar_last_error(void) { return g_last_error; }
+
+const char* semipar_version(void) {
+  return "libsemipar 0.1 gfx950 " __VERSION__;
+}
+
+void region_destroy(semipar_region* r) {
+  if (!r) return;
+  drop_graph(r);
+  free_step_buffers(r);
+  for (int s = 0; s < 3; ++s)
+    for (int c = 0; c < 4; ++c) dfree(r->X.p[s][c]);
+  dfree(r->nxt);
+  dfree(r->prv);
+  dfree(r->id);
+  dfree(r->blkred);
+  dfree(r->ctrl);
+  dfree(r->log);
+  if (r->ctrl_h) (void)hipHostFree(r->ctrl_h);
+  if (r->ev0) (void)hipEventDestroy(r->ev0);
+  if (r->ev1) (void)hipEventDestroy(r->ev1);
+  for (hipEvent_t e : r->tev) (void)hipEventDestroy(e);
+  if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
+  delete r;
+}
+
+int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surface* in, int n_in,
+                              semipar_region** out) {
+  if (!out) return SEMIPAR_E_ARG;
+  *out = nullptr;
+  if (!d || n_in < 0 || (n_in > 0 && !in)) return SEMIPAR_E_ARG;
+  if (!(d->box > 0.0) || d->cosmology < 0 || d->cosmology > 2 || d->capacity < 0)
+    return SEMIPAR_E_ARG;
+  int64_t total = 0;
+  for (int i = 0; i < n_in; ++i) {
+    if (in[i].n < 0 || (in[i].n > 0 && !in[i].recs)) return SEMIPAR_E_ARG;
+    if (in[i].mem != SEMIPAR_MEM_HOST && in[i].mem != SEMIPAR_MEM_DEVICE) return SEMIPAR_E_ARG;
+    total += in[i].n;
+  }
+  if (total >= (int64_t)1 << 30 || d->capacity >= (int64_t)1 << 30) return SEMIPAR_E_ARG;
+  if (d->capacity > 0 && d->capacity < total) return SEMIPAR_E_ARG;
+  semipar_region* r = new (std::nothrow) semipar_region();
+  if (!r) return SEMIPAR_E_OOM;
+  r->n = total;
+  r->cap = d->capacity > 0 ? d->capacity : total;
+  r->cosmology = d->cosmology;
+  r->hcoef = d->cosmology == SEMIPAR_MATTER ? 2.0 : (d->cosmology == SEMIPAR_RADIATION ? 1.0 : 0.0);
+  r->box = d->box;
+  {
+    int ex = 0;
+    const double mant = std::frexp(d->box, &ex);
+    r->P.box = d->box;
+    r->P.pow2 = mant == 0.5 ? 1 : 0;
+    r->P.inv = r->P.pow2 ? std::ldexp(1.0, 1 - ex) : 1.0 / d->box;
+  }
+  r->stream = (hipStream_t)d->stream;
+  int rc = SEMIPAR_OK;
+  auto fail = [&](int code) {
+    region_destroy(r);
+    return code;
+  };
+  if (!r->stream) {
+    // The legacy null stream cannot be captured into a graph: use a blocking stream of
+    // our own (default priority), which orders itself against the null stream.
+    if (hipStreamCreate(&r->stream) != hipSuccess) return fail(SEMIPAR_E_HIP);
+    r->own_stream = true;
+  }
+  const int64_t cap = std::max<int64_t>(r->cap, 1);
+  for (int s = 0; s < 3; ++s)
+    for (int c = 0; c < 4; ++c)
+      if (dalloc(&r->X.p[s][c], cap) != hipSuccess) return fail(SEMIPAR_E_OOM);
+  if (dalloc(&r->nxt, cap) != hipSuccess || dalloc(&r->prv, cap) != hipSuccess ||
+      dalloc(&r->id, cap) != hipSuccess || dalloc(&r->ctrl, 1) != hipSuccess ||
+      dalloc(&r->blkred, 2 * (size_t)blocks(cap)) != hipSuccess)
+    return fail(SEMIPAR_E_OOM);
+  if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
+    return fail(SEMIPAR_E_OOM);
+  if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess)
+    return fail(SEMIPAR_E_HIP);
+  Ctrl c0{};
+  c0.step = 1;
+  c0.tmin_key = KEY_MAX;
+  c0.n_points = total;
+  c0.step_limit = 1;
+  c0.done = 1;
+  c0.ext_key = 0;
+  c0.box = d->box;
+  c0.grow = 1.15;
+  c0.tol = d->box * std::ldexp(1.0, -30);
+  if (total > 0) {
+    // gather all surfaces into one device record array
+    semipar_point_rec* drec = nullptr;
+    if (dalloc(&drec, total) != hipSuccess) return fail(SEMIPAR_E_OOM);
+    int64_t off = 0;
+    for (int i = 0; i < n_in; ++i) {
+      if (in[i].n == 0) continue;
+      const hipMemcpyKind kind =
+          in[i].mem == SEMIPAR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+      if (hipMemcpyAsync(drec + off, in[i].recs, sizeof(semipar_point_rec) * in[i].n, kind,
+                         r->stream) != hipSuccess) {
+        dfree(drec);
+        return fail(SEMIPAR_E_HIP);
+      }
+      off += in[i].n;
+    }
+    semipar_point_rec rec0;
+    if (hipMemcpyAsync(&rec0, drec, sizeof(rec0), hipMemcpyDeviceToHost, r->stream) != hipSuccess ||
+        hipStreamSynchronize(r->stream) != hipSuccess) {
+      dfree(drec);
+      return fail(SEMIPAR_E_HIP);
+    }
+    c0.step = rec0.step;
+    const uint64_t hcap = next_pow2(2 * (uint64_t)total);
+    int64_t* hkey = nullptr;
+    int32_t* hval = nullptr;
+    if (dalloc(&hkey, hcap) != hipSuccess || dalloc(&hval, hcap) != hipSuccess) {
+      dfree(drec);
+      dfree(hkey);
+      dfree(hval);
+      return fail(SEMIPAR_E_OOM);
+    }
+    const int n = (int)total;
+    rc = SEMIPAR_OK;
+    if (hipMemcpyAsync(r->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, r->stream) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
+    if (rc == SEMIPAR_OK) {
+      k_fill_i64<<<blocks((int64_t)hcap), NT, 0, r->stream>>>(hkey, hcap, ID_EMPTY);
+      k_init_insert<<<blocks(n), NT, 0, r->stream>>>(drec, n, hkey, hval, (uint32_t)(hcap - 1),
+                                                     r->ctrl);
+      k_init_links<<<blocks(n), NT, 0, r->stream>>>(drec, n, hkey, hval, (uint32_t)(hcap - 1), r->X,
+                                                    r->nxt, r->prv, r->id, r->ctrl);
+      k_init_check<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->nxt, r->prv, r->P, c0.step,
+                                                    r->ctrl);
+      if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
+    }
+    if (rc == SEMIPAR_OK && read_ctrl(r) != SEMIPAR_OK) rc = SEMIPAR_E_HIP;
+    dfree(drec);
+    dfree(hkey);
+    dfree(hval);
+    if (rc != SEMIPAR_OK) return fail(rc);
+    if (r->ctrl_h->err != 0) return fail(SEMIPAR_E_SURFACE);
+    r->ext0 = from_key(r->ctrl_h->ext_key);
+  } else {
+    if (hipMemcpy(r->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(SEMIPAR_E_HIP);
+    *r->ctrl_h = c0;
+  }
+  if (ensure_log(r, 1 << 16) != SEMIPAR_OK) return fail(SEMIPAR_E_OOM);
+  *out = r;
+  return SEMIPAR_OK;
+}
+
+int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evolve_stats* st) {
+  if (!r || !p || p->max_steps < 0) return SEMIPAR_E_ARG;
+  if (p->screen != SEMIPAR_SCREEN_F64 && p->screen != SEMIPAR_SCREEN_F32) return SEMIPAR_E_ARG;
+  if (r->broken) return SEMIPAR_E_STATE;
+  semipar_evolve_stats zero{};
+  if (st) *st = zero;
+  if (r->n == 0 || p->max_steps == 0) {
+    if (st) {
+      st->final_step = r->ctrl_h->step;
+      st->done = 1;
+    }
+    return SEMIPAR_OK;
+  }
+  int rc = configure(r, p);
+  if (rc != SEMIPAR_OK) return rc;
+  RCCHK(read_ctrl(r));
+  const Ctrl before = *r->ctrl_h;
+  const int64_t lim64 = (int64_t)before.step + p->max_steps;
+  const int32_t step_limit = (int32_t)std::min<int64_t>(lim64, INT32_MAX - 1);
+  const int n = (int)r->n;
+  const bool ic = p->intercommute != 0;
+  const int K = p->steps_per_sync > 0 ? p->steps_per_sync : 32;
+  r->timed = (p->timed_kernel >= 0 && p->timed_kernel <= SEMIPAR_K_RESOLVE) ? p->timed_kernel : -1;
+  if (r->timed >= 0) {
+    rc = ensure_timing_events(r, K);
+    if (rc != SEMIPAR_OK) return rc;
+  }
+  double tk_ms = 0.0;
+  int64_t tk_n = 0;
+  HIPCHK(hipEventRecord(r->ev0, r->stream));
+  k_begin_min<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->ctrl);
+  // grid of the first step: the caller's cell size (kept fixed), else 1.25 x the
+  // initial element-size estimate, then adapted each step to the largest element
+  Cells cells{};
+  int set_cells = 0;
+  if (p->cell_size > 0) {
+    cells = choose_cells(r->box, p->cell_size, r->hc.tol);
+    cells.fixed = 1;
+    set_cells = 1;
+    r->cells_set = true;
+    r->cells_fixed = true;
+  } else if (!r->cells_set || r->cells_fixed) {
+    cells = choose_cells(r->box, r->ext0 > 0 ? 1.25 * r->ext0 : r->box, r->hc.tol);
+    set_cells = 1;
+    r->cells_set = true;
+    r->cells_fixed = false;
+  }
+  k_begin_set<<<1, 64, 0, r->stream>>>(r->ctrl, step_limit, p->t_end, n, cells, set_cells);
+  HIPCHK(hipGetLastError());
+  for (;;) {
+    rc = ensure_log(r, r->ctrl_h->log_n + 2 * r->cap_evt);
+    if (rc != SEMIPAR_OK) return rc;
+    const int64_t taken0 = r->ctrl_h->steps_taken;
+    // HIP events recorded inside a captured graph cannot be timed: a timed call
+    // issues its steps eagerly.
+    if (p->use_graph && r->timed < 0) {
+      if (!r->gexec || r->g_steps != K || r->g_timed != r->timed) {
+        drop_graph(r);
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < K; ++i) issue_step(r, ic, i);
+        HIPCHK(hipStreamEndCapture(r->stream, &g));
+        HIPCHK(hipGraphInstantiate(&r->gexec, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        r->g_steps = K;
+        r->g_timed = r->timed;
+      }
+      HIPCHK(hipGraphLaunch(r->gexec, r->stream));
+    } else {
+      for (int i = 0; i < K; ++i) issue_step(r, ic, i);
+      HIPCHK(hipGetLastError());
+    }
+    RCCHK(read_ctrl(r));
+    const Ctrl& c = *r->ctrl_h;
+    if (r->timed >= 0) {
+      const int64_t taken = c.steps_taken - taken0;
+      for (int64_t i = 0; i < taken && i < K; ++i) {
+        float e = 0.f;
+        HIPCHK(hipEventElapsedTime(&e, r->tev[2 * i], r->tev[2 * i + 1]));
+        tk_ms += e;
+        tk_n += 1;
+      }
+    }
+    if (c.defer) {
+      // a per-step buffer was too small: the step was not taken; grow and retake it
+      if (c.defer & 4) {
+        rc = ensure_log(r, c.log_n + 4 * r->cap_evt);
+        if (rc != SEMIPAR_OK) return rc;
+      }
+      if (c.defer & 3) {
+        rc = grow_step_caps(r, c.defer);
+        if (rc != SEMIPAR_OK) {
+          r->broken = true;
+          return rc;
+        }
+      }
+      k_clear_defer<<<1, 64, 0, r->stream>>>(r->ctrl);
+      HIPCHK(hipGetLastError());
+      RCCHK(read_ctrl(r));
+      continue;
+    }
+    if (c.done) break;
+  }
+  HIPCHK(hipEventRecord(r->ev1, r->stream));
+  HIPCHK(hipEventSynchronize(r->ev1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+  const Ctrl& a = *r->ctrl_h;
+  if (st) {
+    st->steps = a.steps_taken - before.steps_taken;
+    st->point_steps = a.point_steps - before.point_steps;
+    st->candidates = a.cand_total - before.cand_total;
+    st->confirmed = a.conf_total - before.conf_total;
+    st->accepted = a.acc_total - before.acc_total;
+    st->large_elements = a.large_total - before.large_total;
+    st->final_step = a.step;
+    st->done = 1;
+    st->elapsed_ms = ms;
+    st->timed_kernel_ms = tk_ms;
+    st->timed_kernel_launches = tk_n;
+  }
+  return SEMIPAR_OK;
+}
+
+int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], const int64_t cap[4],
+                               int64_t n[4], int32_t mem) {
+  if (!r || !n) return SEMIPAR_E_ARG;
+  if (mem != SEMIPAR_MEM_HOST && mem != SEMIPAR_MEM_DEVICE) return SEMIPAR_E_ARG;
+  n[0] = r->n;
+  n[1] = n[2] = n[3] = 0;
+  if (!out || !out[0] || r->n == 0) return SEMIPAR_OK;
+  if (!cap || cap[0] < r->n) return SEMIPAR_E_ARG;
+  RCCHK(read_ctrl(r));
+  const int s = r->ctrl_h->step;
+  const int nn = (int)r->n;
+  if (mem == SEMIPAR_MEM_DEVICE) {
+    k_emit_all<<<blocks(nn), NT, 0, r->stream>>>(r->X, nn, r->nxt, r->prv, r->id, s, out[0]);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(r->stream));
+  } else {
+    semipar_point_rec* tmp = nullptr;
+    HIPCHK(dalloc(&tmp, r->n));
+    k_emit_all<<<blocks(nn), NT, 0, r->stream>>>(r->X, nn, r->nxt, r->prv, r->id, s, tmp);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipMemcpyAsync(out[0], tmp, sizeof(semipar_point_rec) * r->n,
+                                   hipMemcpyDeviceToHost, r->stream);
+    hipError_t e3 = hipStreamSynchronize(r->stream);
+    dfree(tmp);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return SEMIPAR_E_HIP;
+  }
+  return SEMIPAR_OK;
+}
+
+int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int64_t* n) {
+  if (!r || !n || cap < 0) return SEMIPAR_E_ARG;
+  semipar_region* rr = const_cast<semipar_region*>(r);
+  RCCHK(read_ctrl(rr));
+  const int64_t total = rr->ctrl_h->log_n;
+  if (!buf) {
+    *n = total;
+    return SEMIPAR_OK;
+  }
+  std::vector<semipar_event> all((size_t)total);
+  if (total > 0) {
+    HIPCHK(hipMemcpyAsync(all.data(), rr->log, sizeof(semipar_event) * total, hipMemcpyDeviceToHost,
+                          rr->stream));
+    HIPCHK(hipStreamSynchronize(rr->stream));
+  }
+  // Listing order (the log is written in completion order within a step).
+  std::sort(all.begin(), all.end(), [](const semipar_event& a, const semipar_event& b) {
+    if (a.step != b.step) return a.step < b.step;
+    if (a.t_star != b.t_star) return a.t_star < b.t_star;
+    if (a.id_a != b.id_a) return a.id_a < b.id_a;
+    return a.id_b < b.id_b;
+  });
+  const int64_t m = std::min(total, cap);
+  if (m > 0) memcpy(buf, all.data(), sizeof(semipar_event) * m);
+  *n = m;
+  return SEMIPAR_OK;
+}
+
+}  // extern "C"

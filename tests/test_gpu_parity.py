@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar (written here): events identical bit for bit (integer/topology), positions
+within 1e-12 relative (bitwise equality expected, since both sides evaluate the same
+FP64 expressions without contraction). Every test prints the case it runs first.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1011_4046_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1011_4046_amd import semipar
+    semipar.lib()
+    return semipar
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def by_id(recs):
+    return recs[np.argsort(recs["id"], kind="stable")]
+
+
+def assert_same_state(gpu, orc):
+    g, o = by_id(gpu), by_id(orc)
+    assert np.array_equal(g["id"], o["id"])
+    assert np.array_equal(g["next_id"], o["next_id"])
+    assert np.array_equal(g["prev_id"], o["prev_id"])
+    assert np.array_equal(g["step"], o["step"])
+    for f in ("x", "x_prev"):
+        scale = max(1.0, float(np.abs(o[f]).max()))
+        err = float(np.abs(g[f] - o[f]).max()) / scale
+        assert err <= REL_TOL, (f, err)
+    # bitwise is what the design delivers; report if it ever is not
+    assert g["x"].tobytes() == o["x"].tobytes()
+    assert g["x_prev"].tobytes() == o["x_prev"].tobytes()
+
+
+def assert_same_events(ge, oe):
+    assert len(ge) == len(oe), (len(ge), len(oe))
+    assert np.array_equal(ge["step"], oe["step"])
+    assert np.array_equal(ge["id_a"], oe["id_a"])
+    assert np.array_equal(ge["id_b"], oe["id_b"])
+    assert ge.tobytes() == oe.tobytes()
+
+
+def run_gpu(S, net, steps, t_end=float("inf"), **kw):
+    r = S.Region(net["recs"], net["box"], net["cosmology"])
+    st = r.evolve(steps, t_end, **kw)
+    out = r.emit(), r.events(), st
+    r.close()
+    return out
+
+
+def run_oracle(net, steps, t_end=float("inf"), intercommute=True):
+    return O.run(net, steps, t_end, O.GRID, intercommute)
+
+
+# ---------------------------------------------------------------------------------
+def test_flat_kt_loops_no_intercommutation_closed_form(S):
+    say("case: 8 KT loops x 256, flat, 2000 steps, intercommutation off")
+    net = I.kt_loops()
+    g, ge, st = run_gpu(S, net, 2000, intercommute=False)
+    o, oe, _ = run_oracle(net, 2000, intercommute=False)
+    assert len(ge) == 0 and st["steps"] == 2000 and st["point_steps"] == 2000 * 2048
+    assert_same_state(g, o)
+
+
+@pytest.mark.parametrize("screen", [0, 1])
+def test_flat_kt_loops_full(S, screen):
+    say(f"case: 8 KT loops x 256, flat, 2000 steps, p=1, screen={'f64' if screen == 0 else 'f32'}")
+    net = I.kt_loops()
+    g, ge, st = run_gpu(S, net, 2000, screen=screen)
+    o, oe, ost = run_oracle(net, 2000)
+    assert len(oe) > 100
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+    assert st["accepted"] == ost["accepted"] and st["confirmed"] == ost["confirmed"]
+
+
+@pytest.mark.parametrize("m,seed", [(4, 0), (6, 1), (8, 2), (5, 3)])
+def test_matter_vv_small_full_run(S, m, seed):
+    say(f"case: VV {m}^3 seed {seed}, matter era, until min t >= 16")
+    net = I.vv_network(m=m, seed=seed)
+    g, ge, st = run_gpu(S, net, 100000, t_end=16.0)
+    o, oe, ost = run_oracle(net, 100000, t_end=16.0)
+    assert ost["steps"] == st["steps"] and st["steps"] > 100
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+
+
+def test_matter_vv_full_size_first_steps(S):
+    """Full-size matter-era workload (32^3 VV, ~2.4e5 points), first 30 steps, in the
+    benchmark's launch configuration (graph-captured step blocks)."""
+    say("case: VV 32^3 seed 0, matter era, 30 steps, graph")
+    net = I.vv_network()
+    g, ge, st = run_gpu(S, net, 30, use_graph=True, steps_per_sync=30)
+    o, oe, _ = run_oracle(net, 30)
+    assert len(oe) > 1000
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+
+
+def test_screen_precision_does_not_change_events_full_run(S):
+    """Property at full size: the FP32 screen only adds false positives, so the whole
+    matter-era run gives the same events and positions as the FP64 screen."""
+    say("case: VV 32^3 seed 0, matter era, 200 steps, f32 vs f64 screen")
+    net = I.vv_network()
+    a = run_gpu(S, net, 200, screen=0, use_graph=True)
+    b = run_gpu(S, net, 200, screen=1, use_graph=True)
+    assert_same_events(a[1], b[1])
+    assert a[0].tobytes() == b[0].tobytes()
+    assert b[2]["candidates"] >= a[2]["candidates"]
+
+
+def test_graph_and_eager_identical(S):
+    say("case: 8 KT loops, 600 steps, eager vs graph (K=7)")
+    net = I.kt_loops()
+    a = run_gpu(S, net, 600)
+    b = run_gpu(S, net, 600, use_graph=True, steps_per_sync=7)
+    assert_same_events(a[1], b[1])
+    assert a[0].tobytes() == b[0].tobytes()
+
+
+@pytest.mark.parametrize("cell", [1e-6, 0.9])
+def test_large_element_path(S, cell):
+    """Tiny cells (every element larger than a cell) and one huge cell (no hash at
+    all) must still find exactly the oracle's events."""
+    say(f"case: 3 KT loops x 64, flat, 300 steps, cell={cell}")
+    net = I.kt_loops(n_loops=3, n_pts=64, seed=4)
+    g, ge, st = run_gpu(S, net, 300, cell_size=cell)
+    o, oe, _ = run_oracle(net, 300)
+    assert st["large_elements"] > 0
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+
+
+def test_buffer_overflow_retakes_step(S):
+    say("case: VV 6^3, matter, tiny candidate/event buffers (deferred steps)")
+    net = I.vv_network(m=6, seed=1)
+    g, ge, st = run_gpu(S, net, 120, cand_per_point=1e-4, events_per_point=1e-4)
+    o, oe, _ = run_oracle(net, 120)
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+
+
+def test_ragged_and_degenerate_inputs(S):
+    say("case: ragged sizes: loops of 3, 5, 257 points; 2-point loop")
+    rng = np.random.default_rng(9)
+    chains = []
+    for n in (3, 5, 257, 2):
+        P = rng.uniform(0.3, 0.7, (n, 3))
+        chains.append(dict(A=P, B=P[::-1].copy(), wA=np.zeros(3), wB=np.zeros(3)))
+    net = I.make_network(chains, 1.0, 1.0 / 64, 0.0, I.FLAT)
+    g, ge, st = run_gpu(S, net, 150)
+    o, oe, _ = run_oracle(net, 150)
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+
+
+def test_empty_region(S):
+    say("case: empty region")
+    net = I.kt_loops(n_loops=1, n_pts=8)
+    r = S.Region(net["recs"][:0], 1.0, I.FLAT)
+    st = r.evolve(100)
+    assert st["steps"] == 0 and st["point_steps"] == 0
+    assert len(r.emit()) == 0 and len(r.events()) == 0
+    r.close()
+
+
+def test_surface_errors(S):
+    say("case: invalid surfaces")
+    net = I.kt_loops(n_loops=2, n_pts=16)
+    recs = net["recs"].copy()
+    recs["id"][3] = recs["id"][4]
+    with pytest.raises(S.SemiparError) as e:
+        S.Region(recs, 1.0, I.FLAT)
+    assert e.value.code == -2
+    recs = net["recs"].copy()
+    recs["next_id"][2] = 12345
+    with pytest.raises(S.SemiparError):
+        S.Region(recs, 1.0, I.FLAT)
+
+
+def test_device_resident_input_and_output(S):
+    import torch
+    say("case: device-resident records in and out (VV 8^3, matter, 80 steps)")
+    net = I.vv_network(m=8, seed=5)
+    raw = torch.from_numpy(net["recs"].view(np.uint8).copy()).cuda()
+    r = S.Region(raw, net["box"], net["cosmology"])
+    st = r.evolve(80)
+    out = torch.zeros_like(raw)
+    n = r.emit_device(out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().view(I.REC_DTYPE)[:n]
+    ge = r.events()
+    r.close()
+    o, oe, _ = run_oracle(net, 80)
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+
+
+def test_matter_static_string_bitwise_static_gpu(S):
+    say("case: static straight string, matter era")
+    chain, delta = I.straight_string(32, 4.0, v=0.0)
+    net = I.make_network([chain], 4.0, delta, 8.0, I.MATTER)
+    g, ge, st = run_gpu(S, net, 100)
+    g = by_id(g)
+    n = int(g["step"][0])
+    assert np.all(g["x"][:, 0] == (np.arange(32) + n / 2) * delta)
+    assert np.all(g["x"][:, 1:3] == 0.0)
+    assert np.all(g["x"][:, 3] == 8.0 + n * delta / 2)
+
+
+def test_repeat_runs_identical(S):
+    say("case: determinism, VV 8^3 twice")
+    net = I.vv_network(m=8, seed=7)
+    a = run_gpu(S, net, 150)
+    b = run_gpu(S, net, 150)
+    assert a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
