@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--m", type=int, default=32, help="lattice size of the VV network")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", type=int, default=1, help="also time the plain per-step path")
+    ap.add_argument("--max-steps", type=int, default=10 ** 7,
+                    help="cap on lattice steps per run (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
@@ -71,7 +73,7 @@ def main():
 
     for w in range(args.warmup):
         r = fresh()
-        st = r.evolve(10 ** 7, t_end, **kw)
+        st = r.evolve(args.max_steps, t_end, **kw)
         r.close()
         print(f"bench: warmup {w}: {st['steps']} steps, {st['elapsed_ms']:.1f} ms",
               file=sys.stderr, flush=True)
@@ -81,7 +83,7 @@ def main():
     stats = []
     t_start = time.perf_counter()
     for r in regions:
-        stats.append(r.evolve(10 ** 7, t_end, **kw))
+        stats.append(r.evolve(args.max_steps, t_end, **kw))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     for r in regions:
@@ -96,7 +98,7 @@ def main():
     # recorded on the region's stream during one more full run (events cannot be timed
     # inside a captured graph, so this run issues its steps eagerly)
     r = fresh()
-    tst = r.evolve(10 ** 7, t_end, screen=screen, use_graph=False,
+    tst = r.evolve(args.max_steps, t_end, screen=screen, use_graph=False,
                    steps_per_sync=args.sync_steps, timed_kernel=S.K_EVOLVE)
     r.close()
     ev_ms = tst["timed_kernel_ms"]
@@ -113,7 +115,7 @@ def main():
         r = fresh()
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        sp = r.evolve(10 ** 7, t_end, screen=S.SCREEN_F64, use_graph=False, steps_per_sync=1)
+        sp = r.evolve(args.max_steps, t_end, screen=S.SCREEN_F64, use_graph=False, steps_per_sync=1)
         torch.cuda.synchronize()
         te = time.perf_counter() - ts
         r.close()

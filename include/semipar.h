@@ -141,8 +141,10 @@ typedef struct semipar_evolve_params {
   double events_per_point;
   int32_t timed_kernel;   /* -1: none; else one of SEMIPAR_K_*: HIP events are recorded
                              around every launch of that kernel and the summed device
-                             time is returned in the stats (measurement only) */
-  int32_t reserved1;
+                             time is returned in the stats (measurement only; a timed
+                             call issues its steps without graphs) */
+  int32_t screen_split;   /* threads sharing the 14 cell lookups of one element in the
+                             screen: 1, 2, 7 or 14 (0 = 7). Performance only */
 } semipar_evolve_params;
 
 /* kernels that can be timed through semipar_evolve_params.timed_kernel */

@@ -371,15 +371,17 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
                                                 const int32_t* __restrict__ epos,
                                                 const int32_t* __restrict__ loc,
                                                 const int32_t* __restrict__ tile_tot, int ntiles,
+                                                int32_t* __restrict__ toff,
                                                 const void* __restrict__ ebox,
-                                                int32_t* __restrict__ scell,
-                                                int32_t* __restrict__ sid,
+                                                int2* __restrict__ sent,
                                                 void* __restrict__ sbox, HashCfg hc,
                                                 const Ctrl* ctrl) {
   if (ctrl->done) return;
   __shared__ int32_t s_toff[MAX_TILES + 1];
   __shared__ int32_t s_tmp[NT];
   block_tile_offsets(tile_tot, ntiles, s_toff, s_tmp);
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i <= ntiles; i += NT) toff[i] = s_toff[i];
   const int nc = ctrl->cells.nc;
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k >= n) return;
@@ -387,8 +389,7 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
   if (c < 0) return;
   const uint32_t b = bucket_of(nc, hc.bmask, c & 1023, (c >> 10) & 1023, (c >> 20) & 1023);
   const int pos = bucket_start(loc, s_toff, b) + epos[k];
-  scell[pos] = c;
-  sid[pos] = k;
+  sent[pos] = make_int2(c, k);
   if constexpr (SCR == 1) {
     const double4* src = (const double4*)ebox + (size_t)k * 2;
     double4* dst = (double4*)sbox + (size_t)pos * 2;
@@ -447,36 +448,51 @@ __device__ __forceinline__ bool box_overlap(const SBox<T>& a, const SBox<T>& b, 
          a.v[3] <= b.v[7] && b.v[3] <= a.v[7];
 }
 
-constexpr int SBUF = 2048;  // candidates staged in LDS per block
+constexpr int SBUF = 256;  // candidates staged in LDS per block (more go straight to memory)
 
-// Half-shell screen over the cell-sorted elements: thread q takes the element at
-// sorted position q and tests the later entries of its own cell and every entry of the
-// 13 forward neighbour cells; threads past the hashed elements take one large element
-// each. Every normal element also tests every large element; two large elements are
-// tested by the one of smaller slot. Each unordered pair is therefore tested once.
-template <int SCR>
-__global__ __launch_bounds__(NT) void k_screen(int n, const int32_t* __restrict__ scell,
-                                               const int32_t* __restrict__ sid,
+// Workgroups are handed to the 8 XCDs of the chip in turn (workgroup i to XCD i mod 8),
+// each XCD with its own L2. xcd_block() renumbers a 1-D grid of 8*ceil(total/8)
+// workgroups so that XCD x runs the logical blocks [x*per, (x+1)*per): consecutive logical
+// blocks then share one L2. Returns a value >= total for the padding workgroups.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_block(int total) {
+  const int lin = blockIdx.x;
+  const int per = (total + N_XCD - 1) / N_XCD;
+  return (lin % N_XCD) * per + lin / N_XCD;
+}
+inline int xcd_grid(int total) { return (total + N_XCD - 1) / N_XCD * N_XCD; }
+
+// Half-shell screen over the cell-sorted elements. The element at sorted position q is
+// tested against the later entries of its own cell (slice 0) and every entry of the 13
+// forward neighbour cells (slices 1..13). G threads share an element, each taking the
+// slices [g*14/G, (g+1)*14/G); thread g = 0 also tests the element against every large
+// element (two large ones: by the one of smaller slot). Threads past the hashed
+// elements take one large element each. Each unordered pair is tested exactly once.
+// Logical block = (element block, g), renumbered per XCD (xcd_block).
+template <int SCR, int G>
+__global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ sent,
                                                const void* __restrict__ sbox,
                                                const int32_t* __restrict__ nxt,
                                                const int32_t* __restrict__ prv,
                                                const int32_t* __restrict__ loc,
-                                               const int32_t* __restrict__ tile_tot, int ntiles,
+                                               const int32_t* __restrict__ toff, int ntiles,
                                                const LargeBox* __restrict__ large, HashCfg hc,
                                                sp::Period P, int2* __restrict__ cand, int cap,
-                                               Ctrl* ctrl) {
+                                               int nblk, Ctrl* ctrl) {
   if (ctrl->done) return;
+  const int lid = xcd_block(nblk * G);
+  if (lid >= nblk * G) return;
+  const int eblk = lid / G, g = lid % G;
+  const int o_beg = g * 14 / G, o_end = (g + 1) * 14 / G;
   using T = typename std::conditional<SCR == 1, double, float>::type;
   __shared__ int2 sbuf[SBUF];
-  __shared__ int32_t s_toff[MAX_TILES + 1];
-  __shared__ int32_t s_tmp[NT];
   __shared__ int s_cnt, s_base;
   if (threadIdx.x == 0) s_cnt = 0;
-  block_tile_offsets(tile_tot, ntiles, s_toff, s_tmp);
+  __syncthreads();
   const Cells cs = ctrl->cells;
-  const int q = blockIdx.x * NT + threadIdx.x;
-  const int n_norm = s_toff[ntiles];
   const int nl = ctrl->n_large;
+  const int q = eblk * NT + threadIdx.x;
+  const int n_norm = toff[ntiles];
   auto push = [&](int a, int b) {
     const int i = atomicAdd(&s_cnt, 1);
     if (i < SBUF)
@@ -484,66 +500,74 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int32_t* __restrict_
     else
       push_cand(ctrl, cand, cap, a, b);
   };
-  if (q < n_norm + nl) {
+  if (q < n_norm + nl && (q < n_norm || g == 0)) {
     int k;
     bool own_large;
     double wl[3], ex[3], tlo, thi;  // wrapped box of the element (for large partners)
     if (q < n_norm) {
       own_large = false;
-      const int32_t c = scell[q];
-      k = sid[q];
+      const int2 ent = sent[q];
+      const int32_t c = ent.x;
+      k = ent.y;
       const int nk = nxt[k], pk = prv[k];
       const SBox<T> me = load_sbox<T>(sbox, q);
       const int cx = c & 1023, cy = (c >> 10) & 1023, cz = (c >> 20) & 1023;
-      const int ccx[3] = {cx, cy, cz};
-      for (int i = 0; i < 3; ++i) {
-        wl[i] = (double)ccx[i] * cs.h + (double)me.v[i];
-        ex[i] = (double)me.v[4 + i] - (double)me.v[i];
+      constexpr int MAXS = (14 + G - 1) / G;
+      int rb[MAXS], re[MAXS], rc[MAXS];
+#pragma unroll
+      for (int i = 0; i < MAXS; ++i) {
+        const int o = o_beg + i;
+        rb[i] = 0;
+        re[i] = 0;
+        rc[i] = 0;
+        if (o < o_end) {
+          const int dx = o == 0 ? 0 : (o < 10 ? 1 : 0);
+          const int dy = o == 0 ? 0 : (o < 10 ? (o - 1) / 3 - 1 : (o < 13 ? 1 : 0));
+          const int dz = o == 0 ? 0 : (o < 10 ? (o - 1) % 3 - 1 : (o < 13 ? o - 11 : 1));
+          int x = cx + dx, y = cy + dy, z = cz + dz;
+          x = x < 0 ? x + cs.nc : (x >= cs.nc ? x - cs.nc : x);
+          y = y < 0 ? y + cs.nc : (y >= cs.nc ? y - cs.nc : y);
+          z = z < 0 ? z + cs.nc : (z >= cs.nc ? z - cs.nc : z);
+          const uint32_t b = bucket_of(cs.nc, hc.bmask, x, y, z);
+          rb[i] = o == 0 ? q + 1 : bucket_start(loc, toff, b);
+          re[i] = bucket_start(loc, toff, b + 1);
+          rc[i] = (int)pack_cell(x, y, z);
+        }
       }
-      if constexpr (SCR == 1) {
-        tlo = me.v[3];
-        thi = me.v[7];
-      } else {
-        tlo = (double)me.v[3] + hc.tref;
-        thi = (double)me.v[7] + hc.tref;
+      if (g == 0) {
+        for (int i = 0; i < 3; ++i) {
+          wl[i] = (double)(i == 0 ? cx : (i == 1 ? cy : cz)) * cs.h + (double)me.v[i];
+          ex[i] = (double)me.v[4 + i] - (double)me.v[i];
+        }
+        if constexpr (SCR == 1) {
+          tlo = me.v[3];
+          thi = me.v[7];
+        } else {
+          tlo = (double)me.v[3] + hc.tref;
+          thi = (double)me.v[7] + hc.tref;
+        }
       }
       const T tl = SCR == 1 ? (T)hc.tol : (T)cs.marg32;
       const T hh = SCR == 1 ? (T)cs.h : (T)cs.h32;
-      for (int o = 0; o < 14; ++o) {
-        int dx, dy, dz;
-        if (o == 0) {
-          dx = dy = dz = 0;
-        } else if (o < 10) {
-          dx = 1;
-          dy = (o - 1) / 3 - 1;
-          dz = (o - 1) % 3 - 1;
-        } else if (o < 13) {
-          dx = 0;
-          dy = 1;
-          dz = o - 11;
-        } else {
-          dx = 0;
-          dy = 0;
-          dz = 1;
-        }
-        int x = cx + dx, y = cy + dy, z = cz + dz;
-        x = x < 0 ? x + cs.nc : (x >= cs.nc ? x - cs.nc : x);
-        y = y < 0 ? y + cs.nc : (y >= cs.nc ? y - cs.nc : y);
-        z = z < 0 ? z + cs.nc : (z >= cs.nc ? z - cs.nc : z);
-        const uint32_t b = bucket_of(cs.nc, hc.bmask, x, y, z);
-        int beg = bucket_start(loc, s_toff, b);
-        const int end = bucket_start(loc, s_toff, b + 1);
-        if (o == 0) beg = q + 1;
-        const int32_t pc = (int32_t)pack_cell(x, y, z);
+#pragma unroll
+      for (int i = 0; i < MAXS; ++i) {
+        const int o = o_beg + i;
+        if (o >= o_end || rb[i] >= re[i]) continue;
+        const int dx = o == 0 ? 0 : (o < 10 ? 1 : 0);
+        const int dy = o == 0 ? 0 : (o < 10 ? (o - 1) / 3 - 1 : (o < 13 ? 1 : 0));
+        const int dz = o == 0 ? 0 : (o < 10 ? (o - 1) % 3 - 1 : (o < 13 ? o - 11 : 1));
+        const int32_t pc = rc[i];
         const T sx = (T)dx * hh, sy = (T)dy * hh, sz = (T)dz * hh;
-        int q2 = beg;
+        const int end = re[i];
+        int q2 = rb[i];
         for (; q2 + 4 <= end; q2 += 4) {
           int32_t c4[4], m4[4];
           SBox<T> b4[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            c4[u] = scell[q2 + u];
-            m4[u] = sid[q2 + u];
+            const int2 e = sent[q2 + u];
+            c4[u] = e.x;
+            m4[u] = e.y;
             b4[u] = load_sbox<T>(sbox, q2 + u);
           }
 #pragma unroll
@@ -552,8 +576,9 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int32_t* __restrict_
               push(k, m4[u]);
         }
         for (; q2 < end; ++q2) {
-          if (scell[q2] != pc) continue;
-          const int m = sid[q2];
+          const int2 e = sent[q2];
+          if (e.x != pc) continue;
+          const int m = e.y;
           if (m == nk || m == pk) continue;
           if (box_overlap(me, load_sbox<T>(sbox, q2), sx, sy, sz, tl)) push(k, m);
         }
@@ -569,17 +594,20 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int32_t* __restrict_
       tlo = own.tlo;
       thi = own.thi;
     }
-    const int nk = nxt[k], pk = prv[k];
-    for (int a = 0; a < nl; ++a) {
-      const LargeBox lb = large[a];
-      const int m = lb.slot;
-      if (m == k) continue;
-      if (own_large && m < k) continue;
-      if (m == nk || m == pk) continue;
-      const double tt = hc.tol_t;
-      bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
-      for (int i = 0; i < 3 && ov; ++i) ov = wrap_overlap(wl[i], ex[i], lb.wl[i], lb.ext[i], P, hc.tolL);
-      if (ov) push(k, m);
+    if (g == 0 && nl > 0) {
+      const int nk = nxt[k], pk = prv[k];
+      for (int a = 0; a < nl; ++a) {
+        const LargeBox lb = large[a];
+        const int m = lb.slot;
+        if (m == k) continue;
+        if (own_large && m < k) continue;
+        if (m == nk || m == pk) continue;
+        const double tt = hc.tol_t;
+        bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
+        for (int i = 0; i < 3 && ov; ++i)
+          ov = wrap_overlap(wl[i], ex[i], lb.wl[i], lb.ext[i], P, hc.tolL);
+        if (ov) push(k, m);
+      }
     }
   }
   __syncthreads();
@@ -1056,8 +1084,8 @@ struct semipar_region {
   int32_t *ecell = nullptr, *epos = nullptr;
   LargeBox* large = nullptr;
   HashCfg hc{};
-  int32_t *cnt = nullptr, *loc = nullptr, *tile_tot = nullptr;
-  int32_t *scell = nullptr, *sid = nullptr;  // cell-sorted element cells and slots
+  int32_t *cnt = nullptr, *loc = nullptr, *tile_tot = nullptr, *toff = nullptr;
+  int2* sent = nullptr;                      // cell-sorted (cell, slot) of each element
   void* sbox = nullptr;                      // cell-sorted screen boxes
   int ntiles = 0;
   int2* cand = nullptr;
@@ -1076,6 +1104,7 @@ struct semipar_region {
   int g_steps = 0;
   int g_timed = -1;
   bool cells_set = false;  // the device grid has been chosen (adaptive runs keep it)
+  int split = 7;           // screen threads per element (1, 2, 7 or 14)
   bool cells_fixed = false;
   // measurement: HIP events around every launch of one kernel (timed_kernel)
   int timed = -1;
@@ -1092,8 +1121,8 @@ void free_step_buffers(semipar_region* r) {
   dfree(r->cnt);
   dfree(r->loc);
   dfree(r->tile_tot);
-  dfree(r->scell);
-  dfree(r->sid);
+  dfree(r->toff);
+  dfree(r->sent);
   dfree(r->sbox);
   dfree(r->cand);
   dfree(r->ev);
@@ -1101,7 +1130,8 @@ void free_step_buffers(semipar_region* r) {
   dfree(r->used);
   dfree(r->evs);
   r->ebox = nullptr;
-  r->ecell = r->epos = r->cnt = r->loc = r->tile_tot = r->scell = r->sid = r->used = nullptr;
+  r->ecell = r->epos = r->cnt = r->loc = r->tile_tot = r->toff = r->used = nullptr;
+  r->sent = nullptr;
   r->sbox = nullptr;
   r->large = nullptr;
   r->cand = nullptr;
@@ -1176,8 +1206,8 @@ int configure(semipar_region* r, const semipar_evolve_params* p) {
   HIPCHK(dalloc(&r->cnt, r->hc.B));
   HIPCHK(dalloc(&r->loc, (size_t)r->hc.B + 1));
   HIPCHK(dalloc(&r->tile_tot, r->ntiles));
-  HIPCHK(dalloc(&r->scell, cap));
-  HIPCHK(dalloc(&r->sid, cap));
+  HIPCHK(dalloc(&r->toff, (size_t)r->ntiles + 1));
+  HIPCHK(dalloc(&r->sent, cap));
   HIPCHK(hipMalloc(&r->sbox, (size_t)cap * 8 * (screen == 1 ? sizeof(double) : sizeof(float))));
   HIPCHK(hipMemset(r->cnt, 0, sizeof(int32_t) * r->hc.B));
   HIPCHK(hipMemset(r->loc, 0, sizeof(int32_t) * ((size_t)r->hc.B + 1)));
@@ -1238,6 +1268,31 @@ int grow_step_caps(semipar_region* r, int defer) {
   return SEMIPAR_OK;
 }
 
+template <int SCR, int G>
+void launch_screen_t(semipar_region* r, int n, int nb) {
+  k_screen<SCR, G><<<xcd_grid(nb * G), NT, 0, r->stream>>>(
+      n, r->sent, r->sbox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc, r->P,
+      r->cand, (int)r->cap_cand, nb, r->ctrl);
+}
+
+// Screen launch: precision (FP64 / FP32 boxes) and threads per element (split).
+void launch_screen(semipar_region* r, int n, int nb) {
+  const int g = r->split;
+  if (r->screen == 1) {
+    if (g == 1) launch_screen_t<1, 1>(r, n, nb);
+    else if (g == 7) launch_screen_t<1, 7>(r, n, nb);
+    else if (g == 14) launch_screen_t<1, 14>(r, n, nb);
+    else if (g == 2) launch_screen_t<1, 2>(r, n, nb);
+    else launch_screen_t<1, 7>(r, n, nb);
+  } else {
+    if (g == 1) launch_screen_t<2, 1>(r, n, nb);
+    else if (g == 7) launch_screen_t<2, 7>(r, n, nb);
+    else if (g == 14) launch_screen_t<2, 14>(r, n, nb);
+    else if (g == 2) launch_screen_t<2, 2>(r, n, nb);
+    else launch_screen_t<2, 7>(r, n, nb);
+  }
+}
+
 // Issue one lattice step (all kernels) on the region's stream. i: index of the step in
 // its block (selects the timing-event pair when a kernel is timed).
 void issue_step(semipar_region* r, bool intercommute, int i) {
@@ -1275,21 +1330,14 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
     mark(r, SEMIPAR_K_SCAN, 2 * i + 1);
     mark(r, SEMIPAR_K_SCATTER, 2 * i);
     if (r->screen == 1)
-      k_scatter<1><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->tile_tot, r->ntiles, r->ebox, r->scell,
-                                     r->sid, r->sbox, r->hc, r->ctrl);
+      k_scatter<1><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->tile_tot, r->ntiles, r->toff, r->ebox, r->sent,
+                                     r->sbox, r->hc, r->ctrl);
     else
-      k_scatter<2><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->tile_tot, r->ntiles, r->ebox, r->scell,
-                                     r->sid, r->sbox, r->hc, r->ctrl);
+      k_scatter<2><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->tile_tot, r->ntiles, r->toff, r->ebox, r->sent,
+                                     r->sbox, r->hc, r->ctrl);
     mark(r, SEMIPAR_K_SCATTER, 2 * i + 1);
     mark(r, SEMIPAR_K_SCREEN, 2 * i);
-    if (r->screen == 1)
-      k_screen<1><<<nb, NT, 0, s>>>(n, r->scell, r->sid, r->sbox, r->nxt, r->prv, r->loc, r->tile_tot,
-                                    r->ntiles, r->large, r->hc, r->P, r->cand, (int)r->cap_cand,
-                                    r->ctrl);
-    else
-      k_screen<2><<<nb, NT, 0, s>>>(n, r->scell, r->sid, r->sbox, r->nxt, r->prv, r->loc, r->tile_tot,
-                                    r->ntiles, r->large, r->hc, r->P, r->cand, (int)r->cap_cand,
-                                    r->ctrl);
+    launch_screen(r, n, nb);
     mark(r, SEMIPAR_K_SCREEN, 2 * i + 1);
     mark(r, SEMIPAR_K_CONFIRM, 2 * i);
     k_confirm<<<512, NT, 0, s>>>(r->X, r->nxt, r->id, r->P, r->cand, (int)r->cap_cand, r->ev,
@@ -1507,6 +1555,12 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   const int n = (int)r->n;
   const bool ic = p->intercommute != 0;
   const int K = p->steps_per_sync > 0 ? p->steps_per_sync : 32;
+  {
+    const int sp_ = p->screen_split;
+    const int split = (sp_ == 1 || sp_ == 2 || sp_ == 7 || sp_ == 14) ? sp_ : 7;
+    if (split != r->split) drop_graph(r);
+    r->split = split;
+  }
   r->timed = (p->timed_kernel >= 0 && p->timed_kernel <= SEMIPAR_K_RESOLVE) ? p->timed_kernel : -1;
   if (r->timed >= 0) {
     rc = ensure_timing_events(r, K);

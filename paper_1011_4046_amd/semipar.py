@@ -49,7 +49,7 @@ class EvolveParams(ctypes.Structure):
                 ("cell_size", ctypes.c_double), ("steps_per_sync", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("cand_per_point", ctypes.c_double),
                 ("events_per_point", ctypes.c_double), ("timed_kernel", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32)]
+                ("screen_split", ctypes.c_int32)]
 
 
 class EvolveStats(ctypes.Structure):
@@ -145,10 +145,11 @@ class Region:
 
     def evolve(self, max_steps, t_end=float("inf"), screen=SCREEN_F64, intercommute=True,
                cell_size=0.0, steps_per_sync=0, use_graph=False, cand_per_point=0.0,
-               events_per_point=0.0, timed_kernel=-1):
+               events_per_point=0.0, timed_kernel=-1, screen_split=0):
         p = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
                          float(cell_size), int(steps_per_sync), int(bool(use_graph)),
-                         float(cand_per_point), float(events_per_point), int(timed_kernel), 0)
+                         float(cand_per_point), float(events_per_point), int(timed_kernel),
+                         int(screen_split))
         st = EvolveStats()
         _check(lib().region_evolve(self.h, ctypes.byref(p), ctypes.byref(st)), "region_evolve")
         return st.as_dict()

@@ -128,6 +128,16 @@ def test_screen_precision_does_not_change_events_full_run(S):
     assert b[2]["candidates"] >= a[2]["candidates"]
 
 
+@pytest.mark.parametrize("split", [1, 7, 14])
+def test_screen_split_variants(S, split):
+    say(f"case: VV 8^3 seed 2, matter era, 150 steps, screen split {split}")
+    net = I.vv_network(m=8, seed=2)
+    g, ge, st = run_gpu(S, net, 150, screen_split=split)
+    o, oe, _ = run_oracle(net, 150)
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+
+
 def test_graph_and_eager_identical(S):
     say("case: 8 KT loops, 600 steps, eager vs graph (K=7)")
     net = I.kt_loops()
