@@ -95,21 +95,41 @@ typedef struct semipar_surface {
   int32_t mem;
 } semipar_surface;
 
+/* Record flags (field `flags` of semipar_point_rec). */
+#define SEMIPAR_FLAG_HAS_R 1  /* r, r_prev hold the right neighbour's vertices on slices
+                                 step and step-1 (captured when the point stopped) */
+#define SEMIPAR_FLAG_FROZEN 2 /* the point stopped in this region; bits 8..15 hold
+                                 face + 1 (0: no owning face, e.g. a cut string end) */
+#define SEMIPAR_FLAG_ACTIVE 4 /* the point was still advancing when evolution stopped */
+
 /* Region description.
  *   cosmology  SEMIPAR_FLAT, SEMIPAR_MATTER (a ∝ eta^2, H = 2/eta) or
  *              SEMIPAR_RADIATION (a ∝ eta, H = 1/eta); conformal time eta = t
  *   box        side L of the periodic cube (> 0)
  *   capacity   maximum number of points (0 = number of input records)
+ *   bounded    0: the whole periodic volume, every point advances every step.
+ *              1: one 4-cube of the spacetime tiling (Section "Geometry"): generators
+ *              g/2 (1,1,1,1), g/2 (1,-1,-1,1), g/2 (-1,1,-1,1), g/2 (-1,-1,1,1) in
+ *              (x, y, z, tau), tau = sqrt(3) t; generator coordinates
+ *              c = H^T (P - origin) / (2 g); the region is floor(c) == idx. Point k
+ *              advances at step n only while the earliest point of its next diamond,
+ *              X[n-1][next k], lies in the region and its neighbours' inputs exist;
+ *              otherwise it stops and is emitted on the face its diamond leaves by.
+ *              Links may dangle (next_id/prev_id = -1).
+ *   idx, origin, inv2g  region index, lattice origin (x, y, z, tau) and 1/(2 g)
  *   stream     hipStream_t to run on. NULL: the library creates its own blocking
  *              stream of default priority (ordered against the null stream), since
  *              the null stream cannot be captured into a graph. All work of the
  *              region is ordered on this stream. */
 typedef struct semipar_region_desc {
   int32_t cosmology;
-  int32_t reserved0;
+  int32_t bounded;
   double box;
   int64_t capacity;
   void* stream;
+  int32_t idx[4];
+  double origin[4];
+  double inv2g;
 } semipar_region_desc;
 
 /* Evolution parameters.
@@ -179,7 +199,8 @@ typedef struct semipar_region semipar_region;
  *   d, in[0..n_in)  description and surfaces; all records must sit on one slice
  *   out             receives the new region (owned by the caller until
  *                   region_destroy)
- * Every point must have both neighbours among the records. Errors: SEMIPAR_E_ARG,
+ * In a whole-volume region every point must have both neighbours among the records.
+ * Errors: SEMIPAR_E_ARG,
  * SEMIPAR_E_SURFACE, SEMIPAR_E_OOM, SEMIPAR_E_HIP; *out is NULL on error. An empty
  * input (n_in = 0 or all n = 0) gives a valid empty region. */
 int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surface* in, int n_in,
@@ -197,6 +218,9 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
 /* Write the region's output surfaces (paper: pass on what lies on each final
  * surface). A whole-volume region has one output surface, the current slice: every
  * point goes to out[0] (x = current slice, x_prev = previous slice); n[1..3] = 0.
+ * A bounded region writes each stopped point to out[f], f its face (flags FROZEN,
+ * HAS_R when r holds the right neighbour's inputs); points without an owning face and
+ * points still active (ACTIVE, when max_steps ended the call) go to out[0].
  * Two-call pattern: with out[f] == NULL the counts are returned in n[f]. cap[f] is
  * the capacity of out[f] in records; a short buffer gives SEMIPAR_E_ARG. mem says
  * whether the out pointers are host or device memory. Records are in slot order. */

@@ -32,6 +32,7 @@ EVT = np.dtype([
 ])
 
 GRID, BRUTE = 0, 1
+FLAG_HAS_R, FLAG_FROZEN, FLAG_ACTIVE = 1, 2, 4
 
 
 def build(force: bool = False) -> str:
@@ -82,6 +83,12 @@ def lib():
         L.orc_tri_tri.restype = ctypes.c_int
         L.orc_last_confirmed.argtypes = [P, P, P, P]
         L.orc_last_confirmed.restype = i64
+        L.orc_create_bounded.argtypes = [P, i64, dbl, ctypes.c_int, dbl, P, ctypes.POINTER(P)]
+        L.orc_create_bounded.restype = ctypes.c_int
+        L.orc_region_coords.argtypes = [P, P, P]
+        L.orc_region_coords.restype = None
+        L.orc_active.argtypes = [P]
+        L.orc_active.restype = i64
         L.orc_threads.argtypes = []
         L.orc_threads.restype = ctypes.c_int
         _lib = L
@@ -93,14 +100,23 @@ def _ptr(a):
 
 
 class OracleRegion:
-    """Whole-volume region evolved by the oracle (lockstep lattice, periodic box)."""
+    """Region evolved by the oracle (lockstep lattice, periodic box).
 
-    def __init__(self, recs, box, cosmology, hcoef):
+    With ``geom`` = (V[4], inv2g, idx[4]) the region is one 4-cube of the tiling:
+    points stop when their next diamond's earliest point leaves it."""
+
+    def __init__(self, recs, box, cosmology, hcoef, geom=None):
         recs = np.ascontiguousarray(recs, dtype=REC)
         self._keep = recs
         h = ctypes.c_void_p()
-        rc = lib().orc_create(_ptr(recs), len(recs), float(box), int(cosmology), float(hcoef),
-                              ctypes.byref(h))
+        if geom is None:
+            rc = lib().orc_create(_ptr(recs), len(recs), float(box), int(cosmology),
+                                  float(hcoef), ctypes.byref(h))
+        else:
+            g = np.ascontiguousarray(geom, dtype=np.float64)
+            assert g.shape == (9,)
+            rc = lib().orc_create_bounded(_ptr(recs), len(recs), float(box), int(cosmology),
+                                          float(hcoef), _ptr(g), ctypes.byref(h))
         if rc != 0:
             raise ValueError(f"oracle rejected the surface (code {rc})")
         self.h = h
@@ -141,6 +157,17 @@ class OracleRegion:
     def step(self):
         return lib().orc_step(self.h)
 
+    @property
+    def active(self):
+        return lib().orc_active(self.h)
+
+    def coords(self, P):
+        """Generator coordinates of a spacetime point (x, y, z, t)."""
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        c = np.zeros(4)
+        lib().orc_region_coords(self.h, _ptr(P), _ptr(c))
+        return c
+
     def band_candidates(self, search=GRID):
         """Exact-overlap candidate id pairs of the current band (no state change)."""
         n = lib().orc_band_candidates(self.h, int(search), None, 0)
@@ -161,9 +188,10 @@ class OracleRegion:
 
 
 def run(net, steps, t_end=float("inf"), search=GRID, intercommute=True):
-    """Convenience: evolve a generated network and return (records, events, stats)."""
+    """Convenience: evolve a generated network (or region, when it carries "geom") and
+    return (records, events, stats)."""
     hc = {0: 0.0, 1: 2.0, 2: 1.0}[net["cosmology"]]
-    r = OracleRegion(net["recs"], net["box"], net["cosmology"], hc)
+    r = OracleRegion(net["recs"], net["box"], net["cosmology"], hc, net.get("geom"))
     r.evolve(steps, t_end, search, intercommute)
     out = (r.read(), r.events(), r.stats())
     r.close()

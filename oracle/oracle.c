@@ -54,6 +54,11 @@
 #define ORC_E_SURFACE (-2)
 #define ORC_E_OOM (-3)
 
+/* record flags */
+#define FLAG_HAS_R 1  /* r, r_prev hold the right neighbour's vertices on slices step, step-1 */
+#define FLAG_FROZEN 2 /* the point stopped in this region; (face + 1) << 8 names the face */
+#define FLAG_ACTIVE 4 /* the point was still advancing when the evolution stopped */
+
 typedef struct {
   int64_t id, next_id, prev_id;
   int32_t step, flags;
@@ -88,6 +93,17 @@ typedef struct {
   /* event log */
   orc_event *log;
   int64_t nlog, caplog;
+  /* bounded region (one 4-cube of the tiling); all fields unused when bounded == 0 */
+  int bounded;
+  double V[4];     /* lattice origin (x, y, z, tau) of the tiling */
+  double inv2g;    /* 1 / (2 g), g the generator scale */
+  double sqrt3;    /* tau = sqrt(3) t */
+  int64_t idx[4];  /* region index */
+  int32_t* fstep;  /* slice at which the point froze, INT32_MAX while active */
+  int32_t* face;   /* face through which a frozen point's next diamond leaves */
+  unsigned char *adv, *valid; /* advanced this step / element of this band exists */
+  orc_rec* frz;    /* record captured when the point froze */
+  int64_t n_active;
   /* confirmed events of the most recent step, in key order (for tests) */
   orc_cand_event *last_conf;
   int64_t n_last_conf;
@@ -229,13 +245,18 @@ void orc_destroy(orc_region* r) {
   free(r->hi);
   free(r->log);
   free(r->last_conf);
+  free(r->fstep);
+  free(r->face);
+  free(r->adv);
+  free(r->valid);
+  free(r->frz);
   free(r);
 }
 
 /* Whole-volume region: every point must have both neighbours present and all records
  * must sit on the same slice. */
-int orc_create(const orc_rec* recs, int64_t n, double box, int cosmology, double hcoef,
-               orc_region** out) {
+static int create_impl(const orc_rec* recs, int64_t n, double box, int cosmology, double hcoef,
+                       int bounded, orc_region** out) {
   *out = NULL;
   if (n < 0 || !(box > 0.0)) return ORC_E_ARG;
   orc_region* r = (orc_region*)calloc(1, sizeof(orc_region));
@@ -256,9 +277,14 @@ int orc_create(const orc_rec* recs, int64_t n, double box, int cosmology, double
   r->hi = malloc(sizeof(double[4]) * nn);
   r->caplog = 1024;
   r->log = (orc_event*)malloc(sizeof(orc_event) * r->caplog);
+  r->fstep = (int32_t*)malloc(sizeof(int32_t) * nn);
+  r->face = (int32_t*)malloc(sizeof(int32_t) * nn);
+  r->adv = (unsigned char*)malloc(nn);
+  r->valid = (unsigned char*)malloc(nn);
+  r->frz = (orc_rec*)calloc((size_t)nn, sizeof(orc_rec));
   idslot* map = (idslot*)malloc(sizeof(idslot) * nn);
   if (!r->id || !r->nx || !r->pv || !r->cur || !r->prv || !r->nw || !r->vert || !r->lo || !r->hi ||
-      !r->log || !map) {
+      !r->log || !map || !r->fstep || !r->face || !r->adv || !r->valid || !r->frz) {
     free(map);
     orc_destroy(r);
     return ORC_E_OOM;
@@ -277,14 +303,19 @@ int orc_create(const orc_rec* recs, int64_t n, double box, int cosmology, double
   for (int64_t k = 1; k < n; ++k)
     if (map[k].id == map[k - 1].id) rc = ORC_E_SURFACE;
   for (int64_t k = 0; k < n && rc == ORC_OK; ++k) {
-    int64_t a = find_slot(map, n, recs[k].next_id);
-    int64_t b = find_slot(map, n, recs[k].prev_id);
-    if (a < 0 || b < 0) rc = ORC_E_SURFACE;
+    int64_t a = recs[k].next_id < 0 ? -1 : find_slot(map, n, recs[k].next_id);
+    int64_t b = recs[k].prev_id < 0 ? -1 : find_slot(map, n, recs[k].prev_id);
+    if (!bounded && (a < 0 || b < 0)) rc = ORC_E_SURFACE;
     r->nx[k] = (int32_t)a;
     r->pv[k] = (int32_t)b;
+    r->fstep[k] = INT32_MAX;
+    r->face[k] = -1;
   }
-  for (int64_t k = 0; k < n && rc == ORC_OK; ++k)
-    if (r->pv[r->nx[k]] != k) rc = ORC_E_SURFACE;
+  for (int64_t k = 0; k < n && rc == ORC_OK; ++k) {
+    if (r->nx[k] >= 0 && r->pv[r->nx[k]] != k) rc = ORC_E_SURFACE;
+    if (r->pv[k] >= 0 && r->nx[r->pv[k]] != k) rc = ORC_E_SURFACE;
+  }
+  r->n_active = n;
   free(map);
   if (rc != ORC_OK) {
     orc_destroy(r);
@@ -292,6 +323,72 @@ int orc_create(const orc_rec* recs, int64_t n, double box, int cosmology, double
   }
   *out = r;
   return ORC_OK;
+}
+
+int orc_create(const orc_rec* recs, int64_t n, double box, int cosmology, double hcoef,
+               orc_region** out) {
+  return create_impl(recs, n, box, cosmology, hcoef, 0, out);
+}
+
+/* One 4-cube region of the tiling (Section "Geometry"): generators
+ * g/2 (1,1,1,1), g/2 (1,-1,-1,1), g/2 (-1,1,-1,1), g/2 (-1,-1,1,1) in (x, y, z, tau),
+ * tau = sqrt(3) t (the time shrink that makes the faces null), lattice origin V,
+ * region index idx. geom = {V[0..3], inv2g, idx[0..3]}. Links may dangle (-1). */
+int orc_create_bounded(const orc_rec* recs, int64_t n, double box, int cosmology, double hcoef,
+                       const double geom[9], orc_region** out) {
+  int rc = create_impl(recs, n, box, cosmology, hcoef, 1, out);
+  if (rc != ORC_OK) return rc;
+  orc_region* r = *out;
+  r->bounded = 1;
+  for (int i = 0; i < 4; ++i) r->V[i] = geom[i];
+  r->inv2g = geom[4];
+  for (int i = 0; i < 4; ++i) r->idx[i] = (int64_t)geom[5 + i];
+  r->sqrt3 = sqrt(3.0);
+  return ORC_OK;
+}
+
+/* Generator coordinates c = H^T (P - V) / (2 g) of a spacetime point (x, y, z, t). */
+void orc_region_coords(const orc_region* r, const double P[4], double c[4]) {
+  double dx = P[0] - r->V[0];
+  double dy = P[1] - r->V[1];
+  double dz = P[2] - r->V[2];
+  double dtau = r->sqrt3 * P[3] - r->V[3];
+  double a = dx + dy, b = dz + dtau, cc = dx - dy, d = dtau - dz;
+  c[0] = (a + b) * r->inv2g;
+  c[1] = (cc + d) * r->inv2g;
+  c[2] = (d - cc) * r->inv2g;
+  c[3] = (b - a) * r->inv2g;
+}
+
+/* -1 when P lies in the region (floor(c) == idx); otherwise the first i with
+ * floor(c_i) > idx_i (the final face crossed), else the first i with floor(c_i) != idx_i. */
+static int exit_face(const orc_region* r, const double P[4]) {
+  double c[4];
+  orc_region_coords(r, P, c);
+  int first_ne = -1;
+  for (int i = 0; i < 4; ++i) {
+    double f = floor(c[i]);
+    if (f > (double)r->idx[i]) return i;
+    if (f != (double)r->idx[i] && first_ne < 0) first_ne = i;
+  }
+  return first_ne;
+}
+
+static void freeze(orc_region* r, int64_t k, int face, int with_r) {
+  orc_rec* f = &r->frz[k];
+  int64_t j = r->nx[k];
+  memset(f, 0, sizeof(*f));
+  f->id = r->id[k];
+  f->next_id = j >= 0 ? r->id[j] : -1;
+  f->prev_id = r->pv[k] >= 0 ? r->id[r->pv[k]] : -1;
+  f->step = r->step;
+  f->flags = FLAG_FROZEN | (with_r ? FLAG_HAS_R : 0) | ((face + 1) << 8);
+  memcpy(f->x, r->cur[k], sizeof(double[4]));
+  memcpy(f->x_prev, r->prv[k], sizeof(double[4]));
+  if (with_r) {
+    memcpy(f->r, r->cur[j], sizeof(double[4]));
+    memcpy(f->r_prev, r->prv[j], sizeof(double[4]));
+  }
 }
 
 /* Vertices and FP64 4-D bounding box of element k of the current band. */
@@ -411,7 +508,7 @@ static int search_brute(orc_region* r, pairvec* out) {
   double S[3];
   for (int64_t k = 0; k < r->n; ++k)
     for (int64_t m = k + 1; m < r->n; ++m) {
-      if (is_adjacent(r, k, m)) continue;
+      if (!r->valid[k] || !r->valid[m] || is_adjacent(r, k, m)) continue;
       int64_t a = k, b = m;
       if (r->id[b] < r->id[a]) {
         a = m;
@@ -429,7 +526,7 @@ static int search_grid(orc_region* r, pairvec* out) {
   int64_t n = r->n;
   double E = 0.0, maxabs = r->L;
   for (int64_t k = 0; k < n; ++k)
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3 && r->valid[k]; ++c) {
       double e = r->hi[k][c] - r->lo[k][c];
       if (e > E) E = e;
       if (fabs(r->lo[k][c]) > maxabs) maxabs = fabs(r->lo[k][c]);
@@ -456,6 +553,10 @@ static int search_grid(orc_region* r, pairvec* out) {
     return ORC_E_OOM;
   }
   for (int64_t k = 0; k < n; ++k) {
+    if (!r->valid[k]) {
+      cc[k][0] = -1;
+      continue;
+    }
     for (int c = 0; c < 3; ++c) {
       double w = r->lo[k][c] - r->L * floor(r->lo[k][c] / r->L);
       int64_t ci = (int64_t)floor(w / h);
@@ -467,12 +568,14 @@ static int search_grid(orc_region* r, pairvec* out) {
   }
   for (int64_t i = 0; i < ncell; ++i) start[i + 1] += start[i];
   for (int64_t k = 0; k < n; ++k) {
+    if (cc[k][0] < 0) continue;
     int64_t id = (cc[k][0] * nc + cc[k][1]) * nc + cc[k][2];
     list[start[id] + fill[id]++] = k;
   }
   int rc = ORC_OK;
   double S[3];
   for (int64_t k = 0; k < n && rc == ORC_OK; ++k) {
+    if (cc[k][0] < 0) continue;
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dz = -1; dz <= 1; ++dz) {
@@ -524,14 +627,66 @@ static int cmp_pair(const void* pa, const void* pb) {
 static int one_step(orc_region* r, int search, int intercommute) {
   int64_t n = r->n;
   int rc = ORC_OK;
-#pragma omp parallel for schedule(static)
+  /* Which points advance. A bounded region computes the diamond of point k at step n
+   * only when its earliest point, the bottom B = X[n-1][next[k]], lies in the region
+   * (Section "Semi-parallel cosmic string simulation": each diamond is created in the
+   * region that contains its earliest point) and both inputs exist; otherwise k stops
+   * here and is handed on. All decisions use the state before the step. */
+  if (r->bounded) {
+    int32_t* nf = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t* nface = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    if (!nf || !nface) {
+      free(nf);
+      free(nface);
+      return ORC_E_OOM;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+      nf[k] = r->fstep[k];
+      nface[k] = r->face[k];
+      r->adv[k] = 0;
+      if (r->fstep[k] != INT32_MAX) continue;
+      int64_t j = r->nx[k];
+      if (j < 0) {
+        freeze(r, k, -1, 0);
+      } else if (r->fstep[j] < r->step) {
+        freeze(r, k, r->face[j], 0);
+      } else {
+        int f = exit_face(r, r->prv[j]);
+        if (f < 0) {
+          r->adv[k] = 1;
+          continue;
+        }
+        freeze(r, k, f, 1);
+        nface[k] = f;
+        nf[k] = r->step;
+        continue;
+      }
+      nface[k] = j < 0 ? -1 : r->face[j];
+      nf[k] = r->step;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+      if (nf[k] != r->fstep[k]) r->n_active--;
+      r->fstep[k] = nf[k];
+      r->face[k] = nface[k];
+    }
+    free(nf);
+    free(nface);
+  } else {
+    memset(r->adv, 1, (size_t)n);
+  }
+  int64_t n_adv = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_adv)
   for (int64_t k = 0; k < n; ++k) {
+    if (!r->adv[k]) continue;
     int64_t j = r->nx[k];
     orc_top(r->cosmology, r->hcoef, r->L, r->cur[k], r->cur[j], r->prv[j], r->nw[k]);
+    n_adv++;
   }
+  for (int64_t k = 0; k < n; ++k) r->valid[k] = r->adv[k] && r->nx[k] >= 0 && r->adv[r->nx[k]];
   if (!intercommute) goto rotate;
 #pragma omp parallel for schedule(static)
-  for (int64_t k = 0; k < n; ++k) build_element(r, k);
+  for (int64_t k = 0; k < n; ++k)
+    if (r->valid[k]) build_element(r, k);
 
   pairvec cand = {0, 0, 0};
   rc = search ? search_brute(r, &cand) : search_grid(r, &cand);
@@ -590,7 +745,7 @@ rotate:;
   r->cur = r->nw;
   r->nw = tmp;
   r->step += 1;
-  r->point_steps += n;
+  r->point_steps += n_adv;
   r->steps_done += 1;
   return rc;
 }
@@ -600,10 +755,10 @@ rotate:;
 int orc_evolve(orc_region* r, int64_t max_steps, double t_end, int search, int intercommute) {
   if (!r) return ORC_E_ARG;
   for (int64_t s = 0; s < max_steps; ++s) {
-    if (r->n == 0) break;
-    double tmin = r->cur[0][3];
-    for (int64_t k = 1; k < r->n; ++k)
-      if (r->cur[k][3] < tmin) tmin = r->cur[k][3];
+    if (r->n_active == 0) break;
+    double tmin = INFINITY;
+    for (int64_t k = 0; k < r->n; ++k)
+      if (r->fstep[k] == INT32_MAX && r->cur[k][3] < tmin) tmin = r->cur[k][3];
     if (tmin >= t_end) break;
     int rc = one_step(r, search, intercommute);
     if (rc != ORC_OK) return rc;
@@ -615,6 +770,7 @@ int orc_evolve(orc_region* r, int64_t max_steps, double t_end, int search, int i
  * sorted). Returns the count; writes at most cap pairs. */
 int64_t orc_band_candidates(orc_region* r, int search, int64_t* out, int64_t cap) {
   int64_t n = r->n;
+  for (int64_t k = 0; k < n; ++k) r->valid[k] = 1;
   for (int64_t k = 0; k < n; ++k) {
     int64_t j = r->nx[k];
     orc_top(r->cosmology, r->hcoef, r->L, r->cur[k], r->cur[j], r->prv[j], r->nw[k]);
@@ -653,6 +809,7 @@ int64_t orc_last_confirmed(const orc_region* r, double* t, int64_t* ids, double*
 }
 
 int64_t orc_n(const orc_region* r) { return r->n; }
+int64_t orc_active(const orc_region* r) { return r->n_active; }
 int32_t orc_step(const orc_region* r) { return r->step; }
 int64_t orc_event_count(const orc_region* r) { return r->nlog; }
 
@@ -672,10 +829,15 @@ int orc_events(const orc_region* r, orc_event* out) {
 /* Current state as records in slot order: x = slice step, x_prev = slice step-1. */
 int orc_read(const orc_region* r, orc_rec* out) {
   for (int64_t k = 0; k < r->n; ++k) {
+    if (r->bounded && r->fstep[k] != INT32_MAX) {
+      out[k] = r->frz[k];
+      continue;
+    }
     memset(&out[k], 0, sizeof(orc_rec));
+    if (r->bounded) out[k].flags = FLAG_ACTIVE;
     out[k].id = r->id[k];
-    out[k].next_id = r->id[r->nx[k]];
-    out[k].prev_id = r->id[r->pv[k]];
+    out[k].next_id = r->nx[k] >= 0 ? r->id[r->nx[k]] : -1;
+    out[k].prev_id = r->pv[k] >= 0 ? r->id[r->pv[k]] : -1;
     out[k].step = r->step;
     memcpy(out[k].x, r->cur[k], sizeof(double[4]));
     memcpy(out[k].x_prev, r->prv[k], sizeof(double[4]));

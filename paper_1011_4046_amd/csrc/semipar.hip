@@ -59,6 +59,38 @@ struct Cells {
   float marg32;    // slack of FP32 spatial comparisons
 };
 
+// One 4-cube of the spacetime tiling: generator coordinates c = H^T (P - V) / (2 g)
+// with tau = sqrt(3) t, region = floor(c) == idx.
+struct RegionGeom {
+  double V[4];
+  double inv2g;
+  double sqrt3;
+  int32_t idx[4];
+};
+
+// -1 when P lies in the region; else the first i with floor(c_i) > idx_i (the final face
+// its future leaves by), else the first i with floor(c_i) != idx_i.
+__device__ __forceinline__ int exit_face(const RegionGeom& G, const V4& P) {
+  const double dx = P.x - G.V[0];
+  const double dy = P.y - G.V[1];
+  const double dz = P.z - G.V[2];
+  const double dtau = G.sqrt3 * P.t - G.V[3];
+  const double a = dx + dy, b = dz + dtau, cc = dx - dy, d = dtau - dz;
+  const double c[4] = {(a + b) * G.inv2g, (cc + d) * G.inv2g, (d - cc) * G.inv2g,
+                       (b - a) * G.inv2g};
+  int first_ne = -1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double f = floor(c[i]);
+    if (f > (double)G.idx[i]) return i;
+    if (f != (double)G.idx[i] && first_ne < 0) first_ne = i;
+  }
+  return first_ne;
+}
+
+constexpr int32_t FS_ACTIVE = INT32_MAX;  // stop step of a point that still advances
+constexpr int32_t NO_ELEM = INT32_MIN;    // ecell of a point without an element this band
+
 struct Ctrl {
   int32_t step;        // lattice index of the current slice
   int32_t step_limit;  // a step is taken only while step < step_limit
@@ -211,15 +243,57 @@ __host__ __device__ inline Cells choose_cells(double box, double ext, double tol
 // ---------------------------------------------------------------------------------
 
 // SCR: 0 = evolution only, 1 = FP64 screen data, 2 = FP32 screen data.
-template <bool FRW, int SCR>
-__global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restrict__ nxt, int n,
+// Record of a point that stops at slice s (x = X[s][k], x_prev = X[s-1][k]); with_r
+// adds the right neighbour's vertices X[s][j], X[s-1][j] (its next diamond's inputs).
+__device__ __forceinline__ void write_frozen(semipar_point_rec* __restrict__ frz, const Slices& X,
+                                             int ic, int ip, int k, int j, bool with_r, int face,
+                                             int s, const int32_t* __restrict__ prv,
+                                             const int64_t* __restrict__ id) {
+  semipar_point_rec r;
+  r.id = id[k];
+  r.next_id = j >= 0 ? id[j] : -1;
+  const int pk = prv[k];
+  r.prev_id = pk >= 0 ? id[pk] : -1;
+  r.step = s;
+  r.flags = SEMIPAR_FLAG_FROZEN | (with_r ? SEMIPAR_FLAG_HAS_R : 0) | ((face + 1) << 8);
+  const V4 a = ld(X, ic, k), b = ld(X, ip, k);
+  r.x[0] = a.x; r.x[1] = a.y; r.x[2] = a.z; r.x[3] = a.t;
+  r.x_prev[0] = b.x; r.x_prev[1] = b.y; r.x_prev[2] = b.z; r.x_prev[3] = b.t;
+  if (with_r) {
+    const V4 c = ld(X, ic, j), d = ld(X, ip, j);
+    r.r[0] = c.x; r.r[1] = c.y; r.r[2] = c.z; r.r[3] = c.t;
+    r.r_prev[0] = d.x; r.r_prev[1] = d.y; r.r_prev[2] = d.z; r.r_prev[3] = d.t;
+  } else {
+    for (int i = 0; i < 4; ++i) {
+      r.r[i] = 0.0;
+      r.r_prev[i] = 0.0;
+    }
+  }
+  frz[k] = r;
+}
+
+// One step for every point: the diamond top X[n+1][k] (flat or first-order FRW) and,
+// when SCR != 0, the element of band n (k to next[k]): FP64 box, cell, bucket count.
+// BND: bounded region. Point k advances only when it is active, next[k] exists and is
+// not stopped before this step, and the bottom X[n-1][next k] of its diamond lies in the
+// region; otherwise it stops now (its record is written to frz). Its element exists when
+// both k and next[k] advance; thread k re-derives next[k]'s decision from the same
+// inputs. All decisions read the state before the step (a stop written in this step
+// never satisfies "stopped before this step").
+template <bool FRW, int SCR, bool BND>
+__global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restrict__ nxt,
+                                               const int32_t* __restrict__ prv,
+                                               const int64_t* __restrict__ id, int n,
                                                sp::Period P, double hcoef, Ctrl* ctrl, HashCfg hc,
                                                void* __restrict__ ebox,
                                                int32_t* __restrict__ ecell,
                                                int32_t* __restrict__ epos,
                                                int32_t* __restrict__ cnt,
                                                LargeBox* __restrict__ large,
-                                               uint64_t* __restrict__ blkred) {
+                                               uint64_t* __restrict__ blkred,
+                                               int32_t* __restrict__ fstep,
+                                               int32_t* __restrict__ face,
+                                               semipar_point_rec* __restrict__ frz, RegionGeom G) {
   if (ctrl->done) return;
   const int s = ctrl->step;
   const Cells cs = ctrl->cells;
@@ -227,90 +301,141 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   const int k = blockIdx.x * NT + threadIdx.x;
   uint64_t tkey = KEY_MAX;
   uint64_t xkey = 0;
+  uint32_t nadv = 0;
   if (k < n) {
-    const int j = nxt[k];
-    const V4 L = ld(X, ic, k);
-    const V4 R = ld(X, ic, j);
-    const V4 B = ld(X, ip, j);
-    const V4 T = sp::top<FRW>(L, R, B, P, hcoef);
-    st(X, in, k, T);
-    tkey = order_key(T.t);
-    if constexpr (SCR != 0) {
-      const int jj = nxt[j];
-      const V4 Rj = ld(X, ic, jj);
-      const V4 Bj = ld(X, ip, jj);
-      const V4 Tj = sp::top<FRW>(R, Rj, Bj, P, hcoef);
-      const Elem e = sp::make_elem(L, R, T, Tj, P);
-      const Box4 b = sp::elem_box(e);
-      double ext = b.hi[0] - b.lo[0];
-      ext = fmax(ext, b.hi[1] - b.lo[1]);
-      ext = fmax(ext, b.hi[2] - b.lo[2]);
-      xkey = order_key(ext);
-      double W[3], w[3];
-      for (int c = 0; c < 3; ++c) {
-        W[c] = P.box * floor(b.lo[c] * P.inv);
-        w[c] = b.lo[c] - W[c];
-      }
-      if (cs.nc == 0 || !(ext <= cs.hlim)) {
-        const int li = atomicAdd(&ctrl->n_large, 1);
-        LargeBox lb;
-        for (int c = 0; c < 3; ++c) {
-          lb.wl[c] = w[c];
-          lb.ext[c] = b.hi[c] - b.lo[c];
-        }
-        lb.tlo = b.lo[3];
-        lb.thi = b.hi[3];
-        lb.slot = k;
-        lb.pad = 0;
-        large[li] = lb;
-        ecell[k] = -1 - li;
-      } else {
-        int ci[3];
-        double lor[3], hir[3];
-        for (int c = 0; c < 3; ++c) {
-          int q = (int)floor(w[c] * cs.inv_h);
-          q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
-          ci[c] = q;
-          lor[c] = w[c] - (double)q * cs.h;
-          hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
-        }
-        if constexpr (SCR == 1) {
-          double4* o = (double4*)ebox + (size_t)k * 2;
-          o[0] = make_double4(lor[0], lor[1], lor[2], b.lo[3]);
-          o[1] = make_double4(hir[0], hir[1], hir[2], b.hi[3]);
+    bool adv = true;
+    int j = nxt[k];
+    if constexpr (BND) {
+      adv = false;
+      if (fstep[k] == FS_ACTIVE) {
+        int f = -1;
+        bool with_r = false;
+        if (j < 0) {
+          f = -1;
+        } else if (fstep[j] < s) {
+          f = face[j];
         } else {
-          float4* o = (float4*)ebox + (size_t)k * 2;
-          o[0] = make_float4(__double2float_rd(lor[0] - hc.tol), __double2float_rd(lor[1] - hc.tol),
-                             __double2float_rd(lor[2] - hc.tol),
-                             __double2float_rd((b.lo[3] - hc.tref) - hc.tol_t));
-          o[1] = make_float4(__double2float_ru(hir[0] + hc.tol), __double2float_ru(hir[1] + hc.tol),
-                             __double2float_ru(hir[2] + hc.tol),
-                             __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
+          f = exit_face(G, ld(X, ip, j));
+          if (f < 0) adv = true;
+          with_r = true;
         }
-        const uint32_t bk = bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
-        epos[k] = atomicAdd(&cnt[bk], 1);
-        ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
+        if (!adv) {
+          write_frozen(frz, X, ic, ip, k, j, with_r, f, s, prv, id);
+          face[k] = f;
+          fstep[k] = s;
+        }
       }
     }
+    if (adv) {
+      nadv = 1;
+      const V4 L = ld(X, ic, k);
+      const V4 R = ld(X, ic, j);
+      const V4 B = ld(X, ip, j);
+      const V4 T = sp::top<FRW>(L, R, B, P, hcoef);
+      st(X, in, k, T);
+      tkey = order_key(T.t);
+      if constexpr (SCR != 0) {
+        const int jj = nxt[j];
+        bool jadv = true;
+        V4 Rj, Bj;
+        if constexpr (BND) {
+          jadv = fstep[j] == FS_ACTIVE && jj >= 0 && fstep[jj] >= s;
+          if (jadv) {
+            Bj = ld(X, ip, jj);
+            jadv = exit_face(G, Bj) < 0;
+          }
+          if (jadv) Rj = ld(X, ic, jj);
+        } else {
+          Rj = ld(X, ic, jj);
+          Bj = ld(X, ip, jj);
+        }
+        if (!jadv) {
+          ecell[k] = NO_ELEM;
+        } else {
+          const V4 Tj = sp::top<FRW>(R, Rj, Bj, P, hcoef);
+          const Elem e = sp::make_elem(L, R, T, Tj, P);
+          const Box4 b = sp::elem_box(e);
+          double ext = b.hi[0] - b.lo[0];
+          ext = fmax(ext, b.hi[1] - b.lo[1]);
+          ext = fmax(ext, b.hi[2] - b.lo[2]);
+          xkey = order_key(ext);
+          double W[3], w[3];
+          for (int c = 0; c < 3; ++c) {
+            W[c] = P.box * floor(b.lo[c] * P.inv);
+            w[c] = b.lo[c] - W[c];
+          }
+          if (cs.nc == 0 || !(ext <= cs.hlim)) {
+            const int li = atomicAdd(&ctrl->n_large, 1);
+            LargeBox lb;
+            for (int c = 0; c < 3; ++c) {
+              lb.wl[c] = w[c];
+              lb.ext[c] = b.hi[c] - b.lo[c];
+            }
+            lb.tlo = b.lo[3];
+            lb.thi = b.hi[3];
+            lb.slot = k;
+            lb.pad = 0;
+            large[li] = lb;
+            ecell[k] = -1 - li;
+          } else {
+            int ci[3];
+            double lor[3], hir[3];
+            for (int c = 0; c < 3; ++c) {
+              int q = (int)floor(w[c] * cs.inv_h);
+              q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
+              ci[c] = q;
+              lor[c] = w[c] - (double)q * cs.h;
+              hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
+            }
+            if constexpr (SCR == 1) {
+              double4* o = (double4*)ebox + (size_t)k * 2;
+              o[0] = make_double4(lor[0], lor[1], lor[2], b.lo[3]);
+              o[1] = make_double4(hir[0], hir[1], hir[2], b.hi[3]);
+            } else {
+              float4* o = (float4*)ebox + (size_t)k * 2;
+              o[0] = make_float4(__double2float_rd(lor[0] - hc.tol),
+                                 __double2float_rd(lor[1] - hc.tol),
+                                 __double2float_rd(lor[2] - hc.tol),
+                                 __double2float_rd((b.lo[3] - hc.tref) - hc.tol_t));
+              o[1] = make_float4(__double2float_ru(hir[0] + hc.tol),
+                                 __double2float_ru(hir[1] + hc.tol),
+                                 __double2float_ru(hir[2] + hc.tol),
+                                 __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
+            }
+            const uint32_t bk = bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
+            epos[k] = atomicAdd(&cnt[bk], 1);
+            ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
+          }
+        }
+      }
+    } else if constexpr (SCR != 0) {
+      ecell[k] = NO_ELEM;
+    }
   }
-  // per-block minimum of the new slice's t and maximum element extent, reduced by
-  // k_resolve (no same-address atomics across the grid)
+  // per block: minimum t of the new slice, largest element extent, points advanced;
+  // reduced by k_resolve (no same-address atomics across the grid)
   __shared__ uint64_t wmin[NT / 64], wmax[NT / 64];
+  __shared__ uint32_t wadv[NT / 64];
   tkey = wave_min_u64(tkey);
   xkey = wave_max_u64(xkey);
+  for (int o = 32; o > 0; o >>= 1) nadv += __shfl_xor(nadv, o, 64);
   if ((threadIdx.x & 63) == 0) {
     wmin[threadIdx.x >> 6] = tkey;
     wmax[threadIdx.x >> 6] = xkey;
+    wadv[threadIdx.x >> 6] = nadv;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t m = wmin[0], x = wmax[0];
+    uint64_t a = wadv[0];
     for (int w = 1; w < NT / 64; ++w) {
       m = wmin[w] < m ? wmin[w] : m;
       x = wmax[w] > x ? wmax[w] : x;
+      a += wadv[w];
     }
-    blkred[2 * blockIdx.x] = m;
-    blkred[2 * blockIdx.x + 1] = x;
+    blkred[4 * blockIdx.x] = m;
+    blkred[4 * blockIdx.x + 1] = x;
+    blkred[4 * blockIdx.x + 2] = a;
   }
 }
 
@@ -744,7 +869,7 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     const uint64_t* __restrict__ blkred, int nblk, Ctrl* ctrl) {
   __shared__ int s_live;
   __shared__ int s_nacc;
-  __shared__ uint64_t s_min[RESOLVE_NT / 64], s_max[RESOLVE_NT / 64];
+  __shared__ uint64_t s_min[RESOLVE_NT / 64], s_max[RESOLVE_NT / 64], s_adv[RESOLVE_NT / 64];
   if (ctrl->done) return;
   const int t = threadIdx.x;
   const int ncand = ctrl->n_cand;
@@ -832,23 +957,27 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
       }
   }
   // smallest t of the slice written by this step's k_evolve, largest element extent
-  uint64_t mk = KEY_MAX, xk = 0;
+  uint64_t mk = KEY_MAX, xk = 0, ak = 0;
   for (int b = t; b < nblk; b += RESOLVE_NT) {
-    mk = blkred[2 * b] < mk ? blkred[2 * b] : mk;
-    xk = blkred[2 * b + 1] > xk ? blkred[2 * b + 1] : xk;
+    mk = blkred[4 * b] < mk ? blkred[4 * b] : mk;
+    xk = blkred[4 * b + 1] > xk ? blkred[4 * b + 1] : xk;
+    ak += blkred[4 * b + 2];
   }
   mk = wave_min_u64(mk);
   xk = wave_max_u64(xk);
+  for (int o = 32; o > 0; o >>= 1) ak += __shfl_xor(ak, o, 64);
   if ((t & 63) == 0) {
     s_min[t >> 6] = mk;
     s_max[t >> 6] = xk;
+    s_adv[t >> 6] = ak;
   }
   __syncthreads();
   if (t == 0) {
-    uint64_t m = s_min[0], x = s_max[0];
+    uint64_t m = s_min[0], x = s_max[0], nadv = s_adv[0];
     for (int w = 1; w < RESOLVE_NT / 64; ++w) {
       m = s_min[w] < m ? s_min[w] : m;
       x = s_max[w] > x ? s_max[w] : x;
+      nadv += s_adv[w];
     }
     if (!ctrl->cells.fixed && x != 0)
       ctrl->cells = choose_cells(ctrl->box, ctrl->grow * from_key(x), ctrl->tol);
@@ -863,26 +992,68 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     ctrl->stamp = (int32_t)(base + iter);
     ctrl->step += 1;
     ctrl->steps_taken += 1;
-    ctrl->point_steps += ctrl->n_points;
-    const double tmin = from_key(m);
-    ctrl->done = (ctrl->step >= ctrl->step_limit || tmin >= ctrl->t_end) ? 1 : 0;
+    ctrl->point_steps += (int64_t)nadv;
+    const double tmin = nadv ? from_key(m) : 0.0;
+    ctrl->done = (ctrl->step >= ctrl->step_limit || nadv == 0 || tmin >= ctrl->t_end) ? 1 : 0;
   }
 }
 
-// Start of an evolve call: smallest t on the current slice.
-__global__ __launch_bounds__(NT) void k_begin_min(Slices X, int n, Ctrl* ctrl) {
+// Start of an evolve call: per block, the smallest t on the current slice and the number
+// of points still advancing (all points of a whole-volume region).
+__global__ __launch_bounds__(NT) void k_begin_min(Slices X, int n, const int32_t* fstep,
+                                                  uint64_t* __restrict__ blkred, Ctrl* ctrl) {
   const int s = ctrl->step;
   const int k = blockIdx.x * NT + threadIdx.x;
   uint64_t key = KEY_MAX;
-  if (k < n) key = order_key(X.p[s % 3][3][k]);
+  uint32_t act = 0;
+  if (k < n && (!fstep || fstep[k] == FS_ACTIVE)) {
+    key = order_key(X.p[s % 3][3][k]);
+    act = 1;
+  }
+  __shared__ uint64_t wmin[NT / 64];
+  __shared__ uint32_t wact[NT / 64];
   key = wave_min_u64(key);
-  if ((threadIdx.x & 63) == 0 && key != KEY_MAX)
-    atomicMin((unsigned long long*)&ctrl->tmin_key, (unsigned long long)key);
+  for (int o = 32; o > 0; o >>= 1) act += __shfl_xor(act, o, 64);
+  if ((threadIdx.x & 63) == 0) {
+    wmin[threadIdx.x >> 6] = key;
+    wact[threadIdx.x >> 6] = act;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t m = wmin[0], a = wact[0];
+    for (int w = 1; w < NT / 64; ++w) {
+      m = wmin[w] < m ? wmin[w] : m;
+      a += wact[w];
+    }
+    blkred[4 * blockIdx.x] = m;
+    blkred[4 * blockIdx.x + 1] = 0;
+    blkred[4 * blockIdx.x + 2] = a;
+  }
 }
 
-__global__ void k_begin_set(Ctrl* ctrl, int32_t step_limit, double t_end, int n, Cells cells,
-                            int set_cells) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(1024) void k_begin_set(Ctrl* ctrl, int32_t step_limit, double t_end,
+                                                    const uint64_t* __restrict__ blkred, int nblk,
+                                                    Cells cells, int set_cells) {
+  __shared__ uint64_t s_min[16], s_act[16];
+  const int t = threadIdx.x;
+  uint64_t mk = KEY_MAX, ak = 0;
+  for (int b = t; b < nblk; b += 1024) {
+    mk = blkred[4 * b] < mk ? blkred[4 * b] : mk;
+    ak += blkred[4 * b + 2];
+  }
+  mk = wave_min_u64(mk);
+  for (int o = 32; o > 0; o >>= 1) ak += __shfl_xor(ak, o, 64);
+  if ((t & 63) == 0) {
+    s_min[t >> 6] = mk;
+    s_act[t >> 6] = ak;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  uint64_t m = s_min[0], a = s_act[0];
+  for (int w = 1; w < 16; ++w) {
+    m = s_min[w] < m ? s_min[w] : m;
+    a += s_act[w];
+  }
   if (set_cells) ctrl->cells = cells;
   ctrl->step_limit = step_limit;
   ctrl->t_end = t_end;
@@ -890,9 +1061,8 @@ __global__ void k_begin_set(Ctrl* ctrl, int32_t step_limit, double t_end, int n,
   ctrl->n_cand = 0;
   ctrl->n_evt = 0;
   ctrl->n_large = 0;
-  const double tmin = from_key(ctrl->tmin_key);
-  ctrl->tmin_key = KEY_MAX;
-  ctrl->done = (n == 0 || ctrl->step >= step_limit || tmin >= t_end) ? 1 : 0;
+  const double tmin = a ? from_key(m) : 0.0;
+  ctrl->done = (a == 0 || ctrl->step >= step_limit || tmin >= t_end) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------------
@@ -958,7 +1128,8 @@ __global__ __launch_bounds__(NT) void k_init_links(const semipar_point_rec* __re
                                                    const int64_t* __restrict__ hkey,
                                                    const int32_t* __restrict__ hval,
                                                    uint32_t hmask, Slices X, int32_t* nxt,
-                                                   int32_t* prv, int64_t* id, Ctrl* ctrl) {
+                                                   int32_t* prv, int64_t* id, int bounded,
+                                                   int32_t* fstep, int32_t* face, Ctrl* ctrl) {
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k >= n) return;
   const semipar_point_rec r = rec[k];
@@ -966,9 +1137,16 @@ __global__ __launch_bounds__(NT) void k_init_links(const semipar_point_rec* __re
   if (s != rec[0].step || s < 1) atomicOr(&ctrl->err, 8);
   const int a = id_lookup(hkey, hval, hmask, r.next_id);
   const int b = id_lookup(hkey, hval, hmask, r.prev_id);
-  if (a < 0 || b < 0) atomicOr(&ctrl->err, 16);
-  nxt[k] = a < 0 ? k : a;
-  prv[k] = b < 0 ? k : b;
+  if (bounded) {
+    nxt[k] = a;
+    prv[k] = b;
+    fstep[k] = FS_ACTIVE;
+    face[k] = -1;
+  } else {
+    if (a < 0 || b < 0) atomicOr(&ctrl->err, 16);
+    nxt[k] = a < 0 ? k : a;
+    prv[k] = b < 0 ? k : b;
+  }
   id[k] = r.id;
   const int ic = ((s % 3) + 3) % 3, ip = (ic + 2) % 3;
   st(X, ic, k, V4{r.x[0], r.x[1], r.x[2], r.x[3]});
@@ -982,10 +1160,12 @@ __global__ __launch_bounds__(NT) void k_init_check(Slices X, int n, const int32_
   const int k = blockIdx.x * NT + threadIdx.x;
   uint64_t key = 0;
   if (k < n) {
+    const int pk = prv[k];
+    if (pk >= 0 && nxt[pk] != k) atomicOr(&ctrl->err, 32);
     const int j = nxt[k];
-    if (prv[j] != k) atomicOr(&ctrl->err, 32);
+    if (j >= 0 && prv[j] != k) atomicOr(&ctrl->err, 32);
     const int ic = s % 3, ip = (s + 2) % 3;
-    const V4 a = ld(X, ic, k), b = ld(X, ic, j), c = ld(X, ip, k);
+    const V4 a = ld(X, ic, k), b = ld(X, ic, j >= 0 ? j : k), c = ld(X, ip, k);
     double e1 = fabs(sp::min_image(b.x - a.x, P));
     e1 = fmax(e1, fabs(sp::min_image(b.y - a.y, P)));
     e1 = fmax(e1, fabs(sp::min_image(b.z - a.z, P)));
@@ -999,18 +1179,28 @@ __global__ __launch_bounds__(NT) void k_init_check(Slices X, int n, const int32_
   if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&ctrl->ext_key, (unsigned long long)key);
 }
 
-__global__ __launch_bounds__(NT) void k_emit_all(Slices X, int n, const int32_t* nxt,
-                                                 const int32_t* prv, const int64_t* id, int s,
-                                                 semipar_point_rec* __restrict__ out) {
-  const int k = blockIdx.x * NT + threadIdx.x;
-  if (k >= n) return;
+// Output record of slot k and the surface stream it goes to: a stopped point of a
+// bounded region goes to its face (no owning face: stream 0); a point still on the
+// current slice goes to stream 0 (flag ACTIVE in a bounded region).
+__device__ __forceinline__ int emit_stream(int k, const int32_t* fstep,
+                                           const semipar_point_rec* frz) {
+  if (fstep && fstep[k] != FS_ACTIVE) {
+    const int f = ((frz[k].flags >> 8) & 0xff) - 1;
+    return f >= 0 && f < 4 ? f : 0;
+  }
+  return 0;
+}
+
+__device__ __forceinline__ semipar_point_rec current_record(const Slices& X, int k, int s,
+                                                            const int32_t* nxt, const int32_t* prv,
+                                                            const int64_t* id, int32_t flags) {
   const int ic = s % 3, ip = (s + 2) % 3;
   semipar_point_rec r;
   r.id = id[k];
-  r.next_id = id[nxt[k]];
-  r.prev_id = id[prv[k]];
+  r.next_id = nxt[k] >= 0 ? id[nxt[k]] : -1;
+  r.prev_id = prv[k] >= 0 ? id[prv[k]] : -1;
   r.step = s;
-  r.flags = 0;
+  r.flags = flags;
   const V4 a = ld(X, ic, k), b = ld(X, ip, k);
   r.x[0] = a.x;
   r.x[1] = a.y;
@@ -1024,7 +1214,81 @@ __global__ __launch_bounds__(NT) void k_emit_all(Slices X, int n, const int32_t*
     r.r[c] = 0.0;
     r.r_prev[c] = 0.0;
   }
-  out[k] = r;
+  return r;
+}
+
+// Per block, the number of records of each of the 4 streams.
+__global__ __launch_bounds__(NT) void k_emit_count(int n, const int32_t* fstep,
+                                                   const semipar_point_rec* frz,
+                                                   int32_t* __restrict__ blkcnt) {
+  __shared__ int c[4];
+  if (threadIdx.x < 4) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k < n) atomicAdd(&c[emit_stream(k, fstep, frz)], 1);
+  __syncthreads();
+  if (threadIdx.x < 4) blkcnt[4 * blockIdx.x + threadIdx.x] = c[threadIdx.x];
+}
+
+// Exclusive scan of the block counts of each stream (one workgroup); tot[f] = totals.
+__global__ __launch_bounds__(1024) void k_emit_scan(const int32_t* __restrict__ blkcnt, int nblk,
+                                                    int32_t* __restrict__ blkoff,
+                                                    int32_t* __restrict__ tot) {
+  __shared__ int32_t sh[1024];
+  const int t = threadIdx.x;
+  const int per = (nblk + 1023) / 1024;
+  for (int f = 0; f < 4; ++f) {
+    int sum = 0;
+    for (int i = 0; i < per; ++i)
+      if (t * per + i < nblk) sum += blkcnt[4 * (t * per + i) + f];
+    sh[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int add = t >= o ? sh[t - o] : 0;
+      __syncthreads();
+      sh[t] += add;
+      __syncthreads();
+    }
+    int run = sh[t] - sum;
+    for (int i = 0; i < per; ++i)
+      if (t * per + i < nblk) {
+        blkoff[4 * (t * per + i) + f] = run;
+        run += blkcnt[4 * (t * per + i) + f];
+      }
+    if (t == 1023) tot[f] = sh[1023];
+    __syncthreads();
+  }
+}
+
+// Records in slot order within each stream; stream f starts at base[f] of out.
+__global__ __launch_bounds__(NT) void k_emit_write(Slices X, int n, int s, const int32_t* nxt,
+                                                   const int32_t* prv, const int64_t* id,
+                                                   const int32_t* fstep,
+                                                   const semipar_point_rec* frz,
+                                                   const int32_t* __restrict__ blkoff,
+                                                   const int32_t* __restrict__ tot,
+                                                   semipar_point_rec* __restrict__ out) {
+  __shared__ int32_t sh[4][NT];
+  const int t = threadIdx.x;
+  const int k = blockIdx.x * NT + t;
+  const int f = k < n ? emit_stream(k, fstep, frz) : -1;
+  for (int q = 0; q < 4; ++q) sh[q][t] = (f == q) ? 1 : 0;
+  __syncthreads();
+  for (int o = 1; o < NT; o <<= 1) {
+    int add[4];
+    for (int q = 0; q < 4; ++q) add[q] = t >= o ? sh[q][t - o] : 0;
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) sh[q][t] += add[q];
+    __syncthreads();
+  }
+  if (f < 0) return;
+  int base = 0;
+  for (int q = 0; q < f; ++q) base += tot[q];
+  const int pos = base + blkoff[4 * blockIdx.x + f] + sh[f][t] - 1;
+  if (fstep && fstep[k] != FS_ACTIVE)
+    out[pos] = frz[k];
+  else
+    out[pos] = current_record(X, k, s, nxt, prv, id, fstep ? SEMIPAR_FLAG_ACTIVE : 0);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1067,6 +1331,10 @@ inline int blocks(int64_t n, int nt = NT) { return (int)((n + nt - 1) / nt); }
 
 struct semipar_region {
   int64_t n = 0, cap = 0;
+  bool bounded = false;
+  RegionGeom geom{};
+  int32_t *fstep = nullptr, *face = nullptr;  // bounded: stop step and exit face per point
+  semipar_point_rec* frz = nullptr;           // bounded: record of each stopped point
   int cosmology = 0;
   double hcoef = 0.0, box = 1.0;
   hipStream_t stream = nullptr;
@@ -1268,6 +1536,31 @@ int grow_step_caps(semipar_region* r, int defer) {
   return SEMIPAR_OK;
 }
 
+template <bool FRW, int SCR, bool BND>
+void launch_evolve_t(semipar_region* r, int n, int nb) {
+  k_evolve<FRW, SCR, BND><<<nb, NT, 0, r->stream>>>(
+      r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell, r->epos,
+      r->cnt, r->large, r->blkred, r->fstep, r->face, r->frz, r->geom);
+}
+
+template <bool FRW, bool BND>
+void launch_evolve_s(semipar_region* r, int scr, int n, int nb) {
+  if (scr == 0) launch_evolve_t<FRW, 0, BND>(r, n, nb);
+  else if (scr == 1) launch_evolve_t<FRW, 1, BND>(r, n, nb);
+  else launch_evolve_t<FRW, 2, BND>(r, n, nb);
+}
+
+// Diamond tops (+ element data when scr != 0) of one step.
+void launch_evolve(semipar_region* r, bool frw, int scr, bool bnd, int n, int nb) {
+  if (frw) {
+    if (bnd) launch_evolve_s<true, true>(r, scr, n, nb);
+    else launch_evolve_s<true, false>(r, scr, n, nb);
+  } else {
+    if (bnd) launch_evolve_s<false, true>(r, scr, n, nb);
+    else launch_evolve_s<false, false>(r, scr, n, nb);
+  }
+}
+
 template <int SCR, int G>
 void launch_screen_t(semipar_region* r, int n, int nb) {
   k_screen<SCR, G><<<xcd_grid(nb * G), NT, 0, r->stream>>>(
@@ -1301,28 +1594,8 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
   hipStream_t s = r->stream;
   const bool frw = r->cosmology != SEMIPAR_FLAT;
   mark(r, SEMIPAR_K_EVOLVE, 2 * i);
-  if (!intercommute) {
-    if (frw)
-      k_evolve<true, 0><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
-                                          r->ecell, r->epos, r->cnt, r->large, r->blkred);
-    else
-      k_evolve<false, 0><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
-                                           r->ecell, r->epos, r->cnt, r->large, r->blkred);
-  } else if (r->screen == 1) {
-    if (frw)
-      k_evolve<true, 1><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
-                                          r->ecell, r->epos, r->cnt, r->large, r->blkred);
-    else
-      k_evolve<false, 1><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
-                                           r->ecell, r->epos, r->cnt, r->large, r->blkred);
-  } else {
-    if (frw)
-      k_evolve<true, 2><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
-                                          r->ecell, r->epos, r->cnt, r->large, r->blkred);
-    else
-      k_evolve<false, 2><<<nb, NT, 0, s>>>(r->X, r->nxt, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox,
-                                           r->ecell, r->epos, r->cnt, r->large, r->blkred);
-  }
+  const int scr = intercommute ? r->screen : 0;
+  launch_evolve(r, frw, scr, r->bounded, n, nb);
   mark(r, SEMIPAR_K_EVOLVE, 2 * i + 1);
   if (intercommute) {
     mark(r, SEMIPAR_K_SCAN, 2 * i);
@@ -1397,6 +1670,9 @@ void region_destroy(semipar_region* r) {
   dfree(r->prv);
   dfree(r->id);
   dfree(r->blkred);
+  dfree(r->fstep);
+  dfree(r->face);
+  dfree(r->frz);
   dfree(r->ctrl);
   dfree(r->log);
   if (r->ctrl_h) (void)hipHostFree(r->ctrl_h);
@@ -1414,6 +1690,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
   if (!d || n_in < 0 || (n_in > 0 && !in)) return SEMIPAR_E_ARG;
   if (!(d->box > 0.0) || d->cosmology < 0 || d->cosmology > 2 || d->capacity < 0)
     return SEMIPAR_E_ARG;
+  if (d->bounded && !(d->inv2g > 0.0)) return SEMIPAR_E_ARG;
   int64_t total = 0;
   for (int i = 0; i < n_in; ++i) {
     if (in[i].n < 0 || (in[i].n > 0 && !in[i].recs)) return SEMIPAR_E_ARG;
@@ -1429,6 +1706,15 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
   r->cosmology = d->cosmology;
   r->hcoef = d->cosmology == SEMIPAR_MATTER ? 2.0 : (d->cosmology == SEMIPAR_RADIATION ? 1.0 : 0.0);
   r->box = d->box;
+  r->bounded = d->bounded != 0;
+  if (r->bounded) {
+    for (int i = 0; i < 4; ++i) {
+      r->geom.V[i] = d->origin[i];
+      r->geom.idx[i] = d->idx[i];
+    }
+    r->geom.inv2g = d->inv2g;
+    r->geom.sqrt3 = std::sqrt(3.0);
+  }
   {
     int ex = 0;
     const double mant = std::frexp(d->box, &ex);
@@ -1454,7 +1740,9 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       if (dalloc(&r->X.p[s][c], cap) != hipSuccess) return fail(SEMIPAR_E_OOM);
   if (dalloc(&r->nxt, cap) != hipSuccess || dalloc(&r->prv, cap) != hipSuccess ||
       dalloc(&r->id, cap) != hipSuccess || dalloc(&r->ctrl, 1) != hipSuccess ||
-      dalloc(&r->blkred, 2 * (size_t)blocks(cap)) != hipSuccess)
+      dalloc(&r->blkred, 4 * (size_t)blocks(cap)) != hipSuccess ||
+      dalloc(&r->fstep, cap) != hipSuccess || dalloc(&r->face, cap) != hipSuccess ||
+      (d->bounded && dalloc(&r->frz, cap) != hipSuccess))
     return fail(SEMIPAR_E_OOM);
   if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
     return fail(SEMIPAR_E_OOM);
@@ -1511,7 +1799,8 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       k_init_insert<<<blocks(n), NT, 0, r->stream>>>(drec, n, hkey, hval, (uint32_t)(hcap - 1),
                                                      r->ctrl);
       k_init_links<<<blocks(n), NT, 0, r->stream>>>(drec, n, hkey, hval, (uint32_t)(hcap - 1), r->X,
-                                                    r->nxt, r->prv, r->id, r->ctrl);
+                                                    r->nxt, r->prv, r->id, r->bounded ? 1 : 0,
+                                                    r->fstep, r->face, r->ctrl);
       k_init_check<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->nxt, r->prv, r->P, c0.step,
                                                     r->ctrl);
       if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
@@ -1569,7 +1858,8 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   double tk_ms = 0.0;
   int64_t tk_n = 0;
   HIPCHK(hipEventRecord(r->ev0, r->stream));
-  k_begin_min<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->ctrl);
+  k_begin_min<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->bounded ? r->fstep : nullptr,
+                                                r->blkred, r->ctrl);
   // grid of the first step: the caller's cell size (kept fixed), else 1.25 x the
   // initial element-size estimate, then adapted each step to the largest element
   Cells cells{};
@@ -1586,7 +1876,8 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     r->cells_set = true;
     r->cells_fixed = false;
   }
-  k_begin_set<<<1, 64, 0, r->stream>>>(r->ctrl, step_limit, p->t_end, n, cells, set_cells);
+  k_begin_set<<<1, 1024, 0, r->stream>>>(r->ctrl, step_limit, p->t_end, r->blkred, blocks(n),
+                                         cells, set_cells);
   HIPCHK(hipGetLastError());
   for (;;) {
     rc = ensure_log(r, r->ctrl_h->log_n + 2 * r->cap_evt);
@@ -1667,29 +1958,58 @@ int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], con
                                int64_t n[4], int32_t mem) {
   if (!r || !n) return SEMIPAR_E_ARG;
   if (mem != SEMIPAR_MEM_HOST && mem != SEMIPAR_MEM_DEVICE) return SEMIPAR_E_ARG;
-  n[0] = r->n;
-  n[1] = n[2] = n[3] = 0;
-  if (!out || !out[0] || r->n == 0) return SEMIPAR_OK;
-  if (!cap || cap[0] < r->n) return SEMIPAR_E_ARG;
+  for (int f = 0; f < 4; ++f) n[f] = 0;
+  if (r->n == 0) return SEMIPAR_OK;
   RCCHK(read_ctrl(r));
   const int s = r->ctrl_h->step;
   const int nn = (int)r->n;
-  if (mem == SEMIPAR_MEM_DEVICE) {
-    k_emit_all<<<blocks(nn), NT, 0, r->stream>>>(r->X, nn, r->nxt, r->prv, r->id, s, out[0]);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(r->stream));
+  const int nb = blocks(nn);
+  const int32_t* fs = r->bounded ? r->fstep : nullptr;
+  int32_t *blkcnt = nullptr, *blkoff = nullptr, *tot = nullptr;
+  semipar_point_rec* tmp = nullptr;
+  int rc = SEMIPAR_OK;
+  int32_t th[4] = {0, 0, 0, 0};
+  if (dalloc(&blkcnt, 4 * (size_t)nb) != hipSuccess || dalloc(&blkoff, 4 * (size_t)nb) != hipSuccess ||
+      dalloc(&tot, 4) != hipSuccess) {
+    rc = SEMIPAR_E_OOM;
   } else {
-    semipar_point_rec* tmp = nullptr;
-    HIPCHK(dalloc(&tmp, r->n));
-    k_emit_all<<<blocks(nn), NT, 0, r->stream>>>(r->X, nn, r->nxt, r->prv, r->id, s, tmp);
-    hipError_t e1 = hipGetLastError();
-    hipError_t e2 = hipMemcpyAsync(out[0], tmp, sizeof(semipar_point_rec) * r->n,
-                                   hipMemcpyDeviceToHost, r->stream);
-    hipError_t e3 = hipStreamSynchronize(r->stream);
-    dfree(tmp);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return SEMIPAR_E_HIP;
+    k_emit_count<<<nb, NT, 0, r->stream>>>(nn, fs, r->frz, blkcnt);
+    k_emit_scan<<<1, 1024, 0, r->stream>>>(blkcnt, nb, blkoff, tot);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(th, tot, sizeof(th), hipMemcpyDeviceToHost, r->stream) != hipSuccess ||
+        hipStreamSynchronize(r->stream) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
   }
-  return SEMIPAR_OK;
+  if (rc == SEMIPAR_OK) {
+    for (int f = 0; f < 4; ++f) n[f] = th[f];
+    bool want = out != nullptr;
+    for (int f = 0; f < 4 && want; ++f)
+      if (n[f] > 0 && (!out[f] || !cap || cap[f] < n[f])) rc = SEMIPAR_E_ARG;
+    if (want && rc == SEMIPAR_OK) {
+      if (dalloc(&tmp, r->n) != hipSuccess) rc = SEMIPAR_E_OOM;
+      if (rc == SEMIPAR_OK) {
+        k_emit_write<<<nb, NT, 0, r->stream>>>(r->X, nn, s, r->nxt, r->prv, r->id, fs, r->frz,
+                                               blkoff, tot, tmp);
+        if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
+        int64_t off = 0;
+        const hipMemcpyKind kind =
+            mem == SEMIPAR_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        for (int f = 0; f < 4 && rc == SEMIPAR_OK; ++f) {
+          if (n[f] > 0 &&
+              hipMemcpyAsync(out[f], tmp + off, sizeof(semipar_point_rec) * n[f], kind,
+                             r->stream) != hipSuccess)
+            rc = SEMIPAR_E_HIP;
+          off += n[f];
+        }
+        if (rc == SEMIPAR_OK && hipStreamSynchronize(r->stream) != hipSuccess) rc = SEMIPAR_E_HIP;
+      }
+    }
+  }
+  dfree(blkcnt);
+  dfree(blkoff);
+  dfree(tot);
+  dfree(tmp);
+  return rc;
 }
 
 int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int64_t* n) {

@@ -356,3 +356,93 @@ def crossing_strings(n_pts=64, box=1.0, v=0.5, y0=0.1, x0=0.30078125, z_off=0.00
     net["t_star"] = y0 / v2
     net["x_star"] = np.array([x0, 0.0, 0.0])
     return net
+
+
+# --------------------------------------------------------------------------------------
+# Standalone regions of the tiling (first layer: they generate their own initial data)
+# --------------------------------------------------------------------------------------
+
+def region_geometry(size, t_mid, centre=(0.0, 0.0, 0.0)):
+    """One 4-cube region of the spacetime tiling (Section "Geometry").
+
+    Generators g/2 (1,1,1,1), g/2 (1,-1,-1,1), g/2 (-1,1,-1,1), g/2 (-1,-1,1,1) in
+    (x, y, z, tau) with tau = sqrt(3) t, region "size" s = rhombohedron edge, so
+    g = s / sqrt(2). The region with index 0 and lattice origin V has its mid-time
+    centre at (centre, tau = sqrt(3) t_mid) when V = (centre, sqrt(3) t_mid - g).
+    Returns geom = [V0, V1, V2, V3, 1/(2g), 0, 0, 0, 0] and g.
+    """
+    g = size / np.sqrt(2.0)
+    V = [float(centre[0]), float(centre[1]), float(centre[2]), float(np.sqrt(3.0) * t_mid - g)]
+    return np.array(V + [1.0 / (2.0 * g), 0.0, 0.0, 0.0, 0.0]), g
+
+
+def region_network(n_target, size, seed, t_mid=8.0, centre=(0.0, 0.0, 0.0), pts_per_xi=8,
+                   jitter=0.15, cosmology=MATTER, box=None):
+    """Initial data of a first-layer region: a VV-style network at rest cut to the
+    region's spatial cross-section at its mid-time (the octahedron |x|+|y|+|z| < g
+    around the centre, the middle slice of a 4-cube standing on a vertex).
+
+    The lattice spacing xi is chosen so that about n_target points fall inside.
+    Points are kept when their slice-0 position lies inside the octahedron by more than
+    one sigma spacing; links to dropped points become -1 (dangling). box is the periodic
+    length used by the evolver (default: a power of two larger than 4 g, so that no
+    difference inside the region is ever folded).
+    """
+    rng = np.random.default_rng(seed)
+    geom, g = region_geometry(size, t_mid, centre)
+    if n_target <= 0:
+        recs = np.zeros(0, dtype=REC_DTYPE)
+        L = box or 2.0 ** np.ceil(np.log2(4 * g))
+        return Network(recs=recs, box=float(L), delta=1.0, t0=float(t_mid), cosmology=cosmology,
+                       chains=[], geom=geom, g=g)
+    xi = g * (9.48 / n_target) ** (1.0 / 3.0)
+    m = int(np.ceil((2 * g + 2 * xi) / xi))
+    W = m * xi
+    delta = xi / pts_per_xi
+    raw = vv_chains(m, rng, xi, pts_per_xi, jitter)
+    c = np.asarray(centre, np.float64)
+    pts, nxt_ok = [], []
+    X0s, X1s = [], []
+    for P, wind in raw:
+        n = len(P)
+        Pn = np.concatenate([P[1:], (P[0] + wind * W)[None]], axis=0)
+        step = 0.5 * (Pn - P)
+        w = P - W * np.floor(P / W) - 0.5 * W + c      # wrapped into the box around the centre
+        X0s.append(w)
+        X1s.append(w + step)
+    lim = g - delta
+    recs_list = []
+    base = 0
+    for X0, X1 in zip(X0s, X1s):
+        inside = np.abs(X0 - c).sum(axis=1) < lim
+        n = len(X0)
+        keep_idx = np.nonzero(inside)[0]
+        if len(keep_idx) == 0:
+            continue
+        new_id = -np.ones(n, dtype=np.int64)
+        new_id[keep_idx] = base + np.arange(len(keep_idx))
+        r = np.zeros(len(keep_idx), dtype=REC_DTYPE)
+        r["id"] = new_id[keep_idx]
+        r["next_id"] = new_id[(keep_idx + 1) % n]
+        r["prev_id"] = new_id[(keep_idx - 1) % n]
+        r["step"] = 1
+        r["x"][:, :3] = X1[keep_idx]
+        r["x"][:, 3] = t_mid + 0.5 * delta
+        r["x_prev"][:, :3] = X0[keep_idx]
+        r["x_prev"][:, 3] = t_mid
+        recs_list.append(r)
+        base += len(keep_idx)
+    recs = np.concatenate(recs_list) if recs_list else np.zeros(0, dtype=REC_DTYPE)
+    L = box or float(2.0 ** np.ceil(np.log2(4 * g)))
+    return Network(recs=recs, box=float(L), delta=float(delta), t0=float(t_mid),
+                   cosmology=cosmology, chains=[], geom=geom, g=g)
+
+
+def lognormal_regions(n_regions=512, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2, seed=0):
+    """Per-region point targets of the batched workload: empty with probability p_empty,
+    else min(LogNormal(ln median, sigma), cap)."""
+    rng = np.random.default_rng(seed)
+    empty = rng.random(n_regions) < p_empty
+    n = np.minimum(np.exp(np.log(median) + sigma * rng.standard_normal(n_regions)), cap)
+    n = np.where(empty, 0, np.round(n)).astype(np.int64)
+    return n

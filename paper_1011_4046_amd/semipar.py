@@ -38,9 +38,10 @@ class Surface(ctypes.Structure):
 
 
 class RegionDesc(ctypes.Structure):
-    _fields_ = [("cosmology", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("cosmology", ctypes.c_int32), ("bounded", ctypes.c_int32),
                 ("box", ctypes.c_double), ("capacity", ctypes.c_int64),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("idx", ctypes.c_int32 * 4),
+                ("origin", ctypes.c_double * 4), ("inv2g", ctypes.c_double)]
 
 
 class EvolveParams(ctypes.Structure):
@@ -121,7 +122,7 @@ class Region:
     160-byte records (device-resident input).
     """
 
-    def __init__(self, recs, box, cosmology, capacity=0, stream=None):
+    def __init__(self, recs, box, cosmology, capacity=0, stream=None, geom=None):
         L = lib()
         if isinstance(recs, np.ndarray):
             recs = np.ascontiguousarray(recs, dtype=REC_DTYPE)
@@ -133,8 +134,17 @@ class Region:
             self._keep = recs
         if stream is None and mem == MEM_DEVICE:
             stream = _current_stream()
-        d = RegionDesc(int(cosmology), 0, float(box), int(capacity),
-                       stream if stream is not None else None)
+        d = RegionDesc()
+        d.cosmology = int(cosmology)
+        d.box = float(box)
+        d.capacity = int(capacity)
+        d.stream = stream if stream is not None else None
+        if geom is not None:  # (origin[4], inv2g, idx[4])
+            d.bounded = 1
+            for i in range(4):
+                d.origin[i] = float(geom[i])
+                d.idx[i] = int(geom[5 + i])
+            d.inv2g = float(geom[4])
         surf = Surface(ptr, n, -1, mem)
         h = ctypes.c_void_p()
         _check(L.region_init_from_surfaces(ctypes.byref(d), ctypes.byref(surf), 1, ctypes.byref(h)),
@@ -154,16 +164,21 @@ class Region:
         _check(lib().region_evolve(self.h, ctypes.byref(p), ctypes.byref(st)), "region_evolve")
         return st.as_dict()
 
-    def emit(self):
-        """Final surface records (host numpy array, slot order)."""
+    def emit_faces(self):
+        """Output surfaces: list of 4 host record arrays (one per final face)."""
         L = lib()
         n = (ctypes.c_int64 * 4)()
         _check(L.region_emit_final_surfaces(self.h, None, None, n, MEM_HOST), "emit (count)")
-        out = np.zeros(n[0], dtype=REC_DTYPE)
-        ptrs = (ctypes.c_void_p * 4)(out.ctypes.data if n[0] else None, None, None, None)
-        cap = (ctypes.c_int64 * 4)(n[0], 0, 0, 0)
+        outs = [np.zeros(n[f], dtype=REC_DTYPE) for f in range(4)]
+        ptrs = (ctypes.c_void_p * 4)(*[o.ctypes.data if len(o) else None for o in outs])
+        cap = (ctypes.c_int64 * 4)(*[len(o) for o in outs])
         _check(L.region_emit_final_surfaces(self.h, ptrs, cap, n, MEM_HOST), "emit")
-        return out
+        return outs
+
+    def emit(self):
+        """All output records (host numpy array): slot order for a whole-volume region,
+        faces 0..3 concatenated for a bounded one."""
+        return np.concatenate(self.emit_faces())
 
     def emit_device(self, out_tensor):
         """Write the final surface into a torch uint8 CUDA tensor (n*160 bytes)."""

@@ -38,16 +38,18 @@ def test_record_layouts_match_header():
     from paper_1011_4046_amd.inputs import EVENT_DTYPE, REC_DTYPE
     assert REC_DTYPE.itemsize == 160 and EVENT_DTYPE.itemsize == 56
     assert ctypes.sizeof(S.EvolveParams) == 64
-    assert ctypes.sizeof(S.RegionDesc) == 32
+    assert ctypes.sizeof(S.RegionDesc) == 32 + 16 + 32 + 8
 
 
 def test_argument_errors_without_gpu():
     L = S.lib()
     h = ctypes.c_void_p()
     assert L.region_init_from_surfaces(None, None, 0, ctypes.byref(h)) == -1
-    d = S.RegionDesc(0, 0, -1.0, 0, None)
+    d = S.RegionDesc()
+    d.box = -1.0
     assert L.region_init_from_surfaces(ctypes.byref(d), None, 0, ctypes.byref(h)) == -1
-    d = S.RegionDesc(7, 0, 1.0, 0, None)
+    d = S.RegionDesc()
+    d.cosmology, d.box = 7, 1.0
     assert L.region_init_from_surfaces(ctypes.byref(d), None, 0, ctypes.byref(h)) == -1
     assert L.region_evolve(None, None, None) == -1
     n = (ctypes.c_int64 * 4)()

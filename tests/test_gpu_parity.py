@@ -243,3 +243,92 @@ def test_repeat_runs_identical(S):
     a = run_gpu(S, net, 150)
     b = run_gpu(S, net, 150)
     assert a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
+
+
+# ---------------------------------------------------------------------------------
+# bounded regions (one 4-cube of the tiling)
+# ---------------------------------------------------------------------------------
+def run_gpu_region(S, net, steps=100000, **kw):
+    r = S.Region(net["recs"], net["box"], net["cosmology"], geom=net["geom"])
+    st = r.evolve(steps, **kw)
+    faces, ev = r.emit_faces(), r.events()
+    r.close()
+    return faces, ev, st
+
+
+def assert_same_records(g, o):
+    g, o = by_id(g), by_id(o)
+    assert len(g) == len(o)
+    for f in ("id", "next_id", "prev_id", "step", "flags"):
+        assert np.array_equal(g[f], o[f]), f
+    for f in ("x", "x_prev", "r", "r_prev"):
+        scale = max(1.0, float(np.abs(o[f]).max()) if len(o) else 1.0)
+        assert float(np.abs(g[f] - o[f]).max() if len(o) else 0.0) / scale <= REL_TOL, f
+    assert g.tobytes() == o.tobytes()
+
+
+def check_faces(faces):
+    for f, recs in enumerate(faces):
+        face = (recs["flags"] >> 8) - 1
+        frozen = (recs["flags"] & 2) != 0
+        if f == 0:
+            assert np.all(~frozen | (face <= 0))
+        else:
+            assert np.all(frozen & (face == f))
+
+
+@pytest.mark.parametrize("n_target,seed,screen", [(600, 1, 0), (3000, 2, 1), (20000, 3, 1),
+                                                  (20000, 4, 0)])
+def test_bounded_region_matter_parity(S, n_target, seed, screen):
+    say(f"case: bounded region, VV cut to the octahedron, ~{n_target} points, seed {seed}, "
+        f"screen {screen}")
+    net = I.region_network(n_target, 4.0, seed=seed)
+    faces, ge, st = run_gpu_region(S, net, screen=screen)
+    o, oe, ost = run_oracle(net, 100000)
+    assert st["steps"] == ost["steps"] and st["point_steps"] == ost["point_steps"]
+    assert_same_events(ge, oe)
+    assert_same_records(np.concatenate(faces), o)
+    check_faces(faces)
+
+
+def _loops_in_region(size, t_mid, n_loops=3, n_pts=64, seed=0, cosmology=I.FLAT):
+    geom, g = I.region_geometry(size, t_mid)
+    rng = np.random.default_rng(seed)
+    chains = []
+    for _ in range(n_loops):
+        a = I._fourier_closed_curve(rng, 3, n_pts, 1 << 12) * (0.6 * g)
+        b = I._fourier_closed_curve(rng, 3, n_pts, 1 << 12) * (0.6 * g)
+        c = rng.uniform(-0.15 * g, 0.15 * g, 3)
+        k = np.arange(n_pts)
+        chains.append(dict(A=a[(-k) % n_pts] + c, B=b[k] + c, wA=np.zeros(3), wB=np.zeros(3)))
+    net = I.make_network(chains, 64.0, 0.6 * g / n_pts, t_mid, cosmology)
+    net["geom"] = geom
+    return net
+
+
+@pytest.mark.parametrize("cosmo", [I.FLAT, I.MATTER])
+def test_bounded_region_loops_parity(S, cosmo):
+    say(f"case: bounded region with closed loops, cosmology {cosmo}")
+    net = _loops_in_region(4.0, 8.0, n_loops=6, n_pts=128, seed=11, cosmology=cosmo)
+    faces, ge, st = run_gpu_region(S, net)
+    o, oe, _ = run_oracle(net, 100000)
+    assert_same_events(ge, oe)
+    assert_same_records(np.concatenate(faces), o)
+
+
+def test_bounded_region_stopped_early_emits_active(S):
+    say("case: bounded region stopped after 10 steps")
+    net = I.region_network(3000, 4.0, seed=5)
+    faces, ge, st = run_gpu_region(S, net, steps=10)
+    o, oe, _ = run_oracle(net, 10)
+    g = np.concatenate(faces)
+    assert np.any(g["flags"] & 4) and np.any(g["flags"] & 2)
+    assert_same_events(ge, oe)
+    assert_same_records(g, o)
+
+
+def test_bounded_empty_region(S):
+    say("case: empty bounded region")
+    net = I.region_network(0, 4.0, seed=0)
+    faces, ge, st = run_gpu_region(S, net)
+    assert st["steps"] == 0 and sum(len(f) for f in faces) == 0 and len(ge) == 0
