@@ -117,10 +117,22 @@ typedef struct semipar_surface {
  *              otherwise it stops and is emitted on the face its diamond leaves by.
  *              Links may dangle (next_id/prev_id = -1).
  *   idx, origin, inv2g  region index, lattice origin (x, y, z, tau) and 1/(2 g)
+ *   n_sub, sub  a batch: with bounded = 1 and n_sub > 0, surface i of the init call
+ *              holds the points of sub-region i, whose geometry is sub[i]. The
+ *              sub-regions evolve together, step for step, in one set of launches; they
+ *              must not overlap in space (they never interact) and their point ids
+ *              must be distinct. Results equal those of separate runs.
  *   stream     hipStream_t to run on. NULL: the library creates its own blocking
  *              stream of default priority (ordered against the null stream), since
  *              the null stream cannot be captured into a graph. All work of the
  *              region is ordered on this stream. */
+/* Geometry of one 4-cube region: index, lattice origin (x, y, z, tau), 1/(2 g). */
+typedef struct semipar_region_geom {
+  int32_t idx[4];
+  double origin[4];
+  double inv2g;
+} semipar_region_geom;
+
 typedef struct semipar_region_desc {
   int32_t cosmology;
   int32_t bounded;
@@ -130,6 +142,9 @@ typedef struct semipar_region_desc {
   int32_t idx[4];
   double origin[4];
   double inv2g;
+  int32_t n_sub;                   /* > 0: a batch of n_sub independent bounded regions */
+  int32_t reserved;
+  const semipar_region_geom* sub;  /* n_sub geometries (host memory, copied) */
 } semipar_region_desc;
 
 /* Evolution parameters.

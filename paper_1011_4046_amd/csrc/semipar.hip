@@ -293,7 +293,9 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
                                                uint64_t* __restrict__ blkred,
                                                int32_t* __restrict__ fstep,
                                                int32_t* __restrict__ face,
-                                               semipar_point_rec* __restrict__ frz, RegionGeom G) {
+                                               semipar_point_rec* __restrict__ frz, RegionGeom G0,
+                                               const RegionGeom* __restrict__ geoms,
+                                               const int32_t* __restrict__ rid) {
   if (ctrl->done) return;
   const int s = ctrl->step;
   const Cells cs = ctrl->cells;
@@ -305,6 +307,9 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   if (k < n) {
     bool adv = true;
     int j = nxt[k];
+    // geometry of k's region (links never leave a region, so also next[k]'s)
+    RegionGeom G;
+    if constexpr (BND) G = rid ? geoms[rid[k]] : G0;
     if constexpr (BND) {
       adv = false;
       if (fstep[k] == FS_ACTIVE) {
@@ -1333,6 +1338,9 @@ struct semipar_region {
   int64_t n = 0, cap = 0;
   bool bounded = false;
   RegionGeom geom{};
+  int32_t n_sub = 0;
+  RegionGeom* geoms = nullptr;  // batch: geometry of each sub-region
+  int32_t* rid = nullptr;       // batch: sub-region of each point
   int32_t *fstep = nullptr, *face = nullptr;  // bounded: stop step and exit face per point
   semipar_point_rec* frz = nullptr;           // bounded: record of each stopped point
   int cosmology = 0;
@@ -1540,7 +1548,7 @@ template <bool FRW, int SCR, bool BND>
 void launch_evolve_t(semipar_region* r, int n, int nb) {
   k_evolve<FRW, SCR, BND><<<nb, NT, 0, r->stream>>>(
       r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell, r->epos,
-      r->cnt, r->large, r->blkred, r->fstep, r->face, r->frz, r->geom);
+      r->cnt, r->large, r->blkred, r->fstep, r->face, r->frz, r->geom, r->geoms, r->rid);
 }
 
 template <bool FRW, bool BND>
@@ -1670,6 +1678,8 @@ void region_destroy(semipar_region* r) {
   dfree(r->prv);
   dfree(r->id);
   dfree(r->blkred);
+  dfree(r->geoms);
+  dfree(r->rid);
   dfree(r->fstep);
   dfree(r->face);
   dfree(r->frz);
@@ -1690,7 +1700,11 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
   if (!d || n_in < 0 || (n_in > 0 && !in)) return SEMIPAR_E_ARG;
   if (!(d->box > 0.0) || d->cosmology < 0 || d->cosmology > 2 || d->capacity < 0)
     return SEMIPAR_E_ARG;
-  if (d->bounded && !(d->inv2g > 0.0)) return SEMIPAR_E_ARG;
+  if (d->bounded && d->n_sub == 0 && !(d->inv2g > 0.0)) return SEMIPAR_E_ARG;
+  if (d->n_sub < 0 || (d->n_sub > 0 && (!d->bounded || !d->sub || d->n_sub != n_in)))
+    return SEMIPAR_E_ARG;
+  for (int i = 0; i < d->n_sub; ++i)
+    if (!(d->sub[i].inv2g > 0.0)) return SEMIPAR_E_ARG;
   int64_t total = 0;
   for (int i = 0; i < n_in; ++i) {
     if (in[i].n < 0 || (in[i].n > 0 && !in[i].recs)) return SEMIPAR_E_ARG;
@@ -1746,6 +1760,30 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
     return fail(SEMIPAR_E_OOM);
   if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
     return fail(SEMIPAR_E_OOM);
+  if (d->n_sub > 0) {
+    // batch: per-point sub-region ids (surface order) and the geometry table
+    r->n_sub = d->n_sub;
+    std::vector<RegionGeom> hg((size_t)d->n_sub);
+    for (int i = 0; i < d->n_sub; ++i) {
+      for (int q = 0; q < 4; ++q) {
+        hg[i].V[q] = d->sub[i].origin[q];
+        hg[i].idx[q] = d->sub[i].idx[q];
+      }
+      hg[i].inv2g = d->sub[i].inv2g;
+      hg[i].sqrt3 = std::sqrt(3.0);
+    }
+    std::vector<int32_t> hr((size_t)std::max<int64_t>(total, 1));
+    int64_t off = 0;
+    for (int i = 0; i < n_in; ++i)
+      for (int64_t q = 0; q < in[i].n; ++q) hr[off++] = i;
+    if (dalloc(&r->geoms, d->n_sub) != hipSuccess || dalloc(&r->rid, cap) != hipSuccess)
+      return fail(SEMIPAR_E_OOM);
+    if (hipMemcpy(r->geoms, hg.data(), sizeof(RegionGeom) * d->n_sub, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        (total > 0 && hipMemcpy(r->rid, hr.data(), sizeof(int32_t) * total,
+                                hipMemcpyHostToDevice) != hipSuccess))
+      return fail(SEMIPAR_E_HIP);
+  }
   if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess)
     return fail(SEMIPAR_E_HIP);
   Ctrl c0{};

@@ -179,95 +179,99 @@ def vv_chains(m, rng, xi=1.0, pts_per_xi=8, jitter=0.15):
 
     Path: face centre -> (cube centre + offset) -> face centre. The offset is drawn
     per cube traversal, uniform in [-jitter, jitter]^3 * xi, so that the 2 or 3
-    strings crossing one cube do not touch. The closed polyline is sampled every
+    strings crossing one cube do not touch. Each closed polyline is sampled every
     delta = xi/pts_per_xi of arc length from its first face centre; the closing
-    chord is the remainder (< delta). Cubes with 2 or 3 strings pair their entry
-    and exit faces by a seeded random permutation (cubes in index order).
-    rng order: phases, pairings, offsets (tracing order).
+    chord is the remainder (< delta). Cubes with 2 or 3 strings pair their entry and
+    exit faces by ranking seeded random keys. rng order: phases (m^3), pairing keys
+    (6 per cube), offsets (3 per pierced face, in face order).
     Returns a list of (P, winding) with P the unwrapped points (n x 3).
     """
     phase = rng.integers(0, 3, size=(m, m, m))
-    w = vv_faces(phase)
+    w = vv_faces(phase)                                   # (3, m, m, m) in {-1,0,1}
     M3 = m * m * m
-    fid = lambda ax, i, j, k: ax * M3 + ((i % m) * m + (j % m)) * m + (k % m)
-    succ = {}
-    for i in range(m):
-        for j in range(m):
-            for k in range(m):
-                ins, outs = [], []
-                for ax in range(3):
-                    lo = (i, j, k)
-                    hi = [i, j, k]
-                    hi[ax] += 1
-                    wl = w[ax, lo[0] % m, lo[1] % m, lo[2] % m]
-                    wh = w[ax, hi[0] % m, hi[1] % m, hi[2] % m]
-                    if wl == 1:
-                        ins.append(fid(ax, *lo))
-                    elif wl == -1:
-                        outs.append((fid(ax, *lo), ax, -1))
-                    if wh == -1:
-                        ins.append(fid(ax, *hi))
-                    elif wh == 1:
-                        outs.append((fid(ax, *hi), ax, +1))
-                assert len(ins) == len(outs)
-                if len(ins) == 0:
-                    continue
-                perm = rng.permutation(len(outs)) if len(outs) > 1 else [0]
-                for a, f in enumerate(ins):
-                    succ[f] = outs[perm[a]]
-
-    def face_centre(f):
-        ax, rest = divmod(f, M3)
-        i, rest = divmod(rest, m * m)
-        j, k = divmod(rest, m)
-        c = np.array([i + 0.5, j + 0.5, k + 0.5])
-        c[ax] -= 0.5
-        return c
-
-    def flux_dir(f):
-        ax = f // M3
-        a = f % M3
-        i, rest = divmod(a, m * m)
-        j, k = divmod(rest, m)
-        d = np.zeros(3)
-        d[ax] = float(w[ax, i, j, k])
-        return d
-
-    delta = 1.0 / pts_per_xi
+    I_, J_, K_ = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    cube = (I_ * m + J_) * m + K_
+    # the 6 faces of every cube: (axis, lower/upper); face id = axis*M3 + site index
+    face_ids, fw, is_hi = [], [], []
+    for ax in range(3):
+        for hi in (0, 1):
+            sh = [I_, J_, K_]
+            sh[ax] = (sh[ax] + hi) % m
+            site = (sh[0] * m + sh[1]) * m + sh[2]
+            face_ids.append(ax * M3 + site)
+            fw.append(w[ax].reshape(-1)[site])
+            is_hi.append(np.full(cube.shape, hi))
+    F = np.stack([f.reshape(-1) for f in face_ids], 1)         # (M3, 6)
+    Wf = np.stack([f.reshape(-1) for f in fw], 1)
+    H = np.stack([f.reshape(-1) for f in is_hi], 1)
+    # flux into the cube: lower face with w=+1 or upper face with w=-1
+    incoming = ((H == 0) & (Wf == 1)) | ((H == 1) & (Wf == -1))
+    outgoing = ((H == 0) & (Wf == -1)) | ((H == 1) & (Wf == 1))
+    assert np.all(incoming.sum(1) == outgoing.sum(1))
+    keys = rng.random((M3, 6))
+    # rank incoming faces by position, outgoing faces by random key; pair equal ranks
+    big = 10.0
+    in_order = np.argsort(np.where(incoming, np.arange(6)[None, :], big), axis=1, kind="stable")
+    out_order = np.argsort(np.where(outgoing, keys, big), axis=1, kind="stable")
+    nio = incoming.sum(1)
+    succ = -np.ones(3 * M3, dtype=np.int64)
+    out_dir = np.zeros(3 * M3, dtype=np.int64)         # exit sign of the paired face
+    rows = np.arange(M3)
+    for r in range(3):
+        sel = nio > r
+        fi = F[rows[sel], in_order[sel, r]]
+        slot = out_order[sel, r]
+        fo = F[rows[sel], slot]
+        succ[fi] = fo
+        out_dir[fi] = np.where(H[rows[sel], slot] == 1, 1, -1)
+    pierced = np.nonzero(succ >= 0)[0]
+    offsets = np.zeros((3 * M3, 3))
+    offsets[pierced] = rng.uniform(-jitter, jitter, (len(pierced), 3))
+    # chains = cycles of the permutation succ over pierced faces
+    label = -np.ones(3 * M3, dtype=np.int64)
     chains = []
-    visited = set()
-    for f0 in sorted(succ.keys()):
-        if f0 in visited:
+    step = 1.0 / pts_per_xi
+    axis_of = lambda f: f // M3
+    for f0 in pierced:
+        if label[f0] >= 0:
             continue
-        F = face_centre(f0)
-        start = F.copy()
-        din = flux_dir(f0)
-        verts = [F.copy()]
-        f = f0
-        while True:
-            visited.add(f)
-            nf, ax, sgn = succ[f]
-            dout = np.zeros(3)
-            dout[ax] = float(sgn)
-            C = F + 0.5 * din
-            verts.append(C + rng.uniform(-jitter, jitter, 3))
-            F = C + 0.5 * dout
-            verts.append(F.copy())
-            din = dout
-            f = nf
-            if f == f0:
-                break
-        V = np.array(verts)                      # closed: V[-1] = V[0] + m * winding
+        cyc = [f0]
+        label[f0] = len(chains)
+        f = succ[f0]
+        while f != f0:
+            label[f] = len(chains)
+            cyc.append(f)
+            f = succ[f]
+        cyc = np.asarray(cyc)
+        ax = axis_of(cyc)
+        site = cyc % M3
+        fi_, rest = np.divmod(site, m * m)
+        fj_, fk_ = np.divmod(rest, m)
+        start = np.array([fi_[0] + 0.5, fj_[0] + 0.5, fk_[0] + 0.5])
+        start[ax[0]] -= 0.5
+        din = np.zeros((len(cyc), 3))
+        din[np.arange(len(cyc)), ax] = w[ax, fi_, fj_, fk_]
+        dout = np.zeros((len(cyc), 3))
+        nxt = np.roll(cyc, -1)
+        dout[np.arange(len(cyc)), axis_of(nxt)] = out_dir[cyc]
+        # face centres along the unwrapped path: F_{i+1} = F_i + din_i/2 + dout_i/2
+        moves = 0.5 * din + 0.5 * dout
+        Fc = start + np.concatenate([np.zeros((1, 3)), np.cumsum(moves, axis=0)])
+        C = Fc[:-1] + 0.5 * din + offsets[cyc]
+        V = np.empty((2 * len(cyc) + 1, 3))
+        V[0:-1:2] = Fc[:-1]
+        V[1::2] = C
+        V[-1] = Fc[-1]
         seg = np.linalg.norm(np.diff(V, axis=0), axis=1)
         cum = np.concatenate([[0.0], np.cumsum(seg)])
-        n = int(np.floor(cum[-1] / delta))
-        if cum[-1] - n * delta < 1e-9:
+        n = int(np.floor(cum[-1] / step))
+        if cum[-1] - n * step < 1e-9:
             n -= 1
-        u = np.arange(n + 1, dtype=np.float64) * delta
+        u = np.arange(n + 1, dtype=np.float64) * step
         i = np.clip(np.searchsorted(cum, u, side="right") - 1, 0, len(seg) - 1)
         fr = (u - cum[i]) / seg[i]
         P = V[i] + fr[:, None] * (V[i + 1] - V[i])
-        wind = np.rint((V[-1] - start) / m).astype(np.int64)
+        wind = np.rint((V[-1] - V[0]) / m).astype(np.int64)
         chains.append((P * xi, wind))
     return chains
 
@@ -446,3 +450,26 @@ def lognormal_regions(n_regions=512, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2
     n = np.minimum(np.exp(np.log(median) + sigma * rng.standard_normal(n_regions)), cap)
     n = np.where(empty, 0, np.round(n)).astype(np.int64)
     return n
+
+
+def region_batch(n_targets, size=4.0, seed=0, t_mid=8.0, slots=8, cosmology=MATTER):
+    """Independent first-layer regions on the slots of a periodic box (slots^3 slots,
+    slot spacing >= 2 g + 1, so regions never overlap). Region r has point target
+    n_targets[r] and seed seed + r; its ids are offset to be unique in the batch.
+    Returns (parts, box) with parts = [(recs, geom), ...]."""
+    g = size / np.sqrt(2.0)
+    box = float(2.0 ** np.ceil(np.log2(slots * (2 * g + 1.0))))
+    spacing = box / slots
+    parts = []
+    id_off = 0
+    for r, nt in enumerate(n_targets):
+        i, j, k = r // (slots * slots), (r // slots) % slots, r % slots
+        centre = (spacing * (i + 0.5), spacing * (j + 0.5), spacing * (k + 0.5))
+        net = region_network(int(nt), size, seed + r, t_mid, centre, cosmology=cosmology, box=box)
+        recs = net["recs"].copy()
+        recs["id"] += id_off
+        for f in ("next_id", "prev_id"):
+            recs[f] = np.where(recs[f] >= 0, recs[f] + id_off, -1)
+        parts.append((recs, net["geom"]))
+        id_off += len(recs)
+    return parts, box

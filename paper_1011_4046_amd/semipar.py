@@ -37,11 +37,27 @@ class Surface(ctypes.Structure):
                 ("mem", ctypes.c_int32)]
 
 
+class RegionGeom(ctypes.Structure):
+    _fields_ = [("idx", ctypes.c_int32 * 4), ("origin", ctypes.c_double * 4),
+                ("inv2g", ctypes.c_double)]
+
+
+def _geom_struct(geom):
+    g = RegionGeom()
+    for i in range(4):
+        g.origin[i] = float(geom[i])
+        g.idx[i] = int(geom[5 + i])
+    g.inv2g = float(geom[4])
+    return g
+
+
 class RegionDesc(ctypes.Structure):
     _fields_ = [("cosmology", ctypes.c_int32), ("bounded", ctypes.c_int32),
                 ("box", ctypes.c_double), ("capacity", ctypes.c_int64),
                 ("stream", ctypes.c_void_p), ("idx", ctypes.c_int32 * 4),
-                ("origin", ctypes.c_double * 4), ("inv2g", ctypes.c_double)]
+                ("origin", ctypes.c_double * 4), ("inv2g", ctypes.c_double),
+                ("n_sub", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sub", ctypes.c_void_p)]
 
 
 class EvolveParams(ctypes.Structure):
@@ -121,6 +137,32 @@ class Region:
     ``recs``: a numpy REC_DTYPE array (host) or a torch uint8 CUDA tensor holding
     160-byte records (device-resident input).
     """
+
+    @classmethod
+    def batch(cls, parts, box, cosmology, stream=None):
+        """One region holding many independent bounded regions: parts = [(recs, geom)]."""
+        self = cls.__new__(cls)
+        L = lib()
+        surfs = (Surface * max(len(parts), 1))()
+        geoms = (RegionGeom * max(len(parts), 1))()
+        keep = []
+        total = 0
+        for i, (recs, geom) in enumerate(parts):
+            recs = np.ascontiguousarray(recs, dtype=REC_DTYPE)
+            keep.append(recs)
+            surfs[i] = Surface(recs.ctypes.data if len(recs) else None, len(recs), -1, MEM_HOST)
+            geoms[i] = _geom_struct(geom)
+            total += len(recs)
+        d = RegionDesc()
+        d.cosmology, d.box, d.bounded = int(cosmology), float(box), 1
+        d.stream = stream
+        d.n_sub = len(parts)
+        d.sub = ctypes.cast(geoms, ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(L.region_init_from_surfaces(ctypes.byref(d), surfs, len(parts), ctypes.byref(h)),
+               "region_init_from_surfaces (batch)")
+        self.h, self.n, self._keep = h, total, None
+        return self
 
     def __init__(self, recs, box, cosmology, capacity=0, stream=None, geom=None):
         L = lib()

@@ -38,7 +38,8 @@ def test_record_layouts_match_header():
     from paper_1011_4046_amd.inputs import EVENT_DTYPE, REC_DTYPE
     assert REC_DTYPE.itemsize == 160 and EVENT_DTYPE.itemsize == 56
     assert ctypes.sizeof(S.EvolveParams) == 64
-    assert ctypes.sizeof(S.RegionDesc) == 32 + 16 + 32 + 8
+    assert ctypes.sizeof(S.RegionDesc) == 32 + 16 + 32 + 8 + 16
+    assert ctypes.sizeof(S.RegionGeom) == 56
 
 
 def test_argument_errors_without_gpu():

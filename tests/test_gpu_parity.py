@@ -332,3 +332,30 @@ def test_bounded_empty_region(S):
     net = I.region_network(0, 4.0, seed=0)
     faces, ge, st = run_gpu_region(S, net)
     assert st["steps"] == 0 and sum(len(f) for f in faces) == 0 and len(ge) == 0
+
+
+def test_region_batch_equals_separate_regions(S):
+    """A batch of independent regions evolved in one set of launches gives exactly the
+    union of the regions' separate results (oracle, one region at a time)."""
+    sizes = [0, 300, 5000, 1200, 0, 20000, 800, 2500, 40, 9000]
+    say(f"case: batch of {len(sizes)} regions, sizes {sizes}")
+    parts, box = I.region_batch(sizes, seed=100)
+    r = S.Region.batch(parts, box, I.MATTER)
+    st = r.evolve(100000)
+    faces, ge = r.emit_faces(), r.events()
+    r.close()
+    recs, evs, psteps, steps = [], [], 0, 0
+    for recs_i, geom in parts:
+        if len(recs_i) == 0:
+            continue
+        net = dict(recs=recs_i, box=box, cosmology=I.MATTER, geom=geom)
+        o, oe, ost = run_oracle(net, 100000)
+        recs.append(o)
+        evs.append(oe)
+        psteps += ost["point_steps"]
+        steps = max(steps, ost["steps"])
+    oe = np.concatenate(evs)
+    oe = oe[np.lexsort((oe["id_b"], oe["id_a"], oe["t_star"], oe["step"]))]
+    assert st["point_steps"] == psteps and st["steps"] == steps
+    assert_same_events(ge, oe)
+    assert_same_records(np.concatenate(faces), np.concatenate(recs))
