@@ -260,6 +260,155 @@ const char* semipar_last_error(void);
 /* Library build string (compiler, target). */
 const char* semipar_version(void);
 
+
+/* ---- many regions: the tiling and the scheduler ---------------------------------- */
+
+/* A set of regions to run (paper, Section "Implementation": a manager keeps the
+ * regions whose predecessors have all finished and hands them to idle workers).
+ *   n_regions  number of regions (>= 0)
+ *   cosmology, box  as in semipar_region_desc, shared by all regions
+ *   surfaces   n_regions initial surfaces, surfaces[r] the points of region r (n = 0:
+ *              an empty region, which is only noted, never launched). Point ids must
+ *              be distinct over the whole tiling. Host or device memory per surface.
+ *   geoms      n_regions region geometries (host)
+ *   n_pred     NULL: the regions are independent. Else, per region, the number of
+ *              predecessors that must finish before it may start; succ_off (n_regions
+ *              + 1 offsets) and succ list each region's successors. A region becomes
+ *              ready when its count reaches zero. This orders the work only: a
+ *              successor's input is its own surface, not its predecessors' output.
+ *   stream     hipStream_t for all work (NULL: each region creates its own stream). */
+typedef struct semipar_tiling {
+  int32_t n_regions;
+  int32_t cosmology;
+  double box;
+  const semipar_surface* surfaces;
+  const semipar_region_geom* geoms;
+  const int32_t* n_pred;
+  const int32_t* succ_off;
+  const int32_t* succ;
+  void* stream;
+} semipar_tiling;
+
+enum {
+  SEMIPAR_SCHED_PLAIN = 0,  /* one region at a time, each its own launch sequence */
+  SEMIPAR_SCHED_BATCHED = 1 /* ready regions packed into batches (one set of launches
+                               per batch over the points of all its regions) */
+};
+
+/* Scheduler parameters.
+ *   policy        SEMIPAR_SCHED_PLAIN or SEMIPAR_SCHED_BATCHED
+ *   batch_points  BATCHED: at most this many points per batch (a larger region gets a
+ *                 batch of its own); 0 = all ready regions in one batch
+ *   cost          BATCHED: host array of n_regions predicted costs (lattice steps,
+ *                 e.g. exp of the cost model's output); the ready regions are ordered
+ *                 by decreasing cost and cut into batches in that order. NULL: the
+ *                 point-count heuristic (decreasing number of points). Ordering only:
+ *                 results never depend on it.
+ *   evolve        parameters of every region_evolve call (max_steps, t_end, screen,
+ *                 graphs, ...). Each region runs until all its points have stopped
+ *                 unless max_steps or t_end ends it first.
+ *   out, out_mem  output records (host or device), capacity = total input records;
+ *                 region r owns out[out_off[4r] .. out_off[4r+4]) with its face-f
+ *                 records at out_off[4r+f] .. out_off[4r+f+1] (same content and order
+ *                 as region_emit_final_surfaces of that region run alone). NULL: not
+ *                 written.
+ *   out_off       host, 4 n_regions + 1 entries, or NULL
+ *   events, events_cap, events_off  host event buffer, its capacity and n_regions + 1
+ *                 offsets: region r's events (listing order) at events_off[r] ..
+ *                 events_off[r+1]. Offsets count every event; entries past events_cap
+ *                 are not written (stats.events is the total). NULL: not returned.
+ *   region_steps, region_point_steps, region_batch, region_ms  optional host arrays
+ *                 (n_regions) receiving per-region logs: slices advanced by the
+ *                 region's furthest point, its point-steps, the batch that ran it (-1:
+ *                 empty) and the device time of that batch's evolve call. These are
+ *                 the costs the cost model is trained on. */
+typedef struct semipar_sched_params {
+  int32_t policy;
+  int32_t out_mem;
+  int64_t batch_points;
+  const float* cost;
+  semipar_evolve_params evolve;
+  semipar_point_rec* out;
+  int64_t* out_off;
+  semipar_event* events;
+  int64_t events_cap;
+  int64_t* events_off;
+  int32_t* region_steps;
+  int64_t* region_point_steps;
+  int32_t* region_batch;
+  double* region_ms;
+} semipar_sched_params;
+
+typedef struct semipar_sched_stats {
+  int64_t regions;       /* regions finished */
+  int64_t empty_regions; /* of which empty (no launch) */
+  int64_t batches;       /* launch batches (PLAIN: one per non-empty region) */
+  int64_t point_steps;   /* over all regions */
+  int64_t steps;         /* lattice steps summed over batches */
+  int64_t events;        /* intercommutations over all regions */
+  double makespan_ms;    /* host wall time of the call, from the first upload to the
+                            last result */
+  double evolve_ms;      /* summed device time of the evolve calls */
+} semipar_sched_stats;
+
+/* Run every region of the tiling on this GPU, in dependency order (paper: manager and
+ * workers; empty regions only noted). Per region the result is exactly that of
+ * region_init_from_surfaces + region_evolve + region_emit_final_surfaces on that
+ * region alone. st may be NULL.
+ * Errors: SEMIPAR_E_ARG (bad tiling, or predecessor counts that leave regions never
+ * ready), SEMIPAR_E_SURFACE, SEMIPAR_E_OOM, SEMIPAR_E_HIP, SEMIPAR_E_OVERFLOW. */
+int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
+                     semipar_sched_stats* st);
+
+/* ---- the learned cost model --------------------------------------------------------- */
+#define SEMIPAR_MLP_IN 12
+#define SEMIPAR_MLP_HIDDEN 64
+#define SEMIPAR_MLP_PARAMS 5057 /* 64*12 + 64 + 64*64 + 64 + 64 + 1 */
+
+/* Cost-model features of each region's initial surface, computed on the GPU
+ * (host output, 12 floats per region, zeros for an empty region):
+ *   0 log1p(points)   1 log1p(open string pieces: points without a left neighbour)
+ *   2 RMS transverse speed of the first diamonds
+ *   3..10 occupancy histogram: the region's spatial cube of side 2g (g the generator
+ *         scale) in 16^3 cells; the fraction of points in cells whose count, relative
+ *         to the mean over all cells, has floor(log2) + 4 = b (clamped to 0..7)
+ *   11 log1p(mean distance to the right neighbour / region size) */
+int semipar_region_features(const semipar_tiling* t, float* feat);
+
+/* The cost model is a 12 -> 64 -> 64 -> 1 perceptron with ReLU, FP32. Parameters
+ * (SEMIPAR_MLP_PARAMS floats, row-major): W1[64][12], b1[64], W2[64][64], b2[64],
+ * w3[64], b3. Optional normalisation norm[24] (NULL: none): inputs become
+ * (x - norm[0..11]) * norm[12..23]. All array arguments below are device pointers
+ * unless marked host; x holds n rows of 12 features. The calls synchronise `stream`
+ * before returning. Errors: SEMIPAR_E_ARG, SEMIPAR_E_OOM, SEMIPAR_E_HIP. */
+
+/* y[s] = model(x[s]) for s < n. */
+int semipar_mlp_forward(const float* params, const float* norm, const float* x, int64_t n,
+                        float* y, void* stream);
+
+/* loss = mean over s of (model(x[s]) - target[s])^2 and grad = d loss / d params
+ * (loss may be NULL). Summation is in a fixed order (deterministic). */
+int semipar_mlp_loss_grad(const float* params, const float* norm, const float* x,
+                          const float* target, int64_t n, float* grad, float* loss,
+                          void* stream);
+
+/* One Adam update (Kingma and Ba) at 1-based step number `step`:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * params -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
+int semipar_mlp_adam_step(float* params, float* m, float* v, const float* grad, int64_t step,
+                          float lr, float beta1, float beta2, float eps, void* stream);
+
+/* iters full-batch Adam steps (b1 0.9, b2 0.999, eps 1e-8) on the mean squared error,
+ * numbered step0 + 1 .. step0 + iters. loss_host (host, iters + 1 floats, or NULL):
+ * the loss before each step and, last, at the final parameters. */
+int semipar_mlp_train(float* params, float* m, float* v, const float* norm, const float* x,
+                      const float* target, int64_t n, int32_t iters, int64_t step0, float lr,
+                      float* loss_host, void* stream);
+
+/* Host helper: per-feature mean and inverse standard deviation of n host rows, into
+ * norm[24] (host). A feature with standard deviation below 1e-6 gets scale 1. */
+int semipar_mlp_norm(const float* x, int64_t n, float* norm);
+
 #ifdef __cplusplus
 }
 #endif

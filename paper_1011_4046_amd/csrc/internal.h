@@ -1,0 +1,38 @@
+// internal.h -- calls shared between the translation units of libsemipar (not exported).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "semipar.h"
+
+#define SP_HIDDEN __attribute__((visibility("hidden")))
+
+namespace spi {
+
+// Number of points and the stream of a region.
+SP_HIDDEN int64_t region_points(const semipar_region* r);
+SP_HIDDEN hipStream_t region_stream(const semipar_region* r);
+
+// Batch of sub-regions (a region built with n_sub > 0), after region_evolve:
+// records of every sub-region into tmp (device, r->n records): sub-region q occupies
+// the slots of its input surface, its four streams in order, each in slot order;
+// cnt[4 q + f] = records of q on stream f.
+SP_HIDDEN int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& cnt);
+
+// Per sub-region: slices advanced by its furthest point and its point-steps.
+SP_HIDDEN int batch_stats(semipar_region* r, std::vector<int32_t>& steps,
+                          std::vector<int64_t>& psteps);
+
+// Logged events (listing order within each sub-region) and the sub-region of each.
+SP_HIDDEN int batch_events(semipar_region* r, std::vector<semipar_event>& ev,
+                           std::vector<int32_t>& sub);
+
+// The 12 cost-model features of each sub-region's current surface (host, 12 n_sub).
+SP_HIDDEN int batch_features(semipar_region* r, float* feat);
+
+// Record an error message for semipar_last_error.
+SP_HIDDEN void set_error(const char* msg);
+
+}  // namespace spi

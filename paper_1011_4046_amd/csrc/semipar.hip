@@ -30,6 +30,7 @@
 
 #include "semipar.h"
 #include "geom.h"
+#include "internal.h"
 
 #pragma clang fp contract(off)
 
@@ -871,7 +872,8 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     int32_t* __restrict__ nxt, int32_t* __restrict__ prv, const EvCand* __restrict__ ev,
     int cap_evt, int cap_cand, uint64_t* __restrict__ best, int32_t* __restrict__ used,
     int8_t* __restrict__ evs, semipar_event* __restrict__ log, int64_t log_cap,
-    const uint64_t* __restrict__ blkred, int nblk, Ctrl* ctrl) {
+    const uint64_t* __restrict__ blkred, int nblk, Ctrl* ctrl, const int32_t* __restrict__ rid,
+    int32_t* __restrict__ log_rid) {
   __shared__ int s_live;
   __shared__ int s_nacc;
   __shared__ uint64_t s_min[RESOLVE_NT / 64], s_max[RESOLVE_NT / 64], s_adv[RESOLVE_NT / 64];
@@ -959,6 +961,7 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
         o.x_star[1] = ev[e].y;
         o.x_star[2] = ev[e].z;
         log[log0 + i] = o;
+        if (log_rid) log_rid[log0 + i] = rid[a];
       }
   }
   // smallest t of the slice written by this step's k_evolve, largest element extent
@@ -1296,6 +1299,212 @@ __global__ __launch_bounds__(NT) void k_emit_write(Slices X, int n, int s, const
     out[pos] = current_record(X, k, s, nxt, prv, id, fstep ? SEMIPAR_FLAG_ACTIVE : 0);
 }
 
+// ---- batches of sub-regions: per-sub-region results -------------------------------
+// The points of sub-region q occupy the slots sub_off[q] .. sub_off[q+1]-1 (surface
+// order), so the records of q on stream f are the slots of q with that stream, in slot
+// order. P_f(k) = number of slots before k on stream f (exclusive, over the batch).
+
+// Exclusive in-block counts of the 4 streams before thread t (LDS scan of NT threads).
+__device__ __forceinline__ void block_stream_prefix(int f, int32_t (*sh)[NT], int32_t pre[4]) {
+  const int t = threadIdx.x;
+  for (int q = 0; q < 4; ++q) sh[q][t] = (f == q) ? 1 : 0;
+  __syncthreads();
+  for (int o = 1; o < NT; o <<= 1) {
+    int add[4];
+    for (int q = 0; q < 4; ++q) add[q] = t >= o ? sh[q][t - o] : 0;
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) sh[q][t] += add[q];
+    __syncthreads();
+  }
+  for (int q = 0; q < 4; ++q) pre[q] = sh[q][t] - ((f == q) ? 1 : 0);
+}
+
+// P_q at the first slot of every non-empty sub-region: pst[4 * sub + q].
+__global__ __launch_bounds__(NT) void k_emit_sub_start(int n, const int32_t* fstep,
+                                                       const semipar_point_rec* frz,
+                                                       const int32_t* __restrict__ rid,
+                                                       const int32_t* __restrict__ blkoff,
+                                                       int32_t* __restrict__ pst) {
+  __shared__ int32_t sh[4][NT];
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const int f = k < n ? emit_stream(k, fstep, frz) : -1;
+  int32_t pre[4];
+  block_stream_prefix(f, sh, pre);
+  if (k < n && (k == 0 || rid[k] != rid[k - 1]))
+    for (int q = 0; q < 4; ++q) pst[4 * rid[k] + q] = blkoff[4 * blockIdx.x + q] + pre[q];
+}
+
+// Record of slot k to tmp[dst[4 * sub + f] + P_f(k) - pst[4 * sub + f]].
+__global__ __launch_bounds__(NT) void k_emit_sub_write(Slices X, int n, int s, const int32_t* nxt,
+                                                       const int32_t* prv, const int64_t* id,
+                                                       const int32_t* fstep,
+                                                       const semipar_point_rec* frz,
+                                                       const int32_t* __restrict__ rid,
+                                                       const int32_t* __restrict__ blkoff,
+                                                       const int32_t* __restrict__ pst,
+                                                       const int64_t* __restrict__ dst,
+                                                       semipar_point_rec* __restrict__ out) {
+  __shared__ int32_t sh[4][NT];
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const int f = k < n ? emit_stream(k, fstep, frz) : -1;
+  int32_t pre[4];
+  block_stream_prefix(f, sh, pre);
+  if (f < 0) return;
+  const int q = rid[k];
+  const int64_t pos = dst[4 * q + f] + (blkoff[4 * blockIdx.x + f] + pre[f] - pst[4 * q + f]);
+  if (fstep[k] != FS_ACTIVE)
+    out[pos] = frz[k];
+  else
+    out[pos] = current_record(X, k, s, nxt, prv, id, SEMIPAR_FLAG_ACTIVE);
+}
+
+// True when every active lane of the wave holds the same sub-region as lane 0.
+__device__ __forceinline__ bool wave_uniform(int q, bool live) {
+  const int q0 = __shfl(q, 0, 64);
+  const uint64_t live_m = __ballot(live);
+  const uint64_t same_m = __ballot(live && q == q0);
+  return live_m == same_m && (live_m & 1ull);
+}
+
+// Per sub-region: point-steps (sum over its points of the slices advanced) and the
+// largest number of slices any of its points advanced.
+__global__ __launch_bounds__(NT) void k_sub_stats(int n, const int32_t* __restrict__ fstep,
+                                                  int32_t cur, int32_t step0,
+                                                  const int32_t* __restrict__ rid,
+                                                  unsigned long long* __restrict__ psteps,
+                                                  int32_t* __restrict__ smax) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const bool live = k < n;
+  const int q = live ? (rid ? rid[k] : 0) : -1;
+  int adv = 0;
+  if (live) adv = (fstep[k] == FS_ACTIVE ? cur : fstep[k]) - step0;
+  if (wave_uniform(q, live)) {
+    unsigned long long sum = (unsigned long long)adv;
+    int mx = adv;
+    for (int o = 32; o > 0; o >>= 1) {
+      sum += __shfl_xor(sum, o, 64);
+      const int w = __shfl_xor(mx, o, 64);
+      mx = w > mx ? w : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&psteps[q], sum);
+      atomicMax(&smax[q], mx);
+    }
+  } else if (live) {
+    atomicAdd(&psteps[q], (unsigned long long)adv);
+    atomicMax(&smax[q], adv);
+  }
+}
+
+// ---- cost-model features of the initial surface of each sub-region ----------------
+constexpr int FEAT_GRID = 16;  // cells per side of the occupancy grid of a region
+constexpr int FEAT_CELLS = FEAT_GRID * FEAT_GRID * FEAT_GRID;
+constexpr int FEAT_ACC = 5;  // sum v^2, count, sum edge, count, open pieces
+
+// Per point of the current surface (before any step): transverse speed of the diamond
+// at k (spatial (L-B)+(R-B) over its time extent), length of the edge to next[k] on
+// the current slice, open-piece starts (no prev), and the occupancy of a 16^3 grid
+// over the spatial cube of side 2g around the region's centre.
+__global__ __launch_bounds__(NT) void k_feat_points(Slices X, int n, int s,
+                                                    const int32_t* __restrict__ nxt,
+                                                    const int32_t* __restrict__ prv,
+                                                    const int32_t* __restrict__ rid,
+                                                    const RegionGeom* __restrict__ geoms,
+                                                    sp::Period P, double* __restrict__ acc,
+                                                    int32_t* __restrict__ grid) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const bool live = k < n;
+  const int q = live ? rid[k] : -1;
+  double v2 = 0.0, nv = 0.0, e = 0.0, ne = 0.0, open = 0.0;
+  if (live) {
+    const int ic = s % 3, ip = (s + 2) % 3;
+    const V4 L = ld(X, ic, k);
+    const int j = nxt[k];
+    if (j >= 0) {
+      const V4 R = ld(X, ic, j), B = ld(X, ip, j);
+      const double ax = sp::min_image(L.x - B.x, P), ay = sp::min_image(L.y - B.y, P),
+                   az = sp::min_image(L.z - B.z, P);
+      const double vx = ax + (R.x - B.x), vy = ay + (R.y - B.y), vz = az + (R.z - B.z);
+      const double dt = (L.t - B.t) + (R.t - B.t);
+      if (dt > 0.0) {
+        v2 = (vx * vx + vy * vy + vz * vz) / (dt * dt);
+        nv = 1.0;
+      }
+      const double ex = sp::min_image(R.x - L.x, P), ey = sp::min_image(R.y - L.y, P),
+                   ez = sp::min_image(R.z - L.z, P);
+      e = sqrt(ex * ex + ey * ey + ez * ez);
+      ne = 1.0;
+    }
+    if (prv[k] < 0) open = 1.0;
+    const RegionGeom& G = geoms[q];
+    const double g = 0.5 / G.inv2g;
+    const double c[3] = {sp::min_image(L.x - G.V[0], P), sp::min_image(L.y - G.V[1], P),
+                         sp::min_image(L.z - G.V[2], P)};
+    int ci[3];
+    for (int a = 0; a < 3; ++a) {
+      const int v = (int)floor((c[a] + g) * (FEAT_GRID / (2.0 * g)));
+      ci[a] = v < 0 ? 0 : (v >= FEAT_GRID ? FEAT_GRID - 1 : v);
+    }
+    atomicAdd(&grid[(int64_t)q * FEAT_CELLS + (ci[0] * FEAT_GRID + ci[1]) * FEAT_GRID + ci[2]], 1);
+  }
+  double* a = acc + (int64_t)FEAT_ACC * (q < 0 ? 0 : q);
+  if (wave_uniform(q, live)) {
+    for (int o = 32; o > 0; o >>= 1) {
+      v2 += __shfl_xor(v2, o, 64);
+      nv += __shfl_xor(nv, o, 64);
+      e += __shfl_xor(e, o, 64);
+      ne += __shfl_xor(ne, o, 64);
+      open += __shfl_xor(open, o, 64);
+    }
+    if ((threadIdx.x & 63) != 0) return;
+  } else if (!live) {
+    return;
+  }
+  atomicAdd(&a[0], v2);
+  atomicAdd(&a[1], nv);
+  atomicAdd(&a[2], e);
+  atomicAdd(&a[3], ne);
+  atomicAdd(&a[4], open);
+}
+
+// One workgroup per sub-region: the 12 features (FP32).
+//   0 log1p(points)   1 log1p(open pieces)   2 RMS transverse speed
+//   3..10 fraction of the points in cells whose occupancy, relative to the mean over
+//         the 16^3 grid, falls in log2 bin b (b = floor(log2(rel)) + 4, clamped to 0..7)
+//   11 log1p(mean edge length / region size)
+__global__ __launch_bounds__(256) void k_feat_final(const int32_t* __restrict__ grid,
+                                                    const double* __restrict__ acc,
+                                                    const int64_t* __restrict__ npts,
+                                                    const RegionGeom* __restrict__ geoms,
+                                                    float* __restrict__ feat) {
+  __shared__ unsigned long long hist[8];
+  const int q = blockIdx.x;
+  const int t = threadIdx.x;
+  if (t < 8) hist[t] = 0;
+  __syncthreads();
+  const int64_t nq = npts[q];
+  if (nq > 0)
+    for (int c = t; c < FEAT_CELLS; c += 256) {
+      const int occ = grid[(int64_t)q * FEAT_CELLS + c];
+      if (occ == 0) continue;
+      const double rel = (double)occ * FEAT_CELLS / (double)nq;
+      int b = (int)floor(log2(rel)) + 4;
+      b = b < 0 ? 0 : (b > 7 ? 7 : b);
+      atomicAdd(&hist[b], (unsigned long long)occ);
+    }
+  __syncthreads();
+  if (t == 0) {
+    float* f = feat + 12 * (int64_t)q;
+    const double* a = acc + (int64_t)FEAT_ACC * q;
+    const double size = 1.4142135623730951 * 0.5 / geoms[q].inv2g;
+    f[0] = (float)log1p((double)nq);
+    f[1] = (float)log1p(a[4]);
+    f[2] = (float)(a[1] > 0.0 ? sqrt(a[0] / a[1]) : 0.0);
+    for (int b = 0; b < 8; ++b) f[3 + b] = nq > 0 ? (float)((double)hist[b] / (double)nq) : 0.f;
+    f[11] = (float)(a[3] > 0.0 ? log1p(a[2] / a[3] / size) : 0.0);
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------
@@ -1341,6 +1550,9 @@ struct semipar_region {
   int32_t n_sub = 0;
   RegionGeom* geoms = nullptr;  // batch: geometry of each sub-region
   int32_t* rid = nullptr;       // batch: sub-region of each point
+  std::vector<int64_t> sub_off;  // batch: first slot of each sub-region (n_sub + 1 entries)
+  int32_t* log_rid = nullptr;    // batch: sub-region of each logged event
+  int32_t step0 = 1;             // slice index of the initial surfaces
   int32_t *fstep = nullptr, *face = nullptr;  // bounded: stop step and exit face per point
   semipar_point_rec* frz = nullptr;           // bounded: record of each stopped point
   int cosmology = 0;
@@ -1512,6 +1724,16 @@ int ensure_log(semipar_region* r, int64_t need) {
     HIPCHK(hipMemcpyAsync(nl, r->log, sizeof(semipar_event) * r->ctrl_h->log_n,
                           hipMemcpyDeviceToDevice, r->stream));
   HIPCHK(hipStreamSynchronize(r->stream));
+  if (r->rid) {
+    int32_t* nr = nullptr;
+    HIPCHK(hipMalloc(&nr, sizeof(int32_t) * nc));
+    if (r->log_rid && r->ctrl_h->log_n > 0)
+      HIPCHK(hipMemcpyAsync(nr, r->log_rid, sizeof(int32_t) * r->ctrl_h->log_n,
+                            hipMemcpyDeviceToDevice, r->stream));
+    HIPCHK(hipStreamSynchronize(r->stream));
+    dfree(r->log_rid);
+    r->log_rid = nr;
+  }
   dfree(r->log);
   r->log = nl;
   r->log_cap = nc;
@@ -1628,7 +1850,7 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
   mark(r, SEMIPAR_K_RESOLVE, 2 * i);
   k_resolve<<<1, RESOLVE_NT, 0, s>>>(r->nxt, r->prv, r->ev, (int)r->cap_evt, (int)r->cap_cand,
                                      r->best, r->used, r->evs, r->log, r->log_cap, r->blkred, nb,
-                                     r->ctrl);
+                                     r->ctrl, r->rid, r->log_rid);
   mark(r, SEMIPAR_K_RESOLVE, 2 * i + 1);
 }
 
@@ -1685,6 +1907,7 @@ void region_destroy(semipar_region* r) {
   dfree(r->frz);
   dfree(r->ctrl);
   dfree(r->log);
+  dfree(r->log_rid);
   if (r->ctrl_h) (void)hipHostFree(r->ctrl_h);
   if (r->ev0) (void)hipEventDestroy(r->ev0);
   if (r->ev1) (void)hipEventDestroy(r->ev1);
@@ -1774,8 +1997,12 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
     }
     std::vector<int32_t> hr((size_t)std::max<int64_t>(total, 1));
     int64_t off = 0;
-    for (int i = 0; i < n_in; ++i)
+    r->sub_off.assign((size_t)n_in + 1, 0);
+    for (int i = 0; i < n_in; ++i) {
+      r->sub_off[i] = off;
       for (int64_t q = 0; q < in[i].n; ++q) hr[off++] = i;
+    }
+    r->sub_off[n_in] = off;
     if (dalloc(&r->geoms, d->n_sub) != hipSuccess || dalloc(&r->rid, cap) != hipSuccess)
       return fail(SEMIPAR_E_OOM);
     if (hipMemcpy(r->geoms, hg.data(), sizeof(RegionGeom) * d->n_sub, hipMemcpyHostToDevice) !=
@@ -1819,6 +2046,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       return fail(SEMIPAR_E_HIP);
     }
     c0.step = rec0.step;
+    r->step0 = rec0.step;
     const uint64_t hcap = next_pow2(2 * (uint64_t)total);
     int64_t* hkey = nullptr;
     int32_t* hval = nullptr;
@@ -2079,3 +2307,185 @@ int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int6
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// internal calls for the scheduler and the cost model
+// ---------------------------------------------------------------------------------
+namespace spi {
+
+int64_t region_points(const semipar_region* r) { return r ? r->n : 0; }
+hipStream_t region_stream(const semipar_region* r) { return r ? r->stream : nullptr; }
+
+void set_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
+int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& cnt) {
+  if (!r || r->n_sub <= 0 || !r->rid) return SEMIPAR_E_ARG;
+  const int ns = r->n_sub;
+  cnt.assign(4 * (size_t)ns, 0);
+  if (r->n == 0) return SEMIPAR_OK;
+  RCCHK(read_ctrl(r));
+  const int s = r->ctrl_h->step;
+  const int nn = (int)r->n;
+  const int nb = blocks(nn);
+  int32_t *blkcnt = nullptr, *blkoff = nullptr, *tot = nullptr, *pst = nullptr;
+  int64_t* dst = nullptr;
+  int rc = SEMIPAR_OK;
+  std::vector<int32_t> hp(4 * (size_t)ns, 0);
+  int32_t th[4] = {0, 0, 0, 0};
+  if (dalloc(&blkcnt, 4 * (size_t)nb) != hipSuccess || dalloc(&blkoff, 4 * (size_t)nb) != hipSuccess ||
+      dalloc(&tot, 4) != hipSuccess || dalloc(&pst, 4 * (size_t)ns) != hipSuccess ||
+      dalloc(&dst, 4 * (size_t)ns) != hipSuccess)
+    rc = SEMIPAR_E_OOM;
+  if (rc == SEMIPAR_OK) {
+    k_emit_count<<<nb, NT, 0, r->stream>>>(nn, r->fstep, r->frz, blkcnt);
+    k_emit_scan<<<1, 1024, 0, r->stream>>>(blkcnt, nb, blkoff, tot);
+    k_emit_sub_start<<<nb, NT, 0, r->stream>>>(nn, r->fstep, r->frz, r->rid, blkoff, pst);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(hp.data(), pst, sizeof(int32_t) * 4 * ns, hipMemcpyDeviceToHost,
+                       r->stream) != hipSuccess ||
+        hipMemcpyAsync(th, tot, sizeof(th), hipMemcpyDeviceToHost, r->stream) != hipSuccess ||
+        hipStreamSynchronize(r->stream) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
+  }
+  if (rc == SEMIPAR_OK) {
+    // per sub-region: stream counts from the prefixes at its first slot and at the
+    // first slot of the next non-empty sub-region (the totals after the last one)
+    std::vector<int64_t> hd(4 * (size_t)ns, 0);
+    int next = -1;
+    for (int q = ns - 1; q >= 0; --q) {
+      const int64_t nq = r->sub_off[q + 1] - r->sub_off[q];
+      if (nq == 0) continue;
+      int64_t base = r->sub_off[q];
+      for (int f = 0; f < 4; ++f) {
+        const int64_t end = next >= 0 ? hp[4 * next + f] : th[f];
+        cnt[4 * q + f] = end - hp[4 * q + f];
+        hd[4 * q + f] = base;
+        base += cnt[4 * q + f];
+      }
+      next = q;
+    }
+    if (hipMemcpyAsync(dst, hd.data(), sizeof(int64_t) * 4 * ns, hipMemcpyHostToDevice,
+                       r->stream) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
+    if (rc == SEMIPAR_OK) {
+      k_emit_sub_write<<<nb, NT, 0, r->stream>>>(r->X, nn, s, r->nxt, r->prv, r->id, r->fstep,
+                                                 r->frz, r->rid, blkoff, pst, dst, tmp);
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(r->stream) != hipSuccess)
+        rc = SEMIPAR_E_HIP;
+    }
+  }
+  dfree(blkcnt);
+  dfree(blkoff);
+  dfree(tot);
+  dfree(pst);
+  dfree(dst);
+  return rc;
+}
+
+int batch_stats(semipar_region* r, std::vector<int32_t>& steps, std::vector<int64_t>& psteps) {
+  if (!r || !r->bounded) return SEMIPAR_E_ARG;
+  const int ns = r->n_sub > 0 ? r->n_sub : 1;  // a lone bounded region is one sub-region
+  steps.assign(ns, 0);
+  psteps.assign(ns, 0);
+  if (r->n == 0) return SEMIPAR_OK;
+  RCCHK(read_ctrl(r));
+  unsigned long long* ps = nullptr;
+  int32_t* sm = nullptr;
+  int rc = SEMIPAR_OK;
+  if (dalloc(&ps, ns) != hipSuccess || dalloc(&sm, ns) != hipSuccess) rc = SEMIPAR_E_OOM;
+  if (rc == SEMIPAR_OK &&
+      (hipMemsetAsync(ps, 0, sizeof(unsigned long long) * ns, r->stream) != hipSuccess ||
+       hipMemsetAsync(sm, 0, sizeof(int32_t) * ns, r->stream) != hipSuccess))
+    rc = SEMIPAR_E_HIP;
+  if (rc == SEMIPAR_OK) {
+    k_sub_stats<<<blocks(r->n), NT, 0, r->stream>>>((int)r->n, r->fstep, r->ctrl_h->step, r->step0,
+                                                    r->rid, ps, sm);
+    std::vector<unsigned long long> hps((size_t)ns);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(hps.data(), ps, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost,
+                       r->stream) != hipSuccess ||
+        hipMemcpyAsync(steps.data(), sm, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, r->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(r->stream) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
+    for (int q = 0; q < ns; ++q) psteps[q] = (int64_t)hps[q];
+  }
+  dfree(ps);
+  dfree(sm);
+  return rc;
+}
+
+int batch_events(semipar_region* r, std::vector<semipar_event>& ev, std::vector<int32_t>& sub) {
+  if (!r || r->n_sub <= 0 || !r->rid) return SEMIPAR_E_ARG;
+  ev.clear();
+  sub.clear();
+  RCCHK(read_ctrl(r));
+  const int64_t total = r->ctrl_h->log_n;
+  if (total == 0) return SEMIPAR_OK;
+  std::vector<semipar_event> all((size_t)total);
+  std::vector<int32_t> rq((size_t)total);
+  HIPCHK(hipMemcpyAsync(all.data(), r->log, sizeof(semipar_event) * total, hipMemcpyDeviceToHost,
+                        r->stream));
+  HIPCHK(hipMemcpyAsync(rq.data(), r->log_rid, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
+                        r->stream));
+  HIPCHK(hipStreamSynchronize(r->stream));
+  std::vector<int64_t> ord((size_t)total);
+  for (int64_t i = 0; i < total; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+    const semipar_event &a = all[x], &b = all[y];
+    if (rq[x] != rq[y]) return rq[x] < rq[y];
+    if (a.step != b.step) return a.step < b.step;
+    if (a.t_star != b.t_star) return a.t_star < b.t_star;
+    if (a.id_a != b.id_a) return a.id_a < b.id_a;
+    return a.id_b < b.id_b;
+  });
+  ev.resize((size_t)total);
+  sub.resize((size_t)total);
+  for (int64_t i = 0; i < total; ++i) {
+    ev[i] = all[ord[i]];
+    sub[i] = rq[ord[i]];
+  }
+  return SEMIPAR_OK;
+}
+
+int batch_features(semipar_region* r, float* feat) {
+  if (!r || r->n_sub <= 0 || !feat) return SEMIPAR_E_ARG;
+  const int ns = r->n_sub;
+  for (int64_t i = 0; i < 12 * (int64_t)ns; ++i) feat[i] = 0.f;
+  if (r->n == 0) return SEMIPAR_OK;
+  RCCHK(read_ctrl(r));
+  double* acc = nullptr;
+  int32_t* grid = nullptr;
+  int64_t* np = nullptr;
+  float* df = nullptr;
+  int rc = SEMIPAR_OK;
+  if (dalloc(&acc, FEAT_ACC * (size_t)ns) != hipSuccess ||
+      dalloc(&grid, (size_t)FEAT_CELLS * ns) != hipSuccess || dalloc(&np, ns) != hipSuccess ||
+      dalloc(&df, 12 * (size_t)ns) != hipSuccess)
+    rc = SEMIPAR_E_OOM;
+  std::vector<int64_t> hn((size_t)ns);
+  for (int q = 0; q < ns; ++q) hn[q] = r->sub_off[q + 1] - r->sub_off[q];
+  if (rc == SEMIPAR_OK &&
+      (hipMemsetAsync(acc, 0, sizeof(double) * FEAT_ACC * ns, r->stream) != hipSuccess ||
+       hipMemsetAsync(grid, 0, sizeof(int32_t) * FEAT_CELLS * (size_t)ns, r->stream) != hipSuccess ||
+       hipMemcpyAsync(np, hn.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, r->stream) !=
+           hipSuccess))
+    rc = SEMIPAR_E_HIP;
+  if (rc == SEMIPAR_OK) {
+    k_feat_points<<<blocks(r->n), NT, 0, r->stream>>>(r->X, (int)r->n, r->ctrl_h->step, r->nxt,
+                                                      r->prv, r->rid, r->geoms, r->P, acc, grid);
+    k_feat_final<<<ns, 256, 0, r->stream>>>(grid, acc, np, r->geoms, df);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(feat, df, sizeof(float) * 12 * ns, hipMemcpyDeviceToHost, r->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(r->stream) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
+  }
+  dfree(acc);
+  dfree(grid);
+  dfree(np);
+  dfree(df);
+  return rc;
+}
+
+}  // namespace spi

@@ -227,22 +227,34 @@ def vv_chains(m, rng, xi=1.0, pts_per_xi=8, jitter=0.15):
     pierced = np.nonzero(succ >= 0)[0]
     offsets = np.zeros((3 * M3, 3))
     offsets[pierced] = rng.uniform(-jitter, jitter, (len(pierced), 3))
-    # chains = cycles of the permutation succ over pierced faces
-    label = -np.ones(3 * M3, dtype=np.int64)
+    # chains = cycles of the permutation succ over pierced faces, each started at its
+    # smallest face id, in increasing order of that id
+    F = len(pierced)
+    cidx = -np.ones(3 * M3, dtype=np.int64)
+    cidx[pierced] = np.arange(F)
+    nxt = cidx[succ[pierced]]
+    lab = np.arange(F)
+    jump = nxt.copy()
+    for _ in range(max(1, int(np.ceil(np.log2(max(F, 2))))) + 1):
+        lab = np.minimum(lab, lab[jump])
+        jump = jump[jump]
+    # distance from the cycle start: break each cycle before its start, rank the lists
+    tail = nxt == lab
+    dist = np.where(tail, 0, 1)
+    jump = np.where(tail, np.arange(F), nxt)
+    for _ in range(max(1, int(np.ceil(np.log2(max(F, 2))))) + 1):
+        dist = dist + np.where(jump == np.arange(F), 0, dist[jump])
+        jump = jump[jump]
+    length = np.bincount(lab, minlength=F)
+    rank = length[lab] - 1 - dist
+    order = np.lexsort((rank, lab))
+    starts = np.nonzero(rank[order] == 0)[0]
+    ends = np.append(starts[1:], F)
     chains = []
     step = 1.0 / pts_per_xi
     axis_of = lambda f: f // M3
-    for f0 in pierced:
-        if label[f0] >= 0:
-            continue
-        cyc = [f0]
-        label[f0] = len(chains)
-        f = succ[f0]
-        while f != f0:
-            label[f] = len(chains)
-            cyc.append(f)
-            f = succ[f]
-        cyc = np.asarray(cyc)
+    for a0, a1 in zip(starts, ends):
+        cyc = pierced[order[a0:a1]]
         ax = axis_of(cyc)
         site = cyc % M3
         fi_, rest = np.divmod(site, m * m)
@@ -452,24 +464,63 @@ def lognormal_regions(n_regions=512, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2
     return n
 
 
-def region_batch(n_targets, size=4.0, seed=0, t_mid=8.0, slots=8, cosmology=MATTER):
+def region_batch(n_targets, size=4.0, seed=0, t_mid=8.0, slots=8, cosmology=MATTER,
+                 pts_per_xi=None, workers=0):
     """Independent first-layer regions on the slots of a periodic box (slots^3 slots,
     slot spacing >= 2 g + 1, so regions never overlap). Region r has point target
-    n_targets[r] and seed seed + r; its ids are offset to be unique in the batch.
+    n_targets[r], seed seed + r and pts_per_xi[r] points per correlation length
+    (default 8); its ids are offset to be unique in the batch. workers > 1 generates
+    the regions in that many processes (same result).
     Returns (parts, box) with parts = [(recs, geom), ...]."""
     g = size / np.sqrt(2.0)
+    nr = len(n_targets)
+    assert nr <= slots ** 3
     box = float(2.0 ** np.ceil(np.log2(slots * (2 * g + 1.0))))
     spacing = box / slots
-    parts = []
-    id_off = 0
+    ppx = [8] * nr if pts_per_xi is None else [int(v) for v in pts_per_xi]
+    jobs = []
     for r, nt in enumerate(n_targets):
         i, j, k = r // (slots * slots), (r // slots) % slots, r % slots
         centre = (spacing * (i + 0.5), spacing * (j + 0.5), spacing * (k + 0.5))
-        net = region_network(int(nt), size, seed + r, t_mid, centre, cosmology=cosmology, box=box)
-        recs = net["recs"].copy()
+        jobs.append((int(nt), size, seed + r, t_mid, centre, ppx[r], cosmology, box))
+    if workers and workers > 1 and nr > 1 and not _gpu_in_use():
+        # forked copies of this process (no GPU state yet), pure NumPy work
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            nets = pool.map(_region_job, jobs, chunksize=1)
+    else:
+        nets = [_region_job(j) for j in jobs]
+    parts = []
+    id_off = 0
+    for recs, geom in nets:
         recs["id"] += id_off
         for f in ("next_id", "prev_id"):
             recs[f] = np.where(recs[f] >= 0, recs[f] + id_off, -1)
-        parts.append((recs, net["geom"]))
+        parts.append((recs, geom))
         id_off += len(recs)
     return parts, box
+
+
+def _gpu_in_use():
+    import sys
+    torch = sys.modules.get("torch")
+    return bool(torch is not None and torch.cuda.is_initialized())
+
+
+def _region_job(job):
+    nt, size, seed, t_mid, centre, ppx, cosmology, box = job
+    net = region_network(nt, size, seed, t_mid, centre, pts_per_xi=ppx, cosmology=cosmology,
+                         box=box)
+    return net["recs"].copy(), net["geom"]
+
+
+def mixed_regions(n_regions=256, median=2000, sigma=1.0, cap=50000, p_empty=0.1, seed=0,
+                  ppx_choices=(4, 6, 8, 12, 16)):
+    """Point targets and resolutions of a workload whose region cost is not a function
+    of the point count: targets as in lognormal_regions, and each region's points per
+    correlation length drawn uniformly from ppx_choices (seeded), which sets its sigma
+    spacing and hence the number of lattice steps it needs."""
+    n = lognormal_regions(n_regions, median, sigma, cap, p_empty, seed)
+    rng = np.random.default_rng(seed + 7919)
+    ppx = rng.choice(np.asarray(ppx_choices), size=n_regions)
+    return n, ppx

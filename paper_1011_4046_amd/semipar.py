@@ -81,10 +81,43 @@ class EvolveStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Tiling(ctypes.Structure):
+    _fields_ = [("n_regions", ctypes.c_int32), ("cosmology", ctypes.c_int32),
+                ("box", ctypes.c_double), ("surfaces", ctypes.c_void_p),
+                ("geoms", ctypes.c_void_p), ("n_pred", ctypes.c_void_p),
+                ("succ_off", ctypes.c_void_p), ("succ", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
+
+
+class SchedParams(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("out_mem", ctypes.c_int32),
+                ("batch_points", ctypes.c_int64), ("cost", ctypes.c_void_p),
+                ("evolve", EvolveParams), ("out", ctypes.c_void_p), ("out_off", ctypes.c_void_p),
+                ("events", ctypes.c_void_p), ("events_cap", ctypes.c_int64),
+                ("events_off", ctypes.c_void_p), ("region_steps", ctypes.c_void_p),
+                ("region_point_steps", ctypes.c_void_p), ("region_batch", ctypes.c_void_p),
+                ("region_ms", ctypes.c_void_p)]
+
+
+class SchedStats(ctypes.Structure):
+    _fields_ = [("regions", ctypes.c_int64), ("empty_regions", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("point_steps", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("events", ctypes.c_int64),
+                ("makespan_ms", ctypes.c_double), ("evolve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+SCHED_PLAIN, SCHED_BATCHED = 0, 1
+MLP_IN, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
+
 # exported symbols declared in include/semipar.h
 SYMBOLS = ["region_init_from_surfaces", "region_evolve", "region_emit_final_surfaces",
            "region_events", "region_destroy", "semipar_strerror", "semipar_version",
-           "semipar_last_error"]
+           "semipar_last_error", "schedule_regions", "semipar_region_features",
+           "semipar_mlp_forward", "semipar_mlp_loss_grad", "semipar_mlp_adam_step",
+           "semipar_mlp_train", "semipar_mlp_norm"]
 
 _lib = None
 
@@ -115,6 +148,23 @@ def lib():
         L.semipar_version.restype = ctypes.c_char_p
         L.semipar_last_error.argtypes = []
         L.semipar_last_error.restype = ctypes.c_char_p
+        L.schedule_regions.argtypes = [ctypes.POINTER(Tiling), ctypes.POINTER(SchedParams),
+                                       ctypes.POINTER(SchedStats)]
+        L.schedule_regions.restype = ctypes.c_int
+        L.semipar_region_features.argtypes = [ctypes.POINTER(Tiling), P]
+        L.semipar_region_features.restype = ctypes.c_int
+        L.semipar_mlp_forward.argtypes = [P, P, P, ctypes.c_int64, P, P]
+        L.semipar_mlp_forward.restype = ctypes.c_int
+        L.semipar_mlp_loss_grad.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P]
+        L.semipar_mlp_loss_grad.restype = ctypes.c_int
+        L.semipar_mlp_adam_step.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
+        L.semipar_mlp_adam_step.restype = ctypes.c_int
+        L.semipar_mlp_train.argtypes = [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int64, ctypes.c_float, P, P]
+        L.semipar_mlp_train.restype = ctypes.c_int
+        L.semipar_mlp_norm.argtypes = [P, ctypes.c_int64, P]
+        L.semipar_mlp_norm.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -259,3 +309,209 @@ def version():
 
 def strerror(code):
     return lib().semipar_strerror(int(code)).decode()
+
+
+# ---- many regions ----------------------------------------------------------------
+
+class RegionSet:
+    """Regions of a tiling, packed for schedule_regions / region_features.
+
+    recs: all regions' records concatenated (numpy REC_DTYPE on the host, or a torch
+    uint8 CUDA tensor of 160-byte records); counts[r]: records of region r;
+    geoms[r]: (origin[4], inv2g, idx[4]) as produced by inputs.region_geometry.
+    n_pred / succ: optional dependency lists (succ[r] = list of successors of r).
+    """
+
+    def __init__(self, recs, counts, geoms, box, cosmology, n_pred=None, succ=None):
+        self.counts = np.asarray(counts, dtype=np.int64)
+        nr = len(self.counts)
+        self.box, self.cosmology = float(box), int(cosmology)
+        if isinstance(recs, np.ndarray):
+            self.recs = np.ascontiguousarray(recs, dtype=REC_DTYPE)
+            base, mem = self.recs.ctypes.data, MEM_HOST
+        else:
+            assert recs.is_cuda and recs.numel() % REC_DTYPE.itemsize == 0
+            self.recs = recs
+            base, mem = recs.data_ptr(), MEM_DEVICE
+        assert int(self.counts.sum()) * REC_DTYPE.itemsize == (
+            self.recs.nbytes if mem == MEM_HOST else recs.numel())
+        self.mem = mem
+        self.surfs = (Surface * max(nr, 1))()
+        off = np.concatenate([[0], np.cumsum(self.counts)])
+        self.offsets = off
+        for r in range(nr):
+            n = int(self.counts[r])
+            self.surfs[r] = Surface(base + int(off[r]) * REC_DTYPE.itemsize if n else None, n, -1, mem)
+        self.geoms = (RegionGeom * max(nr, 1))()
+        for r in range(nr):
+            self.geoms[r] = _geom_struct(geoms[r])
+        self.n_regions = nr
+        self._dag = None
+        if n_pred is not None:
+            npred = np.ascontiguousarray(n_pred, dtype=np.int32)
+            so = np.zeros(nr + 1, dtype=np.int32)
+            flat = []
+            for r in range(nr):
+                flat.extend(int(x) for x in succ[r])
+                so[r + 1] = len(flat)
+            sl = np.ascontiguousarray(flat if flat else [0], dtype=np.int32)
+            self._dag = (npred, so, sl)
+
+    def tiling(self, stream=None):
+        t = Tiling()
+        t.n_regions = self.n_regions
+        t.cosmology = self.cosmology
+        t.box = self.box
+        t.surfaces = ctypes.cast(self.surfs, ctypes.c_void_p)
+        t.geoms = ctypes.cast(self.geoms, ctypes.c_void_p)
+        if self._dag is not None:
+            t.n_pred = self._dag[0].ctypes.data
+            t.succ_off = self._dag[1].ctypes.data
+            t.succ = self._dag[2].ctypes.data
+        if stream is None and self.mem == MEM_DEVICE:
+            stream = _current_stream()
+        t.stream = stream
+        return t
+
+    @classmethod
+    def from_parts(cls, parts, box, cosmology, device=False, **kw):
+        """parts = [(recs, geom)]; device=True uploads the records to the current GPU."""
+        counts = [len(p[0]) for p in parts]
+        recs = np.concatenate([p[0] for p in parts]) if parts else np.zeros(0, REC_DTYPE)
+        if device:
+            import torch
+            recs = torch.from_numpy(recs.view(np.uint8).copy()).cuda()
+        return cls(recs, counts, [p[1] for p in parts], box, cosmology, **kw)
+
+
+def region_features(rs, stream=None):
+    """12 cost-model features per region (numpy float32, n_regions x 12), on the GPU."""
+    feat = np.zeros((max(rs.n_regions, 1), MLP_IN), dtype=np.float32)
+    t = rs.tiling(stream)
+    _check(lib().semipar_region_features(ctypes.byref(t), feat.ctypes.data), "region_features")
+    return feat[:rs.n_regions]
+
+
+def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="host",
+                     events=True, stream=None, max_steps=10 ** 7, t_end=float("inf"),
+                     screen=SCREEN_F64, intercommute=True, cell_size=0.0, steps_per_sync=0,
+                     use_graph=False, cand_per_point=0.0, events_per_point=0.0,
+                     screen_split=0):
+    """Run every region of rs; returns a dict with the stats, per-region logs, output
+    records (out = "host": numpy; "device": torch uint8 CUDA tensor; None: not
+    written), their offsets (4 per region + 1) and the events with offsets."""
+    L = lib()
+    nr = rs.n_regions
+    p = SchedParams()
+    p.policy = int(policy)
+    p.batch_points = int(batch_points)
+    cost_arr = None
+    if cost is not None:
+        cost_arr = np.ascontiguousarray(cost, dtype=np.float32)
+        assert len(cost_arr) == nr
+        p.cost = cost_arr.ctypes.data
+    p.evolve = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
+                            float(cell_size), int(steps_per_sync), int(bool(use_graph)),
+                            float(cand_per_point), float(events_per_point), -1, int(screen_split))
+    total = int(rs.counts.sum())
+    out_off = np.zeros(4 * nr + 1, dtype=np.int64)
+    res = {}
+    if out == "host":
+        o = np.zeros(total, dtype=REC_DTYPE)
+        p.out, p.out_mem = (o.ctypes.data if total else None), MEM_HOST
+        res["out"] = o
+    elif out == "device":
+        import torch
+        o = torch.empty(max(total, 1) * REC_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        p.out, p.out_mem = o.data_ptr(), MEM_DEVICE
+        res["out"] = o
+    p.out_off = out_off.ctypes.data
+    ev_off = np.zeros(nr + 1, dtype=np.int64)
+    ev_cap = max(2 * total, 4096)
+    ev = np.zeros(ev_cap, dtype=EVENT_DTYPE) if events else None
+    if events:
+        p.events, p.events_cap, p.events_off = ev.ctypes.data, ev_cap, ev_off.ctypes.data
+    steps = np.zeros(max(nr, 1), dtype=np.int32)
+    psteps = np.zeros(max(nr, 1), dtype=np.int64)
+    batch = np.zeros(max(nr, 1), dtype=np.int32)
+    ms = np.zeros(max(nr, 1), dtype=np.float64)
+    p.region_steps, p.region_point_steps = steps.ctypes.data, psteps.ctypes.data
+    p.region_batch, p.region_ms = batch.ctypes.data, ms.ctypes.data
+    st = SchedStats()
+    t = rs.tiling(stream)
+    _check(L.schedule_regions(ctypes.byref(t), ctypes.byref(p), ctypes.byref(st)),
+           "schedule_regions")
+    res.update(stats=st.as_dict(), out_off=out_off, region_steps=steps[:nr],
+               region_point_steps=psteps[:nr], region_batch=batch[:nr], region_ms=ms[:nr])
+    if events:
+        if st.events > ev_cap:
+            raise SemiparError(-5, f"schedule_regions: {st.events} events > buffer {ev_cap}")
+        res["events"], res["events_off"] = ev[:st.events], ev_off
+    return res
+
+
+# ---- cost model --------------------------------------------------------------------
+
+class CostModel:
+    """The 12 -> 64 -> 64 -> 1 ReLU cost model, trained and run by libsemipar's FP32
+    kernels on the current GPU. params: numpy float32 (MLP_PARAMS) initial values."""
+
+    def __init__(self, params, norm=None):
+        import torch
+        self.torch = torch
+        self.params = torch.from_numpy(np.ascontiguousarray(params, np.float32)).cuda()
+        assert self.params.numel() == MLP_PARAMS
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.norm = None if norm is None else torch.from_numpy(
+            np.ascontiguousarray(norm, np.float32)).cuda()
+        self.step = 0
+
+    def _dev(self, a):
+        return self.torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+    def _np(self, p):
+        return p.data_ptr() if p is not None else None
+
+    def set_norm_from(self, x):
+        x = np.ascontiguousarray(x, np.float32)
+        norm = np.zeros(2 * MLP_IN, np.float32)
+        _check(lib().semipar_mlp_norm(x.ctypes.data, len(x), norm.ctypes.data), "mlp_norm")
+        self.norm = self._dev(norm)
+        return norm
+
+    def forward(self, x):
+        xd = self._dev(x)
+        y = self.torch.empty(len(x), dtype=self.torch.float32, device="cuda")
+        _check(lib().semipar_mlp_forward(self._np(self.params), self._np(self.norm), self._np(xd),
+                                         len(x), self._np(y), _current_stream()), "mlp_forward")
+        return y.cpu().numpy()
+
+    def loss_grad(self, x, target):
+        xd, td = self._dev(x), self._dev(target)
+        g = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device="cuda")
+        l = self.torch.empty(1, dtype=self.torch.float32, device="cuda")
+        _check(lib().semipar_mlp_loss_grad(self._np(self.params), self._np(self.norm), self._np(xd),
+                                           self._np(td), len(x), self._np(g), self._np(l),
+                                           _current_stream()), "mlp_loss_grad")
+        return float(l.cpu()[0]), g.cpu().numpy()
+
+    def adam_step(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        gd = self._dev(grad)
+        self.step += 1
+        _check(lib().semipar_mlp_adam_step(self._np(self.params), self._np(self.m), self._np(self.v),
+                                           self._np(gd), self.step, lr, beta1, beta2, eps,
+                                           _current_stream()), "mlp_adam_step")
+
+    def train(self, x, target, iters=2000, lr=1e-3):
+        xd, td = self._dev(x), self._dev(target)
+        loss = np.zeros(iters + 1, np.float32)
+        _check(lib().semipar_mlp_train(self._np(self.params), self._np(self.m), self._np(self.v),
+                                       self._np(self.norm), self._np(xd), self._np(td), len(x),
+                                       int(iters), self.step, float(lr), loss.ctypes.data,
+                                       _current_stream()), "mlp_train")
+        self.step += iters
+        return loss
+
+    def get_params(self):
+        return self.params.cpu().numpy()

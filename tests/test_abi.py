@@ -3,6 +3,7 @@ argument errors are reported without touching a GPU."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -34,12 +35,106 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
-def test_record_layouts_match_header():
+LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "semipar.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+#define Z(T) printf(#T " %zu\n", sizeof(T));
+int main(void) {
+  Z(semipar_point_rec) Z(semipar_event) Z(semipar_surface) Z(semipar_region_geom)
+  Z(semipar_region_desc) Z(semipar_evolve_params) Z(semipar_evolve_stats)
+  Z(semipar_tiling) Z(semipar_sched_params) Z(semipar_sched_stats)
+  F(semipar_region_desc, stream) F(semipar_region_desc, inv2g) F(semipar_region_desc, sub)
+  F(semipar_evolve_params, screen_split) F(semipar_evolve_stats, timed_kernel_launches)
+  F(semipar_tiling, surfaces) F(semipar_tiling, stream)
+  F(semipar_sched_params, cost) F(semipar_sched_params, evolve) F(semipar_sched_params, out)
+  F(semipar_sched_params, events_cap) F(semipar_sched_params, region_ms)
+  F(semipar_sched_stats, makespan_ms)
+  return 0;
+}
+"""
+
+
+def c_layout(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {k: int(v) for k, v in (line.split() for line in out.splitlines())}
+
+
+def test_record_layouts_match_header(tmp_path):
     from paper_1011_4046_amd.inputs import EVENT_DTYPE, REC_DTYPE
-    assert REC_DTYPE.itemsize == 160 and EVENT_DTYPE.itemsize == 56
-    assert ctypes.sizeof(S.EvolveParams) == 64
-    assert ctypes.sizeof(S.RegionDesc) == 32 + 16 + 32 + 8 + 16
-    assert ctypes.sizeof(S.RegionGeom) == 56
+    c = c_layout(tmp_path)
+    assert c["semipar_point_rec"] == REC_DTYPE.itemsize == 160
+    assert c["semipar_event"] == EVENT_DTYPE.itemsize == 56
+    pairs = {"semipar_surface": S.Surface, "semipar_region_geom": S.RegionGeom,
+             "semipar_region_desc": S.RegionDesc, "semipar_evolve_params": S.EvolveParams,
+             "semipar_evolve_stats": S.EvolveStats, "semipar_tiling": S.Tiling,
+             "semipar_sched_params": S.SchedParams, "semipar_sched_stats": S.SchedStats}
+    for cname, py in pairs.items():
+        assert c[cname] == ctypes.sizeof(py), cname
+    fields = {"semipar_region_desc": S.RegionDesc, "semipar_evolve_params": S.EvolveParams,
+              "semipar_evolve_stats": S.EvolveStats, "semipar_tiling": S.Tiling,
+              "semipar_sched_params": S.SchedParams, "semipar_sched_stats": S.SchedStats}
+    for key, off in c.items():
+        if "." in key:
+            cname, f = key.split(".")
+            assert getattr(fields[cname], f).offset == off, key
+    for n, name in ((S.MLP_IN, "IN"), (S.MLP_HIDDEN, "HIDDEN"), (S.MLP_PARAMS, "PARAMS")):
+        assert re.search(rf"#define SEMIPAR_MLP_{name} {n}\b", open(HEADER).read())
+    assert S.MLP_PARAMS == 64 * 12 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def test_scheduler_without_gpu_work():
+    """Empty regions are only noted (no launch), and predecessor counts that leave a
+    region never ready are an argument error."""
+    import numpy as np
+    from paper_1011_4046_amd import inputs as I
+    geom, _ = I.region_geometry(4.0, 8.0)
+    empty = np.zeros(0, dtype=I.REC_DTYPE)
+    rs = S.RegionSet(empty, [0, 0, 0], [geom] * 3, 16.0, I.MATTER,
+                     n_pred=[0, 1, 1], succ=[[1, 2], [], []])
+    res = S.schedule_regions(rs, policy=S.SCHED_BATCHED)
+    st = res["stats"]
+    assert st["regions"] == 3 and st["empty_regions"] == 3 and st["batches"] == 0
+    assert list(res["region_batch"]) == [-1, -1, -1]
+    assert list(res["out_off"]) == [0] * 13
+    cyc = S.RegionSet(empty, [0, 0], [geom] * 2, 16.0, I.MATTER, n_pred=[1, 1], succ=[[1], [0]])
+    with pytest.raises(S.SemiparError):
+        S.schedule_regions(cyc)
+    L = S.lib()
+    t = rs.tiling()
+    p = S.SchedParams()
+    p.policy = 7
+    assert L.schedule_regions(ctypes.byref(t), ctypes.byref(p), None) == -1
+    assert L.schedule_regions(None, ctypes.byref(p), None) == -1
+    t.box = -1.0
+    p.policy = 0
+    assert L.schedule_regions(ctypes.byref(t), ctypes.byref(p), None) == -1
+
+
+def test_mlp_host_normalisation_and_argument_errors():
+    import numpy as np
+    rng = np.random.default_rng(0)
+    x = rng.normal(3.0, 2.0, (500, 12)).astype(np.float32)
+    x[:, 5] = 1.0  # constant feature: scale 1
+    norm = np.zeros(24, np.float32)
+    L = S.lib()
+    assert L.semipar_mlp_norm(x.ctypes.data, len(x), norm.ctypes.data) == 0
+    xd = x.astype(np.float64)
+    assert np.allclose(norm[:12], xd.mean(0), rtol=1e-6)
+    sd = xd.std(0)
+    expect = np.where(sd > 1e-6, 1.0 / np.where(sd > 0, sd, 1), 1.0)
+    assert np.allclose(norm[12:], expect, rtol=1e-5)
+    assert L.semipar_mlp_norm(None, 3, norm.ctypes.data) == -1
+    assert L.semipar_mlp_forward(None, None, None, 1, None, None) == -1
+    assert L.semipar_mlp_loss_grad(None, None, None, None, 0, None, None, None) == -1
+    assert L.semipar_mlp_adam_step(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.semipar_mlp_train(None, None, None, None, None, None, 0, 1, 0, 1e-3, None, None) == -1
 
 
 def test_argument_errors_without_gpu():

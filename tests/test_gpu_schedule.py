@@ -1,0 +1,261 @@
+"""GPU tests of the many-region path: schedule_regions against the oracle run region by
+region, the cost-model features and FP32 kernels against the FP64 oracle, and the
+gain of the trained cost model over the point-count heuristic.
+
+Bars: per region, records and events identical to the oracle's run of that region
+alone (bitwise), under every policy and packing; features within FP32 rounding of the
+FP64 oracle (1e-5 relative); forward within 1e-5, gradient within 1e-3 (norm-wise,
+FP32 against FP64) and the Adam update within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import costmodel as C
+from paper_1011_4046_amd import inputs as I
+from test_gpu_parity import assert_same_events, assert_same_records, check_faces, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1011_4046_amd import semipar
+    semipar.lib()
+    return semipar
+
+
+_oracle_cache = {}
+
+
+def oracle_regions(parts, box, key):
+    """Each region run alone by the oracle: (records, events, stats, steps advanced)."""
+    if key in _oracle_cache:
+        return _oracle_cache[key]
+    res = []
+    for recs, geom in parts:
+        if len(recs) == 0:
+            res.append(None)
+            continue
+        net = dict(recs=recs, box=box, cosmology=I.MATTER, geom=geom)
+        o, oe, ost = O.run(net, 100000)
+        res.append((o, oe, ost, int(o["step"].max()) - int(recs["step"][0])))
+    _oracle_cache[key] = res
+    return res
+
+
+def check_against_oracle(res, parts, orc):
+    out, off = res["out"], res["out_off"]
+    ev, eoff = res["events"], res["events_off"]
+    total_ps = 0
+    for r, (recs, geom) in enumerate(parts):
+        mine = out[off[4 * r]:off[4 * r + 4]]
+        mine_ev = ev[eoff[r]:eoff[r + 1]]
+        if orc[r] is None:
+            assert len(mine) == 0 and len(mine_ev) == 0
+            assert res["region_batch"][r] == -1
+            continue
+        o, oe, ost, steps = orc[r]
+        assert_same_records(mine, o)
+        assert_same_events(mine_ev, oe)
+        check_faces([out[off[4 * r + f]:off[4 * r + f + 1]] for f in range(4)])
+        assert res["region_point_steps"][r] == ost["point_steps"]
+        assert res["region_steps"][r] == steps
+        total_ps += ost["point_steps"]
+    assert res["stats"]["point_steps"] == total_ps
+
+
+SIZES = [0, 300, 5000, 1200, 0, 20000, 800, 2500, 40, 9000, 150, 3000]
+
+
+@pytest.mark.parametrize("case", ["plain", "batched-heuristic", "batched-cost", "one-batch-f32"])
+def test_schedule_policies_equal_oracle_region_by_region(S, case):
+    say(f"case: schedule_regions {case}, sizes {SIZES}, seed 200")
+    parts, box = I.region_batch(SIZES, seed=200)
+    orc = oracle_regions(parts, box, "sizes200")
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    if case == "plain":
+        res = S.schedule_regions(rs, S.SCHED_PLAIN, steps_per_sync=1)
+        assert res["stats"]["batches"] == 10
+    elif case == "batched-heuristic":
+        res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=6000, use_graph=True,
+                                 screen=S.SCREEN_F32)
+        assert res["stats"]["batches"] >= 4
+        # point-count order: the batch index never decreases as regions get smaller
+        nz = [r for r in range(len(SIZES)) if len(parts[r][0])]
+        order = sorted(nz, key=lambda r: -len(parts[r][0]))
+        b = [res["region_batch"][r] for r in order]
+        assert b == sorted(b)
+    elif case == "batched-cost":
+        cost = np.random.default_rng(5).permutation(len(SIZES)).astype(np.float32)
+        res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=8000, cost=cost)
+        nz = [r for r in range(len(SIZES)) if len(parts[r][0])]
+        order = sorted(nz, key=lambda r: -cost[r])
+        b = [res["region_batch"][r] for r in order]
+        assert b == sorted(b)
+    else:
+        res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=0, use_graph=True,
+                                 screen=S.SCREEN_F32, steps_per_sync=16)
+        assert res["stats"]["batches"] == 1
+    assert res["stats"]["empty_regions"] == 2 and res["stats"]["regions"] == len(SIZES)
+    check_against_oracle(res, parts, orc)
+
+
+def test_schedule_device_resident_io_and_dependencies(S):
+    """Device-resident input and output, and a dependency order: a region starts only
+    in a later wave than all its predecessors; results unchanged."""
+    import torch
+    say("case: schedule_regions device I/O with a dependency DAG, sizes[:8], seed 200")
+    sizes = SIZES[:8]
+    parts, box = I.region_batch(sizes, seed=200)
+    orc = oracle_regions(parts, box, "sizes200")[:8]
+    succ = [[1, 2], [3], [3, 4], [5], [6], [7], [7], []]
+    npred = [0] * 8
+    for r in range(8):
+        for q in succ[r]:
+            npred[q] += 1
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER, device=True, n_pred=npred, succ=succ)
+    res = S.schedule_regions(rs, S.SCHED_BATCHED, out="device", use_graph=True,
+                             screen=S.SCREEN_F32)
+    torch.cuda.synchronize()
+    res["out"] = res["out"].cpu().numpy().view(I.REC_DTYPE)[:int(rs.counts.sum())]
+    check_against_oracle(res, parts, orc)
+    b = res["region_batch"]
+    for r in range(8):
+        for q in succ[r]:
+            if b[r] >= 0 and b[q] >= 0:
+                assert b[q] > b[r], (r, q)
+
+
+def test_region_features_match_oracle(S):
+    say("case: cost-model features of 12 regions (seed 200) and two strings")
+    parts, box = I.region_batch(SIZES, seed=200)
+    chain, delta = I.straight_string(200, 16.0, v=0.6)
+    s1 = I.make_network([chain], 16.0, delta, 8.0, I.MATTER)
+    geom, _ = I.region_geometry(4.0, 8.0, (0.3, 0.2, 0.1))
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    f = S.region_features(rs)
+    for r, (recs, geom_r) in enumerate(parts):
+        want = C.features(recs, geom_r, box)
+        assert np.allclose(f[r], want, rtol=1e-5, atol=1e-6), (r, f[r], want)
+    rs1 = S.RegionSet.from_parts([(s1["recs"], geom)], 16.0, I.MATTER)
+    f1 = S.region_features(rs1)[0]
+    assert np.allclose(f1, C.features(s1["recs"], geom, 16.0), rtol=1e-5, atol=1e-6)
+    assert f1[2] == pytest.approx(0.6, rel=1e-5)
+
+
+def _mlp_case(seed, n=700):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0.0, 0.25, C.NP).astype(np.float32)
+    x = rng.normal(1.0, 2.0, (n, 12)).astype(np.float32)
+    t = (0.5 * x[:, 0] - 0.2 * x[:, 4] + 0.1 * x[:, 7] ** 2).astype(np.float32)
+    return p, x, t
+
+
+def test_mlp_forward_and_gradient_against_fp64_oracle(S):
+    say("case: cost MLP forward / gradient / Adam vs FP64 oracle, n = 700 and 33")
+    for n in (700, 33):
+        p, x, t = _mlp_case(1, n)
+        m = S.CostModel(p)
+        norm = m.set_norm_from(x)
+        assert np.allclose(norm, C.norm_of(x), rtol=1e-5)
+        y = m.forward(x)
+        yo, _ = C.forward(p, x, norm)
+        assert np.max(np.abs(y - yo)) <= 1e-5 * max(1.0, np.max(np.abs(yo)))
+        l, g = m.loss_grad(x, t)
+        lo, go = C.loss_grad(p, x, t, norm)
+        assert l == pytest.approx(lo, rel=1e-5)
+        assert np.linalg.norm(g - go) <= 1e-3 * np.linalg.norm(go)
+        assert np.max(np.abs(g - go)) <= 1e-3 * np.max(np.abs(go))
+        # the FP64 gradient is itself pinned to central differences; spot-check here too
+        for i in (0, 800, 4930, 5056):
+            e = np.zeros(C.NP)
+            e[i] = 1e-6
+            fd = (C.loss(p + e, x, t, norm) - C.loss(p - e, x, t, norm)) / 2e-6
+            assert abs(g[i] - fd) <= 1e-3 * max(abs(fd), 1e-3 * np.max(np.abs(go)))
+
+
+def test_mlp_adam_and_training_against_fp64_oracle(S):
+    say("case: cost MLP Adam step and 200 training steps vs FP64 oracle")
+    p, x, t = _mlp_case(2)
+    m = S.CostModel(p)
+    norm = m.set_norm_from(x)
+    _, g = m.loss_grad(x, t)
+    # two steps: the second uses non-zero moments
+    po, mo, vo = p.astype(np.float64), np.zeros(C.NP), np.zeros(C.NP)
+    for k in (1, 2):
+        m.adam_step(g, lr=1e-3)
+        po, mo, vo = C.adam_step(po, mo, vo, g.astype(np.float64), k, lr=1e-3)
+    got = m.get_params()
+    assert np.max(np.abs(got - po)) <= 1e-6 * max(1.0, np.max(np.abs(po)))
+    m2 = S.CostModel(p, norm)
+    losses = m2.train(x, t, iters=200, lr=1e-3)
+    _, lo = C.train(p, x, t, 200, lr=1e-3, norm=norm)
+    assert np.allclose(losses, lo, rtol=2e-3, atol=1e-6)
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def _work(steps, counts, batch):
+    """Point-steps the batched kernels visit: every point of a batch, every step of the
+    batch (the batch runs as long as its longest region)."""
+    tot = 0
+    for b in np.unique(batch[batch >= 0]):
+        sel = batch == b
+        tot += int(steps[sel].max()) * int(counts[sel].sum())
+    return tot
+
+
+def test_learned_packing_beats_point_count_heuristic(S):
+    """Regions of random resolution: the point count says little about how many steps a
+    region needs, the features do. Trained on one workload's logged steps, the model
+    packs another workload with less wasted work than the point-count heuristic, and
+    the results are identical under both packings."""
+    say("case: learned packing, mixed workloads seeds 11 (train) and 12 (test), 160 regions")
+    runs = {}
+    for seed in (11, 12):
+        n, ppx = I.mixed_regions(160, median=800, sigma=1.0, cap=20000, p_empty=0.1, seed=seed)
+        parts, box = I.region_batch(n, seed=1000 * seed, pts_per_xi=ppx)
+        rs = S.RegionSet.from_parts(parts, box, I.MATTER, device=True)
+        runs[seed] = (rs, parts, box, S.region_features(rs))
+    rs, parts, box, feat = runs[11]
+    log = S.schedule_regions(rs, S.SCHED_BATCHED, use_graph=True, screen=S.SCREEN_F32,
+                             out=None, events=False)
+    live = rs.counts > 0
+    target = np.log(np.maximum(log["region_steps"][live], 1)).astype(np.float32)
+    p0 = np.random.default_rng(0).normal(0.0, 0.1, C.NP).astype(np.float32)
+    model = S.CostModel(p0)
+    model.set_norm_from(feat[live])
+    losses = model.train(feat[live], target, iters=2000, lr=3e-3)
+    say(f"  training loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.25 * losses[0]
+    rs, parts, box, feat = runs[12]
+    pred = np.exp(model.forward(feat)).astype(np.float32)
+    budget = int(rs.counts.sum() // 6)
+    out = {}
+    for name, cost in (("heuristic", None), ("learned", pred)):
+        out[name] = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=budget, cost=cost,
+                                       use_graph=True, screen=S.SCREEN_F32)
+    steps = out["heuristic"]["region_steps"]
+    assert np.array_equal(steps, out["learned"]["region_steps"])
+    live = rs.counts > 0
+    corr = np.corrcoef(np.log(pred[live]), np.log(np.maximum(steps[live], 1)))[0, 1]
+    corr_n = np.corrcoef(np.log(rs.counts[live]), np.log(np.maximum(steps[live], 1)))[0, 1]
+    w = {k: _work(steps, rs.counts, v["region_batch"]) for k, v in out.items()}
+    ms = {k: v["stats"]["makespan_ms"] for k, v in out.items()}
+    say(f"  corr(pred, steps) {corr:.3f}  corr(log n, steps) {corr_n:.3f}  "
+        f"visited point-steps {w}  makespan ms {ms}")
+    assert corr > 0.9
+    assert w["learned"] < 0.9 * w["heuristic"]
+    # identical results under both packings
+    for r in range(rs.n_regions):
+        a = out["heuristic"]
+        b = out["learned"]
+        ra = a["out"][a["out_off"][4 * r]:a["out_off"][4 * r + 4]]
+        rb = b["out"][b["out_off"][4 * r]:b["out_off"][4 * r + 4]]
+        assert ra.tobytes() == rb.tobytes()
+        ea = a["events"][a["events_off"][r]:a["events_off"][r + 1]]
+        eb = b["events"][b["events_off"][r]:b["events_off"][r + 1]]
+        assert ea.tobytes() == eb.tobytes()
