@@ -1,12 +1,27 @@
 #!/usr/bin/env python3
-"""Benchmark: string point-steps/s of one whole-volume matter-era region on one MI355X.
+"""Benchmark: string point-steps/s on one MI355X, batched + learned scheduling against
+the plain per-region path.
 
-Workload: a Vachaspati-Vilenkin-style network from Z3 phases on a periodic 32^3
-lattice (box L = 32 correlation lengths, 8 points per correlation length,
-~2.4e5 points, at rest), evolved in the matter era from conformal time 8 until the
-smallest time on the current slice reaches 16. One benchmark step = one such run
-(diamond tops, element boxes, spatial hash, screen, FP64 confirmation, resolution,
-partner exchange) from the initial surface already resident in HBM.
+Default workload (--workload batched): 512 independent first-layer regions of an
+8x8x8 tiling (region size 4, matter era), each an independent Vachaspati-Vilenkin-
+style network at rest cut to the region's mid-time cross-section; point counts
+lognormal (median 2e4, sigma 1.5, capped at 2e5) with 20% of the regions empty, 8
+points per correlation length, about 1.6e7 points in about 410 non-empty regions.
+Every region runs until all of its points have stopped (left the region).
+
+One benchmark step = one whole schedule of all regions with inputs resident in HBM:
+cost-model features (GPU) + cost-model inference (GPU) + schedule_regions(BATCHED)
+ordered and packed by the predicted steps, FP32 screen with FP64 confirmation,
+graph-captured step blocks, output surfaces written to HBM, event lists to the host.
+The cost model is trained beforehand on the logged steps of a separate workload of
+the same recipe (seed 1), by the library's own kernels.
+
+Also reported: the point-count heuristic (same pipeline, no model), the plain
+per-region path (one region at a time, FP64 screen, one host check per step, no
+graphs, no batching), the roofline of the dominant kernel and the oracle on the host.
+
+--workload vv32: one whole-volume matter-era region (32^3 VV network, ~2.4e5 points,
+eta 8 -> 16), as before.
 
 Prints one JSON line. --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -23,13 +38,243 @@ METRIC = "string point-steps/s (evolve+intersect), batched+learned vs plain per-
 HBM_PEAK_GBS = 8000.0
 
 
-def evolve_bytes_per_point(screen_f32):
-    """Compulsory HBM bytes of one k_evolve launch per point: read X[n], X[n-1]
-    (4 x FP64 each) and next (int32); write X[n+1] (4 x FP64), the element box
-    (8 x FP32 or 8 x FP64), cell id and bucket slot (int32 each), and one
-    read-modify-write of a bucket counter (int32)."""
+def evolve_bytes_per_point(screen_f32, bounded):
+    """Compulsory HBM bytes of k_evolve per point-step: read X[n], X[n-1] (4 x FP64
+    each) and next (int32); write X[n+1] (4 x FP64), the element box (8 x FP32 or
+    8 x FP64), cell id and bucket slot (int32 each), one read-modify-write of a bucket
+    counter (int32); bounded regions also read the stop step and sub-region (int32)."""
     box = 32 if screen_f32 else 64
-    return 32 + 32 + 4 + 32 + box + 4 + 4 + 8
+    return 32 + 32 + 4 + 32 + box + 4 + 4 + 8 + (8 if bounded else 0)
+
+
+def screen_bytes_per_element(screen_f32):
+    """Compulsory HBM bytes of k_screen per element: its cell-sorted entry (cell, slot:
+    2 x int32) and screen box (8 x FP32 or FP64), each read once."""
+    return 8 + (32 if screen_f32 else 64)
+
+
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
+
+
+def make_inputs(args):
+    from paper_1011_4046_amd import inputs as I
+    t = time.perf_counter()
+    nt = I.lognormal_regions(args.regions, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2, seed=0)
+    parts, box = I.region_batch(nt, size=4.0, seed=0, slots=8, workers=args.workers)
+    log(f"workload: {len(parts)} regions, {sum(len(p[0]) for p in parts)} points "
+        f"({time.perf_counter() - t:.1f} s)")
+    t = time.perf_counter()
+    nt = I.lognormal_regions(args.train_regions, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2,
+                             seed=1)
+    train, tbox = I.region_batch(nt, size=4.0, seed=100000, slots=8, workers=args.workers)
+    log(f"training workload: {len(train)} regions, {sum(len(p[0]) for p in train)} points "
+        f"({time.perf_counter() - t:.1f} s)")
+    return parts, box, train, tbox
+
+
+def bench_batched(args):
+    import numpy as np
+    parts, box, train, tbox = make_inputs(args)   # before any GPU use (process pool)
+    import torch
+    from paper_1011_4046_amd import inputs as I
+    from paper_1011_4046_amd import scheduler as SC
+    from paper_1011_4046_amd import semipar as S
+    torch.cuda.set_device(0)
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER, device=True)
+    rs_tr = S.RegionSet.from_parts(train, tbox, I.MATTER, device=True)
+    torch.cuda.synchronize()
+    screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
+    fast = dict(use_graph=True, screen=screen, out="device", events=True)
+
+    # cost model: trained on the logged steps of the training workload
+    t = time.perf_counter()
+    logrun = S.schedule_regions(rs_tr, S.SCHED_BATCHED, use_graph=True, screen=screen,
+                                out=None, events=False)
+    cm = SC.LearnedCost(seed=0).fit(S.region_features(rs_tr), logrun["region_steps"],
+                                    iters=2000, lr=3e-3)
+    log(f"cost model: trained on {int((rs_tr.counts > 0).sum())} logged regions, loss "
+        f"{cm.losses[0]:.3f} -> {cm.losses[-1]:.4f} ({time.perf_counter() - t:.1f} s)")
+    del rs_tr
+
+    feat = S.region_features(rs)
+    pred = cm.predict(feat)
+    cfg = {"batch_frac": args.batch_frac, "screen_split": 7, "steps_per_sync": 64}
+    if args.tune:
+        cfg = SC.autotune(rs, pred, screen=screen, cache=args.tune_cache or None, log=log)
+        log(f"autotune: {cfg}")
+    bp = SC.batch_points_for(rs, cfg)
+    kw = dict(fast, batch_points=bp, screen_split=cfg["screen_split"],
+              steps_per_sync=cfg["steps_per_sync"])
+
+    for w in range(args.warmup):
+        r = SC.learned_schedule(rs, cm, **kw)
+        log(f"warmup {w}: {r['stats']['batches']} batches, {r['stats']['makespan_ms']:.0f} ms")
+        del r
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        runs.append(SC.learned_schedule(rs, cm, **kw))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    point_steps = sum(r["stats"]["point_steps"] for r in runs)
+    value = point_steps / elapsed
+    st = runs[0]["stats"]
+    steps = runs[0]["region_steps"]
+    live = rs.counts > 0
+    corr = float(np.corrcoef(np.log(pred[live]), np.log(np.maximum(steps[live], 1)))[0, 1])
+    log(f"timed {args.steps} schedules: {elapsed * 1e3:.0f} ms, {point_steps} point-steps, "
+        f"{st['batches']} batches, {st['events']} events per schedule")
+    extra = {"learned": {"batches": st["batches"], "makespan_ms": st["makespan_ms"],
+                         "predict_ms": runs[0]["predict_ms"],
+                         "corr_log_pred_log_steps": round(corr, 4)}}
+    del runs
+
+    # point-count heuristic, same batch size
+    t = time.perf_counter()
+    rh = S.schedule_regions(rs, S.SCHED_BATCHED, **kw)
+    torch.cuda.synchronize()
+    th = time.perf_counter() - t
+    extra["heuristic"] = {"point_steps_per_s": rh["stats"]["point_steps"] / th,
+                          "batches": rh["stats"]["batches"], "ms": th * 1e3}
+    log(f"heuristic: {th * 1e3:.0f} ms")
+    del rh
+
+    # plain per-region path
+    if args.plain:
+        t = time.perf_counter()
+        rp = S.schedule_regions(rs, S.SCHED_PLAIN, screen=S.SCREEN_F64, use_graph=False,
+                                steps_per_sync=1, out="device", events=True)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        pv = rp["stats"]["point_steps"] / tp
+        assert rp["stats"]["point_steps"] == st["point_steps"]
+        extra["plain_per_region"] = {"point_steps_per_s": pv, "ms": tp * 1e3,
+                                     "speedup_batched_learned": value / pv}
+        log(f"plain per-region: {tp * 1e3:.0f} ms, speed-up {value / pv:.2f}x")
+        del rp
+
+    # roofline: one eager schedule per timed kernel (events cannot be timed in graphs)
+    roofs = {}
+    for kname, kid in (("k_evolve", S.K_EVOLVE), ("k_screen", S.K_SCREEN)):
+        rr = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=pred, out=None,
+                                events=False, use_graph=False, screen=screen,
+                                screen_split=cfg["screen_split"],
+                                steps_per_sync=cfg["steps_per_sync"], timed_kernel=kid)
+        s2 = rr["stats"]
+        ms, nl = s2["timed_kernel_ms"], max(s2["timed_kernel_launches"], 1)
+        unit = (evolve_bytes_per_point(screen == S.SCREEN_F32, True) if kname == "k_evolve"
+                else screen_bytes_per_element(screen == S.SCREEN_F32))
+        # one element per point-step (the band piece to the right neighbour)
+        alg = unit * s2["point_steps"]
+        ach = alg / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        roofs[kname] = {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": None, "bytes_per_point_step": unit,
+                        "avg_launch_us": round(ms / nl * 1e3, 3), "launches": nl,
+                        "total_ms": round(ms, 2)}
+        log(f"{kname}: {nl} launches, {ms:.1f} ms, {ach:.0f} GB/s algorithmic")
+    dom = max(roofs, key=lambda k: roofs[k]["total_ms"])
+    roof = roofs[dom]
+    other = {k: v for k, v in roofs.items() if k != dom}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_regions(parts, box)
+    return {
+        "value": value, "ms_per_step": elapsed * 1e3 / args.steps,
+        "config": {"workload": "512 independent matter-era regions (8x8x8 first layer, size 4), "
+                               "lognormal points median 2e4 sigma 1.5 cap 2e5, 20% empty, "
+                               "each run until all its points stop",
+                   "regions": rs.n_regions, "points": int(rs.counts.sum()),
+                   "point_steps_per_schedule": st["point_steps"],
+                   "screen": args.screen, "graph": True, "batch_points": bp,
+                   "screen_split": cfg["screen_split"], "steps_per_sync": cfg["steps_per_sync"],
+                   "path": "batched + learned cost model (features, inference and schedule "
+                           "inside the timed region)"},
+        "roofline": roof, "roofline_other": other, "cpu_baseline": cpu, **extra,
+    }
+
+
+def cpu_baseline_regions(parts, box):
+    """The oracle on a sample of the same regions: every 25th non-empty region."""
+    import numpy as np
+    import oracle as O
+    from paper_1011_4046_amd import inputs as I
+    live = [i for i, p in enumerate(parts) if len(p[0])]
+    sample = live[::25]
+    t = time.perf_counter()
+    ps = 0
+    for i in sample:
+        recs, geom = parts[i]
+        net = dict(recs=recs, box=box, cosmology=I.MATTER, geom=geom)
+        _, _, ost = O.run(net, 10 ** 7)
+        ps += ost["point_steps"]
+    tc = time.perf_counter() - t
+    npts = int(np.sum([len(parts[i][0]) for i in sample]))
+    return {"value": ps / tc, "unit": "point-steps/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"{len(sample)} of the {len(live)} non-empty regions (every 25th, "
+                      f"{npts} points, {ps} point-steps, {tc:.1f} s), each run to completion"}
+
+
+def bench_vv32(args):
+    import numpy as np
+    import torch
+    from paper_1011_4046_amd import inputs as I
+    from paper_1011_4046_amd import semipar as S
+    torch.cuda.set_device(0)
+    net = I.vv_network(m=args.m, seed=0)
+    n = len(net["recs"])
+    t0, t_end = net["t0"], 2.0 * net["t0"]
+    raw = torch.from_numpy(net["recs"].view(np.uint8).copy()).cuda()
+    screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
+    kw = dict(screen=screen, use_graph=True, steps_per_sync=64)
+    log(f"VV {args.m}^3 matter era, {n} points, eta {t0} -> {t_end}")
+
+    def fresh():
+        return S.Region(raw, net["box"], net["cosmology"])
+
+    for _ in range(args.warmup):
+        r = fresh()
+        r.evolve(args.max_steps, t_end, **kw)
+        r.close()
+    regions = [fresh() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    stats = [r.evolve(args.max_steps, t_end, **kw) for r in regions]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    for r in regions:
+        r.close()
+    ps = sum(s["point_steps"] for s in stats)
+    r = fresh()
+    tst = r.evolve(args.max_steps, t_end, screen=screen, use_graph=False, steps_per_sync=64,
+                   timed_kernel=S.K_EVOLVE)
+    r.close()
+    unit = evolve_bytes_per_point(screen == S.SCREEN_F32, False)
+    ms, nl = tst["timed_kernel_ms"], max(tst["timed_kernel_launches"], 1)
+    ach = unit * tst["point_steps"] / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": "k_evolve", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_point_step": unit, "avg_launch_us": round(ms / nl * 1e3, 3)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        ro = O.OracleRegion(net["recs"], net["box"], net["cosmology"], I.HCOEF[net["cosmology"]])
+        tc = time.perf_counter()
+        ro.evolve(30)
+        tcpu = time.perf_counter() - tc
+        cst = ro.stats()
+        ro.close()
+        cpu = {"value": cst["point_steps"] / tcpu, "unit": "point-steps/s", "cores": O.threads(),
+               "kind": "oracle", "sample": f"first 30 lattice steps ({cst['point_steps']} "
+                                           f"point-steps, {tcpu:.1f} s)"}
+    return {"value": ps / elapsed, "ms_per_step": elapsed * 1e3 / args.steps,
+            "config": {"workload": f"matter-era VV network {args.m}^3, one whole-volume region, "
+                                   f"eta 8 -> 16", "points": n,
+                       "lattice_steps_per_run": stats[0]["steps"], "screen": args.screen},
+            "roofline": roof, "cpu_baseline": cpu}
 
 
 def main():
@@ -37,121 +282,29 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["batched", "vv32"], default="batched")
     ap.add_argument("--screen", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--graph", type=int, default=1)
-    ap.add_argument("--sync-steps", type=int, default=64)
-    ap.add_argument("--m", type=int, default=32, help="lattice size of the VV network")
+    ap.add_argument("--regions", type=int, default=512)
+    ap.add_argument("--train-regions", type=int, default=128)
+    ap.add_argument("--workers", type=int, default=8, help="processes generating the inputs")
+    ap.add_argument("--batch-frac", type=float, default=1.0,
+                    help="batch size as a fraction of all points (1 = one batch)")
+    ap.add_argument("--tune", type=int, default=0, help="run the autotuner first")
+    ap.add_argument("--tune-cache", default="")
+    ap.add_argument("--plain", type=int, default=1, help="also time the plain per-region path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--plain", type=int, default=1, help="also time the plain per-step path")
-    ap.add_argument("--max-steps", type=int, default=10 ** 7,
-                    help="cap on lattice steps per run (profiling runs)")
+    ap.add_argument("--m", type=int, default=32)
+    ap.add_argument("--max-steps", type=int, default=10 ** 7)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    from paper_1011_4046_amd import inputs as I
-    from paper_1011_4046_amd import semipar as S
-
-    torch.cuda.set_device(0)
-    net = I.vv_network(m=args.m, seed=0)
-    n = len(net["recs"])
-    t0, t_end = net["t0"], 2.0 * net["t0"]
-    raw = torch.from_numpy(net["recs"].view(np.uint8).copy()).cuda()
-    stream = torch.cuda.current_stream()
-    screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
-    kw = dict(screen=screen, use_graph=bool(args.graph), steps_per_sync=args.sync_steps)
-    print(f"bench: VV {args.m}^3 matter era, {n} points, eta {t0} -> {t_end}, "
-          f"screen {args.screen}, graph {args.graph}", file=sys.stderr, flush=True)
-
-    def fresh():
-        return S.Region(raw, net["box"], net["cosmology"])
-
-    for w in range(args.warmup):
-        r = fresh()
-        st = r.evolve(args.max_steps, t_end, **kw)
-        r.close()
-        print(f"bench: warmup {w}: {st['steps']} steps, {st['elapsed_ms']:.1f} ms",
-              file=sys.stderr, flush=True)
-
-    regions = [fresh() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    stats = []
-    t_start = time.perf_counter()
-    for r in regions:
-        stats.append(r.evolve(args.max_steps, t_end, **kw))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    for r in regions:
-        r.close()
-    point_steps = sum(s["point_steps"] for s in stats)
-    value = point_steps / elapsed
-    lattice_steps = stats[0]["steps"]
-    print(f"bench: timed {args.steps} runs: {elapsed * 1e3:.1f} ms, {point_steps} point-steps, "
-          f"{lattice_steps} lattice steps per run", file=sys.stderr, flush=True)
-
-    # roofline of the dominant kernel (k_evolve): HIP events around each of its launches,
-    # recorded on the region's stream during one more full run (events cannot be timed
-    # inside a captured graph, so this run issues its steps eagerly)
-    r = fresh()
-    tst = r.evolve(args.max_steps, t_end, screen=screen, use_graph=False,
-                   steps_per_sync=args.sync_steps, timed_kernel=S.K_EVOLVE)
-    r.close()
-    ev_ms = tst["timed_kernel_ms"]
-    ev_n = tst["timed_kernel_launches"]
-    bpp = evolve_bytes_per_point(args.screen == "f32")
-    avg_s = ev_ms / max(ev_n, 1) / 1e3
-    achieved = bpp * n / avg_s / 1e9 if avg_s > 0 else 0.0
-    roof = {"bound": "hbm", "kernel": "k_evolve", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "bytes_per_point": bpp, "avg_launch_us": round(avg_s * 1e6, 3)}
-
-    extra = {}
-    if args.plain:
-        r = fresh()
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        sp = r.evolve(args.max_steps, t_end, screen=S.SCREEN_F64, use_graph=False, steps_per_sync=1)
-        torch.cuda.synchronize()
-        te = time.perf_counter() - ts
-        r.close()
-        extra["plain_per_region_point_steps_per_s"] = sp["point_steps"] / te
-        extra["plain_ms"] = te * 1e3
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle as O
-        sample_steps = 30
-        ro = O.OracleRegion(net["recs"], net["box"], net["cosmology"], I.HCOEF[net["cosmology"]])
-        tc = time.perf_counter()
-        ro.evolve(sample_steps)
-        tcpu = time.perf_counter() - tc
-        cst = ro.stats()
-        ro.close()
-        cpu = {"value": cst["point_steps"] / tcpu, "unit": "point-steps/s", "cores": O.threads(),
-               "kind": "oracle",
-               "sample": f"first {sample_steps} lattice steps of the same network "
-                         f"({cst['point_steps']} point-steps, {tcpu:.1f} s)"}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "point-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"matter-era VV network {args.m}^3 (L={args.m}, 8 points per "
-                               f"correlation length), one whole-volume region, eta 8 -> 16",
-                   "points": n, "lattice_steps_per_run": lattice_steps,
-                   "screen": args.screen, "graph": bool(args.graph),
-                   "path": "plain per-region (single region, graph-captured step blocks)"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "events_per_run": stats[0]["accepted"],
-        **extra,
-    }
+    res = bench_batched(args) if args.workload == "batched" else bench_vv32(args)
+    out = {"metric": METRIC, "value": res.pop("value"), "unit": "point-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", **res}
     print(json.dumps(out), flush=True)
 
 

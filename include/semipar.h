@@ -349,6 +349,9 @@ typedef struct semipar_sched_stats {
   double makespan_ms;    /* host wall time of the call, from the first upload to the
                             last result */
   double evolve_ms;      /* summed device time of the evolve calls */
+  double timed_kernel_ms;        /* with evolve.timed_kernel set: summed device time of
+                                    that kernel over all calls (HIP events) */
+  int64_t timed_kernel_launches; /* and the number of its launches that did work */
 } semipar_sched_stats;
 
 /* Run every region of the tiling on this GPU, in dependency order (paper: manager and

@@ -141,6 +141,8 @@ struct Runner {
     acc.point_steps += es.point_steps;
     acc.steps += es.steps;
     acc.evolve_ms += es.elapsed_ms;
+    acc.timed_kernel_ms += es.timed_kernel_ms;
+    acc.timed_kernel_launches += es.timed_kernel_launches;
     acc.batches += 1;
     log_region(r, steps[0], ps[0], batch_id++, es.elapsed_ms);
     return SEMIPAR_OK;
@@ -204,6 +206,8 @@ struct Runner {
     acc.point_steps += es.point_steps;
     acc.steps += es.steps;
     acc.evolve_ms += es.elapsed_ms;
+    acc.timed_kernel_ms += es.timed_kernel_ms;
+    acc.timed_kernel_launches += es.timed_kernel_launches;
     acc.batches += 1;
     for (size_t i = 0; i < regs.size(); ++i)
       log_region(regs[i], steps[i], ps[i], batch_id, es.elapsed_ms);

@@ -143,6 +143,22 @@ struct HashCfg {   // fixed for a configuration
   double tol_t;    // slack of FP32 time conversion
 };
 
+// Local grid of one sub-region of a batch: a non-periodic cube of side W = 2.5 g around
+// the region's spatial origin (the region's points lie within g of it per axis), nc^3
+// cells of edge h. Elements outside are clamped into the boundary cells, which only
+// merges cells (more pairs tested, never fewer). Cells of region q occupy the buckets
+// (base + row-major index) mod B; cell keys carry the region's salt.
+struct RCell {
+  double ox, oy, oz;  // grid origin
+  double h, inv_h, hlim;
+  float h32, marg32;
+  int32_t nc;
+  uint32_t base;
+  uint32_t salt;
+  int32_t pad;
+};
+constexpr double RCELL_W = 2.5;  // grid side in units of g
+
 __device__ __forceinline__ V4 ld(const Slices& X, int s, int k) {
   return V4{X.p[s][0][k], X.p[s][1][k], X.p[s][2][k], X.p[s][3][k]};
 }
@@ -296,7 +312,9 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
                                                int32_t* __restrict__ face,
                                                semipar_point_rec* __restrict__ frz, RegionGeom G0,
                                                const RegionGeom* __restrict__ geoms,
-                                               const int32_t* __restrict__ rid) {
+                                               const int32_t* __restrict__ rid,
+                                               const RCell* __restrict__ rcell,
+                                               uint64_t* __restrict__ rext) {
   if (ctrl->done) return;
   const int s = ctrl->step;
   const Cells cs = ctrl->cells;
@@ -370,7 +388,10 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
             W[c] = P.box * floor(b.lo[c] * P.inv);
             w[c] = b.lo[c] - W[c];
           }
-          if (cs.nc == 0 || !(ext <= cs.hlim)) {
+          const bool local = BND && rcell != nullptr;
+          RCell C{};
+          if (local) C = rcell[rid[k]];
+          if (local ? !(ext <= C.hlim) : (cs.nc == 0 || !(ext <= cs.hlim))) {
             const int li = atomicAdd(&ctrl->n_large, 1);
             LargeBox lb;
             for (int c = 0; c < 3; ++c) {
@@ -386,12 +407,27 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
           } else {
             int ci[3];
             double lor[3], hir[3];
-            for (int c = 0; c < 3; ++c) {
-              int q = (int)floor(w[c] * cs.inv_h);
-              q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
-              ci[c] = q;
-              lor[c] = w[c] - (double)q * cs.h;
-              hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
+            if (local) {
+              // coordinates relative to the region's grid origin (minimum image)
+              const double o[3] = {C.ox, C.oy, C.oz};
+              for (int c = 0; c < 3; ++c) {
+                const double d = b.lo[c] - o[c];
+                const double sh = P.box * P.nearest(d);
+                const double dl = d - sh;
+                int q = (int)floor(dl * C.inv_h);
+                q = q < 0 ? 0 : (q > C.nc - 1 ? C.nc - 1 : q);
+                ci[c] = q;
+                lor[c] = dl - (double)q * C.h;
+                hir[c] = ((b.hi[c] - o[c]) - sh) - (double)q * C.h;
+              }
+            } else {
+              for (int c = 0; c < 3; ++c) {
+                int q = (int)floor(w[c] * cs.inv_h);
+                q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
+                ci[c] = q;
+                lor[c] = w[c] - (double)q * cs.h;
+                hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
+              }
             }
             if constexpr (SCR == 1) {
               double4* o = (double4*)ebox + (size_t)k * 2;
@@ -408,7 +444,9 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
                                  __double2float_ru(hir[2] + hc.tol),
                                  __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
             }
-            const uint32_t bk = bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
+            const uint32_t bk =
+                local ? (C.base + (uint32_t)((ci[0] * C.nc + ci[1]) * C.nc + ci[2])) & hc.bmask
+                      : bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
             epos[k] = atomicAdd(&cnt[bk], 1);
             ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
           }
@@ -416,6 +454,22 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
       }
     } else if constexpr (SCR != 0) {
       ecell[k] = NO_ELEM;
+    }
+  }
+  // batch: largest element extent per sub-region (one atomic per wave when the wave
+  // holds one sub-region)
+  if constexpr (BND && SCR != 0) {
+    if (rext) {
+      const bool live = k < n;
+      const int q = live ? rid[k] : -1;
+      const int q0 = __shfl(q, 0, 64);
+      const uint64_t lm = __ballot(live), sm = __ballot(live && q == q0);
+      if (lm == sm && (lm & 1ull)) {
+        const uint64_t m = wave_max_u64(xkey);
+        if ((threadIdx.x & 63) == 0 && m != 0) atomicMax((unsigned long long*)&rext[q0], m);
+      } else if (live && xkey != 0) {
+        atomicMax((unsigned long long*)&rext[q], xkey);
+      }
     }
   }
   // per block: minimum t of the new slice, largest element extent, points advanced;
@@ -496,31 +550,48 @@ __device__ __forceinline__ int bucket_start(const int32_t* loc, const int32_t* s
   return loc[b] + s_toff[b >> TS_LOG];
 }
 
-// Cell-sorted copies of each hashed element: cell, slot and screen box.
+// Exclusive scan of the tile totals (one workgroup): toff[t] = first sorted position of
+// tile t, toff[ntiles] = number of hashed elements.
+__global__ __launch_bounds__(1024) void k_toff(const int32_t* __restrict__ tile_tot, int ntiles,
+                                               int32_t* __restrict__ toff, const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  __shared__ int32_t s_toff[MAX_TILES + 1];
+  __shared__ int32_t s_tmp[1024];
+  block_tile_offsets(tile_tot, ntiles, s_toff, s_tmp);
+  for (int i = threadIdx.x; i <= ntiles; i += 1024) toff[i] = s_toff[i];
+}
+
+// Cell-sorted copies of each hashed element: cell key, slot and screen box. In a batch
+// the key is the packed local cell xor the sub-region's salt.
 template <int SCR>
 __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict__ ecell,
                                                 const int32_t* __restrict__ epos,
                                                 const int32_t* __restrict__ loc,
-                                                const int32_t* __restrict__ tile_tot, int ntiles,
-                                                int32_t* __restrict__ toff,
+                                                const int32_t* __restrict__ toff,
                                                 const void* __restrict__ ebox,
                                                 int2* __restrict__ sent,
                                                 void* __restrict__ sbox, HashCfg hc,
+                                                const int32_t* __restrict__ rid,
+                                                const RCell* __restrict__ rcell,
                                                 const Ctrl* ctrl) {
   if (ctrl->done) return;
-  __shared__ int32_t s_toff[MAX_TILES + 1];
-  __shared__ int32_t s_tmp[NT];
-  block_tile_offsets(tile_tot, ntiles, s_toff, s_tmp);
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i <= ntiles; i += NT) toff[i] = s_toff[i];
   const int nc = ctrl->cells.nc;
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k >= n) return;
   const int32_t c = ecell[k];
   if (c < 0) return;
-  const uint32_t b = bucket_of(nc, hc.bmask, c & 1023, (c >> 10) & 1023, (c >> 20) & 1023);
-  const int pos = bucket_start(loc, s_toff, b) + epos[k];
-  sent[pos] = make_int2(c, k);
+  const int x = c & 1023, y = (c >> 10) & 1023, z = (c >> 20) & 1023;
+  uint32_t b;
+  int32_t key = c;
+  if (rcell) {
+    const RCell C = rcell[rid[k]];
+    b = (C.base + (uint32_t)((x * C.nc + y) * C.nc + z)) & hc.bmask;
+    key = (int32_t)((uint32_t)c ^ C.salt);
+  } else {
+    b = bucket_of(nc, hc.bmask, x, y, z);
+  }
+  const int pos = bucket_start(loc, toff, b) + epos[k];
+  sent[pos] = make_int2(key, k);
   if constexpr (SCR == 1) {
     const double4* src = (const double4*)ebox + (size_t)k * 2;
     double4* dst = (double4*)sbox + (size_t)pos * 2;
@@ -609,7 +680,9 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
                                                const int32_t* __restrict__ toff, int ntiles,
                                                const LargeBox* __restrict__ large, HashCfg hc,
                                                sp::Period P, int2* __restrict__ cand, int cap,
-                                               int nblk, Ctrl* ctrl) {
+                                               int nblk, Ctrl* ctrl,
+                                               const int32_t* __restrict__ rid,
+                                               const RCell* __restrict__ rcell) {
   if (ctrl->done) return;
   const int lid = xcd_block(nblk * G);
   if (lid >= nblk * G) return;
@@ -638,8 +711,17 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
     if (q < n_norm) {
       own_large = false;
       const int2 ent = sent[q];
-      const int32_t c = ent.x;
       k = ent.y;
+      // grid of the element: the region's own (batch) or the periodic box's
+      RCell C{};
+      uint32_t salt = 0;
+      int gnc = cs.nc;
+      if (rcell) {
+        C = rcell[rid[k]];
+        salt = C.salt;
+        gnc = C.nc;
+      }
+      const int32_t c = (int32_t)((uint32_t)ent.x ^ salt);
       const int nk = nxt[k], pk = prv[k];
       const SBox<T> me = load_sbox<T>(sbox, q);
       const int cx = c & 1023, cy = (c >> 10) & 1023, cz = (c >> 20) & 1023;
@@ -656,18 +738,31 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
           const int dy = o == 0 ? 0 : (o < 10 ? (o - 1) / 3 - 1 : (o < 13 ? 1 : 0));
           const int dz = o == 0 ? 0 : (o < 10 ? (o - 1) % 3 - 1 : (o < 13 ? o - 11 : 1));
           int x = cx + dx, y = cy + dy, z = cz + dz;
-          x = x < 0 ? x + cs.nc : (x >= cs.nc ? x - cs.nc : x);
-          y = y < 0 ? y + cs.nc : (y >= cs.nc ? y - cs.nc : y);
-          z = z < 0 ? z + cs.nc : (z >= cs.nc ? z - cs.nc : z);
-          const uint32_t b = bucket_of(cs.nc, hc.bmask, x, y, z);
-          rb[i] = o == 0 ? q + 1 : bucket_start(loc, toff, b);
-          re[i] = bucket_start(loc, toff, b + 1);
-          rc[i] = (int)pack_cell(x, y, z);
+          if (rcell) {
+            // local grid: no periodic wrap; nothing lies outside
+            if (x < 0 || y < 0 || z < 0 || x >= gnc || y >= gnc || z >= gnc) continue;
+            const uint32_t b = (C.base + (uint32_t)((x * gnc + y) * gnc + z)) & hc.bmask;
+            rb[i] = o == 0 ? q + 1 : bucket_start(loc, toff, b);
+            re[i] = bucket_start(loc, toff, b + 1);
+            rc[i] = (int32_t)(pack_cell(x, y, z) ^ salt);
+          } else {
+            x = x < 0 ? x + gnc : (x >= gnc ? x - gnc : x);
+            y = y < 0 ? y + gnc : (y >= gnc ? y - gnc : y);
+            z = z < 0 ? z + gnc : (z >= gnc ? z - gnc : z);
+            const uint32_t b = bucket_of(gnc, hc.bmask, x, y, z);
+            rb[i] = o == 0 ? q + 1 : bucket_start(loc, toff, b);
+            re[i] = bucket_start(loc, toff, b + 1);
+            rc[i] = (int)pack_cell(x, y, z);
+          }
         }
       }
       if (g == 0) {
+        // the element's box in global coordinates (any periodic image) for the
+        // comparisons with large elements
+        const double gh = rcell ? C.h : cs.h;
+        const double go[3] = {rcell ? C.ox : 0.0, rcell ? C.oy : 0.0, rcell ? C.oz : 0.0};
         for (int i = 0; i < 3; ++i) {
-          wl[i] = (double)(i == 0 ? cx : (i == 1 ? cy : cz)) * cs.h + (double)me.v[i];
+          wl[i] = go[i] + ((double)(i == 0 ? cx : (i == 1 ? cy : cz)) * gh + (double)me.v[i]);
           ex[i] = (double)me.v[4 + i] - (double)me.v[i];
         }
         if constexpr (SCR == 1) {
@@ -678,8 +773,8 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
           thi = (double)me.v[7] + hc.tref;
         }
       }
-      const T tl = SCR == 1 ? (T)hc.tol : (T)cs.marg32;
-      const T hh = SCR == 1 ? (T)cs.h : (T)cs.h32;
+      const T tl = SCR == 1 ? (T)hc.tol : (T)(rcell ? C.marg32 : cs.marg32);
+      const T hh = SCR == 1 ? (T)(rcell ? C.h : cs.h) : (T)(rcell ? C.h32 : cs.h32);
 #pragma unroll
       for (int i = 0; i < MAXS; ++i) {
         const int o = o_beg + i;
@@ -1071,6 +1166,68 @@ __global__ __launch_bounds__(1024) void k_begin_set(Ctrl* ctrl, int32_t step_lim
   ctrl->n_large = 0;
   const double tmin = a ? from_key(m) : 0.0;
   ctrl->done = (a == 0 || ctrl->step >= step_limit || tmin >= t_end) ? 1 : 0;
+}
+
+// Local grids of the sub-regions of a batch for the next step (one workgroup). h_set > 0:
+// every region gets cells of edge >= h_set (start of a call, or a fixed cell size);
+// otherwise each region's cells follow its own largest element of the step just taken
+// (grow x extent; regions without elements keep their grid). Bucket bases are the
+// running sum of the regions' cell counts. The extents are reset for the next step.
+__global__ __launch_bounds__(1024) void k_rcells(const RegionGeom* __restrict__ geoms, int n_sub,
+                                                 uint64_t* __restrict__ rext,
+                                                 RCell* __restrict__ rc, double h_set,
+                                                 const Ctrl* ctrl) {
+  if (h_set <= 0.0 && ctrl->done) return;
+  __shared__ uint64_t s_sum[1024];
+  const int t = threadIdx.x;
+  const int per = (n_sub + 1023) / 1024;
+  const double grow = ctrl->grow;
+  uint64_t sum = 0;
+  for (int i = 0; i < per; ++i) {
+    const int q = t * per + i;
+    if (q >= n_sub) break;
+    RCell C = rc[q];
+    const double g = 0.5 / geoms[q].inv2g;
+    const double W = RCELL_W * g;
+    double target = h_set;
+    if (h_set <= 0.0) {
+      const uint64_t x = rext[q];
+      target = x != 0 ? grow * from_key(x) : (C.nc > 0 ? C.h : W / 3.0);
+    }
+    rext[q] = 0;
+    int nc = (int)floor(W / target);
+    nc = nc < 3 ? 3 : (nc > 1023 ? 1023 : nc);
+    C.nc = nc;
+    C.h = W / nc;
+    C.inv_h = 1.0 / C.h;
+    C.hlim = C.h - 4.0 * ctrl->tol;
+    C.h32 = (float)C.h;
+    // FP32 slack: a few ulps at the largest local magnitude (clamped elements lie up to
+    // W from a cell origin)
+    C.marg32 = (float)((W + 3.0 * C.h) * 0x1p-20);
+    C.ox = geoms[q].V[0] - 0.5 * W;
+    C.oy = geoms[q].V[1] - 0.5 * W;
+    C.oz = geoms[q].V[2] - 0.5 * W;
+    C.salt = (uint32_t)q * 0x9E3779B1u;
+    rc[q] = C;
+    sum += (uint64_t)nc * nc * nc;
+  }
+  s_sum[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint64_t add = t >= o ? s_sum[t - o] : 0;
+    __syncthreads();
+    s_sum[t] += add;
+    __syncthreads();
+  }
+  uint64_t run = s_sum[t] - sum;
+  for (int i = 0; i < per; ++i) {
+    const int q = t * per + i;
+    if (q >= n_sub) break;
+    rc[q].base = (uint32_t)run;
+    const int nc = rc[q].nc;
+    run += (uint64_t)nc * nc * nc;
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -1552,6 +1709,9 @@ struct semipar_region {
   int32_t* rid = nullptr;       // batch: sub-region of each point
   std::vector<int64_t> sub_off;  // batch: first slot of each sub-region (n_sub + 1 entries)
   int32_t* log_rid = nullptr;    // batch: sub-region of each logged event
+  RCell* rcell = nullptr;        // batch: local grid of each sub-region
+  uint64_t* rext = nullptr;      // batch: largest element extent per sub-region (key)
+  double rc_fixed_h = 0.0;       // batch: fixed cell edge (0 = adaptive)
   int32_t step0 = 1;             // slice index of the initial surfaces
   int32_t *fstep = nullptr, *face = nullptr;  // bounded: stop step and exit face per point
   semipar_point_rec* frz = nullptr;           // bounded: record of each stopped point
@@ -1770,7 +1930,8 @@ template <bool FRW, int SCR, bool BND>
 void launch_evolve_t(semipar_region* r, int n, int nb) {
   k_evolve<FRW, SCR, BND><<<nb, NT, 0, r->stream>>>(
       r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell, r->epos,
-      r->cnt, r->large, r->blkred, r->fstep, r->face, r->frz, r->geom, r->geoms, r->rid);
+      r->cnt, r->large, r->blkred, r->fstep, r->face, r->frz, r->geom, r->geoms, r->rid, r->rcell,
+      r->rext);
 }
 
 template <bool FRW, bool BND>
@@ -1795,7 +1956,7 @@ template <int SCR, int G>
 void launch_screen_t(semipar_region* r, int n, int nb) {
   k_screen<SCR, G><<<xcd_grid(nb * G), NT, 0, r->stream>>>(
       n, r->sent, r->sbox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc, r->P,
-      r->cand, (int)r->cap_cand, nb, r->ctrl);
+      r->cand, (int)r->cap_cand, nb, r->ctrl, r->rid, r->rcell);
 }
 
 // Screen launch: precision (FP64 / FP32 boxes) and threads per element (split).
@@ -1832,12 +1993,13 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
     k_scan<<<r->ntiles, 256, 0, s>>>(r->cnt, r->loc, r->tile_tot, r->ctrl);
     mark(r, SEMIPAR_K_SCAN, 2 * i + 1);
     mark(r, SEMIPAR_K_SCATTER, 2 * i);
+    k_toff<<<1, 1024, 0, s>>>(r->tile_tot, r->ntiles, r->toff, r->ctrl);
     if (r->screen == 1)
-      k_scatter<1><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->tile_tot, r->ntiles, r->toff, r->ebox, r->sent,
-                                     r->sbox, r->hc, r->ctrl);
+      k_scatter<1><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
+                                     r->sbox, r->hc, r->rid, r->rcell, r->ctrl);
     else
-      k_scatter<2><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->tile_tot, r->ntiles, r->toff, r->ebox, r->sent,
-                                     r->sbox, r->hc, r->ctrl);
+      k_scatter<2><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
+                                     r->sbox, r->hc, r->rid, r->rcell, r->ctrl);
     mark(r, SEMIPAR_K_SCATTER, 2 * i + 1);
     mark(r, SEMIPAR_K_SCREEN, 2 * i);
     launch_screen(r, n, nb);
@@ -1851,6 +2013,8 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
   k_resolve<<<1, RESOLVE_NT, 0, s>>>(r->nxt, r->prv, r->ev, (int)r->cap_evt, (int)r->cap_cand,
                                      r->best, r->used, r->evs, r->log, r->log_cap, r->blkred, nb,
                                      r->ctrl, r->rid, r->log_rid);
+  if (intercommute && r->rcell)
+    k_rcells<<<1, 1024, 0, s>>>(r->geoms, r->n_sub, r->rext, r->rcell, r->rc_fixed_h, r->ctrl);
   mark(r, SEMIPAR_K_RESOLVE, 2 * i + 1);
 }
 
@@ -1908,6 +2072,8 @@ void region_destroy(semipar_region* r) {
   dfree(r->ctrl);
   dfree(r->log);
   dfree(r->log_rid);
+  dfree(r->rcell);
+  dfree(r->rext);
   if (r->ctrl_h) (void)hipHostFree(r->ctrl_h);
   if (r->ev0) (void)hipEventDestroy(r->ev0);
   if (r->ev1) (void)hipEventDestroy(r->ev1);
@@ -2003,8 +2169,12 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       for (int64_t q = 0; q < in[i].n; ++q) hr[off++] = i;
     }
     r->sub_off[n_in] = off;
-    if (dalloc(&r->geoms, d->n_sub) != hipSuccess || dalloc(&r->rid, cap) != hipSuccess)
+    if (dalloc(&r->geoms, d->n_sub) != hipSuccess || dalloc(&r->rid, cap) != hipSuccess ||
+        dalloc(&r->rcell, d->n_sub) != hipSuccess || dalloc(&r->rext, d->n_sub) != hipSuccess)
       return fail(SEMIPAR_E_OOM);
+    if (hipMemset(r->rcell, 0, sizeof(RCell) * d->n_sub) != hipSuccess ||
+        hipMemset(r->rext, 0, sizeof(uint64_t) * d->n_sub) != hipSuccess)
+      return fail(SEMIPAR_E_HIP);
     if (hipMemcpy(r->geoms, hg.data(), sizeof(RegionGeom) * d->n_sub, hipMemcpyHostToDevice) !=
             hipSuccess ||
         (total > 0 && hipMemcpy(r->rid, hr.data(), sizeof(int32_t) * total,
@@ -2144,6 +2314,15 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   }
   k_begin_set<<<1, 1024, 0, r->stream>>>(r->ctrl, step_limit, p->t_end, r->blkred, blocks(n),
                                          cells, set_cells);
+  if (r->rcell) {
+    // batch: every sub-region starts with cells fitting the largest initial element
+    // (or the fixed size), then follows its own elements
+    const double fh = p->cell_size > 0 ? p->cell_size : 0.0;
+    if (fh != r->rc_fixed_h) drop_graph(r);  // the per-step launch carries it
+    r->rc_fixed_h = fh;
+    const double h0 = p->cell_size > 0 ? p->cell_size : 1.25 * std::max(r->ext0, 1e-300);
+    k_rcells<<<1, 1024, 0, r->stream>>>(r->geoms, r->n_sub, r->rext, r->rcell, h0, r->ctrl);
+  }
   HIPCHK(hipGetLastError());
   for (;;) {
     rc = ensure_log(r, r->ctrl_h->log_n + 2 * r->cap_evt);

@@ -1,0 +1,154 @@
+"""Scheduling pipeline over libsemipar: learned cost model and autotuner.
+
+Paper, Section "Performance": the elapsed time is set by the most difficult regions,
+which a scheduler can start first and group with regions of similar cost. Here:
+
+* features of every region's initial surface come from the library's GPU kernel;
+* the cost model (12 -> 64 -> 64 -> 1, FP32) is trained by the library's own forward,
+  gradient and Adam kernels on logged per-region step counts (log steps);
+* the scheduler orders regions by the predicted steps and cuts them into launch
+  batches (schedule_regions with a cost vector); without a model it falls back to the
+  point-count order;
+* an autotuner picks the batch size, the screen split and the steps per host check by
+  timing short runs on a sample of the regions, and caches the choice per workload.
+
+Nothing here changes results: every choice only orders or groups regions, or sets
+launch shapes.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+from . import semipar as S
+
+
+def init_params(seed=0):
+    """He-uniform initial weights (seeded), zero biases, in the library's layout."""
+    rng = np.random.default_rng(seed)
+    ni, nh = S.MLP_IN, S.MLP_HIDDEN
+    w1 = rng.uniform(-1, 1, (nh, ni)) * np.sqrt(6.0 / ni)
+    w2 = rng.uniform(-1, 1, (nh, nh)) * np.sqrt(6.0 / nh)
+    w3 = rng.uniform(-1, 1, nh) * np.sqrt(6.0 / nh)
+    p = np.concatenate([w1.ravel(), np.zeros(nh), w2.ravel(), np.zeros(nh), w3, [0.0]])
+    assert p.size == S.MLP_PARAMS
+    return p.astype(np.float32)
+
+
+class LearnedCost:
+    """Cost model trained on logged (features, steps) pairs of earlier runs."""
+
+    def __init__(self, seed=0):
+        self.model = S.CostModel(init_params(seed))
+        self.losses = None
+
+    def fit(self, feat, steps, iters=2000, lr=3e-3):
+        live = np.asarray(feat)[:, 0] > 0  # log1p(points) > 0: non-empty regions
+        x = np.asarray(feat, np.float32)[live]
+        y = np.log(np.maximum(np.asarray(steps, np.float64)[live], 1.0)).astype(np.float32)
+        self.model.set_norm_from(x)
+        self.losses = self.model.train(x, y, iters=iters, lr=lr)
+        return self
+
+    def predict(self, feat):
+        """Predicted lattice steps per region (empty regions: 0)."""
+        feat = np.asarray(feat, np.float32)
+        y = np.exp(self.model.forward(feat)).astype(np.float32)
+        return np.where(feat[:, 0] > 0, y, 0.0).astype(np.float32)
+
+
+def learned_schedule(rs, cost_model, **kw):
+    """Features on the GPU, cost-model inference, then the batched schedule."""
+    t0 = time.perf_counter()
+    feat = S.region_features(rs)
+    pred = cost_model.predict(feat)
+    t1 = time.perf_counter()
+    res = S.schedule_regions(rs, S.SCHED_BATCHED, cost=pred, **kw)
+    res["predict_ms"] = (t1 - t0) * 1e3
+    res["pred"] = pred
+    return res
+
+
+# ---- autotuner ------------------------------------------------------------------
+
+TUNABLE = {
+    "batch_frac": [1.0, 0.5, 0.25, 0.125],  # batch_points as a fraction of all points
+    "screen_split": [7, 14, 2],
+    "steps_per_sync": [64, 32, 128],
+}
+
+
+def workload_key(rs, screen):
+    n = rs.counts[rs.counts > 0]
+    return (f"r{rs.n_regions}-n{int(np.log2(max(int(n.sum()), 1)))}-"
+            f"m{int(np.log2(max(int(np.median(n)) if len(n) else 1, 1)))}-c{rs.cosmology}-s{screen}")
+
+
+def _sample(rs, every):
+    """Every `every`-th region of rs as a new RegionSet (host copy of its records)."""
+    idx = np.arange(0, rs.n_regions, every)
+    recs = rs.recs
+    if not isinstance(recs, np.ndarray):
+        recs = recs.cpu().numpy().view(S.REC_DTYPE)
+    parts = []
+    for r in idx:
+        a, b = int(rs.offsets[r]), int(rs.offsets[r + 1])
+        g = rs.geoms[r]
+        geom = list(g.origin) + [g.inv2g] + list(g.idx)
+        parts.append((recs[a:b], np.asarray(geom)))
+    return S.RegionSet.from_parts(parts, rs.box, rs.cosmology, device=True), idx
+
+
+def autotune(rs, cost=None, screen=S.SCREEN_F32, cache=None, every=4, log=None):
+    """Coordinate search over TUNABLE on every `every`-th region, timing one batched
+    schedule per candidate (makespan). Returns the parameter dict; with `cache` (a JSON
+    path) a previous choice for the same workload key is reused."""
+    key = workload_key(rs, screen)
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            got = json.load(f).get(key)
+        if got:
+            return dict(got, cached=True)
+    sub, idx = _sample(rs, every)
+    sub_cost = None if cost is None else np.asarray(cost, np.float32)[idx]
+    total = int(sub.counts.sum())
+    best = {k: v[0] for k, v in TUNABLE.items()}
+
+    def run(cfg):
+        bp = int(total * cfg["batch_frac"]) if cfg["batch_frac"] < 1.0 else 0
+        res = S.schedule_regions(sub, S.SCHED_BATCHED, batch_points=bp, cost=sub_cost,
+                                 out=None, events=False, use_graph=True, screen=screen,
+                                 screen_split=cfg["screen_split"],
+                                 steps_per_sync=cfg["steps_per_sync"])
+        return res["stats"]["makespan_ms"]
+
+    run(best)  # warm-up (graph instantiation, allocator)
+    best_ms = run(best)
+    for k, vals in TUNABLE.items():
+        for v in vals[1:]:
+            cfg = dict(best, **{k: v})
+            ms = run(cfg)
+            if log:
+                log(f"autotune {key}: {cfg} -> {ms:.1f} ms")
+            if ms < best_ms:
+                best, best_ms = cfg, ms
+    out = dict(best, sample_ms=best_ms)
+    if cache:
+        data = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                data = json.load(f)
+        data[key] = out
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return out
+
+
+def batch_points_for(rs, cfg):
+    f = cfg.get("batch_frac", 1.0)
+    return int(int(rs.counts.sum()) * f) if f < 1.0 else 0

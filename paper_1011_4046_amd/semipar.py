@@ -103,7 +103,8 @@ class SchedStats(ctypes.Structure):
     _fields_ = [("regions", ctypes.c_int64), ("empty_regions", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("point_steps", ctypes.c_int64),
                 ("steps", ctypes.c_int64), ("events", ctypes.c_int64),
-                ("makespan_ms", ctypes.c_double), ("evolve_ms", ctypes.c_double)]
+                ("makespan_ms", ctypes.c_double), ("evolve_ms", ctypes.c_double),
+                ("timed_kernel_ms", ctypes.c_double), ("timed_kernel_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -396,7 +397,7 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
                      events=True, stream=None, max_steps=10 ** 7, t_end=float("inf"),
                      screen=SCREEN_F64, intercommute=True, cell_size=0.0, steps_per_sync=0,
                      use_graph=False, cand_per_point=0.0, events_per_point=0.0,
-                     screen_split=0):
+                     screen_split=0, timed_kernel=-1):
     """Run every region of rs; returns a dict with the stats, per-region logs, output
     records (out = "host": numpy; "device": torch uint8 CUDA tensor; None: not
     written), their offsets (4 per region + 1) and the events with offsets."""
@@ -412,7 +413,8 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
         p.cost = cost_arr.ctypes.data
     p.evolve = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
                             float(cell_size), int(steps_per_sync), int(bool(use_graph)),
-                            float(cand_per_point), float(events_per_point), -1, int(screen_split))
+                            float(cand_per_point), float(events_per_point), int(timed_kernel),
+                            int(screen_split))
     total = int(rs.counts.sum())
     out_off = np.zeros(4 * nr + 1, dtype=np.int64)
     res = {}

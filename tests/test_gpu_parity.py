@@ -334,26 +334,43 @@ def test_bounded_empty_region(S):
     assert st["steps"] == 0 and sum(len(f) for f in faces) == 0 and len(ge) == 0
 
 
-def test_region_batch_equals_separate_regions(S):
+_batch_oracle = {}
+
+
+BATCH_SIZES = {"big": [0, 300, 5000, 1200, 0, 20000, 800, 2500, 40, 9000],
+               "small": [0, 300, 1200, 40, 800]}
+
+
+@pytest.mark.parametrize("which,cell,screen", [("big", 0.0, 0), ("big", 0.0, 1),
+                                               ("small", 1e-6, 1), ("small", 0.9, 0),
+                                               ("big", 0.05, 1)])
+def test_region_batch_equals_separate_regions(S, which, cell, screen):
     """A batch of independent regions evolved in one set of launches gives exactly the
-    union of the regions' separate results (oracle, one region at a time)."""
-    sizes = [0, 300, 5000, 1200, 0, 20000, 800, 2500, 40, 9000]
-    say(f"case: batch of {len(sizes)} regions, sizes {sizes}")
+    union of the regions' separate results (oracle, one region at a time), with each
+    region's own adaptive grid or a fixed cell size (tiny: elements go to the
+    large-element path; coarse: many elements per cell)."""
+    sizes = BATCH_SIZES[which]
+    say(f"case: batch of {len(sizes)} regions, sizes {sizes}, cell {cell}, screen {screen}")
     parts, box = I.region_batch(sizes, seed=100)
     r = S.Region.batch(parts, box, I.MATTER)
-    st = r.evolve(100000)
+    st = r.evolve(100000, cell_size=cell, screen=screen, use_graph=cell > 0)
     faces, ge = r.emit_faces(), r.events()
     r.close()
-    recs, evs, psteps, steps = [], [], 0, 0
-    for recs_i, geom in parts:
-        if len(recs_i) == 0:
-            continue
-        net = dict(recs=recs_i, box=box, cosmology=I.MATTER, geom=geom)
-        o, oe, ost = run_oracle(net, 100000)
-        recs.append(o)
-        evs.append(oe)
-        psteps += ost["point_steps"]
-        steps = max(steps, ost["steps"])
+    if which not in _batch_oracle:
+        recs, evs, psteps, steps = [], [], 0, 0
+        for recs_i, geom in parts:
+            if len(recs_i) == 0:
+                continue
+            net = dict(recs=recs_i, box=box, cosmology=I.MATTER, geom=geom)
+            o, oe, ost = run_oracle(net, 100000)
+            recs.append(o)
+            evs.append(oe)
+            psteps += ost["point_steps"]
+            steps = max(steps, ost["steps"])
+        _batch_oracle[which] = dict(recs=recs, evs=evs, psteps=psteps, steps=steps)
+    cached = _batch_oracle[which]
+    recs, evs = cached["recs"], cached["evs"]
+    psteps, steps = cached["psteps"], cached["steps"]
     oe = np.concatenate(evs)
     oe = oe[np.lexsort((oe["id_b"], oe["id_a"], oe["t_star"], oe["step"]))]
     assert st["point_steps"] == psteps and st["steps"] == steps
