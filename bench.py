@@ -99,7 +99,7 @@ def bench_batched(args):
 
     feat = S.region_features(rs)
     pred = cm.predict(feat)
-    cfg = {"batch_frac": args.batch_frac, "screen_split": 7, "steps_per_sync": 64}
+    cfg = {"batch_frac": args.batch_frac, "screen_split": 1, "steps_per_sync": 32}
     if args.tune:
         cfg = SC.autotune(rs, pred, screen=screen, cache=args.tune_cache or None, log=log)
         log(f"autotune: {cfg}")
@@ -181,6 +181,7 @@ def bench_batched(args):
 
     cpu = None
     if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a sample of the regions")
         cpu = cpu_baseline_regions(parts, box)
     return {
         "value": value, "ms_per_step": elapsed * 1e3 / args.steps,
@@ -197,25 +198,31 @@ def bench_batched(args):
     }
 
 
-def cpu_baseline_regions(parts, box):
-    """The oracle on a sample of the same regions: every 25th non-empty region."""
+def cpu_baseline_regions(parts, box, steps=40, budget_s=20.0):
+    """The oracle on a bounded sample of the same regions: every 25th non-empty region,
+    each for its first `steps` lattice steps, until `budget_s` seconds are used."""
     import numpy as np
     import oracle as O
     from paper_1011_4046_amd import inputs as I
     live = [i for i, p in enumerate(parts) if len(p[0])]
     sample = live[::25]
     t = time.perf_counter()
-    ps = 0
+    ps, used = 0, []
     for i in sample:
         recs, geom = parts[i]
         net = dict(recs=recs, box=box, cosmology=I.MATTER, geom=geom)
-        _, _, ost = O.run(net, 10 ** 7)
+        _, _, ost = O.run(net, steps)
         ps += ost["point_steps"]
+        used.append(i)
+        log(f"cpu baseline: region {i} ({len(recs)} points), {time.perf_counter() - t:.1f} s")
+        if time.perf_counter() - t > budget_s:
+            break
     tc = time.perf_counter() - t
-    npts = int(np.sum([len(parts[i][0]) for i in sample]))
+    npts = int(np.sum([len(parts[i][0]) for i in used]))
     return {"value": ps / tc, "unit": "point-steps/s", "cores": O.threads(), "kind": "oracle",
-            "sample": f"{len(sample)} of the {len(live)} non-empty regions (every 25th, "
-                      f"{npts} points, {ps} point-steps, {tc:.1f} s), each run to completion"}
+            "sample": f"{len(used)} of the {len(live)} non-empty regions (every 25th, {npts} "
+                      f"points), first {steps} lattice steps of each: {ps} point-steps in "
+                      f"{tc:.1f} s"}
 
 
 def bench_vv32(args):
@@ -289,7 +296,7 @@ def main():
     ap.add_argument("--workers", type=int, default=8, help="processes generating the inputs")
     ap.add_argument("--batch-frac", type=float, default=1.0,
                     help="batch size as a fraction of all points (1 = one batch)")
-    ap.add_argument("--tune", type=int, default=0, help="run the autotuner first")
+    ap.add_argument("--tune", type=int, default=1, help="run the autotuner first")
     ap.add_argument("--tune-cache", default="")
     ap.add_argument("--plain", type=int, default=1, help="also time the plain per-region path")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -178,8 +178,9 @@ typedef struct semipar_evolve_params {
                              around every launch of that kernel and the summed device
                              time is returned in the stats (measurement only; a timed
                              call issues its steps without graphs) */
-  int32_t screen_split;   /* threads sharing the 14 cell lookups of one element in the
-                             screen: 1, 2, 7 or 14 (0 = 7). Performance only */
+  int32_t screen_split;   /* threads sharing the 5 neighbour-pencil lookups of one
+                             element in the screen: 1 or 5 (any other value = 5).
+                             Performance only */
 } semipar_evolve_params;
 
 /* kernels that can be timed through semipar_evolve_params.timed_kernel */

@@ -25,9 +25,10 @@ SP_HIDDEN int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<
 SP_HIDDEN int batch_stats(semipar_region* r, std::vector<int32_t>& steps,
                           std::vector<int64_t>& psteps);
 
-// Logged events (listing order within each sub-region) and the sub-region of each.
+// Logged events grouped by sub-region (sub-region q's at off[q] .. off[q+1]), each
+// group in listing order (step, t*, id_a, id_b).
 SP_HIDDEN int batch_events(semipar_region* r, std::vector<semipar_event>& ev,
-                           std::vector<int32_t>& sub);
+                           std::vector<int64_t>& off);
 
 // The 12 cost-model features of each sub-region's current surface (host, 12 n_sub).
 SP_HIDDEN int batch_features(semipar_region* r, float* feat);

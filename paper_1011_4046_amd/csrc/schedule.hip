@@ -194,9 +194,10 @@ struct Runner {
     }
     if (rc == SEMIPAR_OK && p->events) {
       std::vector<semipar_event> e;
-      std::vector<int32_t> sub;
-      rc = spi::batch_events(reg, e, sub);
-      for (size_t i = 0; i < e.size() && rc == SEMIPAR_OK; ++i) ev[regs[sub[i]]].push_back(e[i]);
+      std::vector<int64_t> off;
+      rc = spi::batch_events(reg, e, off);
+      for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i)
+        ev[regs[i]].assign(e.begin() + off[i], e.begin() + off[i + 1]);
     }
     std::vector<int32_t> steps;
     std::vector<int64_t> ps;
@@ -310,15 +311,13 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
   // event lists, region by region
   int64_t ne = 0;
   for (int r = 0; r < nr; ++r) {
+    const int64_t m = (int64_t)R.ev[r].size();
     if (p->events) {
       p->events_off[r] = ne;
-      for (const semipar_event& e : R.ev[r]) {
-        if (ne < p->events_cap) p->events[ne] = e;
-        ++ne;
-      }
-    } else {
-      ne += (int64_t)R.ev[r].size();
+      const int64_t fit = std::max<int64_t>(0, std::min(m, p->events_cap - ne));
+      if (fit > 0) memcpy(p->events + ne, R.ev[r].data(), sizeof(semipar_event) * fit);
     }
+    ne += m;
   }
   if (p->events) p->events_off[nr] = ne;
   R.acc.events = ne;

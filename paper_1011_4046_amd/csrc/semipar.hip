@@ -18,6 +18,7 @@
 // A device control block carries the step index, the stop rule and the counters,
 // so a block of steps can be issued (or graph-replayed) without host round trips.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <new>
@@ -201,11 +202,24 @@ __device__ __forceinline__ uint32_t pack_cell(int x, int y, int z) {
   return (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
 }
 
-// Bucket of a cell: its row-major index modulo the (power-of-two) bucket count. Cells
-// adjacent in z map to adjacent buckets, so the lists a wave reads are close in memory;
-// when nc^3 <= buckets every cell has a bucket of its own.
+// Linear index of a cell: the (x, y) plane is cut into 4 x 4 tiles of z-rows; tiles are
+// row-major, the 16 rows of a tile follow each other, z is fastest. Cells adjacent in z
+// are adjacent in the index (a neighbour pencil z-1..z+1 is one run of buckets), and the
+// rows that a tile's elements visit as neighbours mostly lie in the same tile, so they
+// are read while still in L2.
+__device__ __forceinline__ uint32_t cell_index(int nc, int x, int y, int z) {
+  const int nt = (nc + 3) >> 2;
+  return (uint32_t)(((((x >> 2) * nt + (y >> 2)) << 4) + (((x & 3) << 2) | (y & 3))) * nc + z);
+}
+__host__ __device__ __forceinline__ uint64_t cell_count(int nc) {
+  const uint64_t nt = (uint64_t)((nc + 3) >> 2);
+  return nt * nt * 16 * (uint64_t)nc;
+}
+
+// Bucket of a cell: its index modulo the (power-of-two) bucket count; when the grid has
+// no more cells than buckets every cell has a bucket of its own.
 __device__ __forceinline__ uint32_t bucket_of(int nc, uint32_t bmask, int x, int y, int z) {
-  return (uint32_t)((x * nc + y) * nc + z) & bmask;
+  return cell_index(nc, x, y, z) & bmask;
 }
 
 // Exclusive scan of the tile totals into LDS: s_toff[t] = first sorted position of
@@ -445,7 +459,7 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
                                  __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
             }
             const uint32_t bk =
-                local ? (C.base + (uint32_t)((ci[0] * C.nc + ci[1]) * C.nc + ci[2])) & hc.bmask
+                local ? (C.base + cell_index(C.nc, ci[0], ci[1], ci[2])) & hc.bmask
                       : bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
             epos[k] = atomicAdd(&cnt[bk], 1);
             ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
@@ -585,7 +599,7 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
   int32_t key = c;
   if (rcell) {
     const RCell C = rcell[rid[k]];
-    b = (C.base + (uint32_t)((x * C.nc + y) * C.nc + z)) & hc.bmask;
+    b = (C.base + cell_index(C.nc, x, y, z)) & hc.bmask;
     key = (int32_t)((uint32_t)c ^ C.salt);
   } else {
     b = bucket_of(nc, hc.bmask, x, y, z);
@@ -664,13 +678,23 @@ __device__ __forceinline__ int xcd_block(int total) {
 }
 inline int xcd_grid(int total) { return (total + N_XCD - 1) / N_XCD * N_XCD; }
 
-// Half-shell screen over the cell-sorted elements. The element at sorted position q is
-// tested against the later entries of its own cell (slice 0) and every entry of the 13
-// forward neighbour cells (slices 1..13). G threads share an element, each taking the
-// slices [g*14/G, (g+1)*14/G); thread g = 0 also tests the element against every large
-// element (two large ones: by the one of smaller slot). Threads past the hashed
-// elements take one large element each. Each unordered pair is tested exactly once.
-// Logical block = (element block, g), renumbered per XCD (xcd_block).
+// Half-shell screen over the cell-sorted elements, by z-pencils. The element at sorted
+// position q (cell (x, y, z)) is tested against
+//   pencil 0: the later entries of its own cell and every entry of cell (x, y, z+1);
+//   pencils 1..4: every entry of the cells (x', y', z-1 .. z+1) for
+//                 (x', y') = (x, y+1), (x+1, y-1), (x+1, y), (x+1, y+1),
+// i.e. the 14 cells of the forward half shell. Buckets are row-major in the cell index
+// with z fastest, so a pencil's cells are consecutive buckets and one range of the
+// sorted entries: 5 range lookups per element instead of 14. Where a pencil's buckets
+// are not consecutive (periodic wrap in z, end of the bucket table) its cells are
+// looked up one by one. Entries of other cells sharing a bucket are skipped by key.
+// G threads share an element (G = 1: all pencils; G = 5: one pencil each); thread
+// g = 0 also tests the element against every large element (two large ones: by the
+// one of smaller slot). Threads past the hashed elements take one large element each.
+// Each unordered pair is tested exactly once. Logical block = (element block, g),
+// renumbered per XCD (xcd_block).
+constexpr int N_PENCIL = 5;
+
 template <int SCR, int G>
 __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ sent,
                                                const void* __restrict__ sbox,
@@ -683,11 +707,11 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
                                                int nblk, Ctrl* ctrl,
                                                const int32_t* __restrict__ rid,
                                                const RCell* __restrict__ rcell) {
+  static_assert(G == 1 || G == N_PENCIL, "one or five threads per element");
   if (ctrl->done) return;
   const int lid = xcd_block(nblk * G);
   if (lid >= nblk * G) return;
   const int eblk = lid / G, g = lid % G;
-  const int o_beg = g * 14 / G, o_end = (g + 1) * 14 / G;
   using T = typename std::conditional<SCR == 1, double, float>::type;
   __shared__ int2 sbuf[SBUF];
   __shared__ int s_cnt, s_base;
@@ -716,7 +740,8 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
       RCell C{};
       uint32_t salt = 0;
       int gnc = cs.nc;
-      if (rcell) {
+      const bool local = rcell != nullptr;
+      if (local) {
         C = rcell[rid[k]];
         salt = C.salt;
         gnc = C.nc;
@@ -725,42 +750,129 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
       const int nk = nxt[k], pk = prv[k];
       const SBox<T> me = load_sbox<T>(sbox, q);
       const int cx = c & 1023, cy = (c >> 10) & 1023, cz = (c >> 20) & 1023;
-      constexpr int MAXS = (14 + G - 1) / G;
-      int rb[MAXS], re[MAXS], rc[MAXS];
+      const T tl = SCR == 1 ? (T)hc.tol : (T)(local ? C.marg32 : cs.marg32);
+      const T hh = SCR == 1 ? (T)(local ? C.h : cs.h) : (T)(local ? C.h32 : cs.h32);
+      auto bucket = [&](int x, int y, int z) -> uint32_t {
+        return local ? (C.base + cell_index(gnc, x, y, z)) & hc.bmask
+                     : bucket_of(gnc, hc.bmask, x, y, z);
+      };
+      auto wrapc = [&](int v) { return v < 0 ? v + gnc : (v >= gnc ? v - gnc : v); };
+      // test the entries [beg, end) whose key is that of the pencil cell z + dz for a
+      // dz in {-1, 0, 1} with valid bit set (kv[dz + 1])
+      auto scan = [&](int beg, int end, const int32_t (&kk)[3], const bool (&kv)[3], int dx,
+                      int dy) {
+        const T sx = (T)dx * hh, sy = (T)dy * hh;
+        auto test = [&](const int2 e, const SBox<T>& b) {
+          int dz = 2;
 #pragma unroll
-      for (int i = 0; i < MAXS; ++i) {
-        const int o = o_beg + i;
-        rb[i] = 0;
-        re[i] = 0;
-        rc[i] = 0;
-        if (o < o_end) {
-          const int dx = o == 0 ? 0 : (o < 10 ? 1 : 0);
-          const int dy = o == 0 ? 0 : (o < 10 ? (o - 1) / 3 - 1 : (o < 13 ? 1 : 0));
-          const int dz = o == 0 ? 0 : (o < 10 ? (o - 1) % 3 - 1 : (o < 13 ? o - 11 : 1));
-          int x = cx + dx, y = cy + dy, z = cz + dz;
-          if (rcell) {
-            // local grid: no periodic wrap; nothing lies outside
-            if (x < 0 || y < 0 || z < 0 || x >= gnc || y >= gnc || z >= gnc) continue;
-            const uint32_t b = (C.base + (uint32_t)((x * gnc + y) * gnc + z)) & hc.bmask;
-            rb[i] = o == 0 ? q + 1 : bucket_start(loc, toff, b);
-            re[i] = bucket_start(loc, toff, b + 1);
-            rc[i] = (int32_t)(pack_cell(x, y, z) ^ salt);
+          for (int u = 0; u < 3; ++u)
+            if (kv[u] && e.x == kk[u]) dz = u - 1;
+          const int m = e.y;
+          if (dz != 2 && m != nk && m != pk && box_overlap(me, b, sx, sy, (T)dz * hh, tl))
+            push(k, m);
+        };
+        int q2 = beg;
+        // four entries at a time: independent loads in flight together
+        for (; q2 + 4 <= end; q2 += 4) {
+          int2 e4[4];
+          SBox<T> b4[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            e4[v] = sent[q2 + v];
+            b4[v] = load_sbox<T>(sbox, q2 + v);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) test(e4[v], b4[v]);
+        }
+        for (; q2 < end; ++q2) test(sent[q2], load_sbox<T>(sbox, q2));
+      };
+      // phase 1: every pencil's cells, keys and the bounds of their entry ranges (all
+      // bucket-offset loads issued before any range is scanned)
+      constexpr int NPT = (N_PENCIL + G - 1) / G;  // pencils per thread
+      bool kv[NPT][3];
+      int32_t kk[NPT][3];
+      int rb[NPT][3], re[NPT][3];
+      bool one[NPT];
+#pragma unroll
+      for (int pi = 0; pi < NPT; ++pi) {
+        const int p = g + pi * G;
+        one[pi] = true;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          kv[pi][u] = false;
+          kk[pi][u] = 0;
+          rb[pi][u] = 0;
+          re[pi][u] = 0;
+        }
+        if (p >= N_PENCIL) continue;
+        const int dx = p == 0 ? 0 : (p == 1 ? 0 : 1);
+        const int dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
+        int x = cx + dx, y = cy + dy;
+        if (local) {
+          if (x >= gnc || y < 0 || y >= gnc) continue;
+        } else {
+          x = wrapc(x);
+          y = wrapc(y);
+        }
+        // the pencil's cells z + dz: dz = 0, 1 (pencil 0, own cell from q + 1) or -1, 0, 1
+        uint32_t bk[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int dz = u - 1;
+          int z = cz + dz;
+          bool v = !(p == 0 && dz < 0);
+          if (local) {
+            v = v && z >= 0 && z < gnc;
           } else {
-            x = x < 0 ? x + gnc : (x >= gnc ? x - gnc : x);
-            y = y < 0 ? y + gnc : (y >= gnc ? y - gnc : y);
-            z = z < 0 ? z + gnc : (z >= gnc ? z - gnc : z);
-            const uint32_t b = bucket_of(gnc, hc.bmask, x, y, z);
-            rb[i] = o == 0 ? q + 1 : bucket_start(loc, toff, b);
-            re[i] = bucket_start(loc, toff, b + 1);
-            rc[i] = (int)pack_cell(x, y, z);
+            z = wrapc(z);
+          }
+          kv[pi][u] = v;
+          bk[u] = bucket(x, y, z);
+          kk[pi][u] = local ? (int32_t)(pack_cell(x, y, z) ^ salt) : (int32_t)pack_cell(x, y, z);
+        }
+        // one range when the valid cells' buckets are consecutive
+        const int first = kv[pi][0] ? 0 : 1;  // cz itself is always valid
+        const int last = kv[pi][2] ? 2 : 1;
+        bool consec = true;
+        if (first == 0) consec = consec && bk[1] == bk[0] + 1;
+        if (last == 2) consec = consec && bk[2] == bk[1] + 1;
+        one[pi] = consec;
+        if (consec) {
+          rb[pi][0] = (p == 0) ? q + 1 : bucket_start(loc, toff, first == 0 ? bk[0] : bk[1]);
+          re[pi][0] = bucket_start(loc, toff, (last == 2 ? bk[2] : bk[1]) + 1);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+            if (kv[pi][u]) {
+              rb[pi][u] = (p == 0 && u == 1) ? q + 1 : bucket_start(loc, toff, bk[u]);
+              re[pi][u] = bucket_start(loc, toff, bk[u] + 1);
+            }
+        }
+      }
+      // phase 2: the scans
+#pragma unroll
+      for (int pi = 0; pi < NPT; ++pi) {
+        const int p = g + pi * G;
+        if (p >= N_PENCIL) continue;
+        const int dx = p == 0 ? 0 : (p == 1 ? 0 : 1);
+        const int dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
+        if (one[pi]) {
+          scan(rb[pi][0], re[pi][0], kk[pi], kv[pi], dx, dy);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            if (!kv[pi][u]) continue;
+            const bool only[3] = {u == 0, u == 1, u == 2};
+            scan(rb[pi][u], re[pi][u], kk[pi], only, dx, dy);
           }
         }
       }
       if (g == 0) {
         // the element's box in global coordinates (any periodic image) for the
         // comparisons with large elements
-        const double gh = rcell ? C.h : cs.h;
-        const double go[3] = {rcell ? C.ox : 0.0, rcell ? C.oy : 0.0, rcell ? C.oz : 0.0};
+        const double gh = local ? C.h : cs.h;
+        const double go[3] = {local ? C.ox : 0.0, local ? C.oy : 0.0, local ? C.oz : 0.0};
+#pragma unroll
         for (int i = 0; i < 3; ++i) {
           wl[i] = go[i] + ((double)(i == 0 ? cx : (i == 1 ? cy : cz)) * gh + (double)me.v[i]);
           ex[i] = (double)me.v[4 + i] - (double)me.v[i];
@@ -773,46 +885,11 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
           thi = (double)me.v[7] + hc.tref;
         }
       }
-      const T tl = SCR == 1 ? (T)hc.tol : (T)(rcell ? C.marg32 : cs.marg32);
-      const T hh = SCR == 1 ? (T)(rcell ? C.h : cs.h) : (T)(rcell ? C.h32 : cs.h32);
-#pragma unroll
-      for (int i = 0; i < MAXS; ++i) {
-        const int o = o_beg + i;
-        if (o >= o_end || rb[i] >= re[i]) continue;
-        const int dx = o == 0 ? 0 : (o < 10 ? 1 : 0);
-        const int dy = o == 0 ? 0 : (o < 10 ? (o - 1) / 3 - 1 : (o < 13 ? 1 : 0));
-        const int dz = o == 0 ? 0 : (o < 10 ? (o - 1) % 3 - 1 : (o < 13 ? o - 11 : 1));
-        const int32_t pc = rc[i];
-        const T sx = (T)dx * hh, sy = (T)dy * hh, sz = (T)dz * hh;
-        const int end = re[i];
-        int q2 = rb[i];
-        for (; q2 + 4 <= end; q2 += 4) {
-          int32_t c4[4], m4[4];
-          SBox<T> b4[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int2 e = sent[q2 + u];
-            c4[u] = e.x;
-            m4[u] = e.y;
-            b4[u] = load_sbox<T>(sbox, q2 + u);
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (c4[u] == pc && m4[u] != nk && m4[u] != pk && box_overlap(me, b4[u], sx, sy, sz, tl))
-              push(k, m4[u]);
-        }
-        for (; q2 < end; ++q2) {
-          const int2 e = sent[q2];
-          if (e.x != pc) continue;
-          const int m = e.y;
-          if (m == nk || m == pk) continue;
-          if (box_overlap(me, load_sbox<T>(sbox, q2), sx, sy, sz, tl)) push(k, m);
-        }
-      }
     } else {
       own_large = true;
       const LargeBox own = large[q - n_norm];
       k = own.slot;
+#pragma unroll
       for (int i = 0; i < 3; ++i) {
         wl[i] = own.wl[i];
         ex[i] = own.ext[i];
@@ -830,8 +907,9 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
         if (m == nk || m == pk) continue;
         const double tt = hc.tol_t;
         bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
-        for (int i = 0; i < 3 && ov; ++i)
-          ov = wrap_overlap(wl[i], ex[i], lb.wl[i], lb.ext[i], P, hc.tolL);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          ov = ov && wrap_overlap(wl[i], ex[i], lb.wl[i], lb.ext[i], P, hc.tolL);
         if (ov) push(k, m);
       }
     }
@@ -1210,7 +1288,7 @@ __global__ __launch_bounds__(1024) void k_rcells(const RegionGeom* __restrict__ 
     C.oz = geoms[q].V[2] - 0.5 * W;
     C.salt = (uint32_t)q * 0x9E3779B1u;
     rc[q] = C;
-    sum += (uint64_t)nc * nc * nc;
+    sum += cell_count(nc);
   }
   s_sum[t] = sum;
   __syncthreads();
@@ -1225,8 +1303,7 @@ __global__ __launch_bounds__(1024) void k_rcells(const RegionGeom* __restrict__ 
     const int q = t * per + i;
     if (q >= n_sub) break;
     rc[q].base = (uint32_t)run;
-    const int nc = rc[q].nc;
-    run += (uint64_t)nc * nc * nc;
+    run += cell_count(rc[q].nc);
   }
 }
 
@@ -1662,6 +1739,45 @@ __global__ __launch_bounds__(256) void k_feat_final(const int32_t* __restrict__ 
   }
 }
 
+// ---- event log of a batch: order (sub-region, step, t*, id_a, id_b) ---------------
+__global__ __launch_bounds__(NT) void k_iota(int32_t* __restrict__ idx, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i < n) idx[i] = (int32_t)i;
+}
+
+// Sort key of pass `pass` for the events in the current order idx (least significant
+// first: id_b, id_a, t*, then sub-region and step).
+__global__ __launch_bounds__(NT) void k_ev_keys(const semipar_event* __restrict__ log,
+                                                const int32_t* __restrict__ lrid,
+                                                const int32_t* __restrict__ idx, int64_t n,
+                                                int pass, uint64_t* __restrict__ keys) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= n) return;
+  const int32_t e = idx[i];
+  uint64_t k;
+  if (pass == 0)
+    k = (uint64_t)log[e].id_b;
+  else if (pass == 1)
+    k = (uint64_t)log[e].id_a;
+  else if (pass == 2)
+    k = order_key(log[e].t_star);
+  else
+    k = ((uint64_t)(uint32_t)lrid[e] << 32) | (uint32_t)log[e].step;
+  keys[i] = k;
+}
+
+__global__ __launch_bounds__(NT) void k_ev_gather(const semipar_event* __restrict__ log,
+                                                  const int32_t* __restrict__ lrid,
+                                                  const int32_t* __restrict__ idx, int64_t n,
+                                                  semipar_event* __restrict__ out,
+                                                  int32_t* __restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= n) return;
+  const int32_t e = idx[i];
+  out[i] = log[e];
+  atomicAdd(&cnt[lrid[e]], 1);
+}
+
 // ---------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------
@@ -1752,7 +1868,7 @@ struct semipar_region {
   int g_steps = 0;
   int g_timed = -1;
   bool cells_set = false;  // the device grid has been chosen (adaptive runs keep it)
-  int split = 7;           // screen threads per element (1, 2, 7 or 14)
+  int split = N_PENCIL;    // screen threads per element (1 or 5)
   bool cells_fixed = false;
   // measurement: HIP events around every launch of one kernel (timed_kernel)
   int timed = -1;
@@ -1959,21 +2075,15 @@ void launch_screen_t(semipar_region* r, int n, int nb) {
       r->cand, (int)r->cap_cand, nb, r->ctrl, r->rid, r->rcell);
 }
 
-// Screen launch: precision (FP64 / FP32 boxes) and threads per element (split).
+// Screen launch: precision (FP64 / FP32 boxes) and threads per element (1 or 5).
 void launch_screen(semipar_region* r, int n, int nb) {
-  const int g = r->split;
+  const bool one = r->split == 1;
   if (r->screen == 1) {
-    if (g == 1) launch_screen_t<1, 1>(r, n, nb);
-    else if (g == 7) launch_screen_t<1, 7>(r, n, nb);
-    else if (g == 14) launch_screen_t<1, 14>(r, n, nb);
-    else if (g == 2) launch_screen_t<1, 2>(r, n, nb);
-    else launch_screen_t<1, 7>(r, n, nb);
+    if (one) launch_screen_t<1, 1>(r, n, nb);
+    else launch_screen_t<1, N_PENCIL>(r, n, nb);
   } else {
-    if (g == 1) launch_screen_t<2, 1>(r, n, nb);
-    else if (g == 7) launch_screen_t<2, 7>(r, n, nb);
-    else if (g == 14) launch_screen_t<2, 14>(r, n, nb);
-    else if (g == 2) launch_screen_t<2, 2>(r, n, nb);
-    else launch_screen_t<2, 7>(r, n, nb);
+    if (one) launch_screen_t<2, 1>(r, n, nb);
+    else launch_screen_t<2, N_PENCIL>(r, n, nb);
   }
 }
 
@@ -2282,7 +2392,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   const int K = p->steps_per_sync > 0 ? p->steps_per_sync : 32;
   {
     const int sp_ = p->screen_split;
-    const int split = (sp_ == 1 || sp_ == 2 || sp_ == 7 || sp_ == 14) ? sp_ : 7;
+    const int split = sp_ == 1 ? 1 : N_PENCIL;
     if (split != r->split) drop_graph(r);
     r->split = split;
   }
@@ -2594,37 +2704,70 @@ int batch_stats(semipar_region* r, std::vector<int32_t>& steps, std::vector<int6
   return rc;
 }
 
-int batch_events(semipar_region* r, std::vector<semipar_event>& ev, std::vector<int32_t>& sub) {
+int batch_events(semipar_region* r, std::vector<semipar_event>& ev, std::vector<int64_t>& off) {
   if (!r || r->n_sub <= 0 || !r->rid) return SEMIPAR_E_ARG;
+  const int ns = r->n_sub;
   ev.clear();
-  sub.clear();
+  off.assign((size_t)ns + 1, 0);
   RCCHK(read_ctrl(r));
   const int64_t total = r->ctrl_h->log_n;
   if (total == 0) return SEMIPAR_OK;
-  std::vector<semipar_event> all((size_t)total);
-  std::vector<int32_t> rq((size_t)total);
-  HIPCHK(hipMemcpyAsync(all.data(), r->log, sizeof(semipar_event) * total, hipMemcpyDeviceToHost,
-                        r->stream));
-  HIPCHK(hipMemcpyAsync(rq.data(), r->log_rid, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
-                        r->stream));
-  HIPCHK(hipStreamSynchronize(r->stream));
-  std::vector<int64_t> ord((size_t)total);
-  for (int64_t i = 0; i < total; ++i) ord[i] = i;
-  std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
-    const semipar_event &a = all[x], &b = all[y];
-    if (rq[x] != rq[y]) return rq[x] < rq[y];
-    if (a.step != b.step) return a.step < b.step;
-    if (a.t_star != b.t_star) return a.t_star < b.t_star;
-    if (a.id_a != b.id_a) return a.id_a < b.id_a;
-    return a.id_b < b.id_b;
-  });
-  ev.resize((size_t)total);
-  sub.resize((size_t)total);
-  for (int64_t i = 0; i < total; ++i) {
-    ev[i] = all[ord[i]];
-    sub[i] = rq[ord[i]];
+  if (total >= INT32_MAX) return SEMIPAR_E_OVERFLOW;
+  // LSD radix sorts (stable) on the device: id_b, id_a, t*, then (sub-region, step)
+  const int n = (int)total;
+  int32_t *ia = nullptr, *ib = nullptr, *cnt = nullptr;
+  uint64_t *ka = nullptr, *kb = nullptr;
+  semipar_event* sorted = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  int rc = SEMIPAR_OK;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, ka, kb, ia, ib, n, 0, 64,
+                                         r->stream) != hipSuccess)
+    rc = SEMIPAR_E_HIP;
+  if (rc == SEMIPAR_OK &&
+      (dalloc(&ia, total) != hipSuccess || dalloc(&ib, total) != hipSuccess ||
+       dalloc(&ka, total) != hipSuccess || dalloc(&kb, total) != hipSuccess ||
+       dalloc(&sorted, total) != hipSuccess || dalloc(&cnt, ns) != hipSuccess ||
+       hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)) != hipSuccess))
+    rc = SEMIPAR_E_OOM;
+  std::vector<int32_t> hc((size_t)ns, 0);
+  if (rc == SEMIPAR_OK) {
+    const int nb = blocks(total);
+    k_iota<<<nb, NT, 0, r->stream>>>(ia, total);
+    for (int pass = 0; pass < 4 && rc == SEMIPAR_OK; ++pass) {
+      k_ev_keys<<<nb, NT, 0, r->stream>>>(r->log, r->log_rid, ia, total, pass, ka);
+      const int end_bit = pass == 2 ? 64 : (pass == 3 ? 64 : 63);
+      size_t tb = tmp_bytes;
+      if (hipcub::DeviceRadixSort::SortPairs(tmp, tb, ka, kb, ia, ib, n, 0, end_bit,
+                                             r->stream) != hipSuccess)
+        rc = SEMIPAR_E_HIP;
+      std::swap(ia, ib);
+    }
+    if (rc == SEMIPAR_OK &&
+        hipMemsetAsync(cnt, 0, sizeof(int32_t) * ns, r->stream) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
+    if (rc == SEMIPAR_OK) {
+      k_ev_gather<<<nb, NT, 0, r->stream>>>(r->log, r->log_rid, ia, total, sorted, cnt);
+      ev.resize((size_t)total);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(ev.data(), sorted, sizeof(semipar_event) * total, hipMemcpyDeviceToHost,
+                         r->stream) != hipSuccess ||
+          hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * ns, hipMemcpyDeviceToHost,
+                         r->stream) != hipSuccess ||
+          hipStreamSynchronize(r->stream) != hipSuccess)
+        rc = SEMIPAR_E_HIP;
+    }
   }
-  return SEMIPAR_OK;
+  for (int q = 0; q < ns; ++q) off[q + 1] = off[q] + hc[q];
+  dfree(ia);
+  dfree(ib);
+  dfree(ka);
+  dfree(kb);
+  dfree(sorted);
+  dfree(cnt);
+  dfree(tmp);
+  if (rc != SEMIPAR_OK) ev.clear();
+  return rc;
 }
 
 int batch_features(semipar_region* r, float* feat) {

@@ -76,7 +76,7 @@ def learned_schedule(rs, cost_model, **kw):
 
 TUNABLE = {
     "batch_frac": [1.0, 0.5, 0.25, 0.125],  # batch_points as a fraction of all points
-    "screen_split": [7, 14, 2],
+    "screen_split": [5, 1],
     "steps_per_sync": [64, 32, 128],
 }
 
@@ -87,24 +87,11 @@ def workload_key(rs, screen):
             f"m{int(np.log2(max(int(np.median(n)) if len(n) else 1, 1)))}-c{rs.cosmology}-s{screen}")
 
 
-def _sample(rs, every):
-    """Every `every`-th region of rs as a new RegionSet (host copy of its records)."""
-    idx = np.arange(0, rs.n_regions, every)
-    recs = rs.recs
-    if not isinstance(recs, np.ndarray):
-        recs = recs.cpu().numpy().view(S.REC_DTYPE)
-    parts = []
-    for r in idx:
-        a, b = int(rs.offsets[r]), int(rs.offsets[r + 1])
-        g = rs.geoms[r]
-        geom = list(g.origin) + [g.inv2g] + list(g.idx)
-        parts.append((recs[a:b], np.asarray(geom)))
-    return S.RegionSet.from_parts(parts, rs.box, rs.cosmology, device=True), idx
-
-
-def autotune(rs, cost=None, screen=S.SCREEN_F32, cache=None, every=4, log=None):
-    """Coordinate search over TUNABLE on every `every`-th region, timing one batched
-    schedule per candidate (makespan). Returns the parameter dict; with `cache` (a JSON
+def autotune(rs, cost=None, screen=S.SCREEN_F32, cache=None, max_steps=96, log=None):
+    """Coordinate search over TUNABLE, timing one batched schedule of all regions per
+    candidate, each batch cut after max_steps lattice steps (the per-step costs, not the
+    tails, decide launch shapes; a batch size that splits regions of different length
+    shows its cost as more batches). Returns the parameter dict; with `cache` (a JSON
     path) a previous choice for the same workload key is reused."""
     key = workload_key(rs, screen)
     if cache and os.path.exists(cache):
@@ -112,18 +99,18 @@ def autotune(rs, cost=None, screen=S.SCREEN_F32, cache=None, every=4, log=None):
             got = json.load(f).get(key)
         if got:
             return dict(got, cached=True)
-    sub, idx = _sample(rs, every)
-    sub_cost = None if cost is None else np.asarray(cost, np.float32)[idx]
-    total = int(sub.counts.sum())
+    total = int(rs.counts.sum())
     best = {k: v[0] for k, v in TUNABLE.items()}
 
     def run(cfg):
         bp = int(total * cfg["batch_frac"]) if cfg["batch_frac"] < 1.0 else 0
-        res = S.schedule_regions(sub, S.SCHED_BATCHED, batch_points=bp, cost=sub_cost,
+        res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=cost,
                                  out=None, events=False, use_graph=True, screen=screen,
                                  screen_split=cfg["screen_split"],
-                                 steps_per_sync=cfg["steps_per_sync"])
-        return res["stats"]["makespan_ms"]
+                                 steps_per_sync=cfg["steps_per_sync"], max_steps=max_steps)
+        st = res["stats"]
+        # time per point-step of the truncated schedule
+        return st["makespan_ms"] / max(st["point_steps"], 1) * 1e6
 
     run(best)  # warm-up (graph instantiation, allocator)
     best_ms = run(best)
@@ -132,10 +119,10 @@ def autotune(rs, cost=None, screen=S.SCREEN_F32, cache=None, every=4, log=None):
             cfg = dict(best, **{k: v})
             ms = run(cfg)
             if log:
-                log(f"autotune {key}: {cfg} -> {ms:.1f} ms")
+                log(f"autotune {key}: {cfg} -> {ms:.3f} ns per point-step")
             if ms < best_ms:
                 best, best_ms = cfg, ms
-    out = dict(best, sample_ms=best_ms)
+    out = dict(best, ns_per_point_step=best_ms)
     if cache:
         data = {}
         if os.path.exists(cache):

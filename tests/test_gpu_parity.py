@@ -128,7 +128,7 @@ def test_screen_precision_does_not_change_events_full_run(S):
     assert b[2]["candidates"] >= a[2]["candidates"]
 
 
-@pytest.mark.parametrize("split", [1, 7, 14])
+@pytest.mark.parametrize("split", [1, 5, 7])
 def test_screen_split_variants(S, split):
     say(f"case: VV 8^3 seed 2, matter era, 150 steps, screen split {split}")
     net = I.vv_network(m=8, seed=2)
