@@ -57,6 +57,36 @@ def log(*a):
     print("bench:", *a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1011_4046_amd", "csrc", "semipar.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(kernel, launch_config):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summaries
+    (profiles/*.txt lines 'traffic-per-launch: ...'), when they were taken on the same
+    kernel source and launch configuration; else None."""
+    want = kernel_source_hash()
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".txt"):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                if not line.startswith("traffic-per-launch:"):
+                    continue
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+                if (kv.get("kernel") == kernel and kv.get("source") == want
+                        and kv.get("config") == launch_config):
+                    return int(float(kv["fetch_bytes"]) + float(kv["write_bytes"]))
+    return None
+
+
 def make_inputs(args):
     from paper_1011_4046_amd import inputs as I
     t = time.perf_counter()
@@ -99,7 +129,8 @@ def bench_batched(args):
 
     feat = S.region_features(rs)
     pred = cm.predict(feat)
-    cfg = {"batch_frac": args.batch_frac, "screen_split": 1, "steps_per_sync": 32}
+    cfg = {"batch_frac": args.batch_frac, "screen_split": args.split,
+           "steps_per_sync": args.sync_steps}
     if args.tune:
         cfg = SC.autotune(rs, pred, screen=screen, cache=args.tune_cache or None, log=log)
         log(f"autotune: {cfg}")
@@ -175,6 +206,11 @@ def bench_batched(args):
                         "avg_launch_us": round(ms / nl * 1e3, 3), "launches": nl,
                         "total_ms": round(ms, 2)}
         log(f"{kname}: {nl} launches, {ms:.1f} ms, {ach:.0f} GB/s algorithmic")
+    launch_config = f"bp{bp}-split{cfg['screen_split']}-sync{cfg['steps_per_sync']}-{args.screen}"
+    for kname, rf in roofs.items():
+        rf["traffic"] = counted_traffic(kname, launch_config)
+        rf["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)"
+        rf["launch_config"] = launch_config
     dom = max(roofs, key=lambda k: roofs[k]["total_ms"])
     roof = roofs[dom]
     other = {k: v for k, v in roofs.items() if k != dom}
@@ -198,31 +234,36 @@ def bench_batched(args):
     }
 
 
-def cpu_baseline_regions(parts, box, steps=40, budget_s=20.0):
-    """The oracle on a bounded sample of the same regions: every 25th non-empty region,
-    each for its first `steps` lattice steps, until `budget_s` seconds are used."""
+def cpu_baseline_regions(parts, box, every=50, budget_s=20.0):
+    """The oracle on a bounded sample of the same regions: every `every`-th non-empty
+    region, each stepped one lattice step at a time for an equal share of `budget_s`
+    seconds (or until it has stopped)."""
     import numpy as np
     import oracle as O
     from paper_1011_4046_amd import inputs as I
     live = [i for i, p in enumerate(parts) if len(p[0])]
-    sample = live[::25]
+    sample = live[::every]
+    share = budget_s / max(len(sample), 1)
     t = time.perf_counter()
-    ps, used = 0, []
+    ps, steps, npts = 0, 0, 0
     for i in sample:
         recs, geom = parts[i]
-        net = dict(recs=recs, box=box, cosmology=I.MATTER, geom=geom)
-        _, _, ost = O.run(net, steps)
-        ps += ost["point_steps"]
-        used.append(i)
-        log(f"cpu baseline: region {i} ({len(recs)} points), {time.perf_counter() - t:.1f} s")
-        if time.perf_counter() - t > budget_s:
-            break
+        ro = O.OracleRegion(recs, box, I.MATTER, I.HCOEF[I.MATTER], geom)
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < share and ro.active > 0:
+            ro.evolve(1)
+        st = ro.stats()
+        ps += st["point_steps"]
+        steps += st["steps"]
+        npts += len(recs)
+        ro.close()
+        log(f"cpu baseline: region {i} ({len(recs)} points), {st['steps']} steps, "
+            f"{time.perf_counter() - t:.1f} s")
     tc = time.perf_counter() - t
-    npts = int(np.sum([len(parts[i][0]) for i in used]))
     return {"value": ps / tc, "unit": "point-steps/s", "cores": O.threads(), "kind": "oracle",
-            "sample": f"{len(used)} of the {len(live)} non-empty regions (every 25th, {npts} "
-                      f"points), first {steps} lattice steps of each: {ps} point-steps in "
-                      f"{tc:.1f} s"}
+            "sample": f"{len(sample)} of the {len(live)} non-empty regions (every {every}th, "
+                      f"{npts} points), each stepped for {share:.1f} s: {steps} lattice steps, "
+                      f"{ps} point-steps in {tc:.1f} s"}
 
 
 def bench_vv32(args):
@@ -294,9 +335,13 @@ def main():
     ap.add_argument("--regions", type=int, default=512)
     ap.add_argument("--train-regions", type=int, default=128)
     ap.add_argument("--workers", type=int, default=8, help="processes generating the inputs")
-    ap.add_argument("--batch-frac", type=float, default=1.0,
+    ap.add_argument("--batch-frac", type=float, default=0.5,
                     help="batch size as a fraction of all points (1 = one batch)")
-    ap.add_argument("--tune", type=int, default=1, help="run the autotuner first")
+    ap.add_argument("--split", type=int, default=1, help="screen threads per element (1 or 5)")
+    ap.add_argument("--sync-steps", type=int, default=32, help="lattice steps per host check")
+    ap.add_argument("--tune", type=int, default=0,
+                    help="run the autotuner first (the defaults are its choice for this "
+                         "workload)")
     ap.add_argument("--tune-cache", default="")
     ap.add_argument("--plain", type=int, default=1, help="also time the plain per-region path")
     ap.add_argument("--no-cpu-baseline", action="store_true")

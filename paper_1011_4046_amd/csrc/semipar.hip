@@ -21,6 +21,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <climits>
 #include <new>
 #include <type_traits>
 #include <cmath>
@@ -333,10 +334,18 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   const int s = ctrl->step;
   const Cells cs = ctrl->cells;
   const int ic = s % 3, ip = (s + 2) % 3, in = (s + 1) % 3;
-  const int k = blockIdx.x * NT + threadIdx.x;
+  // grid-stride over the points in slot order (neighbouring lanes read neighbouring
+  // slots, so the SoA loads stay coalesced), with the same trip count for every thread
+  // so that wave-wide operations stay uniform
+  const int span = gridDim.x * NT;
+  const int iters = (n + span - 1) / span;
   uint64_t tkey = KEY_MAX;
   uint64_t xkey = 0;
   uint32_t nadv = 0;
+  for (int it = 0; it < iters; ++it) {
+  const int ii = it * span + blockIdx.x * NT + threadIdx.x;
+  const int k = ii < n ? ii : n;
+  uint64_t xk = 0;  // this point's element extent
   if (k < n) {
     bool adv = true;
     int j = nxt[k];
@@ -365,13 +374,14 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
       }
     }
     if (adv) {
-      nadv = 1;
+      nadv += 1;
       const V4 L = ld(X, ic, k);
       const V4 R = ld(X, ic, j);
       const V4 B = ld(X, ip, j);
       const V4 T = sp::top<FRW>(L, R, B, P, hcoef);
       st(X, in, k, T);
-      tkey = order_key(T.t);
+      const uint64_t tk = order_key(T.t);
+      tkey = tk < tkey ? tk : tkey;
       if constexpr (SCR != 0) {
         const int jj = nxt[j];
         bool jadv = true;
@@ -396,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
           double ext = b.hi[0] - b.lo[0];
           ext = fmax(ext, b.hi[1] - b.lo[1]);
           ext = fmax(ext, b.hi[2] - b.lo[2]);
-          xkey = order_key(ext);
+          xk = order_key(ext);
           double W[3], w[3];
           for (int c = 0; c < 3; ++c) {
             W[c] = P.box * floor(b.lo[c] * P.inv);
@@ -479,13 +489,15 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
       const int q0 = __shfl(q, 0, 64);
       const uint64_t lm = __ballot(live), sm = __ballot(live && q == q0);
       if (lm == sm && (lm & 1ull)) {
-        const uint64_t m = wave_max_u64(xkey);
+        const uint64_t m = wave_max_u64(xk);
         if ((threadIdx.x & 63) == 0 && m != 0) atomicMax((unsigned long long*)&rext[q0], m);
-      } else if (live && xkey != 0) {
-        atomicMax((unsigned long long*)&rext[q], xkey);
+      } else if (live && xk != 0) {
+        atomicMax((unsigned long long*)&rext[q], xk);
       }
     }
   }
+  xkey = xk > xkey ? xk : xkey;
+  }  // grid-stride loop
   // per block: minimum t of the new slice, largest element extent, points advanced;
   // reduced by k_resolve (no same-address atomics across the grid)
   __shared__ uint64_t wmin[NT / 64], wmax[NT / 64];
@@ -559,6 +571,7 @@ __global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t
 }
 
 constexpr int MAX_TILES = 2048;  // buckets <= 2^23
+constexpr int POINT_GRID = 2048;  // most workgroups of the grid-stride per-point kernels
 
 __device__ __forceinline__ int bucket_start(const int32_t* loc, const int32_t* s_toff, uint32_t b) {
   return loc[b] + s_toff[b >> TS_LOG];
@@ -590,10 +603,9 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
                                                 const Ctrl* ctrl) {
   if (ctrl->done) return;
   const int nc = ctrl->cells.nc;
-  const int k = blockIdx.x * NT + threadIdx.x;
-  if (k >= n) return;
+  for (int k = blockIdx.x * NT + threadIdx.x; k < n; k += gridDim.x * NT) {
   const int32_t c = ecell[k];
-  if (c < 0) return;
+  if (c < 0) continue;
   const int x = c & 1023, y = (c >> 10) & 1023, z = (c >> 20) & 1023;
   uint32_t b;
   int32_t key = c;
@@ -617,6 +629,7 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
     dst[0] = src[0];
     dst[1] = src[1];
   }
+  }  // grid-stride loop
 }
 
 __device__ __forceinline__ void push_cand(Ctrl* ctrl, int2* cand, int cap, int k, int m) {
@@ -694,6 +707,7 @@ inline int xcd_grid(int total) { return (total + N_XCD - 1) / N_XCD * N_XCD; }
 // Each unordered pair is tested exactly once. Logical block = (element block, g),
 // renumbered per XCD (xcd_block).
 constexpr int N_PENCIL = 5;
+constexpr int SCREEN_EPW = 12;  // elements per wave when five lanes share an element
 
 template <int SCR, int G>
 __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ sent,
@@ -709,9 +723,22 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
                                                const RCell* __restrict__ rcell) {
   static_assert(G == 1 || G == N_PENCIL, "one or five threads per element");
   if (ctrl->done) return;
-  const int lid = xcd_block(nblk * G);
-  if (lid >= nblk * G) return;
-  const int eblk = lid / G, g = lid % G;
+  const int lid = xcd_block(nblk);
+  if (lid >= nblk) return;
+  // G = 1: one element per thread. G = 5: an element's five threads are neighbouring
+  // lanes of one wave (12 elements per wave, lanes 60..63 idle), so their identical
+  // loads of the element's own data are served by one request.
+  int q, g;
+  if constexpr (G == 1) {
+    q = lid * NT + (int)threadIdx.x;
+    g = 0;
+  } else {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    g = lane % N_PENCIL;
+    q = lane < SCREEN_EPW * N_PENCIL ? (lid * (NT / 64) + wv) * SCREEN_EPW + lane / N_PENCIL
+                                      : INT_MAX;
+  }
   using T = typename std::conditional<SCR == 1, double, float>::type;
   __shared__ int2 sbuf[SBUF];
   __shared__ int s_cnt, s_base;
@@ -719,7 +746,6 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
   __syncthreads();
   const Cells cs = ctrl->cells;
   const int nl = ctrl->n_large;
-  const int q = eblk * NT + threadIdx.x;
   const int n_norm = toff[ntiles];
   auto push = [&](int a, int b) {
     const int i = atomicAdd(&s_cnt, 1);
@@ -2070,9 +2096,11 @@ void launch_evolve(semipar_region* r, bool frw, int scr, bool bnd, int n, int nb
 
 template <int SCR, int G>
 void launch_screen_t(semipar_region* r, int n, int nb) {
-  k_screen<SCR, G><<<xcd_grid(nb * G), NT, 0, r->stream>>>(
+  // logical blocks covering n elements (hashed + large <= n)
+  const int nl = G == 1 ? nb : (int)((n + (NT / 64) * SCREEN_EPW - 1) / ((NT / 64) * SCREEN_EPW));
+  k_screen<SCR, G><<<xcd_grid(nl), NT, 0, r->stream>>>(
       n, r->sent, r->sbox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc, r->P,
-      r->cand, (int)r->cap_cand, nb, r->ctrl, r->rid, r->rcell);
+      r->cand, (int)r->cap_cand, nl, r->ctrl, r->rid, r->rcell);
 }
 
 // Screen launch: precision (FP64 / FP32 boxes) and threads per element (1 or 5).
@@ -2092,11 +2120,12 @@ void launch_screen(semipar_region* r, int n, int nb) {
 void issue_step(semipar_region* r, bool intercommute, int i) {
   const int n = (int)r->n;
   const int nb = blocks(n);
+  const int nbe = std::min(nb, POINT_GRID);  // grid of the per-point kernels
   hipStream_t s = r->stream;
   const bool frw = r->cosmology != SEMIPAR_FLAT;
   mark(r, SEMIPAR_K_EVOLVE, 2 * i);
   const int scr = intercommute ? r->screen : 0;
-  launch_evolve(r, frw, scr, r->bounded, n, nb);
+  launch_evolve(r, frw, scr, r->bounded, n, nbe);
   mark(r, SEMIPAR_K_EVOLVE, 2 * i + 1);
   if (intercommute) {
     mark(r, SEMIPAR_K_SCAN, 2 * i);
@@ -2105,11 +2134,11 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
     mark(r, SEMIPAR_K_SCATTER, 2 * i);
     k_toff<<<1, 1024, 0, s>>>(r->tile_tot, r->ntiles, r->toff, r->ctrl);
     if (r->screen == 1)
-      k_scatter<1><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
-                                     r->sbox, r->hc, r->rid, r->rcell, r->ctrl);
+      k_scatter<1><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
+                                      r->sbox, r->hc, r->rid, r->rcell, r->ctrl);
     else
-      k_scatter<2><<<nb, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
-                                     r->sbox, r->hc, r->rid, r->rcell, r->ctrl);
+      k_scatter<2><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
+                                      r->sbox, r->hc, r->rid, r->rcell, r->ctrl);
     mark(r, SEMIPAR_K_SCATTER, 2 * i + 1);
     mark(r, SEMIPAR_K_SCREEN, 2 * i);
     launch_screen(r, n, nb);
@@ -2121,7 +2150,7 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
   }
   mark(r, SEMIPAR_K_RESOLVE, 2 * i);
   k_resolve<<<1, RESOLVE_NT, 0, s>>>(r->nxt, r->prv, r->ev, (int)r->cap_evt, (int)r->cap_cand,
-                                     r->best, r->used, r->evs, r->log, r->log_cap, r->blkred, nb,
+                                     r->best, r->used, r->evs, r->log, r->log_cap, r->blkred, nbe,
                                      r->ctrl, r->rid, r->log_rid);
   if (intercommute && r->rcell)
     k_rcells<<<1, 1024, 0, s>>>(r->geoms, r->n_sub, r->rext, r->rcell, r->rc_fixed_h, r->ctrl);
