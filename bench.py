@@ -91,13 +91,16 @@ def make_inputs(args):
     from paper_1011_4046_amd import inputs as I
     t = time.perf_counter()
     nt = I.lognormal_regions(args.regions, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2, seed=0)
-    parts, box = I.region_batch(nt, size=4.0, seed=0, slots=8, workers=args.workers)
+    prog = lambda i: (i % 64 == 63) and log(f"  generated {i + 1} regions")
+    parts, box = I.region_batch(nt, size=4.0, seed=0, slots=8, workers=args.workers,
+                                progress=prog)
     log(f"workload: {len(parts)} regions, {sum(len(p[0]) for p in parts)} points "
         f"({time.perf_counter() - t:.1f} s)")
     t = time.perf_counter()
     nt = I.lognormal_regions(args.train_regions, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2,
                              seed=1)
-    train, tbox = I.region_batch(nt, size=4.0, seed=100000, slots=8, workers=args.workers)
+    train, tbox = I.region_batch(nt, size=4.0, seed=100000, slots=8, workers=args.workers,
+                                 progress=prog)
     log(f"training workload: {len(train)} regions, {sum(len(p[0]) for p in train)} points "
         f"({time.perf_counter() - t:.1f} s)")
     return parts, box, train, tbox
@@ -334,7 +337,9 @@ def main():
     ap.add_argument("--screen", choices=["f32", "f64"], default="f32")
     ap.add_argument("--regions", type=int, default=512)
     ap.add_argument("--train-regions", type=int, default=128)
-    ap.add_argument("--workers", type=int, default=8, help="processes generating the inputs")
+    ap.add_argument("--workers", type=int, default=8,
+                    help="forked processes generating the inputs (0 under a profiler, which "
+                         "loads the GPU runtime before the program starts)")
     ap.add_argument("--batch-frac", type=float, default=0.5,
                     help="batch size as a fraction of all points (1 = one batch)")
     ap.add_argument("--split", type=int, default=1, help="screen threads per element (1 or 5)")

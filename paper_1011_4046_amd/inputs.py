@@ -465,12 +465,14 @@ def lognormal_regions(n_regions=512, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2
 
 
 def region_batch(n_targets, size=4.0, seed=0, t_mid=8.0, slots=8, cosmology=MATTER,
-                 pts_per_xi=None, workers=0):
+                 pts_per_xi=None, workers=0, progress=None):
     """Independent first-layer regions on the slots of a periodic box (slots^3 slots,
     slot spacing >= 2 g + 1, so regions never overlap). Region r has point target
     n_targets[r], seed seed + r and pts_per_xi[r] points per correlation length
     (default 8); its ids are offset to be unique in the batch. workers > 1 generates
-    the regions in that many processes (same result).
+    the regions in that many forked processes (same result; only while no GPU runtime
+    is loaded in this process); progress(i) is called after every region generated
+    serially.
     Returns (parts, box) with parts = [(recs, geom), ...]."""
     g = size / np.sqrt(2.0)
     nr = len(n_targets)
@@ -489,7 +491,11 @@ def region_batch(n_targets, size=4.0, seed=0, t_mid=8.0, slots=8, cosmology=MATT
         with mp.get_context("fork").Pool(workers) as pool:
             nets = pool.map(_region_job, jobs, chunksize=1)
     else:
-        nets = [_region_job(j) for j in jobs]
+        nets = []
+        for i, j in enumerate(jobs):
+            nets.append(_region_job(j))
+            if progress:
+                progress(i)
     parts = []
     id_off = 0
     for recs, geom in nets:
