@@ -133,13 +133,13 @@ def bench_batched(args):
     feat = S.region_features(rs)
     pred = cm.predict(feat)
     cfg = {"batch_frac": args.batch_frac, "screen_split": args.split,
-           "steps_per_sync": args.sync_steps}
+           "steps_per_sync": args.sync_steps, "lanes": args.lanes}
     if args.tune:
         cfg = SC.autotune(rs, pred, screen=screen, cache=args.tune_cache or None, log=log)
         log(f"autotune: {cfg}")
     bp = SC.batch_points_for(rs, cfg)
     kw = dict(fast, batch_points=bp, screen_split=cfg["screen_split"],
-              steps_per_sync=cfg["steps_per_sync"])
+              steps_per_sync=cfg["steps_per_sync"], lanes=cfg["lanes"])
 
     for w in range(args.warmup):
         r = SC.learned_schedule(rs, cm, **kw)
@@ -189,7 +189,8 @@ def bench_batched(args):
         log(f"plain per-region: {tp * 1e3:.0f} ms, speed-up {value / pv:.2f}x")
         del rp
 
-    # roofline: one eager schedule per timed kernel (events cannot be timed in graphs)
+    # roofline: one eager schedule per timed kernel (events cannot be timed in graphs),
+    # one lane, so that no other batch's kernels run beside the timed ones
     roofs = {}
     for kname, kid in (("k_evolve", S.K_EVOLVE), ("k_screen", S.K_SCREEN)):
         rr = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=pred, out=None,
@@ -231,6 +232,7 @@ def bench_batched(args):
                    "point_steps_per_schedule": st["point_steps"],
                    "screen": args.screen, "graph": True, "batch_points": bp,
                    "screen_split": cfg["screen_split"], "steps_per_sync": cfg["steps_per_sync"],
+                   "lanes": cfg["lanes"],
                    "path": "batched + learned cost model (features, inference and schedule "
                            "inside the timed region)"},
         "roofline": roof, "roofline_other": other, "cpu_baseline": cpu, **extra,
@@ -340,9 +342,10 @@ def main():
     ap.add_argument("--workers", type=int, default=8,
                     help="forked processes generating the inputs (0 under a profiler, which "
                          "loads the GPU runtime before the program starts)")
-    ap.add_argument("--batch-frac", type=float, default=0.5,
+    ap.add_argument("--batch-frac", type=float, default=0.34,
                     help="batch size as a fraction of all points (1 = one batch)")
     ap.add_argument("--split", type=int, default=1, help="screen threads per element (1 or 5)")
+    ap.add_argument("--lanes", type=int, default=3, help="batches evolved concurrently")
     ap.add_argument("--sync-steps", type=int, default=32, help="lattice steps per host check")
     ap.add_argument("--tune", type=int, default=0,
                     help="run the autotuner first (the defaults are its choice for this "

@@ -318,6 +318,7 @@ enum {
  *                 offsets: region r's events (listing order) at events_off[r] ..
  *                 events_off[r+1]. Offsets count every event; entries past events_cap
  *                 are not written (stats.events is the total). NULL: not returned.
+ *   lanes         BATCHED: concurrent lanes (see the field)
  *   region_steps, region_point_steps, region_batch, region_ms  optional host arrays
  *                 (n_regions) receiving per-region logs: slices advanced by the
  *                 region's furthest point, its point-steps, the batch that ran it (-1:
@@ -338,6 +339,10 @@ typedef struct semipar_sched_params {
   int64_t* region_point_steps;
   int32_t* region_batch;
   double* region_ms;
+  int32_t lanes;     /* BATCHED: batches evolved concurrently, each lane a host thread
+                        with a stream of its own (0 or 1: one after another on the
+                        tiling's stream). Batches go to lanes longest predicted first. */
+  int32_t reserved;
 } semipar_sched_params;
 
 typedef struct semipar_sched_stats {

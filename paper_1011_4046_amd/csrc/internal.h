@@ -11,6 +11,10 @@
 
 namespace spi {
 
+// Allocate the step buffers and the event log that region_evolve with these
+// parameters would allocate at its start (so that it frees nothing while running).
+SP_HIDDEN int region_prepare(semipar_region* r, const semipar_evolve_params* p);
+
 // Number of points and the stream of a region.
 SP_HIDDEN int64_t region_points(const semipar_region* r);
 SP_HIDDEN hipStream_t region_stream(const semipar_region* r);

@@ -19,6 +19,7 @@
 #include <cstdint>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -148,21 +149,39 @@ struct Runner {
     return SEMIPAR_OK;
   }
 
-  // batched policy: regs share one batch region
-  int run_batch(const std::vector<int32_t>& regs) {
-    std::vector<semipar_region_geom> g;
-    semipar_region_desc d = batch_desc(t, regs, g);
-    std::vector<semipar_surface> in(regs.size());
-    int64_t total = 0;
-    for (size_t i = 0; i < regs.size(); ++i) {
-      in[i] = t->surfaces[regs[i]];
-      total += in[i].n;
-    }
+  // batched policy: regs share one batch region. A batch goes through three phases:
+  // build (init from the surfaces, step buffers and log sized up front), evolve, and
+  // finish (per-region records, events and logs; destroy).
+  struct Batch {
+    std::vector<int32_t> regs;
+    std::vector<int64_t> n;
     semipar_region* reg = nullptr;
-    int rc = region_init_from_surfaces(&d, in.data(), (int)in.size(), &reg);
-    if (rc != SEMIPAR_OK) return rc;
     semipar_evolve_stats es{};
-    rc = region_evolve(reg, &p->evolve, &es);
+    int rc = SEMIPAR_OK;
+    double cost = 0.0;  // predicted device time, for assigning batches to lanes
+  };
+
+  int build_batch(Batch& b, void* stream) {
+    std::vector<semipar_region_geom> g;
+    semipar_region_desc d = batch_desc(t, b.regs, g);
+    d.stream = stream;
+    std::vector<semipar_surface> in(b.regs.size());
+    b.n.resize(b.regs.size());
+    for (size_t i = 0; i < b.regs.size(); ++i) {
+      in[i] = t->surfaces[b.regs[i]];
+      b.n[i] = in[i].n;
+    }
+    int rc = region_init_from_surfaces(&d, in.data(), (int)in.size(), &b.reg);
+    if (rc == SEMIPAR_OK) rc = spi::region_prepare(b.reg, &p->evolve);
+    return rc;
+  }
+
+  int finish_batch(Batch& b) {
+    int rc = b.rc;
+    semipar_region* reg = b.reg;
+    const auto& regs = b.regs;
+    int64_t total = 0;
+    for (int64_t x : b.n) total += x;
     if (rc == SEMIPAR_OK && p->out && total > 0) {
       if (tmp_cap < total) {
         if (tmp) (void)hipFree(tmp);
@@ -179,7 +198,7 @@ struct Runner {
       int64_t src = 0;
       for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i) {
         const int32_t r = regs[i];
-        const int64_t nr = in[i].n;
+        const int64_t nr = b.n[i];
         int64_t off = slab[r].base;
         for (int f = 0; f < 4; ++f) {
           if (p->out_off) p->out_off[4 * r + f] = off;
@@ -203,7 +222,9 @@ struct Runner {
     std::vector<int64_t> ps;
     if (rc == SEMIPAR_OK) rc = spi::batch_stats(reg, steps, ps);
     region_destroy(reg);
+    b.reg = nullptr;
     if (rc != SEMIPAR_OK) return rc;
+    const semipar_evolve_stats& es = b.es;
     acc.point_steps += es.point_steps;
     acc.steps += es.steps;
     acc.evolve_ms += es.elapsed_ms;
@@ -214,6 +235,82 @@ struct Runner {
       log_region(regs[i], steps[i], ps[i], batch_id, es.elapsed_ms);
     batch_id++;
     return SEMIPAR_OK;
+  }
+
+  // Run the batches of one wave: with one lane, one after another on the tiling's
+  // stream; with L lanes, all batches are built first (nothing is freed while kernels
+  // run, since hipFree waits for the whole device), then L host threads each evolve
+  // their batches on a stream of their own, longest predicted batch first onto the
+  // least loaded lane, and the results are collected afterwards.
+  int run_batches(std::vector<Batch>& bs) {
+    const int lanes = std::max(1, std::min<int>(p->lanes, (int)bs.size()));
+    if (lanes == 1) {
+      for (Batch& b : bs) {
+        int rc = build_batch(b, t->stream);
+        if (rc == SEMIPAR_OK) rc = region_evolve(b.reg, &p->evolve, &b.es);
+        b.rc = rc;
+        RCCHK_R(finish_batch(b));
+      }
+      return SEMIPAR_OK;
+    }
+    std::vector<hipStream_t> ls(lanes, nullptr);
+    hipEvent_t ready = nullptr;
+    int rc = SEMIPAR_OK;
+    for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
+      if (hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking) != hipSuccess) rc = SEMIPAR_E_HIP;
+    if (rc == SEMIPAR_OK && t->stream) {
+      // device-resident surfaces may still be in flight on the caller's stream
+      if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+          hipEventRecord(ready, (hipStream_t)t->stream) != hipSuccess)
+        rc = SEMIPAR_E_HIP;
+      for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
+        if (hipStreamWaitEvent(ls[l], ready, 0) != hipSuccess) rc = SEMIPAR_E_HIP;
+    }
+    // longest processing time first onto the least loaded lane
+    std::vector<int> order(bs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return bs[a].cost > bs[b].cost; });
+    std::vector<std::vector<int>> work(lanes);
+    std::vector<double> load(lanes, 0.0);
+    for (int i : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      work[l].push_back(i);
+      load[l] += bs[i].cost;
+    }
+    for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
+      for (int i : work[l]) {
+        rc = build_batch(bs[i], ls[l]);
+        if (rc != SEMIPAR_OK) break;
+      }
+    if (rc == SEMIPAR_OK) {
+      std::vector<std::thread> th;
+      for (int l = 0; l < lanes; ++l)
+        th.emplace_back([&, l]() {
+          for (int i : work[l]) {
+            bs[i].rc = region_evolve(bs[i].reg, &p->evolve, &bs[i].es);
+            if (bs[i].rc != SEMIPAR_OK) break;
+          }
+        });
+      for (auto& x : th) x.join();
+      for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
+        for (int i : work[l])
+          if (bs[i].rc != SEMIPAR_OK) rc = bs[i].rc;
+    }
+    for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
+      for (int i : work[l]) {
+        rc = finish_batch(bs[i]);
+        if (rc != SEMIPAR_OK) break;
+      }
+    for (Batch& b : bs)
+      if (b.reg) {
+        region_destroy(b.reg);
+        b.reg = nullptr;
+      }
+    for (hipStream_t x : ls)
+      if (x) (void)hipStreamDestroy(x);
+    if (ready) (void)hipEventDestroy(ready);
+    return rc;
   }
 
   // one wave of ready regions
@@ -240,20 +337,28 @@ struct Runner {
       if (p->cost) return p->cost[a] > p->cost[b];
       return t->surfaces[a].n > t->surfaces[b].n;
     });
-    std::vector<int32_t> cur;
+    std::vector<Batch> bs;
     int64_t pts = 0;
     for (int32_t r : live) {
       const int64_t nr = t->surfaces[r].n;
-      if (!cur.empty() && p->batch_points > 0 && pts + nr > p->batch_points) {
-        RCCHK_R(run_batch(cur));
-        cur.clear();
+      if (bs.empty() || (p->batch_points > 0 && pts + nr > p->batch_points)) {
+        bs.emplace_back();
         pts = 0;
       }
-      cur.push_back(r);
+      bs.back().regs.push_back(r);
       pts += nr;
     }
-    if (!cur.empty()) RCCHK_R(run_batch(cur));
-    return SEMIPAR_OK;
+    // predicted device time of a batch: its points, for as many steps as its longest
+    // region needs (steps from the cost model; without one, the points alone)
+    for (Batch& b : bs) {
+      double np = 0.0, mx = 1.0;
+      for (int32_t r : b.regs) {
+        np += (double)t->surfaces[r].n;
+        if (p->cost) mx = std::max(mx, (double)p->cost[r]);
+      }
+      b.cost = np * mx;
+    }
+    return run_batches(bs);
   }
 };
 
@@ -267,6 +372,7 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
   int rc = check_tiling(t);
   if (rc != SEMIPAR_OK) return rc;
   if (p->policy != SEMIPAR_SCHED_PLAIN && p->policy != SEMIPAR_SCHED_BATCHED) return SEMIPAR_E_ARG;
+  if (p->lanes < 0 || p->lanes > 16) return SEMIPAR_E_ARG;
   if (p->batch_points < 0 || (p->out && p->out_mem != SEMIPAR_MEM_HOST &&
                               p->out_mem != SEMIPAR_MEM_DEVICE))
     return SEMIPAR_E_ARG;

@@ -346,7 +346,11 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   const int ii = it * span + blockIdx.x * NT + threadIdx.x;
   const int k = ii < n ? ii : n;
   uint64_t xk = 0;  // this point's element extent
-  if (k < n) {
+  // a point of a bounded region that stopped before this step has nothing to do (its
+  // element cell already reads NO_ELEM)
+  bool live_pt = k < n;
+  if constexpr (BND) live_pt = live_pt && fstep[k] == FS_ACTIVE;
+  if (live_pt) {
     bool adv = true;
     int j = nxt[k];
     // geometry of k's region (links never leave a region, so also next[k]'s)
@@ -354,7 +358,7 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
     if constexpr (BND) G = rid ? geoms[rid[k]] : G0;
     if constexpr (BND) {
       adv = false;
-      if (fstep[k] == FS_ACTIVE) {
+      {
         int f = -1;
         bool with_r = false;
         if (j < 0) {
@@ -1374,6 +1378,11 @@ __global__ __launch_bounds__(NT) void k_init_insert(const semipar_point_rec* __r
   atomicOr(&ctrl->err, 4);
 }
 
+__global__ __launch_bounds__(NT) void k_fill_i32(int32_t* p, uint64_t m, int32_t v) {
+  const uint64_t i = blockIdx.x * (uint64_t)NT + threadIdx.x;
+  if (i < m) p[i] = v;
+}
+
 __global__ __launch_bounds__(NT) void k_fill_i64(int64_t* p, uint64_t m, int64_t v) {
   const uint64_t i = blockIdx.x * (uint64_t)NT + threadIdx.x;
   if (i < m) p[i] = v;
@@ -1991,6 +2000,9 @@ int configure(semipar_region* r, const semipar_evolve_params* p) {
   r->ntiles = r->hc.B / TS;
   HIPCHK(hipMalloc(&r->ebox, (size_t)cap * 8 * (screen == 1 ? sizeof(double) : sizeof(float))));
   HIPCHK(dalloc(&r->ecell, cap));
+  // points that have stopped are never visited again: their cell must read NO_ELEM
+  k_fill_i32<<<blocks(cap), NT, 0, r->stream>>>(r->ecell, (uint64_t)cap, NO_ELEM);
+  HIPCHK(hipGetLastError());
   HIPCHK(dalloc(&r->epos, cap));
   HIPCHK(dalloc(&r->large, cap));
   HIPCHK(dalloc(&r->cnt, r->hc.B));
@@ -2632,6 +2644,15 @@ int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int6
 namespace spi {
 
 int64_t region_points(const semipar_region* r) { return r ? r->n : 0; }
+
+int region_prepare(semipar_region* r, const semipar_evolve_params* p) {
+  if (!r || !p) return SEMIPAR_E_ARG;
+  if (r->n == 0) return SEMIPAR_OK;
+  RCCHK(configure(r, p));
+  RCCHK(read_ctrl(r));
+  // the log size region_evolve asks for at its first block
+  return ensure_log(r, r->ctrl_h->log_n + 2 * r->cap_evt);
+}
 hipStream_t region_stream(const semipar_region* r) { return r ? r->stream : nullptr; }
 
 void set_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }

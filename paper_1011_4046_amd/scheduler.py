@@ -9,8 +9,9 @@ which a scheduler can start first and group with regions of similar cost. Here:
 * the scheduler orders regions by the predicted steps and cuts them into launch
   batches (schedule_regions with a cost vector); without a model it falls back to the
   point-count order;
-* an autotuner picks the batch size, the screen split and the steps per host check by
-  timing short runs on a sample of the regions, and caches the choice per workload.
+* an autotuner picks the batch size, the number of concurrent lanes, the screen split
+  and the steps per host check by timing capped schedules of the whole workload, and
+  caches the choice per workload.
 
 Nothing here changes results: every choice only orders or groups regions, or sets
 launch shapes.
@@ -75,7 +76,8 @@ def learned_schedule(rs, cost_model, **kw):
 # ---- autotuner ------------------------------------------------------------------
 
 TUNABLE = {
-    "batch_frac": [1.0, 0.5, 0.25, 0.125],  # batch_points as a fraction of all points
+    "batch_frac": [1.0, 0.5, 0.34, 0.25, 0.125],  # batch_points as a fraction of all points
+    "lanes": [1, 2, 3],                            # batches evolved concurrently
     "screen_split": [5, 1],
     "steps_per_sync": [64, 32, 128],
 }
@@ -107,7 +109,8 @@ def autotune(rs, cost=None, screen=S.SCREEN_F32, cache=None, max_steps=96, log=N
         res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=cost,
                                  out=None, events=False, use_graph=True, screen=screen,
                                  screen_split=cfg["screen_split"],
-                                 steps_per_sync=cfg["steps_per_sync"], max_steps=max_steps)
+                                 steps_per_sync=cfg["steps_per_sync"], max_steps=max_steps,
+                                 lanes=cfg["lanes"])
         st = res["stats"]
         # time per point-step of the truncated schedule
         return st["makespan_ms"] / max(st["point_steps"], 1) * 1e6

@@ -50,6 +50,7 @@ int main(void) {
   F(semipar_tiling, surfaces) F(semipar_tiling, stream)
   F(semipar_sched_params, cost) F(semipar_sched_params, evolve) F(semipar_sched_params, out)
   F(semipar_sched_params, events_cap) F(semipar_sched_params, region_ms)
+  F(semipar_sched_params, lanes)
   F(semipar_sched_stats, makespan_ms) F(semipar_sched_stats, timed_kernel_launches)
   return 0;
 }

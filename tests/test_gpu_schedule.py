@@ -71,7 +71,8 @@ def check_against_oracle(res, parts, orc):
 SIZES = [0, 300, 5000, 1200, 0, 20000, 800, 2500, 40, 9000, 150, 3000]
 
 
-@pytest.mark.parametrize("case", ["plain", "batched-heuristic", "batched-cost", "one-batch-f32"])
+@pytest.mark.parametrize("case", ["plain", "batched-heuristic", "batched-cost", "one-batch-f32",
+                                  "lanes"])
 def test_schedule_policies_equal_oracle_region_by_region(S, case):
     say(f"case: schedule_regions {case}, sizes {SIZES}, seed 200")
     parts, box = I.region_batch(SIZES, seed=200)
@@ -96,6 +97,11 @@ def test_schedule_policies_equal_oracle_region_by_region(S, case):
         order = sorted(nz, key=lambda r: -cost[r])
         b = [res["region_batch"][r] for r in order]
         assert b == sorted(b)
+    elif case == "lanes":
+        # batches evolved concurrently by three host threads on streams of their own
+        res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=6000, use_graph=True,
+                                 screen=S.SCREEN_F32, lanes=3)
+        assert res["stats"]["batches"] >= 4
     else:
         res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=0, use_graph=True,
                                  screen=S.SCREEN_F32, steps_per_sync=16)
