@@ -714,7 +714,7 @@ constexpr int N_PENCIL = 5;
 constexpr int SCREEN_EPW = 12;  // elements per wave when five lanes share an element
 
 template <int SCR, int G>
-__global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ sent,
+__global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int n, const int2* __restrict__ sent,
                                                const void* __restrict__ sbox,
                                                const int32_t* __restrict__ nxt,
                                                const int32_t* __restrict__ prv,
@@ -816,24 +816,20 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
         }
         for (; q2 < end; ++q2) test(sent[q2], load_sbox<T>(sbox, q2));
       };
-      // phase 1: every pencil's cells, keys and the bounds of their entry ranges (all
-      // bucket-offset loads issued before any range is scanned)
+      // phase 1: every pencil's entry range (all bucket-offset loads issued before any
+      // range is scanned). A pencil whose cells are consecutive buckets is kept as one
+      // range, its centre cell key (unsalted) and a mask of its valid cells: cell z+dz
+      // has key centre + dz * 2^20 (z lies in bits 20..29 and does not wrap then).
+      // Pencils whose buckets are not consecutive are scanned cell by cell right here.
       constexpr int NPT = (N_PENCIL + G - 1) / G;  // pencils per thread
-      bool kv[NPT][3];
-      int32_t kk[NPT][3];
-      int rb[NPT][3], re[NPT][3];
-      bool one[NPT];
+      int rb[NPT], re[NPT], cen[NPT], msk[NPT];
 #pragma unroll
       for (int pi = 0; pi < NPT; ++pi) {
         const int p = g + pi * G;
-        one[pi] = true;
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          kv[pi][u] = false;
-          kk[pi][u] = 0;
-          rb[pi][u] = 0;
-          re[pi][u] = 0;
-        }
+        rb[pi] = 0;
+        re[pi] = 0;
+        cen[pi] = 0;
+        msk[pi] = 0;
         if (p >= N_PENCIL) continue;
         const int dx = p == 0 ? 0 : (p == 1 ? 0 : 1);
         const int dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
@@ -845,6 +841,8 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
           y = wrapc(y);
         }
         // the pencil's cells z + dz: dz = 0, 1 (pencil 0, own cell from q + 1) or -1, 0, 1
+        bool kv[3];
+        int32_t kk[3];
         uint32_t bk[3];
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
@@ -856,46 +854,65 @@ __global__ __launch_bounds__(NT) void k_screen(int n, const int2* __restrict__ s
           } else {
             z = wrapc(z);
           }
-          kv[pi][u] = v;
+          kv[u] = v;
           bk[u] = bucket(x, y, z);
-          kk[pi][u] = local ? (int32_t)(pack_cell(x, y, z) ^ salt) : (int32_t)pack_cell(x, y, z);
+          kk[u] = local ? (int32_t)(pack_cell(x, y, z) ^ salt) : (int32_t)pack_cell(x, y, z);
         }
-        // one range when the valid cells' buckets are consecutive
-        const int first = kv[pi][0] ? 0 : 1;  // cz itself is always valid
-        const int last = kv[pi][2] ? 2 : 1;
+        const int first = kv[0] ? 0 : 1;  // cz itself is always valid
+        const int last = kv[2] ? 2 : 1;
         bool consec = true;
         if (first == 0) consec = consec && bk[1] == bk[0] + 1;
         if (last == 2) consec = consec && bk[2] == bk[1] + 1;
-        one[pi] = consec;
         if (consec) {
-          rb[pi][0] = (p == 0) ? q + 1 : bucket_start(loc, toff, first == 0 ? bk[0] : bk[1]);
-          re[pi][0] = bucket_start(loc, toff, (last == 2 ? bk[2] : bk[1]) + 1);
-        } else {
-#pragma unroll
-          for (int u = 0; u < 3; ++u)
-            if (kv[pi][u]) {
-              rb[pi][u] = (p == 0 && u == 1) ? q + 1 : bucket_start(loc, toff, bk[u]);
-              re[pi][u] = bucket_start(loc, toff, bk[u] + 1);
-            }
-        }
-      }
-      // phase 2: the scans
-#pragma unroll
-      for (int pi = 0; pi < NPT; ++pi) {
-        const int p = g + pi * G;
-        if (p >= N_PENCIL) continue;
-        const int dx = p == 0 ? 0 : (p == 1 ? 0 : 1);
-        const int dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
-        if (one[pi]) {
-          scan(rb[pi][0], re[pi][0], kk[pi], kv[pi], dx, dy);
+          rb[pi] = (p == 0) ? q + 1 : bucket_start(loc, toff, first == 0 ? bk[0] : bk[1]);
+          re[pi] = bucket_start(loc, toff, (last == 2 ? bk[2] : bk[1]) + 1);
+          cen[pi] = (int32_t)pack_cell(x, y, cz);
+          msk[pi] = (kv[0] ? 1 : 0) | 2 | (kv[2] ? 4 : 0);
         } else {
 #pragma unroll
           for (int u = 0; u < 3; ++u) {
-            if (!kv[pi][u]) continue;
+            if (!kv[u]) continue;
             const bool only[3] = {u == 0, u == 1, u == 2};
-            scan(rb[pi][u], re[pi][u], kk[pi], only, dx, dy);
+            const int beg = (p == 0 && u == 1) ? q + 1 : bucket_start(loc, toff, bk[u]);
+            const int end = bucket_start(loc, toff, bk[u] + 1);
+            scan(beg, end, kk, only, dx, dy);
           }
         }
+      }
+      // phase 2: the consecutive-bucket pencils, four entries at a time
+#pragma unroll
+      for (int pi = 0; pi < NPT; ++pi) {
+        const int p = g + pi * G;
+        if (p >= N_PENCIL || rb[pi] >= re[pi]) continue;
+        const int dx = p == 0 ? 0 : (p == 1 ? 0 : 1);
+        const int dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
+        const T sx = (T)dx * hh, sy = (T)dy * hh;
+        const uint32_t c0 = (uint32_t)cen[pi];
+        const int mk = msk[pi];
+        auto test2 = [&](const int2 e, const SBox<T>& b) {
+          const uint32_t d = ((uint32_t)e.x ^ salt) - c0;
+          int dz = 2;
+          if (d == 0u) dz = 0;
+          else if (d == (1u << 20)) dz = (mk & 4) ? 1 : 2;
+          else if (d == (uint32_t)(-(1 << 20))) dz = (mk & 1) ? -1 : 2;
+          const int m = e.y;
+          if (dz != 2 && m != nk && m != pk && box_overlap(me, b, sx, sy, (T)dz * hh, tl))
+            push(k, m);
+        };
+        const int end = re[pi];
+        int q2 = rb[pi];
+        for (; q2 + 4 <= end; q2 += 4) {
+          int2 e4[4];
+          SBox<T> b4[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            e4[v] = sent[q2 + v];
+            b4[v] = load_sbox<T>(sbox, q2 + v);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) test2(e4[v], b4[v]);
+        }
+        for (; q2 < end; ++q2) test2(sent[q2], load_sbox<T>(sbox, q2));
       }
       if (g == 0) {
         // the element's box in global coordinates (any periodic image) for the
