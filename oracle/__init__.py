@@ -31,8 +31,13 @@ EVT = np.dtype([
     ("t_star", "<f8"), ("x_star", "<f8", (3,)),
 ])
 
+LOOP = np.dtype([
+    ("step", "<i4"), ("n_points", "<i4"), ("rep_id", "<i8"),
+    ("energy", "<f8"), ("centre", "<f8", (3,)),
+])
+
 GRID, BRUTE = 0, 1
-FLAG_HAS_R, FLAG_FROZEN, FLAG_ACTIVE = 1, 2, 4
+FLAG_HAS_R, FLAG_FROZEN, FLAG_ACTIVE, FLAG_REMOVED = 1, 2, 4, 8
 
 
 def build(force: bool = False) -> str:
@@ -57,7 +62,7 @@ def lib():
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.orc_create.argtypes = [P, i64, dbl, ctypes.c_int, dbl, ctypes.POINTER(P)]
         L.orc_create.restype = ctypes.c_int
-        L.orc_evolve.argtypes = [P, i64, dbl, ctypes.c_int, ctypes.c_int]
+        L.orc_evolve.argtypes = [P, i64, dbl, ctypes.c_int, ctypes.c_int, i32]
         L.orc_evolve.restype = ctypes.c_int
         L.orc_destroy.argtypes = [P]
         L.orc_destroy.restype = None
@@ -91,6 +96,10 @@ def lib():
         L.orc_active.restype = i64
         L.orc_threads.argtypes = []
         L.orc_threads.restype = ctypes.c_int
+        L.orc_loop_count.argtypes = [P]
+        L.orc_loop_count.restype = i64
+        L.orc_loops.argtypes = [P, P]
+        L.orc_loops.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -121,9 +130,10 @@ class OracleRegion:
             raise ValueError(f"oracle rejected the surface (code {rc})")
         self.h = h
 
-    def evolve(self, max_steps, t_end=float("inf"), search=GRID, intercommute=True):
+    def evolve(self, max_steps, t_end=float("inf"), search=GRID, intercommute=True,
+               loop_every=0):
         rc = lib().orc_evolve(self.h, int(max_steps), float(t_end), int(search),
-                              int(bool(intercommute)))
+                              int(bool(intercommute)), int(loop_every))
         if rc != 0:
             raise RuntimeError(f"oracle evolve failed (code {rc})")
 
@@ -131,6 +141,14 @@ class OracleRegion:
         n = lib().orc_n(self.h)
         out = np.zeros(n, dtype=REC)
         lib().orc_read(self.h, _ptr(out))
+        return out
+
+    def loops(self):
+        """Loops recorded and removed, in removal order (step, then lowest slot)."""
+        n = lib().orc_loop_count(self.h)
+        out = np.zeros(n, dtype=LOOP)
+        if n:
+            lib().orc_loops(self.h, _ptr(out))
         return out
 
     def events(self):
@@ -187,12 +205,12 @@ class OracleRegion:
             pass
 
 
-def run(net, steps, t_end=float("inf"), search=GRID, intercommute=True):
+def run(net, steps, t_end=float("inf"), search=GRID, intercommute=True, loop_every=0):
     """Convenience: evolve a generated network (or region, when it carries "geom") and
     return (records, events, stats)."""
     hc = {0: 0.0, 1: 2.0, 2: 1.0}[net["cosmology"]]
     r = OracleRegion(net["recs"], net["box"], net["cosmology"], hc, net.get("geom"))
-    r.evolve(steps, t_end, search, intercommute)
+    r.evolve(steps, t_end, search, intercommute, loop_every)
     out = (r.read(), r.events(), r.stats())
     r.close()
     return out

@@ -58,6 +58,7 @@
 #define FLAG_HAS_R 1  /* r, r_prev hold the right neighbour's vertices on slices step, step-1 */
 #define FLAG_FROZEN 2 /* the point stopped in this region; (face + 1) << 8 names the face */
 #define FLAG_ACTIVE 4 /* the point was still advancing when the evolution stopped */
+#define FLAG_REMOVED 8 /* the point belongs to a loop that was recorded and removed */
 
 typedef struct {
   int64_t id, next_id, prev_id;
@@ -77,6 +78,13 @@ typedef struct {
   int64_t sa, sb;
   double x[3];
 } orc_cand_event;
+
+/* A loop recorded and removed: step, points, id of its lowest slot, energy, centre. */
+typedef struct {
+  int32_t step, n_points;
+  int64_t rep_id;
+  double energy, centre[3];
+} orc_loop;
 
 typedef struct {
   int64_t n;
@@ -107,6 +115,11 @@ typedef struct {
   /* confirmed events of the most recent step, in key order (for tests) */
   orc_cand_event *last_conf;
   int64_t n_last_conf;
+  /* loop removal */
+  int32_t step0;   /* slice of the initial surface */
+  int32_t* ev;     /* step of the last accepted event of each point's element */
+  orc_loop* loops;
+  int64_t nloops, caploops;
   /* stats */
   int64_t point_steps, n_cand_total, n_conf_total, n_accepted_total, steps_done;
 } orc_region;
@@ -250,6 +263,8 @@ void orc_destroy(orc_region* r) {
   free(r->adv);
   free(r->valid);
   free(r->frz);
+  free(r->ev);
+  free(r->loops);
   free(r);
 }
 
@@ -282,9 +297,10 @@ static int create_impl(const orc_rec* recs, int64_t n, double box, int cosmology
   r->adv = (unsigned char*)malloc(nn);
   r->valid = (unsigned char*)malloc(nn);
   r->frz = (orc_rec*)calloc((size_t)nn, sizeof(orc_rec));
+  r->ev = (int32_t*)malloc(sizeof(int32_t) * nn);
   idslot* map = (idslot*)malloc(sizeof(idslot) * nn);
   if (!r->id || !r->nx || !r->pv || !r->cur || !r->prv || !r->nw || !r->vert || !r->lo || !r->hi ||
-      !r->log || !map || !r->fstep || !r->face || !r->adv || !r->valid || !r->frz) {
+      !r->log || !map || !r->fstep || !r->face || !r->adv || !r->valid || !r->frz || !r->ev) {
     free(map);
     orc_destroy(r);
     return ORC_E_OOM;
@@ -299,6 +315,9 @@ static int create_impl(const orc_rec* recs, int64_t n, double box, int cosmology
     if (recs[k].step != recs[0].step) rc = ORC_E_SURFACE;
   }
   r->step = n > 0 ? recs[0].step : 1;
+  r->step0 = r->step;
+  /* no event yet: as if the last one were in the step before the initial slice */
+  for (int64_t k = 0; k < n; ++k) r->ev[k] = r->step0 - 1;
   qsort(map, (size_t)n, sizeof(idslot), cmp_idslot);
   for (int64_t k = 1; k < n; ++k)
     if (map[k].id == map[k - 1].id) rc = ORC_E_SURFACE;
@@ -672,7 +691,7 @@ static int one_step(orc_region* r, int search, int intercommute) {
     free(nf);
     free(nface);
   } else {
-    memset(r->adv, 1, (size_t)n);
+    for (int64_t k = 0; k < n; ++k) r->adv[k] = r->fstep[k] == INT32_MAX;
   }
   int64_t n_adv = 0;
 #pragma omp parallel for schedule(static) reduction(+ : n_adv)
@@ -726,6 +745,7 @@ static int one_step(orc_region* r, int search, int intercommute) {
     r->nx[b] = ja;
     r->pv[jb] = (int32_t)a;
     r->pv[ja] = (int32_t)b;
+    r->ev[a] = r->ev[b] = r->step;
     orc_event e;
     e.step = r->step;
     e.kind = 0;
@@ -750,12 +770,131 @@ rotate:;
   return rc;
 }
 
+/* Loop record and removal (Section "Semi-parallel cosmic string simulation": loops that
+ * will not intersect again are recorded and removed). Reading: at the start of a step
+ * n, a closed chain of still-active points (a loop) of L points is removed when no
+ * accepted event touched any of its elements during the last L steps, n - L .. n - 1
+ * (its period in flat space), and every point lies within a quarter of the box, per
+ * axis, of the loop's lowest slot (a string winding the box never does). The record holds the step, L, the
+ * id of the lowest slot, the energy sum over k of |X[n][k] - X[n-1][j]| + |X[n][j] -
+ * X[n-1][j]| (j = next k; spatial, minimum image) and the centre, the mean position
+ * about the lowest slot. The loop's points stop (flag REMOVED, no owning face). */
+static int loop_check(orc_region* r) {
+  int64_t n = r->n;
+  unsigned char* seen = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+  int64_t* cyc = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!seen || !cyc) {
+    free(seen);
+    free(cyc);
+    return ORC_E_OOM;
+  }
+  int rc = ORC_OK;
+  for (int64_t k0 = 0; k0 < n && rc == ORC_OK; ++k0) {
+    if (seen[k0] || r->fstep[k0] != INT32_MAX) continue;
+    /* walk forward from k0: a loop when it returns to k0 through unseen active points */
+    int64_t L = 0, k = k0;
+    int closed = 0;
+    for (;;) {
+      if (k < 0 || seen[k] || r->fstep[k] != INT32_MAX) break;
+      seen[k] = 1;
+      cyc[L++] = k;
+      k = r->nx[k];
+      if (k == k0) {
+        closed = 1;
+        break;
+      }
+    }
+    if (!closed) continue;
+    int64_t rep = cyc[0];
+    int32_t last = r->step0 - 1;
+    for (int64_t i = 0; i < L; ++i) {
+      if (cyc[i] < rep) rep = cyc[i];
+      if (r->ev[cyc[i]] > last) last = r->ev[cyc[i]];
+    }
+    /* an event in step e changes the loop from step e + 1 on: quiet for a full period
+     * when the steps e + 1 .. e + L have all been taken, n > e + L */
+    if ((int64_t)r->step - last <= L) continue;
+    int compact = 1;
+    for (int64_t i = 0; i < L && compact; ++i)
+      for (int c = 0; c < 3; ++c) {
+        double d = r->cur[cyc[i]][c] - r->cur[rep][c];
+        d -= r->L * rint(d / r->L);
+        if (!(fabs(d) < 0.25 * r->L)) compact = 0;
+      }
+    if (!compact) continue;
+    orc_loop lp;
+    lp.step = r->step;
+    lp.n_points = (int32_t)L;
+    lp.rep_id = r->id[rep];
+    double e = 0.0, cs[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < L; ++i) {
+      int64_t a = cyc[i], j = r->nx[a];
+      double da[3], db[3];
+      for (int c = 0; c < 3; ++c) {
+        da[c] = r->cur[a][c] - r->prv[j][c];
+        da[c] -= r->L * rint(da[c] / r->L);
+        db[c] = r->cur[j][c] - r->prv[j][c];
+        double d = r->cur[a][c] - r->cur[rep][c];
+        cs[c] += d - r->L * rint(d / r->L);
+      }
+      e += sqrt(da[0] * da[0] + da[1] * da[1] + da[2] * da[2]) +
+           sqrt(db[0] * db[0] + db[1] * db[1] + db[2] * db[2]);
+    }
+    lp.energy = e;
+    for (int c = 0; c < 3; ++c) lp.centre[c] = r->cur[rep][c] + cs[c] / (double)L;
+    if (r->nloops == r->caploops) {
+      int64_t nc = r->caploops ? 2 * r->caploops : 64;
+      orc_loop* nl = (orc_loop*)realloc(r->loops, sizeof(orc_loop) * (size_t)nc);
+      if (!nl) {
+        rc = ORC_E_OOM;
+        break;
+      }
+      r->loops = nl;
+      r->caploops = nc;
+    }
+    r->loops[r->nloops++] = lp;
+    for (int64_t i = 0; i < L; ++i) {
+      int64_t a = cyc[i];
+      orc_rec* f = &r->frz[a];
+      memset(f, 0, sizeof(*f));
+      f->id = r->id[a];
+      f->next_id = r->id[r->nx[a]];
+      f->prev_id = r->id[r->pv[a]];
+      f->step = r->step;
+      f->flags = FLAG_REMOVED;
+      memcpy(f->x, r->cur[a], sizeof(double[4]));
+      memcpy(f->x_prev, r->prv[a], sizeof(double[4]));
+      r->fstep[a] = r->step;
+      r->face[a] = -1;
+      r->n_active--;
+    }
+  }
+  free(seen);
+  free(cyc);
+  return rc;
+}
+
+int64_t orc_loop_count(const orc_region* r) { return r->nloops; }
+
+int orc_loops(const orc_region* r, orc_loop* out) {
+  if (r->nloops) memcpy(out, r->loops, sizeof(orc_loop) * (size_t)r->nloops);
+  return ORC_OK;
+}
+
 /* Evolve until max_steps steps were taken, or until the smallest time on the current
- * slice reaches t_end. search: 0 = periodic grid, 1 = brute force over all pairs. */
-int orc_evolve(orc_region* r, int64_t max_steps, double t_end, int search, int intercommute) {
-  if (!r) return ORC_E_ARG;
+ * slice reaches t_end. search: 0 = periodic grid, 1 = brute force over all pairs.
+ * loop_every > 0: loop record and removal before every step n with n - step0 a
+ * positive multiple of loop_every. */
+int orc_evolve(orc_region* r, int64_t max_steps, double t_end, int search, int intercommute,
+               int32_t loop_every) {
+  if (!r || loop_every < 0) return ORC_E_ARG;
   for (int64_t s = 0; s < max_steps; ++s) {
     if (r->n_active == 0) break;
+    if (loop_every > 0 && r->step > r->step0 && (r->step - r->step0) % loop_every == 0) {
+      int rc = loop_check(r);
+      if (rc != ORC_OK) return rc;
+      if (r->n_active == 0) break;
+    }
     double tmin = INFINITY;
     for (int64_t k = 0; k < r->n; ++k)
       if (r->fstep[k] == INT32_MAX && r->cur[k][3] < tmin) tmin = r->cur[k][3];
@@ -829,7 +968,7 @@ int orc_events(const orc_region* r, orc_event* out) {
 /* Current state as records in slot order: x = slice step, x_prev = slice step-1. */
 int orc_read(const orc_region* r, orc_rec* out) {
   for (int64_t k = 0; k < r->n; ++k) {
-    if (r->bounded && r->fstep[k] != INT32_MAX) {
+    if (r->fstep[k] != INT32_MAX) {
       out[k] = r->frz[k];
       continue;
     }

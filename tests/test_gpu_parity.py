@@ -128,6 +128,36 @@ def test_screen_precision_does_not_change_events_full_run(S):
     assert b[2]["candidates"] >= a[2]["candidates"]
 
 
+def test_screen_precision_dense_64_network_false_positive_rate(S):
+    """The dense 64^3 network (about 1.9e6 points, L = 64 correlation lengths): the FP32
+    screen with its conservative margin gives the same events and positions as the FP64
+    screen. Its false-positive rate is (cand_f32 - cand_f64) / cand_f32; the boxes are
+    rounded outward by a few ulps, so it must stay small."""
+    say("case: VV 64^3 seed 0, matter era, 60 steps, f32 vs f64 screen")
+    net = I.vv_network(m=64, seed=0)
+    a = run_gpu(S, net, 60, screen=0, use_graph=True)
+    b = run_gpu(S, net, 60, screen=1, use_graph=True)
+    assert_same_events(a[1], b[1])
+    assert a[0].tobytes() == b[0].tobytes()
+    c64, c32 = a[2]["candidates"], b[2]["candidates"]
+    assert c32 >= c64 > 0
+    rate = (c32 - c64) / c32
+    say(f"  {len(net['recs'])} points, candidates f64 {c64} f32 {c32}, "
+        f"false-positive rate {rate:.2e}, events {len(a[1])}")
+    assert rate < 1e-2
+
+
+def test_radiation_era_parity(S):
+    """Radiation era (H = 1/eta) against the oracle: same first-order diamond with the
+    other Hubble coefficient."""
+    say("case: VV 6^3 seed 4, radiation era, 150 steps")
+    net = I.vv_network(m=6, seed=4, cosmology=I.RADIATION)
+    g, ge, st = run_gpu(S, net, 150, use_graph=True)
+    o, oe, _ = run_oracle(net, 150)
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)
+
+
 @pytest.mark.parametrize("split", [1, 5, 7])
 def test_screen_split_variants(S, split):
     say(f"case: VV 8^3 seed 2, matter era, 150 steps, screen split {split}")
