@@ -101,6 +101,9 @@ typedef struct semipar_surface {
 #define SEMIPAR_FLAG_FROZEN 2 /* the point stopped in this region; bits 8..15 hold
                                  face + 1 (0: no owning face, e.g. a cut string end) */
 #define SEMIPAR_FLAG_ACTIVE 4 /* the point was still advancing when evolution stopped */
+#define SEMIPAR_FLAG_REMOVED 8 /* the point belongs to a loop that was recorded and
+                                  removed (semipar_evolve_params.loop_every); x, x_prev
+                                  are its vertices at the removal step */
 
 /* Region description.
  *   cosmology  SEMIPAR_FLAT, SEMIPAR_MATTER (a ∝ eta^2, H = 2/eta) or
@@ -163,7 +166,19 @@ typedef struct semipar_region_desc {
  *                 count (+64); 0 = defaults 4*n + 65536 and n/2 + 65536. A step that
  *                 overflows either buffer is not taken: the buffer is doubled and the
  *                 step is taken again from the same state, so results never depend on
- *                 these sizes. */
+ *                 these sizes.
+ *   loop_every    loop record and removal (Section "Semi-parallel cosmic string
+ *                 simulation": loops that cannot intersect again are logged and taken
+ *                 out of the simulation). 0: off. P > 0: before every step n with
+ *                 n - n0 a positive multiple of P (n0 the slice of the initial
+ *                 surfaces), every closed chain of still-advancing points is tested;
+ *                 a chain of L points is recorded (semipar_loop) and its points stop
+ *                 (flag REMOVED, no owning face) when no accepted event touched any
+ *                 of its elements in steps n - L .. n - 1 (one period of a flat-space
+ *                 loop of L points) and every point lies within a quarter of the box,
+ *                 per axis, of the chain's lowest slot (a string winding the box never
+ *                 does). Events are tracked from init, whatever this field was in
+ *                 earlier calls. */
 typedef struct semipar_evolve_params {
   int64_t max_steps;
   double t_end;
@@ -181,6 +196,8 @@ typedef struct semipar_evolve_params {
   int32_t screen_split;   /* threads sharing the 5 neighbour-pencil lookups of one
                              element in the screen: 1 or 5 (any other value = 5).
                              Performance only */
+  int32_t loop_every;     /* loop record and removal period P in steps (0: off) */
+  int32_t reserved;       /* 0 */
 } semipar_evolve_params;
 
 /* kernels that can be timed through semipar_evolve_params.timed_kernel */
@@ -206,7 +223,27 @@ typedef struct semipar_evolve_stats {
   double elapsed_ms;      /* device time of the call's step loop (HIP events) */
   double timed_kernel_ms; /* summed device time of the timed kernel (HIP events) */
   int64_t timed_kernel_launches; /* launches of the timed kernel that did work */
+  int64_t loops;          /* loops recorded and removed */
+  int64_t loop_points;    /* points they held */
 } semipar_evolve_stats;
+
+/* A loop recorded and removed (48 bytes).
+ *   step      slice n at which it was removed (the check before step n)
+ *   n_points  its number of points L
+ *   rep_id    id of its point in the lowest slot (input record order)
+ *   energy    sum over its points k, j = next(k), of |X[n][k] - X[n-1][j]| +
+ *             |X[n][j] - X[n-1][j]| (spatial parts, the first to the nearest periodic
+ *             image): the string length of its last band, the invariant energy of a
+ *             flat-space loop
+ *   centre    mean spatial position of its points on slice n, each taken at the
+ *             periodic image nearest the lowest slot's point
+ * Energy and centre are FP64 sums in an unspecified order (not bitwise
+ * reproducible); step, n_points and rep_id are exact. */
+typedef struct semipar_loop {
+  int32_t step, n_points;
+  int64_t rep_id;
+  double energy, centre[3];
+} semipar_loop;
 
 typedef struct semipar_region semipar_region;
 
@@ -236,12 +273,20 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
  * point goes to out[0] (x = current slice, x_prev = previous slice); n[1..3] = 0.
  * A bounded region writes each stopped point to out[f], f its face (flags FROZEN,
  * HAS_R when r holds the right neighbour's inputs); points without an owning face and
- * points still active (ACTIVE, when max_steps ended the call) go to out[0].
+ * points still active (ACTIVE, when max_steps ended the call) go to out[0]. Points of
+ * a removed loop (flag REMOVED, either kind of region) go to out[0] with their
+ * vertices at the removal step.
  * Two-call pattern: with out[f] == NULL the counts are returned in n[f]. cap[f] is
  * the capacity of out[f] in records; a short buffer gives SEMIPAR_E_ARG. mem says
  * whether the out pointers are host or device memory. Records are in slot order. */
 int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4],
                                const int64_t cap[4], int64_t n[4], int32_t mem);
+
+/* Copy the loop log (every loop recorded and removed since init) into host memory,
+ * sorted by (step, rep_id). buf == NULL returns the count in *n only; otherwise at
+ * most cap loops are written and *n is the number written. Errors: SEMIPAR_E_ARG,
+ * SEMIPAR_E_HIP. */
+int region_loops(const semipar_region* r, semipar_loop* buf, int64_t cap, int64_t* n);
 
 /* Copy the event log (all intercommutations since init) into host memory, sorted by
  * (step, t_star, id_a, id_b). buf == NULL returns the count in *n only; otherwise at
@@ -343,6 +388,13 @@ typedef struct semipar_sched_params {
                         with a stream of its own (0 or 1: one after another on the
                         tiling's stream). Batches go to lanes longest predicted first. */
   int32_t reserved;
+  semipar_loop* loops;  /* host loop buffer (evolve.loop_every > 0), capacity loops_cap,
+                           and n_regions + 1 offsets loops_off: region r's loops, sorted
+                           by (step, rep_id), at loops_off[r] .. loops_off[r+1]. Offsets
+                           count every loop; entries past loops_cap are not written
+                           (stats.loops is the total). NULL: not returned. */
+  int64_t loops_cap;
+  int64_t* loops_off;
 } semipar_sched_params;
 
 typedef struct semipar_sched_stats {
@@ -358,6 +410,7 @@ typedef struct semipar_sched_stats {
   double timed_kernel_ms;        /* with evolve.timed_kernel set: summed device time of
                                     that kernel over all calls (HIP events) */
   int64_t timed_kernel_launches; /* and the number of its launches that did work */
+  int64_t loops;                 /* loops recorded and removed over all regions */
 } semipar_sched_stats;
 
 /* Run every region of the tiling on this GPU, in dependency order (paper: manager and

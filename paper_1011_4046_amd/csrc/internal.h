@@ -34,6 +34,11 @@ SP_HIDDEN int batch_stats(semipar_region* r, std::vector<int32_t>& steps,
 SP_HIDDEN int batch_events(semipar_region* r, std::vector<semipar_event>& ev,
                            std::vector<int64_t>& off);
 
+// Logged loops grouped by sub-region (sub-region q's at off[q] .. off[q+1]), each group
+// sorted by (step, rep_id).
+SP_HIDDEN int batch_loops(semipar_region* r, std::vector<semipar_loop>& lp,
+                          std::vector<int64_t>& off);
+
 // The 12 cost-model features of each sub-region's current surface (host, 12 n_sub).
 SP_HIDDEN int batch_features(semipar_region* r, float* feat);
 

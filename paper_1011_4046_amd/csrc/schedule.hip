@@ -78,6 +78,7 @@ struct Runner {
   const semipar_sched_params* p;
   std::vector<Slab> slab;
   std::vector<std::vector<semipar_event>> ev;  // per region
+  std::vector<std::vector<semipar_loop>> lp;   // per region
   semipar_sched_stats acc{};
   int32_t batch_id = 0;
   semipar_point_rec* tmp = nullptr;
@@ -134,6 +135,14 @@ struct Runner {
         if (ne > 0) rc = region_events(reg, ev[r].data(), ne, &ne);
       }
     }
+    if (rc == SEMIPAR_OK && p->loops) {
+      int64_t nl = 0;
+      rc = region_loops(reg, nullptr, 0, &nl);
+      if (rc == SEMIPAR_OK) {
+        lp[r].resize((size_t)nl);
+        if (nl > 0) rc = region_loops(reg, lp[r].data(), nl, &nl);
+      }
+    }
     std::vector<int32_t> steps;
     std::vector<int64_t> ps;
     if (rc == SEMIPAR_OK) rc = spi::batch_stats(reg, steps, ps);
@@ -144,6 +153,7 @@ struct Runner {
     acc.evolve_ms += es.elapsed_ms;
     acc.timed_kernel_ms += es.timed_kernel_ms;
     acc.timed_kernel_launches += es.timed_kernel_launches;
+    acc.loops += es.loops;
     acc.batches += 1;
     log_region(r, steps[0], ps[0], batch_id++, es.elapsed_ms);
     return SEMIPAR_OK;
@@ -218,6 +228,13 @@ struct Runner {
       for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i)
         ev[regs[i]].assign(e.begin() + off[i], e.begin() + off[i + 1]);
     }
+    if (rc == SEMIPAR_OK && p->loops) {
+      std::vector<semipar_loop> l;
+      std::vector<int64_t> off;
+      rc = spi::batch_loops(reg, l, off);
+      for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i)
+        lp[regs[i]].assign(l.begin() + off[i], l.begin() + off[i + 1]);
+    }
     std::vector<int32_t> steps;
     std::vector<int64_t> ps;
     if (rc == SEMIPAR_OK) rc = spi::batch_stats(reg, steps, ps);
@@ -230,6 +247,7 @@ struct Runner {
     acc.evolve_ms += es.elapsed_ms;
     acc.timed_kernel_ms += es.timed_kernel_ms;
     acc.timed_kernel_launches += es.timed_kernel_launches;
+    acc.loops += es.loops;
     acc.batches += 1;
     for (size_t i = 0; i < regs.size(); ++i)
       log_region(regs[i], steps[i], ps[i], batch_id, es.elapsed_ms);
@@ -377,6 +395,8 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
                               p->out_mem != SEMIPAR_MEM_DEVICE))
     return SEMIPAR_E_ARG;
   if (p->events && (!p->events_off || p->events_cap < 0)) return SEMIPAR_E_ARG;
+  if (p->loops && (!p->loops_off || p->loops_cap < 0)) return SEMIPAR_E_ARG;
+  if (p->evolve.loop_every < 0) return SEMIPAR_E_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   Runner R;
   R.t = t;
@@ -384,6 +404,7 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
   const int nr = t->n_regions;
   R.slab.resize(nr);
   R.ev.resize(nr);
+  R.lp.resize(nr);
   int64_t base = 0;
   for (int r = 0; r < nr; ++r) {
     R.slab[r].base = base;
@@ -427,6 +448,17 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
   }
   if (p->events) p->events_off[nr] = ne;
   R.acc.events = ne;
+  int64_t nl = 0;
+  for (int r = 0; r < nr; ++r) {
+    const int64_t m = (int64_t)R.lp[r].size();
+    if (p->loops) {
+      p->loops_off[r] = nl;
+      const int64_t fit = std::max<int64_t>(0, std::min(m, p->loops_cap - nl));
+      if (fit > 0) memcpy(p->loops + nl, R.lp[r].data(), sizeof(semipar_loop) * fit);
+    }
+    nl += m;
+  }
+  if (p->loops) p->loops_off[nr] = nl;
   R.acc.makespan_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (st) *st = R.acc;

@@ -199,6 +199,14 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
+// True when every active lane of the wave holds the same key (sub-region, chain) as lane 0.
+__device__ __forceinline__ bool wave_uniform(int q, bool live) {
+  const int q0 = __shfl(q, 0, 64);
+  const uint64_t live_m = __ballot(live);
+  const uint64_t same_m = __ballot(live && q == q0);
+  return live_m == same_m && (live_m & 1ull);
+}
+
 __device__ __forceinline__ uint32_t pack_cell(int x, int y, int z) {
   return (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
 }
@@ -346,10 +354,12 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   const int ii = it * span + blockIdx.x * NT + threadIdx.x;
   const int k = ii < n ? ii : n;
   uint64_t xk = 0;  // this point's element extent
-  // a point of a bounded region that stopped before this step has nothing to do (its
+  // a point of a bounded region that stopped before this step, or a point of a removed
+  // loop (fstep is then passed for a whole-volume region too), has nothing to do (its
   // element cell already reads NO_ELEM)
   bool live_pt = k < n;
   if constexpr (BND) live_pt = live_pt && fstep[k] == FS_ACTIVE;
+  else live_pt = live_pt && (!fstep || fstep[k] == FS_ACTIVE);
   if (live_pt) {
     bool adv = true;
     int j = nxt[k];
@@ -1093,7 +1103,7 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     int cap_evt, int cap_cand, uint64_t* __restrict__ best, int32_t* __restrict__ used,
     int8_t* __restrict__ evs, semipar_event* __restrict__ log, int64_t log_cap,
     const uint64_t* __restrict__ blkred, int nblk, Ctrl* ctrl, const int32_t* __restrict__ rid,
-    int32_t* __restrict__ log_rid) {
+    int32_t* __restrict__ log_rid, int32_t* __restrict__ lev) {
   __shared__ int s_live;
   __shared__ int s_nacc;
   __shared__ uint64_t s_min[RESOLVE_NT / 64], s_max[RESOLVE_NT / 64], s_adv[RESOLVE_NT / 64];
@@ -1182,6 +1192,8 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
         o.x_star[2] = ev[e].z;
         log[log0 + i] = o;
         if (log_rid) log_rid[log0 + i] = rid[a];
+        lev[a] = n_step;
+        lev[b] = n_step;
       }
   }
   // smallest t of the slice written by this step's k_evolve, largest element extent
@@ -1291,6 +1303,218 @@ __global__ __launch_bounds__(1024) void k_begin_set(Ctrl* ctrl, int32_t step_lim
   ctrl->n_large = 0;
   const double tmin = a ? from_key(m) : 0.0;
   ctrl->done = (a == 0 || ctrl->step >= step_limit || tmin >= t_end) ? 1 : 0;
+}
+
+// ---- loop record and removal ---------------------------------------------------------
+// Section "Semi-parallel cosmic string simulation": a loop that will not meet anything
+// again is logged and taken out. Chains of still-advancing points are labelled by list
+// ranking (pointer doubling): after R rounds with 2^R >= n, lab[k] is the smallest slot
+// of k's chain when the chain closes on itself through advancing points, else LAB_OPEN
+// (following next from k reaches a point whose right neighbour is missing or stopped).
+// Links form a partial permutation (init checks the next/prev pairing and a partner
+// exchange keeps it), so every chain is a cycle or a path.
+constexpr int32_t LAB_OPEN = -1;
+constexpr int32_t LAB_NONE = -2;  // the point no longer advances
+
+// Nearest periodic image of a spatial difference, as d - L rint(d / L).
+__device__ __forceinline__ double wrap_box(double d, double box) {
+  return d - box * rint(d / box);
+}
+
+__global__ __launch_bounds__(NT) void k_loop_init(int n, const int32_t* __restrict__ nxt,
+                                                  const int32_t* __restrict__ fstep,
+                                                  int32_t* __restrict__ lab,
+                                                  int32_t* __restrict__ ptr,
+                                                  int32_t* __restrict__ lcnt,
+                                                  int32_t* __restrict__ levm,
+                                                  int32_t* __restrict__ lbad) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  int32_t l = LAB_NONE, q = k;
+  if (fstep[k] == FS_ACTIVE) {
+    const int j = nxt[k];
+    const bool end = j < 0 || fstep[j] != FS_ACTIVE;
+    l = end ? LAB_OPEN : k;
+    q = end ? k : j;  // a chain's end points to itself
+  }
+  lab[k] = l;
+  ptr[k] = q;
+  lcnt[k] = 0;
+  levm[k] = INT32_MIN;
+  lbad[k] = 0;
+}
+
+// One doubling round: lab covers 2^(r+1) successors, ptr jumps 2^(r+1) links.
+__global__ __launch_bounds__(NT) void k_loop_jump(int n, const int32_t* __restrict__ lab_in,
+                                                  const int32_t* __restrict__ ptr_in,
+                                                  int32_t* __restrict__ lab_out,
+                                                  int32_t* __restrict__ ptr_out) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const int32_t l = lab_in[k];
+  const int q = ptr_in[k];
+  if (l == LAB_NONE) {
+    lab_out[k] = LAB_NONE;
+    ptr_out[k] = q;
+    return;
+  }
+  const int32_t lq = lab_in[q];
+  lab_out[k] = lq < l ? lq : l;
+  ptr_out[k] = ptr_in[q];
+}
+
+// Per closed chain (indexed by its lowest slot): point count, latest event step, and
+// whether some point lies a quarter box or more from the lowest slot's point (per axis,
+// nearest image). One atomic per wave where the wave holds one chain.
+__global__ __launch_bounds__(NT) void k_loop_gather(int n, int s, Slices X,
+                                                    const int32_t* __restrict__ lab,
+                                                    const int32_t* __restrict__ lev, double box,
+                                                    int32_t* __restrict__ lcnt,
+                                                    int32_t* __restrict__ levm,
+                                                    int32_t* __restrict__ lbad) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const int32_t q = k < n ? lab[k] : LAB_NONE;
+  const bool live = q >= 0;
+  int32_t e = INT32_MIN, bad = 0;
+  if (live) {
+    const int ic = s % 3;
+    const V4 a = ld(X, ic, k), b = ld(X, ic, q);
+    const double lim = 0.25 * box;
+    bad = (fabs(wrap_box(a.x - b.x, box)) < lim && fabs(wrap_box(a.y - b.y, box)) < lim &&
+           fabs(wrap_box(a.z - b.z, box)) < lim)
+              ? 0
+              : 1;
+    e = lev[k];
+  }
+  if (wave_uniform(q, live)) {
+    int32_t c = live ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) {
+      c += __shfl_xor(c, o, 64);
+      const int32_t e2 = __shfl_xor(e, o, 64);
+      e = e2 > e ? e2 : e;
+      bad |= __shfl_xor(bad, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&lcnt[q], c);
+      atomicMax(&levm[q], e);
+      if (bad) atomicOr(&lbad[q], 1);
+    }
+  } else if (live) {
+    atomicAdd(&lcnt[q], 1);
+    atomicMax(&levm[q], e);
+    if (bad) atomicOr(&lbad[q], 1);
+  }
+}
+
+// Decision per closed chain of L points at the start of step s: removed when compact
+// and no event in steps s - L .. s - 1 (s - latest > L). Accepted chains get a loop
+// index (completion order); ctr[0] counts loops, ctr[1] their points.
+__global__ __launch_bounds__(NT) void k_loop_decide(int n, int s, const int32_t* __restrict__ lab,
+                                                    const int32_t* __restrict__ lcnt,
+                                                    const int32_t* __restrict__ levm,
+                                                    const int32_t* __restrict__ lbad,
+                                                    int32_t* __restrict__ lidx,
+                                                    int32_t* __restrict__ lrep,
+                                                    int32_t* __restrict__ ctr) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n || lab[k] != k) return;
+  const int32_t L = lcnt[k];
+  int32_t li = -1;
+  if (!lbad[k] && (int64_t)s - (int64_t)levm[k] > (int64_t)L) {
+    li = atomicAdd(&ctr[0], 1);
+    atomicAdd(&ctr[1], L);
+    lrep[li] = k;
+  }
+  lidx[k] = li;
+}
+
+// Points of accepted loops: energy and centre sums, then the point stops at slice s
+// (record flagged REMOVED, no owning face, no element from now on).
+__global__ __launch_bounds__(NT) void k_loop_apply(int n, int s, Slices X,
+                                                   const int32_t* __restrict__ lab,
+                                                   const int32_t* __restrict__ lidx,
+                                                   const int32_t* __restrict__ nxt,
+                                                   const int32_t* __restrict__ prv,
+                                                   const int64_t* __restrict__ id, double box,
+                                                   double* __restrict__ lacc,
+                                                   semipar_point_rec* __restrict__ frz,
+                                                   int32_t* __restrict__ fstep,
+                                                   int32_t* __restrict__ face,
+                                                   int32_t* __restrict__ ecell) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const int32_t q = k < n ? lab[k] : LAB_NONE;
+  const int32_t li = q >= 0 ? lidx[q] : -1;
+  const bool live = li >= 0;
+  double e = 0.0, c[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    const int ic = s % 3, ip = (s + 2) % 3;
+    const int j = nxt[k];
+    const V4 a = ld(X, ic, k), aj = ld(X, ic, j), pj = ld(X, ip, j), r0 = ld(X, ic, q);
+    const double d0 = wrap_box(a.x - pj.x, box), d1 = wrap_box(a.y - pj.y, box),
+                 d2 = wrap_box(a.z - pj.z, box);
+    const double f0 = aj.x - pj.x, f1 = aj.y - pj.y, f2 = aj.z - pj.z;
+    e = sqrt(d0 * d0 + d1 * d1 + d2 * d2) + sqrt(f0 * f0 + f1 * f1 + f2 * f2);
+    c[0] = wrap_box(a.x - r0.x, box);
+    c[1] = wrap_box(a.y - r0.y, box);
+    c[2] = wrap_box(a.z - r0.z, box);
+    semipar_point_rec r;
+    r.id = id[k];
+    const int pk = prv[k];
+    r.next_id = id[j];
+    r.prev_id = pk >= 0 ? id[pk] : -1;
+    r.step = s;
+    r.flags = SEMIPAR_FLAG_REMOVED;
+    const V4 b = ld(X, ip, k);
+    r.x[0] = a.x; r.x[1] = a.y; r.x[2] = a.z; r.x[3] = a.t;
+    r.x_prev[0] = b.x; r.x_prev[1] = b.y; r.x_prev[2] = b.z; r.x_prev[3] = b.t;
+    for (int i = 0; i < 4; ++i) {
+      r.r[i] = 0.0;
+      r.r_prev[i] = 0.0;
+    }
+    frz[k] = r;
+    fstep[k] = s;
+    face[k] = -1;
+    if (ecell) ecell[k] = NO_ELEM;
+  }
+  if (wave_uniform(li, live)) {
+    for (int o = 32; o > 0; o >>= 1) {
+      e += __shfl_xor(e, o, 64);
+      for (int i = 0; i < 3; ++i) c[i] += __shfl_xor(c[i], o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&lacc[4 * li], e);
+      for (int i = 0; i < 3; ++i) atomicAdd(&lacc[4 * li + 1 + i], c[i]);
+    }
+  } else if (live) {
+    atomicAdd(&lacc[4 * li], e);
+    for (int i = 0; i < 3; ++i) atomicAdd(&lacc[4 * li + 1 + i], c[i]);
+  }
+}
+
+// Loop records: centre = lowest slot's point + mean nearest-image displacement.
+__global__ __launch_bounds__(NT) void k_loop_final(int nl, int s, Slices X,
+                                                   const int32_t* __restrict__ lrep,
+                                                   const int32_t* __restrict__ lcnt,
+                                                   const int64_t* __restrict__ id,
+                                                   const double* __restrict__ lacc,
+                                                   const int32_t* __restrict__ rid,
+                                                   semipar_loop* __restrict__ out,
+                                                   int32_t* __restrict__ out_rid) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= nl) return;
+  const int q = lrep[i];
+  const int32_t L = lcnt[q];
+  const V4 r0 = ld(X, s % 3, q);
+  semipar_loop o;
+  o.step = s;
+  o.n_points = L;
+  o.rep_id = id[q];
+  o.energy = lacc[4 * i];
+  o.centre[0] = r0.x + lacc[4 * i + 1] / (double)L;
+  o.centre[1] = r0.y + lacc[4 * i + 2] / (double)L;
+  o.centre[2] = r0.z + lacc[4 * i + 3] / (double)L;
+  out[i] = o;
+  if (out_rid) out_rid[i] = rid ? rid[q] : 0;
 }
 
 // Local grids of the sub-regions of a batch for the next step (one workgroup). h_set > 0:
@@ -1423,7 +1647,8 @@ __global__ __launch_bounds__(NT) void k_init_links(const semipar_point_rec* __re
                                                    const int32_t* __restrict__ hval,
                                                    uint32_t hmask, Slices X, int32_t* nxt,
                                                    int32_t* prv, int64_t* id, int bounded,
-                                                   int32_t* fstep, int32_t* face, Ctrl* ctrl) {
+                                                   int32_t* fstep, int32_t* face, int32_t* lev,
+                                                   Ctrl* ctrl) {
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k >= n) return;
   const semipar_point_rec r = rec[k];
@@ -1431,11 +1656,12 @@ __global__ __launch_bounds__(NT) void k_init_links(const semipar_point_rec* __re
   if (s != rec[0].step || s < 1) atomicOr(&ctrl->err, 8);
   const int a = id_lookup(hkey, hval, hmask, r.next_id);
   const int b = id_lookup(hkey, hval, hmask, r.prev_id);
+  fstep[k] = FS_ACTIVE;
+  face[k] = -1;
+  lev[k] = s - 1;  // no event yet: as if the last one were before the initial slice
   if (bounded) {
     nxt[k] = a;
     prv[k] = b;
-    fstep[k] = FS_ACTIVE;
-    face[k] = -1;
   } else {
     if (a < 0 || b < 0) atomicOr(&ctrl->err, 16);
     nxt[k] = a < 0 ? k : a;
@@ -1474,8 +1700,8 @@ __global__ __launch_bounds__(NT) void k_init_check(Slices X, int n, const int32_
 }
 
 // Output record of slot k and the surface stream it goes to: a stopped point of a
-// bounded region goes to its face (no owning face: stream 0); a point still on the
-// current slice goes to stream 0 (flag ACTIVE in a bounded region).
+// bounded region goes to its face (no owning face, or a removed loop: stream 0); a
+// point still on the current slice goes to stream 0 (flag ACTIVE in a bounded region).
 __device__ __forceinline__ int emit_stream(int k, const int32_t* fstep,
                                            const semipar_point_rec* frz) {
   if (fstep && fstep[k] != FS_ACTIVE) {
@@ -1561,6 +1787,7 @@ __global__ __launch_bounds__(NT) void k_emit_write(Slices X, int n, int s, const
                                                    const semipar_point_rec* frz,
                                                    const int32_t* __restrict__ blkoff,
                                                    const int32_t* __restrict__ tot,
+                                                   int32_t act_flags,
                                                    semipar_point_rec* __restrict__ out) {
   __shared__ int32_t sh[4][NT];
   const int t = threadIdx.x;
@@ -1582,7 +1809,7 @@ __global__ __launch_bounds__(NT) void k_emit_write(Slices X, int n, int s, const
   if (fstep && fstep[k] != FS_ACTIVE)
     out[pos] = frz[k];
   else
-    out[pos] = current_record(X, k, s, nxt, prv, id, fstep ? SEMIPAR_FLAG_ACTIVE : 0);
+    out[pos] = current_record(X, k, s, nxt, prv, id, act_flags);
 }
 
 // ---- batches of sub-regions: per-sub-region results -------------------------------
@@ -1642,14 +1869,6 @@ __global__ __launch_bounds__(NT) void k_emit_sub_write(Slices X, int n, int s, c
     out[pos] = frz[k];
   else
     out[pos] = current_record(X, k, s, nxt, prv, id, SEMIPAR_FLAG_ACTIVE);
-}
-
-// True when every active lane of the wave holds the same sub-region as lane 0.
-__device__ __forceinline__ bool wave_uniform(int q, bool live) {
-  const int q0 = __shfl(q, 0, 64);
-  const uint64_t live_m = __ballot(live);
-  const uint64_t same_m = __ballot(live && q == q0);
-  return live_m == same_m && (live_m & 1ull);
 }
 
 // Per sub-region: point-steps (sum over its points of the slices advanced) and the
@@ -1925,6 +2144,19 @@ struct semipar_region {
   // measurement: HIP events around every launch of one kernel (timed_kernel)
   int timed = -1;
   std::vector<hipEvent_t> tev;
+  // loop record and removal
+  int32_t* lev = nullptr;  // step of the last accepted event touching each point's element
+  bool removed = false;    // a loop was removed: whole-volume kernels then read fstep
+  int32_t *lab[2] = {nullptr, nullptr}, *lptr[2] = {nullptr, nullptr};  // list ranking
+  int32_t *lcnt = nullptr, *levm = nullptr, *lbad = nullptr;  // per chain (lowest slot)
+  int32_t *lidx = nullptr, *lrep = nullptr;  // chain -> loop index, loop index -> chain
+  int32_t* lctr = nullptr;                   // loops and points of one check
+  int32_t* lctr_h = nullptr;                 // pinned mirror
+  double* lacc = nullptr;                    // per loop of one check: energy, centre sums
+  int64_t lacc_cap = 0;
+  semipar_loop* llog = nullptr;  // loop log (completion order within a check)
+  int32_t* llog_rid = nullptr;   // sub-region of each logged loop (batches; else 0)
+  int64_t llog_n = 0, llog_cap = 0;
 };
 
 namespace {
@@ -2101,8 +2333,8 @@ template <bool FRW, int SCR, bool BND>
 void launch_evolve_t(semipar_region* r, int n, int nb) {
   k_evolve<FRW, SCR, BND><<<nb, NT, 0, r->stream>>>(
       r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell, r->epos,
-      r->cnt, r->large, r->blkred, r->fstep, r->face, r->frz, r->geom, r->geoms, r->rid, r->rcell,
-      r->rext);
+      r->cnt, r->large, r->blkred, (BND || r->removed) ? r->fstep : nullptr, r->face, r->frz,
+      r->geom, r->geoms, r->rid, r->rcell, r->rext);
 }
 
 template <bool FRW, bool BND>
@@ -2180,7 +2412,7 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
   mark(r, SEMIPAR_K_RESOLVE, 2 * i);
   k_resolve<<<1, RESOLVE_NT, 0, s>>>(r->nxt, r->prv, r->ev, (int)r->cap_evt, (int)r->cap_cand,
                                      r->best, r->used, r->evs, r->log, r->log_cap, r->blkred, nbe,
-                                     r->ctrl, r->rid, r->log_rid);
+                                     r->ctrl, r->rid, r->log_rid, r->lev);
   if (intercommute && r->rcell)
     k_rcells<<<1, 1024, 0, s>>>(r->geoms, r->n_sub, r->rext, r->rcell, r->rc_fixed_h, r->ctrl);
   mark(r, SEMIPAR_K_RESOLVE, 2 * i + 1);
@@ -2197,6 +2429,103 @@ __global__ void k_clear_defer(Ctrl* ctrl) {
     ctrl->defer = 0;
     ctrl->done = 0;
   }
+}
+
+// Per-point stop state the kernels read: always for a bounded region, and for a
+// whole-volume region once a loop has been removed from it.
+const int32_t* stop_state(const semipar_region* r) {
+  return (r->bounded || r->removed) ? r->fstep : nullptr;
+}
+
+int loop_setup(semipar_region* r) {
+  if (r->lab[0]) return SEMIPAR_OK;
+  const int64_t cap = std::max<int64_t>(r->cap, 1);
+  if (!r->frz) HIPCHK(dalloc(&r->frz, cap));
+  for (int i = 0; i < 2; ++i) {
+    HIPCHK(dalloc(&r->lab[i], cap));
+    HIPCHK(dalloc(&r->lptr[i], cap));
+  }
+  HIPCHK(dalloc(&r->lcnt, cap));
+  HIPCHK(dalloc(&r->levm, cap));
+  HIPCHK(dalloc(&r->lbad, cap));
+  HIPCHK(dalloc(&r->lidx, cap));
+  HIPCHK(dalloc(&r->lrep, cap));
+  HIPCHK(dalloc(&r->lctr, 2));
+  HIPCHK(hipHostMalloc((void**)&r->lctr_h, 2 * sizeof(int32_t), hipHostMallocDefault));
+  return SEMIPAR_OK;
+}
+
+int grow_loop_log(semipar_region* r, int64_t need) {
+  if (r->llog_cap >= need) return SEMIPAR_OK;
+  const int64_t nc = std::max<int64_t>(need, std::max<int64_t>(2 * r->llog_cap, 1024));
+  semipar_loop* nl = nullptr;
+  int32_t* nr = nullptr;
+  HIPCHK(dalloc(&nl, nc));
+  HIPCHK(dalloc(&nr, nc));
+  if (r->llog_n > 0) {
+    HIPCHK(hipMemcpyAsync(nl, r->llog, sizeof(semipar_loop) * r->llog_n, hipMemcpyDeviceToDevice,
+                          r->stream));
+    HIPCHK(hipMemcpyAsync(nr, r->llog_rid, sizeof(int32_t) * r->llog_n, hipMemcpyDeviceToDevice,
+                          r->stream));
+  }
+  HIPCHK(hipStreamSynchronize(r->stream));
+  dfree(r->llog);
+  dfree(r->llog_rid);
+  r->llog = nl;
+  r->llog_rid = nr;
+  r->llog_cap = nc;
+  return SEMIPAR_OK;
+}
+
+// Loop record and removal at the start of step s (between steps, never inside a
+// captured graph). Adds the loops and points removed to *nl, *np.
+int loop_check(semipar_region* r, int32_t s, int64_t* nl, int64_t* np) {
+  RCCHK(loop_setup(r));
+  const int n = (int)r->n;
+  const int nb = blocks(n);
+  hipStream_t st = r->stream;
+  k_fill_i32<<<1, NT, 0, st>>>(r->lctr, 2, 0);
+  k_loop_init<<<nb, NT, 0, st>>>(n, r->nxt, r->fstep, r->lab[0], r->lptr[0], r->lcnt, r->levm,
+                                 r->lbad);
+  int c = 0;
+  for (int64_t span = 1; span < n; span <<= 1) {
+    k_loop_jump<<<nb, NT, 0, st>>>(n, r->lab[c], r->lptr[c], r->lab[c ^ 1], r->lptr[c ^ 1]);
+    c ^= 1;
+  }
+  k_loop_gather<<<nb, NT, 0, st>>>(n, s, r->X, r->lab[c], r->lev, r->box, r->lcnt, r->levm,
+                                   r->lbad);
+  k_loop_decide<<<nb, NT, 0, st>>>(n, s, r->lab[c], r->lcnt, r->levm, r->lbad, r->lidx, r->lrep,
+                                   r->lctr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(r->lctr_h, r->lctr, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int32_t loops = r->lctr_h[0], pts = r->lctr_h[1];
+  if (loops == 0) return SEMIPAR_OK;
+  if (r->lacc_cap < loops) {
+    dfree(r->lacc);
+    r->lacc = nullptr;
+    r->lacc_cap = 0;
+    const int64_t want = std::max<int64_t>(loops, 256);
+    HIPCHK(dalloc(&r->lacc, 4 * want));
+    r->lacc_cap = want;
+  }
+  RCCHK(grow_loop_log(r, r->llog_n + loops));
+  HIPCHK(hipMemsetAsync(r->lacc, 0, sizeof(double) * 4 * (size_t)loops, st));
+  k_loop_apply<<<nb, NT, 0, st>>>(n, s, r->X, r->lab[c], r->lidx, r->nxt, r->prv, r->id, r->box,
+                                  r->lacc, r->frz, r->fstep, r->face, r->ecell);
+  k_loop_final<<<blocks(loops), NT, 0, st>>>(loops, s, r->X, r->lrep, r->lcnt, r->id, r->lacc,
+                                             r->rid, r->llog + r->llog_n,
+                                             r->llog_rid + r->llog_n);
+  HIPCHK(hipGetLastError());
+  r->llog_n += loops;
+  *nl += loops;
+  *np += pts;
+  if (!r->removed) {
+    // launches captured so far pass no stop state to whole-volume kernels
+    r->removed = true;
+    drop_graph(r);
+  }
+  return SEMIPAR_OK;
 }
 
 }  // namespace
@@ -2242,6 +2571,21 @@ void region_destroy(semipar_region* r) {
   dfree(r->log_rid);
   dfree(r->rcell);
   dfree(r->rext);
+  dfree(r->lev);
+  for (int i = 0; i < 2; ++i) {
+    dfree(r->lab[i]);
+    dfree(r->lptr[i]);
+  }
+  dfree(r->lcnt);
+  dfree(r->levm);
+  dfree(r->lbad);
+  dfree(r->lidx);
+  dfree(r->lrep);
+  dfree(r->lctr);
+  dfree(r->lacc);
+  dfree(r->llog);
+  dfree(r->llog_rid);
+  if (r->lctr_h) (void)hipHostFree(r->lctr_h);
   if (r->ctrl_h) (void)hipHostFree(r->ctrl_h);
   if (r->ev0) (void)hipEventDestroy(r->ev0);
   if (r->ev1) (void)hipEventDestroy(r->ev1);
@@ -2313,7 +2657,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       dalloc(&r->id, cap) != hipSuccess || dalloc(&r->ctrl, 1) != hipSuccess ||
       dalloc(&r->blkred, 4 * (size_t)blocks(cap)) != hipSuccess ||
       dalloc(&r->fstep, cap) != hipSuccess || dalloc(&r->face, cap) != hipSuccess ||
-      (d->bounded && dalloc(&r->frz, cap) != hipSuccess))
+      dalloc(&r->lev, cap) != hipSuccess || (d->bounded && dalloc(&r->frz, cap) != hipSuccess))
     return fail(SEMIPAR_E_OOM);
   if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
     return fail(SEMIPAR_E_OOM);
@@ -2404,7 +2748,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
                                                      r->ctrl);
       k_init_links<<<blocks(n), NT, 0, r->stream>>>(drec, n, hkey, hval, (uint32_t)(hcap - 1), r->X,
                                                     r->nxt, r->prv, r->id, r->bounded ? 1 : 0,
-                                                    r->fstep, r->face, r->ctrl);
+                                                    r->fstep, r->face, r->lev, r->ctrl);
       k_init_check<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->nxt, r->prv, r->P, c0.step,
                                                     r->ctrl);
       if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
@@ -2427,7 +2771,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
 }
 
 int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evolve_stats* st) {
-  if (!r || !p || p->max_steps < 0) return SEMIPAR_E_ARG;
+  if (!r || !p || p->max_steps < 0 || p->loop_every < 0) return SEMIPAR_E_ARG;
   if (p->screen != SEMIPAR_SCREEN_F64 && p->screen != SEMIPAR_SCREEN_F32) return SEMIPAR_E_ARG;
   if (r->broken) return SEMIPAR_E_STATE;
   semipar_evolve_stats zero{};
@@ -2461,9 +2805,26 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   }
   double tk_ms = 0.0;
   int64_t tk_n = 0;
+  // Loop checks come before every step n with n - n0 a positive multiple of P: the
+  // steps run in segments that end at the next such n (or at the call's limit).
+  const int32_t P = p->loop_every;
+  const int32_t s0 = r->step0;
+  auto is_check = [&](int32_t s) {
+    return P > 0 && s > s0 && ((int64_t)s - s0) % P == 0;
+  };
+  auto seg_limit = [&](int32_t s) -> int32_t {
+    if (P <= 0) return step_limit;
+    const int64_t c = (int64_t)s0 + (((int64_t)s - s0) / P + 1) * (int64_t)P;
+    return (int32_t)std::min<int64_t>(c, step_limit);
+  };
+  int64_t n_loops = 0, n_lpts = 0;
+  int32_t checked = INT32_MIN;
   HIPCHK(hipEventRecord(r->ev0, r->stream));
-  k_begin_min<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->bounded ? r->fstep : nullptr,
-                                                r->blkred, r->ctrl);
+  if (is_check(before.step)) {
+    RCCHK(loop_check(r, before.step, &n_loops, &n_lpts));
+    checked = before.step;
+  }
+  k_begin_min<<<blocks(n), NT, 0, r->stream>>>(r->X, n, stop_state(r), r->blkred, r->ctrl);
   // grid of the first step: the caller's cell size (kept fixed), else 1.25 x the
   // initial element-size estimate, then adapted each step to the largest element
   Cells cells{};
@@ -2480,8 +2841,8 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     r->cells_set = true;
     r->cells_fixed = false;
   }
-  k_begin_set<<<1, 1024, 0, r->stream>>>(r->ctrl, step_limit, p->t_end, r->blkred, blocks(n),
-                                         cells, set_cells);
+  k_begin_set<<<1, 1024, 0, r->stream>>>(r->ctrl, seg_limit(before.step), p->t_end, r->blkred,
+                                         blocks(n), cells, set_cells);
   if (r->rcell) {
     // batch: every sub-region starts with cells fitting the largest initial element
     // (or the fixed size), then follows its own elements
@@ -2544,7 +2905,21 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
       RCCHK(read_ctrl(r));
       continue;
     }
-    if (c.done) break;
+    if (c.done) {
+      const int32_t s = c.step;
+      if (is_check(s) && s < step_limit && s != checked) {
+        // end of a segment: check, then the stop rule over the points still advancing
+        RCCHK(loop_check(r, s, &n_loops, &n_lpts));
+        checked = s;
+        k_begin_min<<<blocks(n), NT, 0, r->stream>>>(r->X, n, stop_state(r), r->blkred, r->ctrl);
+        k_begin_set<<<1, 1024, 0, r->stream>>>(r->ctrl, seg_limit(s), p->t_end, r->blkred,
+                                               blocks(n), Cells{}, 0);
+        HIPCHK(hipGetLastError());
+        RCCHK(read_ctrl(r));
+        if (!r->ctrl_h->done) continue;
+      }
+      break;
+    }
   }
   HIPCHK(hipEventRecord(r->ev1, r->stream));
   HIPCHK(hipEventSynchronize(r->ev1));
@@ -2563,6 +2938,8 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     st->elapsed_ms = ms;
     st->timed_kernel_ms = tk_ms;
     st->timed_kernel_launches = tk_n;
+    st->loops = n_loops;
+    st->loop_points = n_lpts;
   }
   return SEMIPAR_OK;
 }
@@ -2577,7 +2954,7 @@ int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], con
   const int s = r->ctrl_h->step;
   const int nn = (int)r->n;
   const int nb = blocks(nn);
-  const int32_t* fs = r->bounded ? r->fstep : nullptr;
+  const int32_t* fs = stop_state(r);
   int32_t *blkcnt = nullptr, *blkoff = nullptr, *tot = nullptr;
   semipar_point_rec* tmp = nullptr;
   int rc = SEMIPAR_OK;
@@ -2602,7 +2979,8 @@ int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], con
       if (dalloc(&tmp, r->n) != hipSuccess) rc = SEMIPAR_E_OOM;
       if (rc == SEMIPAR_OK) {
         k_emit_write<<<nb, NT, 0, r->stream>>>(r->X, nn, s, r->nxt, r->prv, r->id, fs, r->frz,
-                                               blkoff, tot, tmp);
+                                               blkoff, tot,
+                                               r->bounded ? SEMIPAR_FLAG_ACTIVE : 0, tmp);
         if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
         int64_t off = 0;
         const hipMemcpyKind kind =
@@ -2623,6 +3001,29 @@ int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], con
   dfree(tot);
   dfree(tmp);
   return rc;
+}
+
+int region_loops(const semipar_region* r, semipar_loop* buf, int64_t cap, int64_t* n) {
+  if (!r || !n || cap < 0) return SEMIPAR_E_ARG;
+  const int64_t total = r->llog_n;
+  if (!buf) {
+    *n = total;
+    return SEMIPAR_OK;
+  }
+  std::vector<semipar_loop> all((size_t)total);
+  if (total > 0) {
+    HIPCHK(hipMemcpyAsync(all.data(), r->llog, sizeof(semipar_loop) * total, hipMemcpyDeviceToHost,
+                          r->stream));
+    HIPCHK(hipStreamSynchronize(r->stream));
+  }
+  std::sort(all.begin(), all.end(), [](const semipar_loop& a, const semipar_loop& b) {
+    if (a.step != b.step) return a.step < b.step;
+    return a.rep_id < b.rep_id;
+  });
+  const int64_t m = std::min(total, cap);
+  if (m > 0) memcpy(buf, all.data(), sizeof(semipar_loop) * m);
+  *n = m;
+  return SEMIPAR_OK;
 }
 
 int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int64_t* n) {
@@ -2667,6 +3068,15 @@ int region_prepare(semipar_region* r, const semipar_evolve_params* p) {
   if (r->n == 0) return SEMIPAR_OK;
   RCCHK(configure(r, p));
   RCCHK(read_ctrl(r));
+  if (p->loop_every > 0) {
+    // loop buffers up front (hipFree inside a check would wait for other lanes' work)
+    RCCHK(loop_setup(r));
+    RCCHK(grow_loop_log(r, 1024));
+    if (!r->lacc) {
+      HIPCHK(dalloc(&r->lacc, 4 * 1024));
+      r->lacc_cap = 1024;
+    }
+  }
   // the log size region_evolve asks for at its first block
   return ensure_log(r, r->ctrl_h->log_n + 2 * r->cap_evt);
 }
@@ -2835,6 +3245,36 @@ int batch_events(semipar_region* r, std::vector<semipar_event>& ev, std::vector<
   dfree(tmp);
   if (rc != SEMIPAR_OK) ev.clear();
   return rc;
+}
+
+int batch_loops(semipar_region* r, std::vector<semipar_loop>& lp, std::vector<int64_t>& off) {
+  if (!r || r->n_sub <= 0) return SEMIPAR_E_ARG;
+  const int ns = r->n_sub;
+  lp.clear();
+  off.assign((size_t)ns + 1, 0);
+  const int64_t total = r->llog_n;
+  if (total == 0) return SEMIPAR_OK;
+  std::vector<semipar_loop> all((size_t)total);
+  std::vector<int32_t> q((size_t)total);
+  HIPCHK(hipMemcpyAsync(all.data(), r->llog, sizeof(semipar_loop) * total, hipMemcpyDeviceToHost,
+                        r->stream));
+  HIPCHK(hipMemcpyAsync(q.data(), r->llog_rid, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
+                        r->stream));
+  HIPCHK(hipStreamSynchronize(r->stream));
+  std::vector<int64_t> ord((size_t)total);
+  for (int64_t i = 0; i < total; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+    if (q[a] != q[b]) return q[a] < q[b];
+    if (all[a].step != all[b].step) return all[a].step < all[b].step;
+    return all[a].rep_id < all[b].rep_id;
+  });
+  lp.resize((size_t)total);
+  for (int64_t i = 0; i < total; ++i) {
+    lp[i] = all[ord[i]];
+    off[q[ord[i]] + 1] += 1;
+  }
+  for (int i = 0; i < ns; ++i) off[i + 1] += off[i];
+  return SEMIPAR_OK;
 }
 
 int batch_features(semipar_region* r, float* feat) {

@@ -47,6 +47,13 @@ EVENT_DTYPE = np.dtype([
 ])
 assert EVENT_DTYPE.itemsize == 56
 
+# Loop record of the C ABI (48 bytes): a loop recorded and removed.
+LOOP_DTYPE = np.dtype([
+    ("step", "<i4"), ("n_points", "<i4"), ("rep_id", "<i8"),
+    ("energy", "<f8"), ("centre", "<f8", (3,)),
+])
+assert LOOP_DTYPE.itemsize == 48
+
 FLAT, MATTER, RADIATION = 0, 1, 2
 # H = HCOEF / eta in conformal time for a ∝ eta^HCOEF (matter: a ∝ eta^2).
 HCOEF = {FLAT: 0.0, MATTER: 2.0, RADIATION: 1.0}

@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-from .inputs import EVENT_DTYPE, REC_DTYPE
+from .inputs import EVENT_DTYPE, LOOP_DTYPE, REC_DTYPE
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsemipar.so")
@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsemipar.so")
 FLAT, MATTER, RADIATION = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 SCREEN_F64, SCREEN_F32 = 0, 1
+FLAG_HAS_R, FLAG_FROZEN, FLAG_ACTIVE, FLAG_REMOVED = 1, 2, 4, 8
 K_EVOLVE, K_SCAN, K_SCATTER, K_SCREEN, K_CONFIRM, K_RESOLVE = range(6)
 
 ERRORS = {0: "ok", -1: "E_ARG", -2: "E_SURFACE", -3: "E_OOM", -4: "E_HIP",
@@ -66,7 +67,8 @@ class EvolveParams(ctypes.Structure):
                 ("cell_size", ctypes.c_double), ("steps_per_sync", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("cand_per_point", ctypes.c_double),
                 ("events_per_point", ctypes.c_double), ("timed_kernel", ctypes.c_int32),
-                ("screen_split", ctypes.c_int32)]
+                ("screen_split", ctypes.c_int32), ("loop_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class EvolveStats(ctypes.Structure):
@@ -75,7 +77,8 @@ class EvolveStats(ctypes.Structure):
                 ("accepted", ctypes.c_int64), ("large_elements", ctypes.c_int64),
                 ("final_step", ctypes.c_int32), ("done", ctypes.c_int32),
                 ("elapsed_ms", ctypes.c_double), ("timed_kernel_ms", ctypes.c_double),
-                ("timed_kernel_launches", ctypes.c_int64)]
+                ("timed_kernel_launches", ctypes.c_int64), ("loops", ctypes.c_int64),
+                ("loop_points", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -97,7 +100,8 @@ class SchedParams(ctypes.Structure):
                 ("events_off", ctypes.c_void_p), ("region_steps", ctypes.c_void_p),
                 ("region_point_steps", ctypes.c_void_p), ("region_batch", ctypes.c_void_p),
                 ("region_ms", ctypes.c_void_p), ("lanes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("loops", ctypes.c_void_p),
+                ("loops_cap", ctypes.c_int64), ("loops_off", ctypes.c_void_p)]
 
 
 class SchedStats(ctypes.Structure):
@@ -105,7 +109,8 @@ class SchedStats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("point_steps", ctypes.c_int64),
                 ("steps", ctypes.c_int64), ("events", ctypes.c_int64),
                 ("makespan_ms", ctypes.c_double), ("evolve_ms", ctypes.c_double),
-                ("timed_kernel_ms", ctypes.c_double), ("timed_kernel_launches", ctypes.c_int64)]
+                ("timed_kernel_ms", ctypes.c_double), ("timed_kernel_launches", ctypes.c_int64),
+                ("loops", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -116,7 +121,7 @@ MLP_IN, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
 
 # exported symbols declared in include/semipar.h
 SYMBOLS = ["region_init_from_surfaces", "region_evolve", "region_emit_final_surfaces",
-           "region_events", "region_destroy", "semipar_strerror", "semipar_version",
+           "region_events", "region_loops", "region_destroy", "semipar_strerror", "semipar_version",
            "semipar_last_error", "schedule_regions", "semipar_region_features",
            "semipar_mlp_forward", "semipar_mlp_loss_grad", "semipar_mlp_adam_step",
            "semipar_mlp_train", "semipar_mlp_norm"]
@@ -142,6 +147,8 @@ def lib():
         L.region_emit_final_surfaces.restype = ctypes.c_int
         L.region_events.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.region_events.restype = ctypes.c_int
+        L.region_loops.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        L.region_loops.restype = ctypes.c_int
         L.region_destroy.argtypes = [P]
         L.region_destroy.restype = None
         L.semipar_strerror.argtypes = [ctypes.c_int]
@@ -249,11 +256,11 @@ class Region:
 
     def evolve(self, max_steps, t_end=float("inf"), screen=SCREEN_F64, intercommute=True,
                cell_size=0.0, steps_per_sync=0, use_graph=False, cand_per_point=0.0,
-               events_per_point=0.0, timed_kernel=-1, screen_split=0):
+               events_per_point=0.0, timed_kernel=-1, screen_split=0, loop_every=0):
         p = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
                          float(cell_size), int(steps_per_sync), int(bool(use_graph)),
                          float(cand_per_point), float(events_per_point), int(timed_kernel),
-                         int(screen_split))
+                         int(screen_split), int(loop_every), 0)
         st = EvolveStats()
         _check(lib().region_evolve(self.h, ctypes.byref(p), ctypes.byref(st)), "region_evolve")
         return st.as_dict()
@@ -291,6 +298,17 @@ class Region:
         if n.value:
             _check(L.region_events(self.h, out.ctypes.data, n.value, ctypes.byref(n)),
                    "region_events")
+        return out
+
+    def loops(self):
+        """Loops recorded and removed since init, sorted by (step, rep_id)."""
+        L = lib()
+        n = ctypes.c_int64()
+        _check(L.region_loops(self.h, None, 0, ctypes.byref(n)), "region_loops (count)")
+        out = np.zeros(n.value, dtype=LOOP_DTYPE)
+        if n.value:
+            _check(L.region_loops(self.h, out.ctypes.data, n.value, ctypes.byref(n)),
+                   "region_loops")
         return out
 
     def close(self):
@@ -398,7 +416,7 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
                      events=True, stream=None, max_steps=10 ** 7, t_end=float("inf"),
                      screen=SCREEN_F64, intercommute=True, cell_size=0.0, steps_per_sync=0,
                      use_graph=False, cand_per_point=0.0, events_per_point=0.0,
-                     screen_split=0, timed_kernel=-1, lanes=1):
+                     screen_split=0, timed_kernel=-1, lanes=1, loop_every=0):
     """Run every region of rs; returns a dict with the stats, per-region logs, output
     records (out = "host": numpy; "device": torch uint8 CUDA tensor; None: not
     written), their offsets (4 per region + 1) and the events with offsets."""
@@ -416,7 +434,7 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
     p.evolve = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
                             float(cell_size), int(steps_per_sync), int(bool(use_graph)),
                             float(cand_per_point), float(events_per_point), int(timed_kernel),
-                            int(screen_split))
+                            int(screen_split), int(loop_every), 0)
     total = int(rs.counts.sum())
     out_off = np.zeros(4 * nr + 1, dtype=np.int64)
     res = {}
@@ -435,6 +453,11 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
     ev = np.zeros(ev_cap, dtype=EVENT_DTYPE) if events else None
     if events:
         p.events, p.events_cap, p.events_off = ev.ctypes.data, ev_cap, ev_off.ctypes.data
+    lp_off = np.zeros(nr + 1, dtype=np.int64)
+    lp_cap = max(total, 1024)
+    lp = np.zeros(lp_cap, dtype=LOOP_DTYPE) if loop_every else None
+    if loop_every:
+        p.loops, p.loops_cap, p.loops_off = lp.ctypes.data, lp_cap, lp_off.ctypes.data
     steps = np.zeros(max(nr, 1), dtype=np.int32)
     psteps = np.zeros(max(nr, 1), dtype=np.int64)
     batch = np.zeros(max(nr, 1), dtype=np.int32)
@@ -451,6 +474,8 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
         if st.events > ev_cap:
             raise SemiparError(-5, f"schedule_regions: {st.events} events > buffer {ev_cap}")
         res["events"], res["events_off"] = ev[:st.events], ev_off
+    if loop_every:
+        res["loops"], res["loops_off"] = lp[:st.loops], lp_off
     return res
 
 

@@ -35,6 +35,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
+def test_every_call_has_a_ctypes_signature():
+    """Without argtypes ctypes passes Python ints as C int: 64-bit pointers and sizes
+    would be truncated."""
+    L = S.lib()
+    for name in S.SYMBOLS:
+        assert getattr(L, name).argtypes is not None, name
+
+
 LAYOUT_C = r"""
 #include <stdio.h>
 #include <stddef.h>
@@ -44,14 +52,19 @@ LAYOUT_C = r"""
 int main(void) {
   Z(semipar_point_rec) Z(semipar_event) Z(semipar_surface) Z(semipar_region_geom)
   Z(semipar_region_desc) Z(semipar_evolve_params) Z(semipar_evolve_stats)
-  Z(semipar_tiling) Z(semipar_sched_params) Z(semipar_sched_stats)
+  Z(semipar_tiling) Z(semipar_sched_params) Z(semipar_sched_stats) Z(semipar_loop)
   F(semipar_region_desc, stream) F(semipar_region_desc, inv2g) F(semipar_region_desc, sub)
-  F(semipar_evolve_params, screen_split) F(semipar_evolve_stats, timed_kernel_launches)
+  F(semipar_evolve_params, screen_split) F(semipar_evolve_params, loop_every)
+  F(semipar_evolve_stats, timed_kernel_launches) F(semipar_evolve_stats, loop_points)
+  F(semipar_loop, rep_id) F(semipar_loop, energy) F(semipar_loop, centre)
   F(semipar_tiling, surfaces) F(semipar_tiling, stream)
   F(semipar_sched_params, cost) F(semipar_sched_params, evolve) F(semipar_sched_params, out)
   F(semipar_sched_params, events_cap) F(semipar_sched_params, region_ms)
-  F(semipar_sched_params, lanes)
+  F(semipar_sched_params, lanes) F(semipar_sched_params, loops)
+  F(semipar_sched_params, loops_off)
   F(semipar_sched_stats, makespan_ms) F(semipar_sched_stats, timed_kernel_launches)
+  F(semipar_sched_stats, loops)
+  printf("SEMIPAR_FLAG_REMOVED %d\n", SEMIPAR_FLAG_REMOVED);
   return 0;
 }
 """
@@ -68,10 +81,14 @@ def c_layout(tmp_path):
 
 
 def test_record_layouts_match_header(tmp_path):
-    from paper_1011_4046_amd.inputs import EVENT_DTYPE, REC_DTYPE
+    from paper_1011_4046_amd.inputs import EVENT_DTYPE, LOOP_DTYPE, REC_DTYPE
     c = c_layout(tmp_path)
     assert c["semipar_point_rec"] == REC_DTYPE.itemsize == 160
     assert c["semipar_event"] == EVENT_DTYPE.itemsize == 56
+    assert c["semipar_loop"] == LOOP_DTYPE.itemsize == 48
+    assert c.pop("SEMIPAR_FLAG_REMOVED") == S.FLAG_REMOVED
+    for f in ("rep_id", "energy", "centre"):
+        assert c.pop(f"semipar_loop.{f}") == LOOP_DTYPE.fields[f][1]
     pairs = {"semipar_surface": S.Surface, "semipar_region_geom": S.RegionGeom,
              "semipar_region_desc": S.RegionDesc, "semipar_evolve_params": S.EvolveParams,
              "semipar_evolve_stats": S.EvolveStats, "semipar_tiling": S.Tiling,
