@@ -20,6 +20,11 @@ Also reported: the point-count heuristic (same pipeline, no model), the plain
 per-region path (one region at a time, FP64 screen, one host check per step, no
 graphs, no batching), the roofline of the dominant kernel and the oracle on the host.
 
+--workload tiling: the learned-scheduling workload. The initial slice of a 32^3 VV
+network (seed 1) is cut into a periodic spacetime tiling of 16 layers x 256 regions
+(4096), run in dependency order; the cost model is trained on the seed-0 network in the
+same tiling. Same pipeline and report as the default.
+
 --workload vv32: one whole-volume matter-era region (32^3 VV network, ~2.4e5 points,
 eta 8 -> 16), as before.
 
@@ -106,16 +111,44 @@ def make_inputs(args):
     return parts, box, train, tbox
 
 
+def make_tiling_inputs(args):
+    """Learned-scheduling workload: the initial slice of a 32^3 matter-era VV network
+    (seed 1) cut into a periodic spacetime tiling of 16 layers x 256 regions, run in
+    dependency order. Training logs come from the seed-0 network in the same tiling."""
+    from paper_1011_4046_amd import inputs as I
+    t = time.perf_counter()
+    out = []
+    for seed in (1, 0):
+        net = I.vv_network(m=args.m, seed=seed)
+        parts, box, n_pred, succ, _ = I.tiling_regions(net, M=4, layers=16)
+        out.append((parts, box, dict(n_pred=n_pred, succ=succ)))
+        log(f"tiling (seed {seed}): {len(parts)} regions, "
+            f"{sum(1 for p in parts if len(p[0]))} non-empty, "
+            f"{sum(len(p[0]) for p in parts)} points ({time.perf_counter() - t:.1f} s)")
+    return out
+
+
 def bench_batched(args):
+    if args.workload == "tiling":
+        (parts, box, dag), (train, tbox, dag_tr) = make_tiling_inputs(args)
+        desc = (f"learned scheduling: {args.m}^3 matter-era VV network (seed 1) cut at eta 8 "
+                f"into a periodic spacetime tiling of 16 layers x 256 regions (4096), run in "
+                f"dependency order until every region's points stop; cost model trained on "
+                f"the seed-0 network in the same tiling")
+    else:
+        parts, box, train, tbox = make_inputs(args)   # before any GPU use (process pool)
+        dag, dag_tr = {}, {}
+        desc = ("512 independent matter-era regions (8x8x8 first layer, size 4), "
+                "lognormal points median 2e4 sigma 1.5 cap 2e5, 20% empty, "
+                "each run until all its points stop")
     import numpy as np
-    parts, box, train, tbox = make_inputs(args)   # before any GPU use (process pool)
     import torch
     from paper_1011_4046_amd import inputs as I
     from paper_1011_4046_amd import scheduler as SC
     from paper_1011_4046_amd import semipar as S
     torch.cuda.set_device(0)
-    rs = S.RegionSet.from_parts(parts, box, I.MATTER, device=True)
-    rs_tr = S.RegionSet.from_parts(train, tbox, I.MATTER, device=True)
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER, device=True, **dag)
+    rs_tr = S.RegionSet.from_parts(train, tbox, I.MATTER, device=True, **dag_tr)
     torch.cuda.synchronize()
     screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
     fast = dict(use_graph=True, screen=screen, out="device", events=True)
@@ -225,9 +258,7 @@ def bench_batched(args):
         cpu = cpu_baseline_regions(parts, box)
     return {
         "value": value, "ms_per_step": elapsed * 1e3 / args.steps,
-        "config": {"workload": "512 independent matter-era regions (8x8x8 first layer, size 4), "
-                               "lognormal points median 2e4 sigma 1.5 cap 2e5, 20% empty, "
-                               "each run until all its points stop",
+        "config": {"workload": desc,
                    "regions": rs.n_regions, "points": int(rs.counts.sum()),
                    "point_steps_per_schedule": st["point_steps"],
                    "screen": args.screen, "graph": True, "batch_points": bp,
@@ -335,7 +366,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "vv32"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "tiling", "vv32"], default="batched")
     ap.add_argument("--screen", choices=["f32", "f64"], default="f32")
     ap.add_argument("--regions", type=int, default=512)
     ap.add_argument("--train-regions", type=int, default=128)
@@ -360,7 +391,7 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
-    res = bench_batched(args) if args.workload == "batched" else bench_vv32(args)
+    res = bench_vv32(args) if args.workload == "vv32" else bench_batched(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "point-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",

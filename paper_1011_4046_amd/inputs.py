@@ -514,6 +514,117 @@ def region_batch(n_targets, size=4.0, seed=0, t_mid=8.0, slots=8, cosmology=MATT
     return parts, box
 
 
+# spatial part (x, y, z) of the four generators, in units of g/2
+_GEN_XYZ = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.int64)
+
+
+def _gen_coords(P, t, V, inv2g):
+    """Generator coordinates c of points (P, t) about the lattice origin V (x, y, z,
+    tau), written in the same operation order as the library's region test."""
+    dx, dy, dz = P[:, 0] - V[0], P[:, 1] - V[1], P[:, 2] - V[2]
+    dtau = np.sqrt(3.0) * t - V[3]
+    a, b, cc, d = dx + dy, dz + dtau, dx - dy, dtau - dz
+    return np.stack([(a + b) * inv2g, (cc + d) * inv2g, (d - cc) * inv2g, (b - a) * inv2g], 1)
+
+
+def tiling_regions(net, M=4, layers=16, lead=1.75):
+    """Cut a whole-volume network at its initial slice into the regions of a periodic
+    spacetime tiling (Section "Geometry": 4-cubes spanned by four null generators; its
+    subsection "Boundary conditions": the tiling repeats with the box).
+
+    The box L holds M steps of 2 g per axis (g = L / 2M, region size s = g sqrt 2), so
+    a layer -- the regions whose indices sum to S -- has 4 M^3 regions. Layers
+    S = 0 .. layers-1 are kept. The lattice origin puts the initial slice `lead` g
+    above the past vertex of layer 0 in tau, so the slice crosses layers 0 .. 3.
+    A region is named by (S, p mod 4M) with p = the past vertex's spatial position in
+    units of g/2; every point is moved by whole boxes into its region's canonical image
+    (p in [0, 4M)^3). Region r's predecessors are the four regions r - e_m of layer
+    S - 1 (none for layer 0). Links to points of other regions become -1. Regions cut
+    by the initial slice take the points inside them; the others start empty.
+
+    Returns (parts, box, n_pred, succ, layer) with parts = [(recs, geom)] in
+    (layer, spatial key) order and geom = (origin[4], 1/(2 g), idx[4])."""
+    L = float(net["box"])
+    g = L / (2 * M)
+    inv2g = 1.0 / (2.0 * g)
+    recs = net["recs"]
+    t0 = float(recs["x_prev"][0, 3]) if len(recs) else float(net["t0"])
+    V = np.array([0.0, 0.0, 0.0, np.sqrt(3.0) * t0 - lead * g])
+    K = 4 * M
+    A = _GEN_XYZ.T                                    # p = A @ i
+    # regions of one layer: canonical index for every spatial key in [0, K)^3
+    rng_i = np.arange(-K, K + 1)
+    I1, I2, I3 = np.meshgrid(rng_i, rng_i, rng_i, indexing="ij")
+    cand = np.stack([I1.ravel(), I2.ravel(), I3.ravel()], 1)
+    keys_of_layer = []
+    for S in range(layers):
+        i = np.concatenate([cand, (S - cand.sum(1))[:, None]], 1)
+        p = i @ A.T
+        ok = np.all((p >= 0) & (p < K), axis=1)
+        i, p = i[ok], p[ok]
+        key = (p[:, 0] * K + p[:, 1]) * K + p[:, 2]
+        order = np.argsort(key)
+        i, key = i[order], key[order]
+        assert len(key) == 4 * M ** 3 and len(np.unique(key)) == len(key)
+        keys_of_layer.append((key, i))
+    per = 4 * M ** 3
+    nr = layers * per
+    # points: region index from the initial-slice position, moved to the canonical image
+    x0, x1 = recs["x_prev"][:, :3].copy(), recs["x"][:, :3].copy()
+    c = _gen_coords(x0, recs["x_prev"][:, 3], V, inv2g)
+    i = np.floor(c).astype(np.int64)
+    p = i @ A.T
+    wrap = np.floor_divide(p, K)
+    x0 -= wrap * L
+    x1 -= wrap * L
+    c2 = _gen_coords(x0, recs["x_prev"][:, 3], V, inv2g)
+    i2 = np.floor(c2).astype(np.int64)
+    shift = np.array([[M, M, -M, -M], [M, -M, M, -M], [M, -M, -M, M]], dtype=np.int64)
+    assert np.array_equal(i2, i - wrap @ shift), "a point sits on a region boundary"
+    S_pt = i2.sum(1)
+    p2 = i2 @ A.T
+    assert np.all((p2 >= 0) & (p2 < K))
+    inside = (S_pt >= 0) & (S_pt < layers)
+    key_pt = (p2[:, 0] * K + p2[:, 1]) * K + p2[:, 2]
+    rid = -np.ones(len(recs), dtype=np.int64)
+    for S in range(layers):
+        sel = inside & (S_pt == S)
+        key, _ = keys_of_layer[S]
+        rid[sel] = S * per + np.searchsorted(key, key_pt[sel])
+    moved = recs.copy()
+    moved["x"][:, :3] = x1
+    moved["x_prev"][:, :3] = x0
+    # links across regions dangle
+    pos = {int(v): k for k, v in enumerate(recs["id"])}
+    nxt = np.array([pos.get(int(v), -1) for v in recs["next_id"]], dtype=np.int64)
+    prv = np.array([pos.get(int(v), -1) for v in recs["prev_id"]], dtype=np.int64)
+    same_n = (nxt >= 0) & (rid[np.maximum(nxt, 0)] == rid)
+    same_p = (prv >= 0) & (rid[np.maximum(prv, 0)] == rid)
+    moved["next_id"] = np.where(same_n, moved["next_id"], -1)
+    moved["prev_id"] = np.where(same_p, moved["prev_id"], -1)
+    order = np.argsort(rid, kind="stable")
+    counts = np.bincount(rid[rid >= 0], minlength=nr)
+    sorted_recs = moved[order][rid[order] >= 0]
+    off = np.concatenate([[0], np.cumsum(counts)])
+    parts, n_pred, succ, layer = [], np.zeros(nr, np.int64), [[] for _ in range(nr)], []
+    for S in range(layers):
+        key, idx = keys_of_layer[S]
+        for q in range(per):
+            r = S * per + q
+            geom = np.array([V[0], V[1], V[2], V[3], inv2g] + [float(v) for v in idx[q]])
+            parts.append((sorted_recs[off[r]:off[r + 1]].copy(), geom))
+            layer.append(S)
+            if S + 1 < layers:
+                pk = np.array([key[q] // (K * K), (key[q] // K) % K, key[q] % K])
+                nkey, _ = keys_of_layer[S + 1]
+                for m in range(4):
+                    qp = (pk + _GEN_XYZ[m]) % K
+                    s_id = (S + 1) * per + int(np.searchsorted(nkey, (qp[0] * K + qp[1]) * K + qp[2]))
+                    succ[r].append(s_id)
+                    n_pred[s_id] += 1
+    return parts, L, n_pred, succ, np.array(layer)
+
+
 def _gpu_in_use():
     import sys
     torch = sys.modules.get("torch")

@@ -136,6 +136,28 @@ def test_schedule_device_resident_io_and_dependencies(S):
                 assert b[q] > b[r], (r, q)
 
 
+@pytest.mark.parametrize("policy,lanes", [(0, 1), (1, 1), (1, 3)])
+def test_spacetime_tiling_in_dependency_order(S, policy, lanes):
+    """A matter-era network cut at its initial slice into a periodic spacetime tiling
+    (6 layers x 32 regions), run in dependency order: every region equals the
+    oracle's run of that region alone, and no region runs before a predecessor."""
+    say(f"case: tiling of VV 8^3 seed 3 (M=2, 6 layers), policy {policy}, lanes {lanes}")
+    net = I.vv_network(m=8, seed=3)
+    parts, box, n_pred, succ, layer = I.tiling_regions(net, M=2, layers=6)
+    orc = oracle_regions(parts, box, "tiling8")
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER, n_pred=n_pred, succ=succ)
+    res = S.schedule_regions(rs, policy, batch_points=1500 if lanes > 1 else 0, lanes=lanes,
+                             use_graph=True, screen=S.SCREEN_F32)
+    check_against_oracle(res, parts, orc)
+    assert res["stats"]["regions"] == len(parts)
+    assert res["stats"]["empty_regions"] == sum(1 for p in parts if len(p[0]) == 0)
+    b = res["region_batch"]
+    for r in range(len(parts)):
+        for q in succ[r]:
+            if b[r] >= 0 and b[q] >= 0:
+                assert b[q] > b[r], (r, q)
+
+
 def test_region_features_match_oracle(S):
     say("case: cost-model features of 12 regions (seed 200) and two strings")
     parts, box = I.region_batch(SIZES, seed=200)
