@@ -432,7 +432,8 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
  *   0 log1p(points)   1 log1p(open string pieces: points without a left neighbour)
  *   2 RMS transverse speed of the first diamonds
  *   3..10 occupancy histogram: the region's spatial cube of side 2g (g the generator
- *         scale) in 16^3 cells; the fraction of points in cells whose count, relative
+ *         scale) around its centre (origin + g/2 times the index summed along the
+ *         generators' spatial parts) in 16^3 cells; the fraction of points in cells whose count, relative
  *         to the mean over all cells, has floor(log2) + 4 = b (clamped to 0..7)
  *   11 log1p(mean distance to the right neighbour / region size) */
 int semipar_region_features(const semipar_tiling* t, float* feat);

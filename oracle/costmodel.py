@@ -122,7 +122,7 @@ def features(recs, geom, box):
       2 RMS over points with a right neighbour j of |(L - B) + (R - B)| / (dt_L + dt_R)
         (L = x_k, R = x_j, B = x_prev_j; spatial parts by minimum image),
       3..10 fraction of the points in 16^3 grid cells over the cube of side 2g around the
-        region's spatial origin whose count relative to n / 4096 has
+        region's spatial centre whose count relative to n / 4096 has
         floor(log2) + 4 = b (clamped to 0..7),
       11 log1p(mean |R - L| / size), size = sqrt(2) g."""
     n = len(recs)
@@ -158,7 +158,12 @@ def features(recs, geom, box):
     e = np.sqrt((mi(R - L) ** 2).sum(1))
     g = 0.5 / geom[4]
     size = np.sqrt(2.0) * g
-    c = mi(L - np.asarray(geom[:3]))
+    # the region's spatial centre: the lattice origin plus g/2 times the index summed
+    # along the generators' spatial parts (1,1,1), (1,-1,-1), (-1,1,-1), (-1,-1,1)
+    i1, i2, i3, i4 = (float(v) for v in geom[5:9])
+    steps = np.array([i1 + i2 - i3 - i4, i1 - i2 + i3 - i4, i1 - i2 - i3 + i4])
+    centre = np.asarray(geom[:3], dtype=np.float64) + (0.25 / geom[4]) * steps
+    c = mi(L - centre)
     ci = np.floor((c + g) * (16 / (2.0 * g))).astype(np.int64)
     ci = np.clip(ci, 0, 15)
     cell = (ci[:, 0] * 16 + ci[:, 1]) * 16 + ci[:, 2]

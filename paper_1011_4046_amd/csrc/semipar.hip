@@ -71,6 +71,17 @@ struct RegionGeom {
   int32_t idx[4];
 };
 
+// Spatial centre of the region: the lattice origin moved by the region's index along
+// the generators, whose spatial parts are g/2 (1,1,1), (1,-1,-1), (-1,1,-1), (-1,-1,1).
+// Every point of the region lies within g of it per axis.
+__host__ __device__ inline void region_centre(const RegionGeom& G, double c[3]) {
+  const double h = 0.25 / G.inv2g;  // g / 2
+  const int a = G.idx[0], b = G.idx[1], e = G.idx[2], d = G.idx[3];
+  c[0] = G.V[0] + h * (double)(a + b - e - d);
+  c[1] = G.V[1] + h * (double)(a - b + e - d);
+  c[2] = G.V[2] + h * (double)(a - b - e + d);
+}
+
 // -1 when P lies in the region; else the first i with floor(c_i) > idx_i (the final face
 // its future leaves by), else the first i with floor(c_i) != idx_i.
 __device__ __forceinline__ int exit_face(const RegionGeom& G, const V4& P) {
@@ -146,7 +157,7 @@ struct HashCfg {   // fixed for a configuration
 };
 
 // Local grid of one sub-region of a batch: a non-periodic cube of side W = 2.5 g around
-// the region's spatial origin (the region's points lie within g of it per axis), nc^3
+// the region's spatial centre (the region's points lie within g of it per axis), nc^3
 // cells of edge h. Elements outside are clamped into the boundary cells, which only
 // merges cells (more pairs tested, never fewer). Cells of region q occupy the buckets
 // (base + row-major index) mod B; cell keys carry the region's salt.
@@ -1554,9 +1565,11 @@ __global__ __launch_bounds__(1024) void k_rcells(const RegionGeom* __restrict__ 
     // FP32 slack: a few ulps at the largest local magnitude (clamped elements lie up to
     // W from a cell origin)
     C.marg32 = (float)((W + 3.0 * C.h) * 0x1p-20);
-    C.ox = geoms[q].V[0] - 0.5 * W;
-    C.oy = geoms[q].V[1] - 0.5 * W;
-    C.oz = geoms[q].V[2] - 0.5 * W;
+    double ctr[3];
+    region_centre(geoms[q], ctr);
+    C.ox = ctr[0] - 0.5 * W;
+    C.oy = ctr[1] - 0.5 * W;
+    C.oz = ctr[2] - 0.5 * W;
     C.salt = (uint32_t)q * 0x9E3779B1u;
     rc[q] = C;
     sum += cell_count(nc);
@@ -1943,8 +1956,10 @@ __global__ __launch_bounds__(NT) void k_feat_points(Slices X, int n, int s,
     if (prv[k] < 0) open = 1.0;
     const RegionGeom& G = geoms[q];
     const double g = 0.5 / G.inv2g;
-    const double c[3] = {sp::min_image(L.x - G.V[0], P), sp::min_image(L.y - G.V[1], P),
-                         sp::min_image(L.z - G.V[2], P)};
+    double ctr[3];
+    region_centre(G, ctr);
+    const double c[3] = {sp::min_image(L.x - ctr[0], P), sp::min_image(L.y - ctr[1], P),
+                         sp::min_image(L.z - ctr[2], P)};
     int ci[3];
     for (int a = 0; a < 3; ++a) {
       const int v = (int)floor((c[a] + g) * (FEAT_GRID / (2.0 * g)));

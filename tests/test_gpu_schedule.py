@@ -173,6 +173,13 @@ def test_region_features_match_oracle(S):
     f1 = S.region_features(rs1)[0]
     assert np.allclose(f1, C.features(s1["recs"], geom, 16.0), rtol=1e-5, atol=1e-6)
     assert f1[2] == pytest.approx(0.6, rel=1e-5)
+    # regions of a spacetime tiling: nonzero indices, one shared lattice origin
+    net = I.vv_network(m=8, seed=3)
+    tparts, tbox, _, _, _ = I.tiling_regions(net, M=2, layers=6)
+    ft = S.region_features(S.RegionSet.from_parts(tparts, tbox, I.MATTER))
+    for r, (recs, geom_r) in enumerate(tparts):
+        want = C.features(recs, geom_r, tbox)
+        assert np.allclose(ft[r], want, rtol=1e-5, atol=1e-6), (r, ft[r], want)
 
 
 def _mlp_case(seed, n=700):

@@ -134,3 +134,25 @@ def test_features_occupancy_histogram_by_hand():
     recs2["x_prev"][:, :3] = p2
     f2 = C.features(recs2, geom, 64.0)
     assert f2[3 + 4] == pytest.approx(1.0) and f2[3:11].sum() == pytest.approx(1.0)
+
+
+def test_features_follow_the_region_index():
+    """Moving a region by whole generator steps (index + k e_m) and its points by the
+    generators' spatial part leaves every feature unchanged: the occupancy grid is
+    centred on the region, not on the tiling's lattice origin."""
+    net = I.region_network(3000, 4.0, seed=5)
+    recs, geom, g, box = net["recs"], net["geom"], net["g"], net["box"]
+    f0 = C.features(recs, geom, box)
+    gens = 0.5 * g * np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)
+    for m in range(4):
+        for k in (1, -2, 3):
+            geom2 = geom.copy()
+            geom2[5 + m] += k
+            r2 = recs.copy()
+            r2["x"][:, :3] += k * gens[m]
+            r2["x_prev"][:, :3] += k * gens[m]
+            assert np.allclose(C.features(r2, geom2, box), f0, rtol=1e-12, atol=1e-12), (m, k)
+    # a region displaced without moving its index sees its points off-centre
+    geom3 = geom.copy()
+    geom3[5] += 1
+    assert not np.allclose(C.features(recs, geom3, box), f0)
