@@ -348,10 +348,12 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
                                                const RegionGeom* __restrict__ geoms,
                                                const int32_t* __restrict__ rid,
                                                const RCell* __restrict__ rcell,
-                                               uint64_t* __restrict__ rext) {
+                                               uint64_t* __restrict__ rext,
+                                               uint8_t* __restrict__ wlive) {
   if (ctrl->done) return;
   const int s = ctrl->step;
   const Cells cs = ctrl->cells;
+  const int nw = (n + 63) >> 6;
   const int ic = s % 3, ip = (s + 2) % 3, in = (s + 1) % 3;
   // grid-stride over the points in slot order (neighbouring lanes read neighbouring
   // slots, so the SoA loads stay coalesced), with the same trip count for every thread
@@ -363,8 +365,13 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   uint32_t nadv = 0;
   for (int it = 0; it < iters; ++it) {
   const int ii = it * span + blockIdx.x * NT + threadIdx.x;
+  // a wave of 64 slots none of which still advances is skipped: its flag was cleared by
+  // the step that stopped its last point, and stopped points never advance again
+  const int wv = __builtin_amdgcn_readfirstlane(ii >> 6);
+  if (wv < nw && !wlive[wv]) continue;
   const int k = ii < n ? ii : n;
   uint64_t xk = 0;  // this point's element extent
+  bool still = false;  // k advanced in this step (and so is still active)
   // a point of a bounded region that stopped before this step, or a point of a removed
   // loop (fstep is then passed for a whole-volume region too), has nothing to do (its
   // element cell already reads NO_ELEM)
@@ -400,6 +407,7 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
     }
     if (adv) {
       nadv += 1;
+      still = true;
       const V4 L = ld(X, ic, k);
       const V4 R = ld(X, ic, j);
       const V4 B = ld(X, ip, j);
@@ -522,6 +530,10 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
     }
   }
   xkey = xk > xkey ? xk : xkey;
+  {
+    const uint64_t any = __ballot(still);
+    if ((threadIdx.x & 63) == 0 && wv < nw) wlive[wv] = any != 0ull ? 1 : 0;
+  }
   }  // grid-stride loop
   // per block: minimum t of the new slice, largest element extent, points advanced;
   // reduced by k_resolve (no same-address atomics across the grid)
@@ -625,10 +637,13 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
                                                 void* __restrict__ sbox, HashCfg hc,
                                                 const int32_t* __restrict__ rid,
                                                 const RCell* __restrict__ rcell,
+                                                const uint8_t* __restrict__ wlive,
                                                 const Ctrl* ctrl) {
   if (ctrl->done) return;
   const int nc = ctrl->cells.nc;
   for (int k = blockIdx.x * NT + threadIdx.x; k < n; k += gridDim.x * NT) {
+  // no point of a cleared wave advanced this step, so none has an element
+  if (!wlive[__builtin_amdgcn_readfirstlane(k >> 6)]) continue;
   const int32_t c = ecell[k];
   if (c < 0) continue;
   const int x = c & 1023, y = (c >> 10) & 1023, z = (c >> 20) & 1023;
@@ -2116,6 +2131,7 @@ struct semipar_region {
   double rc_fixed_h = 0.0;       // batch: fixed cell edge (0 = adaptive)
   int32_t step0 = 1;             // slice index of the initial surfaces
   int32_t *fstep = nullptr, *face = nullptr;  // bounded: stop step and exit face per point
+  uint8_t* wlive = nullptr;  // per 64 slots: 1 while one of them may still advance
   semipar_point_rec* frz = nullptr;           // bounded: record of each stopped point
   int cosmology = 0;
   double hcoef = 0.0, box = 1.0;
@@ -2349,7 +2365,7 @@ void launch_evolve_t(semipar_region* r, int n, int nb) {
   k_evolve<FRW, SCR, BND><<<nb, NT, 0, r->stream>>>(
       r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell, r->epos,
       r->cnt, r->large, r->blkred, (BND || r->removed) ? r->fstep : nullptr, r->face, r->frz,
-      r->geom, r->geoms, r->rid, r->rcell, r->rext);
+      r->geom, r->geoms, r->rid, r->rcell, r->rext, r->wlive);
 }
 
 template <bool FRW, bool BND>
@@ -2411,10 +2427,10 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
     k_toff<<<1, 1024, 0, s>>>(r->tile_tot, r->ntiles, r->toff, r->ctrl);
     if (r->screen == 1)
       k_scatter<1><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
-                                      r->sbox, r->hc, r->rid, r->rcell, r->ctrl);
+                                      r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl);
     else
       k_scatter<2><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
-                                      r->sbox, r->hc, r->rid, r->rcell, r->ctrl);
+                                      r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl);
     mark(r, SEMIPAR_K_SCATTER, 2 * i + 1);
     mark(r, SEMIPAR_K_SCREEN, 2 * i);
     launch_screen(r, n, nb);
@@ -2580,6 +2596,7 @@ void region_destroy(semipar_region* r) {
   dfree(r->rid);
   dfree(r->fstep);
   dfree(r->face);
+  dfree(r->wlive);
   dfree(r->frz);
   dfree(r->ctrl);
   dfree(r->log);
@@ -2672,10 +2689,12 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       dalloc(&r->id, cap) != hipSuccess || dalloc(&r->ctrl, 1) != hipSuccess ||
       dalloc(&r->blkred, 4 * (size_t)blocks(cap)) != hipSuccess ||
       dalloc(&r->fstep, cap) != hipSuccess || dalloc(&r->face, cap) != hipSuccess ||
-      dalloc(&r->lev, cap) != hipSuccess || (d->bounded && dalloc(&r->frz, cap) != hipSuccess))
+      dalloc(&r->lev, cap) != hipSuccess || dalloc(&r->wlive, (cap + 63) / 64) != hipSuccess ||
+      (d->bounded && dalloc(&r->frz, cap) != hipSuccess))
     return fail(SEMIPAR_E_OOM);
   if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
     return fail(SEMIPAR_E_OOM);
+  if (hipMemset(r->wlive, 1, (size_t)(cap + 63) / 64) != hipSuccess) return fail(SEMIPAR_E_HIP);
   if (d->n_sub > 0) {
     // batch: per-point sub-region ids (surface order) and the geometry table
     r->n_sub = d->n_sub;
