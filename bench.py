@@ -166,23 +166,24 @@ def bench_batched(args):
     feat = S.region_features(rs)
     pred = cm.predict(feat)
     cfg = {"batch_frac": args.batch_frac, "screen_split": args.split,
-           "steps_per_sync": args.sync_steps, "lanes": args.lanes}
+           "steps_per_sync": args.sync_steps, "lanes": args.lanes, "pack": args.pack}
     if args.tune:
         cfg = SC.autotune(rs, pred, screen=screen, cache=args.tune_cache or None, log=log)
         log(f"autotune: {cfg}")
     bp = SC.batch_points_for(rs, cfg)
     kw = dict(fast, batch_points=bp, screen_split=cfg["screen_split"],
               steps_per_sync=cfg["steps_per_sync"], lanes=cfg["lanes"])
+    kw_learned = dict(kw, pack=cfg.get("pack", S.PACK_POINTS))
 
     for w in range(args.warmup):
-        r = SC.learned_schedule(rs, cm, **kw)
+        r = SC.learned_schedule(rs, cm, **kw_learned)
         log(f"warmup {w}: {r['stats']['batches']} batches, {r['stats']['makespan_ms']:.0f} ms")
         del r
     torch.cuda.synchronize()
     runs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        runs.append(SC.learned_schedule(rs, cm, **kw))
+        runs.append(SC.learned_schedule(rs, cm, **kw_learned))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     point_steps = sum(r["stats"]["point_steps"] for r in runs)
@@ -263,7 +264,7 @@ def bench_batched(args):
                    "point_steps_per_schedule": st["point_steps"],
                    "screen": args.screen, "graph": True, "batch_points": bp,
                    "screen_split": cfg["screen_split"], "steps_per_sync": cfg["steps_per_sync"],
-                   "lanes": cfg["lanes"],
+                   "lanes": cfg["lanes"], "pack": cfg.get("pack", 0),
                    "path": "batched + learned cost model (features, inference and schedule "
                            "inside the timed region)"},
         "roofline": roof, "roofline_other": other, "cpu_baseline": cpu, **extra,
@@ -378,6 +379,9 @@ def main():
     ap.add_argument("--split", type=int, default=1, help="screen threads per element (1 or 5)")
     ap.add_argument("--lanes", type=int, default=3, help="batches evolved concurrently")
     ap.add_argument("--sync-steps", type=int, default=32, help="lattice steps per host check")
+    ap.add_argument("--pack", type=int, default=0,
+                    help="learned schedule: 0 = batches of equal points, 1 = of equal "
+                         "predicted point-steps")
     ap.add_argument("--tune", type=int, default=0,
                     help="run the autotuner first (the defaults are its choice for this "
                          "workload)")

@@ -336,6 +336,11 @@ typedef struct semipar_tiling {
 } semipar_tiling;
 
 enum {
+  SEMIPAR_PACK_POINTS = 0, /* batches of at most batch_points points */
+  SEMIPAR_PACK_WORK = 1    /* batches of equal predicted work (needs cost) */
+};
+
+enum {
   SEMIPAR_SCHED_PLAIN = 0,  /* one region at a time, each its own launch sequence */
   SEMIPAR_SCHED_BATCHED = 1 /* ready regions packed into batches (one set of launches
                                per batch over the points of all its regions) */
@@ -387,7 +392,12 @@ typedef struct semipar_sched_params {
   int32_t lanes;     /* BATCHED: batches evolved concurrently, each lane a host thread
                         with a stream of its own (0 or 1: one after another on the
                         tiling's stream). Batches go to lanes longest predicted first. */
-  int32_t reserved;
+  int32_t pack;      /* BATCHED: SEMIPAR_PACK_POINTS, or SEMIPAR_PACK_WORK: with a cost
+                        vector, the ready regions (in decreasing cost order) are cut into
+                        B = max(lanes, ceil(points / batch_points)) batches holding about
+                        equal shares of the predicted point-steps (points x cost), so that
+                        the regions needing the most steps share a smaller batch. Without
+                        a cost vector it acts as SEMIPAR_PACK_POINTS. Ordering only. */
   semipar_loop* loops;  /* host loop buffer (evolve.loop_every > 0), capacity loops_cap,
                            and n_regions + 1 offsets loops_off: region r's loops, sorted
                            by (step, rep_id), at loops_off[r] .. loops_off[r+1]. Offsets

@@ -356,15 +356,36 @@ struct Runner {
       return t->surfaces[a].n > t->surfaces[b].n;
     });
     std::vector<Batch> bs;
-    int64_t pts = 0;
-    for (int32_t r : live) {
-      const int64_t nr = t->surfaces[r].n;
-      if (bs.empty() || (p->batch_points > 0 && pts + nr > p->batch_points)) {
-        bs.emplace_back();
-        pts = 0;
+    if (p->pack == SEMIPAR_PACK_WORK && p->cost && !live.empty()) {
+      // equal shares of the predicted point-steps, in decreasing cost order
+      double work = 0.0;
+      int64_t total = 0;
+      for (int32_t r : live) {
+        work += (double)t->surfaces[r].n * std::max(1.0, (double)p->cost[r]);
+        total += t->surfaces[r].n;
       }
-      bs.back().regs.push_back(r);
-      pts += nr;
+      int64_t nb = std::max<int64_t>(1, p->lanes);
+      if (p->batch_points > 0) nb = std::max(nb, (total + p->batch_points - 1) / p->batch_points);
+      nb = std::min<int64_t>(nb, (int64_t)live.size());
+      const double share = work / (double)nb;
+      double done = 0.0;
+      for (int32_t r : live) {
+        if (bs.empty() || ((int64_t)bs.size() < nb && done >= share * (double)bs.size()))
+          bs.emplace_back();
+        bs.back().regs.push_back(r);
+        done += (double)t->surfaces[r].n * std::max(1.0, (double)p->cost[r]);
+      }
+    } else {
+      int64_t pts = 0;
+      for (int32_t r : live) {
+        const int64_t nr = t->surfaces[r].n;
+        if (bs.empty() || (p->batch_points > 0 && pts + nr > p->batch_points)) {
+          bs.emplace_back();
+          pts = 0;
+        }
+        bs.back().regs.push_back(r);
+        pts += nr;
+      }
     }
     // predicted device time of a batch: its points, for as many steps as its longest
     // region needs (steps from the cost model; without one, the points alone)
@@ -391,6 +412,7 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
   if (rc != SEMIPAR_OK) return rc;
   if (p->policy != SEMIPAR_SCHED_PLAIN && p->policy != SEMIPAR_SCHED_BATCHED) return SEMIPAR_E_ARG;
   if (p->lanes < 0 || p->lanes > 16) return SEMIPAR_E_ARG;
+  if (p->pack != SEMIPAR_PACK_POINTS && p->pack != SEMIPAR_PACK_WORK) return SEMIPAR_E_ARG;
   if (p->batch_points < 0 || (p->out && p->out_mem != SEMIPAR_MEM_HOST &&
                               p->out_mem != SEMIPAR_MEM_DEVICE))
     return SEMIPAR_E_ARG;

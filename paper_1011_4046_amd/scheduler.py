@@ -80,6 +80,7 @@ TUNABLE = {
     "lanes": [1, 2, 3],                            # batches evolved concurrently
     "screen_split": [5, 1],
     "steps_per_sync": [64, 32, 128],
+    "pack": [S.PACK_POINTS, S.PACK_WORK],         # equal points / equal predicted work
 }
 
 
@@ -110,7 +111,7 @@ def autotune(rs, cost=None, screen=S.SCREEN_F32, cache=None, max_steps=96, log=N
                                  out=None, events=False, use_graph=True, screen=screen,
                                  screen_split=cfg["screen_split"],
                                  steps_per_sync=cfg["steps_per_sync"], max_steps=max_steps,
-                                 lanes=cfg["lanes"])
+                                 lanes=cfg["lanes"], pack=cfg["pack"] if cost is not None else 0)
         st = res["stats"]
         # time per point-step of the truncated schedule
         return st["makespan_ms"] / max(st["point_steps"], 1) * 1e6

@@ -100,7 +100,7 @@ class SchedParams(ctypes.Structure):
                 ("events_off", ctypes.c_void_p), ("region_steps", ctypes.c_void_p),
                 ("region_point_steps", ctypes.c_void_p), ("region_batch", ctypes.c_void_p),
                 ("region_ms", ctypes.c_void_p), ("lanes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("loops", ctypes.c_void_p),
+                ("pack", ctypes.c_int32), ("loops", ctypes.c_void_p),
                 ("loops_cap", ctypes.c_int64), ("loops_off", ctypes.c_void_p)]
 
 
@@ -117,6 +117,7 @@ class SchedStats(ctypes.Structure):
 
 
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
+PACK_POINTS, PACK_WORK = 0, 1
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
 
 # exported symbols declared in include/semipar.h
@@ -416,7 +417,8 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
                      events=True, stream=None, max_steps=10 ** 7, t_end=float("inf"),
                      screen=SCREEN_F64, intercommute=True, cell_size=0.0, steps_per_sync=0,
                      use_graph=False, cand_per_point=0.0, events_per_point=0.0,
-                     screen_split=0, timed_kernel=-1, lanes=1, loop_every=0):
+                     screen_split=0, timed_kernel=-1, lanes=1, loop_every=0,
+                     pack=PACK_POINTS):
     """Run every region of rs; returns a dict with the stats, per-region logs, output
     records (out = "host": numpy; "device": torch uint8 CUDA tensor; None: not
     written), their offsets (4 per region + 1) and the events with offsets."""
@@ -426,6 +428,7 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
     p.policy = int(policy)
     p.batch_points = int(batch_points)
     p.lanes = int(lanes)
+    p.pack = int(pack)
     cost_arr = None
     if cost is not None:
         cost_arr = np.ascontiguousarray(cost, dtype=np.float32)

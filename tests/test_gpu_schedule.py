@@ -72,7 +72,7 @@ SIZES = [0, 300, 5000, 1200, 0, 20000, 800, 2500, 40, 9000, 150, 3000]
 
 
 @pytest.mark.parametrize("case", ["plain", "batched-heuristic", "batched-cost", "one-batch-f32",
-                                  "lanes"])
+                                  "lanes", "work-packing"])
 def test_schedule_policies_equal_oracle_region_by_region(S, case):
     say(f"case: schedule_regions {case}, sizes {SIZES}, seed 200")
     parts, box = I.region_batch(SIZES, seed=200)
@@ -97,6 +97,29 @@ def test_schedule_policies_equal_oracle_region_by_region(S, case):
         order = sorted(nz, key=lambda r: -cost[r])
         b = [res["region_batch"][r] for r in order]
         assert b == sorted(b)
+    elif case == "work-packing":
+        # equal shares of predicted point-steps (points x cost) over 3 batches (one lane,
+        # so that the batches run, and are numbered, in cut order)
+        cost = np.random.default_rng(6).uniform(10, 300, len(SIZES)).astype(np.float32)
+        bp = -(-int(rs.counts.sum()) // 3)
+        res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=cost, lanes=1,
+                                 pack=S.PACK_WORK, use_graph=True, screen=S.SCREEN_F32)
+        nz = [r for r in range(len(SIZES)) if len(parts[r][0])]
+        order = sorted(nz, key=lambda r: -cost[r])
+        b = [res["region_batch"][r] for r in order]
+        assert res["stats"]["batches"] == 3
+        # cut in cost order: region i opens a new batch when the predicted work before it
+        # has reached (batches so far) shares and fewer than 3 batches exist
+        wk = [len(parts[r][0]) * float(cost[r]) for r in order]
+        share = sum(wk) / 3
+        want, done = [], 0.0
+        for w in wk:
+            if not want or (want[-1] + 1 < 3 and done >= share * (want[-1] + 1)):
+                want.append(len(want) and want[-1] + 1)
+            else:
+                want.append(want[-1])
+            done += w
+        assert [x - b[0] for x in b] == want
     elif case == "lanes":
         # batches evolved concurrently by three host threads on streams of their own
         res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=6000, use_graph=True,
@@ -294,3 +317,61 @@ def test_learned_packing_beats_point_count_heuristic(S):
         ea = a["events"][a["events_off"][r]:a["events_off"][r + 1]]
         eb = b["events"][b["events_off"][r]:b["events_off"][r + 1]]
         assert ea.tobytes() == eb.tobytes()
+
+
+def test_autotuner_choice_is_valid_cached_and_changes_no_result(S, tmp_path):
+    """The autotuner's coordinate search returns one value of every tunable, reuses
+    its cached choice for the same workload, and the schedule it picks gives exactly
+    the records and events of the default launch shape."""
+    from paper_1011_4046_amd import scheduler as SC
+    say("case: autotune on sizes seed 200, max_steps 24, cache in tmp")
+    parts, box = I.region_batch(SIZES, seed=200)
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    cost = rs.counts.astype(np.float32)
+    cache = str(tmp_path / "tune.json")
+    cfg = SC.autotune(rs, cost, screen=S.SCREEN_F32, cache=cache, max_steps=24)
+    for k, vals in SC.TUNABLE.items():
+        assert cfg[k] in vals, k
+    assert cfg["ns_per_point_step"] > 0 and not cfg.get("cached")
+    again = SC.autotune(rs, cost, screen=S.SCREEN_F32, cache=cache, max_steps=24)
+    assert again["cached"] and all(again[k] == cfg[k] for k in SC.TUNABLE)
+    kw = dict(use_graph=True, screen=S.SCREEN_F32)
+    base = S.schedule_regions(rs, S.SCHED_BATCHED, cost=cost, **kw)
+    tuned = S.schedule_regions(rs, S.SCHED_BATCHED, cost=cost,
+                               batch_points=SC.batch_points_for(rs, cfg),
+                               screen_split=cfg["screen_split"],
+                               steps_per_sync=cfg["steps_per_sync"], lanes=cfg["lanes"],
+                               pack=cfg["pack"], **kw)
+    for r in range(rs.n_regions):
+        a = base["out"][base["out_off"][4 * r]:base["out_off"][4 * r + 4]]
+        b = tuned["out"][tuned["out_off"][4 * r]:tuned["out_off"][4 * r + 4]]
+        assert a.tobytes() == b.tobytes()
+        ea = base["events"][base["events_off"][r]:base["events_off"][r + 1]]
+        eb = tuned["events"][tuned["events_off"][r]:tuned["events_off"][r + 1]]
+        assert ea.tobytes() == eb.tobytes()
+
+
+def test_learned_cost_fit_and_predict(S):
+    """LearnedCost trains on logged step counts of non-empty regions (log steps) and
+    predicts zero for empty regions; the learned schedule equals the plain batched one
+    region by region."""
+    from paper_1011_4046_amd import scheduler as SC
+    say("case: LearnedCost on sizes seed 200")
+    parts, box = I.region_batch(SIZES, seed=200)
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    log = S.schedule_regions(rs, S.SCHED_BATCHED, use_graph=True, screen=S.SCREEN_F32)
+    feat = S.region_features(rs)
+    cm = SC.LearnedCost(seed=0).fit(feat, log["region_steps"], iters=500, lr=3e-3)
+    assert cm.losses[-1] < 0.1 * cm.losses[0]
+    pred = cm.predict(feat)
+    live = rs.counts > 0
+    assert np.all(pred[~live] == 0) and np.all(pred[live] > 0)
+    steps = log["region_steps"][live]
+    assert np.allclose(np.log(pred[live]), np.log(steps), atol=0.35)
+    res = SC.learned_schedule(rs, cm, use_graph=True, screen=S.SCREEN_F32, lanes=2,
+                              batch_points=8000)
+    assert np.array_equal(res["pred"], pred)
+    for r in range(rs.n_regions):
+        a = log["out"][log["out_off"][4 * r]:log["out_off"][4 * r + 4]]
+        b = res["out"][res["out_off"][4 * r]:res["out_off"][4 * r + 4]]
+        assert a.tobytes() == b.tobytes()
