@@ -609,6 +609,7 @@ __global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t
 
 constexpr int MAX_TILES = 2048;  // buckets <= 2^23
 constexpr int POINT_GRID = 2048;  // most workgroups of the grid-stride per-point kernels
+constexpr int SCREEN_GRID = 2560;  // most workgroups of the screen (a multiple of 8)
 
 __device__ __forceinline__ int bucket_start(const int32_t* loc, const int32_t* s_toff, uint32_t b) {
   return loc[b] + s_toff[b >> TS_LOG];
@@ -758,13 +759,28 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
                                                const int32_t* __restrict__ toff, int ntiles,
                                                const LargeBox* __restrict__ large, HashCfg hc,
                                                sp::Period P, int2* __restrict__ cand, int cap,
-                                               int nblk, Ctrl* ctrl,
+                                               Ctrl* ctrl,
                                                const int32_t* __restrict__ rid,
                                                const RCell* __restrict__ rcell) {
   static_assert(G == 1 || G == N_PENCIL, "one or five threads per element");
   if (ctrl->done) return;
-  const int lid = xcd_block(nblk);
-  if (lid >= nblk) return;
+  using T = typename std::conditional<SCR == 1, double, float>::type;
+  __shared__ int2 sbuf[SBUF];
+  __shared__ int s_cnt, s_base;
+  const Cells cs = ctrl->cells;
+  const int nl = ctrl->n_large;
+  const int n_norm = toff[ntiles];
+  // The grid is sized for the resident workgroups, not for the points: the blocks of
+  // each XCD walk a contiguous range of element chunks (neighbouring cells, shared L2)
+  // and stop at this step's hashed + large element count, read on the device.
+  constexpr int EPB = G == 1 ? NT : (NT / 64) * SCREEN_EPW;  // elements per chunk
+  const int nchunk = (n_norm + nl + EPB - 1) / EPB;
+  const int cper = (nchunk + N_XCD - 1) / N_XCD;
+  const int xcd = (int)blockIdx.x % N_XCD;
+  const int bper = (int)gridDim.x / N_XCD;
+  for (int c = (int)blockIdx.x / N_XCD; c < cper; c += bper) {
+  const int lid = xcd * cper + c;
+  if (lid >= nchunk) break;
   // G = 1: one element per thread. G = 5: an element's five threads are neighbouring
   // lanes of one wave (12 elements per wave, lanes 60..63 idle), so their identical
   // loads of the element's own data are served by one request.
@@ -779,14 +795,8 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
     q = lane < SCREEN_EPW * N_PENCIL ? (lid * (NT / 64) + wv) * SCREEN_EPW + lane / N_PENCIL
                                       : INT_MAX;
   }
-  using T = typename std::conditional<SCR == 1, double, float>::type;
-  __shared__ int2 sbuf[SBUF];
-  __shared__ int s_cnt, s_base;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  const Cells cs = ctrl->cells;
-  const int nl = ctrl->n_large;
-  const int n_norm = toff[ntiles];
   auto push = [&](int a, int b) {
     const int i = atomicAdd(&s_cnt, 1);
     if (i < SBUF)
@@ -1005,6 +1015,8 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
     const int idx = s_base + i;
     if (idx < cap) cand[idx] = sbuf[i];
   }
+  __syncthreads();  // the staged candidates are copied before the next chunk reuses LDS
+  }  // chunks
 }
 
 __device__ __forceinline__ Elem load_elem(const Slices& X, int ic, int in, int a, int ja,
@@ -2388,11 +2400,12 @@ void launch_evolve(semipar_region* r, bool frw, int scr, bool bnd, int n, int nb
 
 template <int SCR, int G>
 void launch_screen_t(semipar_region* r, int n, int nb) {
-  // logical blocks covering n elements (hashed + large <= n)
+  // chunks covering n elements at most (hashed + large <= n), at most SCREEN_GRID
+  // workgroups walking them
   const int nl = G == 1 ? nb : (int)((n + (NT / 64) * SCREEN_EPW - 1) / ((NT / 64) * SCREEN_EPW));
-  k_screen<SCR, G><<<xcd_grid(nl), NT, 0, r->stream>>>(
+  k_screen<SCR, G><<<xcd_grid(std::min(nl, SCREEN_GRID)), NT, 0, r->stream>>>(
       n, r->sent, r->sbox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc, r->P,
-      r->cand, (int)r->cap_cand, nl, r->ctrl, r->rid, r->rcell);
+      r->cand, (int)r->cap_cand, r->ctrl, r->rid, r->rcell);
 }
 
 // Screen launch: precision (FP64 / FP32 boxes) and threads per element (1 or 5).
