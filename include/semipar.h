@@ -225,6 +225,8 @@ typedef struct semipar_evolve_stats {
   int64_t timed_kernel_launches; /* launches of the timed kernel that did work */
   int64_t loops;          /* loops recorded and removed */
   int64_t loop_points;    /* points they held */
+  int64_t resolve_rounds; /* rounds of the event matching (iterated local minima),
+                             summed over the steps taken */
 } semipar_evolve_stats;
 
 /* A loop recorded and removed (48 bytes).

@@ -2987,6 +2987,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     st->timed_kernel_launches = tk_n;
     st->loops = n_loops;
     st->loop_points = n_lpts;
+    st->resolve_rounds = (int64_t)(uint32_t)(a.stamp - before.stamp);
   }
   return SEMIPAR_OK;
 }

@@ -78,7 +78,7 @@ class EvolveStats(ctypes.Structure):
                 ("final_step", ctypes.c_int32), ("done", ctypes.c_int32),
                 ("elapsed_ms", ctypes.c_double), ("timed_kernel_ms", ctypes.c_double),
                 ("timed_kernel_launches", ctypes.c_int64), ("loops", ctypes.c_int64),
-                ("loop_points", ctypes.c_int64)]
+                ("loop_points", ctypes.c_int64), ("resolve_rounds", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
