@@ -171,6 +171,10 @@ struct RCell {
   int32_t pad;
 };
 constexpr double RCELL_W = 2.5;  // grid side in units of g
+// Per-sub-region extent maxima sit one cache line apart: every wave of a sub-region
+// updates its entry each step, and neighbouring entries on one line would serialise the
+// atomics of different sub-regions.
+constexpr int REXT_STRIDE = 16;
 
 __device__ __forceinline__ V4 ld(const Slices& X, int s, int k) {
   return V4{X.p[s][0][k], X.p[s][1][k], X.p[s][2][k], X.p[s][3][k]};
@@ -523,9 +527,10 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
       const uint64_t lm = __ballot(live), sm = __ballot(live && q == q0);
       if (lm == sm && (lm & 1ull)) {
         const uint64_t m = wave_max_u64(xk);
-        if ((threadIdx.x & 63) == 0 && m != 0) atomicMax((unsigned long long*)&rext[q0], m);
+        if ((threadIdx.x & 63) == 0 && m != 0)
+          atomicMax((unsigned long long*)&rext[(size_t)q0 * REXT_STRIDE], m);
       } else if (live && xk != 0) {
-        atomicMax((unsigned long long*)&rext[q], xk);
+        atomicMax((unsigned long long*)&rext[(size_t)q * REXT_STRIDE], xk);
       }
     }
   }
@@ -718,7 +723,8 @@ __device__ __forceinline__ bool box_overlap(const SBox<T>& a, const SBox<T>& b, 
          a.v[3] <= b.v[7] && b.v[3] <= a.v[7];
 }
 
-constexpr int SBUF = 256;  // candidates staged in LDS per block (more go straight to memory)
+constexpr int SBUF = 1024;       // candidates staged in LDS per block (more go straight to memory)
+constexpr int SBUF_FLUSH = 512;  // staged candidates are written out from this many on
 
 // Workgroups are handed to the 8 XCDs of the chip in turn (workgroup i to XCD i mod 8),
 // each XCD with its own L2. xcd_block() renumbers a 1-D grid of 8*ceil(total/8)
@@ -778,9 +784,13 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
   const int cper = (nchunk + N_XCD - 1) / N_XCD;
   const int xcd = (int)blockIdx.x % N_XCD;
   const int bper = (int)gridDim.x / N_XCD;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
   for (int c = (int)blockIdx.x / N_XCD; c < cper; c += bper) {
   const int lid = xcd * cper + c;
   if (lid >= nchunk) break;
+  // the block's last chunk: the staged candidates are written out after it
+  const bool last = c + bper >= cper || lid + bper >= nchunk;
   // G = 1: one element per thread. G = 5: an element's five threads are neighbouring
   // lanes of one wave (12 elements per wave, lanes 60..63 idle), so their identical
   // loads of the element's own data are served by one request.
@@ -795,8 +805,6 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
     q = lane < SCREEN_EPW * N_PENCIL ? (lid * (NT / 64) + wv) * SCREEN_EPW + lane / N_PENCIL
                                       : INT_MAX;
   }
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
   auto push = [&](int a, int b) {
     const int i = atomicAdd(&s_cnt, 1);
     if (i < SBUF)
@@ -1008,14 +1016,21 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
     }
   }
   __syncthreads();
-  const int cnt = min(s_cnt, SBUF);
-  if (threadIdx.x == 0 && cnt > 0) s_base = atomicAdd(&ctrl->n_cand, cnt);
-  __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += NT) {
-    const int idx = s_base + i;
-    if (idx < cap) cand[idx] = sbuf[i];
+  // staged candidates go out in one reservation once half the buffer is used, and after
+  // the block's last chunk
+  const int staged = s_cnt;
+  if (staged >= SBUF_FLUSH || last) {
+    const int cnt = min(staged, SBUF);
+    if (threadIdx.x == 0 && cnt > 0) s_base = atomicAdd(&ctrl->n_cand, cnt);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += NT) {
+      const int idx = s_base + i;
+      if (idx < cap) cand[idx] = sbuf[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_cnt = 0;
   }
-  __syncthreads();  // the staged candidates are copied before the next chunk reuses LDS
+  __syncthreads();  // the buffer count is settled before the next chunk pushes
   }  // chunks
 }
 
@@ -1578,10 +1593,10 @@ __global__ __launch_bounds__(1024) void k_rcells(const RegionGeom* __restrict__ 
     const double W = RCELL_W * g;
     double target = h_set;
     if (h_set <= 0.0) {
-      const uint64_t x = rext[q];
+      const uint64_t x = rext[(size_t)q * REXT_STRIDE];
       target = x != 0 ? grow * from_key(x) : (C.nc > 0 ? C.h : W / 3.0);
     }
-    rext[q] = 0;
+    rext[(size_t)q * REXT_STRIDE] = 0;
     int nc = (int)floor(W / target);
     nc = nc < 3 ? 3 : (nc > 1023 ? 1023 : nc);
     C.nc = nc;
@@ -2139,7 +2154,8 @@ struct semipar_region {
   std::vector<int64_t> sub_off;  // batch: first slot of each sub-region (n_sub + 1 entries)
   int32_t* log_rid = nullptr;    // batch: sub-region of each logged event
   RCell* rcell = nullptr;        // batch: local grid of each sub-region
-  uint64_t* rext = nullptr;      // batch: largest element extent per sub-region (key)
+  uint64_t* rext = nullptr;      // batch: largest element extent per sub-region (key), one
+                                 // entry per REXT_STRIDE words
   double rc_fixed_h = 0.0;       // batch: fixed cell edge (0 = adaptive)
   int32_t step0 = 1;             // slice index of the initial surfaces
   int32_t *fstep = nullptr, *face = nullptr;  // bounded: stop step and exit face per point
@@ -2729,10 +2745,11 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
     }
     r->sub_off[n_in] = off;
     if (dalloc(&r->geoms, d->n_sub) != hipSuccess || dalloc(&r->rid, cap) != hipSuccess ||
-        dalloc(&r->rcell, d->n_sub) != hipSuccess || dalloc(&r->rext, d->n_sub) != hipSuccess)
+        dalloc(&r->rcell, d->n_sub) != hipSuccess ||
+        dalloc(&r->rext, (size_t)d->n_sub * REXT_STRIDE) != hipSuccess)
       return fail(SEMIPAR_E_OOM);
     if (hipMemset(r->rcell, 0, sizeof(RCell) * d->n_sub) != hipSuccess ||
-        hipMemset(r->rext, 0, sizeof(uint64_t) * d->n_sub) != hipSuccess)
+        hipMemset(r->rext, 0, sizeof(uint64_t) * d->n_sub * REXT_STRIDE) != hipSuccess)
       return fail(SEMIPAR_E_HIP);
     if (hipMemcpy(r->geoms, hg.data(), sizeof(RegionGeom) * d->n_sub, hipMemcpyHostToDevice) !=
             hipSuccess ||
