@@ -1674,6 +1674,21 @@ __global__ __launch_bounds__(NT) void k_init_insert(const semipar_point_rec* __r
   atomicOr(&ctrl->err, 4);
 }
 
+// Sub-region of every slot of a batch from the first slot of each sub-region (off has
+// n_sub + 1 non-decreasing entries, off[n_sub] = n): the last q with off[q] <= k.
+__global__ __launch_bounds__(NT) void k_fill_rid(int32_t* __restrict__ rid, int n,
+                                                 const int64_t* __restrict__ off, int n_sub) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  int lo = 0, hi = n_sub - 1;  // off[lo] <= k < off[hi + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= (int64_t)k) lo = mid;
+    else hi = mid - 1;
+  }
+  rid[k] = lo;
+}
+
 __global__ __launch_bounds__(NT) void k_fill_i32(int32_t* p, uint64_t m, int32_t v) {
   const uint64_t i = blockIdx.x * (uint64_t)NT + threadIdx.x;
   if (i < m) p[i] = v;
@@ -1747,11 +1762,16 @@ __global__ __launch_bounds__(NT) void k_init_check(Slices X, int n, const int32_
     double e2 = fmax(fmax(fabs(a.x - c.x), fabs(a.y - c.y)), fabs(a.z - c.z));
     key = order_key(e1 + e2);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    uint64_t w = __shfl_xor(key, o, 64);
-    key = w > key ? w : key;
+  key = wave_max_u64(key);
+  // one atomic per block on the shared estimate
+  __shared__ uint64_t wk[NT / 64];
+  if ((threadIdx.x & 63) == 0) wk[threadIdx.x >> 6] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t m = wk[0];
+    for (int w = 1; w < NT / 64; ++w) m = wk[w] > m ? wk[w] : m;
+    atomicMax((unsigned long long*)&ctrl->ext_key, (unsigned long long)m);
   }
-  if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&ctrl->ext_key, (unsigned long long)key);
 }
 
 // Output record of slot k and the surface stream it goes to: a stopped point of a
@@ -1960,6 +1980,8 @@ __global__ __launch_bounds__(NT) void k_sub_stats(int n, const int32_t* __restri
 constexpr int FEAT_GRID = 16;  // cells per side of the occupancy grid of a region
 constexpr int FEAT_CELLS = FEAT_GRID * FEAT_GRID * FEAT_GRID;
 constexpr int FEAT_ACC = 5;  // sum v^2, count, sum edge, count, open pieces
+constexpr int FEAT_STRIDE = 16;  // one cache line per region's sums (their atomics do not share)
+static_assert(FEAT_ACC <= FEAT_STRIDE, "feature sums fit one line");
 
 // Per point of the current surface (before any step): transverse speed of the diamond
 // at k (spatial (L-B)+(R-B) over its time extent), length of the edge to next[k] on
@@ -2009,7 +2031,7 @@ __global__ __launch_bounds__(NT) void k_feat_points(Slices X, int n, int s,
     }
     atomicAdd(&grid[(int64_t)q * FEAT_CELLS + (ci[0] * FEAT_GRID + ci[1]) * FEAT_GRID + ci[2]], 1);
   }
-  double* a = acc + (int64_t)FEAT_ACC * (q < 0 ? 0 : q);
+  double* a = acc + (int64_t)FEAT_STRIDE * (q < 0 ? 0 : q);
   if (wave_uniform(q, live)) {
     for (int o = 32; o > 0; o >>= 1) {
       v2 += __shfl_xor(v2, o, 64);
@@ -2057,7 +2079,7 @@ __global__ __launch_bounds__(256) void k_feat_final(const int32_t* __restrict__ 
   __syncthreads();
   if (t == 0) {
     float* f = feat + 12 * (int64_t)q;
-    const double* a = acc + (int64_t)FEAT_ACC * q;
+    const double* a = acc + (int64_t)FEAT_STRIDE * q;
     const double size = 1.4142135623730951 * 0.5 / geoms[q].inv2g;
     f[0] = (float)log1p((double)nq);
     f[1] = (float)log1p(a[4]);
@@ -2736,12 +2758,11 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       hg[i].inv2g = d->sub[i].inv2g;
       hg[i].sqrt3 = std::sqrt(3.0);
     }
-    std::vector<int32_t> hr((size_t)std::max<int64_t>(total, 1));
     int64_t off = 0;
     r->sub_off.assign((size_t)n_in + 1, 0);
     for (int i = 0; i < n_in; ++i) {
       r->sub_off[i] = off;
-      for (int64_t q = 0; q < in[i].n; ++q) hr[off++] = i;
+      off += in[i].n;
     }
     r->sub_off[n_in] = off;
     if (dalloc(&r->geoms, d->n_sub) != hipSuccess || dalloc(&r->rid, cap) != hipSuccess ||
@@ -2752,10 +2773,22 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
         hipMemset(r->rext, 0, sizeof(uint64_t) * d->n_sub * REXT_STRIDE) != hipSuccess)
       return fail(SEMIPAR_E_HIP);
     if (hipMemcpy(r->geoms, hg.data(), sizeof(RegionGeom) * d->n_sub, hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        (total > 0 && hipMemcpy(r->rid, hr.data(), sizeof(int32_t) * total,
-                                hipMemcpyHostToDevice) != hipSuccess))
+        hipSuccess)
       return fail(SEMIPAR_E_HIP);
+    if (total > 0) {
+      // sub-region of each slot, filled on the device from the sub-region offsets
+      int64_t* doff = nullptr;
+      if (dalloc(&doff, (size_t)n_in + 1) != hipSuccess) return fail(SEMIPAR_E_OOM);
+      const bool ok =
+          hipMemcpy(doff, r->sub_off.data(), sizeof(int64_t) * ((size_t)n_in + 1),
+                    hipMemcpyHostToDevice) == hipSuccess;
+      if (ok)
+        k_fill_rid<<<blocks(total), NT, 0, r->stream>>>(r->rid, (int)total, doff, n_in);
+      const bool ok2 = ok && hipGetLastError() == hipSuccess &&
+                       hipStreamSynchronize(r->stream) == hipSuccess;
+      dfree(doff);
+      if (!ok2) return fail(SEMIPAR_E_HIP);
+    }
   }
   if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess)
     return fail(SEMIPAR_E_HIP);
@@ -3353,14 +3386,14 @@ int batch_features(semipar_region* r, float* feat) {
   int64_t* np = nullptr;
   float* df = nullptr;
   int rc = SEMIPAR_OK;
-  if (dalloc(&acc, FEAT_ACC * (size_t)ns) != hipSuccess ||
+  if (dalloc(&acc, FEAT_STRIDE * (size_t)ns) != hipSuccess ||
       dalloc(&grid, (size_t)FEAT_CELLS * ns) != hipSuccess || dalloc(&np, ns) != hipSuccess ||
       dalloc(&df, 12 * (size_t)ns) != hipSuccess)
     rc = SEMIPAR_E_OOM;
   std::vector<int64_t> hn((size_t)ns);
   for (int q = 0; q < ns; ++q) hn[q] = r->sub_off[q + 1] - r->sub_off[q];
   if (rc == SEMIPAR_OK &&
-      (hipMemsetAsync(acc, 0, sizeof(double) * FEAT_ACC * ns, r->stream) != hipSuccess ||
+      (hipMemsetAsync(acc, 0, sizeof(double) * FEAT_STRIDE * ns, r->stream) != hipSuccess ||
        hipMemsetAsync(grid, 0, sizeof(int32_t) * FEAT_CELLS * (size_t)ns, r->stream) != hipSuccess ||
        hipMemcpyAsync(np, hn.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, r->stream) !=
            hipSuccess))
