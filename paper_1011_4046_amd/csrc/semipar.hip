@@ -376,6 +376,8 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   const int k = ii < n ? ii : n;
   uint64_t xk = 0;  // this point's element extent
   bool still = false;  // k advanced in this step (and so is still active)
+  bool hashed = false;  // k's element goes to bucket hbk of the spatial hash
+  uint32_t hbk = 0;
   // a point of a bounded region that stopped before this step, or a point of a removed
   // loop (fstep is then passed for a whole-volume region too), has nothing to do (its
   // element cell already reads NO_ELEM)
@@ -508,7 +510,8 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
             const uint32_t bk =
                 local ? (C.base + cell_index(C.nc, ci[0], ci[1], ci[2])) & hc.bmask
                       : bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
-            epos[k] = atomicAdd(&cnt[bk], 1);
+            hashed = true;
+            hbk = bk;
             ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
           }
         }
@@ -516,6 +519,28 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
     } else if constexpr (SCR != 0) {
       ecell[k] = NO_ELEM;
     }
+  }
+  // slots in bucket order: neighbouring lanes are neighbouring points of a string and
+  // often share a cell, so each run of lanes with one bucket reserves its places with a
+  // single atomic (the order of entries within a bucket is immaterial to the screen)
+  if constexpr (SCR != 0) {
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t pb = __shfl_up(hbk, 1, 64);
+    const bool ph = __shfl_up(hashed ? 1 : 0, 1, 64) != 0;
+    const bool head = hashed && (lane == 0 || !ph || pb != hbk);
+    const uint64_t heads = __ballot(head);
+    const uint64_t inmask = __ballot(hashed);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0..lane
+    int base = 0;
+    if (head) {
+      const uint64_t after = (heads | ~inmask) & ~upto;  // run boundaries past this lane
+      const int end = after ? __ffsll((unsigned long long)after) - 1 : 64;
+      base = atomicAdd(&cnt[hbk], end - lane);
+    }
+    const uint64_t hs = heads & upto;
+    const int hl = hs ? 63 - __clzll((long long)hs) : 0;
+    base = __shfl(base, hl, 64);
+    if (hashed) epos[k] = base + (lane - hl);
   }
   // batch: largest element extent per sub-region (one atomic per wave when the wave
   // holds one sub-region)
