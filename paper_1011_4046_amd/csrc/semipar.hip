@@ -110,9 +110,6 @@ struct Ctrl {
   int32_t step_limit;  // a step is taken only while step < step_limit
   int32_t done;        // set: every kernel of a step returns at once
   int32_t defer;       // step not taken: 1 candidates, 2 events, 4 log overflowed
-  int32_t n_cand;      // candidate appends this step (may exceed the buffer)
-  int32_t n_evt;       // confirmed crossings this step (may exceed the buffer)
-  int32_t n_large;     // elements of this step outside the hash
   int32_t stamp;       // resolve iteration stamp
   uint64_t tmin_key;   // order key of the smallest t of the slice being written
   double t_end;
@@ -126,6 +123,11 @@ struct Ctrl {
   double box;          // periodic length (for the grid choice)
   double grow;         // next cell = grow * largest element extent of this step
   double tol;          // slack of FP64 spatial comparisons
+  // the counters that the step kernels update atomically, on a cache line apart from
+  // the fields every workgroup reads at its start
+  alignas(128) int32_t n_cand;  // candidate appends this step (may exceed the buffer)
+  int32_t n_evt;                // confirmed crossings this step (may exceed the buffer)
+  int32_t n_large;              // elements of this step outside the hash
 };
 
 struct Slices {
