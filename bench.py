@@ -53,9 +53,10 @@ def evolve_bytes_per_point(screen_f32, bounded):
 
 
 def screen_bytes_per_element(screen_f32):
-    """Compulsory HBM bytes of k_screen per element: its cell-sorted entry (cell, slot:
-    2 x int32) and screen box (8 x FP32 or FP64), each read once."""
-    return 8 + (32 if screen_f32 else 64)
+    """Compulsory HBM bytes of k_screen per element, its cell-sorted entry read once:
+    FP32, the spatial box with the cell key and slot packed in (8 x 4 B); FP64, the
+    (cell, slot) pair (2 x int32) and the box (8 x FP64)."""
+    return 32 if screen_f32 else 8 + 64
 
 
 def log(*a):

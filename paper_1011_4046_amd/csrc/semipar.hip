@@ -690,17 +690,21 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
     b = bucket_of(nc, hc.bmask, x, y, z);
   }
   const int pos = bucket_start(loc, toff, b) + epos[k];
-  sent[pos] = make_int2(key, k);
   if constexpr (SCR == 1) {
+    sent[pos] = make_int2(key, k);
     const double4* src = (const double4*)ebox + (size_t)k * 2;
     double4* dst = (double4*)sbox + (size_t)pos * 2;
     dst[0] = src[0];
     dst[1] = src[1];
   } else {
+    // (lo.xyz, key), (hi.xyz, slot): the screen's spatial box with its key and slot
     const float4* src = (const float4*)ebox + (size_t)k * 2;
     float4* dst = (float4*)sbox + (size_t)pos * 2;
-    dst[0] = src[0];
-    dst[1] = src[1];
+    float4 lo = src[0], hi = src[1];
+    lo.w = __int_as_float(key);
+    hi.w = __int_as_float(k);
+    dst[0] = lo;
+    dst[1] = hi;
   }
   }  // grid-stride loop
 }
@@ -741,13 +745,26 @@ __device__ __forceinline__ SBox<T> load_sbox(const void* sbox, int q) {
   return b;
 }
 
-// Overlap of box a with box b shifted by (sx, sy, sz), spatial slack tl, exact in t.
+// Spatial overlap of box a with box b shifted by (sx, sy, sz), slack tl. The screen
+// tests space only: the time ranges of elements of one band that are close in space
+// nearly always overlap, and the FP64 confirmation tests the exact 4-D boxes, so leaving
+// time out only admits a few more candidates (in either precision).
 template <class T>
 __device__ __forceinline__ bool box_overlap(const SBox<T>& a, const SBox<T>& b, T sx, T sy, T sz,
                                             T tl) {
   return a.v[0] <= b.v[4] + sx + tl && b.v[0] + sx <= a.v[4] + tl && a.v[1] <= b.v[5] + sy + tl &&
-         b.v[1] + sy <= a.v[5] + tl && a.v[2] <= b.v[6] + sz + tl && b.v[2] + sz <= a.v[6] + tl &&
-         a.v[3] <= b.v[7] && b.v[3] <= a.v[7];
+         b.v[1] + sy <= a.v[5] + tl && a.v[2] <= b.v[6] + sz + tl && b.v[2] + sz <= a.v[6] + tl;
+}
+
+// The FP32 screen's sorted entries carry their cell key and slot in the fourth component
+// of the two float4 (lo.xyz, key) and (hi.xyz, slot), where the time range would be: one
+// 32-byte entry per element, read with two loads.
+template <int SCR>
+__device__ __forceinline__ int2 entry_key_slot(const int2* __restrict__ sent,
+                                               const SBox<typename std::conditional<SCR == 1, double, float>::type>& b,
+                                               int q) {
+  if constexpr (SCR == 2) return make_int2(__float_as_int(b.v[3]), __float_as_int(b.v[7]));
+  else return sent[q];
 }
 
 constexpr int SBUF = 1024;       // candidates staged in LDS per block (more go straight to memory)
@@ -786,6 +803,7 @@ constexpr int SCREEN_EPW = 12;  // elements per wave when five lanes share an el
 template <int SCR, int G>
 __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int n, const int2* __restrict__ sent,
                                                const void* __restrict__ sbox,
+                                               const void* __restrict__ ebox_slot,
                                                const int32_t* __restrict__ nxt,
                                                const int32_t* __restrict__ prv,
                                                const int32_t* __restrict__ loc,
@@ -845,7 +863,8 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
     double wl[3], ex[3], tlo, thi;  // wrapped box of the element (for large partners)
     if (q < n_norm) {
       own_large = false;
-      const int2 ent = sent[q];
+      const SBox<T> me = load_sbox<T>(sbox, q);
+      const int2 ent = entry_key_slot<SCR>(sent, me, q);
       k = ent.y;
       // grid of the element: the region's own (batch) or the periodic box's
       RCell C{};
@@ -859,7 +878,6 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
       }
       const int32_t c = (int32_t)((uint32_t)ent.x ^ salt);
       const int nk = nxt[k], pk = prv[k];
-      const SBox<T> me = load_sbox<T>(sbox, q);
       const int cx = c & 1023, cy = (c >> 10) & 1023, cz = (c >> 20) & 1023;
       const T tl = SCR == 1 ? (T)hc.tol : (T)(local ? C.marg32 : cs.marg32);
       const T hh = SCR == 1 ? (T)(local ? C.h : cs.h) : (T)(local ? C.h32 : cs.h32);
@@ -889,13 +907,16 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
           SBox<T> b4[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            e4[v] = sent[q2 + v];
             b4[v] = load_sbox<T>(sbox, q2 + v);
+            e4[v] = entry_key_slot<SCR>(sent, b4[v], q2 + v);
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) test(e4[v], b4[v]);
         }
-        for (; q2 < end; ++q2) test(sent[q2], load_sbox<T>(sbox, q2));
+        for (; q2 < end; ++q2) {
+          const SBox<T> b1 = load_sbox<T>(sbox, q2);
+          test(entry_key_slot<SCR>(sent, b1, q2), b1);
+        }
       };
       // phase 1: every pencil's entry range (all bucket-offset loads issued before any
       // range is scanned). A pencil whose cells are consecutive buckets is kept as one
@@ -987,13 +1008,16 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
           SBox<T> b4[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            e4[v] = sent[q2 + v];
             b4[v] = load_sbox<T>(sbox, q2 + v);
+            e4[v] = entry_key_slot<SCR>(sent, b4[v], q2 + v);
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) test2(e4[v], b4[v]);
         }
-        for (; q2 < end; ++q2) test2(sent[q2], load_sbox<T>(sbox, q2));
+        for (; q2 < end; ++q2) {
+          const SBox<T> b1 = load_sbox<T>(sbox, q2);
+          test2(entry_key_slot<SCR>(sent, b1, q2), b1);
+        }
       }
       if (g == 0) {
         // the element's box in global coordinates (any periodic image) for the
@@ -1009,8 +1033,10 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
           tlo = me.v[3];
           thi = me.v[7];
         } else {
-          tlo = (double)me.v[3] + hc.tref;
-          thi = (double)me.v[7] + hc.tref;
+          // the sorted entry holds key and slot there: the time range from the slot's box
+          const float4* eb = (const float4*)ebox_slot + (size_t)k * 2;
+          tlo = (double)eb[0].w + hc.tref;
+          thi = (double)eb[1].w + hc.tref;
         }
       }
     } else {
@@ -2469,8 +2495,8 @@ void launch_screen_t(semipar_region* r, int n, int nb) {
   // workgroups walking them
   const int nl = G == 1 ? nb : (int)((n + (NT / 64) * SCREEN_EPW - 1) / ((NT / 64) * SCREEN_EPW));
   k_screen<SCR, G><<<xcd_grid(std::min(nl, SCREEN_GRID)), NT, 0, r->stream>>>(
-      n, r->sent, r->sbox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc, r->P,
-      r->cand, (int)r->cap_cand, r->ctrl, r->rid, r->rcell);
+      n, r->sent, r->sbox, r->ebox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc,
+      r->P, r->cand, (int)r->cap_cand, r->ctrl, r->rid, r->rcell);
 }
 
 // Screen launch: precision (FP64 / FP32 boxes) and threads per element (1 or 5).
