@@ -129,14 +129,15 @@ def test_screen_precision_does_not_change_events_full_run(S):
 
 
 def test_screen_precision_dense_64_network_false_positive_rate(S):
-    """The dense 64^3 network (about 1.9e6 points, L = 64 correlation lengths): the FP32
-    screen with its conservative margin gives the same events and positions as the FP64
-    screen. Its false-positive rate is (cand_f32 - cand_f64) / cand_f32; the boxes are
-    rounded outward by a few ulps, so it must stay small."""
-    say("case: VV 64^3 seed 0, matter era, 60 steps, f32 vs f64 screen")
+    """The dense 64^3 network (about 1.9e6 points, L = 64 correlation lengths), 500 steps:
+    the FP32 screen with its conservative margin gives the same events and positions as
+    the FP64 screen. Its false-positive rate is (cand_f32 - cand_f64) / cand_f32; both
+    screens test the same spatial boxes and the FP32 ones are rounded outward by a few
+    ulps, so it must stay small."""
+    say("case: VV 64^3 seed 0, matter era, 500 steps, f32 vs f64 screen")
     net = I.vv_network(m=64, seed=0)
-    a = run_gpu(S, net, 60, screen=0, use_graph=True)
-    b = run_gpu(S, net, 60, screen=1, use_graph=True)
+    a = run_gpu(S, net, 500, screen=0, use_graph=True)
+    b = run_gpu(S, net, 500, screen=1, use_graph=True)
     assert_same_events(a[1], b[1])
     assert a[0].tobytes() == b[0].tobytes()
     c64, c32 = a[2]["candidates"], b[2]["candidates"]
