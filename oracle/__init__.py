@@ -100,6 +100,12 @@ def lib():
         L.orc_loop_count.restype = i64
         L.orc_loops.argtypes = [P, P]
         L.orc_loops.restype = ctypes.c_int
+        L.orc_set_coin.argtypes = [P, dbl, ctypes.c_uint64]
+        L.orc_set_coin.restype = ctypes.c_int
+        L.orc_philox4x64.argtypes = [P, P, P]
+        L.orc_philox4x64.restype = None
+        L.orc_coin.argtypes = [ctypes.c_uint64, i32, i64, i64]
+        L.orc_coin.restype = dbl
         _lib = L
     return _lib
 
@@ -131,7 +137,12 @@ class OracleRegion:
         self.h = h
 
     def evolve(self, max_steps, t_end=float("inf"), search=GRID, intercommute=True,
-               loop_every=0):
+               loop_every=0, p=1.0, seed=0):
+        """p: intercommutation probability in (0, 1]; seed: key of the crossings'
+        random numbers (both apply to this call's steps)."""
+        rc = lib().orc_set_coin(self.h, float(p), int(seed))
+        if rc != 0:
+            raise ValueError(f"oracle rejected p = {p} (code {rc})")
         rc = lib().orc_evolve(self.h, int(max_steps), float(t_end), int(search),
                               int(bool(intercommute)), int(loop_every))
         if rc != 0:
@@ -159,10 +170,10 @@ class OracleRegion:
         return out
 
     def stats(self):
-        s = np.zeros(5, dtype=np.int64)
+        s = np.zeros(6, dtype=np.int64)
         lib().orc_stats(self.h, _ptr(s))
         return dict(point_steps=int(s[0]), candidates=int(s[1]), confirmed=int(s[2]),
-                    accepted=int(s[3]), steps=int(s[4]))
+                    accepted=int(s[3]), steps=int(s[4]), passed=int(s[5]))
 
     def last_confirmed(self):
         """Confirmed events of the most recent step, sorted by (t*, id_a, id_b)."""
@@ -205,12 +216,13 @@ class OracleRegion:
             pass
 
 
-def run(net, steps, t_end=float("inf"), search=GRID, intercommute=True, loop_every=0):
+def run(net, steps, t_end=float("inf"), search=GRID, intercommute=True, loop_every=0, p=1.0,
+        seed=0):
     """Convenience: evolve a generated network (or region, when it carries "geom") and
     return (records, events, stats)."""
     hc = {0: 0.0, 1: 2.0, 2: 1.0}[net["cosmology"]]
     r = OracleRegion(net["recs"], net["box"], net["cosmology"], hc, net.get("geom"))
-    r.evolve(steps, t_end, search, intercommute, loop_every)
+    r.evolve(steps, t_end, search, intercommute, loop_every, p, seed)
     out = (r.read(), r.events(), r.stats())
     r.close()
     return out
@@ -241,3 +253,19 @@ def tri_tri(P, Q):
 
 def threads():
     return lib().orc_threads()
+
+
+def philox4x64(ctr, key):
+    """Philox4x64-10 of a 4-word counter under a 2-word key (uint64 words)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    assert c.shape == (4,) and k.shape == (2,)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def coin(seed, step, id_a, id_b):
+    """Uniform number in [0, 1) deciding whether crossing (id_a, id_b) of step
+    `step` exchanges partners (it does when the number is below p)."""
+    return lib().orc_coin(int(seed), int(step), int(id_a), int(id_b))

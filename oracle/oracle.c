@@ -24,7 +24,9 @@
  *    frw_top below is the first-order transport of both past edges across the
  *    diamond under the conformal-gauge FRW string equations, H = hcoef/eta.
  *  - Intersections between different pieces of string are searched each step and
- *    the two strings exchange partners (probability p = 1).
+ *    the two strings exchange partners with probability p (1 for field-theory
+ *    strings; as low as 1e-3 for superstrings). Crossings that do not exchange
+ *    partners pass through each other.
  *
  * Readings where the paper is silent (the paper defers these details to other
  * papers; each is listed in the design doc):
@@ -37,6 +39,12 @@
  *  - one event per element per step: events sorted by (t*, id_min, id_max) and
  *    accepted greedily.
  *  - exchange of partners: swap next[a] and next[b], fix prev.
+ *  - probability p: every confirmed crossing of a step draws u in [0, 1) from the
+ *    counter-based generator Philox4x64-10 (orc_philox4x64 below) with key
+ *    (seed, 0) and counter (id_a, id_b, step, 0), u = (first output word >> 11) 2^-53,
+ *    and exchanges partners only when u < p. The crossings that fail are logged
+ *    (kind 1), claim no element, and count as events for loop removal; the greedy
+ *    matching runs over the others.
  *  - periodic box of side L; positions unwrapped along each point's own trajectory;
  *    differences between distinct points use the minimum image L*rint(d/L).
  */
@@ -117,11 +125,15 @@ typedef struct {
   int64_t n_last_conf;
   /* loop removal */
   int32_t step0;   /* slice of the initial surface */
-  int32_t* ev;     /* step of the last accepted event of each point's element */
+  int32_t* ev;     /* step of the last logged event of each point's element */
   orc_loop* loops;
   int64_t nloops, caploops;
+  /* intercommutation probability and the generator's seed */
+  double p_ic;
+  uint64_t seed;
   /* stats */
   int64_t point_steps, n_cand_total, n_conf_total, n_accepted_total, steps_done;
+  int64_t n_passed_total;
 } orc_region;
 
 /* ------------------------------------------------------------------------------ */
@@ -166,6 +178,49 @@ void orc_top(int cosmology, double hcoef, double box, const double Lp[4], const 
     flat_top(Lp, Rp, Bp, T);
   else
     frw_top(Lp, Rp, Bp, box, hcoef, T);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Counter-based random numbers                                                     */
+/* ------------------------------------------------------------------------------ */
+
+/* Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as
+ * 1, 2, 3", SC 2011): ten rounds over a 4-word counter under a 2-word key. Each round
+ * takes the two 128-bit products M0 c0 and M1 c2 and outputs
+ * (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key grows by
+ * the Weyl increments (W0, W1) before every round but the first. */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+    unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* The uniform number of one crossing: u = (first word >> 11) 2^-53 in [0, 1). */
+double orc_coin(uint64_t seed, int32_t step, int64_t id_a, int64_t id_b) {
+  const uint64_t ctr[4] = {(uint64_t)id_a, (uint64_t)id_b, (uint64_t)(int64_t)step, 0};
+  const uint64_t key[2] = {seed, 0};
+  uint64_t o[4];
+  orc_philox4x64(ctr, key, o);
+  return (double)(o[0] >> 11) * 0x1.0p-53;
 }
 
 /* ------------------------------------------------------------------------------ */
@@ -280,6 +335,8 @@ static int create_impl(const orc_rec* recs, int64_t n, double box, int cosmology
   r->L = box;
   r->cosmology = cosmology;
   r->hcoef = hcoef;
+  r->p_ic = 1.0;
+  r->seed = 0;
   int64_t nn = n > 0 ? n : 1;
   r->id = (int64_t*)malloc(sizeof(int64_t) * nn);
   r->nx = (int32_t*)malloc(sizeof(int32_t) * nn);
@@ -738,6 +795,20 @@ static int one_step(orc_region* r, int search, int intercommute) {
   }
   for (int64_t i = 0; i < nev && rc == ORC_OK; ++i) {
     int64_t a = ev[i].sa, b = ev[i].sb;
+    if (!(orc_coin(r->seed, r->step, ev[i].ida, ev[i].idb) < r->p_ic)) {
+      /* the strings pass through each other: logged, no exchange, no claim */
+      r->ev[a] = r->ev[b] = r->step;
+      orc_event e;
+      e.step = r->step;
+      e.kind = 1;
+      e.id_a = ev[i].ida;
+      e.id_b = ev[i].idb;
+      e.t_star = ev[i].t;
+      memcpy(e.x_star, ev[i].x, sizeof(e.x_star));
+      rc = log_push(r, &e);
+      r->n_passed_total++;
+      continue;
+    }
     if (used[a] || used[b]) continue;
     used[a] = used[b] = 1;
     int32_t ja = r->nx[a], jb = r->nx[b];
@@ -773,7 +844,8 @@ rotate:;
 /* Loop record and removal (Section "Semi-parallel cosmic string simulation": loops that
  * will not intersect again are recorded and removed). Reading: at the start of a step
  * n, a closed chain of still-active points (a loop) of L points is removed when no
- * accepted event touched any of its elements during the last L steps, n - L .. n - 1
+ * logged event (an exchange, or with p < 1 a crossing that passed through) touched
+ * any of its elements during the last L steps, n - L .. n - 1
  * (its period in flat space), and every point lies within a quarter of the box, per
  * axis, of the loop's lowest slot (a string winding the box never does). The record holds the step, L, the
  * id of the lowest slot, the energy sum over k of |X[n][k] - X[n-1][j]| + |X[n][j] -
@@ -952,12 +1024,22 @@ int64_t orc_active(const orc_region* r) { return r->n_active; }
 int32_t orc_step(const orc_region* r) { return r->step; }
 int64_t orc_event_count(const orc_region* r) { return r->nlog; }
 
-void orc_stats(const orc_region* r, int64_t out[5]) {
+void orc_stats(const orc_region* r, int64_t out[6]) {
   out[0] = r->point_steps;
   out[1] = r->n_cand_total;
   out[2] = r->n_conf_total;
   out[3] = r->n_accepted_total;
   out[4] = r->steps_done;
+  out[5] = r->n_passed_total;
+}
+
+/* Intercommutation probability p in (0, 1] and the generator's seed for later steps
+ * (the default is p = 1: every accepted crossing exchanges partners). */
+int orc_set_coin(orc_region* r, double p, uint64_t seed) {
+  if (!r || !(p > 0.0 && p <= 1.0)) return ORC_E_ARG;
+  r->p_ic = p;
+  r->seed = seed;
+  return ORC_OK;
 }
 
 int orc_events(const orc_region* r, orc_event* out) {
