@@ -152,12 +152,13 @@ def bench_batched(args):
     rs_tr = S.RegionSet.from_parts(train, tbox, I.MATTER, device=True, **dag_tr)
     torch.cuda.synchronize()
     screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
-    fast = dict(use_graph=True, screen=screen, out="device", events=True)
+    coin = dict(p=args.p, seed=args.seed)
+    fast = dict(use_graph=True, screen=screen, out="device", events=True, **coin)
 
     # cost model: trained on the logged steps of the training workload
     t = time.perf_counter()
     logrun = S.schedule_regions(rs_tr, S.SCHED_BATCHED, use_graph=True, screen=screen,
-                                out=None, events=False)
+                                out=None, events=False, **coin)
     cm = SC.LearnedCost(seed=0).fit(S.region_features(rs_tr), logrun["region_steps"],
                                     iters=2000, lr=3e-3)
     log(f"cost model: trained on {int((rs_tr.counts > 0).sum())} logged regions, loss "
@@ -214,7 +215,7 @@ def bench_batched(args):
     if args.plain:
         t = time.perf_counter()
         rp = S.schedule_regions(rs, S.SCHED_PLAIN, screen=S.SCREEN_F64, use_graph=False,
-                                steps_per_sync=1, out="device", events=True)
+                                steps_per_sync=1, out="device", events=True, **coin)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t
         pv = rp["stats"]["point_steps"] / tp
@@ -231,7 +232,7 @@ def bench_batched(args):
         rr = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=pred, out=None,
                                 events=False, use_graph=False, screen=screen,
                                 screen_split=cfg["screen_split"],
-                                steps_per_sync=cfg["steps_per_sync"], timed_kernel=kid)
+                                steps_per_sync=cfg["steps_per_sync"], timed_kernel=kid, **coin)
         s2 = rr["stats"]
         ms, nl = s2["timed_kernel_ms"], max(s2["timed_kernel_launches"], 1)
         unit = (evolve_bytes_per_point(screen == S.SCREEN_F32, True) if kname == "k_evolve"
@@ -257,7 +258,7 @@ def bench_batched(args):
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a sample of the regions")
-        cpu = cpu_baseline_regions(parts, box)
+        cpu = cpu_baseline_regions(parts, box, coin=coin)
     return {
         "value": value, "ms_per_step": elapsed * 1e3 / args.steps,
         "config": {"workload": desc,
@@ -266,13 +267,14 @@ def bench_batched(args):
                    "screen": args.screen, "graph": True, "batch_points": bp,
                    "screen_split": cfg["screen_split"], "steps_per_sync": cfg["steps_per_sync"],
                    "lanes": cfg["lanes"], "pack": cfg.get("pack", 0),
+                   "p_intercommute": args.p,
                    "path": "batched + learned cost model (features, inference and schedule "
                            "inside the timed region)"},
         "roofline": roof, "roofline_other": other, "cpu_baseline": cpu, **extra,
     }
 
 
-def cpu_baseline_regions(parts, box, every=50, budget_s=20.0):
+def cpu_baseline_regions(parts, box, every=50, budget_s=20.0, coin=None):
     """The oracle on a bounded sample of the same regions: every `every`-th non-empty
     region, each stepped one lattice step at a time for an equal share of `budget_s`
     seconds (or until it has stopped)."""
@@ -289,7 +291,7 @@ def cpu_baseline_regions(parts, box, every=50, budget_s=20.0):
         ro = O.OracleRegion(recs, box, I.MATTER, I.HCOEF[I.MATTER], geom)
         t1 = time.perf_counter()
         while time.perf_counter() - t1 < share and ro.active > 0:
-            ro.evolve(1)
+            ro.evolve(1, **(coin or {}))
         st = ro.stats()
         ps += st["point_steps"]
         steps += st["steps"]
@@ -315,7 +317,8 @@ def bench_vv32(args):
     t0, t_end = net["t0"], 2.0 * net["t0"]
     raw = torch.from_numpy(net["recs"].view(np.uint8).copy()).cuda()
     screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
-    kw = dict(screen=screen, use_graph=True, steps_per_sync=64)
+    coin = dict(p=args.p, seed=args.seed)
+    kw = dict(screen=screen, use_graph=True, steps_per_sync=64, **coin)
     log(f"VV {args.m}^3 matter era, {n} points, eta {t0} -> {t_end}")
 
     def fresh():
@@ -336,7 +339,7 @@ def bench_vv32(args):
     ps = sum(s["point_steps"] for s in stats)
     r = fresh()
     tst = r.evolve(args.max_steps, t_end, screen=screen, use_graph=False, steps_per_sync=64,
-                   timed_kernel=S.K_EVOLVE)
+                   timed_kernel=S.K_EVOLVE, **coin)
     r.close()
     unit = evolve_bytes_per_point(screen == S.SCREEN_F32, False)
     ms, nl = tst["timed_kernel_ms"], max(tst["timed_kernel_launches"], 1)
@@ -349,7 +352,7 @@ def bench_vv32(args):
         import oracle as O
         ro = O.OracleRegion(net["recs"], net["box"], net["cosmology"], I.HCOEF[net["cosmology"]])
         tc = time.perf_counter()
-        ro.evolve(30)
+        ro.evolve(30, **coin)
         tcpu = time.perf_counter() - tc
         cst = ro.stats()
         ro.close()
@@ -359,7 +362,8 @@ def bench_vv32(args):
     return {"value": ps / elapsed, "ms_per_step": elapsed * 1e3 / args.steps,
             "config": {"workload": f"matter-era VV network {args.m}^3, one whole-volume region, "
                                    f"eta 8 -> 16", "points": n,
-                       "lattice_steps_per_run": stats[0]["steps"], "screen": args.screen},
+                       "lattice_steps_per_run": stats[0]["steps"], "screen": args.screen,
+                       "p_intercommute": args.p},
             "roofline": roof, "cpu_baseline": cpu}
 
 
@@ -391,6 +395,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--max-steps", type=int, default=10 ** 7)
+    ap.add_argument("--p", type=float, default=1.0,
+                    help="intercommutation probability in (0, 1] (1: every crossing exchanges)")
+    ap.add_argument("--seed", type=int, default=0, help="key of the crossings' draws (p < 1)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",

@@ -72,9 +72,11 @@ typedef struct semipar_point_rec {
   double x[4], x_prev[4], r[4], r_prev[4];
 } semipar_point_rec;
 
-/* One intercommutation (exchange of partners), 56 bytes.
+/* One logged crossing, 56 bytes.
  *   step    lattice step n whose band (slice n to n+1) held the crossing
- *   kind    0 = intercommutation
+ *   kind    0 = intercommutation (exchange of partners); 1 = the strings passed through
+ *           each other (intercommutation probability p < 1: the crossing's draw was
+ *           >= p, see semipar_evolve_params.p)
  *   id_a < id_b  ids of the two points whose elements (strip to the right neighbour)
  *           crossed; after the event next(a) and next(b) are exchanged
  *   t_star, x_star  meeting point, in the periodic image of element a */
@@ -173,8 +175,8 @@ typedef struct semipar_region_desc {
  *                 n - n0 a positive multiple of P (n0 the slice of the initial
  *                 surfaces), every closed chain of still-advancing points is tested;
  *                 a chain of L points is recorded (semipar_loop) and its points stop
- *                 (flag REMOVED, no owning face) when no accepted event touched any
- *                 of its elements in steps n - L .. n - 1 (one period of a flat-space
+ *                 (flag REMOVED, no owning face) when no logged event (either kind)
+ *                 touched any of its elements in steps n - L .. n - 1 (one period of a flat-space
  *                 loop of L points) and every point lies within a quarter of the box,
  *                 per axis, of the chain's lowest slot (a string winding the box never
  *                 does). Events are tracked from init, whatever this field was in
@@ -198,6 +200,18 @@ typedef struct semipar_evolve_params {
                              Performance only */
   int32_t loop_every;     /* loop record and removal period P in steps (0: off) */
   int32_t reserved;       /* 0 */
+  double p;               /* intercommutation probability in (0, 1]; 0 means 1 (Section
+                             "Semi-parallel cosmic string simulation": crossing strings
+                             exchange partners with probability p, 1 for field-theory
+                             strings, down to 1e-3 for superstrings). Each confirmed
+                             crossing (id_a < id_b) of step n draws u = (w >> 11) 2^-53,
+                             w the first word of Philox4x64-10 (Salmon et al., SC 2011)
+                             under key (seed, 0) of counter (id_a, id_b, n, 0); u >= p:
+                             the strings pass through (logged with kind 1, neither element
+                             claimed), else the crossing enters the greedy matching.
+                             Results depend on (p, seed) only, never on batching or launch
+                             order. Outside [0, 1] or NaN: SEMIPAR_E_ARG */
+  uint64_t seed;          /* key of the crossings' draws (used when p < 1) */
 } semipar_evolve_params;
 
 /* kernels that can be timed through semipar_evolve_params.timed_kernel */
@@ -227,6 +241,7 @@ typedef struct semipar_evolve_stats {
   int64_t loop_points;    /* points they held */
   int64_t resolve_rounds; /* rounds of the event matching (iterated local minima),
                              summed over the steps taken */
+  int64_t passed;         /* crossings that passed through (p < 1), logged with kind 1 */
 } semipar_evolve_stats;
 
 /* A loop recorded and removed (48 bytes).
@@ -415,7 +430,8 @@ typedef struct semipar_sched_stats {
   int64_t batches;       /* launch batches (PLAIN: one per non-empty region) */
   int64_t point_steps;   /* over all regions */
   int64_t steps;         /* lattice steps summed over batches */
-  int64_t events;        /* intercommutations over all regions */
+  int64_t events;        /* logged crossings over all regions (with p < 1 also those of
+                            kind 1, which passed through) */
   double makespan_ms;    /* host wall time of the call, from the first upload to the
                             last result */
   double evolve_ms;      /* summed device time of the evolve calls */
@@ -423,6 +439,7 @@ typedef struct semipar_sched_stats {
                                     that kernel over all calls (HIP events) */
   int64_t timed_kernel_launches; /* and the number of its launches that did work */
   int64_t loops;                 /* loops recorded and removed over all regions */
+  int64_t passed;                /* crossings that passed through (p < 1) */
 } semipar_sched_stats;
 
 /* Run every region of the tiling on this GPU, in dependency order (paper: manager and

@@ -154,6 +154,7 @@ struct Runner {
     acc.timed_kernel_ms += es.timed_kernel_ms;
     acc.timed_kernel_launches += es.timed_kernel_launches;
     acc.loops += es.loops;
+    acc.passed += es.passed;
     acc.batches += 1;
     log_region(r, steps[0], ps[0], batch_id++, es.elapsed_ms);
     return SEMIPAR_OK;
@@ -248,6 +249,7 @@ struct Runner {
     acc.timed_kernel_ms += es.timed_kernel_ms;
     acc.timed_kernel_launches += es.timed_kernel_launches;
     acc.loops += es.loops;
+    acc.passed += es.passed;
     acc.batches += 1;
     for (size_t i = 0; i < regs.size(); ++i)
       log_region(regs[i], steps[i], ps[i], batch_id, es.elapsed_ms);

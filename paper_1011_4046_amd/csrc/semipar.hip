@@ -114,6 +114,7 @@ struct Ctrl {
   uint64_t tmin_key;   // order key of the smallest t of the slice being written
   double t_end;
   int64_t point_steps, cand_total, conf_total, acc_total, large_total, steps_taken;
+  int64_t pass_total;  // crossings that passed through (probability p < 1)
   int64_t log_n;
   int64_t n_points;
   int32_t err;
@@ -1168,6 +1169,30 @@ __global__ __launch_bounds__(NT) void k_confirm(Slices X, const int32_t* __restr
   }
 }
 
+// The draw that decides whether a crossing exchanges partners (Section "Semi-parallel
+// cosmic string simulation": with probability p). Philox4x64-10 (Salmon, Moraes, Dror and
+// Shaw, SC 2011) under key (seed, 0) of counter (id_a, id_b, step, 0): per round the
+// products M0 c0 and M1 c2 give (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0), then the key
+// advances by the Weyl increments. u = (word 0 >> 11) 2^-53, an exact FP64 value in [0, 1).
+__device__ __forceinline__ double crossing_draw(uint64_t seed, int32_t step, int64_t ida,
+                                                int64_t idb) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  uint64_t c0 = (uint64_t)ida, c1 = (uint64_t)idb, c2 = (uint64_t)(int64_t)step, c3 = 0;
+  uint64_t k0 = seed, k1 = 0;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B97F4A7C15ull;
+    k1 += 0xBB67AE8584CAA73Bull;
+  }
+  return (double)(c0 >> 11) * 0x1.0p-53;
+}
+
 __device__ __forceinline__ bool key_less(const EvCand& p, const EvCand& q) {
   if (p.t < q.t) return true;
   if (p.t > q.t) return false;
@@ -1203,15 +1228,17 @@ __device__ __forceinline__ void propose(uint64_t* best, int slot, uint32_t st, i
 }
 
 // One workgroup: the greedy matching of the step's events in (t*, id_a, id_b) order,
-// computed as iterated local minima; partner exchange; log; step bookkeeping.
+// computed as iterated local minima; partner exchange; log; step bookkeeping. With
+// p < 1 each crossing first draws u; one with u >= p passes through: it is logged
+// (kind 1) and marks its elements for the loop rule, but claims neither.
 __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     int32_t* __restrict__ nxt, int32_t* __restrict__ prv, const EvCand* __restrict__ ev,
     int cap_evt, int cap_cand, uint64_t* __restrict__ best, int32_t* __restrict__ used,
     int8_t* __restrict__ evs, semipar_event* __restrict__ log, int64_t log_cap,
     const uint64_t* __restrict__ blkred, int nblk, Ctrl* ctrl, const int32_t* __restrict__ rid,
-    int32_t* __restrict__ log_rid, int32_t* __restrict__ lev) {
+    int32_t* __restrict__ log_rid, int32_t* __restrict__ lev, double p_ic, uint64_t seed) {
   __shared__ int s_live;
-  __shared__ int s_nacc;
+  __shared__ int s_nacc, s_npass, s_nlog;
   __shared__ uint64_t s_min[RESOLVE_NT / 64], s_max[RESOLVE_NT / 64], s_adv[RESOLVE_NT / 64];
   if (ctrl->done) return;
   const int t = threadIdx.x;
@@ -1235,8 +1262,15 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
   }
   const int32_t step_stamp = ctrl->step + 1;
   const uint32_t base = (uint32_t)ctrl->stamp;
-  for (int e = t; e < ne; e += RESOLVE_NT) evs[e] = 1;
-  if (t == 0) s_nacc = 0;
+  const int32_t n_step = ctrl->step;
+  // 1: in the matching, 3: passes through (2: accepted, 0: blocked, set below)
+  for (int e = t; e < ne; e += RESOLVE_NT)
+    evs[e] = (p_ic >= 1.0 || crossing_draw(seed, n_step, ev[e].ida, ev[e].idb) < p_ic) ? 1 : 3;
+  if (t == 0) {
+    s_nacc = 0;
+    s_npass = 0;
+    s_nlog = 0;
+  }
   __syncthreads();
   uint32_t iter = 0;
   if (ne > 0) {
@@ -1276,20 +1310,25 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
       if (remaining == 0) break;
     }
     // partner exchange (accepted events touch disjoint elements) and log
-    const int32_t n_step = ctrl->step;
     const int64_t log0 = ctrl->log_n;
-    for (int e = t; e < ne; e += RESOLVE_NT)
-      if (evs[e] == 2) {
+    for (int e = t; e < ne; e += RESOLVE_NT) {
+      const int8_t es = evs[e];
+      if (es == 2 || es == 3) {
         const int a = ev[e].sa, b = ev[e].sb;
-        const int ja = nxt[a], jb = nxt[b];
-        nxt[a] = jb;
-        nxt[b] = ja;
-        prv[jb] = a;
-        prv[ja] = b;
-        const int i = atomicAdd(&s_nacc, 1);
+        if (es == 2) {
+          const int ja = nxt[a], jb = nxt[b];
+          nxt[a] = jb;
+          nxt[b] = ja;
+          prv[jb] = a;
+          prv[ja] = b;
+          atomicAdd(&s_nacc, 1);
+        } else {
+          atomicAdd(&s_npass, 1);
+        }
+        const int i = atomicAdd(&s_nlog, 1);
         semipar_event o;
         o.step = n_step;
-        o.kind = 0;
+        o.kind = es == 2 ? 0 : 1;
         o.id_a = ev[e].ida;
         o.id_b = ev[e].idb;
         o.t_star = ev[e].t;
@@ -1301,6 +1340,7 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
         lev[a] = n_step;
         lev[b] = n_step;
       }
+    }
   }
   // smallest t of the slice written by this step's k_evolve, largest element extent
   uint64_t mk = KEY_MAX, xk = 0, ak = 0;
@@ -1327,8 +1367,9 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     }
     if (!ctrl->cells.fixed && x != 0)
       ctrl->cells = choose_cells(ctrl->box, ctrl->grow * from_key(x), ctrl->tol);
-    ctrl->log_n += s_nacc;
+    ctrl->log_n += s_nlog;
     ctrl->acc_total += s_nacc;
+    ctrl->pass_total += s_npass;
     ctrl->conf_total += ne;
     ctrl->cand_total += ncand;
     ctrl->large_total += ctrl->n_large;
@@ -2232,6 +2273,8 @@ struct semipar_region {
   uint64_t* rext = nullptr;      // batch: largest element extent per sub-region (key), one
                                  // entry per REXT_STRIDE words
   double rc_fixed_h = 0.0;       // batch: fixed cell edge (0 = adaptive)
+  double p_ic = 1.0;             // intercommutation probability (the resolve launch carries it)
+  uint64_t seed = 0;             // key of the crossings' draws
   int32_t step0 = 1;             // slice index of the initial surfaces
   int32_t *fstep = nullptr, *face = nullptr;  // bounded: stop step and exit face per point
   uint8_t* wlive = nullptr;  // per 64 slots: 1 while one of them may still advance
@@ -2547,7 +2590,7 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
   mark(r, SEMIPAR_K_RESOLVE, 2 * i);
   k_resolve<<<1, RESOLVE_NT, 0, s>>>(r->nxt, r->prv, r->ev, (int)r->cap_evt, (int)r->cap_cand,
                                      r->best, r->used, r->evs, r->log, r->log_cap, r->blkred, nbe,
-                                     r->ctrl, r->rid, r->log_rid, r->lev);
+                                     r->ctrl, r->rid, r->log_rid, r->lev, r->p_ic, r->seed);
   if (intercommute && r->rcell)
     k_rcells<<<1, 1024, 0, s>>>(r->geoms, r->n_sub, r->rext, r->rcell, r->rc_fixed_h, r->ctrl);
   mark(r, SEMIPAR_K_RESOLVE, 2 * i + 1);
@@ -2923,6 +2966,8 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
 int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evolve_stats* st) {
   if (!r || !p || p->max_steps < 0 || p->loop_every < 0) return SEMIPAR_E_ARG;
   if (p->screen != SEMIPAR_SCREEN_F64 && p->screen != SEMIPAR_SCREEN_F32) return SEMIPAR_E_ARG;
+  const double p_ic = p->p == 0.0 ? 1.0 : p->p;
+  if (!(p_ic > 0.0 && p_ic <= 1.0)) return SEMIPAR_E_ARG;
   if (r->broken) return SEMIPAR_E_STATE;
   semipar_evolve_stats zero{};
   if (st) *st = zero;
@@ -2947,6 +2992,9 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     const int split = sp_ == 1 ? 1 : N_PENCIL;
     if (split != r->split) drop_graph(r);
     r->split = split;
+    if (p_ic != r->p_ic || p->seed != r->seed) drop_graph(r);
+    r->p_ic = p_ic;
+    r->seed = p->seed;
   }
   r->timed = (p->timed_kernel >= 0 && p->timed_kernel <= SEMIPAR_K_RESOLVE) ? p->timed_kernel : -1;
   if (r->timed >= 0) {
@@ -3082,6 +3130,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     st->candidates = a.cand_total - before.cand_total;
     st->confirmed = a.conf_total - before.conf_total;
     st->accepted = a.acc_total - before.acc_total;
+    st->passed = a.pass_total - before.pass_total;
     st->large_elements = a.large_total - before.large_total;
     st->final_step = a.step;
     st->done = 1;

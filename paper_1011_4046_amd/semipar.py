@@ -21,6 +21,7 @@ FLAT, MATTER, RADIATION = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 SCREEN_F64, SCREEN_F32 = 0, 1
 FLAG_HAS_R, FLAG_FROZEN, FLAG_ACTIVE, FLAG_REMOVED = 1, 2, 4, 8
+EVENT_EXCHANGE, EVENT_PASSED = 0, 1  # semipar_event.kind
 K_EVOLVE, K_SCAN, K_SCATTER, K_SCREEN, K_CONFIRM, K_RESOLVE = range(6)
 
 ERRORS = {0: "ok", -1: "E_ARG", -2: "E_SURFACE", -3: "E_OOM", -4: "E_HIP",
@@ -68,7 +69,7 @@ class EvolveParams(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("cand_per_point", ctypes.c_double),
                 ("events_per_point", ctypes.c_double), ("timed_kernel", ctypes.c_int32),
                 ("screen_split", ctypes.c_int32), ("loop_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("p", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class EvolveStats(ctypes.Structure):
@@ -78,7 +79,8 @@ class EvolveStats(ctypes.Structure):
                 ("final_step", ctypes.c_int32), ("done", ctypes.c_int32),
                 ("elapsed_ms", ctypes.c_double), ("timed_kernel_ms", ctypes.c_double),
                 ("timed_kernel_launches", ctypes.c_int64), ("loops", ctypes.c_int64),
-                ("loop_points", ctypes.c_int64), ("resolve_rounds", ctypes.c_int64)]
+                ("loop_points", ctypes.c_int64), ("resolve_rounds", ctypes.c_int64),
+                ("passed", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -110,7 +112,7 @@ class SchedStats(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("events", ctypes.c_int64),
                 ("makespan_ms", ctypes.c_double), ("evolve_ms", ctypes.c_double),
                 ("timed_kernel_ms", ctypes.c_double), ("timed_kernel_launches", ctypes.c_int64),
-                ("loops", ctypes.c_int64)]
+                ("loops", ctypes.c_int64), ("passed", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -257,13 +259,15 @@ class Region:
 
     def evolve(self, max_steps, t_end=float("inf"), screen=SCREEN_F64, intercommute=True,
                cell_size=0.0, steps_per_sync=0, use_graph=False, cand_per_point=0.0,
-               events_per_point=0.0, timed_kernel=-1, screen_split=0, loop_every=0):
-        p = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
-                         float(cell_size), int(steps_per_sync), int(bool(use_graph)),
-                         float(cand_per_point), float(events_per_point), int(timed_kernel),
-                         int(screen_split), int(loop_every), 0)
+               events_per_point=0.0, timed_kernel=-1, screen_split=0, loop_every=0, p=1.0,
+               seed=0):
+        """p: intercommutation probability in (0, 1]; seed: key of the crossings' draws."""
+        prm = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
+                           float(cell_size), int(steps_per_sync), int(bool(use_graph)),
+                           float(cand_per_point), float(events_per_point), int(timed_kernel),
+                           int(screen_split), int(loop_every), 0, float(p), int(seed))
         st = EvolveStats()
-        _check(lib().region_evolve(self.h, ctypes.byref(p), ctypes.byref(st)), "region_evolve")
+        _check(lib().region_evolve(self.h, ctypes.byref(prm), ctypes.byref(st)), "region_evolve")
         return st.as_dict()
 
     def emit_faces(self):
@@ -418,12 +422,13 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
                      screen=SCREEN_F64, intercommute=True, cell_size=0.0, steps_per_sync=0,
                      use_graph=False, cand_per_point=0.0, events_per_point=0.0,
                      screen_split=0, timed_kernel=-1, lanes=1, loop_every=0,
-                     pack=PACK_POINTS):
+                     pack=PACK_POINTS, p=1.0, seed=0):
     """Run every region of rs; returns a dict with the stats, per-region logs, output
     records (out = "host": numpy; "device": torch uint8 CUDA tensor; None: not
     written), their offsets (4 per region + 1) and the events with offsets."""
     L = lib()
     nr = rs.n_regions
+    p_ic = float(p)  # the name p is the parameter block below
     p = SchedParams()
     p.policy = int(policy)
     p.batch_points = int(batch_points)
@@ -437,7 +442,7 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
     p.evolve = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
                             float(cell_size), int(steps_per_sync), int(bool(use_graph)),
                             float(cand_per_point), float(events_per_point), int(timed_kernel),
-                            int(screen_split), int(loop_every), 0)
+                            int(screen_split), int(loop_every), 0, p_ic, int(seed))
     total = int(rs.counts.sum())
     out_off = np.zeros(4 * nr + 1, dtype=np.int64)
     res = {}

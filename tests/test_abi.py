@@ -57,6 +57,7 @@ int main(void) {
   F(semipar_evolve_params, screen_split) F(semipar_evolve_params, loop_every)
   F(semipar_evolve_stats, timed_kernel_launches) F(semipar_evolve_stats, loop_points)
   F(semipar_evolve_stats, resolve_rounds) F(semipar_sched_params, pack)
+  F(semipar_evolve_params, p) F(semipar_evolve_params, seed) F(semipar_evolve_stats, passed)
   F(semipar_loop, rep_id) F(semipar_loop, energy) F(semipar_loop, centre)
   F(semipar_tiling, surfaces) F(semipar_tiling, stream)
   F(semipar_sched_params, cost) F(semipar_sched_params, evolve) F(semipar_sched_params, out)
@@ -64,7 +65,7 @@ int main(void) {
   F(semipar_sched_params, lanes) F(semipar_sched_params, loops)
   F(semipar_sched_params, loops_off)
   F(semipar_sched_stats, makespan_ms) F(semipar_sched_stats, timed_kernel_launches)
-  F(semipar_sched_stats, loops)
+  F(semipar_sched_stats, loops) F(semipar_sched_stats, passed)
   printf("SEMIPAR_FLAG_REMOVED %d\n", SEMIPAR_FLAG_REMOVED);
   return 0;
 }

@@ -1,0 +1,234 @@
+"""GPU parity of the intercommutation probability p < 1 (through the C ABI) against the
+oracle (Section "Semi-parallel cosmic string simulation": crossing strings exchange
+partners with probability p). Every crossing's draw depends only on (seed, id_a, id_b,
+step), so the logged crossings of both kinds, the loops and the final records equal the
+oracle's bit for bit, whole-volume or bounded, alone, batched or scheduled, eager or
+graph-captured, and when p or the seed changes between calls."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1011_4046_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1011_4046_amd import semipar
+    semipar.lib()
+    return semipar
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def by_id(recs):
+    return recs[np.argsort(recs["id"], kind="stable")]
+
+
+def same_records(g, o):
+    assert by_id(g).tobytes() == by_id(o).tobytes()
+
+
+def same_events(g, o):
+    assert len(g) == len(o), (len(g), len(o))
+    assert g.tobytes() == o.tobytes()
+
+
+def same_loops(g, o, box):
+    o = o[np.lexsort((o["rep_id"], o["step"]))]
+    assert len(g) == len(o)
+    for f in ("step", "n_points", "rep_id"):
+        assert np.array_equal(g[f], o[f]), f
+    if len(o):
+        err = np.abs(g["energy"] - o["energy"]) / np.abs(o["energy"])
+        assert float(err.max()) <= 1e-12
+        assert float(np.abs(g["centre"] - o["centre"]).max()) <= 1e-12 * box
+
+
+def oracle_region(net):
+    hc = {0: 0.0, 1: 2.0, 2: 1.0}[net["cosmology"]]
+    return O.OracleRegion(net["recs"], net["box"], net["cosmology"], hc, net.get("geom"))
+
+
+def run_both(S, net, calls, **kw):
+    """Same sequence of calls (max_steps, t_end, p, seed, loop_every) on both sides."""
+    r = S.Region(net["recs"], net["box"], net["cosmology"], geom=net.get("geom"))
+    o = oracle_region(net)
+    sts = []
+    for steps, t_end, p, seed, every in calls:
+        sts.append(r.evolve(steps, t_end, p=p, seed=seed, loop_every=every, **kw))
+        o.evolve(steps, t_end, O.GRID, True, every, p, seed)
+    g = (r.emit(), r.events(), r.loops(), sts)
+    r.close()
+    oo = (o.read(), o.events(), o.loops(), o.stats())
+    o.close()
+    return g, oo
+
+
+@pytest.mark.parametrize("p,seed,graph", [(0.5, 1, False), (0.5, 1, True), (0.05, 7, True),
+                                          (1e-3, 3, True)])
+def test_matter_network_until_t_end(S, p, seed, graph):
+    say(f"case: VV 8^3 seed 2, matter, p {p}, seed {seed}, graph {graph}, until min t >= 16")
+    net = I.vv_network(m=8, seed=2)
+    g, o = run_both(S, net, [(100000, 16.0, p, seed, 0)], use_graph=graph)
+    ev = o[1]
+    assert np.any(ev["kind"] == 1)
+    same_events(g[1], ev)
+    same_records(g[0], o[0])
+    st = g[3][0]
+    assert st["passed"] == o[3]["passed"] == int((ev["kind"] == 1).sum())
+    assert st["accepted"] == o[3]["accepted"] and st["confirmed"] == o[3]["confirmed"]
+
+
+def test_flat_loops_with_removal(S):
+    say("case: 8 KT loops x 256, flat, p 0.3 seed 5, loop_every 16, 600 steps, graph")
+    net = I.kt_loops()
+    g, o = run_both(S, net, [(600, np.inf, 0.3, 5, 16)], use_graph=True, steps_per_sync=7)
+    assert len(o[2]) > 10 and np.any(o[1]["kind"] == 1)
+    same_events(g[1], o[1])
+    same_loops(g[2], o[2], net["box"])
+    same_records(g[0], o[0])
+
+
+def test_p_and_seed_change_between_calls(S):
+    """The captured step block carries p and the seed: a change must take effect."""
+    say("case: VV 6^3 seed 1, matter, calls (p, seed) = (0.5, 1), (0.5, 2), (0.2, 2), (1, 0)")
+    net = I.vv_network(m=6, seed=1)
+    calls = [(30, np.inf, 0.5, 1, 8), (30, np.inf, 0.5, 2, 8), (40, np.inf, 0.2, 2, 8),
+             (300, 16.0, 1.0, 0, 8)]
+    g, o = run_both(S, net, calls, use_graph=True, steps_per_sync=5)
+    assert np.any(o[1]["kind"] == 1) and np.any(o[1]["kind"] == 0)
+    same_events(g[1], o[1])
+    same_loops(g[2], o[2], net["box"])
+    same_records(g[0], o[0])
+
+
+def test_p_one_equals_the_default(S):
+    say("case: VV 6^3 seed 1, matter, p = 1 and p = 0 (means 1) against the default")
+    net = I.vv_network(m=6, seed=1)
+    out = []
+    for kw in ({}, {"p": 1.0, "seed": 9}, {"p": 0.0}):
+        r = S.Region(net["recs"], net["box"], net["cosmology"])
+        st = r.evolve(200, use_graph=True, **kw)
+        out.append((r.emit().tobytes(), r.events().tobytes(), st["passed"]))
+        r.close()
+    assert out[0] == out[1] == out[2] and out[0][2] == 0
+
+
+def test_p_out_of_range_is_rejected(S):
+    say("case: p = -0.1, 1.5, nan rejected with E_ARG")
+    net = I.vv_network(m=4, seed=1)
+    r = S.Region(net["recs"], net["box"], net["cosmology"])
+    for p in (-0.1, 1.5, float("nan")):
+        with pytest.raises(S.SemiparError):
+            r.evolve(5, p=p)
+    r.close()
+
+
+def loops_in_region(size, t_mid, n_loops, n_pts, seed, cosmology):
+    """Closed loops inside one bounded region of the tiling (centred on its middle)."""
+    geom, g = I.region_geometry(size, t_mid)
+    rng = np.random.default_rng(seed)
+    chains = []
+    for _ in range(n_loops):
+        a = I._fourier_closed_curve(rng, 3, n_pts, 1 << 12) * (0.6 * g)
+        b = I._fourier_closed_curve(rng, 3, n_pts, 1 << 12) * (0.6 * g)
+        c = rng.uniform(-0.15 * g, 0.15 * g, 3)
+        k = np.arange(n_pts)
+        chains.append(dict(A=a[(-k) % n_pts] + c, B=b[k] + c, wA=np.zeros(3), wB=np.zeros(3)))
+    net = I.make_network(chains, 64.0, 0.6 * g / n_pts, t_mid, cosmology)
+    net["geom"] = geom
+    return net
+
+
+@pytest.mark.parametrize("cosmo,n_pts,p,seed", [(I.MATTER, 64, 0.25, 4), (I.FLAT, 32, 0.5, 2)])
+def test_bounded_region(S, cosmo, n_pts, p, seed):
+    say(f"case: bounded region, 6 loops x {n_pts}, cosmology {cosmo}, p {p} seed {seed}, "
+        f"loop_every 4")
+    net = loops_in_region(4.0, 8.0, 6, n_pts, 11, cosmo)
+    r = S.Region(net["recs"], net["box"], net["cosmology"], geom=net["geom"])
+    st = r.evolve(100000, p=p, seed=seed, loop_every=4, use_graph=True)
+    faces, ge, gl = r.emit_faces(), r.events(), r.loops()
+    r.close()
+    o = oracle_region(net)
+    o.evolve(100000, np.inf, O.GRID, True, 4, p, seed)
+    oe = o.events()
+    assert np.sum(oe["kind"] == 1) > 20 and len(o.loops()) > 10
+    assert st["passed"] == o.stats()["passed"]
+    same_events(ge, oe)
+    same_loops(gl, o.loops(), net["box"])
+    same_records(np.concatenate(faces), o.read())
+    o.close()
+
+
+SIZES = [0, 300, 1200, 40, 800, 2500]
+P_B, SEED_B = 0.4, 21
+
+
+@pytest.fixture(scope="module")
+def batch_oracle():
+    parts, box = I.region_batch(SIZES, seed=100)
+    out = []
+    for recs_i, geom in parts:
+        if len(recs_i) == 0:
+            out.append((recs_i, np.zeros(0, I.EVENT_DTYPE), np.zeros(0, I.LOOP_DTYPE)))
+            continue
+        o = O.OracleRegion(recs_i, box, I.MATTER, 2.0, geom)
+        o.evolve(100000, np.inf, O.GRID, True, 4, P_B, SEED_B)
+        out.append((o.read(), o.events(), o.loops()))
+        o.close()
+    return parts, box, out
+
+
+def test_batch_equals_separate_regions(S, batch_oracle):
+    say(f"case: batch of {len(SIZES)} bounded regions {SIZES}, matter, p {P_B}, loop_every 4")
+    parts, box, ref = batch_oracle
+    r = S.Region.batch(parts, box, I.MATTER)
+    st = r.evolve(100000, loop_every=4, use_graph=True, p=P_B, seed=SEED_B)
+    faces, ge, gl = r.emit_faces(), r.events(), r.loops()
+    r.close()
+    recs = np.concatenate([x[0] for x in ref])
+    evs = np.concatenate([x[1] for x in ref])
+    lps = np.concatenate([x[2] for x in ref])
+    assert np.any(evs["kind"] == 1) and st["passed"] == int((evs["kind"] == 1).sum())
+    same_loops(gl, lps, box)
+    same_records(np.concatenate(faces), recs)
+    key = lambda e: np.lexsort((e["id_b"], e["id_a"], e["t_star"], e["step"]))
+    assert ge[key(ge)].tobytes() == evs[key(evs)].tobytes()
+
+
+@pytest.mark.parametrize("policy,batch_points,lanes", [(0, 0, 1), (1, 0, 1), (1, 1500, 2)])
+def test_schedule_regions(S, batch_oracle, policy, batch_points, lanes):
+    say(f"case: schedule_regions policy {policy}, batch_points {batch_points}, lanes {lanes}, "
+        f"p {P_B}, loop_every 4")
+    parts, box, ref = batch_oracle
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    res = S.schedule_regions(rs, policy, batch_points=batch_points, lanes=lanes, loop_every=4,
+                             use_graph=True, p=P_B, seed=SEED_B)
+    eo, lo, oo = res["events_off"], res["loops_off"], res["out_off"]
+    assert res["stats"]["passed"] == sum(int((x[1]["kind"] == 1).sum()) for x in ref)
+    for q, (recs, evs, lps) in enumerate(ref):
+        same_events(res["events"][eo[q]:eo[q + 1]], evs)
+        same_loops(res["loops"][lo[q]:lo[q + 1]], lps, box)
+        same_records(res["out"][oo[4 * q]:oo[4 * q + 4]], recs)
+
+
+def test_full_size_network_in_bench_launch_configuration(S):
+    """Full-size matter-era workload (32^3 VV, ~2.4e5 points), 80 steps, p = 0.1,
+    graph-captured blocks of 32 steps, FP32 screen."""
+    say("case: VV 32^3 seed 0, matter, p 0.1 seed 77, 80 steps, graph, sync 32, f32 screen")
+    net = I.vv_network()
+    g, o = run_both(S, net, [(80, np.inf, 0.1, 77, 0)], use_graph=True, steps_per_sync=32,
+                    screen=S.SCREEN_F32, screen_split=1)
+    assert int((o[1]["kind"] == 1).sum()) > 1000
+    same_events(g[1], o[1])
+    same_records(g[0], o[0])
