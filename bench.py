@@ -114,14 +114,15 @@ def make_inputs(args):
 
 def make_tiling_inputs(args):
     """Learned-scheduling workload: the initial slice of a 32^3 matter-era VV network
-    (seed 1) cut into a periodic spacetime tiling of 16 layers x 256 regions, run in
-    dependency order. Training logs come from the seed-0 network in the same tiling."""
+    (seed 1) cut into a periodic spacetime tiling of 16 layers x 4 M^3 regions (M =
+    --split, 4 by default: 256 per layer), run in dependency order. Training logs come
+    from the seed-0 network in the same tiling."""
     from paper_1011_4046_amd import inputs as I
     t = time.perf_counter()
     out = []
     for seed in (1, 0):
         net = I.vv_network(m=args.m, seed=seed)
-        parts, box, n_pred, succ, _ = I.tiling_regions(net, M=4, layers=16)
+        parts, box, n_pred, succ, _ = I.tiling_regions(net, M=args.split_m, layers=16)
         out.append((parts, box, dict(n_pred=n_pred, succ=succ)))
         log(f"tiling (seed {seed}): {len(parts)} regions, "
             f"{sum(1 for p in parts if len(p[0]))} non-empty, "
@@ -132,10 +133,11 @@ def make_tiling_inputs(args):
 def bench_batched(args):
     if args.workload == "tiling":
         (parts, box, dag), (train, tbox, dag_tr) = make_tiling_inputs(args)
+        per = 4 * args.split_m ** 3
         desc = (f"learned scheduling: {args.m}^3 matter-era VV network (seed 1) cut at eta 8 "
-                f"into a periodic spacetime tiling of 16 layers x 256 regions (4096), run in "
-                f"dependency order until every region's points stop; cost model trained on "
-                f"the seed-0 network in the same tiling")
+                f"into a periodic spacetime tiling of 16 layers x {per} regions "
+                f"({16 * per}), run in dependency order until every region's points stop; "
+                f"cost model trained on the seed-0 network in the same tiling")
     else:
         parts, box, train, tbox = make_inputs(args)   # before any GPU use (process pool)
         dag, dag_tr = {}, {}
@@ -196,7 +198,14 @@ def bench_batched(args):
     corr = float(np.corrcoef(np.log(pred[live]), np.log(np.maximum(steps[live], 1)))[0, 1])
     log(f"timed {args.steps} schedules: {elapsed * 1e3:.0f} ms, {point_steps} point-steps, "
         f"{st['batches']} batches, {st['events']} events per schedule")
+    # the paper's split-factor metrics, with lanes in the place of processors: busy
+    # device time of the evolve calls ("CPU time"), makespan ("elapsed"), their ratio
+    # (degree of parallelism) and its share of the lanes (utilisation)
+    busy = st["evolve_ms"]
     extra = {"learned": {"batches": st["batches"], "makespan_ms": st["makespan_ms"],
+                         "evolve_busy_ms": busy,
+                         "parallelism": busy / max(st["makespan_ms"], 1e-9),
+                         "lane_utilisation": busy / max(cfg["lanes"] * st["makespan_ms"], 1e-9),
                          "predict_ms": runs[0]["predict_ms"],
                          "corr_log_pred_log_steps": round(corr, 4)}}
     del runs
@@ -394,6 +403,8 @@ def main():
     ap.add_argument("--plain", type=int, default=1, help="also time the plain per-region path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--m", type=int, default=32)
+    ap.add_argument("--split-m", type=int, default=4,
+                    help="tiling workload: regions per layer 4 M^3 (the split factor)")
     ap.add_argument("--max-steps", type=int, default=10 ** 7)
     ap.add_argument("--p", type=float, default=1.0,
                     help="intercommutation probability in (0, 1] (1: every crossing exchanges)")

@@ -1227,6 +1227,54 @@ __device__ __forceinline__ void propose(uint64_t* best, int slot, uint32_t st, i
   }
 }
 
+// Matching in LDS (steps with at most RES_LDS_EVT events): each event's two elements get
+// a local index through an open-addressing table of slots, and a round's proposals are
+// LDS atomics on 32-bit tags (round << 12 | event). A slot taken by an accepted event
+// holds RES_USED. Key comparisons use the bits of t* (order-preserving) and fall back to
+// the ids in global memory only on equal t*.
+constexpr int RES_LDS_EVT = 4096;
+constexpr int RES_HASH = 12288;  // > 2 RES_LDS_EVT: an insert always finds room
+constexpr uint32_t RES_USED = 0xFFFFFFFFu;
+static_assert(RES_LDS_EVT <= 4096, "event index in the low 12 bits of a tag");
+
+__device__ __forceinline__ uint64_t order_bits(double t) {
+  const uint64_t u = (uint64_t)__double_as_longlong(t + 0.0);  // -0 -> +0
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+// Event e's key is below event f's: (t*, id_a, id_b) order.
+__device__ __forceinline__ bool lkey_less(const uint64_t* s_t, const EvCand* ev, int e, int f) {
+  const uint64_t a = s_t[e], b = s_t[f];
+  if (a != b) return a < b;
+  const int64_t ea = ev[e].ida, fa = ev[f].ida;
+  if (ea != fa) return ea < fa;
+  return ev[e].idb < ev[f].idb;
+}
+
+// Local index of `slot` in the table (inserted if absent).
+__device__ __forceinline__ int lslot(int32_t* s_hkey, int32_t slot) {
+  uint32_t h = (uint32_t)(((uint64_t)((uint32_t)slot * 0x9E3779B1u) * RES_HASH) >> 32);
+  for (;;) {
+    const int32_t prev = atomicCAS(&s_hkey[h], -1, slot);
+    if (prev == -1 || prev == slot) return (int)h;
+    h = h + 1 == (uint32_t)RES_HASH ? 0u : h + 1;
+  }
+}
+
+// Claim local slot h for event e with `tag` unless an event of smaller key holds it this
+// round, or an accepted event took it.
+__device__ __forceinline__ void lpropose(uint32_t* s_best, int h, uint32_t tag, int e,
+                                         const uint64_t* s_t, const EvCand* ev) {
+  uint32_t old = __hip_atomic_load(&s_best[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  for (;;) {
+    if (old == RES_USED) return;
+    if ((old >> 12) == (tag >> 12) && lkey_less(s_t, ev, (int)(old & 4095u), e)) return;
+    const uint32_t prev = atomicCAS(&s_best[h], old, tag);
+    if (prev == old) return;
+    old = prev;
+  }
+}
+
 // One workgroup: the greedy matching of the step's events in (t*, id_a, id_b) order,
 // computed as iterated local minima; partner exchange; log; step bookkeeping. With
 // p < 1 each crossing first draws u; one with u >= p passes through: it is logged
@@ -1239,6 +1287,11 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     int32_t* __restrict__ log_rid, int32_t* __restrict__ lev, double p_ic, uint64_t seed) {
   __shared__ int s_live;
   __shared__ int s_nacc, s_npass, s_nlog;
+  __shared__ uint64_t s_t[RES_LDS_EVT];
+  __shared__ int16_t s_la[RES_LDS_EVT], s_lb[RES_LDS_EVT];
+  __shared__ int8_t s_evs[RES_LDS_EVT];
+  __shared__ int32_t s_hkey[RES_HASH];
+  __shared__ uint32_t s_best[RES_HASH];
   __shared__ uint64_t s_min[RESOLVE_NT / 64], s_max[RESOLVE_NT / 64], s_adv[RESOLVE_NT / 64];
   if (ctrl->done) return;
   const int t = threadIdx.x;
@@ -1263,9 +1316,25 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
   const int32_t step_stamp = ctrl->step + 1;
   const uint32_t base = (uint32_t)ctrl->stamp;
   const int32_t n_step = ctrl->step;
-  // 1: in the matching, 3: passes through (2: accepted, 0: blocked, set below)
-  for (int e = t; e < ne; e += RESOLVE_NT)
-    evs[e] = (p_ic >= 1.0 || crossing_draw(seed, n_step, ev[e].ida, ev[e].idb) < p_ic) ? 1 : 3;
+  const bool in_lds = ne <= RES_LDS_EVT;
+  if (in_lds) {
+    for (int i = t; i < RES_HASH; i += RESOLVE_NT) {
+      s_hkey[i] = -1;
+      s_best[i] = 0;
+    }
+    __syncthreads();
+  }
+  // event states: 1 in the matching, 3 passes through (2 accepted, 0 blocked, set below)
+  int8_t* const st = in_lds ? s_evs : evs;
+  for (int e = t; e < ne; e += RESOLVE_NT) {
+    const int64_t ia = ev[e].ida, ib = ev[e].idb;
+    st[e] = (p_ic >= 1.0 || crossing_draw(seed, n_step, ia, ib) < p_ic) ? 1 : 3;
+    if (in_lds) {
+      s_t[e] = order_bits(ev[e].t);
+      s_la[e] = (int16_t)lslot(s_hkey, ev[e].sa);
+      s_lb[e] = (int16_t)lslot(s_hkey, ev[e].sb);
+    }
+  }
   if (t == 0) {
     s_nacc = 0;
     s_npass = 0;
@@ -1273,7 +1342,45 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
   }
   __syncthreads();
   uint32_t iter = 0;
-  if (ne > 0) {
+  if (ne > 0 && in_lds) {
+    for (;;) {
+      const uint32_t tag0 = (iter + 1) << 12;
+      for (int e = t; e < ne; e += RESOLVE_NT)
+        if (s_evs[e] == 1) {
+          lpropose(s_best, s_la[e], tag0 | (uint32_t)e, e, s_t, ev);
+          lpropose(s_best, s_lb[e], tag0 | (uint32_t)e, e, s_t, ev);
+        }
+      __syncthreads();
+      // an event holding both its slots is accepted and takes them; an event whose
+      // slot holds another tag cannot hold it, so the two checks do not interfere
+      for (int e = t; e < ne; e += RESOLVE_NT)
+        if (s_evs[e] == 1) {
+          const uint32_t tag = tag0 | (uint32_t)e;
+          const int la = s_la[e], lb = s_lb[e];
+          if (s_best[la] == tag && s_best[lb] == tag) {
+            s_evs[e] = 2;
+            s_best[la] = RES_USED;
+            s_best[lb] = RES_USED;
+          }
+        }
+      if (t == 0) s_live = 0;
+      __syncthreads();
+      int live = 0;
+      for (int e = t; e < ne; e += RESOLVE_NT)
+        if (s_evs[e] == 1) {
+          if (s_best[s_la[e]] == RES_USED || s_best[s_lb[e]] == RES_USED)
+            s_evs[e] = 0;
+          else
+            live++;
+        }
+      if (live) atomicAdd(&s_live, live);
+      __syncthreads();
+      const int remaining = s_live;
+      __syncthreads();
+      ++iter;
+      if (remaining == 0) break;
+    }
+  } else if (ne > 0) {
     for (;;) {
       const uint32_t stp = base + 1 + iter;
       for (int e = t; e < ne; e += RESOLVE_NT)
@@ -1309,10 +1416,12 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
       ++iter;
       if (remaining == 0) break;
     }
+  }
+  if (ne > 0) {
     // partner exchange (accepted events touch disjoint elements) and log
     const int64_t log0 = ctrl->log_n;
     for (int e = t; e < ne; e += RESOLVE_NT) {
-      const int8_t es = evs[e];
+      const int8_t es = st[e];
       if (es == 2 || es == 3) {
         const int a = ev[e].sa, b = ev[e].sb;
         if (es == 2) {

@@ -570,17 +570,19 @@ def tiling_regions(net, M=4, layers=16, lead=1.75):
     per = 4 * M ** 3
     nr = layers * per
     # points: region index from the initial-slice position, moved to the canonical image
+    # (a point within rounding of a region boundary may land in the neighbouring region
+    # after a move; it is moved again until its own coordinates put it in a canonical one)
     x0, x1 = recs["x_prev"][:, :3].copy(), recs["x"][:, :3].copy()
-    c = _gen_coords(x0, recs["x_prev"][:, 3], V, inv2g)
-    i = np.floor(c).astype(np.int64)
-    p = i @ A.T
-    wrap = np.floor_divide(p, K)
-    x0 -= wrap * L
-    x1 -= wrap * L
-    c2 = _gen_coords(x0, recs["x_prev"][:, 3], V, inv2g)
-    i2 = np.floor(c2).astype(np.int64)
-    shift = np.array([[M, M, -M, -M], [M, -M, M, -M], [M, -M, -M, M]], dtype=np.int64)
-    assert np.array_equal(i2, i - wrap @ shift), "a point sits on a region boundary"
+    for _ in range(4):
+        c2 = _gen_coords(x0, recs["x_prev"][:, 3], V, inv2g)
+        i2 = np.floor(c2).astype(np.int64)
+        wrap = np.floor_divide(i2 @ A.T, K)
+        if not wrap.any():
+            break
+        x0 -= wrap * L
+        x1 -= wrap * L
+    else:
+        raise AssertionError("points do not settle in a canonical region image")
     S_pt = i2.sum(1)
     p2 = i2 @ A.T
     assert np.all((p2 >= 0) & (p2 < K))
