@@ -2325,10 +2325,25 @@ __global__ __launch_bounds__(NT) void k_ev_gather(const semipar_event* __restric
                                                   semipar_event* __restrict__ out,
                                                   int32_t* __restrict__ cnt) {
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
-  if (i >= n) return;
-  const int32_t e = idx[i];
-  out[i] = log[e];
-  atomicAdd(&cnt[lrid[e]], 1);
+  const bool live = i < n;
+  int32_t q = -1;
+  if (live) {
+    const int32_t e = idx[i];
+    out[i] = log[e];
+    q = lrid[e];
+  }
+  // The events are in sub-region order, so a wave holds a few runs of equal sub-region:
+  // one counter update per run (per-event atomics on a few cache lines serialise).
+  const int lane = (int)(threadIdx.x & 63);
+  const int32_t qp = __shfl_up(q, 1, 64);
+  const bool head = live && (lane == 0 || qp != q);
+  const uint64_t heads = __ballot(head);
+  const int n_live = __popcll(__ballot(live));
+  if (head) {
+    const uint64_t above = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+    const int end = above ? __ffsll((unsigned long long)above) - 1 : n_live;
+    atomicAdd(&cnt[q], end - lane);
+  }
 }
 
 // ---------------------------------------------------------------------------------
