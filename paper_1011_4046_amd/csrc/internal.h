@@ -42,6 +42,11 @@ SP_HIDDEN int batch_loops(semipar_region* r, std::vector<semipar_loop>& lp,
 // The 12 cost-model features of each sub-region's current surface (host, 12 n_sub).
 SP_HIDDEN int batch_features(semipar_region* r, float* feat);
 
+// The same features of every region of a tiling read in place from its surfaces, which
+// must all be device memory (SEMIPAR_E_ARG otherwise, nothing launched): no region state
+// is built, only an id table for the right neighbours (host, 12 n_regions).
+SP_HIDDEN int surface_features(const semipar_tiling* t, float* feat);
+
 // Record an error message for semipar_last_error.
 SP_HIDDEN void set_error(const char* msg);
 

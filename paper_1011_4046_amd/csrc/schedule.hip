@@ -493,6 +493,11 @@ int semipar_region_features(const semipar_tiling* t, float* feat) {
   int rc = check_tiling(t);
   if (rc != SEMIPAR_OK || !feat) return SEMIPAR_E_ARG;
   if (t->n_regions == 0) return SEMIPAR_OK;
+  // surfaces in device memory: read in place; otherwise through a batch of all regions
+  bool on_device = true;
+  for (int r = 0; r < t->n_regions; ++r)
+    on_device = on_device && (t->surfaces[r].n == 0 || t->surfaces[r].mem == SEMIPAR_MEM_DEVICE);
+  if (on_device) return spi::surface_features(t, feat);
   std::vector<int32_t> all((size_t)t->n_regions);
   std::iota(all.begin(), all.end(), 0);
   std::vector<semipar_region_geom> g;

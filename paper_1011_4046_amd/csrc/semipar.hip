@@ -2190,23 +2190,17 @@ static_assert(FEAT_ACC <= FEAT_STRIDE, "feature sums fit one line");
 // at k (spatial (L-B)+(R-B) over its time extent), length of the edge to next[k] on
 // the current slice, open-piece starts (no prev), and the occupancy of a 16^3 grid
 // over the spatial cube of side 2g around the region's centre.
-__global__ __launch_bounds__(NT) void k_feat_points(Slices X, int n, int s,
-                                                    const int32_t* __restrict__ nxt,
-                                                    const int32_t* __restrict__ prv,
-                                                    const int32_t* __restrict__ rid,
-                                                    const RegionGeom* __restrict__ geoms,
-                                                    sp::Period P, double* __restrict__ acc,
-                                                    int32_t* __restrict__ grid) {
-  const int k = blockIdx.x * NT + threadIdx.x;
-  const bool live = k < n;
-  const int q = live ? rid[k] : -1;
+// One point's share of its sub-region's feature sums (every lane of the wave calls it):
+// L its vertex on the current slice; with a right neighbour (has_j), R and B that
+// neighbour's vertices on the current and previous slices; open: no left neighbour.
+__device__ __forceinline__ void feat_accumulate(bool live, int q, const V4& L, bool has_j,
+                                                const V4& R, const V4& B, bool open_,
+                                                const RegionGeom* __restrict__ geoms,
+                                                const sp::Period& P, double* __restrict__ acc,
+                                                int32_t* __restrict__ grid) {
   double v2 = 0.0, nv = 0.0, e = 0.0, ne = 0.0, open = 0.0;
   if (live) {
-    const int ic = s % 3, ip = (s + 2) % 3;
-    const V4 L = ld(X, ic, k);
-    const int j = nxt[k];
-    if (j >= 0) {
-      const V4 R = ld(X, ic, j), B = ld(X, ip, j);
+    if (has_j) {
       const double ax = sp::min_image(L.x - B.x, P), ay = sp::min_image(L.y - B.y, P),
                    az = sp::min_image(L.z - B.z, P);
       const double vx = ax + (R.x - B.x), vy = ay + (R.y - B.y), vz = az + (R.z - B.z);
@@ -2220,7 +2214,7 @@ __global__ __launch_bounds__(NT) void k_feat_points(Slices X, int n, int s,
       e = sqrt(ex * ex + ey * ey + ez * ez);
       ne = 1.0;
     }
-    if (prv[k] < 0) open = 1.0;
+    if (open_) open = 1.0;
     const RegionGeom& G = geoms[q];
     const double g = 0.5 / G.inv2g;
     double ctr[3];
@@ -2252,6 +2246,100 @@ __global__ __launch_bounds__(NT) void k_feat_points(Slices X, int n, int s,
   atomicAdd(&a[2], e);
   atomicAdd(&a[3], ne);
   atomicAdd(&a[4], open);
+}
+
+__global__ __launch_bounds__(NT) void k_feat_points(Slices X, int n, int s,
+                                                    const int32_t* __restrict__ nxt,
+                                                    const int32_t* __restrict__ prv,
+                                                    const int32_t* __restrict__ rid,
+                                                    const RegionGeom* __restrict__ geoms,
+                                                    sp::Period P, double* __restrict__ acc,
+                                                    int32_t* __restrict__ grid) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const bool live = k < n;
+  const int q = live ? rid[k] : -1;
+  V4 L{}, R{}, B{};
+  bool has_j = false, open_ = false;
+  if (live) {
+    const int ic = s % 3, ip = (s + 2) % 3;
+    L = ld(X, ic, k);
+    const int j = nxt[k];
+    if (j >= 0) {
+      R = ld(X, ic, j);
+      B = ld(X, ip, j);
+      has_j = true;
+    }
+    open_ = prv[k] < 0;
+  }
+  feat_accumulate(live, q, L, has_j, R, B, open_, geoms, P, acc, grid);
+}
+
+// The same sums straight from the surfaces of a tiling (device memory, read in place):
+// point k of the concatenation lies in region q = region_of(k) at k - off[q].
+__device__ __forceinline__ int region_of(const int64_t* __restrict__ off, int nr, int64_t k) {
+  int lo = 0, hi = nr - 1;  // off[lo] <= k < off[hi + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(NT) void k_featsurf_insert(
+    const semipar_point_rec* const* __restrict__ srf, const int64_t* __restrict__ off, int nr,
+    int n, int64_t* __restrict__ hkey, int32_t* __restrict__ hval, uint32_t hmask,
+    int32_t* __restrict__ err) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const int q = region_of(off, nr, k);
+  const int64_t id = srf[q][k - off[q]].id;
+  if (id == ID_EMPTY) {
+    atomicOr(err, 1);
+    return;
+  }
+  uint32_t h = id_hash(id, hmask);
+  for (uint32_t probe = 0; probe <= hmask; ++probe) {
+    const unsigned long long prev = atomicCAS((unsigned long long*)&hkey[h],
+                                              (unsigned long long)ID_EMPTY, (unsigned long long)id);
+    if ((int64_t)prev == ID_EMPTY) {
+      hval[h] = k;
+      return;
+    }
+    if ((int64_t)prev == id) {
+      atomicOr(err, 2);  // duplicate id
+      return;
+    }
+    h = (h + 1) & hmask;
+  }
+  atomicOr(err, 4);
+}
+
+__global__ __launch_bounds__(NT) void k_featsurf_points(
+    const semipar_point_rec* const* __restrict__ srf, const int64_t* __restrict__ off, int nr,
+    int n, const int64_t* __restrict__ hkey, const int32_t* __restrict__ hval, uint32_t hmask,
+    const RegionGeom* __restrict__ geoms, sp::Period P, double* __restrict__ acc,
+    int32_t* __restrict__ grid) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const bool live = k < n;
+  int q = -1;
+  V4 L{}, R{}, B{};
+  bool has_j = false, open_ = false;
+  if (live) {
+    q = region_of(off, nr, k);
+    const semipar_point_rec& r = srf[q][k - off[q]];
+    L = V4{r.x[0], r.x[1], r.x[2], r.x[3]};
+    const int j = id_lookup(hkey, hval, hmask, r.next_id);
+    if (j >= 0) {
+      const int qj = region_of(off, nr, j);
+      const semipar_point_rec& rj = srf[qj][j - off[qj]];
+      R = V4{rj.x[0], rj.x[1], rj.x[2], rj.x[3]};
+      B = V4{rj.x_prev[0], rj.x_prev[1], rj.x_prev[2], rj.x_prev[3]};
+      has_j = true;
+    }
+    open_ = id_lookup(hkey, hval, hmask, r.prev_id) < 0;
+  }
+  feat_accumulate(live, q, L, has_j, R, B, open_, geoms, P, acc, grid);
 }
 
 // One workgroup per sub-region: the 12 features (FP32).
@@ -3637,6 +3725,96 @@ int batch_features(semipar_region* r, float* feat) {
   dfree(acc);
   dfree(grid);
   dfree(np);
+  dfree(df);
+  return rc;
+}
+
+int surface_features(const semipar_tiling* t, float* feat) {
+  const int nr = t->n_regions;
+  std::vector<int64_t> off((size_t)nr + 1, 0);
+  std::vector<const semipar_point_rec*> ptr((size_t)nr, nullptr);
+  for (int q = 0; q < nr; ++q) {
+    const semipar_surface& sf = t->surfaces[q];
+    if (sf.n > 0 && sf.mem != SEMIPAR_MEM_DEVICE) return SEMIPAR_E_ARG;
+    off[q + 1] = off[q] + sf.n;
+    ptr[q] = sf.recs;
+  }
+  for (int64_t i = 0; i < 12 * (int64_t)nr; ++i) feat[i] = 0.f;
+  const int64_t total = off[nr];
+  if (total == 0) return SEMIPAR_OK;
+  if (total >= (int64_t)1 << 30) return SEMIPAR_E_ARG;
+  const int n = (int)total;
+  uint64_t hcap = 2;
+  while (hcap < 2 * (uint64_t)total) hcap <<= 1;
+  std::vector<RegionGeom> hg((size_t)nr);
+  std::vector<int64_t> hn((size_t)nr);
+  for (int q = 0; q < nr; ++q) {
+    for (int i = 0; i < 4; ++i) {
+      hg[q].V[i] = t->geoms[q].origin[i];
+      hg[q].idx[i] = t->geoms[q].idx[i];
+    }
+    hg[q].inv2g = t->geoms[q].inv2g;
+    hg[q].sqrt3 = std::sqrt(3.0);
+    hn[q] = off[q + 1] - off[q];
+  }
+  sp::Period P{};
+  {
+    int ex = 0;
+    const double mant = std::frexp(t->box, &ex);
+    P.box = t->box;
+    P.pow2 = mant == 0.5 ? 1 : 0;
+    P.inv = P.pow2 ? std::ldexp(1.0, 1 - ex) : 1.0 / t->box;
+  }
+  hipStream_t st = (hipStream_t)t->stream;
+  const semipar_point_rec** dsrf = nullptr;
+  int64_t *doff = nullptr, *hkey = nullptr, *np = nullptr;
+  int32_t *hval = nullptr, *err = nullptr, *grid = nullptr;
+  RegionGeom* dgeo = nullptr;
+  double* acc = nullptr;
+  float* df = nullptr;
+  int rc = SEMIPAR_OK;
+  if (dalloc(&dsrf, (size_t)nr) != hipSuccess || dalloc(&doff, (size_t)nr + 1) != hipSuccess ||
+      dalloc(&dgeo, (size_t)nr) != hipSuccess || dalloc(&np, (size_t)nr) != hipSuccess ||
+      dalloc(&hkey, hcap) != hipSuccess || dalloc(&hval, hcap) != hipSuccess ||
+      dalloc(&err, 1) != hipSuccess || dalloc(&acc, FEAT_STRIDE * (size_t)nr) != hipSuccess ||
+      dalloc(&grid, (size_t)FEAT_CELLS * nr) != hipSuccess || dalloc(&df, 12 * (size_t)nr) != hipSuccess)
+    rc = SEMIPAR_E_OOM;
+  int32_t herr = 0;
+  if (rc == SEMIPAR_OK &&
+      (hipMemcpyAsync(dsrf, ptr.data(), sizeof(void*) * nr, hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (nr + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(dgeo, hg.data(), sizeof(RegionGeom) * nr, hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(np, hn.data(), sizeof(int64_t) * nr, hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemsetAsync(err, 0, sizeof(int32_t), st) != hipSuccess ||
+       hipMemsetAsync(acc, 0, sizeof(double) * FEAT_STRIDE * nr, st) != hipSuccess ||
+       hipMemsetAsync(grid, 0, sizeof(int32_t) * FEAT_CELLS * (size_t)nr, st) != hipSuccess))
+    rc = SEMIPAR_E_HIP;
+  if (rc == SEMIPAR_OK) {
+    const uint32_t hmask = (uint32_t)(hcap - 1);
+    k_fill_i64<<<blocks((int64_t)hcap), NT, 0, st>>>(hkey, hcap, ID_EMPTY);
+    k_featsurf_insert<<<blocks(n), NT, 0, st>>>(dsrf, doff, nr, n, hkey, hval, hmask, err);
+    k_featsurf_points<<<blocks(n), NT, 0, st>>>(dsrf, doff, nr, n, hkey, hval, hmask, dgeo, P,
+                                                acc, grid);
+    k_feat_final<<<nr, 256, 0, st>>>(grid, acc, np, dgeo, df);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(feat, df, sizeof(float) * 12 * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
+    else if (herr != 0)
+      rc = SEMIPAR_E_SURFACE;
+  }
+  if (rc != SEMIPAR_OK)
+    for (int64_t i = 0; i < 12 * (int64_t)nr; ++i) feat[i] = 0.f;
+  dfree(dsrf);
+  dfree(doff);
+  dfree(dgeo);
+  dfree(np);
+  dfree(hkey);
+  dfree(hval);
+  dfree(err);
+  dfree(acc);
+  dfree(grid);
   dfree(df);
   return rc;
 }

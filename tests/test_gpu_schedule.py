@@ -181,28 +181,53 @@ def test_spacetime_tiling_in_dependency_order(S, policy, lanes):
                 assert b[q] > b[r], (r, q)
 
 
-def test_region_features_match_oracle(S):
-    say("case: cost-model features of 12 regions (seed 200) and two strings")
+@pytest.mark.parametrize("device", [False, True])
+def test_region_features_match_oracle(S, device):
+    """Host surfaces go through a batch region of all regions; device surfaces are read
+    in place. Both give the oracle's features."""
+    say(f"case: cost-model features of 12 regions (seed 200) and two strings, device {device}")
     parts, box = I.region_batch(SIZES, seed=200)
     chain, delta = I.straight_string(200, 16.0, v=0.6)
     s1 = I.make_network([chain], 16.0, delta, 8.0, I.MATTER)
     geom, _ = I.region_geometry(4.0, 8.0, (0.3, 0.2, 0.1))
-    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER, device=device)
     f = S.region_features(rs)
     for r, (recs, geom_r) in enumerate(parts):
         want = C.features(recs, geom_r, box)
         assert np.allclose(f[r], want, rtol=1e-5, atol=1e-6), (r, f[r], want)
-    rs1 = S.RegionSet.from_parts([(s1["recs"], geom)], 16.0, I.MATTER)
+    rs1 = S.RegionSet.from_parts([(s1["recs"], geom)], 16.0, I.MATTER, device=device)
     f1 = S.region_features(rs1)[0]
     assert np.allclose(f1, C.features(s1["recs"], geom, 16.0), rtol=1e-5, atol=1e-6)
     assert f1[2] == pytest.approx(0.6, rel=1e-5)
-    # regions of a spacetime tiling: nonzero indices, one shared lattice origin
+    # regions of a spacetime tiling: nonzero indices, one shared lattice origin, empty
+    # regions among them (also the last ones)
     net = I.vv_network(m=8, seed=3)
     tparts, tbox, _, _, _ = I.tiling_regions(net, M=2, layers=6)
-    ft = S.region_features(S.RegionSet.from_parts(tparts, tbox, I.MATTER))
+    assert len(tparts[-1][0]) == 0
+    ft = S.region_features(S.RegionSet.from_parts(tparts, tbox, I.MATTER, device=device))
     for r, (recs, geom_r) in enumerate(tparts):
         want = C.features(recs, geom_r, tbox)
         assert np.allclose(ft[r], want, rtol=1e-5, atol=1e-6), (r, ft[r], want)
+
+
+def test_region_features_in_place_equal_the_batch_path(S):
+    say("case: features of the 512-region workload's first 64 regions, host vs device surfaces")
+    nt = I.lognormal_regions(64, median=2e3, sigma=1.0, cap=2e4, p_empty=0.2, seed=5)
+    parts, box = I.region_batch(nt, size=4.0, seed=5, slots=4)
+    fh = S.region_features(S.RegionSet.from_parts(parts, box, I.MATTER))
+    fd = S.region_features(S.RegionSet.from_parts(parts, box, I.MATTER, device=True))
+    assert np.allclose(fh, fd, rtol=1e-6, atol=1e-7)
+    assert np.all(fd[[len(p[0]) == 0 for p in parts]] == 0)
+
+
+def test_region_features_reject_duplicate_ids_in_place(S):
+    say("case: device surfaces with a duplicated id are rejected")
+    parts, box = I.region_batch([300, 200], seed=7)
+    recs = parts[1][0].copy()
+    recs["id"][5] = parts[0][0]["id"][3]
+    bad = [parts[0], (recs, parts[1][1])]
+    with pytest.raises(S.SemiparError):
+        S.region_features(S.RegionSet.from_parts(bad, box, I.MATTER, device=True))
 
 
 def _mlp_case(seed, n=700):
