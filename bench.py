@@ -28,7 +28,7 @@ same tiling. Same pipeline and report as the default.
 --workload vv32: one whole-volume matter-era region (32^3 VV network, ~2.4e5 points,
 eta 8 -> 16), as before.
 
-Prints one JSON line. --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line. --gpus N > 1 is refused: the library runs on one GPU.
 """
 import argparse
 import json
@@ -411,7 +411,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0, help="key of the crossings' draws (p < 1)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the library runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
     res = bench_vv32(args) if args.workload == "vv32" else bench_batched(args)

@@ -28,8 +28,7 @@
  *    strings; as low as 1e-3 for superstrings). Crossings that do not exchange
  *    partners pass through each other.
  *
- * Readings where the paper is silent (the paper defers these details to other
- * papers; each is listed in the design doc):
+ * Readings where the paper is silent (it defers these details to other papers):
  *  - "element" k of band n: the world-sheet strip between points k and next[k] from
  *    slice n to n+1, as two triangles U = (X[n][k], X[n][j], X[n+1][k]) and
  *    D = (X[n+1][k], X[n][j], X[n+1][j]).
