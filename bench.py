@@ -414,6 +414,9 @@ def main():
         print(f"bench.py: the library runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
+    if not 0.0 < args.p <= 1.0:
+        print(f"bench.py: --p {args.p} is outside (0, 1]", file=sys.stderr)
+        sys.exit(2)
     res = bench_vv32(args) if args.workload == "vv32" else bench_batched(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "point-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
