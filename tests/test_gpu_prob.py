@@ -232,3 +232,18 @@ def test_full_size_network_in_bench_launch_configuration(S):
     assert int((o[1]["kind"] == 1).sum()) > 1000
     same_events(g[1], o[1])
     same_records(g[0], o[0])
+
+
+@pytest.mark.parametrize("seed", [2 ** 63 + 12345, 2 ** 64 - 1])
+def test_seed_uses_all_64_bits(S, seed):
+    """Seeds at and above 2^63 (the top bit set) reach the draw unchanged."""
+    say(f"case: VV 6^3 seed 1, matter, p 0.5, seed {seed}, 150 steps")
+    net = I.vv_network(m=6, seed=1)
+    g, o = run_both(S, net, [(150, np.inf, 0.5, seed, 0)], use_graph=True)
+    assert np.any(o[1]["kind"] == 1)
+    same_events(g[1], o[1])
+    same_records(g[0], o[0])
+    # a seed differing only in its top bit draws differently
+    g2, o2 = run_both(S, net, [(150, np.inf, 0.5, seed ^ (1 << 63), 0)], use_graph=True)
+    same_events(g2[1], o2[1])
+    assert g2[1].tobytes() != g[1].tobytes()
