@@ -464,7 +464,11 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
  *         scale) around its centre (origin + g/2 times the index summed along the
  *         generators' spatial parts) in 16^3 cells; the fraction of points in cells whose count, relative
  *         to the mean over all cells, has floor(log2) + 4 = b (clamped to 0..7)
- *   11 log1p(mean distance to the right neighbour / region size) */
+ *   11 log1p(mean distance to the right neighbour / region size)
+ * Surfaces all in device memory are read in place (only an id table for the right
+ * neighbours is built); otherwise the regions are loaded as one batch first. Both give
+ * the same features. Errors: SEMIPAR_E_ARG, SEMIPAR_E_SURFACE (a duplicate id),
+ * SEMIPAR_E_OOM, SEMIPAR_E_HIP; feat holds no valid features then. */
 int semipar_region_features(const semipar_tiling* t, float* feat);
 
 /* The cost model is a 12 -> 64 -> 64 -> 1 perceptron with ReLU, FP32. Parameters
