@@ -61,10 +61,13 @@ enum { SEMIPAR_SCREEN_F64 = 0, SEMIPAR_SCREEN_F32 = 1 };
  *   next_id  id of the right neighbour along the string, -1 when absent
  *   prev_id  id of the left neighbour, -1 when absent
  *   step     lattice slice index of x; x_prev is slice step-1
- *   flags    0 (reserved)
+ *   flags    SEMIPAR_FLAG_* bits below. Input records: 0. Output records: FROZEN (with
+ *            the exit face in bits 8..15), HAS_R, ACTIVE or REMOVED
  *   x        world-sheet vertex (x, y, z, t) of this point on slice `step`
  *   x_prev   the same point on slice step-1
- *   r, r_prev reserved (right neighbour's vertices for bounded regions), zero here
+ *   r, r_prev output records with HAS_R: the right neighbour's vertices on slices step
+ *            and step-1 (the other inputs of this point's next diamond); else zero.
+ *            Ignored on input
  * Positions are unwrapped along each point's own trajectory in the periodic box. */
 typedef struct semipar_point_rec {
   int64_t id, next_id, prev_id;

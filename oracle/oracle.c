@@ -595,8 +595,22 @@ static int search_brute(orc_region* r, pairvec* out) {
   return ORC_OK;
 }
 
+/* Bucket of cell (x, y, z) of the grid: a hash of the three coordinates, so that a
+ * fine grid over a large box needs only as many buckets as there are elements. */
+static uint64_t cell_bucket(int64_t x, int64_t y, int64_t z, uint64_t mask) {
+  uint64_t h = (uint64_t)x * 0x9E3779B97F4A7C15ull;
+  h ^= (uint64_t)y * 0xC2B2AE3D27D4EB4Full;
+  h ^= (uint64_t)z * 0x165667B19E3779F9ull;
+  h ^= h >> 29;
+  return h & mask;
+}
+
 /* The same set through a uniform periodic grid whose cell is at least the largest
- * element extent: overlapping boxes then sit in neighbouring cells. */
+ * element extent: overlapping boxes then sit in neighbouring cells. Cells are hashed
+ * into a power-of-two number of buckets (at least 2n); a bucket may hold elements of
+ * several cells, which only adds pairs that the exact box test then rejects. Each
+ * element visits the distinct buckets of its 27 neighbour cells once, and a pair is
+ * taken from its element of lower slot, so every pair is tested at most once. */
 static int search_grid(orc_region* r, pairvec* out) {
   int64_t n = r->n;
   double E = 0.0, maxabs = r->L;
@@ -609,19 +623,21 @@ static int search_grid(orc_region* r, pairvec* out) {
     }
   double hmin = E + maxabs * 0x1p-36;
   double ncd = floor(r->L / hmin);
-  double cap = floor(cbrt(16.0 * (double)n));
-  if (ncd > cap) ncd = cap;
   if (ncd > 1024) ncd = 1024;
   if (ncd < 3) return search_brute(r, out);
   int64_t nc = (int64_t)ncd;
   double h = r->L / (double)nc;
-  int64_t ncell = nc * nc * nc;
+  uint64_t nb = 1024;
+  while (nb < 2 * (uint64_t)n) nb <<= 1;
+  const uint64_t mask = nb - 1;
   int32_t(*cc)[3] = malloc(sizeof(int32_t[3]) * (n > 0 ? n : 1));
-  int64_t* start = (int64_t*)calloc((size_t)ncell + 1, sizeof(int64_t));
+  uint64_t* bk = (uint64_t*)malloc(sizeof(uint64_t) * (n > 0 ? n : 1));
+  int64_t* start = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
   int64_t* list = (int64_t*)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
-  int64_t* fill = (int64_t*)calloc((size_t)ncell, sizeof(int64_t));
-  if (!cc || !start || !list || !fill) {
+  int64_t* fill = (int64_t*)calloc((size_t)nb, sizeof(int64_t));
+  if (!cc || !bk || !start || !list || !fill) {
     free(cc);
+    free(bk);
     free(start);
     free(list);
     free(fill);
@@ -639,38 +655,45 @@ static int search_grid(orc_region* r, pairvec* out) {
       if (ci > nc - 1) ci = nc - 1;
       cc[k][c] = (int32_t)ci;
     }
-    start[(cc[k][0] * nc + cc[k][1]) * nc + cc[k][2] + 1]++;
+    bk[k] = cell_bucket(cc[k][0], cc[k][1], cc[k][2], mask);
+    start[bk[k] + 1]++;
   }
-  for (int64_t i = 0; i < ncell; ++i) start[i + 1] += start[i];
+  for (uint64_t i = 0; i < nb; ++i) start[i + 1] += start[i];
   for (int64_t k = 0; k < n; ++k) {
     if (cc[k][0] < 0) continue;
-    int64_t id = (cc[k][0] * nc + cc[k][1]) * nc + cc[k][2];
-    list[start[id] + fill[id]++] = k;
+    list[start[bk[k]] + fill[bk[k]]++] = k;
   }
   int rc = ORC_OK;
   double S[3];
   for (int64_t k = 0; k < n && rc == ORC_OK; ++k) {
     if (cc[k][0] < 0) continue;
+    uint64_t seen[27];
+    int nseen = 0;
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dz = -1; dz <= 1; ++dz) {
           int64_t x = (cc[k][0] + dx + nc) % nc, y = (cc[k][1] + dy + nc) % nc,
                   z = (cc[k][2] + dz + nc) % nc;
-          int64_t id = (x * nc + y) * nc + z;
-          for (int64_t q = start[id]; q < start[id + 1]; ++q) {
+          uint64_t b = cell_bucket(x, y, z, mask);
+          int dup = 0;
+          for (int i = 0; i < nseen; ++i) dup |= seen[i] == b;
+          if (dup) continue;
+          seen[nseen++] = b;
+          for (int64_t q = start[b]; q < start[b + 1]; ++q) {
             int64_t m = list[q];
             if (m <= k || is_adjacent(r, k, m)) continue;
-            int64_t a = k, b = m;
-            if (r->id[b] < r->id[a]) {
+            int64_t a = k, b2 = m;
+            if (r->id[b2] < r->id[a]) {
               a = m;
-              b = k;
+              b2 = k;
             }
-            if (pair_overlap(r, a, b, S))
+            if (pair_overlap(r, a, b2, S))
               if (pv_push(out, k, m)) rc = ORC_E_OOM;
           }
         }
   }
   free(cc);
+  free(bk);
   free(start);
   free(list);
   free(fill);

@@ -1915,20 +1915,28 @@ __device__ __forceinline__ int id_lookup(const int64_t* hkey, const int32_t* hva
   return -1;
 }
 
+// Links of every point. In a batch (rid set) a link whose target lies in another
+// sub-region is cut (-1), exactly as a separate run of the sub-region, which never sees
+// the other sub-region's points, leaves it dangling: links never leave a sub-region.
 __global__ __launch_bounds__(NT) void k_init_links(const semipar_point_rec* __restrict__ rec, int n,
                                                    const int64_t* __restrict__ hkey,
                                                    const int32_t* __restrict__ hval,
                                                    uint32_t hmask, Slices X, int32_t* nxt,
                                                    int32_t* prv, int64_t* id, int bounded,
                                                    int32_t* fstep, int32_t* face, int32_t* lev,
-                                                   Ctrl* ctrl) {
+                                                   const int32_t* __restrict__ rid, Ctrl* ctrl) {
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k >= n) return;
   const semipar_point_rec r = rec[k];
   const int s = r.step;
   if (s != rec[0].step || s < 1) atomicOr(&ctrl->err, 8);
-  const int a = id_lookup(hkey, hval, hmask, r.next_id);
-  const int b = id_lookup(hkey, hval, hmask, r.prev_id);
+  int a = id_lookup(hkey, hval, hmask, r.next_id);
+  int b = id_lookup(hkey, hval, hmask, r.prev_id);
+  if (rid) {
+    const int q = rid[k];
+    if (a >= 0 && rid[a] != q) a = -1;
+    if (b >= 0 && rid[b] != q) b = -1;
+  }
   fstep[k] = FS_ACTIVE;
   face[k] = -1;
   lev[k] = s - 1;  // no event yet: as if the last one were before the initial slice
@@ -2329,15 +2337,17 @@ __global__ __launch_bounds__(NT) void k_featsurf_points(
     q = region_of(off, nr, k);
     const semipar_point_rec& r = srf[q][k - off[q]];
     L = V4{r.x[0], r.x[1], r.x[2], r.x[3]};
+    // a neighbour in another region's surface is absent, as in that region alone
     const int j = id_lookup(hkey, hval, hmask, r.next_id);
-    if (j >= 0) {
-      const int qj = region_of(off, nr, j);
+    const int qj = j >= 0 ? region_of(off, nr, j) : -1;
+    if (qj == q) {
       const semipar_point_rec& rj = srf[qj][j - off[qj]];
       R = V4{rj.x[0], rj.x[1], rj.x[2], rj.x[3]};
       B = V4{rj.x_prev[0], rj.x_prev[1], rj.x_prev[2], rj.x_prev[3]};
       has_j = true;
     }
-    open_ = id_lookup(hkey, hval, hmask, r.prev_id) < 0;
+    const int pk = id_lookup(hkey, hval, hmask, r.prev_id);
+    open_ = pk < 0 || region_of(off, nr, pk) != q;
   }
   feat_accumulate(live, q, L, has_j, R, B, open_, geoms, P, acc, grid);
 }
@@ -3153,7 +3163,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
                                                      r->ctrl);
       k_init_links<<<blocks(n), NT, 0, r->stream>>>(drec, n, hkey, hval, (uint32_t)(hcap - 1), r->X,
                                                     r->nxt, r->prv, r->id, r->bounded ? 1 : 0,
-                                                    r->fstep, r->face, r->lev, r->ctrl);
+                                                    r->fstep, r->face, r->lev, r->rid, r->ctrl);
       k_init_check<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->nxt, r->prv, r->P, c0.step,
                                                     r->ctrl);
       if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;

@@ -628,9 +628,19 @@ def tiling_regions(net, M=4, layers=16, lead=1.75):
 
 
 def _gpu_in_use():
+    """True when this process may hold GPU runtime state that a forked child must not
+    inherit: torch has initialised its GPU context, or the HSA runtime is mapped at all
+    (libsemipar was loaded, or a profiler preloaded its library before the program
+    started)."""
     import sys
     torch = sys.modules.get("torch")
-    return bool(torch is not None and torch.cuda.is_initialized())
+    if torch is not None and torch.cuda.is_initialized():
+        return True
+    try:
+        with open("/proc/self/maps") as f:
+            return any("libhsa-runtime64" in line for line in f)
+    except OSError:
+        return True  # cannot tell: do not fork
 
 
 def _region_job(job):

@@ -173,3 +173,21 @@ def test_argument_errors_without_gpu():
     L.region_destroy(None)
     assert S.strerror(-2).startswith("inconsistent surface")
     assert "gfx950" in S.version()
+
+
+def test_fork_guard_sees_a_loaded_gpu_runtime():
+    """The input generators fork worker processes only while no GPU runtime is mapped
+    in this process: loading libsemipar (which maps the HSA runtime) or a profiler's
+    preload turns the guard on even when torch never touched the GPU."""
+    import subprocess
+    import sys
+    code = (
+        "import ctypes, sys\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "from paper_1011_4046_amd import inputs as I, build as B\n"
+        "before = I._gpu_in_use()\n"
+        "ctypes.CDLL(B.LIB)\n"
+        "print(before, I._gpu_in_use())\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         check=True).stdout.split()
+    assert out == ["False", "True"], out

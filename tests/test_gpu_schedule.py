@@ -400,3 +400,55 @@ def test_learned_cost_fit_and_predict(S):
         a = log["out"][log["out_off"][4 * r]:log["out_off"][4 * r + 4]]
         b = res["out"][res["out_off"][4 * r]:res["out_off"][4 * r + 4]]
         assert a.tobytes() == b.tobytes()
+
+
+def _cross_linked(parts):
+    """The same regions with surfaces that name points of other regions: every region's
+    first dangling right end is joined (both ways) to the next region's first dangling
+    left end. A region run alone never sees the other region's points, so these links
+    dangle there."""
+    parts = [(recs.copy(), geom) for recs, geom in parts]
+    live = [r for r in range(len(parts)) if len(parts[r][0])]
+    joined = 0
+    for a, b in zip(live, live[1:] + live[:1]):
+        ra, rb = parts[a][0], parts[b][0]
+        ia = np.nonzero(ra["next_id"] < 0)[0]
+        ib = np.nonzero(rb["prev_id"] < 0)[0]
+        if len(ia) == 0 or len(ib) == 0 or a == b:
+            continue
+        ra["next_id"][ia[0]] = rb["id"][ib[0]]
+        rb["prev_id"][ib[0]] = ra["id"][ia[0]]
+        joined += 1
+    return parts, joined
+
+
+def test_links_between_regions_of_a_batch_are_cut(S):
+    """Surfaces whose links name points of other regions: under every policy, and for
+    the features, each region behaves as when run alone (links never leave a region)."""
+    say("case: cross-region links, sizes[:8] seed 200, plain vs batched vs oracle")
+    parts, box = I.region_batch(SIZES[:8], seed=200)
+    orc = oracle_regions(parts, box, "sizes200")[:8]
+    xparts, joined = _cross_linked(parts)
+    assert joined >= 4
+    rs = S.RegionSet.from_parts(xparts, box, I.MATTER)
+    for policy in (S.SCHED_PLAIN, S.SCHED_BATCHED):
+        res = S.schedule_regions(rs, policy, batch_points=0, use_graph=True,
+                                 screen=S.SCREEN_F32)
+        if policy == S.SCHED_BATCHED:
+            assert res["stats"]["batches"] == 1
+        # the oracle ran the surfaces without the extra links: every field must agree
+        for r in range(len(parts)):
+            mine = res["out"][res["out_off"][4 * r]:res["out_off"][4 * r + 4]]
+            ev = res["events"][res["events_off"][r]:res["events_off"][r + 1]]
+            if orc[r] is None:
+                assert len(mine) == 0 and len(ev) == 0
+                continue
+            o, oe, _, _ = orc[r]
+            a, b = mine[np.argsort(mine["id"])], o[np.argsort(o["id"])]
+            assert a.tobytes() == b.tobytes(), (policy, r)
+            assert ev.tobytes() == oe.tobytes(), (policy, r)
+    for device in (False, True):
+        f = S.region_features(S.RegionSet.from_parts(xparts, box, I.MATTER, device=device))
+        for r, (recs, geom_r) in enumerate(parts):
+            want = C.features(recs, geom_r, box)
+            assert np.allclose(f[r], want, rtol=1e-5, atol=1e-6), (device, r, f[r], want)

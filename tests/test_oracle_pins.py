@@ -101,6 +101,28 @@ def test_grid_equals_brute_force_vv(seed):
     assert rg.read().tobytes() == rb.read().tobytes()
 
 
+def test_grid_equals_brute_force_bounded_region_in_large_box():
+    """A small bounded region in a 64-wide periodic box: the grid has about 10^9 cells,
+    hashed into a few thousand buckets, so buckets hold elements of many cells and the
+    27 neighbour cells of an element share buckets. The pairs found are still exactly
+    the brute-force set, step by step, and the run is the same."""
+    parts, box = I.region_batch([1500], seed=31)
+    recs, geom = parts[0]
+    assert box == 64.0
+    hc = I.HCOEF[I.MATTER]
+    rg = O.OracleRegion(recs, box, I.MATTER, hc, geom)
+    rb = O.OracleRegion(recs, box, I.MATTER, hc, geom)
+    # both searches apply the same exact box test, so the grid's pairs are a subset of
+    # brute force's; equal counts at every step make them the same set
+    for _ in range(40):
+        rg.evolve(1, search=O.GRID)
+        rb.evolve(1, search=O.BRUTE)
+        assert rg.stats()["candidates"] == rb.stats()["candidates"]
+    assert rg.stats()["candidates"] > 1000 and rg.stats()["accepted"] > 0
+    assert rg.events().tobytes() == rb.events().tobytes()
+    assert rg.read().tobytes() == rb.read().tobytes()
+
+
 def test_grid_equals_brute_force_flat_loops():
     net = I.kt_loops(n_loops=3, n_pts=48, seed=5)
     a = O.run(net, 300, search=O.GRID)
@@ -294,6 +316,53 @@ def test_matter_circular_loop_against_ode():
         errs.append(abs(R - _rk4_loop(1.0, 8.0, t, 2.0, nsteps=4000)))
     assert errs[0] < 1e-3
     assert 0.3 < errs[1] / errs[0] < 0.75 and 0.3 < errs[2] / errs[1] < 0.75, errs
+
+
+def _run_gamma_v(n_pts, eta_end, cosmology):
+    """gamma v of a straight string moving at 0.6 along y, evolved by the oracle through
+    the same entry the parity tests use (O.run picks H = hcoef / eta from the
+    cosmology), and the conformal time it refers to."""
+    chain, delta = I.straight_string(n_pts, 1.0, v=0.6, axis=0, vdir=1)
+    net = I.make_network([chain], 1.0, delta, 8.0, cosmology)
+    rec, _, _ = O.run(net, 100000, t_end=eta_end)
+    t1, t0 = rec["x"][0, 3], rec["x_prev"][0, 3]
+    assert np.all(rec["x"][:, 3] == t1)
+    v = (rec["x"][0, 1] - rec["x_prev"][0, 1]) / (t1 - t0)
+    g = 1.0 / (n_pts * delta)
+    v0 = np.sqrt(1 - g * g)
+    return v / np.sqrt(1 - v * v), v0 / np.sqrt(1 - v0 * v0), 0.5 * (t1 + t0)
+
+
+def test_radiation_moving_straight_string_momentum_redshift():
+    """Radiation era, a ∝ eta, H = 1/eta: d(gamma v)/d eta = -2 H gamma v gives
+    gamma v ∝ eta^-2 (the momentum redshifts as 1/a^2). The lattice converges to it at
+    first order in delta. A matter-era coefficient (H = 2/eta, eta^-4) misses by a
+    factor (8/12)^2 = 0.44 at eta = 12."""
+    errs = []
+    for n in (32, 64, 128):
+        gv, gv0, eta = _run_gamma_v(n, 12.0, I.RADIATION)
+        errs.append(abs(gv / (gv0 * (8.0 / eta) ** 2) - 1.0))
+    assert errs[0] < 0.05
+    assert 0.3 < errs[1] / errs[0] < 0.7 and 0.3 < errs[2] / errs[1] < 0.7, errs
+
+
+def test_radiation_circular_loop_against_ode():
+    """A circular loop released from rest in the radiation era (H = 1/eta), through the
+    parity tests' entry: its mean radius at eta = 8.8 follows the RK4 solution of
+    R'' = -2 H R'(1 - R'^2) - (1 - R'^2)/R within 1e-5 at every resolution. The
+    matter-era rate (H = 2/eta) or no expansion (H = 0) would put the ODE 1.3e-2 away.
+    With half the matter-era rate the first-order term no longer dominates the
+    polygon's O(delta^2) error here, so the order of convergence is shown by the moving
+    string above, not by this case."""
+    for n in (256, 512, 1024):
+        chain, delta = I.circular_loop(n, 1.0)
+        net = I.make_network([chain], 16.0, delta, 8.0, I.RADIATION)
+        rec, _, _ = O.run(net, 100000, t_end=8.8)
+        assert np.ptp(rec["x"][:, 3]) < 1e-12
+        t = rec["x"][0, 3]
+        R = np.linalg.norm(rec["x"][:, :2], axis=1).mean()
+        assert abs(R - _rk4_loop(1.0, 8.0, t, 1.0, nsteps=4000)) < 1e-5, n
+        assert abs(R - _rk4_loop(1.0, 8.0, t, 2.0, nsteps=4000)) > 1e-2, n
 
 
 # ----------------------------------------------------------------------------------
