@@ -313,6 +313,15 @@ int region_loops(const semipar_region* r, semipar_loop* buf, int64_t cap, int64_
  * most cap events are written and *n is the number written. */
 int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int64_t* n);
 
+/* Diagnostics of the screen (C ABI for tests): the pairs of elements that passed the
+ * bounding-box screen in the last step the region took, as (smaller id, larger id) of
+ * the two points whose elements they are, sorted, into ids[2 i], ids[2 i + 1]. Both
+ * screens report what they passed, so the FP32 screen's pairs of a step can be checked
+ * to contain the FP64 screen's. ids == NULL returns the count in *n; otherwise at most
+ * cap pairs are written and *n is the number written. A region that has taken no step
+ * with intercommutation reports 0. Errors: SEMIPAR_E_ARG, SEMIPAR_E_OOM, SEMIPAR_E_HIP. */
+int region_candidates(const semipar_region* r, int64_t* ids, int64_t cap, int64_t* n);
+
 /* Release all device and host memory of the region. NULL is accepted. */
 void region_destroy(semipar_region* r);
 

@@ -117,6 +117,7 @@ struct Ctrl {
   int64_t pass_total;  // crossings that passed through (probability p < 1)
   int64_t log_n;
   int64_t n_points;
+  int64_t last_cand;   // candidate appends of the last step taken (may exceed the buffer)
   int32_t err;
   int32_t pad;
   uint64_t ext_key;    // init: order key of an element-size estimate
@@ -1481,6 +1482,7 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     ctrl->pass_total += s_npass;
     ctrl->conf_total += ne;
     ctrl->cand_total += ncand;
+    ctrl->last_cand = ncand;
     ctrl->large_total += ctrl->n_large;
     ctrl->n_cand = 0;
     ctrl->n_evt = 0;
@@ -2391,6 +2393,17 @@ __global__ __launch_bounds__(256) void k_feat_final(const int32_t* __restrict__ 
 }
 
 // ---- event log of a batch: order (sub-region, step, t*, id_a, id_b) ---------------
+// Candidate slot pairs -> (smaller id, larger id).
+__global__ __launch_bounds__(NT) void k_cand_ids(const int2* __restrict__ cand, int64_t n,
+                                                 const int64_t* __restrict__ id,
+                                                 int64_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= n) return;
+  const int64_t a = id[cand[i].x], b = id[cand[i].y];
+  out[2 * i] = a < b ? a : b;
+  out[2 * i + 1] = a < b ? b : a;
+}
+
 __global__ __launch_bounds__(NT) void k_iota(int32_t* __restrict__ idx, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
   if (i < n) idx[i] = (int32_t)i;
@@ -3472,6 +3485,44 @@ int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int6
   });
   const int64_t m = std::min(total, cap);
   if (m > 0) memcpy(buf, all.data(), sizeof(semipar_event) * m);
+  *n = m;
+  return SEMIPAR_OK;
+}
+
+int region_candidates(const semipar_region* r, int64_t* ids, int64_t cap, int64_t* n) {
+  if (!r || !n || cap < 0) return SEMIPAR_E_ARG;
+  semipar_region* rr = const_cast<semipar_region*>(r);
+  if (r->n == 0 || !rr->cand) {
+    *n = 0;
+    return SEMIPAR_OK;
+  }
+  RCCHK(read_ctrl(rr));
+  const int64_t total = std::min<int64_t>(rr->ctrl_h->last_cand, rr->cap_cand);
+  if (!ids) {
+    *n = total;
+    return SEMIPAR_OK;
+  }
+  std::vector<int64_t> all(2 * (size_t)total);
+  if (total > 0) {
+    int64_t* d = nullptr;
+    HIPCHK(dalloc(&d, 2 * (size_t)total));
+    k_cand_ids<<<blocks(total), NT, 0, rr->stream>>>(rr->cand, total, rr->id, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(all.data(), d, sizeof(int64_t) * 2 * total, hipMemcpyDeviceToHost,
+                         rr->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(rr->stream);
+    dfree(d);
+    if (e != hipSuccess) return hip_fail(e, "candidate copy", __LINE__);
+  }
+  std::vector<std::pair<int64_t, int64_t>> pr((size_t)total);
+  for (int64_t i = 0; i < total; ++i) pr[i] = {all[2 * i], all[2 * i + 1]};
+  std::sort(pr.begin(), pr.end());
+  const int64_t m = std::min(total, cap);
+  for (int64_t i = 0; i < m; ++i) {
+    ids[2 * i] = pr[i].first;
+    ids[2 * i + 1] = pr[i].second;
+  }
   *n = m;
   return SEMIPAR_OK;
 }

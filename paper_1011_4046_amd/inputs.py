@@ -477,9 +477,9 @@ def region_batch(n_targets, size=4.0, seed=0, t_mid=8.0, slots=8, cosmology=MATT
     slot spacing >= 2 g + 1, so regions never overlap). Region r has point target
     n_targets[r], seed seed + r and pts_per_xi[r] points per correlation length
     (default 8); its ids are offset to be unique in the batch. workers > 1 generates
-    the regions in that many forked processes (same result; only while no GPU runtime
-    is loaded in this process); progress(i) is called after every region generated
-    serially.
+    the regions in that many worker processes (same result): forked while no GPU
+    runtime is mapped in this process, spawned otherwise; progress(i) is called after
+    every region generated serially.
     Returns (parts, box) with parts = [(recs, geom), ...]."""
     g = size / np.sqrt(2.0)
     nr = len(n_targets)
@@ -492,10 +492,12 @@ def region_batch(n_targets, size=4.0, seed=0, t_mid=8.0, slots=8, cosmology=MATT
         i, j, k = r // (slots * slots), (r // slots) % slots, r % slots
         centre = (spacing * (i + 0.5), spacing * (j + 0.5), spacing * (k + 0.5))
         jobs.append((int(nt), size, seed + r, t_mid, centre, ppx[r], cosmology, box))
-    if workers and workers > 1 and nr > 1 and not _gpu_in_use():
-        # forked copies of this process (no GPU state yet), pure NumPy work
+    if workers and workers > 1 and nr > 1:
+        # pure NumPy work in worker processes: forked copies of this process while it
+        # holds no GPU runtime state, freshly started interpreters otherwise
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers) as pool:
+        ctx = mp.get_context("spawn" if _gpu_in_use() else "fork")
+        with ctx.Pool(workers) as pool:
             nets = pool.map(_region_job, jobs, chunksize=1)
     else:
         nets = []

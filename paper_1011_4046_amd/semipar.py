@@ -124,7 +124,7 @@ MLP_IN, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
 
 # exported symbols declared in include/semipar.h
 SYMBOLS = ["region_init_from_surfaces", "region_evolve", "region_emit_final_surfaces",
-           "region_events", "region_loops", "region_destroy", "semipar_strerror", "semipar_version",
+           "region_events", "region_candidates", "region_loops", "region_destroy", "semipar_strerror", "semipar_version",
            "semipar_last_error", "schedule_regions", "semipar_region_features",
            "semipar_mlp_forward", "semipar_mlp_loss_grad", "semipar_mlp_adam_step",
            "semipar_mlp_train", "semipar_mlp_norm"]
@@ -150,6 +150,8 @@ def lib():
         L.region_emit_final_surfaces.restype = ctypes.c_int
         L.region_events.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.region_events.restype = ctypes.c_int
+        L.region_candidates.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        L.region_candidates.restype = ctypes.c_int
         L.region_loops.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.region_loops.restype = ctypes.c_int
         L.region_destroy.argtypes = [P]
@@ -179,6 +181,11 @@ def lib():
         L.semipar_mlp_norm.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def last_error():
+    """Text of the library's last recorded error on this thread ("" if none)."""
+    return lib().semipar_last_error().decode()
 
 
 def _check(rc, what):
@@ -304,6 +311,18 @@ class Region:
             _check(L.region_events(self.h, out.ctypes.data, n.value, ctypes.byref(n)),
                    "region_events")
         return out
+
+    def candidates(self):
+        """Pairs that passed the screen in the last step, (n, 2) int64 id pairs
+        (smaller id first), sorted."""
+        L = lib()
+        n = ctypes.c_int64()
+        _check(L.region_candidates(self.h, None, 0, ctypes.byref(n)), "region_candidates (count)")
+        out = np.zeros((n.value, 2), dtype=np.int64)
+        if n.value:
+            _check(L.region_candidates(self.h, out.ctypes.data, n.value, ctypes.byref(n)),
+                   "region_candidates")
+        return out[:n.value]
 
     def loops(self):
         """Loops recorded and removed since init, sorted by (step, rep_id)."""

@@ -407,3 +407,82 @@ def test_region_batch_equals_separate_regions(S, which, cell, screen):
     assert st["point_steps"] == psteps and st["steps"] == steps
     assert_same_events(ge, oe)
     assert_same_records(np.concatenate(faces), np.concatenate(recs))
+
+
+def _pair_keys(pairs, base):
+    return pairs[:, 0].astype(np.int64) * base + pairs[:, 1].astype(np.int64)
+
+
+def test_screen_candidates_per_step_nest(S):
+    """P6 per step, on a mid-size network (VV 16^3, about 3e4 points, 60 steps): the
+    oracle's exact 4-D box-overlap pairs of the band are among the FP64 screen's pairs,
+    which are among the FP32 screen's pairs (outward-rounded boxes with a margin only
+    add false positives). Events and positions stay identical."""
+    say("case: VV 16^3 seed 5, matter era, 60 single steps, oracle exact ⊆ f64 ⊆ f32")
+    net = I.vv_network(m=16, seed=5)
+    base = int(net["recs"]["id"].max()) + 1
+    a = S.Region(net["recs"], net["box"], net["cosmology"])
+    b = S.Region(net["recs"], net["box"], net["cosmology"])
+    o = O.OracleRegion(net["recs"], net["box"], I.MATTER, I.HCOEF[I.MATTER])
+    n64 = n32 = nex = 0
+    for step in range(60):
+        exact = o.band_candidates(O.GRID)
+        o.evolve(1)
+        a.evolve(1, screen=0)
+        b.evolve(1, screen=1)
+        c64, c32 = a.candidates(), b.candidates()
+        k_ex, k64, k32 = (_pair_keys(c, base) for c in (exact, c64, c32))
+        assert len(np.unique(k64)) == len(k64) and len(np.unique(k32)) == len(k32), step
+        assert np.isin(k_ex, k64).all(), f"step {step}: the FP64 screen missed an overlap"
+        assert np.isin(k64, k32).all(), f"step {step}: the FP32 screen missed an FP64 pair"
+        n64, n32, nex = n64 + len(k64), n32 + len(k32), nex + len(k_ex)
+    assert nex > 0
+    ge, be = a.events(), b.events()
+    assert_same_events(ge, o.events())
+    assert_same_events(be, ge)
+    ga, gb = a.emit(), b.emit()
+    assert_same_state(ga, o.read())
+    assert ga.tobytes() == gb.tobytes()
+    say(f"  pairs over 60 steps: exact {nex}, f64 screen {n64}, f32 screen {n32} "
+        f"(f32 false-positive rate over f64 {(n32 - n64) / max(n32, 1):.2e})")
+    for r in (a, b):
+        r.close()
+    o.close()
+
+
+@pytest.mark.parametrize("screen", [0, 1])
+def test_buffer_overflow_retakes_step_bounded_region(S, screen):
+    """A bounded region with candidate and event buffers far too small: overflowing
+    steps are retaken after the buffers grow, although the first attempt already wrote
+    stop steps, faces, stopped records and wave flags. Results equal the oracle's."""
+    say(f"case: bounded region ~3000 points seed 2, tiny buffers, screen {screen}")
+    net = I.region_network(3000, 4.0, seed=2)
+    faces, ge, st = run_gpu_region(S, net, screen=screen, cand_per_point=1e-5,
+                                   events_per_point=1e-5, use_graph=True, steps_per_sync=8)
+    o, oe, ost = run_oracle(net, 100000)
+    assert st["steps"] == ost["steps"] and st["point_steps"] == ost["point_steps"]
+    assert_same_events(ge, oe)
+    assert_same_records(np.concatenate(faces), o)
+    check_faces(faces)
+
+
+def test_buffer_overflow_retakes_step_batch(S):
+    """The same for a batch of regions through schedule_regions (one batch)."""
+    say("case: batch of 6 regions (seed 41), tiny buffers, one batch, f32 screen")
+    sizes = [900, 0, 2500, 300, 1600, 50]
+    parts, box = I.region_batch(sizes, seed=41)
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=0, use_graph=True,
+                             screen=S.SCREEN_F32, steps_per_sync=8, cand_per_point=1e-5,
+                             events_per_point=1e-5)
+    assert res["stats"]["batches"] == 1
+    for r, (recs, geom) in enumerate(parts):
+        mine = res["out"][res["out_off"][4 * r]:res["out_off"][4 * r + 4]]
+        ev = res["events"][res["events_off"][r]:res["events_off"][r + 1]]
+        if len(recs) == 0:
+            assert len(mine) == 0 and len(ev) == 0
+            continue
+        o, oe, ost = O.run(dict(recs=recs, box=box, cosmology=I.MATTER, geom=geom), 100000)
+        assert_same_events(ev, oe)
+        assert_same_records(mine, o)
+        assert res["region_point_steps"][r] == ost["point_steps"]
