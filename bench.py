@@ -230,39 +230,29 @@ def bench_batched(args):
         pv = rp["stats"]["point_steps"] / tp
         assert rp["stats"]["point_steps"] == st["point_steps"]
         extra["plain_per_region"] = {"point_steps_per_s": pv, "ms": tp * 1e3,
-                                     "speedup_batched_learned": value / pv}
+                                     "speedup_batched_learned": value / pv,
+                                     "steps_per_sync": 1}
         log(f"plain per-region: {tp * 1e3:.0f} ms, speed-up {value / pv:.2f}x")
         del rp
+        # the same plain path with a host check every 32 steps (still no graphs, FP64
+        # screen, one region at a time): what batching alone gains
+        t = time.perf_counter()
+        rp = S.schedule_regions(rs, S.SCHED_PLAIN, screen=S.SCREEN_F64, use_graph=False,
+                                steps_per_sync=32, out="device", events=True, **coin)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        pv = rp["stats"]["point_steps"] / tp
+        extra["plain_per_region_sync32"] = {"point_steps_per_s": pv, "ms": tp * 1e3,
+                                            "speedup_batched_learned": value / pv,
+                                            "steps_per_sync": 32}
+        log(f"plain per-region, 32 steps per host check: {tp * 1e3:.0f} ms, "
+            f"speed-up {value / pv:.2f}x")
+        del rp
 
-    # roofline: one eager schedule per timed kernel (events cannot be timed in graphs),
-    # one lane, so that no other batch's kernels run beside the timed ones
-    roofs = {}
-    for kname, kid in (("k_evolve", S.K_EVOLVE), ("k_screen", S.K_SCREEN)):
-        rr = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=pred, out=None,
-                                events=False, use_graph=False, screen=screen,
-                                screen_split=cfg["screen_split"],
-                                steps_per_sync=cfg["steps_per_sync"], timed_kernel=kid, **coin)
-        s2 = rr["stats"]
-        ms, nl = s2["timed_kernel_ms"], max(s2["timed_kernel_launches"], 1)
-        unit = (evolve_bytes_per_point(screen == S.SCREEN_F32, True) if kname == "k_evolve"
-                else screen_bytes_per_element(screen == S.SCREEN_F32))
-        # one element per point-step (the band piece to the right neighbour)
-        alg = unit * s2["point_steps"]
-        ach = alg / (ms / 1e3) / 1e9 if ms > 0 else 0.0
-        roofs[kname] = {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                        "traffic": None, "bytes_per_point_step": unit,
-                        "avg_launch_us": round(ms / nl * 1e3, 3), "launches": nl,
-                        "total_ms": round(ms, 2)}
-        log(f"{kname}: {nl} launches, {ms:.1f} ms, {ach:.0f} GB/s algorithmic")
-    launch_config = f"bp{bp}-split{cfg['screen_split']}-sync{cfg['steps_per_sync']}-{args.screen}"
-    for kname, rf in roofs.items():
-        rf["traffic"] = counted_traffic(kname, launch_config)
-        rf["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)"
-        rf["launch_config"] = launch_config
-    dom = max(roofs, key=lambda k: roofs[k]["total_ms"])
-    roof = roofs[dom]
-    other = {k: v for k, v in roofs.items() if k != dom}
+    roof, other = roofline_runs(S, rs, bp, cfg, screen, coin, args.screen)
+
+    if args.workload == "batched" and args.mixed:
+        extra["mixed_resolution"] = mixed_leg(S, SC, I, screen, coin, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -281,6 +271,96 @@ def bench_batched(args):
                            "inside the timed region)"},
         "roofline": roof, "roofline_other": other, "cpu_baseline": cpu, **extra,
     }
+
+
+def roofline_runs(S, rs, bp, cfg, screen, coin, screen_name):
+    """Roofline of the evolve and screen kernels: one eager schedule per timed kernel
+    (HIP events around every launch of it, on the batch's stream; events cannot be
+    recorded inside graphs), one lane so that no other batch's kernels run beside the
+    timed ones, batches of the timed configuration's size in point-count order.
+    `bench.py --roofline-only` runs exactly these schedules, for the profiler."""
+    roofs = {}
+    launch_config = (f"eager-1lane-bp{bp}-split{cfg['screen_split']}-sync{cfg['steps_per_sync']}"
+                     f"-{screen_name}")
+    for kname, kid in (("k_evolve", S.K_EVOLVE), ("k_screen", S.K_SCREEN)):
+        rr = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=None, out=None,
+                                events=False, use_graph=False, screen=screen,
+                                screen_split=cfg["screen_split"],
+                                steps_per_sync=cfg["steps_per_sync"], timed_kernel=kid, lanes=1,
+                                **coin)
+        s2 = rr["stats"]
+        ms, nl = s2["timed_kernel_ms"], max(s2["timed_kernel_launches"], 1)
+        if kname == "k_evolve":
+            unit = evolve_bytes_per_point(screen == S.SCREEN_F32, True)
+        else:
+            unit = screen_bytes_per_element(screen == S.SCREEN_F32)
+        # one element per point-step (the band piece to the right neighbour)
+        alg = unit * s2["point_steps"]
+        ach = alg / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        roofs[kname] = {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": counted_traffic(kname, launch_config),
+                        "bytes_per_point_step": unit,
+                        "avg_launch_us": round(ms / nl * 1e3, 3), "launches": nl,
+                        "total_ms": round(ms, 2),
+                        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
+                                        "copy-calibrated)",
+                        "launch_config": launch_config,
+                        "timing": "HIP events around every launch of this kernel in eager "
+                                  "one-lane schedules"}
+        log(f"{kname}: {nl} launches, {ms:.1f} ms, {ach:.0f} GB/s algorithmic")
+    dom = max(roofs, key=lambda k: roofs[k]["total_ms"])
+    return roofs[dom], {k: v for k, v in roofs.items() if k != dom}
+
+
+def mixed_leg(S, SC, I, screen, coin, args):
+    """Learned packing where it should pay: regions of random resolution (points per
+    correlation length from {4, 6, 8, 12, 16}), so that the point count says little about
+    the steps a region needs. The model trains on one such workload's logged steps
+    (seed 11) and packs another (seed 12) into batches of a sixth of the points, one
+    lane; makespans are the best of three runs of each order."""
+    import numpy as np
+    out = {}
+    work = {}
+    for seed in (11, 12):
+        n, ppx = I.mixed_regions(args.mixed_regions, median=args.mixed_median, sigma=1.0,
+                                 cap=50000, p_empty=0.1, seed=seed)
+        parts, box = I.region_batch(n, seed=1000 * seed, pts_per_xi=ppx, workers=args.workers)
+        work[seed] = S.RegionSet.from_parts(parts, box, I.MATTER, device=True)
+    rs_tr, rs = work[11], work[12]
+    logrun = S.schedule_regions(rs_tr, S.SCHED_BATCHED, use_graph=True, screen=screen, out=None,
+                                events=False, **coin)
+    cm = SC.LearnedCost(seed=0).fit(S.region_features(rs_tr), logrun["region_steps"], iters=2000,
+                                    lr=3e-3)
+    pred = cm.predict(S.region_features(rs))
+    bp = int(rs.counts.sum() // 6)
+    kw = dict(batch_points=bp, use_graph=True, screen=screen, out="device", events=True,
+              lanes=1, **coin)
+    for name, cost in (("heuristic", None), ("learned", pred)):
+        best = None
+        for _ in range(3):
+            r = S.schedule_regions(rs, S.SCHED_BATCHED, cost=cost, **kw)
+            if best is None or r["stats"]["makespan_ms"] < best["stats"]["makespan_ms"]:
+                best = r
+        st = best["stats"]
+        steps = best["region_steps"]
+        visited = 0
+        for b in np.unique(best["region_batch"][best["region_batch"] >= 0]):
+            sel = best["region_batch"] == b
+            visited += int(steps[sel].max()) * int(rs.counts[sel].sum())
+        out[name] = {"makespan_ms": round(st["makespan_ms"], 2),
+                     "point_steps_per_s": st["point_steps"] / (st["makespan_ms"] / 1e3),
+                     "batches": st["batches"], "visited_point_steps": visited}
+        log(f"mixed workload, {name}: {st['makespan_ms']:.1f} ms, {st['batches']} batches, "
+            f"visited point-steps {visited}")
+    live = rs.counts > 0
+    out["regions"] = rs.n_regions
+    out["points"] = int(rs.counts.sum())
+    out["point_steps"] = int(st["point_steps"])
+    out["corr_log_pred_log_steps"] = round(float(np.corrcoef(
+        np.log(pred[live]), np.log(np.maximum(steps[live], 1)))[0, 1]), 4)
+    out["learned_gain"] = round(out["heuristic"]["makespan_ms"] / out["learned"]["makespan_ms"], 4)
+    return out
 
 
 def cpu_baseline_regions(parts, box, every=50, budget_s=20.0, coin=None):
@@ -313,6 +393,26 @@ def cpu_baseline_regions(parts, box, every=50, budget_s=20.0, coin=None):
             "sample": f"{len(sample)} of the {len(live)} non-empty regions (every {every}th, "
                       f"{npts} points), each stepped for {share:.1f} s: {steps} lattice steps, "
                       f"{ps} point-steps in {tc:.1f} s"}
+
+
+def roofline_only(args):
+    """The roofline schedules of the batched workload alone (no training, no timed
+    schedules): what a profiler run of the kernels the roofline describes should see."""
+    from paper_1011_4046_amd import inputs as I
+    nt = I.lognormal_regions(args.regions, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2, seed=0)
+    parts, box = I.region_batch(nt, size=4.0, seed=0, slots=8, workers=args.workers)
+    import torch
+    from paper_1011_4046_amd import semipar as S
+    torch.cuda.set_device(0)
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER, device=True)
+    screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
+    cfg = {"batch_frac": args.batch_frac, "screen_split": args.split,
+           "steps_per_sync": args.sync_steps}
+    from paper_1011_4046_amd import scheduler as SC
+    bp = SC.batch_points_for(rs, cfg)
+    roof, other = roofline_runs(S, rs, bp, cfg, screen, dict(p=args.p, seed=args.seed),
+                                args.screen)
+    return {"mode": "roofline-only", "roofline": roof, "roofline_other": other}
 
 
 def bench_vv32(args):
@@ -409,6 +509,14 @@ def main():
     ap.add_argument("--p", type=float, default=1.0,
                     help="intercommutation probability in (0, 1] (1: every crossing exchanges)")
     ap.add_argument("--seed", type=int, default=0, help="key of the crossings' draws (p < 1)")
+    ap.add_argument("--mixed", type=int, default=1,
+                    help="also time learned against point-count packing on a workload of "
+                         "random resolution")
+    ap.add_argument("--mixed-regions", type=int, default=160)
+    ap.add_argument("--mixed-median", type=float, default=4000.0)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the eager one-lane roofline schedules of the batched workload "
+                         "(for a profiler); prints their roofline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only; --gpus {args.gpus} is not supported",
@@ -417,6 +525,9 @@ def main():
     if not 0.0 < args.p <= 1.0:
         print(f"bench.py: --p {args.p} is outside (0, 1]", file=sys.stderr)
         sys.exit(2)
+    if args.roofline_only:
+        print(json.dumps(roofline_only(args)), flush=True)
+        return
     res = bench_vv32(args) if args.workload == "vv32" else bench_batched(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "point-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),

@@ -198,11 +198,25 @@ typedef struct semipar_evolve_params {
                              around every launch of that kernel and the summed device
                              time is returned in the stats (measurement only; a timed
                              call issues its steps without graphs) */
-  int32_t screen_split;   /* threads sharing the 5 neighbour-pencil lookups of one
-                             element in the screen: 1 or 5 (any other value = 5).
+  int32_t screen_split;   /* screen variant: 1 or 5 threads share the 5 neighbour-
+                             pencil lookups of one element; 2: the bucket sort writes
+                             each element's 5 pencil ranges next to its sorted entry and
+                             the screen reads them (64 more bytes per element each way,
+                             two dependent loads fewer). Any other value = 5.
                              Performance only */
   int32_t loop_every;     /* loop record and removal period P in steps (0: off) */
-  int32_t reserved;       /* 0 */
+  int32_t persistent;     /* 1: a batch (n_sub > 0) whose sub-regions all hold at most
+                             SEMIPAR_PERSISTENT_MAX points, evolved to its regions' own
+                             stop (t_end = +inf, loop_every = 0, intercommute = 1, no
+                             timed kernel), runs in one launch of persistent workgroups:
+                             each takes the next sub-region from a device counter and
+                             evolves it through all its steps, testing every pair of its
+                             elements with the exact FP64 box test; results equal the
+                             step kernels'. Stats count those exact-box pairs as
+                             candidates. A step with more crossings than a workgroup
+                             holds gives SEMIPAR_E_OVERFLOW (the region is then unusable:
+                             run it again from its surfaces with persistent = 0).
+                             0 or another batch: the step kernels */
   double p;               /* intercommutation probability in (0, 1]; 0 means 1 (Section
                              "Semi-parallel cosmic string simulation": crossing strings
                              exchange partners with probability p, 1 for field-theory
@@ -216,6 +230,11 @@ typedef struct semipar_evolve_params {
                              order. Outside [0, 1] or NaN: SEMIPAR_E_ARG */
   uint64_t seed;          /* key of the crossings' draws (used when p < 1) */
 } semipar_evolve_params;
+
+/* most points of a sub-region evolved by persistent workgroups, and most crossings of
+ * one of its steps that a workgroup holds */
+#define SEMIPAR_PERSISTENT_MAX 512
+#define SEMIPAR_PERSISTENT_EVENTS 160
 
 /* kernels that can be timed through semipar_evolve_params.timed_kernel */
 enum {
@@ -349,8 +368,12 @@ const char* semipar_version(void);
  *   n_pred     NULL: the regions are independent. Else, per region, the number of
  *              predecessors that must finish before it may start; succ_off (n_regions
  *              + 1 offsets) and succ list each region's successors. A region becomes
- *              ready when its count reaches zero. This orders the work only: a
- *              successor's input is its own surface, not its predecessors' output.
+ *              ready when its count reaches zero. BATCHED keeps these counts, the
+ *              successor lists and the ring of ready regions on the device; a finished
+ *              batch releases its regions' successors at once (a region with no string
+ *              is done as soon as it is ready), and ready regions are packed into the
+ *              next batches. This orders the work only: a successor's input is its own
+ *              surface, not its predecessors' output.
  *   stream     hipStream_t for all work (NULL: each region creates its own stream). */
 typedef struct semipar_tiling {
   int32_t n_regions;
@@ -419,8 +442,8 @@ typedef struct semipar_sched_params {
   int32_t* region_batch;
   double* region_ms;
   int32_t lanes;     /* BATCHED: batches evolved concurrently, each lane a host thread
-                        with a stream of its own (0 or 1: one after another on the
-                        tiling's stream). Batches go to lanes longest predicted first. */
+                        with a stream of its own (0 or 1: one lane). Waiting batches go
+                        to idle lanes longest predicted first. */
   int32_t pack;      /* BATCHED: SEMIPAR_PACK_POINTS, or SEMIPAR_PACK_WORK: with a cost
                         vector, the ready regions (in decreasing cost order) are cut into
                         B = max(lanes, ceil(points / batch_points)) batches holding about

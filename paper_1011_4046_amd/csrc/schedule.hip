@@ -6,18 +6,24 @@
 // time is set by the most difficult regions, which is why uneven regions are packed
 // by predicted cost here.
 //
-// On one GPU the "workers" are launch batches: every ready region of a wave goes into
-// a batch region (one set of kernels over the points of all its sub-regions), and a
-// batch runs until all its sub-regions have stopped. Regions are ordered by predicted
-// lattice steps (cost model) or, without a prediction, by point count, and cut into
-// batches of at most batch_points points, so that regions finishing after similar
-// numbers of steps share a launch.
+// On one GPU the "workers" are launch batches: ready regions go into a batch region
+// (one set of kernels over the points of all its sub-regions), and a batch runs until
+// all its sub-regions have stopped. Regions are ordered by predicted lattice steps (cost
+// model) or, without a prediction, by point count, and cut into batches of at most
+// batch_points points, so that regions finishing after similar numbers of steps share a
+// launch. The manager's bookkeeping -- predecessor counts, successor lists, the ring of
+// ready regions and the empty-region fast path -- is on the device (k_dag_release); a
+// finished batch releases its regions' successors at once, so a region starts as soon
+// as its own predecessors are done.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstdint>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -72,6 +78,64 @@ semipar_region_desc batch_desc(const semipar_tiling* t, const std::vector<int32_
   d.sub = g.data();
   return d;
 }
+
+// ---------------------------------------------------------------------------------
+// the ready queue on the device
+// ---------------------------------------------------------------------------------
+// Per region: predecessors still running (pending), successors (CSR), and whether its
+// initial surface holds no string. A region enters the ready ring exactly once, when
+// its count reaches zero; a ready region without string completes at once (the paper's
+// empty regions are only noted) and so releases its own successors in the same kernel.
+constexpr int DAG_NT = 1024;
+
+// Release the successors of the `nfin` regions in fin (seed = 1: instead, make every
+// region with no pending predecessor ready). Regions that become ready are appended to
+// ring (tail at ctr[0]); ready regions without string are followed through at once,
+// breadth first, on the worklist `work` (nr entries). One workgroup.
+__global__ __launch_bounds__(DAG_NT) void k_dag_release(
+    const int32_t* __restrict__ fin, int nfin, int seed, int nr, int32_t* __restrict__ pending,
+    const int32_t* __restrict__ succ_off, const int32_t* __restrict__ succ,
+    const uint8_t* __restrict__ empty, int32_t* __restrict__ ring, int32_t* __restrict__ ctr,
+    int32_t* __restrict__ work) {
+  __shared__ int s_n;
+  const int t = threadIdx.x;
+  if (t == 0) s_n = 0;
+  __syncthreads();
+  auto ready = [&](int32_t r) {
+    ring[atomicAdd(&ctr[0], 1)] = r;
+    if (empty[r]) work[atomicAdd(&s_n, 1)] = r;
+  };
+  auto release = [&](int32_t r) {
+    for (int32_t e = succ_off[r]; e < succ_off[r + 1]; ++e)
+      if (atomicSub(&pending[succ[e]], 1) == 1) ready(succ[e]);
+  };
+  if (seed) {
+    for (int r = t; r < nr; r += DAG_NT)
+      if (pending[r] == 0) ready(r);
+  } else {
+    for (int i = t; i < nfin; i += DAG_NT) release(fin[i]);
+  }
+  int head = 0;
+  for (;;) {
+    __syncthreads();
+    const int end = s_n;
+    __syncthreads();  // every thread has read the end before new regions are appended
+    if (head >= end) break;
+    for (int i = head + t; i < end; i += DAG_NT) release(work[i]);
+    head = end;
+  }
+}
+
+struct DagDev {
+  int32_t *pending = nullptr, *succ_off = nullptr, *succ = nullptr, *ring = nullptr;
+  int32_t *ctr = nullptr, *work = nullptr, *fin = nullptr;
+  uint8_t* empty = nullptr;
+  ~DagDev() {
+    for (void* q : {(void*)pending, (void*)succ_off, (void*)succ, (void*)ring, (void*)ctr,
+                    (void*)work, (void*)fin, (void*)empty})
+      if (q) (void)hipFree(q);
+  }
+};
 
 struct Runner {
   const semipar_tiling* t;
@@ -257,102 +321,58 @@ struct Runner {
     return SEMIPAR_OK;
   }
 
-  // Run the batches of one wave: with one lane, one after another on the tiling's
-  // stream; with L lanes, all batches are built first (nothing is freed while kernels
-  // run, since hipFree waits for the whole device), then L host threads each evolve
-  // their batches on a stream of their own, longest predicted batch first onto the
-  // least loaded lane, and the results are collected afterwards.
-  int run_batches(std::vector<Batch>& bs) {
-    const int lanes = std::max(1, std::min<int>(p->lanes, (int)bs.size()));
-    if (lanes == 1) {
-      for (Batch& b : bs) {
-        int rc = build_batch(b, t->stream);
-        if (rc == SEMIPAR_OK) rc = region_evolve(b.reg, &p->evolve, &b.es);
-        b.rc = rc;
-        RCCHK_R(finish_batch(b));
+  // Per-region event and loop lists into the caller's buffers, and the stats.
+  int collect(const semipar_tiling* tt, const semipar_sched_params* pp, semipar_sched_stats* st,
+              std::chrono::steady_clock::time_point t0) {
+    const int nr = tt->n_regions;
+    int64_t ne = 0;
+    for (int r = 0; r < nr; ++r) {
+      const int64_t m = (int64_t)ev[r].size();
+      if (pp->events) {
+        pp->events_off[r] = ne;
+        const int64_t fit = std::max<int64_t>(0, std::min(m, pp->events_cap - ne));
+        if (fit > 0) memcpy(pp->events + ne, ev[r].data(), sizeof(semipar_event) * fit);
       }
-      return SEMIPAR_OK;
+      ne += m;
     }
-    std::vector<hipStream_t> ls(lanes, nullptr);
-    hipEvent_t ready = nullptr;
-    int rc = SEMIPAR_OK;
-    for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
-      if (hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking) != hipSuccess) rc = SEMIPAR_E_HIP;
-    if (rc == SEMIPAR_OK && t->stream) {
-      // device-resident surfaces may still be in flight on the caller's stream
-      if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
-          hipEventRecord(ready, (hipStream_t)t->stream) != hipSuccess)
-        rc = SEMIPAR_E_HIP;
-      for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
-        if (hipStreamWaitEvent(ls[l], ready, 0) != hipSuccess) rc = SEMIPAR_E_HIP;
-    }
-    // longest processing time first onto the least loaded lane
-    std::vector<int> order(bs.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return bs[a].cost > bs[b].cost; });
-    std::vector<std::vector<int>> work(lanes);
-    std::vector<double> load(lanes, 0.0);
-    for (int i : order) {
-      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      work[l].push_back(i);
-      load[l] += bs[i].cost;
-    }
-    for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
-      for (int i : work[l]) {
-        rc = build_batch(bs[i], ls[l]);
-        if (rc != SEMIPAR_OK) break;
+    if (pp->events) pp->events_off[nr] = ne;
+    acc.events = ne;
+    int64_t nl = 0;
+    for (int r = 0; r < nr; ++r) {
+      const int64_t m = (int64_t)lp[r].size();
+      if (pp->loops) {
+        pp->loops_off[r] = nl;
+        const int64_t fit = std::max<int64_t>(0, std::min(m, pp->loops_cap - nl));
+        if (fit > 0) memcpy(pp->loops + nl, lp[r].data(), sizeof(semipar_loop) * fit);
       }
-    if (rc == SEMIPAR_OK) {
-      std::vector<std::thread> th;
-      for (int l = 0; l < lanes; ++l)
-        th.emplace_back([&, l]() {
-          for (int i : work[l]) {
-            bs[i].rc = region_evolve(bs[i].reg, &p->evolve, &bs[i].es);
-            if (bs[i].rc != SEMIPAR_OK) break;
-          }
-        });
-      for (auto& x : th) x.join();
-      for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
-        for (int i : work[l])
-          if (bs[i].rc != SEMIPAR_OK) rc = bs[i].rc;
+      nl += m;
     }
-    for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
-      for (int i : work[l]) {
-        rc = finish_batch(bs[i]);
-        if (rc != SEMIPAR_OK) break;
-      }
-    for (Batch& b : bs)
-      if (b.reg) {
-        region_destroy(b.reg);
-        b.reg = nullptr;
-      }
-    for (hipStream_t x : ls)
-      if (x) (void)hipStreamDestroy(x);
-    if (ready) (void)hipEventDestroy(ready);
-    return rc;
+    if (pp->loops) pp->loops_off[nr] = nl;
+    acc.makespan_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = acc;
+    return SEMIPAR_OK;
   }
 
-  // one wave of ready regions
-  int run_wave(std::vector<int32_t> ready) {
-    std::vector<int32_t> live;
-    for (int32_t r : ready) {
-      if (t->surfaces[r].n == 0) {
-        // empty fast path: nothing to simulate, nothing to emit
-        acc.empty_regions += 1;
-        if (p->out_off)
-          for (int f = 0; f < 4; ++f) p->out_off[4 * r + f] = slab[r].base;
-        log_region(r, 0, 0, -1, 0.0);
-      } else {
-        live.push_back(r);
+  // Ready regions into batches: longest predicted first (steps from the cost model, else
+  // points), cut into batches of at most batch_points points, or into equal shares of
+  // the predicted point-steps (PACK_WORK); each batch carries its predicted device time.
+  std::vector<Batch> cut(std::vector<int32_t> live) {
+    if (p->evolve.persistent) {
+      // small regions go to batches of their own, which persistent workgroups evolve
+      std::vector<int32_t> small, large;
+      for (int32_t r : live)
+        (t->surfaces[r].n <= SEMIPAR_PERSISTENT_MAX ? small : large).push_back(r);
+      if (!small.empty() && !large.empty()) {
+        std::vector<Batch> a = cut_some(large), b = cut_some(small);
+        for (Batch& x : b) a.push_back(std::move(x));
+        return a;
       }
-      acc.regions += 1;
     }
-    if (p->policy == SEMIPAR_SCHED_PLAIN) {
-      for (int32_t r : live) RCCHK_R(run_plain(r));
-      return SEMIPAR_OK;
-    }
-    // batched: longest predicted first (steps from the cost model, else points)
+    return cut_some(live);
+  }
+
+  std::vector<Batch> cut_some(std::vector<int32_t> live) {
     std::stable_sort(live.begin(), live.end(), [&](int32_t a, int32_t b) {
       if (p->cost) return p->cost[a] > p->cost[b];
       return t->surfaces[a].n > t->surfaces[b].n;
@@ -399,7 +419,233 @@ struct Runner {
       }
       b.cost = np * mx;
     }
-    return run_batches(bs);
+    return bs;
+  }
+
+
+  // Batched policy, dependency driven. The ready queue lives on the device
+  // (k_dag_release); the host takes the regions that have become ready, packs them into
+  // batches and hands those to idle lanes, longest predicted first. A region's
+  // successors are released when its own batch has finished, not when a whole wave
+  // has. Results are collected after the last batch (in the order the batches were
+  // formed, which numbers them), since releasing device memory waits for the device.
+  int run_dynamic() {
+    const int nr = t->n_regions;
+    const int lanes = std::max(1, p->lanes);
+    std::vector<int32_t> hp((size_t)nr, 0), hoff((size_t)nr + 1, 0), hs;
+    std::vector<uint8_t> he((size_t)nr, 0);
+    for (int r = 0; r < nr; ++r) {
+      hp[r] = t->n_pred ? t->n_pred[r] : 0;
+      he[r] = t->surfaces[r].n == 0 ? 1 : 0;
+    }
+    if (t->n_pred) {
+      for (int r = 0; r <= nr; ++r) hoff[r] = t->succ_off[r] - t->succ_off[0];
+      hs.assign(t->succ + t->succ_off[0], t->succ + t->succ_off[nr]);
+    }
+    DagDev D;
+    const size_t m = std::max<size_t>(hs.size(), 1);
+    if (hipMalloc(&D.pending, sizeof(int32_t) * std::max(nr, 1)) != hipSuccess ||
+        hipMalloc(&D.succ_off, sizeof(int32_t) * (nr + 1)) != hipSuccess ||
+        hipMalloc(&D.succ, sizeof(int32_t) * m) != hipSuccess ||
+        hipMalloc(&D.ring, sizeof(int32_t) * std::max(nr, 1)) != hipSuccess ||
+        hipMalloc(&D.ctr, sizeof(int32_t) * 2) != hipSuccess ||
+        hipMalloc(&D.work, sizeof(int32_t) * std::max(nr, 1)) != hipSuccess ||
+        hipMalloc(&D.fin, sizeof(int32_t) * std::max(nr, 1)) != hipSuccess ||
+        hipMalloc(&D.empty, std::max(nr, 1)) != hipSuccess)
+      return SEMIPAR_E_OOM;
+    std::vector<hipStream_t> ls((size_t)lanes, nullptr);
+    hipStream_t ms = nullptr;  // the queue's kernels and reads, in order
+    hipEvent_t ready_ev = nullptr;
+    std::deque<Batch> bs;
+    auto cleanup = [&]() {
+      for (Batch& b : bs)
+        if (b.reg) {
+          region_destroy(b.reg);
+          b.reg = nullptr;
+        }
+      for (hipStream_t x : ls)
+        if (x) (void)hipStreamDestroy(x);
+      if (ms) (void)hipStreamDestroy(ms);
+      if (ready_ev) (void)hipEventDestroy(ready_ev);
+    };
+    int rc = SEMIPAR_OK;
+    if (hipStreamCreateWithFlags(&ms, hipStreamNonBlocking) != hipSuccess) rc = SEMIPAR_E_HIP;
+    for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
+      if (hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking) != hipSuccess) rc = SEMIPAR_E_HIP;
+    if (rc == SEMIPAR_OK && t->stream) {
+      // device-resident surfaces may still be in flight on the caller's stream
+      if (hipEventCreateWithFlags(&ready_ev, hipEventDisableTiming) != hipSuccess ||
+          hipEventRecord(ready_ev, (hipStream_t)t->stream) != hipSuccess)
+        rc = SEMIPAR_E_HIP;
+      for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
+        if (hipStreamWaitEvent(ls[l], ready_ev, 0) != hipSuccess) rc = SEMIPAR_E_HIP;
+    }
+    const int32_t zero2[2] = {0, 0};
+    if (rc == SEMIPAR_OK &&
+        (hipMemcpyAsync(D.pending, hp.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ms) !=
+             hipSuccess ||
+         hipMemcpyAsync(D.succ_off, hoff.data(), sizeof(int32_t) * (nr + 1),
+                        hipMemcpyHostToDevice, ms) != hipSuccess ||
+         (!hs.empty() && hipMemcpyAsync(D.succ, hs.data(), sizeof(int32_t) * hs.size(),
+                                        hipMemcpyHostToDevice, ms) != hipSuccess) ||
+         hipMemcpyAsync(D.empty, he.data(), (size_t)nr, hipMemcpyHostToDevice, ms) != hipSuccess ||
+         hipMemcpyAsync(D.ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice, ms) != hipSuccess))
+      rc = SEMIPAR_E_HIP;
+    if (rc == SEMIPAR_OK) {
+      k_dag_release<<<1, DAG_NT, 0, ms>>>(nullptr, 0, 1, nr, D.pending, D.succ_off, D.succ,
+                                          D.empty, D.ring, D.ctr, D.work);
+      if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
+    }
+    // regions that have entered the ring since the last read: empty ones are only
+    // noted, the others wait for a batch
+    std::vector<int32_t> host_ring((size_t)std::max(nr, 1));
+    int32_t consumed = 0;
+    auto drain = [&](std::vector<int32_t>& live) -> int {
+      int32_t tail = 0;
+      if (hipMemcpyAsync(&tail, D.ctr, sizeof(int32_t), hipMemcpyDeviceToHost, ms) != hipSuccess ||
+          hipStreamSynchronize(ms) != hipSuccess)
+        return SEMIPAR_E_HIP;
+      if (tail < consumed || tail > nr) return SEMIPAR_E_HIP;
+      if (tail > consumed &&
+          (hipMemcpyAsync(host_ring.data() + consumed, D.ring + consumed,
+                          sizeof(int32_t) * (tail - consumed), hipMemcpyDeviceToHost,
+                          ms) != hipSuccess ||
+           hipStreamSynchronize(ms) != hipSuccess))
+        return SEMIPAR_E_HIP;
+      for (int32_t i = consumed; i < tail; ++i) {
+        const int32_t r = host_ring[i];
+        acc.regions += 1;
+        if (he[r]) {
+          acc.empty_regions += 1;
+          if (p->out_off)
+            for (int f = 0; f < 4; ++f) p->out_off[4 * r + f] = slab[r].base;
+          log_region(r, 0, 0, -1, 0.0);
+        } else {
+          live.push_back(r);
+        }
+      }
+      consumed = tail;
+      return SEMIPAR_OK;
+    };
+    std::mutex mu;
+    std::condition_variable cv_lane, cv_mgr;
+    std::vector<size_t> jobq;  // batches waiting for a lane, longest predicted last
+    std::vector<size_t> done;  // batches finished since the manager last looked
+    int running = 0;
+    bool stop = false;
+    auto dispatch = [&](std::vector<int32_t>& live) {
+      if (live.empty()) return;
+      std::vector<Batch> nb = cut(live);
+      live.clear();
+      std::lock_guard<std::mutex> lk(mu);
+      for (Batch& b : nb) {
+        bs.push_back(std::move(b));
+        jobq.push_back(bs.size() - 1);
+      }
+      std::stable_sort(jobq.begin(), jobq.end(),
+                       [&](size_t a, size_t b) { return bs[a].cost < bs[b].cost; });
+    };
+    std::vector<int32_t> live;
+    if (rc == SEMIPAR_OK) rc = drain(live);
+    if (rc == SEMIPAR_OK) dispatch(live);
+    std::vector<std::thread> th;
+    if (rc == SEMIPAR_OK)
+      for (int l = 0; l < lanes; ++l)
+        th.emplace_back([&, l]() {
+          for (;;) {
+            size_t i;
+            {
+              std::unique_lock<std::mutex> lk(mu);
+              cv_lane.wait(lk, [&] { return stop || !jobq.empty(); });
+              if (jobq.empty()) return;
+              i = jobq.back();
+              jobq.pop_back();
+              ++running;
+            }
+            Batch& b = bs[i];
+            int brc = build_batch(b, ls[l]);
+            if (brc == SEMIPAR_OK) brc = region_evolve(b.reg, &p->evolve, &b.es);
+            if (brc == SEMIPAR_E_OVERFLOW && p->evolve.persistent) {
+              // a step held more crossings than a persistent workgroup keeps: the
+              // batch runs again from its surfaces on the step kernels
+              region_destroy(b.reg);
+              b.reg = nullptr;
+              semipar_evolve_params e2 = p->evolve;
+              e2.persistent = 0;
+              brc = build_batch(b, ls[l]);
+              if (brc == SEMIPAR_OK) brc = region_evolve(b.reg, &e2, &b.es);
+            }
+            {
+              std::lock_guard<std::mutex> lk(mu);
+              b.rc = brc;
+              done.push_back(i);
+              --running;
+            }
+            cv_mgr.notify_one();
+          }
+        });
+    cv_lane.notify_all();
+    std::vector<int32_t> fin;
+    while (rc == SEMIPAR_OK) {
+      std::vector<size_t> got;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_mgr.wait(lk, [&] { return !done.empty() || (running == 0 && jobq.empty()); });
+        got.swap(done);
+      }
+      if (got.empty()) break;  // nothing running, nothing waiting: every ready region ran
+      fin.clear();
+      for (size_t i : got) {
+        if (bs[i].rc != SEMIPAR_OK && rc == SEMIPAR_OK) rc = bs[i].rc;
+        fin.insert(fin.end(), bs[i].regs.begin(), bs[i].regs.end());
+      }
+      if (rc != SEMIPAR_OK) break;
+      if (hipMemcpyAsync(D.fin, fin.data(), sizeof(int32_t) * fin.size(), hipMemcpyHostToDevice,
+                         ms) != hipSuccess) {
+        rc = SEMIPAR_E_HIP;
+        break;
+      }
+      k_dag_release<<<1, DAG_NT, 0, ms>>>(D.fin, (int)fin.size(), 0, nr, D.pending, D.succ_off,
+                                          D.succ, D.empty, D.ring, D.ctr, D.work);
+      if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
+      if (rc == SEMIPAR_OK) rc = drain(live);
+      if (rc == SEMIPAR_OK) dispatch(live);
+      cv_lane.notify_all();
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (rc != SEMIPAR_OK) jobq.clear();
+      stop = true;
+    }
+    cv_lane.notify_all();
+    for (auto& x : th) x.join();
+    if (rc == SEMIPAR_OK && consumed != nr) {
+      spi::set_error("schedule_regions: the predecessor counts leave regions that never become ready");
+      rc = SEMIPAR_E_ARG;
+    }
+    // results, batch by batch in the order they were formed
+    for (size_t i = 0; i < bs.size() && rc == SEMIPAR_OK; ++i) rc = finish_batch(bs[i]);
+    cleanup();
+    return rc;
+  }
+
+  // plain policy: one wave of ready regions, one region at a time
+  int run_wave(std::vector<int32_t> ready) {
+    std::vector<int32_t> live;
+    for (int32_t r : ready) {
+      if (t->surfaces[r].n == 0) {
+        // empty fast path: nothing to simulate, nothing to emit
+        acc.empty_regions += 1;
+        if (p->out_off)
+          for (int f = 0; f < 4; ++f) p->out_off[4 * r + f] = slab[r].base;
+        log_region(r, 0, 0, -1, 0.0);
+      } else {
+        live.push_back(r);
+      }
+      acc.regions += 1;
+    }
+    for (int32_t r : live) RCCHK_R(run_plain(r));
+    return SEMIPAR_OK;
   }
 };
 
@@ -435,7 +681,15 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
     base += t->surfaces[r].n;
   }
   if (p->out_off) p->out_off[4 * (int64_t)nr] = base;
-  // ready queue: regions whose predecessors have all finished, wave by wave
+  bool any_points = false;
+  for (int r = 0; r < nr; ++r) any_points = any_points || t->surfaces[r].n > 0;
+  if (p->policy == SEMIPAR_SCHED_BATCHED && any_points) {
+    rc = R.run_dynamic();
+    if (rc != SEMIPAR_OK) return rc;
+    return R.collect(t, p, st, t0);
+  }
+  // plain policy (one region at a time), or nothing to simulate: wave by wave of ready
+  // regions, counted on the host
   std::vector<int32_t> pending(nr, 0);
   std::vector<int32_t> ready;
   for (int r = 0; r < nr; ++r) {
@@ -459,34 +713,7 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
     spi::set_error("schedule_regions: the predecessor counts leave regions that never become ready");
     return SEMIPAR_E_ARG;
   }
-  // event lists, region by region
-  int64_t ne = 0;
-  for (int r = 0; r < nr; ++r) {
-    const int64_t m = (int64_t)R.ev[r].size();
-    if (p->events) {
-      p->events_off[r] = ne;
-      const int64_t fit = std::max<int64_t>(0, std::min(m, p->events_cap - ne));
-      if (fit > 0) memcpy(p->events + ne, R.ev[r].data(), sizeof(semipar_event) * fit);
-    }
-    ne += m;
-  }
-  if (p->events) p->events_off[nr] = ne;
-  R.acc.events = ne;
-  int64_t nl = 0;
-  for (int r = 0; r < nr; ++r) {
-    const int64_t m = (int64_t)R.lp[r].size();
-    if (p->loops) {
-      p->loops_off[r] = nl;
-      const int64_t fit = std::max<int64_t>(0, std::min(m, p->loops_cap - nl));
-      if (fit > 0) memcpy(p->loops + nl, R.lp[r].data(), sizeof(semipar_loop) * fit);
-    }
-    nl += m;
-  }
-  if (p->loops) p->loops_off[nr] = nl;
-  R.acc.makespan_ms =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  if (st) *st = R.acc;
-  return SEMIPAR_OK;
+  return R.collect(t, p, st, t0);
 }
 
 int semipar_region_features(const semipar_tiling* t, float* feat) {

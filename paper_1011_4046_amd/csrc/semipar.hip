@@ -18,7 +18,6 @@
 // A device control block carries the step index, the stop rule and the counters,
 // so a block of steps can be issued (or graph-replayed) without host round trips.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <climits>
@@ -130,6 +129,11 @@ struct Ctrl {
   alignas(128) int32_t n_cand;  // candidate appends this step (may exceed the buffer)
   int32_t n_evt;                // confirmed crossings this step (may exceed the buffer)
   int32_t n_large;              // elements of this step outside the hash
+  // the event matching's workgroups: log places taken, exchanges, pass-throughs, most
+  // rounds of a group, and workgroups finished (all zero between steps)
+  int32_t res_nlog, res_nacc, res_npass, res_iter, res_done;
+  int32_t scan_done;  // workgroups of the bucket scan finished (zero between steps)
+  int32_t pb_step;    // persistent launch: the furthest slice any of its regions reached
 };
 
 struct Slices {
@@ -340,7 +344,7 @@ __device__ __forceinline__ void write_frozen(semipar_point_rec* __restrict__ frz
 // inputs. All decisions read the state before the step (a stop written in this step
 // never satisfies "stopped before this step").
 template <bool FRW, int SCR, bool BND>
-__global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restrict__ nxt,
+__global__ __launch_bounds__(NT, 4) void k_evolve(Slices X, const int32_t* __restrict__ nxt,
                                                const int32_t* __restrict__ prv,
                                                const int64_t* __restrict__ id, int n,
                                                sp::Period P, double hcoef, Ctrl* ctrl, HashCfg hc,
@@ -388,140 +392,182 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   bool live_pt = k < n;
   if constexpr (BND) live_pt = live_pt && fstep[k] == FS_ACTIVE;
   else live_pt = live_pt && (!fstep || fstep[k] == FS_ACTIVE);
+  // Level 1: k's link and vertex. Lane 63 also reads next[k+1]: when next[k] = k+1 its
+  // element needs the top of a point that the next wave computes, so it prefetches that
+  // point's inputs alongside its own.
+  const int lane = (int)(threadIdx.x & 63);
+  int j = -1, jn = -1;
+  V4 L{};
   if (live_pt) {
-    bool adv = true;
-    int j = nxt[k];
-    // geometry of k's region (links never leave a region, so also next[k]'s)
-    RegionGeom G;
-    if constexpr (BND) G = rid ? geoms[rid[k]] : G0;
+    j = nxt[k];
+    L = ld(X, ic, k);
+    if (lane == 63 && k + 1 < n) jn = nxt[k + 1];
+  }
+  // geometry of k's region (links never leave a region, so also next[k]'s)
+  RegionGeom G;
+  if constexpr (BND) G = live_pt && rid ? geoms[rid[k]] : G0;
+  // Level 2: the diamond's other inputs; lane 63's speculative inputs of k+1's top
+  bool adv = false;
+  V4 R{}, B{}, T{};
+  const bool spec = SCR != 0 && live_pt && lane == 63 && j == k + 1 && jn >= 0;
+  V4 Rs{}, Bs{};
+  int32_t fs_jn = FS_ACTIVE;
+  if (spec) {
+    Rs = ld(X, ic, jn);
+    Bs = ld(X, ip, jn);
+    if constexpr (BND) fs_jn = fstep[jn];
+  }
+  if (live_pt) {
+    adv = true;
+    // the neighbour's vertices are read together with its stop state (not after it)
+    int32_t fj = FS_ACTIVE;
+    if (j >= 0) {
+      B = ld(X, ip, j);
+      R = ld(X, ic, j);
+      if constexpr (BND) fj = fstep[j];
+    }
     if constexpr (BND) {
       adv = false;
-      {
-        int f = -1;
-        bool with_r = false;
-        if (j < 0) {
-          f = -1;
-        } else if (fstep[j] < s) {
-          f = face[j];
-        } else {
-          f = exit_face(G, ld(X, ip, j));
-          if (f < 0) adv = true;
-          with_r = true;
-        }
-        if (!adv) {
-          write_frozen(frz, X, ic, ip, k, j, with_r, f, s, prv, id);
-          face[k] = f;
-          fstep[k] = s;
-        }
+      int f = -1;
+      bool with_r = false;
+      if (j < 0) {
+        f = -1;
+      } else if (fj < s) {
+        f = face[j];
+      } else {
+        f = exit_face(G, B);
+        if (f < 0) adv = true;
+        with_r = true;
+      }
+      if (!adv) {
+        write_frozen(frz, X, ic, ip, k, j, with_r, f, s, prv, id);
+        face[k] = f;
+        fstep[k] = s;
       }
     }
     if (adv) {
       nadv += 1;
       still = true;
-      const V4 L = ld(X, ic, k);
-      const V4 R = ld(X, ic, j);
-      const V4 B = ld(X, ip, j);
-      const V4 T = sp::top<FRW>(L, R, B, P, hcoef);
+      T = sp::top<FRW>(L, R, B, P, hcoef);
       st(X, in, k, T);
       const uint64_t tk = order_key(T.t);
       tkey = tk < tkey ? tk : tkey;
-      if constexpr (SCR != 0) {
-        const int jj = nxt[j];
-        bool jadv = true;
+    }
+  }
+  if constexpr (SCR != 0) {
+    // the element of band n to the right neighbour j needs j's new top: lanes 0..62 take
+    // it (and j's advance decision) from the next lane when j = k+1, computed there from
+    // the same inputs by the same code; lane 63 computes it from its prefetched inputs;
+    // other links read j's inputs now
+    const bool adv_n = __shfl_down(adv ? 1 : 0, 1, 64) != 0;
+    V4 Tn;
+    Tn.x = __shfl_down(T.x, 1, 64);
+    Tn.y = __shfl_down(T.y, 1, 64);
+    Tn.z = __shfl_down(T.z, 1, 64);
+    Tn.t = __shfl_down(T.t, 1, 64);
+    if (adv) {
+      bool jadv = true;
+      V4 Tj;
+      if (lane < 63 && j == k + 1) {
+        jadv = adv_n;
+        Tj = Tn;
+      } else {
+        const int jj = spec ? jn : nxt[j];
         V4 Rj, Bj;
         if constexpr (BND) {
-          jadv = fstep[j] == FS_ACTIVE && jj >= 0 && fstep[jj] >= s;
+          const int32_t fjj = spec ? fs_jn : (jj >= 0 ? fstep[jj] : 0);
+          jadv = fstep[j] == FS_ACTIVE && jj >= 0 && fjj >= s;
           if (jadv) {
-            Bj = ld(X, ip, jj);
+            Bj = spec ? Bs : ld(X, ip, jj);
             jadv = exit_face(G, Bj) < 0;
           }
-          if (jadv) Rj = ld(X, ic, jj);
+          if (jadv) Rj = spec ? Rs : ld(X, ic, jj);
         } else {
-          Rj = ld(X, ic, jj);
-          Bj = ld(X, ip, jj);
+          Rj = spec ? Rs : ld(X, ic, jj);
+          Bj = spec ? Bs : ld(X, ip, jj);
         }
-        if (!jadv) {
-          ecell[k] = NO_ELEM;
-        } else {
-          const V4 Tj = sp::top<FRW>(R, Rj, Bj, P, hcoef);
-          const Elem e = sp::make_elem(L, R, T, Tj, P);
-          const Box4 b = sp::elem_box(e);
-          double ext = b.hi[0] - b.lo[0];
-          ext = fmax(ext, b.hi[1] - b.lo[1]);
-          ext = fmax(ext, b.hi[2] - b.lo[2]);
-          xk = order_key(ext);
-          double W[3], w[3];
-          for (int c = 0; c < 3; ++c) {
-            W[c] = P.box * floor(b.lo[c] * P.inv);
-            w[c] = b.lo[c] - W[c];
-          }
-          const bool local = BND && rcell != nullptr;
-          RCell C{};
-          if (local) C = rcell[rid[k]];
-          if (local ? !(ext <= C.hlim) : (cs.nc == 0 || !(ext <= cs.hlim))) {
-            const int li = atomicAdd(&ctrl->n_large, 1);
-            LargeBox lb;
-            for (int c = 0; c < 3; ++c) {
-              lb.wl[c] = w[c];
-              lb.ext[c] = b.hi[c] - b.lo[c];
-            }
-            lb.tlo = b.lo[3];
-            lb.thi = b.hi[3];
-            lb.slot = k;
-            lb.pad = 0;
-            large[li] = lb;
-            ecell[k] = -1 - li;
-          } else {
-            int ci[3];
-            double lor[3], hir[3];
-            if (local) {
-              // coordinates relative to the region's grid origin (minimum image)
-              const double o[3] = {C.ox, C.oy, C.oz};
-              for (int c = 0; c < 3; ++c) {
-                const double d = b.lo[c] - o[c];
-                const double sh = P.box * P.nearest(d);
-                const double dl = d - sh;
-                int q = (int)floor(dl * C.inv_h);
-                q = q < 0 ? 0 : (q > C.nc - 1 ? C.nc - 1 : q);
-                ci[c] = q;
-                lor[c] = dl - (double)q * C.h;
-                hir[c] = ((b.hi[c] - o[c]) - sh) - (double)q * C.h;
-              }
-            } else {
-              for (int c = 0; c < 3; ++c) {
-                int q = (int)floor(w[c] * cs.inv_h);
-                q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
-                ci[c] = q;
-                lor[c] = w[c] - (double)q * cs.h;
-                hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
-              }
-            }
-            if constexpr (SCR == 1) {
-              double4* o = (double4*)ebox + (size_t)k * 2;
-              o[0] = make_double4(lor[0], lor[1], lor[2], b.lo[3]);
-              o[1] = make_double4(hir[0], hir[1], hir[2], b.hi[3]);
-            } else {
-              float4* o = (float4*)ebox + (size_t)k * 2;
-              o[0] = make_float4(__double2float_rd(lor[0] - hc.tol),
-                                 __double2float_rd(lor[1] - hc.tol),
-                                 __double2float_rd(lor[2] - hc.tol),
-                                 __double2float_rd((b.lo[3] - hc.tref) - hc.tol_t));
-              o[1] = make_float4(__double2float_ru(hir[0] + hc.tol),
-                                 __double2float_ru(hir[1] + hc.tol),
-                                 __double2float_ru(hir[2] + hc.tol),
-                                 __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
-            }
-            const uint32_t bk =
-                local ? (C.base + cell_index(C.nc, ci[0], ci[1], ci[2])) & hc.bmask
-                      : bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
-            hashed = true;
-            hbk = bk;
-            ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
-          }
-        }
+        if (jadv) Tj = sp::top<FRW>(R, Rj, Bj, P, hcoef);
       }
-    } else if constexpr (SCR != 0) {
-      ecell[k] = NO_ELEM;
+      if (!jadv) {
+        ecell[k] = NO_ELEM;
+      } else {
+      const Elem e = sp::make_elem(L, R, T, Tj, P);
+      const Box4 b = sp::elem_box(e);
+      double ext = b.hi[0] - b.lo[0];
+      ext = fmax(ext, b.hi[1] - b.lo[1]);
+      ext = fmax(ext, b.hi[2] - b.lo[2]);
+      xk = order_key(ext);
+      double W[3], w[3];
+      for (int c = 0; c < 3; ++c) {
+        W[c] = P.box * floor(b.lo[c] * P.inv);
+        w[c] = b.lo[c] - W[c];
+      }
+      const bool local = BND && rcell != nullptr;
+      RCell C{};
+      if (local) C = rcell[rid[k]];
+      if (local ? !(ext <= C.hlim) : (cs.nc == 0 || !(ext <= cs.hlim))) {
+        const int li = atomicAdd(&ctrl->n_large, 1);
+        LargeBox lb;
+        for (int c = 0; c < 3; ++c) {
+          lb.wl[c] = w[c];
+          lb.ext[c] = b.hi[c] - b.lo[c];
+        }
+        lb.tlo = b.lo[3];
+        lb.thi = b.hi[3];
+        lb.slot = k;
+        lb.pad = 0;
+        large[li] = lb;
+        ecell[k] = -1 - li;
+      } else {
+        int ci[3];
+        double lor[3], hir[3];
+        if (local) {
+          // coordinates relative to the region's grid origin (minimum image)
+          const double o[3] = {C.ox, C.oy, C.oz};
+          for (int c = 0; c < 3; ++c) {
+            const double d = b.lo[c] - o[c];
+            const double sh = P.box * P.nearest(d);
+            const double dl = d - sh;
+            int q = (int)floor(dl * C.inv_h);
+            q = q < 0 ? 0 : (q > C.nc - 1 ? C.nc - 1 : q);
+            ci[c] = q;
+            lor[c] = dl - (double)q * C.h;
+            hir[c] = ((b.hi[c] - o[c]) - sh) - (double)q * C.h;
+          }
+        } else {
+          for (int c = 0; c < 3; ++c) {
+            int q = (int)floor(w[c] * cs.inv_h);
+            q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
+            ci[c] = q;
+            lor[c] = w[c] - (double)q * cs.h;
+            hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
+          }
+        }
+        if constexpr (SCR == 1) {
+          double4* o = (double4*)ebox + (size_t)k * 2;
+          o[0] = make_double4(lor[0], lor[1], lor[2], b.lo[3]);
+          o[1] = make_double4(hir[0], hir[1], hir[2], b.hi[3]);
+        } else {
+          float4* o = (float4*)ebox + (size_t)k * 2;
+          o[0] = make_float4(__double2float_rd(lor[0] - hc.tol),
+                             __double2float_rd(lor[1] - hc.tol),
+                             __double2float_rd(lor[2] - hc.tol),
+                             __double2float_rd((b.lo[3] - hc.tref) - hc.tol_t));
+          o[1] = make_float4(__double2float_ru(hir[0] + hc.tol),
+                             __double2float_ru(hir[1] + hc.tol),
+                             __double2float_ru(hir[2] + hc.tol),
+                             __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
+        }
+        const uint32_t bk =
+            local ? (C.base + cell_index(C.nc, ci[0], ci[1], ci[2])) & hc.bmask
+                  : bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
+        hashed = true;
+        hbk = bk;
+        ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
+      }
+      }
+    } else if (live_pt) {
+      ecell[k] = NO_ELEM;  // stopped in this step (points stopped before already read so)
     }
   }
   // slots in bucket order: neighbouring lanes are neighbouring points of a string and
@@ -596,12 +642,18 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   }
 }
 
+constexpr int MAX_TILES = 2048;  // buckets <= 2^23
+
 // Per-tile exclusive scan of the bucket counts (counts are reset for the next step);
-// tile totals go to tile_tot. Consumers scan the tile totals themselves, in LDS.
+// tile totals go to tile_tot. The last workgroup to finish scans the tile totals into
+// toff: toff[t] = first sorted position of tile t, toff[ntiles] = hashed elements.
 __global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t* __restrict__ loc,
-                                              int32_t* __restrict__ tile_tot, const Ctrl* ctrl) {
+                                              int32_t* __restrict__ tile_tot, int ntiles,
+                                              int32_t* __restrict__ toff, Ctrl* ctrl) {
   if (ctrl->done) return;
   __shared__ int32_t sh[256];
+  __shared__ int32_t s_toff[MAX_TILES + 1];
+  __shared__ int s_last;
   const int t = threadIdx.x;
   const size_t base = (size_t)blockIdx.x * TS + (size_t)t * 16;
   int4* c4 = (int4*)(cnt + base);
@@ -639,9 +691,17 @@ __global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t
     c4[i] = make_int4(0, 0, 0, 0);
   }
   if (t == 255) tile_tot[blockIdx.x] = sh[255];
+  __threadfence();  // the tile total is visible to the workgroup that counts last
+  __syncthreads();
+  if (t == 0) s_last = atomicAdd(&ctrl->scan_done, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  block_tile_offsets(tile_tot, ntiles, s_toff, sh);
+  for (int i = t; i <= ntiles; i += 256) toff[i] = s_toff[i];
+  if (t == 0) ctrl->scan_done = 0;
 }
 
-constexpr int MAX_TILES = 2048;  // buckets <= 2^23
 constexpr int POINT_GRID = 2048;  // most workgroups of the grid-stride per-point kernels
 constexpr int SCREEN_GRID = 2560;  // most workgroups of the screen (a multiple of 8)
 
@@ -649,15 +709,29 @@ __device__ __forceinline__ int bucket_start(const int32_t* loc, const int32_t* s
   return loc[b] + s_toff[b >> TS_LOG];
 }
 
-// Exclusive scan of the tile totals (one workgroup): toff[t] = first sorted position of
-// tile t, toff[ntiles] = number of hashed elements.
-__global__ __launch_bounds__(1024) void k_toff(const int32_t* __restrict__ tile_tot, int ntiles,
-                                               int32_t* __restrict__ toff, const Ctrl* ctrl) {
-  if (ctrl->done) return;
-  __shared__ int32_t s_toff[MAX_TILES + 1];
-  __shared__ int32_t s_tmp[1024];
-  block_tile_offsets(tile_tot, ntiles, s_toff, s_tmp);
-  for (int i = threadIdx.x; i <= ntiles; i += 1024) toff[i] = s_toff[i];
+// Neighbour pencils of a sorted element (64 bytes), written by k_scatter for the screen
+// variant that reads them instead of looking them up (k_screen_pre). Pencil 0 is the
+// element's own z-row from its own cell: [pos + 1, re0). Pencils 1..4 are the rows
+// (x, y+1), (x+1, y-1), (x+1, y), (x+1, y+1), cells z-1 .. z+1: [rb, re). msk bits
+// 3p .. 3p+2 say which of the cells z-1, z, z+1 of pencil p exist; bit 15 + p says that
+// pencil p's cells are not consecutive buckets (the screen then looks them up one by
+// one). nk, pk are the slots of the element's point's neighbours, salt the key salt and
+// h32, marg32 the cell edge and FP32 slack of its grid.
+constexpr int N_PENCIL = 5;  // forward half shell of a cell: 5 z-pencils of 3 cells
+struct PencilAux {
+  int32_t re0;
+  int32_t rb[4], re[4];
+  uint32_t msk;
+  int32_t nk, pk;
+  uint32_t salt;
+  float h32, marg32;
+  int32_t pad;
+};
+static_assert(sizeof(PencilAux) == 64, "four 16-byte loads");
+
+__device__ __forceinline__ void pencil_offsets(int p, int& dx, int& dy) {
+  dx = p == 0 ? 0 : (p == 1 ? 0 : 1);
+  dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
 }
 
 // Cell-sorted copies of each hashed element: cell key, slot and screen box. In a batch
@@ -673,9 +747,13 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
                                                 const int32_t* __restrict__ rid,
                                                 const RCell* __restrict__ rcell,
                                                 const uint8_t* __restrict__ wlive,
-                                                const Ctrl* ctrl) {
+                                                const Ctrl* ctrl,
+                                                PencilAux* __restrict__ saux,
+                                                const int32_t* __restrict__ nxt,
+                                                const int32_t* __restrict__ prv) {
   if (ctrl->done) return;
   const int nc = ctrl->cells.nc;
+  const Cells cs = ctrl->cells;
   for (int k = blockIdx.x * NT + threadIdx.x; k < n; k += gridDim.x * NT) {
   // no point of a cleared wave advanced this step, so none has an element
   if (!wlive[__builtin_amdgcn_readfirstlane(k >> 6)]) continue;
@@ -684,14 +762,76 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
   const int x = c & 1023, y = (c >> 10) & 1023, z = (c >> 20) & 1023;
   uint32_t b;
   int32_t key = c;
+  RCell C{};
   if (rcell) {
-    const RCell C = rcell[rid[k]];
+    C = rcell[rid[k]];
     b = (C.base + cell_index(C.nc, x, y, z)) & hc.bmask;
     key = (int32_t)((uint32_t)c ^ C.salt);
   } else {
     b = bucket_of(nc, hc.bmask, x, y, z);
   }
   const int pos = bucket_start(loc, toff, b) + epos[k];
+  if (saux) {
+    // the five neighbour pencils' ranges of sorted entries (the screen's lookups, done
+    // here where the element's grid and bucket offsets are already at hand)
+    const bool local = rcell != nullptr;
+    const int gnc = local ? C.nc : nc;
+    auto bucket = [&](int xx, int yy, int zz) -> uint32_t {
+      return local ? (C.base + cell_index(gnc, xx, yy, zz)) & hc.bmask
+                   : bucket_of(gnc, hc.bmask, xx, yy, zz);
+    };
+    auto wrapc = [&](int v) { return v < 0 ? v + gnc : (v >= gnc ? v - gnc : v); };
+    PencilAux A{};
+    A.nk = nxt[k];
+    A.pk = prv[k];
+    A.salt = local ? C.salt : 0u;
+    A.h32 = local ? C.h32 : cs.h32;
+    A.marg32 = local ? C.marg32 : cs.marg32;
+    uint32_t msk = 0;
+#pragma unroll
+    for (int p = 0; p < N_PENCIL; ++p) {
+      int dx, dy;
+      pencil_offsets(p, dx, dy);
+      int xx = x + dx, yy = y + dy;
+      if (local) {
+        if (xx >= gnc || yy < 0 || yy >= gnc) continue;  // no such row: no cells
+      } else {
+        xx = wrapc(xx);
+        yy = wrapc(yy);
+      }
+      bool kv[3];
+      uint32_t bk[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int dz = u - 1;
+        int zz = z + dz;
+        bool v = !(p == 0 && dz < 0);
+        if (local) v = v && zz >= 0 && zz < gnc;
+        else zz = wrapc(zz);
+        kv[u] = v;
+        bk[u] = bucket(xx, yy, zz);
+      }
+      const int first = kv[0] ? 0 : 1;
+      const int last = kv[2] ? 2 : 1;
+      bool consec = true;
+      if (first == 0) consec = consec && bk[1] == bk[0] + 1;
+      if (last == 2) consec = consec && bk[2] == bk[1] + 1;
+      msk |= (uint32_t)((kv[0] ? 1 : 0) | 2 | (kv[2] ? 4 : 0)) << (3 * p);
+      if (!consec) {
+        msk |= 1u << (15 + p);
+        continue;
+      }
+      const int end = bucket_start(loc, toff, (last == 2 ? bk[2] : bk[1]) + 1);
+      if (p == 0) {
+        A.re0 = end;
+      } else {
+        A.rb[p - 1] = bucket_start(loc, toff, first == 0 ? bk[0] : bk[1]);
+        A.re[p - 1] = end;
+      }
+    }
+    A.msk = msk;
+    saux[pos] = A;
+  }
   if constexpr (SCR == 1) {
     sent[pos] = make_int2(key, k);
     const double4* src = (const double4*)ebox + (size_t)k * 2;
@@ -799,8 +939,8 @@ inline int xcd_grid(int total) { return (total + N_XCD - 1) / N_XCD * N_XCD; }
 // one of smaller slot). Threads past the hashed elements take one large element each.
 // Each unordered pair is tested exactly once. Logical block = (element block, g),
 // renumbered per XCD (xcd_block).
-constexpr int N_PENCIL = 5;
-constexpr int SCREEN_EPW = 12;  // elements per wave when five lanes share an element
+constexpr int SCREEN_EPW = 12;
+constexpr int SPLIT_PRE = 2;  // screen variant: pencils precomputed by k_scatter  // elements per wave when five lanes share an element
 
 template <int SCR, int G>
 __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int n, const int2* __restrict__ sent,
@@ -1089,6 +1229,210 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
   }  // chunks
 }
 
+// The same half-shell screen, one thread per element, with the five pencil ranges read
+// from the element's PencilAux (written by k_scatter) instead of being looked up here:
+// a thread loads its entry and its 64-byte record, then scans its pencils. Pencils whose
+// cells are not consecutive buckets, and the tests against large elements, read the
+// element's grid and look their cells up as k_screen does.
+template <int SCR>
+__global__ __launch_bounds__(NT, 5) void k_screen_pre(int n, const int2* __restrict__ sent,
+                                                   const void* __restrict__ sbox,
+                                                   const void* __restrict__ ebox_slot,
+                                                   const PencilAux* __restrict__ saux,
+                                                   const int32_t* __restrict__ loc,
+                                                   const int32_t* __restrict__ toff, int ntiles,
+                                                   const LargeBox* __restrict__ large, HashCfg hc,
+                                                   sp::Period P, int2* __restrict__ cand, int cap,
+                                                   Ctrl* ctrl, const int32_t* __restrict__ rid,
+                                                   const RCell* __restrict__ rcell,
+                                                   const int32_t* __restrict__ nxt,
+                                                   const int32_t* __restrict__ prv) {
+  if (ctrl->done) return;
+  using T = typename std::conditional<SCR == 1, double, float>::type;
+  __shared__ int2 sbuf[SBUF];
+  __shared__ int s_cnt, s_base;
+  const Cells cs = ctrl->cells;
+  const int nl = ctrl->n_large;
+  const int n_norm = toff[ntiles];
+  const int nchunk = (n_norm + nl + NT - 1) / NT;
+  const int cper = (nchunk + N_XCD - 1) / N_XCD;
+  const int xcd = (int)blockIdx.x % N_XCD;
+  const int bper = (int)gridDim.x / N_XCD;
+  const bool local = rcell != nullptr;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  for (int c = (int)blockIdx.x / N_XCD; c < cper; c += bper) {
+  const int lid = xcd * cper + c;
+  if (lid >= nchunk) break;
+  const bool last = c + bper >= cper || lid + bper >= nchunk;
+  const int q = lid * NT + (int)threadIdx.x;
+  auto push = [&](int a, int b) {
+    const int i = atomicAdd(&s_cnt, 1);
+    if (i < SBUF)
+      sbuf[i] = make_int2(a, b);
+    else
+      push_cand(ctrl, cand, cap, a, b);
+  };
+  if (q < n_norm + nl) {
+    int k, nk, pk;
+    bool own_large;
+    double wl[3], ex[3], tlo, thi;  // wrapped box of the element (for large partners)
+    if (q < n_norm) {
+      own_large = false;
+      const SBox<T> me = load_sbox<T>(sbox, q);
+      const int2 ent = entry_key_slot<SCR>(sent, me, q);
+      const PencilAux A = saux[q];
+      k = ent.y;
+      nk = A.nk;
+      pk = A.pk;
+      const uint32_t salt = A.salt;
+      const int32_t cc = (int32_t)((uint32_t)ent.x ^ salt);
+      const int cx = cc & 1023, cy = (cc >> 10) & 1023, cz = (cc >> 20) & 1023;
+      const T tl = SCR == 1 ? (T)hc.tol : (T)A.marg32;
+      // FP64 boxes are relative to a cell edge of FP64 precision (the grid's own h)
+      T hh;
+      if constexpr (SCR == 1) hh = (T)(local ? rcell[rid[k]].h : cs.h);
+      else hh = (T)A.h32;
+      const int gnc = cs.nc;  // the periodic grid's size (a batch's grids do not wrap)
+      auto wrapc = [&](int v) { return v < 0 ? v + gnc : (v >= gnc ? v - gnc : v); };
+      auto test_range = [&](int beg, int end, uint32_t c0, int mk, int dx, int dy) {
+        const T sx = (T)dx * hh, sy = (T)dy * hh;
+        auto test2 = [&](const int2 e, const SBox<T>& b) {
+          const uint32_t d = ((uint32_t)e.x ^ salt) - c0;
+          int dz = 2;
+          if (d == 0u) dz = 0;
+          else if (d == (1u << 20)) dz = (mk & 4) ? 1 : 2;
+          else if (d == (uint32_t)(-(1 << 20))) dz = (mk & 1) ? -1 : 2;
+          const int m = e.y;
+          if (dz != 2 && m != nk && m != pk && box_overlap(me, b, sx, sy, (T)dz * hh, tl))
+            push(k, m);
+        };
+        int q2 = beg;
+        for (; q2 + 4 <= end; q2 += 4) {
+          int2 e4[4];
+          SBox<T> b4[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            b4[v] = load_sbox<T>(sbox, q2 + v);
+            e4[v] = entry_key_slot<SCR>(sent, b4[v], q2 + v);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) test2(e4[v], b4[v]);
+        }
+        for (; q2 < end; ++q2) {
+          const SBox<T> b1 = load_sbox<T>(sbox, q2);
+          test2(entry_key_slot<SCR>(sent, b1, q2), b1);
+        }
+      };
+      const uint32_t msk = A.msk;
+#pragma unroll
+      for (int p = 0; p < N_PENCIL; ++p) {
+        const int mk = (int)((msk >> (3 * p)) & 7u);
+        if (!mk) continue;  // the row lies outside the region's grid
+        int dx, dy;
+        pencil_offsets(p, dx, dy);
+        const int x = local ? cx + dx : wrapc(cx + dx);
+        const int y = local ? cy + dy : wrapc(cy + dy);
+        if ((msk >> (15 + p)) & 1u) {
+          // cells that are not consecutive buckets (a wrap in z, the end of the bucket
+          // table): each valid cell looked up alone
+          RCell C{};
+          if (local) C = rcell[rid[k]];
+          const int lnc = local ? C.nc : gnc;
+          const T sx = (T)dx * hh, sy = (T)dy * hh;
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            if (!((mk >> u) & 1)) continue;
+            const int z = local ? cz + u - 1 : wrapc(cz + u - 1);
+            const uint32_t bk = local ? (C.base + cell_index(lnc, x, y, z)) & hc.bmask
+                                      : bucket_of(lnc, hc.bmask, x, y, z);
+            const int beg = (p == 0 && u == 1) ? q + 1 : bucket_start(loc, toff, bk);
+            const int end = bucket_start(loc, toff, bk + 1);
+            // entries of this one cell (others share its bucket), shifted by u - 1 cells
+            const int32_t kk = (int32_t)(pack_cell(x, y, z) ^ salt);
+            const T sz = (T)(u - 1) * hh;
+            for (int q2 = beg; q2 < end; ++q2) {
+              const SBox<T> b1 = load_sbox<T>(sbox, q2);
+              const int2 e = entry_key_slot<SCR>(sent, b1, q2);
+              const int m = e.y;
+              if (e.x == kk && m != nk && m != pk && box_overlap(me, b1, sx, sy, sz, tl))
+                push(k, m);
+            }
+          }
+          continue;
+        }
+        const int beg = p == 0 ? q + 1 : A.rb[p - 1];
+        const int end = p == 0 ? A.re0 : A.re[p - 1];
+        test_range(beg, end, pack_cell(x, y, cz), mk, dx, dy);
+      }
+      if (nl > 0) {
+        // the element's box in global coordinates (any periodic image) for the
+        // comparisons with large elements
+        RCell C{};
+        if (local) C = rcell[rid[k]];
+        const double gh = local ? C.h : cs.h;
+        const double go[3] = {local ? C.ox : 0.0, local ? C.oy : 0.0, local ? C.oz : 0.0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          wl[i] = go[i] + ((double)(i == 0 ? cx : (i == 1 ? cy : cz)) * gh + (double)me.v[i]);
+          ex[i] = (double)me.v[4 + i] - (double)me.v[i];
+        }
+        if constexpr (SCR == 1) {
+          tlo = me.v[3];
+          thi = me.v[7];
+        } else {
+          const float4* eb = (const float4*)ebox_slot + (size_t)k * 2;
+          tlo = (double)eb[0].w + hc.tref;
+          thi = (double)eb[1].w + hc.tref;
+        }
+      }
+    } else {
+      own_large = true;
+      const LargeBox own = large[q - n_norm];
+      k = own.slot;
+      nk = nxt[k];
+      pk = prv[k];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        wl[i] = own.wl[i];
+        ex[i] = own.ext[i];
+      }
+      tlo = own.tlo;
+      thi = own.thi;
+    }
+    if (nl > 0) {
+      for (int a = 0; a < nl; ++a) {
+        const LargeBox lb = large[a];
+        const int m = lb.slot;
+        if (m == k) continue;
+        if (own_large && m < k) continue;
+        if (m == nk || m == pk) continue;
+        const double tt = hc.tol_t;
+        bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          ov = ov && wrap_overlap(wl[i], ex[i], lb.wl[i], lb.ext[i], P, hc.tolL);
+        if (ov) push(k, m);
+      }
+    }
+  }
+  __syncthreads();
+  const int staged = s_cnt;
+  if (staged >= SBUF_FLUSH || last) {
+    const int cnt = min(staged, SBUF);
+    if (threadIdx.x == 0 && cnt > 0) s_base = atomicAdd(&ctrl->n_cand, cnt);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += NT) {
+      const int idx = s_base + i;
+      if (idx < cap) cand[idx] = sbuf[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_cnt = 0;
+  }
+  __syncthreads();
+  }  // chunks
+}
+
 __device__ __forceinline__ Elem load_elem(const Slices& X, int ic, int in, int a, int ja,
                                           const sp::Period& P) {
   return sp::make_elem(ld(X, ic, a), ld(X, ic, ja), ld(X, in, a), ld(X, in, ja), P);
@@ -1228,14 +1572,15 @@ __device__ __forceinline__ void propose(uint64_t* best, int slot, uint32_t st, i
   }
 }
 
-// Matching in LDS (steps with at most RES_LDS_EVT events): each event's two elements get
+// Matching in LDS (groups with at most RES_LDS_EVT events): each event's two elements get
 // a local index through an open-addressing table of slots, and a round's proposals are
-// LDS atomics on 32-bit tags (round << 12 | event). A slot taken by an accepted event
-// holds RES_USED. Key comparisons use the bits of t* (order-preserving) and fall back to
-// the ids in global memory only on equal t*.
-constexpr int RES_LDS_EVT = 4096;
+// LDS atomics on 32-bit tags (round << 12 | local event). A slot taken by an accepted
+// event holds RES_USED. Key comparisons use the bits of t* (order-preserving) and fall
+// back to the ids in global memory only on equal t*.
+constexpr int RES_LDS_EVT = 3072;
 constexpr int RES_HASH = 12288;  // > 2 RES_LDS_EVT: an insert always finds room
 constexpr uint32_t RES_USED = 0xFFFFFFFFu;
+constexpr int RES_GROUPS = 32;   // most workgroups of the matching (batches)
 static_assert(RES_LDS_EVT <= 4096, "event index in the low 12 bits of a tag");
 
 __device__ __forceinline__ uint64_t order_bits(double t) {
@@ -1243,13 +1588,15 @@ __device__ __forceinline__ uint64_t order_bits(double t) {
   return (u >> 63) ? ~u : (u | (1ull << 63));
 }
 
-// Event e's key is below event f's: (t*, id_a, id_b) order.
-__device__ __forceinline__ bool lkey_less(const uint64_t* s_t, const EvCand* ev, int e, int f) {
-  const uint64_t a = s_t[e], b = s_t[f];
+// Local event i's key is below local event j's: (t*, id_a, id_b) order.
+__device__ __forceinline__ bool lkey_less(const uint64_t* s_t, const int32_t* s_list,
+                                          const EvCand* ev, int i, int j) {
+  const uint64_t a = s_t[i], b = s_t[j];
   if (a != b) return a < b;
-  const int64_t ea = ev[e].ida, fa = ev[f].ida;
-  if (ea != fa) return ea < fa;
-  return ev[e].idb < ev[f].idb;
+  const EvCand& e = ev[s_list[i]];
+  const EvCand& f = ev[s_list[j]];
+  if (e.ida != f.ida) return e.ida < f.ida;
+  return e.idb < f.idb;
 }
 
 // Local index of `slot` in the table (inserted if absent).
@@ -1262,33 +1609,114 @@ __device__ __forceinline__ int lslot(int32_t* s_hkey, int32_t slot) {
   }
 }
 
-// Claim local slot h for event e with `tag` unless an event of smaller key holds it this
-// round, or an accepted event took it.
-__device__ __forceinline__ void lpropose(uint32_t* s_best, int h, uint32_t tag, int e,
-                                         const uint64_t* s_t, const EvCand* ev) {
+// Claim local slot h for local event i with `tag` unless an event of smaller key holds it
+// this round, or an accepted event took it.
+__device__ __forceinline__ void lpropose(uint32_t* s_best, int h, uint32_t tag, int i,
+                                         const uint64_t* s_t, const int32_t* s_list,
+                                         const EvCand* ev) {
   uint32_t old = __hip_atomic_load(&s_best[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   for (;;) {
     if (old == RES_USED) return;
-    if ((old >> 12) == (tag >> 12) && lkey_less(s_t, ev, (int)(old & 4095u), e)) return;
+    if ((old >> 12) == (tag >> 12) && lkey_less(s_t, s_list, ev, (int)(old & 4095u), i)) return;
     const uint32_t prev = atomicCAS(&s_best[h], old, tag);
     if (prev == old) return;
     old = prev;
   }
 }
 
-// One workgroup: the greedy matching of the step's events in (t*, id_a, id_b) order,
-// computed as iterated local minima; partner exchange; log; step bookkeeping. With
-// p < 1 each crossing first draws u; one with u >= p passes through: it is logged
-// (kind 1) and marks its elements for the loop rule, but claims neither.
+// Each sub-region's local grid for the next step (h_set > 0: that cell edge; else grow
+// x its largest element extent of this step), and the bucket bases (prefix sums of the
+// grids' cell counts). Called by a whole workgroup of 1024 threads; s_sum holds 1024
+// values of LDS.
+__device__ __forceinline__ void rcells_update(const RegionGeom* __restrict__ geoms, int n_sub,
+                                              uint64_t* __restrict__ rext,
+                                              RCell* __restrict__ rc, double h_set,
+                                              const Ctrl* ctrl, uint64_t* s_sum) {
+  const int t = threadIdx.x;
+  const int per = (n_sub + 1023) / 1024;
+  const double grow = ctrl->grow;
+  uint64_t sum = 0;
+  for (int i = 0; i < per; ++i) {
+    const int q = t * per + i;
+    if (q >= n_sub) break;
+    RCell C = rc[q];
+    const double g = 0.5 / geoms[q].inv2g;
+    const double W = RCELL_W * g;
+    double target = h_set;
+    if (h_set <= 0.0) {
+      const uint64_t x = rext[(size_t)q * REXT_STRIDE];
+      target = x != 0 ? grow * from_key(x) : (C.nc > 0 ? C.h : W / 3.0);
+    }
+    rext[(size_t)q * REXT_STRIDE] = 0;
+    int nc = (int)floor(W / target);
+    nc = nc < 3 ? 3 : (nc > 1023 ? 1023 : nc);
+    C.nc = nc;
+    C.h = W / nc;
+    C.inv_h = 1.0 / C.h;
+    C.hlim = C.h - 4.0 * ctrl->tol;
+    C.h32 = (float)C.h;
+    // FP32 slack: a few ulps at the largest local magnitude (clamped elements lie up to
+    // W from a cell origin)
+    C.marg32 = (float)((W + 3.0 * C.h) * 0x1p-20);
+    double ctr[3];
+    region_centre(geoms[q], ctr);
+    C.ox = ctr[0] - 0.5 * W;
+    C.oy = ctr[1] - 0.5 * W;
+    C.oz = ctr[2] - 0.5 * W;
+    C.salt = (uint32_t)q * 0x9E3779B1u;
+    rc[q] = C;
+    sum += cell_count(nc);
+  }
+  s_sum[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint64_t add = t >= o ? s_sum[t - o] : 0;
+    __syncthreads();
+    s_sum[t] += add;
+    __syncthreads();
+  }
+  uint64_t run = s_sum[t] - sum;
+  for (int i = 0; i < per; ++i) {
+    const int q = t * per + i;
+    if (q >= n_sub) break;
+    rc[q].base = (uint32_t)run;
+    run += cell_count(rc[q].nc);
+  }
+}
+
+// Wave-aggregated reservation: lanes with `want` get consecutive places from one
+// atomicAdd on *ctr per wave; returns this lane's place (or -1).
+__device__ __forceinline__ int wave_reserve(int32_t* ctr, bool want) {
+  const uint64_t m = __ballot(want);
+  if (!m) return -1;
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(ctr, __popcll(m));
+  base = __shfl(base, leader, 64);
+  const uint64_t below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
+  return want ? base + __popcll(below) : -1;
+}
+
+// The greedy matching of the step's events in (t*, id_a, id_b) order, computed as
+// iterated local minima; partner exchange; log; step bookkeeping. Events of different
+// sub-regions of a batch never share an element, so each workgroup takes the events of
+// the sub-regions q with q mod gridDim.x == blockIdx.x and matches them alone (one
+// workgroup for a single region). With p < 1 each crossing first draws u; one with
+// u >= p passes through: it is logged (kind 1) and marks its elements for the loop rule,
+// but claims neither. The last workgroup to finish does the step's bookkeeping.
 __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     int32_t* __restrict__ nxt, int32_t* __restrict__ prv, const EvCand* __restrict__ ev,
     int cap_evt, int cap_cand, uint64_t* __restrict__ best, int32_t* __restrict__ used,
     int8_t* __restrict__ evs, semipar_event* __restrict__ log, int64_t log_cap,
     const uint64_t* __restrict__ blkred, int nblk, Ctrl* ctrl, const int32_t* __restrict__ rid,
-    int32_t* __restrict__ log_rid, int32_t* __restrict__ lev, double p_ic, uint64_t seed) {
-  __shared__ int s_live;
-  __shared__ int s_nacc, s_npass, s_nlog;
+    int32_t* __restrict__ log_rid, int32_t* __restrict__ lev, double p_ic, uint64_t seed,
+    const RegionGeom* __restrict__ geoms, int n_sub, uint64_t* __restrict__ rext,
+    RCell* __restrict__ rcell, double rc_h) {
+  __shared__ int s_live, s_nloc, s_last;
+  __shared__ int s_nacc, s_npass;
   __shared__ uint64_t s_t[RES_LDS_EVT];
+  __shared__ int32_t s_list[RES_LDS_EVT];
   __shared__ int16_t s_la[RES_LDS_EVT], s_lb[RES_LDS_EVT];
   __shared__ int8_t s_evs[RES_LDS_EVT];
   __shared__ int32_t s_hkey[RES_HASH];
@@ -1296,14 +1724,194 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
   __shared__ uint64_t s_min[RESOLVE_NT / 64], s_max[RESOLVE_NT / 64], s_adv[RESOLVE_NT / 64];
   if (ctrl->done) return;
   const int t = threadIdx.x;
+  const int ngrp = (int)gridDim.x, grp = (int)blockIdx.x;
   const int ncand = ctrl->n_cand;
   const int ne = ctrl->n_evt;
   int defer = 0;
   if (ncand > cap_cand) defer |= 1;
   if (ne > cap_evt) defer |= 2;
   if (ctrl->log_n + (int64_t)ne > log_cap) defer |= 4;
-  if (defer) {
+  const int32_t step_stamp = ctrl->step + 1;
+  const uint32_t base = (uint32_t)ctrl->stamp;
+  const int32_t n_step = ctrl->step;
+  const int64_t log0 = ctrl->log_n;
+  // the event's group: its sub-region modulo the workgroups
+  auto mine = [&](int e) { return ngrp == 1 || rid[ev[e].sa] % ngrp == grp; };
+  if (t == 0) {
+    s_nloc = 0;
+    s_nacc = 0;
+    s_npass = 0;
+  }
+  __syncthreads();
+  uint32_t iter = 0;
+  if (!defer && ne > 0) {
+    // this group's events (any order: the matching depends on the keys only)
+    for (int e = t; e < ne; e += RESOLVE_NT)
+      if (mine(e)) {
+        const int i = atomicAdd(&s_nloc, 1);
+        if (i < RES_LDS_EVT) s_list[i] = e;
+      }
     __syncthreads();
+    const int nloc = s_nloc;
+    const bool in_lds = nloc <= RES_LDS_EVT;
+    if (in_lds) {
+      for (int i = t; i < RES_HASH; i += RESOLVE_NT) {
+        s_hkey[i] = -1;
+        s_best[i] = 0;
+      }
+      __syncthreads();
+      // event states: 1 in the matching, 3 passes through (2 accepted, 0 blocked)
+      for (int i = t; i < nloc; i += RESOLVE_NT) {
+        const EvCand& c = ev[s_list[i]];
+        s_evs[i] = (p_ic >= 1.0 || crossing_draw(seed, n_step, c.ida, c.idb) < p_ic) ? 1 : 3;
+        s_t[i] = order_bits(c.t);
+        s_la[i] = (int16_t)lslot(s_hkey, c.sa);
+        s_lb[i] = (int16_t)lslot(s_hkey, c.sb);
+      }
+      __syncthreads();
+      for (;;) {
+        const uint32_t tag0 = (iter + 1) << 12;
+        for (int i = t; i < nloc; i += RESOLVE_NT)
+          if (s_evs[i] == 1) {
+            lpropose(s_best, s_la[i], tag0 | (uint32_t)i, i, s_t, s_list, ev);
+            lpropose(s_best, s_lb[i], tag0 | (uint32_t)i, i, s_t, s_list, ev);
+          }
+        __syncthreads();
+        // an event holding both its slots is accepted and takes them; an event whose
+        // slot holds another tag cannot hold it, so the two checks do not interfere
+        for (int i = t; i < nloc; i += RESOLVE_NT)
+          if (s_evs[i] == 1) {
+            const uint32_t tag = tag0 | (uint32_t)i;
+            const int la = s_la[i], lb = s_lb[i];
+            if (s_best[la] == tag && s_best[lb] == tag) {
+              s_evs[i] = 2;
+              s_best[la] = RES_USED;
+              s_best[lb] = RES_USED;
+            }
+          }
+        if (t == 0) s_live = 0;
+        __syncthreads();
+        int live = 0;
+        for (int i = t; i < nloc; i += RESOLVE_NT)
+          if (s_evs[i] == 1) {
+            if (s_best[s_la[i]] == RES_USED || s_best[s_lb[i]] == RES_USED)
+              s_evs[i] = 0;
+            else
+              live++;
+          }
+        if (live) atomicAdd(&s_live, live);
+        __syncthreads();
+        const int remaining = s_live;
+        __syncthreads();
+        ++iter;
+        if (remaining == 0) break;
+      }
+    } else {
+      // more events than the LDS holds: the same rounds on per-slot tags in memory
+      for (int e = t; e < ne; e += RESOLVE_NT)
+        if (mine(e)) {
+          const EvCand& c = ev[e];
+          evs[e] = (p_ic >= 1.0 || crossing_draw(seed, n_step, c.ida, c.idb) < p_ic) ? 1 : 3;
+        }
+      __syncthreads();
+      for (;;) {
+        const uint32_t stp = base + 1 + iter;
+        for (int e = t; e < ne; e += RESOLVE_NT)
+          if (mine(e) && evs[e] == 1) {
+            propose(best, ev[e].sa, stp, e, ev);
+            propose(best, ev[e].sb, stp, e, ev);
+          }
+        __syncthreads();
+        const uint64_t tag0 = (uint64_t)stp << 32;
+        for (int e = t; e < ne; e += RESOLVE_NT)
+          if (mine(e) && evs[e] == 1) {
+            const uint64_t tag = tag0 | (uint32_t)e;
+            if (aload64(&best[ev[e].sa]) == tag && aload64(&best[ev[e].sb]) == tag) {
+              evs[e] = 2;
+              astore32(&used[ev[e].sa], step_stamp);
+              astore32(&used[ev[e].sb], step_stamp);
+            }
+          }
+        if (t == 0) s_live = 0;
+        __syncthreads();
+        int live = 0;
+        for (int e = t; e < ne; e += RESOLVE_NT)
+          if (mine(e) && evs[e] == 1) {
+            if (aload32(&used[ev[e].sa]) == step_stamp || aload32(&used[ev[e].sb]) == step_stamp)
+              evs[e] = 0;
+            else
+              live++;
+          }
+        if (live) atomicAdd(&s_live, live);
+        __syncthreads();
+        const int remaining = s_live;
+        __syncthreads();
+        ++iter;
+        if (remaining == 0) break;
+      }
+    }
+    // partner exchange (accepted events touch disjoint elements) and log; places in the
+    // log are reserved once per wave (the log is put in listing order when read)
+    const int nit = in_lds ? nloc : ne;
+    const int span = (nit + RESOLVE_NT - 1) / RESOLVE_NT * RESOLVE_NT;  // whole waves
+    for (int i = t; i < span; i += RESOLVE_NT) {
+      int e = -1;
+      int8_t es = 0;
+      if (i < nit) {
+        if (in_lds) {
+          e = s_list[i];
+          es = s_evs[i];
+        } else if (mine(i)) {
+          e = i;
+          es = evs[i];
+        }
+      }
+      const bool logged = es == 2 || es == 3;
+      const int li = wave_reserve(&ctrl->res_nlog, logged);
+      if (!logged) continue;
+      const int a = ev[e].sa, b = ev[e].sb;
+      if (es == 2) {
+        const int ja = nxt[a], jb = nxt[b];
+        nxt[a] = jb;
+        nxt[b] = ja;
+        prv[jb] = a;
+        prv[ja] = b;
+        atomicAdd(&s_nacc, 1);
+      } else {
+        atomicAdd(&s_npass, 1);
+      }
+      semipar_event o;
+      o.step = n_step;
+      o.kind = es == 2 ? 0 : 1;
+      o.id_a = ev[e].ida;
+      o.id_b = ev[e].idb;
+      o.t_star = ev[e].t;
+      o.x_star[0] = ev[e].x;
+      o.x_star[1] = ev[e].y;
+      o.x_star[2] = ev[e].z;
+      log[log0 + li] = o;
+      if (log_rid) log_rid[log0 + li] = rid[a];
+      lev[a] = n_step;
+      lev[b] = n_step;
+    }
+    __syncthreads();
+    if (t == 0) {
+      if (s_nacc) atomicAdd(&ctrl->res_nacc, s_nacc);
+      if (s_npass) atomicAdd(&ctrl->res_npass, s_npass);
+      atomicMax(&ctrl->res_iter, (int32_t)iter);
+    }
+  }
+  // the last workgroup to get here does the step's bookkeeping (every other workgroup
+  // has read the control block and written its results by then)
+  __syncthreads();
+  if (t == 0) {
+    __threadfence();
+    s_last = atomicAdd(&ctrl->res_done, 1) == ngrp - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (defer) {
     if (t == 0) {
       ctrl->defer = defer;
       ctrl->done = 1;
@@ -1311,146 +1919,9 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
       ctrl->n_evt = 0;
       ctrl->n_large = 0;
       ctrl->tmin_key = KEY_MAX;
+      ctrl->res_done = 0;
     }
     return;
-  }
-  const int32_t step_stamp = ctrl->step + 1;
-  const uint32_t base = (uint32_t)ctrl->stamp;
-  const int32_t n_step = ctrl->step;
-  const bool in_lds = ne <= RES_LDS_EVT;
-  if (in_lds) {
-    for (int i = t; i < RES_HASH; i += RESOLVE_NT) {
-      s_hkey[i] = -1;
-      s_best[i] = 0;
-    }
-    __syncthreads();
-  }
-  // event states: 1 in the matching, 3 passes through (2 accepted, 0 blocked, set below)
-  int8_t* const st = in_lds ? s_evs : evs;
-  for (int e = t; e < ne; e += RESOLVE_NT) {
-    const int64_t ia = ev[e].ida, ib = ev[e].idb;
-    st[e] = (p_ic >= 1.0 || crossing_draw(seed, n_step, ia, ib) < p_ic) ? 1 : 3;
-    if (in_lds) {
-      s_t[e] = order_bits(ev[e].t);
-      s_la[e] = (int16_t)lslot(s_hkey, ev[e].sa);
-      s_lb[e] = (int16_t)lslot(s_hkey, ev[e].sb);
-    }
-  }
-  if (t == 0) {
-    s_nacc = 0;
-    s_npass = 0;
-    s_nlog = 0;
-  }
-  __syncthreads();
-  uint32_t iter = 0;
-  if (ne > 0 && in_lds) {
-    for (;;) {
-      const uint32_t tag0 = (iter + 1) << 12;
-      for (int e = t; e < ne; e += RESOLVE_NT)
-        if (s_evs[e] == 1) {
-          lpropose(s_best, s_la[e], tag0 | (uint32_t)e, e, s_t, ev);
-          lpropose(s_best, s_lb[e], tag0 | (uint32_t)e, e, s_t, ev);
-        }
-      __syncthreads();
-      // an event holding both its slots is accepted and takes them; an event whose
-      // slot holds another tag cannot hold it, so the two checks do not interfere
-      for (int e = t; e < ne; e += RESOLVE_NT)
-        if (s_evs[e] == 1) {
-          const uint32_t tag = tag0 | (uint32_t)e;
-          const int la = s_la[e], lb = s_lb[e];
-          if (s_best[la] == tag && s_best[lb] == tag) {
-            s_evs[e] = 2;
-            s_best[la] = RES_USED;
-            s_best[lb] = RES_USED;
-          }
-        }
-      if (t == 0) s_live = 0;
-      __syncthreads();
-      int live = 0;
-      for (int e = t; e < ne; e += RESOLVE_NT)
-        if (s_evs[e] == 1) {
-          if (s_best[s_la[e]] == RES_USED || s_best[s_lb[e]] == RES_USED)
-            s_evs[e] = 0;
-          else
-            live++;
-        }
-      if (live) atomicAdd(&s_live, live);
-      __syncthreads();
-      const int remaining = s_live;
-      __syncthreads();
-      ++iter;
-      if (remaining == 0) break;
-    }
-  } else if (ne > 0) {
-    for (;;) {
-      const uint32_t stp = base + 1 + iter;
-      for (int e = t; e < ne; e += RESOLVE_NT)
-        if (evs[e] == 1) {
-          propose(best, ev[e].sa, stp, e, ev);
-          propose(best, ev[e].sb, stp, e, ev);
-        }
-      __syncthreads();
-      const uint64_t tag0 = (uint64_t)stp << 32;
-      for (int e = t; e < ne; e += RESOLVE_NT)
-        if (evs[e] == 1) {
-          const uint64_t tag = tag0 | (uint32_t)e;
-          if (aload64(&best[ev[e].sa]) == tag && aload64(&best[ev[e].sb]) == tag) {
-            evs[e] = 2;
-            astore32(&used[ev[e].sa], step_stamp);
-            astore32(&used[ev[e].sb], step_stamp);
-          }
-        }
-      if (t == 0) s_live = 0;
-      __syncthreads();
-      int live = 0;
-      for (int e = t; e < ne; e += RESOLVE_NT)
-        if (evs[e] == 1) {
-          if (aload32(&used[ev[e].sa]) == step_stamp || aload32(&used[ev[e].sb]) == step_stamp)
-            evs[e] = 0;
-          else
-            live++;
-        }
-      if (live) atomicAdd(&s_live, live);
-      __syncthreads();
-      const int remaining = s_live;
-      __syncthreads();
-      ++iter;
-      if (remaining == 0) break;
-    }
-  }
-  if (ne > 0) {
-    // partner exchange (accepted events touch disjoint elements) and log
-    const int64_t log0 = ctrl->log_n;
-    for (int e = t; e < ne; e += RESOLVE_NT) {
-      const int8_t es = st[e];
-      if (es == 2 || es == 3) {
-        const int a = ev[e].sa, b = ev[e].sb;
-        if (es == 2) {
-          const int ja = nxt[a], jb = nxt[b];
-          nxt[a] = jb;
-          nxt[b] = ja;
-          prv[jb] = a;
-          prv[ja] = b;
-          atomicAdd(&s_nacc, 1);
-        } else {
-          atomicAdd(&s_npass, 1);
-        }
-        const int i = atomicAdd(&s_nlog, 1);
-        semipar_event o;
-        o.step = n_step;
-        o.kind = es == 2 ? 0 : 1;
-        o.id_a = ev[e].ida;
-        o.id_b = ev[e].idb;
-        o.t_star = ev[e].t;
-        o.x_star[0] = ev[e].x;
-        o.x_star[1] = ev[e].y;
-        o.x_star[2] = ev[e].z;
-        log[log0 + i] = o;
-        if (log_rid) log_rid[log0 + i] = rid[a];
-        lev[a] = n_step;
-        lev[b] = n_step;
-      }
-    }
   }
   // smallest t of the slice written by this step's k_evolve, largest element extent
   uint64_t mk = KEY_MAX, xk = 0, ak = 0;
@@ -1475,11 +1946,15 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
       x = s_max[w] > x ? s_max[w] : x;
       nadv += s_adv[w];
     }
+    const int32_t nlog = aload32(&ctrl->res_nlog);
+    const int32_t nacc = aload32(&ctrl->res_nacc);
+    const int32_t npass = aload32(&ctrl->res_npass);
+    const int32_t rounds = aload32(&ctrl->res_iter);
     if (!ctrl->cells.fixed && x != 0)
       ctrl->cells = choose_cells(ctrl->box, ctrl->grow * from_key(x), ctrl->tol);
-    ctrl->log_n += s_nlog;
-    ctrl->acc_total += s_nacc;
-    ctrl->pass_total += s_npass;
+    ctrl->log_n += nlog;
+    ctrl->acc_total += nacc;
+    ctrl->pass_total += npass;
     ctrl->conf_total += ne;
     ctrl->cand_total += ncand;
     ctrl->last_cand = ncand;
@@ -1487,12 +1962,322 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     ctrl->n_cand = 0;
     ctrl->n_evt = 0;
     ctrl->n_large = 0;
-    ctrl->stamp = (int32_t)(base + iter);
+    ctrl->res_nlog = 0;
+    ctrl->res_nacc = 0;
+    ctrl->res_npass = 0;
+    ctrl->res_iter = 0;
+    ctrl->res_done = 0;
+    ctrl->stamp = (int32_t)(base + (uint32_t)rounds);
     ctrl->step += 1;
     ctrl->steps_taken += 1;
     ctrl->point_steps += (int64_t)nadv;
     const double tmin = nadv ? from_key(m) : 0.0;
     ctrl->done = (ctrl->step >= ctrl->step_limit || nadv == 0 || tmin >= ctrl->t_end) ? 1 : 0;
+  }
+  // a batch: every sub-region's grid for the next step (the events' LDS is free now)
+  if (rcell) {
+    __syncthreads();
+    if (!(rc_h <= 0.0 && ctrl->done))
+      rcells_update(geoms, n_sub, rext, rcell, rc_h, ctrl, s_t);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// persistent evolution of small regions
+// ---------------------------------------------------------------------------------
+// A batch of small bounded regions in one launch: each workgroup takes the next
+// sub-region from a device counter and evolves it through all of its steps without
+// leaving the kernel (workgroup barriers between the phases of a step), then takes the
+// next. Per step, the same arithmetic as the step kernels: decisions and diamond tops,
+// the elements of the band, every pair of elements of the region tested with the exact
+// FP64 4-D box test that the confirmation applies (which the screen only pre-filters),
+// the four triangle pairs, and the greedy matching in (t*, id_a, id_b) order, taken one
+// event after another. So each region ends exactly as a run of it alone. A step with
+// more crossings than the workgroup holds stops the launch (error bit 64): the caller
+// runs the batch again from its surfaces on the step kernels.
+constexpr int PB_NT = 256;    // threads of a workgroup
+constexpr int PB_MAXP = SEMIPAR_PERSISTENT_MAX;  // most points of a region evolved this way
+constexpr int PB_EVT = SEMIPAR_PERSISTENT_EVENTS;  // crossings of one step held in LDS
+constexpr int PB_GRID = 1024; // most workgroups
+
+struct PbEv {
+  double t, x, y, z;
+  int64_t ida, idb;
+  int32_t sa, sb;
+};
+
+template <bool FRW>
+__global__ __launch_bounds__(PB_NT) void k_region_block(
+    Slices X, int32_t* __restrict__ nxt, int32_t* __restrict__ prv,
+    const int64_t* __restrict__ id, int32_t* __restrict__ fstep, int32_t* __restrict__ face,
+    semipar_point_rec* __restrict__ frz, int32_t* __restrict__ lev,
+    const RegionGeom* __restrict__ geoms, const int64_t* __restrict__ sub_off, int n_sub,
+    int32_t* __restrict__ work_head, sp::Period P, double hcoef, int32_t step0,
+    int32_t step_limit, double p_ic, uint64_t seed, semipar_event* __restrict__ log,
+    int32_t* __restrict__ log_rid, int64_t log_cap, Ctrl* ctrl) {
+  __shared__ double s_lo[PB_MAXP][4], s_hi[PB_MAXP][4];
+  __shared__ double s_anc[PB_MAXP][3];
+  __shared__ int64_t s_id[PB_MAXP];
+  __shared__ uint8_t s_adv[PB_MAXP], s_val[PB_MAXP], s_used[PB_MAXP];
+  __shared__ PbEv s_ev[PB_EVT];
+  __shared__ int s_q, s_nadv, s_nev, s_ncand, s_abort;
+  __shared__ int s_ord[PB_EVT];
+  __shared__ int8_t s_kind[PB_EVT];
+  const int t = threadIdx.x;
+  for (;;) {
+    if (t == 0) s_q = atomicAdd(work_head, 1);
+    __syncthreads();
+    const int q = s_q;
+    if (q >= n_sub) return;
+    const int64_t off = sub_off[q];
+    const int n = (int)(sub_off[q + 1] - off);
+    const RegionGeom G = geoms[q];
+    int64_t psteps = 0, ncand = 0, nconf = 0, nacc = 0, npass = 0;
+    int32_t s = step0;
+    bool aborted = false;
+    while (n > 0 && s < step_limit) {
+      const int ic = s % 3, ip = (s + 2) % 3, in = (s + 1) % 3;
+      if (t == 0) {
+        s_nadv = 0;
+        s_nev = 0;
+        s_ncand = 0;
+        s_abort = ctrl->err & 64;  // another workgroup gave up: so does this one
+      }
+      __syncthreads();
+      if (s_abort) {
+        aborted = true;
+        break;
+      }
+      // decisions and tops (as k_evolve for a bounded region)
+      int my_adv = 0;
+      for (int i = t; i < n; i += PB_NT) {
+        const int k = (int)off + i;
+        bool adv = false;
+        if (fstep[k] == FS_ACTIVE) {
+          const int j = nxt[k];
+          int f = -1;
+          bool with_r = false;
+          V4 B{}, R{};
+          if (j >= 0) {
+            B = ld(X, ip, j);
+            R = ld(X, ic, j);
+          }
+          if (j < 0) {
+            f = -1;
+          } else if (fstep[j] < s) {
+            f = face[j];
+          } else {
+            f = exit_face(G, B);
+            if (f < 0) adv = true;
+            with_r = true;
+          }
+          if (!adv) {
+            write_frozen(frz, X, ic, ip, k, j, with_r, f, s, prv, id);
+            face[k] = f;
+            fstep[k] = s;
+          } else {
+            const V4 L = ld(X, ic, k);
+            st(X, in, k, sp::top<FRW>(L, R, B, P, hcoef));
+            ++my_adv;
+          }
+        }
+        s_adv[i] = adv ? 1 : 0;
+      }
+      if (my_adv) atomicAdd(&s_nadv, my_adv);
+      __syncthreads();
+      const int nadv = s_nadv;
+      if (nadv == 0) {  // every point has stopped: this step counts as taken, as on the
+        ++s;            // step kernels
+        break;
+      }
+      psteps += nadv;
+      // the elements of band s: k and next[k] both advanced
+      for (int i = t; i < n; i += PB_NT) {
+        uint8_t v = 0;
+        if (s_adv[i]) {
+          const int k = (int)off + i;
+          const int j = nxt[k];
+          if (s_adv[j - (int)off]) {
+            const Elem e = sp::make_elem(ld(X, ic, k), ld(X, ic, j), ld(X, in, k), ld(X, in, j), P);
+            const Box4 b = sp::elem_box(e);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              s_lo[i][c] = b.lo[c];
+              s_hi[i][c] = b.hi[c];
+            }
+            s_anc[i][0] = e.v[0].x;
+            s_anc[i][1] = e.v[0].y;
+            s_anc[i][2] = e.v[0].z;
+            v = 1;
+          }
+        }
+        s_val[i] = v;
+        s_used[i] = 0;
+        if (s == step0) s_id[i] = id[(int)off + i];
+      }
+      __syncthreads();
+      // every pair of elements of the region: exact box overlap, then the triangle pairs
+      int my_cand = 0;
+      for (int i = t; i < n; i += PB_NT) {
+        if (!s_val[i]) continue;
+        const int k = (int)off + i;
+        const int nk = nxt[k] - (int)off, pk = prv[k] - (int)off;
+        const int64_t idi = s_id[i];
+        for (int m = i + 1; m < n; ++m) {
+          if (!s_val[m] || m == nk || m == pk) continue;
+          // a = the element of the point with the smaller id (the order the
+          // confirmation uses)
+          int a = i, b = m;
+          if (s_id[m] < idi) {
+            a = m;
+            b = i;
+          }
+          double S[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) S[c] = P.box * P.nearest(s_anc[b][c] - s_anc[a][c]);
+          bool ov = true;
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            ov = ov && (s_lo[a][c] <= s_hi[b][c] - S[c]) && (s_lo[b][c] - S[c] <= s_hi[a][c]);
+          ov = ov && (s_lo[a][3] <= s_hi[b][3]) && (s_lo[b][3] <= s_hi[a][3]);
+          if (!ov) continue;
+          ++my_cand;
+          const int ga = (int)off + a, gb = (int)off + b;
+          const Elem ea = load_elem(X, ic, in, ga, nxt[ga], P);
+          Elem eb = load_elem(X, ic, in, gb, nxt[gb], P);
+          for (int v = 0; v < 4; ++v) {
+            eb.v[v].x = eb.v[v].x - S[0];
+            eb.v[v].y = eb.v[v].y - S[1];
+            eb.v[v].z = eb.v[v].z - S[2];
+          }
+          bool found = false;
+          double bt = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+          for (int ipq = 0; ipq < 4; ++ipq) {
+            const int ipp = ipq >> 1, iq = ipq & 1;
+            double tt, xx, yy, zz;
+            if (sp::tri_tri(ipp ? ea.v[2] : ea.v[0], ea.v[1], ipp ? ea.v[3] : ea.v[2],
+                            iq ? eb.v[2] : eb.v[0], eb.v[1], iq ? eb.v[3] : eb.v[2], tt, xx, yy,
+                            zz)) {
+              if (!found || tt < bt) {
+                found = true;
+                bt = tt;
+                bx = xx;
+                by = yy;
+                bz = zz;
+              }
+            }
+          }
+          if (!found) continue;
+          const int e = atomicAdd(&s_nev, 1);
+          if (e < PB_EVT) {
+            PbEv c;
+            c.t = bt;
+            c.x = bx;
+            c.y = by;
+            c.z = bz;
+            c.ida = id[ga];
+            c.idb = id[gb];
+            c.sa = ga;
+            c.sb = gb;
+            s_ev[e] = c;
+          }
+        }
+      }
+      if (my_cand) atomicAdd(&s_ncand, my_cand);
+      __syncthreads();
+      const int ne = s_nev;
+      if (ne > PB_EVT) {
+        if (t == 0) atomicOr(&ctrl->err, 64);
+        aborted = true;
+        break;
+      }
+      ncand += s_ncand;
+      nconf += ne;
+      // the greedy matching in (t*, id_a, id_b) order, one event after another, after
+      // each crossing's draw (p < 1: a draw >= p passes through, claims nothing)
+      if (t == 0 && ne > 0) {
+        for (int e = 0; e < ne; ++e) s_ord[e] = e;
+        for (int e = 1; e < ne; ++e) {  // insertion sort by key
+          const int x = s_ord[e];
+          int f = e - 1;
+          while (f >= 0) {
+            const PbEv& A = s_ev[s_ord[f]];
+            const PbEv& Bv = s_ev[x];
+            const bool gt = A.t > Bv.t || (A.t == Bv.t && (A.ida > Bv.ida ||
+                                                            (A.ida == Bv.ida && A.idb > Bv.idb)));
+            if (!gt) break;
+            s_ord[f + 1] = s_ord[f];
+            --f;
+          }
+          s_ord[f + 1] = x;
+        }
+        int nlog = 0;
+        for (int o = 0; o < ne; ++o) {
+          const PbEv& c = s_ev[s_ord[o]];
+          int8_t kind = -1;
+          if (!(p_ic >= 1.0 || crossing_draw(seed, s, c.ida, c.idb) < p_ic)) {
+            kind = 1;
+          } else if (!s_used[c.sa - (int)off] && !s_used[c.sb - (int)off]) {
+            kind = 0;
+            s_used[c.sa - (int)off] = 1;
+            s_used[c.sb - (int)off] = 1;
+          }
+          s_kind[o] = kind;
+          if (kind >= 0) ++nlog;
+        }
+        const int64_t base = atomicAdd((unsigned long long*)&ctrl->log_n, (unsigned long long)nlog);
+        if (base + nlog > log_cap) {
+          atomicOr(&ctrl->err, 64);
+          s_abort = 1;
+        } else {
+          int li = 0;
+          for (int o = 0; o < ne; ++o) {
+            if (s_kind[o] < 0) continue;
+            const PbEv& c = s_ev[s_ord[o]];
+            if (s_kind[o] == 0) {
+              const int ja = nxt[c.sa], jb = nxt[c.sb];
+              nxt[c.sa] = jb;
+              nxt[c.sb] = ja;
+              prv[jb] = c.sa;
+              prv[ja] = c.sb;
+              ++nacc;
+            } else {
+              ++npass;
+            }
+            semipar_event ev;
+            ev.step = s;
+            ev.kind = s_kind[o];
+            ev.id_a = c.ida;
+            ev.id_b = c.idb;
+            ev.t_star = c.t;
+            ev.x_star[0] = c.x;
+            ev.x_star[1] = c.y;
+            ev.x_star[2] = c.z;
+            log[base + li] = ev;
+            if (log_rid) log_rid[base + li] = q;
+            lev[c.sa] = s;
+            lev[c.sb] = s;
+            ++li;
+          }
+        }
+      }
+      __syncthreads();
+      if (s_abort) {
+        aborted = true;
+        break;
+      }
+      ++s;
+    }
+    // this region's totals (thread 0 holds the matching's counts)
+    if (t == 0 && !aborted) {
+      atomicAdd((unsigned long long*)&ctrl->point_steps, (unsigned long long)psteps);
+      atomicAdd((unsigned long long*)&ctrl->cand_total, (unsigned long long)ncand);
+      atomicAdd((unsigned long long*)&ctrl->conf_total, (unsigned long long)nconf);
+      atomicAdd((unsigned long long*)&ctrl->acc_total, (unsigned long long)nacc);
+      atomicAdd((unsigned long long*)&ctrl->pass_total, (unsigned long long)npass);
+      atomicMax(&ctrl->pb_step, s);  // the furthest slice any region reached
+    }
+    __syncthreads();
   }
 }
 
@@ -1780,62 +2565,15 @@ __global__ __launch_bounds__(NT) void k_loop_final(int nl, int s, Slices X,
 // otherwise each region's cells follow its own largest element of the step just taken
 // (grow x extent; regions without elements keep their grid). Bucket bases are the
 // running sum of the regions' cell counts. The extents are reset for the next step.
+// The grids of the first step of an evolve call (the per-step update runs in the last
+// workgroup of k_resolve).
 __global__ __launch_bounds__(1024) void k_rcells(const RegionGeom* __restrict__ geoms, int n_sub,
                                                  uint64_t* __restrict__ rext,
                                                  RCell* __restrict__ rc, double h_set,
                                                  const Ctrl* ctrl) {
   if (h_set <= 0.0 && ctrl->done) return;
   __shared__ uint64_t s_sum[1024];
-  const int t = threadIdx.x;
-  const int per = (n_sub + 1023) / 1024;
-  const double grow = ctrl->grow;
-  uint64_t sum = 0;
-  for (int i = 0; i < per; ++i) {
-    const int q = t * per + i;
-    if (q >= n_sub) break;
-    RCell C = rc[q];
-    const double g = 0.5 / geoms[q].inv2g;
-    const double W = RCELL_W * g;
-    double target = h_set;
-    if (h_set <= 0.0) {
-      const uint64_t x = rext[(size_t)q * REXT_STRIDE];
-      target = x != 0 ? grow * from_key(x) : (C.nc > 0 ? C.h : W / 3.0);
-    }
-    rext[(size_t)q * REXT_STRIDE] = 0;
-    int nc = (int)floor(W / target);
-    nc = nc < 3 ? 3 : (nc > 1023 ? 1023 : nc);
-    C.nc = nc;
-    C.h = W / nc;
-    C.inv_h = 1.0 / C.h;
-    C.hlim = C.h - 4.0 * ctrl->tol;
-    C.h32 = (float)C.h;
-    // FP32 slack: a few ulps at the largest local magnitude (clamped elements lie up to
-    // W from a cell origin)
-    C.marg32 = (float)((W + 3.0 * C.h) * 0x1p-20);
-    double ctr[3];
-    region_centre(geoms[q], ctr);
-    C.ox = ctr[0] - 0.5 * W;
-    C.oy = ctr[1] - 0.5 * W;
-    C.oz = ctr[2] - 0.5 * W;
-    C.salt = (uint32_t)q * 0x9E3779B1u;
-    rc[q] = C;
-    sum += cell_count(nc);
-  }
-  s_sum[t] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint64_t add = t >= o ? s_sum[t - o] : 0;
-    __syncthreads();
-    s_sum[t] += add;
-    __syncthreads();
-  }
-  uint64_t run = s_sum[t] - sum;
-  for (int i = 0; i < per; ++i) {
-    const int q = t * per + i;
-    if (q >= n_sub) break;
-    rc[q].base = (uint32_t)run;
-    run += cell_count(rc[q].nc);
-  }
+  rcells_update(geoms, n_sub, rext, rc, h_set, ctrl, s_sum);
 }
 
 // ---------------------------------------------------------------------------------
@@ -2404,42 +3142,110 @@ __global__ __launch_bounds__(NT) void k_cand_ids(const int2* __restrict__ cand, 
   out[2 * i + 1] = a < b ? b : a;
 }
 
-__global__ __launch_bounds__(NT) void k_iota(int32_t* __restrict__ idx, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
-  if (i < n) idx[i] = (int32_t)i;
+
+// Sort of a batch's event log into listing order per sub-region: (sub-region, step,
+// t*, id_a, id_b), a total order (a pair of elements meets at most once per step). A
+// bitonic sort over a power-of-two array of 24-byte keys: hi = (sub-region << 32 | step),
+// mid = order key of t*, and the event's index, whose ids decide equal (hi, mid).
+struct EvKey {
+  uint64_t hi, mid;
+  int32_t idx;
+  int32_t pad;
+};
+constexpr int EVS_LDS = 1024;  // keys sorted in LDS per workgroup (strides below this)
+
+__device__ __forceinline__ bool evkey_less(const EvKey& x, const EvKey& y,
+                                           const semipar_event* __restrict__ log) {
+  if (x.hi != y.hi) return x.hi < y.hi;
+  if (x.mid != y.mid) return x.mid < y.mid;
+  if (x.idx < 0 || y.idx < 0) return x.idx > y.idx;  // padding (idx -1) sorts last
+  const semipar_event& a = log[x.idx];
+  const semipar_event& b = log[y.idx];
+  if (a.id_a != b.id_a) return a.id_a < b.id_a;
+  return a.id_b < b.id_b;
 }
 
-// Sort key of pass `pass` for the events in the current order idx (least significant
-// first: id_b, id_a, t*, then sub-region and step).
 __global__ __launch_bounds__(NT) void k_ev_keys(const semipar_event* __restrict__ log,
-                                                const int32_t* __restrict__ lrid,
-                                                const int32_t* __restrict__ idx, int64_t n,
-                                                int pass, uint64_t* __restrict__ keys) {
+                                                const int32_t* __restrict__ lrid, int64_t n,
+                                                int64_t npow, EvKey* __restrict__ keys) {
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
-  if (i >= n) return;
-  const int32_t e = idx[i];
-  uint64_t k;
-  if (pass == 0)
-    k = (uint64_t)log[e].id_b;
-  else if (pass == 1)
-    k = (uint64_t)log[e].id_a;
-  else if (pass == 2)
-    k = order_key(log[e].t_star);
-  else
-    k = ((uint64_t)(uint32_t)lrid[e] << 32) | (uint32_t)log[e].step;
+  if (i >= npow) return;
+  EvKey k;
+  if (i < n) {
+    k.hi = ((uint64_t)(uint32_t)lrid[i] << 32) | (uint32_t)log[i].step;
+    k.mid = order_key(log[i].t_star);
+    k.idx = (int32_t)i;
+  } else {
+    k.hi = KEY_MAX;
+    k.mid = KEY_MAX;
+    k.idx = -1;
+  }
+  k.pad = 0;
   keys[i] = k;
+}
+
+// Compare-exchange of element i with i ^ j in the bitonic merge of size kk (ascending
+// where i & kk == 0).
+__device__ __forceinline__ void evkey_cx(EvKey* v, int64_t i, int64_t j, int64_t kk,
+                                         const semipar_event* __restrict__ log) {
+  const int64_t l = i ^ j;
+  if (l <= i) return;
+  const bool up = (i & kk) == 0;
+  const EvKey a = v[i], b = v[l];
+  const bool sw = up ? evkey_less(b, a, log) : evkey_less(a, b, log);
+  if (sw) {
+    v[i] = b;
+    v[l] = a;
+  }
+}
+
+// One global stage (stride j >= EVS_LDS) of the merge of size kk.
+__global__ __launch_bounds__(NT) void k_ev_bitonic(EvKey* __restrict__ keys, int64_t npow,
+                                                   int64_t kk, int64_t j,
+                                                   const semipar_event* __restrict__ log) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i < npow) evkey_cx(keys, i, j, kk, log);
+}
+
+// Every stage with stride below EVS_LDS, in LDS, for merges of size kk0 .. kk1 (kk1 <=
+// EVS_LDS: the whole sort of each block; kk0 = kk1 > EVS_LDS: the tail of one merge).
+__global__ __launch_bounds__(NT) void k_ev_bitonic_lds(EvKey* __restrict__ keys, int64_t kk0,
+                                                       int64_t kk1,
+                                                       const semipar_event* __restrict__ log) {
+  __shared__ EvKey v[EVS_LDS];
+  const int64_t base = (int64_t)blockIdx.x * EVS_LDS;
+  for (int i = threadIdx.x; i < EVS_LDS; i += NT) v[i] = keys[base + i];
+  __syncthreads();
+  for (int64_t kk = kk0; kk <= kk1; kk <<= 1) {
+    for (int64_t j = (kk > EVS_LDS ? EVS_LDS : kk) >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < EVS_LDS; i += NT) {
+        const int l = i ^ (int)j;
+        if (l > i) {
+          const bool up = ((base + i) & kk) == 0;
+          const EvKey a = v[i], b = v[l];
+          const bool sw = up ? evkey_less(b, a, log) : evkey_less(a, b, log);
+          if (sw) {
+            v[i] = b;
+            v[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < EVS_LDS; i += NT) keys[base + i] = v[i];
 }
 
 __global__ __launch_bounds__(NT) void k_ev_gather(const semipar_event* __restrict__ log,
                                                   const int32_t* __restrict__ lrid,
-                                                  const int32_t* __restrict__ idx, int64_t n,
+                                                  const EvKey* __restrict__ keys, int64_t n,
                                                   semipar_event* __restrict__ out,
                                                   int32_t* __restrict__ cnt) {
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
   const bool live = i < n;
   int32_t q = -1;
   if (live) {
-    const int32_t e = idx[i];
+    const int32_t e = keys[i].idx;
     out[i] = log[e];
     q = lrid[e];
   }
@@ -2492,6 +3298,19 @@ hipError_t dalloc(T** p, size_t count) {
 }
 
 inline int blocks(int64_t n, int nt = NT) { return (int)((n + nt - 1) / nt); }
+
+// Stream-ordered temporaries: allocated and released in order on one stream, so that
+// building a region never waits for other streams' work (hipFree would wait for the
+// whole device).
+template <class T>
+hipError_t salloc(T** p, size_t count, hipStream_t s) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMallocAsync((void**)p, sizeof(T) * count, s);
+}
+inline void sfree(void* p, hipStream_t s) {
+  if (p) (void)hipFreeAsync(p, s);
+}
 
 }  // namespace
 
@@ -2551,7 +3370,10 @@ struct semipar_region {
   int g_steps = 0;
   int g_timed = -1;
   bool cells_set = false;  // the device grid has been chosen (adaptive runs keep it)
-  int split = N_PENCIL;    // screen threads per element (1 or 5)
+  int split = N_PENCIL;    // screen variant: threads per element (1 or 5), or SPLIT_PRE
+  PencilAux* saux = nullptr;  // SPLIT_PRE: neighbour pencils of each sorted element
+  int64_t* dsub_off = nullptr;  // persistent launches: first slot of each sub-region
+  int32_t* pb_head = nullptr;   // persistent launches: the next sub-region to take
   bool cells_fixed = false;
   // measurement: HIP events around every launch of one kernel (timed_kernel)
   int timed = -1;
@@ -2589,6 +3411,8 @@ void free_step_buffers(semipar_region* r) {
   dfree(r->best);
   dfree(r->used);
   dfree(r->evs);
+  dfree(r->saux);
+  r->saux = nullptr;
   r->ebox = nullptr;
   r->ecell = r->epos = r->cnt = r->loc = r->tile_tot = r->toff = r->used = nullptr;
   r->sent = nullptr;
@@ -2672,8 +3496,8 @@ int configure(semipar_region* r, const semipar_evolve_params* p) {
   HIPCHK(dalloc(&r->toff, (size_t)r->ntiles + 1));
   HIPCHK(dalloc(&r->sent, cap));
   HIPCHK(hipMalloc(&r->sbox, (size_t)cap * 8 * (screen == 1 ? sizeof(double) : sizeof(float))));
-  HIPCHK(hipMemset(r->cnt, 0, sizeof(int32_t) * r->hc.B));
-  HIPCHK(hipMemset(r->loc, 0, sizeof(int32_t) * ((size_t)r->hc.B + 1)));
+  HIPCHK(hipMemsetAsync(r->cnt, 0, sizeof(int32_t) * r->hc.B, r->stream));
+  HIPCHK(hipMemsetAsync(r->loc, 0, sizeof(int32_t) * ((size_t)r->hc.B + 1), r->stream));
   r->cap_cand = std::max(want_cand, old_cand);
   r->cap_evt = std::max(want_evt, old_evt);
   if (r->cap_cand > INT32_MAX / 2) r->cap_cand = INT32_MAX / 2;
@@ -2683,10 +3507,11 @@ int configure(semipar_region* r, const semipar_evolve_params* p) {
   HIPCHK(dalloc(&r->evs, r->cap_evt));
   HIPCHK(dalloc(&r->best, cap));
   HIPCHK(dalloc(&r->used, cap));
-  HIPCHK(hipMemset(r->best, 0, sizeof(uint64_t) * cap));
-  HIPCHK(hipMemset(r->used, 0, sizeof(int32_t) * cap));
+  HIPCHK(hipMemsetAsync(r->best, 0, sizeof(uint64_t) * cap, r->stream));
+  HIPCHK(hipMemsetAsync(r->used, 0, sizeof(int32_t) * cap, r->stream));
   r->screen = screen;
-  HIPCHK(hipDeviceSynchronize());
+  // the region's own stream only: other regions' work on other streams goes on
+  HIPCHK(hipStreamSynchronize(r->stream));
   return SEMIPAR_OK;
 }
 
@@ -2777,8 +3602,21 @@ void launch_screen_t(semipar_region* r, int n, int nb) {
       r->P, r->cand, (int)r->cap_cand, r->ctrl, r->rid, r->rcell);
 }
 
-// Screen launch: precision (FP64 / FP32 boxes) and threads per element (1 or 5).
+template <int SCR>
+void launch_screen_pre_t(semipar_region* r, int n, int nb) {
+  k_screen_pre<SCR><<<xcd_grid(std::min(nb, SCREEN_GRID)), NT, 0, r->stream>>>(
+      n, r->sent, r->sbox, r->ebox, r->saux, r->loc, r->toff, r->ntiles, r->large, r->hc, r->P,
+      r->cand, (int)r->cap_cand, r->ctrl, r->rid, r->rcell, r->nxt, r->prv);
+}
+
+// Screen launch: precision (FP64 / FP32 boxes) and variant (one or five threads per
+// element, or pencils precomputed by k_scatter).
 void launch_screen(semipar_region* r, int n, int nb) {
+  if (r->split == SPLIT_PRE) {
+    if (r->screen == 1) launch_screen_pre_t<1>(r, n, nb);
+    else launch_screen_pre_t<2>(r, n, nb);
+    return;
+  }
   const bool one = r->split == 1;
   if (r->screen == 1) {
     if (one) launch_screen_t<1, 1>(r, n, nb);
@@ -2803,16 +3641,18 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
   mark(r, SEMIPAR_K_EVOLVE, 2 * i + 1);
   if (intercommute) {
     mark(r, SEMIPAR_K_SCAN, 2 * i);
-    k_scan<<<r->ntiles, 256, 0, s>>>(r->cnt, r->loc, r->tile_tot, r->ctrl);
+    k_scan<<<r->ntiles, 256, 0, s>>>(r->cnt, r->loc, r->tile_tot, r->ntiles, r->toff, r->ctrl);
     mark(r, SEMIPAR_K_SCAN, 2 * i + 1);
     mark(r, SEMIPAR_K_SCATTER, 2 * i);
-    k_toff<<<1, 1024, 0, s>>>(r->tile_tot, r->ntiles, r->toff, r->ctrl);
+    PencilAux* saux = r->split == SPLIT_PRE ? r->saux : nullptr;
     if (r->screen == 1)
       k_scatter<1><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
-                                      r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl);
+                                      r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl, saux,
+                                      r->nxt, r->prv);
     else
       k_scatter<2><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
-                                      r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl);
+                                      r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl, saux,
+                                      r->nxt, r->prv);
     mark(r, SEMIPAR_K_SCATTER, 2 * i + 1);
     mark(r, SEMIPAR_K_SCREEN, 2 * i);
     launch_screen(r, n, nb);
@@ -2823,12 +3663,92 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
     mark(r, SEMIPAR_K_CONFIRM, 2 * i + 1);
   }
   mark(r, SEMIPAR_K_RESOLVE, 2 * i);
-  k_resolve<<<1, RESOLVE_NT, 0, s>>>(r->nxt, r->prv, r->ev, (int)r->cap_evt, (int)r->cap_cand,
+  // one workgroup per group of sub-regions (their events never share an element)
+  const int ngrp = r->rid ? std::max(1, std::min<int>(r->n_sub, RES_GROUPS)) : 1;
+  k_resolve<<<ngrp, RESOLVE_NT, 0, s>>>(r->nxt, r->prv, r->ev, (int)r->cap_evt, (int)r->cap_cand,
                                      r->best, r->used, r->evs, r->log, r->log_cap, r->blkred, nbe,
-                                     r->ctrl, r->rid, r->log_rid, r->lev, r->p_ic, r->seed);
-  if (intercommute && r->rcell)
-    k_rcells<<<1, 1024, 0, s>>>(r->geoms, r->n_sub, r->rext, r->rcell, r->rc_fixed_h, r->ctrl);
+                                     r->ctrl, r->rid, r->log_rid, r->lev, r->p_ic, r->seed,
+                                     r->geoms, r->n_sub, r->rext,
+                                     intercommute ? r->rcell : nullptr, r->rc_fixed_h);
   mark(r, SEMIPAR_K_RESOLVE, 2 * i + 1);
+}
+
+int read_ctrl(semipar_region* r);
+
+// A batch can be evolved by persistent workgroups when every sub-region is small, the
+// call runs to the regions' own stop (no loop removal, no time limit) and no kernel is
+// being timed.
+bool persistent_ok(const semipar_region* r, const semipar_evolve_params* p) {
+  if (r->n_sub <= 0 || !r->rid || !p->intercommute || p->loop_every != 0 ||
+      p->timed_kernel >= 0 || !std::isinf(p->t_end) || r->removed)
+    return false;
+  for (int q = 0; q < r->n_sub; ++q)
+    if (r->sub_off[q + 1] - r->sub_off[q] > PB_MAXP) return false;
+  return true;
+}
+
+// Evolve every sub-region of a batch of small regions to its own stop in one launch of
+// persistent workgroups (k_region_block). A step with more crossings than a workgroup
+// holds, or a full event log, gives SEMIPAR_E_OVERFLOW and leaves the region unusable:
+// it is then run again from its surfaces on the step kernels.
+int evolve_persistent(semipar_region* r, const semipar_evolve_params* p,
+                      semipar_evolve_stats* st, const Ctrl& before, int32_t step_limit) {
+  const int ns = r->n_sub;
+  if (!r->dsub_off) {
+    HIPCHK(dalloc(&r->dsub_off, (size_t)ns + 1));
+    HIPCHK(dalloc(&r->pb_head, 1));
+    HIPCHK(hipMemcpyAsync(r->dsub_off, r->sub_off.data(), sizeof(int64_t) * ((size_t)ns + 1),
+                          hipMemcpyHostToDevice, r->stream));
+  }
+  // room for many more events than such regions have (about one per six points over a
+  // whole run); the launch stops cleanly if the log fills anyway
+  RCCHK(ensure_log(r, r->ctrl_h->log_n + 8 * r->n + 65536));
+  drop_graph(r);
+  HIPCHK(hipMemsetAsync(r->pb_head, 0, sizeof(int32_t), r->stream));
+  HIPCHK(hipEventRecord(r->ev0, r->stream));
+  const int grid = std::min(ns, PB_GRID);
+  if (r->cosmology != SEMIPAR_FLAT)
+    k_region_block<true><<<grid, PB_NT, 0, r->stream>>>(
+        r->X, r->nxt, r->prv, r->id, r->fstep, r->face, r->frz, r->lev, r->geoms, r->dsub_off,
+        ns, r->pb_head, r->P, r->hcoef, before.step, step_limit, r->p_ic, r->seed, r->log,
+        r->log_rid, r->log_cap, r->ctrl);
+  else
+    k_region_block<false><<<grid, PB_NT, 0, r->stream>>>(
+        r->X, r->nxt, r->prv, r->id, r->fstep, r->face, r->frz, r->lev, r->geoms, r->dsub_off,
+        ns, r->pb_head, r->P, r->hcoef, before.step, step_limit, r->p_ic, r->seed, r->log,
+        r->log_rid, r->log_cap, r->ctrl);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(r->ev1, r->stream));
+  RCCHK(read_ctrl(r));
+  Ctrl c = *r->ctrl_h;
+  if (c.err & 64) {
+    r->broken = true;
+    spi::set_error("region_evolve: a step of a persistent region held more crossings than its "
+                   "workgroup keeps, or the event log filled; run the regions on the step kernels");
+    return SEMIPAR_E_OVERFLOW;
+  }
+  const int32_t fs = std::max(c.pb_step, before.step);
+  c.steps_taken += fs - before.step;
+  c.step = fs;
+  c.pb_step = 0;
+  c.done = 1;
+  *r->ctrl_h = c;
+  HIPCHK(hipMemcpyAsync(r->ctrl, r->ctrl_h, sizeof(Ctrl), hipMemcpyHostToDevice, r->stream));
+  HIPCHK(hipStreamSynchronize(r->stream));
+  if (st) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r->ev0, r->ev1);
+    st->steps = fs - before.step;
+    st->point_steps = c.point_steps - before.point_steps;
+    st->candidates = c.cand_total - before.cand_total;
+    st->confirmed = c.conf_total - before.conf_total;
+    st->accepted = c.acc_total - before.acc_total;
+    st->passed = c.pass_total - before.pass_total;
+    st->final_step = fs;
+    st->done = 1;
+    st->elapsed_ms = ms;
+  }
+  return SEMIPAR_OK;
 }
 
 int read_ctrl(semipar_region* r) {
@@ -2986,6 +3906,8 @@ void region_destroy(semipar_region* r) {
   dfree(r->rcell);
   dfree(r->rext);
   dfree(r->lev);
+  dfree(r->dsub_off);
+  dfree(r->pb_head);
   for (int i = 0; i < 2; ++i) {
     dfree(r->lab[i]);
     dfree(r->lptr[i]);
@@ -3109,15 +4031,15 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
     if (total > 0) {
       // sub-region of each slot, filled on the device from the sub-region offsets
       int64_t* doff = nullptr;
-      if (dalloc(&doff, (size_t)n_in + 1) != hipSuccess) return fail(SEMIPAR_E_OOM);
+      if (salloc(&doff, (size_t)n_in + 1, r->stream) != hipSuccess) return fail(SEMIPAR_E_OOM);
       const bool ok =
-          hipMemcpy(doff, r->sub_off.data(), sizeof(int64_t) * ((size_t)n_in + 1),
-                    hipMemcpyHostToDevice) == hipSuccess;
+          hipMemcpyAsync(doff, r->sub_off.data(), sizeof(int64_t) * ((size_t)n_in + 1),
+                         hipMemcpyHostToDevice, r->stream) == hipSuccess;
       if (ok)
         k_fill_rid<<<blocks(total), NT, 0, r->stream>>>(r->rid, (int)total, doff, n_in);
       const bool ok2 = ok && hipGetLastError() == hipSuccess &&
                        hipStreamSynchronize(r->stream) == hipSuccess;
-      dfree(doff);
+      sfree(doff, r->stream);
       if (!ok2) return fail(SEMIPAR_E_HIP);
     }
   }
@@ -3136,7 +4058,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
   if (total > 0) {
     // gather all surfaces into one device record array
     semipar_point_rec* drec = nullptr;
-    if (dalloc(&drec, total) != hipSuccess) return fail(SEMIPAR_E_OOM);
+    if (salloc(&drec, total, r->stream) != hipSuccess) return fail(SEMIPAR_E_OOM);
     int64_t off = 0;
     for (int i = 0; i < n_in; ++i) {
       if (in[i].n == 0) continue;
@@ -3144,7 +4066,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
           in[i].mem == SEMIPAR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
       if (hipMemcpyAsync(drec + off, in[i].recs, sizeof(semipar_point_rec) * in[i].n, kind,
                          r->stream) != hipSuccess) {
-        dfree(drec);
+        sfree(drec, r->stream);
         return fail(SEMIPAR_E_HIP);
       }
       off += in[i].n;
@@ -3152,7 +4074,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
     semipar_point_rec rec0;
     if (hipMemcpyAsync(&rec0, drec, sizeof(rec0), hipMemcpyDeviceToHost, r->stream) != hipSuccess ||
         hipStreamSynchronize(r->stream) != hipSuccess) {
-      dfree(drec);
+      sfree(drec, r->stream);
       return fail(SEMIPAR_E_HIP);
     }
     c0.step = rec0.step;
@@ -3160,10 +4082,11 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
     const uint64_t hcap = next_pow2(2 * (uint64_t)total);
     int64_t* hkey = nullptr;
     int32_t* hval = nullptr;
-    if (dalloc(&hkey, hcap) != hipSuccess || dalloc(&hval, hcap) != hipSuccess) {
-      dfree(drec);
-      dfree(hkey);
-      dfree(hval);
+    if (salloc(&hkey, hcap, r->stream) != hipSuccess ||
+        salloc(&hval, hcap, r->stream) != hipSuccess) {
+      sfree(drec, r->stream);
+      sfree(hkey, r->stream);
+      sfree(hval, r->stream);
       return fail(SEMIPAR_E_OOM);
     }
     const int n = (int)total;
@@ -3182,9 +4105,9 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
     }
     if (rc == SEMIPAR_OK && read_ctrl(r) != SEMIPAR_OK) rc = SEMIPAR_E_HIP;
-    dfree(drec);
-    dfree(hkey);
-    dfree(hval);
+    sfree(drec, r->stream);
+    sfree(hkey, r->stream);
+    sfree(hval, r->stream);
     if (rc != SEMIPAR_OK) return fail(rc);
     if (r->ctrl_h->err != 0) return fail(SEMIPAR_E_SURFACE);
     r->ext0 = from_key(r->ctrl_h->ext_key);
@@ -3219,14 +4142,20 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   const Ctrl before = *r->ctrl_h;
   const int64_t lim64 = (int64_t)before.step + p->max_steps;
   const int32_t step_limit = (int32_t)std::min<int64_t>(lim64, INT32_MAX - 1);
+  if (p->persistent && persistent_ok(r, p)) return evolve_persistent(r, p, st, before, step_limit);
   const int n = (int)r->n;
   const bool ic = p->intercommute != 0;
   const int K = p->steps_per_sync > 0 ? p->steps_per_sync : 32;
   {
     const int sp_ = p->screen_split;
-    const int split = sp_ == 1 ? 1 : N_PENCIL;
+    const int split = sp_ == 1 ? 1 : (sp_ == SPLIT_PRE ? SPLIT_PRE : N_PENCIL);
     if (split != r->split) drop_graph(r);
     r->split = split;
+    if (split == SPLIT_PRE && !r->saux) {
+      drop_graph(r);
+      if (dalloc(&r->saux, (size_t)std::max<int64_t>(r->cap, 1)) != hipSuccess)
+        return SEMIPAR_E_OOM;
+    }
     if (p_ic != r->p_ic || p->seed != r->seed) drop_graph(r);
     r->p_ic = p_ic;
     r->seed = p->seed;
@@ -3663,59 +4592,46 @@ int batch_events(semipar_region* r, std::vector<semipar_event>& ev, std::vector<
   const int64_t total = r->ctrl_h->log_n;
   if (total == 0) return SEMIPAR_OK;
   if (total >= INT32_MAX) return SEMIPAR_E_OVERFLOW;
-  // LSD radix sorts (stable) on the device: id_b, id_a, t*, then (sub-region, step)
-  const int n = (int)total;
-  int32_t *ia = nullptr, *ib = nullptr, *cnt = nullptr;
-  uint64_t *ka = nullptr, *kb = nullptr;
+  // the project's bitonic sort on the device (see k_ev_keys)
+  int64_t npow = EVS_LDS;
+  while (npow < total) npow <<= 1;
+  EvKey* keys = nullptr;
+  int32_t* cnt = nullptr;
   semipar_event* sorted = nullptr;
-  void* tmp = nullptr;
-  size_t tmp_bytes = 0;
   int rc = SEMIPAR_OK;
-  if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, ka, kb, ia, ib, n, 0, 64,
-                                         r->stream) != hipSuccess)
-    rc = SEMIPAR_E_HIP;
-  if (rc == SEMIPAR_OK &&
-      (dalloc(&ia, total) != hipSuccess || dalloc(&ib, total) != hipSuccess ||
-       dalloc(&ka, total) != hipSuccess || dalloc(&kb, total) != hipSuccess ||
-       dalloc(&sorted, total) != hipSuccess || dalloc(&cnt, ns) != hipSuccess ||
-       hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)) != hipSuccess))
+  if (dalloc(&keys, npow) != hipSuccess || dalloc(&sorted, total) != hipSuccess ||
+      dalloc(&cnt, ns) != hipSuccess)
     rc = SEMIPAR_E_OOM;
   std::vector<int32_t> hc((size_t)ns, 0);
   if (rc == SEMIPAR_OK) {
-    const int nb = blocks(total);
-    k_iota<<<nb, NT, 0, r->stream>>>(ia, total);
-    for (int pass = 0; pass < 4 && rc == SEMIPAR_OK; ++pass) {
-      k_ev_keys<<<nb, NT, 0, r->stream>>>(r->log, r->log_rid, ia, total, pass, ka);
-      const int end_bit = pass == 2 ? 64 : (pass == 3 ? 64 : 63);
-      size_t tb = tmp_bytes;
-      if (hipcub::DeviceRadixSort::SortPairs(tmp, tb, ka, kb, ia, ib, n, 0, end_bit,
-                                             r->stream) != hipSuccess)
-        rc = SEMIPAR_E_HIP;
-      std::swap(ia, ib);
+    const int nbp = blocks(npow);
+    hipStream_t st = r->stream;
+    k_ev_keys<<<nbp, NT, 0, st>>>(r->log, r->log_rid, total, npow, keys);
+    k_ev_bitonic_lds<<<(int)(npow / EVS_LDS), NT, 0, st>>>(keys, 2, EVS_LDS, r->log);
+    for (int64_t kk = 2 * EVS_LDS; kk <= npow; kk <<= 1) {
+      for (int64_t j = kk >> 1; j >= EVS_LDS; j >>= 1)
+        k_ev_bitonic<<<nbp, NT, 0, st>>>(keys, npow, kk, j, r->log);
+      k_ev_bitonic_lds<<<(int)(npow / EVS_LDS), NT, 0, st>>>(keys, kk, kk, r->log);
     }
-    if (rc == SEMIPAR_OK &&
-        hipMemsetAsync(cnt, 0, sizeof(int32_t) * ns, r->stream) != hipSuccess)
+    if (hipGetLastError() != hipSuccess ||
+        hipMemsetAsync(cnt, 0, sizeof(int32_t) * ns, st) != hipSuccess)
       rc = SEMIPAR_E_HIP;
     if (rc == SEMIPAR_OK) {
-      k_ev_gather<<<nb, NT, 0, r->stream>>>(r->log, r->log_rid, ia, total, sorted, cnt);
+      k_ev_gather<<<blocks(total), NT, 0, st>>>(r->log, r->log_rid, keys, total, sorted, cnt);
       ev.resize((size_t)total);
       if (hipGetLastError() != hipSuccess ||
           hipMemcpyAsync(ev.data(), sorted, sizeof(semipar_event) * total, hipMemcpyDeviceToHost,
-                         r->stream) != hipSuccess ||
-          hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * ns, hipMemcpyDeviceToHost,
-                         r->stream) != hipSuccess ||
-          hipStreamSynchronize(r->stream) != hipSuccess)
+                         st) != hipSuccess ||
+          hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
         rc = SEMIPAR_E_HIP;
     }
   }
   for (int q = 0; q < ns; ++q) off[q + 1] = off[q] + hc[q];
-  dfree(ia);
-  dfree(ib);
-  dfree(ka);
-  dfree(kb);
+  dfree(keys);
   dfree(sorted);
   dfree(cnt);
-  dfree(tmp);
   if (rc != SEMIPAR_OK) ev.clear();
   return rc;
 }

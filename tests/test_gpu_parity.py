@@ -159,7 +159,7 @@ def test_radiation_era_parity(S):
     assert_same_state(g, o)
 
 
-@pytest.mark.parametrize("split", [1, 5, 7])
+@pytest.mark.parametrize("split", [1, 2, 5, 7])
 def test_screen_split_variants(S, split):
     say(f"case: VV 8^3 seed 2, matter era, 150 steps, screen split {split}")
     net = I.vv_network(m=8, seed=2)
@@ -486,3 +486,21 @@ def test_buffer_overflow_retakes_step_batch(S):
         assert_same_events(ev, oe)
         assert_same_records(mine, o)
         assert res["region_point_steps"][r] == ost["point_steps"]
+
+
+@pytest.mark.parametrize("screen", [0, 1])
+def test_precomputed_pencil_screen_bounded_and_wrapping(S, screen):
+    """The screen variant whose pencil ranges are written by the bucket sort: a bounded
+    region (local grid, no wrap) and a whole-volume network in a small periodic box
+    (the z-pencils wrap, so some pencils are looked up cell by cell) equal the oracle."""
+    say(f"case: precomputed pencils, screen {screen}: bounded ~3000 seed 2; VV 4^3 seed 1")
+    net = I.region_network(3000, 4.0, seed=2)
+    faces, ge, st = run_gpu_region(S, net, screen=screen, screen_split=2, use_graph=True)
+    o, oe, ost = run_oracle(net, 100000)
+    assert_same_events(ge, oe)
+    assert_same_records(np.concatenate(faces), o)
+    small = I.vv_network(m=4, seed=1)
+    g, ge, st = run_gpu(S, small, 200, screen=screen, screen_split=2)
+    o, oe, _ = run_oracle(small, 200)
+    assert_same_events(ge, oe)
+    assert_same_state(g, o)

@@ -72,7 +72,7 @@ SIZES = [0, 300, 5000, 1200, 0, 20000, 800, 2500, 40, 9000, 150, 3000]
 
 
 @pytest.mark.parametrize("case", ["plain", "batched-heuristic", "batched-cost", "one-batch-f32",
-                                  "lanes", "work-packing"])
+                                  "lanes", "work-packing", "precomputed-pencils"])
 def test_schedule_policies_equal_oracle_region_by_region(S, case):
     say(f"case: schedule_regions {case}, sizes {SIZES}, seed 200")
     parts, box = I.region_batch(SIZES, seed=200)
@@ -120,6 +120,11 @@ def test_schedule_policies_equal_oracle_region_by_region(S, case):
                 want.append(want[-1])
             done += w
         assert [x - b[0] for x in b] == want
+    elif case == "precomputed-pencils":
+        # the screen variant reading pencil ranges written by the bucket sort
+        res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=6000, use_graph=True,
+                                 screen=S.SCREEN_F32, screen_split=2, lanes=2)
+        assert res["stats"]["batches"] >= 4
     elif case == "lanes":
         # batches evolved concurrently by three host threads on streams of their own
         res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=6000, use_graph=True,
