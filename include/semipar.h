@@ -523,6 +523,20 @@ int semipar_mlp_loss_grad(const float* params, const float* norm, const float* x
                           const float* target, int64_t n, float* grad, float* loss,
                           void* stream);
 
+/* The same loss and gradient without allocating anything, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). The per-block partial gradients live in a fixed array of
+ * device memory that the library holds on each GPU it runs on until the process ends
+ * (about 5 MB). Every call on one GPU uses that same array, so calls that overlap on
+ * one GPU (different streams or threads) race and give wrong results: issue them one
+ * after another. Results equal semipar_mlp_loss_grad's. n above
+ * SEMIPAR_MLP_NOALLOC_MAX gives SEMIPAR_E_ARG (semipar_last_error says why), nothing
+ * launched. Errors otherwise as semipar_mlp_loss_grad. */
+#define SEMIPAR_MLP_NOALLOC_MAX 8192
+int semipar_mlp_loss_grad_noalloc(const float* params, const float* norm, const float* x,
+                                  const float* target, int64_t n, float* grad, float* loss,
+                                  void* stream);
+
 /* One Adam update (Kingma and Ba) at 1-based step number `step`:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * params -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */

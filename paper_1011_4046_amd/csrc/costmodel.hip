@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -186,6 +187,37 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ p, float* 
 
 int grad_blocks(int64_t n) { return (int)((n + GB - 1) / GB); }
 
+// Per-block gradient parts of semipar_mlp_loss_grad_noalloc: a fixed array in device
+// memory, one per GPU the library runs on, held until the process ends. Every call on
+// one GPU shares it (each call overwrites the parts of its own blocks before reading
+// them, so nothing needs clearing between calls).
+constexpr int64_t NOALLOC_MAX_SAMPLES = SEMIPAR_MLP_NOALLOC_MAX;
+constexpr int NOALLOC_MAX_BLOCKS = (int)((NOALLOC_MAX_SAMPLES + GB - 1) / GB);
+__device__ __align__(256) float scratch[(size_t)NOALLOC_MAX_BLOCKS * (NP + 1)];
+
+// Device address of `scratch` on each GPU (the host-side name is only a stand-in),
+// looked up once per device with that device current.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_on_current_device(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SEMIPAR_E_HIP;
+  if (dev < 0 || dev >= MAX_DEVICES) return SEMIPAR_E_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      spi::set_error("hipGetSymbolAddress(scratch) failed in semipar_mlp_loss_grad_noalloc");
+      return SEMIPAR_E_HIP;
+    }
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SEMIPAR_OK;
+}
+
 struct Scratch {
   float* part = nullptr;
   float* grad = nullptr;
@@ -227,6 +259,24 @@ int semipar_mlp_loss_grad(const float* params, const float* norm, const float* x
   if (hipMalloc(&w.part, sizeof(float) * (NP + 1) * (size_t)grad_blocks(n)) != hipSuccess)
     return SEMIPAR_E_OOM;
   int rc = launch_grad(params, norm, x, target, n, w.part, grad, loss, s);
+  if (rc == SEMIPAR_OK && hipStreamSynchronize(s) != hipSuccess) rc = SEMIPAR_E_HIP;
+  return rc;
+}
+
+int semipar_mlp_loss_grad_noalloc(const float* params, const float* norm, const float* x,
+                                  const float* target, int64_t n, float* grad, float* loss,
+                                  void* stream) {
+  if (!params || !grad || n <= 0 || !x || !target) return SEMIPAR_E_ARG;
+  if (n > NOALLOC_MAX_SAMPLES) {
+    spi::set_error("semipar_mlp_loss_grad_noalloc: more samples than its fixed scratch "
+                   "holds (SEMIPAR_MLP_NOALLOC_MAX)");
+    return SEMIPAR_E_ARG;
+  }
+  float* part = nullptr;
+  int rc = scratch_on_current_device(&part);
+  if (rc != SEMIPAR_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = launch_grad(params, norm, x, target, n, part, grad, loss, s);
   if (rc == SEMIPAR_OK && hipStreamSynchronize(s) != hipSuccess) rc = SEMIPAR_E_HIP;
   return rc;
 }

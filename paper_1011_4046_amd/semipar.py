@@ -128,7 +128,8 @@ PERSISTENT_EVENTS = 160  # SEMIPAR_PERSISTENT_EVENTS
 SYMBOLS = ["region_init_from_surfaces", "region_evolve", "region_emit_final_surfaces",
            "region_events", "region_candidates", "region_loops", "region_destroy", "semipar_strerror", "semipar_version",
            "semipar_last_error", "schedule_regions", "semipar_region_features",
-           "semipar_mlp_forward", "semipar_mlp_loss_grad", "semipar_mlp_adam_step",
+           "semipar_mlp_forward", "semipar_mlp_loss_grad", "semipar_mlp_loss_grad_noalloc",
+           "semipar_mlp_adam_step",
            "semipar_mlp_train", "semipar_mlp_norm"]
 
 _lib = None
@@ -173,6 +174,8 @@ def lib():
         L.semipar_mlp_forward.restype = ctypes.c_int
         L.semipar_mlp_loss_grad.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P]
         L.semipar_mlp_loss_grad.restype = ctypes.c_int
+        L.semipar_mlp_loss_grad_noalloc.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P]
+        L.semipar_mlp_loss_grad_noalloc.restype = ctypes.c_int
         L.semipar_mlp_adam_step.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
         L.semipar_mlp_adam_step.restype = ctypes.c_int
@@ -556,6 +559,18 @@ class CostModel:
                                            self._np(td), len(x), self._np(g), self._np(l),
                                            _current_stream()), "mlp_loss_grad")
         return float(l.cpu()[0]), g.cpu().numpy()
+
+    def loss_grad_noalloc(self, x, target, grad=None, loss=None):
+        """The same through semipar_mlp_loss_grad_noalloc: the library allocates
+        nothing. x, target (and the optional outputs grad, loss) are device tensors
+        the caller owns; returns (grad, loss) device tensors."""
+        T = self.torch
+        g = grad if grad is not None else T.empty(MLP_PARAMS, dtype=T.float32, device="cuda")
+        l = loss if loss is not None else T.empty(1, dtype=T.float32, device="cuda")
+        _check(lib().semipar_mlp_loss_grad_noalloc(
+            self._np(self.params), self._np(self.norm), self._np(x), self._np(target), len(x),
+            self._np(g), self._np(l), _current_stream()), "mlp_loss_grad_noalloc")
+        return g, l
 
     def adam_step(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         gd = self._dev(grad)
