@@ -241,6 +241,7 @@ extern "C" {
 
 int semipar_mlp_forward(const float* params, const float* norm, const float* x, int64_t n,
                         float* y, void* stream) {
+  spi::begin_call();
   if (!params || n < 0 || n > MAX_SAMPLES || (n > 0 && (!x || !y))) return SEMIPAR_E_ARG;
   if (n == 0) return SEMIPAR_OK;
   hipStream_t s = (hipStream_t)stream;
@@ -253,6 +254,7 @@ int semipar_mlp_forward(const float* params, const float* norm, const float* x, 
 int semipar_mlp_loss_grad(const float* params, const float* norm, const float* x,
                           const float* target, int64_t n, float* grad, float* loss,
                           void* stream) {
+  spi::begin_call();
   if (!params || !grad || n <= 0 || n > MAX_SAMPLES || !x || !target) return SEMIPAR_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   Scratch w;
@@ -266,6 +268,7 @@ int semipar_mlp_loss_grad(const float* params, const float* norm, const float* x
 int semipar_mlp_loss_grad_noalloc(const float* params, const float* norm, const float* x,
                                   const float* target, int64_t n, float* grad, float* loss,
                                   void* stream) {
+  spi::begin_call();
   if (!params || !grad || n <= 0 || !x || !target) return SEMIPAR_E_ARG;
   if (n > NOALLOC_MAX_SAMPLES) {
     spi::set_error("semipar_mlp_loss_grad_noalloc: more samples than its fixed scratch "
@@ -283,6 +286,7 @@ int semipar_mlp_loss_grad_noalloc(const float* params, const float* norm, const 
 
 int semipar_mlp_adam_step(float* params, float* m, float* v, const float* grad, int64_t step,
                           float lr, float beta1, float beta2, float eps, void* stream) {
+  spi::begin_call();
   if (!params || !m || !v || !grad || step < 1) return SEMIPAR_E_ARG;
   if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
     return SEMIPAR_E_ARG;
@@ -298,6 +302,7 @@ int semipar_mlp_adam_step(float* params, float* m, float* v, const float* grad, 
 int semipar_mlp_train(float* params, float* m, float* v, const float* norm, const float* x,
                       const float* target, int64_t n, int32_t iters, int64_t step0, float lr,
                       float* loss_host, void* stream) {
+  spi::begin_call();
   if (!params || !m || !v || !x || !target || n <= 0 || n > MAX_SAMPLES || iters < 0 || step0 < 0)
     return SEMIPAR_E_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -331,6 +336,7 @@ int semipar_mlp_train(float* params, float* m, float* v, const float* norm, cons
 }
 
 int semipar_mlp_norm(const float* x, int64_t n, float* norm) {
+  spi::begin_call();
   if (!x || !norm || n <= 0) return SEMIPAR_E_ARG;
   for (int j = 0; j < NI; ++j) {
     double mu = 0.0, m2 = 0.0;

@@ -50,4 +50,9 @@ SP_HIDDEN int surface_features(const semipar_tiling* t, float* feat);
 // Record an error message for semipar_last_error.
 SP_HIDDEN void set_error(const char* msg);
 
+// Start of an entry point: clears this thread's message and HIP's per-thread last
+// error, so that a failure left by an earlier call (the caller's own, or a release
+// whose result was ignored) is not taken for a failure of this call's launches.
+SP_HIDDEN void begin_call();
+
 }  // namespace spi

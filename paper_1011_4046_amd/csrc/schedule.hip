@@ -21,10 +21,12 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
 #include <numeric>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -38,6 +40,14 @@
   } while (0)
 
 namespace {
+
+// A failed HIP call: its text for semipar_last_error, and SEMIPAR_E_HIP.
+int hip_err(hipError_t e, const char* what) {
+  char msg[200];
+  snprintf(msg, sizeof(msg), "schedule_regions: %s failed: %s", what, hipGetErrorString(e));
+  spi::set_error(msg);
+  return SEMIPAR_E_HIP;
+}
 
 struct Slab {
   int64_t base = 0;  // first output record of the region
@@ -233,6 +243,7 @@ struct Runner {
     semipar_region* reg = nullptr;
     semipar_evolve_stats es{};
     int rc = SEMIPAR_OK;
+    std::string msg;    // the lane's error message when rc is not SEMIPAR_OK
     double cost = 0.0;  // predicted device time, for assigning batches to lanes
   };
 
@@ -262,8 +273,12 @@ struct Runner {
         if (tmp) (void)hipFree(tmp);
         tmp = nullptr;
         tmp_cap = 0;
-        if (hipMalloc(&tmp, sizeof(semipar_point_rec) * total) != hipSuccess) rc = SEMIPAR_E_OOM;
-        else tmp_cap = total;
+        if (hipMalloc(&tmp, sizeof(semipar_point_rec) * total) != hipSuccess) {
+          spi::set_error("schedule_regions: device allocation of the output staging failed");
+          rc = SEMIPAR_E_OOM;
+        } else {
+          tmp_cap = total;
+        }
       }
       std::vector<int64_t> cnt;
       if (rc == SEMIPAR_OK) rc = spi::batch_emit(reg, tmp, cnt);
@@ -433,10 +448,10 @@ struct Runner {
     const int nr = t->n_regions;
     const int lanes = std::max(1, p->lanes);
     std::vector<int32_t> hp((size_t)nr, 0), hoff((size_t)nr + 1, 0), hs;
-    std::vector<uint8_t> he((size_t)nr, 0);
+    std::vector<uint8_t> hempty((size_t)nr, 0);
     for (int r = 0; r < nr; ++r) {
       hp[r] = t->n_pred ? t->n_pred[r] : 0;
-      he[r] = t->surfaces[r].n == 0 ? 1 : 0;
+      hempty[r] = t->surfaces[r].n == 0 ? 1 : 0;
     }
     if (t->n_pred) {
       for (int r = 0; r <= nr; ++r) hoff[r] = t->succ_off[r] - t->succ_off[0];
@@ -444,15 +459,21 @@ struct Runner {
     }
     DagDev D;
     const size_t m = std::max<size_t>(hs.size(), 1);
-    if (hipMalloc(&D.pending, sizeof(int32_t) * std::max(nr, 1)) != hipSuccess ||
-        hipMalloc(&D.succ_off, sizeof(int32_t) * (nr + 1)) != hipSuccess ||
-        hipMalloc(&D.succ, sizeof(int32_t) * m) != hipSuccess ||
-        hipMalloc(&D.ring, sizeof(int32_t) * std::max(nr, 1)) != hipSuccess ||
-        hipMalloc(&D.ctr, sizeof(int32_t) * 2) != hipSuccess ||
-        hipMalloc(&D.work, sizeof(int32_t) * std::max(nr, 1)) != hipSuccess ||
-        hipMalloc(&D.fin, sizeof(int32_t) * std::max(nr, 1)) != hipSuccess ||
-        hipMalloc(&D.empty, std::max(nr, 1)) != hipSuccess)
-      return SEMIPAR_E_OOM;
+    hipError_t ae = hipSuccess;
+    if ((ae = hipMalloc(&D.pending, sizeof(int32_t) * std::max(nr, 1))) != hipSuccess ||
+        (ae = hipMalloc(&D.succ_off, sizeof(int32_t) * (nr + 1))) != hipSuccess ||
+        (ae = hipMalloc(&D.succ, sizeof(int32_t) * m)) != hipSuccess ||
+        (ae = hipMalloc(&D.ring, sizeof(int32_t) * std::max(nr, 1))) != hipSuccess ||
+        (ae = hipMalloc(&D.ctr, sizeof(int32_t) * 2)) != hipSuccess ||
+        (ae = hipMalloc(&D.work, sizeof(int32_t) * std::max(nr, 1))) != hipSuccess ||
+        (ae = hipMalloc(&D.fin, sizeof(int32_t) * std::max(nr, 1))) != hipSuccess ||
+        (ae = hipMalloc(&D.empty, std::max(nr, 1))) != hipSuccess) {
+      char msg[160];
+      snprintf(msg, sizeof(msg), "schedule_regions: device allocation of the ready queue failed: %s",
+               hipGetErrorString(ae));
+      spi::set_error(msg);
+      return ae == hipErrorOutOfMemory ? SEMIPAR_E_OOM : SEMIPAR_E_HIP;
+    }
     std::vector<hipStream_t> ls((size_t)lanes, nullptr);
     hipStream_t ms = nullptr;  // the queue's kernels and reads, in order
     hipEvent_t ready_ev = nullptr;
@@ -469,32 +490,38 @@ struct Runner {
       if (ready_ev) (void)hipEventDestroy(ready_ev);
     };
     int rc = SEMIPAR_OK;
-    if (hipStreamCreateWithFlags(&ms, hipStreamNonBlocking) != hipSuccess) rc = SEMIPAR_E_HIP;
+    hipError_t he = hipStreamCreateWithFlags(&ms, hipStreamNonBlocking);
+    if (he != hipSuccess) rc = hip_err(he, "queue stream");
     for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
-      if (hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking) != hipSuccess) rc = SEMIPAR_E_HIP;
+      if ((he = hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking)) != hipSuccess)
+        rc = hip_err(he, "lane stream");
     if (rc == SEMIPAR_OK && t->stream) {
       // device-resident surfaces may still be in flight on the caller's stream
-      if (hipEventCreateWithFlags(&ready_ev, hipEventDisableTiming) != hipSuccess ||
-          hipEventRecord(ready_ev, (hipStream_t)t->stream) != hipSuccess)
-        rc = SEMIPAR_E_HIP;
+      if ((he = hipEventCreateWithFlags(&ready_ev, hipEventDisableTiming)) != hipSuccess ||
+          (he = hipEventRecord(ready_ev, (hipStream_t)t->stream)) != hipSuccess)
+        rc = hip_err(he, "event on the caller's stream");
       for (int l = 0; l < lanes && rc == SEMIPAR_OK; ++l)
-        if (hipStreamWaitEvent(ls[l], ready_ev, 0) != hipSuccess) rc = SEMIPAR_E_HIP;
+        if ((he = hipStreamWaitEvent(ls[l], ready_ev, 0)) != hipSuccess)
+          rc = hip_err(he, "lane wait");
     }
     const int32_t zero2[2] = {0, 0};
     if (rc == SEMIPAR_OK &&
-        (hipMemcpyAsync(D.pending, hp.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ms) !=
+        ((he = hipMemcpyAsync(D.pending, hp.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice,
+                              ms)) != hipSuccess ||
+         (he = hipMemcpyAsync(D.succ_off, hoff.data(), sizeof(int32_t) * (nr + 1),
+                              hipMemcpyHostToDevice, ms)) != hipSuccess ||
+         (!hs.empty() && (he = hipMemcpyAsync(D.succ, hs.data(), sizeof(int32_t) * hs.size(),
+                                              hipMemcpyHostToDevice, ms)) != hipSuccess) ||
+         (he = hipMemcpyAsync(D.empty, hempty.data(), (size_t)nr, hipMemcpyHostToDevice, ms)) !=
              hipSuccess ||
-         hipMemcpyAsync(D.succ_off, hoff.data(), sizeof(int32_t) * (nr + 1),
-                        hipMemcpyHostToDevice, ms) != hipSuccess ||
-         (!hs.empty() && hipMemcpyAsync(D.succ, hs.data(), sizeof(int32_t) * hs.size(),
-                                        hipMemcpyHostToDevice, ms) != hipSuccess) ||
-         hipMemcpyAsync(D.empty, he.data(), (size_t)nr, hipMemcpyHostToDevice, ms) != hipSuccess ||
-         hipMemcpyAsync(D.ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice, ms) != hipSuccess))
-      rc = SEMIPAR_E_HIP;
+         (he = hipMemcpyAsync(D.ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice, ms)) !=
+             hipSuccess))
+      rc = hip_err(he, "queue upload");
     if (rc == SEMIPAR_OK) {
+      (void)hipGetLastError();  // only this launch's error counts below
       k_dag_release<<<1, DAG_NT, 0, ms>>>(nullptr, 0, 1, nr, D.pending, D.succ_off, D.succ,
                                           D.empty, D.ring, D.ctr, D.work);
-      if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
+      if ((he = hipGetLastError()) != hipSuccess) rc = hip_err(he, "k_dag_release (seed)");
     }
     // regions that have entered the ring since the last read: empty ones are only
     // noted, the others wait for a batch
@@ -502,20 +529,23 @@ struct Runner {
     int32_t consumed = 0;
     auto drain = [&](std::vector<int32_t>& live) -> int {
       int32_t tail = 0;
-      if (hipMemcpyAsync(&tail, D.ctr, sizeof(int32_t), hipMemcpyDeviceToHost, ms) != hipSuccess ||
-          hipStreamSynchronize(ms) != hipSuccess)
+      hipError_t e = hipMemcpyAsync(&tail, D.ctr, sizeof(int32_t), hipMemcpyDeviceToHost, ms);
+      if (e == hipSuccess) e = hipStreamSynchronize(ms);
+      if (e != hipSuccess) return hip_err(e, "ready-ring count read");
+      if (tail < consumed || tail > nr) {
+        spi::set_error("schedule_regions: the ready ring holds an impossible count");
         return SEMIPAR_E_HIP;
-      if (tail < consumed || tail > nr) return SEMIPAR_E_HIP;
-      if (tail > consumed &&
-          (hipMemcpyAsync(host_ring.data() + consumed, D.ring + consumed,
-                          sizeof(int32_t) * (tail - consumed), hipMemcpyDeviceToHost,
-                          ms) != hipSuccess ||
-           hipStreamSynchronize(ms) != hipSuccess))
-        return SEMIPAR_E_HIP;
+      }
+      if (tail > consumed) {
+        e = hipMemcpyAsync(host_ring.data() + consumed, D.ring + consumed,
+                           sizeof(int32_t) * (tail - consumed), hipMemcpyDeviceToHost, ms);
+        if (e == hipSuccess) e = hipStreamSynchronize(ms);
+        if (e != hipSuccess) return hip_err(e, "ready-ring read");
+      }
       for (int32_t i = consumed; i < tail; ++i) {
         const int32_t r = host_ring[i];
         acc.regions += 1;
-        if (he[r]) {
+        if (hempty[r]) {
           acc.empty_regions += 1;
           if (p->out_off)
             for (int f = 0; f < 4; ++f) p->out_off[4 * r + f] = slab[r].base;
@@ -575,6 +605,7 @@ struct Runner {
               brc = build_batch(b, ls[l]);
               if (brc == SEMIPAR_OK) brc = region_evolve(b.reg, &e2, &b.es);
             }
+            if (brc != SEMIPAR_OK) b.msg = semipar_last_error();
             {
               std::lock_guard<std::mutex> lk(mu);
               b.rc = brc;
@@ -596,18 +627,22 @@ struct Runner {
       if (got.empty()) break;  // nothing running, nothing waiting: every ready region ran
       fin.clear();
       for (size_t i : got) {
-        if (bs[i].rc != SEMIPAR_OK && rc == SEMIPAR_OK) rc = bs[i].rc;
+        if (bs[i].rc != SEMIPAR_OK && rc == SEMIPAR_OK) {
+          rc = bs[i].rc;
+          spi::set_error(bs[i].msg.c_str());  // the lane's message, on the caller's thread
+        }
         fin.insert(fin.end(), bs[i].regs.begin(), bs[i].regs.end());
       }
       if (rc != SEMIPAR_OK) break;
-      if (hipMemcpyAsync(D.fin, fin.data(), sizeof(int32_t) * fin.size(), hipMemcpyHostToDevice,
-                         ms) != hipSuccess) {
-        rc = SEMIPAR_E_HIP;
+      if ((he = hipMemcpyAsync(D.fin, fin.data(), sizeof(int32_t) * fin.size(),
+                               hipMemcpyHostToDevice, ms)) != hipSuccess) {
+        rc = hip_err(he, "finished-region list upload");
         break;
       }
+      (void)hipGetLastError();  // only this launch's error counts below
       k_dag_release<<<1, DAG_NT, 0, ms>>>(D.fin, (int)fin.size(), 0, nr, D.pending, D.succ_off,
                                           D.succ, D.empty, D.ring, D.ctr, D.work);
-      if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
+      if ((he = hipGetLastError()) != hipSuccess) rc = hip_err(he, "k_dag_release");
       if (rc == SEMIPAR_OK) rc = drain(live);
       if (rc == SEMIPAR_OK) dispatch(live);
       cv_lane.notify_all();
@@ -655,6 +690,7 @@ extern "C" {
 
 int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
                      semipar_sched_stats* st) {
+  spi::begin_call();
   if (!p) return SEMIPAR_E_ARG;
   int rc = check_tiling(t);
   if (rc != SEMIPAR_OK) return rc;
@@ -717,6 +753,7 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
 }
 
 int semipar_region_features(const semipar_tiling* t, float* feat) {
+  spi::begin_call();
   int rc = check_tiling(t);
   if (rc != SEMIPAR_OK || !feat) return SEMIPAR_E_ARG;
   if (t->n_regions == 0) return SEMIPAR_OK;

@@ -132,7 +132,6 @@ struct Ctrl {
   // the event matching's workgroups: log places taken, exchanges, pass-throughs, most
   // rounds of a group, and workgroups finished (all zero between steps)
   int32_t res_nlog, res_nacc, res_npass, res_iter, res_done;
-  int32_t scan_done;  // workgroups of the bucket scan finished (zero between steps)
   int32_t pb_step;    // persistent launch: the furthest slice any of its regions reached
 };
 
@@ -344,7 +343,7 @@ __device__ __forceinline__ void write_frozen(semipar_point_rec* __restrict__ frz
 // inputs. All decisions read the state before the step (a stop written in this step
 // never satisfies "stopped before this step").
 template <bool FRW, int SCR, bool BND>
-__global__ __launch_bounds__(NT, 4) void k_evolve(Slices X, const int32_t* __restrict__ nxt,
+__global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restrict__ nxt,
                                                const int32_t* __restrict__ prv,
                                                const int64_t* __restrict__ id, int n,
                                                sp::Period P, double hcoef, Ctrl* ctrl, HashCfg hc,
@@ -392,182 +391,140 @@ __global__ __launch_bounds__(NT, 4) void k_evolve(Slices X, const int32_t* __res
   bool live_pt = k < n;
   if constexpr (BND) live_pt = live_pt && fstep[k] == FS_ACTIVE;
   else live_pt = live_pt && (!fstep || fstep[k] == FS_ACTIVE);
-  // Level 1: k's link and vertex. Lane 63 also reads next[k+1]: when next[k] = k+1 its
-  // element needs the top of a point that the next wave computes, so it prefetches that
-  // point's inputs alongside its own.
-  const int lane = (int)(threadIdx.x & 63);
-  int j = -1, jn = -1;
-  V4 L{};
   if (live_pt) {
-    j = nxt[k];
-    L = ld(X, ic, k);
-    if (lane == 63 && k + 1 < n) jn = nxt[k + 1];
-  }
-  // geometry of k's region (links never leave a region, so also next[k]'s)
-  RegionGeom G;
-  if constexpr (BND) G = live_pt && rid ? geoms[rid[k]] : G0;
-  // Level 2: the diamond's other inputs; lane 63's speculative inputs of k+1's top
-  bool adv = false;
-  V4 R{}, B{}, T{};
-  const bool spec = SCR != 0 && live_pt && lane == 63 && j == k + 1 && jn >= 0;
-  V4 Rs{}, Bs{};
-  int32_t fs_jn = FS_ACTIVE;
-  if (spec) {
-    Rs = ld(X, ic, jn);
-    Bs = ld(X, ip, jn);
-    if constexpr (BND) fs_jn = fstep[jn];
-  }
-  if (live_pt) {
-    adv = true;
-    // the neighbour's vertices are read together with its stop state (not after it)
-    int32_t fj = FS_ACTIVE;
-    if (j >= 0) {
-      B = ld(X, ip, j);
-      R = ld(X, ic, j);
-      if constexpr (BND) fj = fstep[j];
-    }
+    bool adv = true;
+    int j = nxt[k];
+    // geometry of k's region (links never leave a region, so also next[k]'s)
+    RegionGeom G;
+    if constexpr (BND) G = rid ? geoms[rid[k]] : G0;
     if constexpr (BND) {
       adv = false;
-      int f = -1;
-      bool with_r = false;
-      if (j < 0) {
-        f = -1;
-      } else if (fj < s) {
-        f = face[j];
-      } else {
-        f = exit_face(G, B);
-        if (f < 0) adv = true;
-        with_r = true;
-      }
-      if (!adv) {
-        write_frozen(frz, X, ic, ip, k, j, with_r, f, s, prv, id);
-        face[k] = f;
-        fstep[k] = s;
+      {
+        int f = -1;
+        bool with_r = false;
+        if (j < 0) {
+          f = -1;
+        } else if (fstep[j] < s) {
+          f = face[j];
+        } else {
+          f = exit_face(G, ld(X, ip, j));
+          if (f < 0) adv = true;
+          with_r = true;
+        }
+        if (!adv) {
+          write_frozen(frz, X, ic, ip, k, j, with_r, f, s, prv, id);
+          face[k] = f;
+          fstep[k] = s;
+        }
       }
     }
     if (adv) {
       nadv += 1;
       still = true;
-      T = sp::top<FRW>(L, R, B, P, hcoef);
+      const V4 L = ld(X, ic, k);
+      const V4 R = ld(X, ic, j);
+      const V4 B = ld(X, ip, j);
+      const V4 T = sp::top<FRW>(L, R, B, P, hcoef);
       st(X, in, k, T);
       const uint64_t tk = order_key(T.t);
       tkey = tk < tkey ? tk : tkey;
-    }
-  }
-  if constexpr (SCR != 0) {
-    // the element of band n to the right neighbour j needs j's new top: lanes 0..62 take
-    // it (and j's advance decision) from the next lane when j = k+1, computed there from
-    // the same inputs by the same code; lane 63 computes it from its prefetched inputs;
-    // other links read j's inputs now
-    const bool adv_n = __shfl_down(adv ? 1 : 0, 1, 64) != 0;
-    V4 Tn;
-    Tn.x = __shfl_down(T.x, 1, 64);
-    Tn.y = __shfl_down(T.y, 1, 64);
-    Tn.z = __shfl_down(T.z, 1, 64);
-    Tn.t = __shfl_down(T.t, 1, 64);
-    if (adv) {
-      bool jadv = true;
-      V4 Tj;
-      if (lane < 63 && j == k + 1) {
-        jadv = adv_n;
-        Tj = Tn;
-      } else {
-        const int jj = spec ? jn : nxt[j];
+      if constexpr (SCR != 0) {
+        const int jj = nxt[j];
+        bool jadv = true;
         V4 Rj, Bj;
         if constexpr (BND) {
-          const int32_t fjj = spec ? fs_jn : (jj >= 0 ? fstep[jj] : 0);
-          jadv = fstep[j] == FS_ACTIVE && jj >= 0 && fjj >= s;
+          jadv = fstep[j] == FS_ACTIVE && jj >= 0 && fstep[jj] >= s;
           if (jadv) {
-            Bj = spec ? Bs : ld(X, ip, jj);
+            Bj = ld(X, ip, jj);
             jadv = exit_face(G, Bj) < 0;
           }
-          if (jadv) Rj = spec ? Rs : ld(X, ic, jj);
+          if (jadv) Rj = ld(X, ic, jj);
         } else {
-          Rj = spec ? Rs : ld(X, ic, jj);
-          Bj = spec ? Bs : ld(X, ip, jj);
+          Rj = ld(X, ic, jj);
+          Bj = ld(X, ip, jj);
         }
-        if (jadv) Tj = sp::top<FRW>(R, Rj, Bj, P, hcoef);
-      }
-      if (!jadv) {
-        ecell[k] = NO_ELEM;
-      } else {
-      const Elem e = sp::make_elem(L, R, T, Tj, P);
-      const Box4 b = sp::elem_box(e);
-      double ext = b.hi[0] - b.lo[0];
-      ext = fmax(ext, b.hi[1] - b.lo[1]);
-      ext = fmax(ext, b.hi[2] - b.lo[2]);
-      xk = order_key(ext);
-      double W[3], w[3];
-      for (int c = 0; c < 3; ++c) {
-        W[c] = P.box * floor(b.lo[c] * P.inv);
-        w[c] = b.lo[c] - W[c];
-      }
-      const bool local = BND && rcell != nullptr;
-      RCell C{};
-      if (local) C = rcell[rid[k]];
-      if (local ? !(ext <= C.hlim) : (cs.nc == 0 || !(ext <= cs.hlim))) {
-        const int li = atomicAdd(&ctrl->n_large, 1);
-        LargeBox lb;
-        for (int c = 0; c < 3; ++c) {
-          lb.wl[c] = w[c];
-          lb.ext[c] = b.hi[c] - b.lo[c];
-        }
-        lb.tlo = b.lo[3];
-        lb.thi = b.hi[3];
-        lb.slot = k;
-        lb.pad = 0;
-        large[li] = lb;
-        ecell[k] = -1 - li;
-      } else {
-        int ci[3];
-        double lor[3], hir[3];
-        if (local) {
-          // coordinates relative to the region's grid origin (minimum image)
-          const double o[3] = {C.ox, C.oy, C.oz};
+        if (!jadv) {
+          ecell[k] = NO_ELEM;
+        } else {
+          const V4 Tj = sp::top<FRW>(R, Rj, Bj, P, hcoef);
+          const Elem e = sp::make_elem(L, R, T, Tj, P);
+          const Box4 b = sp::elem_box(e);
+          double ext = b.hi[0] - b.lo[0];
+          ext = fmax(ext, b.hi[1] - b.lo[1]);
+          ext = fmax(ext, b.hi[2] - b.lo[2]);
+          xk = order_key(ext);
+          double W[3], w[3];
           for (int c = 0; c < 3; ++c) {
-            const double d = b.lo[c] - o[c];
-            const double sh = P.box * P.nearest(d);
-            const double dl = d - sh;
-            int q = (int)floor(dl * C.inv_h);
-            q = q < 0 ? 0 : (q > C.nc - 1 ? C.nc - 1 : q);
-            ci[c] = q;
-            lor[c] = dl - (double)q * C.h;
-            hir[c] = ((b.hi[c] - o[c]) - sh) - (double)q * C.h;
+            W[c] = P.box * floor(b.lo[c] * P.inv);
+            w[c] = b.lo[c] - W[c];
           }
-        } else {
-          for (int c = 0; c < 3; ++c) {
-            int q = (int)floor(w[c] * cs.inv_h);
-            q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
-            ci[c] = q;
-            lor[c] = w[c] - (double)q * cs.h;
-            hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
+          const bool local = BND && rcell != nullptr;
+          RCell C{};
+          if (local) C = rcell[rid[k]];
+          if (local ? !(ext <= C.hlim) : (cs.nc == 0 || !(ext <= cs.hlim))) {
+            const int li = atomicAdd(&ctrl->n_large, 1);
+            LargeBox lb;
+            for (int c = 0; c < 3; ++c) {
+              lb.wl[c] = w[c];
+              lb.ext[c] = b.hi[c] - b.lo[c];
+            }
+            lb.tlo = b.lo[3];
+            lb.thi = b.hi[3];
+            lb.slot = k;
+            lb.pad = 0;
+            large[li] = lb;
+            ecell[k] = -1 - li;
+          } else {
+            int ci[3];
+            double lor[3], hir[3];
+            if (local) {
+              // coordinates relative to the region's grid origin (minimum image)
+              const double o[3] = {C.ox, C.oy, C.oz};
+              for (int c = 0; c < 3; ++c) {
+                const double d = b.lo[c] - o[c];
+                const double sh = P.box * P.nearest(d);
+                const double dl = d - sh;
+                int q = (int)floor(dl * C.inv_h);
+                q = q < 0 ? 0 : (q > C.nc - 1 ? C.nc - 1 : q);
+                ci[c] = q;
+                lor[c] = dl - (double)q * C.h;
+                hir[c] = ((b.hi[c] - o[c]) - sh) - (double)q * C.h;
+              }
+            } else {
+              for (int c = 0; c < 3; ++c) {
+                int q = (int)floor(w[c] * cs.inv_h);
+                q = q < 0 ? 0 : (q > cs.nc - 1 ? cs.nc - 1 : q);
+                ci[c] = q;
+                lor[c] = w[c] - (double)q * cs.h;
+                hir[c] = (b.hi[c] - W[c]) - (double)q * cs.h;
+              }
+            }
+            if constexpr (SCR == 1) {
+              double4* o = (double4*)ebox + (size_t)k * 2;
+              o[0] = make_double4(lor[0], lor[1], lor[2], b.lo[3]);
+              o[1] = make_double4(hir[0], hir[1], hir[2], b.hi[3]);
+            } else {
+              float4* o = (float4*)ebox + (size_t)k * 2;
+              o[0] = make_float4(__double2float_rd(lor[0] - hc.tol),
+                                 __double2float_rd(lor[1] - hc.tol),
+                                 __double2float_rd(lor[2] - hc.tol),
+                                 __double2float_rd((b.lo[3] - hc.tref) - hc.tol_t));
+              o[1] = make_float4(__double2float_ru(hir[0] + hc.tol),
+                                 __double2float_ru(hir[1] + hc.tol),
+                                 __double2float_ru(hir[2] + hc.tol),
+                                 __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
+            }
+            const uint32_t bk =
+                local ? (C.base + cell_index(C.nc, ci[0], ci[1], ci[2])) & hc.bmask
+                      : bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
+            hashed = true;
+            hbk = bk;
+            ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
           }
         }
-        if constexpr (SCR == 1) {
-          double4* o = (double4*)ebox + (size_t)k * 2;
-          o[0] = make_double4(lor[0], lor[1], lor[2], b.lo[3]);
-          o[1] = make_double4(hir[0], hir[1], hir[2], b.hi[3]);
-        } else {
-          float4* o = (float4*)ebox + (size_t)k * 2;
-          o[0] = make_float4(__double2float_rd(lor[0] - hc.tol),
-                             __double2float_rd(lor[1] - hc.tol),
-                             __double2float_rd(lor[2] - hc.tol),
-                             __double2float_rd((b.lo[3] - hc.tref) - hc.tol_t));
-          o[1] = make_float4(__double2float_ru(hir[0] + hc.tol),
-                             __double2float_ru(hir[1] + hc.tol),
-                             __double2float_ru(hir[2] + hc.tol),
-                             __double2float_ru((b.hi[3] - hc.tref) + hc.tol_t));
-        }
-        const uint32_t bk =
-            local ? (C.base + cell_index(C.nc, ci[0], ci[1], ci[2])) & hc.bmask
-                  : bucket_of(cs.nc, hc.bmask, ci[0], ci[1], ci[2]);
-        hashed = true;
-        hbk = bk;
-        ecell[k] = (int32_t)pack_cell(ci[0], ci[1], ci[2]);
       }
-      }
-    } else if (live_pt) {
-      ecell[k] = NO_ELEM;  // stopped in this step (points stopped before already read so)
+    } else if constexpr (SCR != 0) {
+      ecell[k] = NO_ELEM;
     }
   }
   // slots in bucket order: neighbouring lanes are neighbouring points of a string and
@@ -645,15 +602,13 @@ __global__ __launch_bounds__(NT, 4) void k_evolve(Slices X, const int32_t* __res
 constexpr int MAX_TILES = 2048;  // buckets <= 2^23
 
 // Per-tile exclusive scan of the bucket counts (counts are reset for the next step);
-// tile totals go to tile_tot. The last workgroup to finish scans the tile totals into
-// toff: toff[t] = first sorted position of tile t, toff[ntiles] = hashed elements.
+// tile totals go to tile_tot, which k_toff scans. (The last workgroup could scan them
+// instead, but making the totals visible to it takes a device-scope fence in every
+// workgroup, which writes back the L2: 12 times slower than a second launch.)
 __global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t* __restrict__ loc,
-                                              int32_t* __restrict__ tile_tot, int ntiles,
-                                              int32_t* __restrict__ toff, Ctrl* ctrl) {
+                                              int32_t* __restrict__ tile_tot, const Ctrl* ctrl) {
   if (ctrl->done) return;
   __shared__ int32_t sh[256];
-  __shared__ int32_t s_toff[MAX_TILES + 1];
-  __shared__ int s_last;
   const int t = threadIdx.x;
   const size_t base = (size_t)blockIdx.x * TS + (size_t)t * 16;
   int4* c4 = (int4*)(cnt + base);
@@ -691,22 +646,25 @@ __global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t
     c4[i] = make_int4(0, 0, 0, 0);
   }
   if (t == 255) tile_tot[blockIdx.x] = sh[255];
-  __threadfence();  // the tile total is visible to the workgroup that counts last
-  __syncthreads();
-  if (t == 0) s_last = atomicAdd(&ctrl->scan_done, 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  block_tile_offsets(tile_tot, ntiles, s_toff, sh);
-  for (int i = t; i <= ntiles; i += 256) toff[i] = s_toff[i];
-  if (t == 0) ctrl->scan_done = 0;
 }
 
 constexpr int POINT_GRID = 2048;  // most workgroups of the grid-stride per-point kernels
+
 constexpr int SCREEN_GRID = 2560;  // most workgroups of the screen (a multiple of 8)
 
 __device__ __forceinline__ int bucket_start(const int32_t* loc, const int32_t* s_toff, uint32_t b) {
   return loc[b] + s_toff[b >> TS_LOG];
+}
+
+// Exclusive scan of the tile totals (one workgroup): toff[t] = first sorted position of
+// tile t, toff[ntiles] = number of hashed elements.
+__global__ __launch_bounds__(1024) void k_toff(const int32_t* __restrict__ tile_tot, int ntiles,
+                                               int32_t* __restrict__ toff, const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  __shared__ int32_t s_toff[MAX_TILES + 1];
+  __shared__ int32_t s_tmp[1024];
+  block_tile_offsets(tile_tot, ntiles, s_toff, s_tmp);
+  for (int i = threadIdx.x; i <= ntiles; i += 1024) toff[i] = s_toff[i];
 }
 
 // Neighbour pencils of a sorted element (64 bytes), written by k_scatter for the screen
@@ -939,8 +897,8 @@ inline int xcd_grid(int total) { return (total + N_XCD - 1) / N_XCD * N_XCD; }
 // one of smaller slot). Threads past the hashed elements take one large element each.
 // Each unordered pair is tested exactly once. Logical block = (element block, g),
 // renumbered per XCD (xcd_block).
-constexpr int SCREEN_EPW = 12;
-constexpr int SPLIT_PRE = 2;  // screen variant: pencils precomputed by k_scatter  // elements per wave when five lanes share an element
+constexpr int SCREEN_EPW = 12;  // elements per wave when five lanes share an element
+constexpr int SPLIT_PRE = 2;    // screen variant: pencils precomputed by k_scatter
 
 template <int SCR, int G>
 __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int n, const int2* __restrict__ sent,
@@ -3274,6 +3232,18 @@ inline int hip_fail(hipError_t e, const char* what, int line) {
   return SEMIPAR_E_HIP;
 }
 
+// A failed device allocation: the place and the device's free memory, for
+// semipar_last_error, and SEMIPAR_E_OOM.
+inline int oom(int line) {
+  size_t fr = 0, tot = 0;
+  (void)hipMemGetInfo(&fr, &tot);
+  (void)hipGetLastError();
+  snprintf(g_last_error, sizeof(g_last_error),
+           "device allocation failed at semipar.hip:%d (%.1f of %.1f GiB free)", line,
+           fr / 1073741824.0, tot / 1073741824.0);
+  return oom(__LINE__);
+}
+
 #define RCCHK(x)              \
   do {                        \
     int rc_ = (x);            \
@@ -3641,9 +3611,10 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
   mark(r, SEMIPAR_K_EVOLVE, 2 * i + 1);
   if (intercommute) {
     mark(r, SEMIPAR_K_SCAN, 2 * i);
-    k_scan<<<r->ntiles, 256, 0, s>>>(r->cnt, r->loc, r->tile_tot, r->ntiles, r->toff, r->ctrl);
+    k_scan<<<r->ntiles, 256, 0, s>>>(r->cnt, r->loc, r->tile_tot, r->ctrl);
     mark(r, SEMIPAR_K_SCAN, 2 * i + 1);
     mark(r, SEMIPAR_K_SCATTER, 2 * i);
+    k_toff<<<1, 1024, 0, s>>>(r->tile_tot, r->ntiles, r->toff, r->ctrl);
     PencilAux* saux = r->split == SPLIT_PRE ? r->saux : nullptr;
     if (r->screen == 1)
       k_scatter<1><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
@@ -3928,10 +3899,12 @@ void region_destroy(semipar_region* r) {
   for (hipEvent_t e : r->tev) (void)hipEventDestroy(e);
   if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
   delete r;
+  (void)hipGetLastError();  // a failed release is not reported by later launches
 }
 
 int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surface* in, int n_in,
                               semipar_region** out) {
+  spi::begin_call();
   if (!out) return SEMIPAR_E_ARG;
   *out = nullptr;
   if (!d || n_in < 0 || (n_in > 0 && !in)) return SEMIPAR_E_ARG;
@@ -3988,17 +3961,21 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
   const int64_t cap = std::max<int64_t>(r->cap, 1);
   for (int s = 0; s < 3; ++s)
     for (int c = 0; c < 4; ++c)
-      if (dalloc(&r->X.p[s][c], cap) != hipSuccess) return fail(SEMIPAR_E_OOM);
+      if (dalloc(&r->X.p[s][c], cap) != hipSuccess) return fail(oom(__LINE__));
   if (dalloc(&r->nxt, cap) != hipSuccess || dalloc(&r->prv, cap) != hipSuccess ||
       dalloc(&r->id, cap) != hipSuccess || dalloc(&r->ctrl, 1) != hipSuccess ||
       dalloc(&r->blkred, 4 * (size_t)blocks(cap)) != hipSuccess ||
       dalloc(&r->fstep, cap) != hipSuccess || dalloc(&r->face, cap) != hipSuccess ||
       dalloc(&r->lev, cap) != hipSuccess || dalloc(&r->wlive, (cap + 63) / 64) != hipSuccess ||
       (d->bounded && dalloc(&r->frz, cap) != hipSuccess))
-    return fail(SEMIPAR_E_OOM);
+    return fail(oom(__LINE__));
   if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
-    return fail(SEMIPAR_E_OOM);
-  if (hipMemset(r->wlive, 1, (size_t)(cap + 63) / 64) != hipSuccess) return fail(SEMIPAR_E_HIP);
+    return fail(oom(__LINE__));
+  // Every copy and fill goes on the region's stream: a null-stream operation waits for
+  // all streams, and invalidates a graph capture in progress on any other thread (a
+  // batch on another lane of the scheduler).
+  if (hipMemsetAsync(r->wlive, 1, (size_t)(cap + 63) / 64, r->stream) != hipSuccess)
+    return fail(SEMIPAR_E_HIP);
   if (d->n_sub > 0) {
     // batch: per-point sub-region ids (surface order) and the geometry table
     r->n_sub = d->n_sub;
@@ -4021,17 +3998,18 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
     if (dalloc(&r->geoms, d->n_sub) != hipSuccess || dalloc(&r->rid, cap) != hipSuccess ||
         dalloc(&r->rcell, d->n_sub) != hipSuccess ||
         dalloc(&r->rext, (size_t)d->n_sub * REXT_STRIDE) != hipSuccess)
-      return fail(SEMIPAR_E_OOM);
-    if (hipMemset(r->rcell, 0, sizeof(RCell) * d->n_sub) != hipSuccess ||
-        hipMemset(r->rext, 0, sizeof(uint64_t) * d->n_sub * REXT_STRIDE) != hipSuccess)
-      return fail(SEMIPAR_E_HIP);
-    if (hipMemcpy(r->geoms, hg.data(), sizeof(RegionGeom) * d->n_sub, hipMemcpyHostToDevice) !=
-        hipSuccess)
+      return fail(oom(__LINE__));
+    if (hipMemsetAsync(r->rcell, 0, sizeof(RCell) * d->n_sub, r->stream) != hipSuccess ||
+        hipMemsetAsync(r->rext, 0, sizeof(uint64_t) * d->n_sub * REXT_STRIDE, r->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(r->geoms, hg.data(), sizeof(RegionGeom) * d->n_sub, hipMemcpyHostToDevice,
+                       r->stream) != hipSuccess ||
+        hipStreamSynchronize(r->stream) != hipSuccess)  // hg is read before it goes
       return fail(SEMIPAR_E_HIP);
     if (total > 0) {
       // sub-region of each slot, filled on the device from the sub-region offsets
       int64_t* doff = nullptr;
-      if (salloc(&doff, (size_t)n_in + 1, r->stream) != hipSuccess) return fail(SEMIPAR_E_OOM);
+      if (salloc(&doff, (size_t)n_in + 1, r->stream) != hipSuccess) return fail(oom(__LINE__));
       const bool ok =
           hipMemcpyAsync(doff, r->sub_off.data(), sizeof(int64_t) * ((size_t)n_in + 1),
                          hipMemcpyHostToDevice, r->stream) == hipSuccess;
@@ -4058,7 +4036,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
   if (total > 0) {
     // gather all surfaces into one device record array
     semipar_point_rec* drec = nullptr;
-    if (salloc(&drec, total, r->stream) != hipSuccess) return fail(SEMIPAR_E_OOM);
+    if (salloc(&drec, total, r->stream) != hipSuccess) return fail(oom(__LINE__));
     int64_t off = 0;
     for (int i = 0; i < n_in; ++i) {
       if (in[i].n == 0) continue;
@@ -4087,7 +4065,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       sfree(drec, r->stream);
       sfree(hkey, r->stream);
       sfree(hval, r->stream);
-      return fail(SEMIPAR_E_OOM);
+      return fail(oom(__LINE__));
     }
     const int n = (int)total;
     rc = SEMIPAR_OK;
@@ -4102,7 +4080,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
                                                     r->fstep, r->face, r->lev, r->rid, r->ctrl);
       k_init_check<<<blocks(n), NT, 0, r->stream>>>(r->X, n, r->nxt, r->prv, r->P, c0.step,
                                                     r->ctrl);
-      if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
+      if (hipError_t e_ = hipGetLastError(); e_ != hipSuccess) rc = hip_fail(e_, "launch", __LINE__);
     }
     if (rc == SEMIPAR_OK && read_ctrl(r) != SEMIPAR_OK) rc = SEMIPAR_E_HIP;
     sfree(drec, r->stream);
@@ -4112,16 +4090,19 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
     if (r->ctrl_h->err != 0) return fail(SEMIPAR_E_SURFACE);
     r->ext0 = from_key(r->ctrl_h->ext_key);
   } else {
-    if (hipMemcpy(r->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpyAsync(r->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, r->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(r->stream) != hipSuccess)
       return fail(SEMIPAR_E_HIP);
     *r->ctrl_h = c0;
   }
-  if (ensure_log(r, 1 << 16) != SEMIPAR_OK) return fail(SEMIPAR_E_OOM);
+  if (ensure_log(r, 1 << 16) != SEMIPAR_OK) return fail(oom(__LINE__));
   *out = r;
   return SEMIPAR_OK;
 }
 
 int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evolve_stats* st) {
+  spi::begin_call();
   if (!r || !p || p->max_steps < 0 || p->loop_every < 0) return SEMIPAR_E_ARG;
   if (p->screen != SEMIPAR_SCREEN_F64 && p->screen != SEMIPAR_SCREEN_F32) return SEMIPAR_E_ARG;
   const double p_ic = p->p == 0.0 ? 1.0 : p->p;
@@ -4142,7 +4123,6 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   const Ctrl before = *r->ctrl_h;
   const int64_t lim64 = (int64_t)before.step + p->max_steps;
   const int32_t step_limit = (int32_t)std::min<int64_t>(lim64, INT32_MAX - 1);
-  if (p->persistent && persistent_ok(r, p)) return evolve_persistent(r, p, st, before, step_limit);
   const int n = (int)r->n;
   const bool ic = p->intercommute != 0;
   const int K = p->steps_per_sync > 0 ? p->steps_per_sync : 32;
@@ -4154,12 +4134,13 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     if (split == SPLIT_PRE && !r->saux) {
       drop_graph(r);
       if (dalloc(&r->saux, (size_t)std::max<int64_t>(r->cap, 1)) != hipSuccess)
-        return SEMIPAR_E_OOM;
+        return oom(__LINE__);
     }
     if (p_ic != r->p_ic || p->seed != r->seed) drop_graph(r);
     r->p_ic = p_ic;
     r->seed = p->seed;
   }
+  if (p->persistent && persistent_ok(r, p)) return evolve_persistent(r, p, st, before, step_limit);
   r->timed = (p->timed_kernel >= 0 && p->timed_kernel <= SEMIPAR_K_RESOLVE) ? p->timed_kernel : -1;
   if (r->timed >= 0) {
     rc = ensure_timing_events(r, K);
@@ -4310,6 +4291,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
 
 int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], const int64_t cap[4],
                                int64_t n[4], int32_t mem) {
+  spi::begin_call();
   if (!r || !n) return SEMIPAR_E_ARG;
   if (mem != SEMIPAR_MEM_HOST && mem != SEMIPAR_MEM_DEVICE) return SEMIPAR_E_ARG;
   for (int f = 0; f < 4; ++f) n[f] = 0;
@@ -4325,7 +4307,7 @@ int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], con
   int32_t th[4] = {0, 0, 0, 0};
   if (dalloc(&blkcnt, 4 * (size_t)nb) != hipSuccess || dalloc(&blkoff, 4 * (size_t)nb) != hipSuccess ||
       dalloc(&tot, 4) != hipSuccess) {
-    rc = SEMIPAR_E_OOM;
+    rc = oom(__LINE__);
   } else {
     k_emit_count<<<nb, NT, 0, r->stream>>>(nn, fs, r->frz, blkcnt);
     k_emit_scan<<<1, 1024, 0, r->stream>>>(blkcnt, nb, blkoff, tot);
@@ -4340,12 +4322,12 @@ int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], con
     for (int f = 0; f < 4 && want; ++f)
       if (n[f] > 0 && (!out[f] || !cap || cap[f] < n[f])) rc = SEMIPAR_E_ARG;
     if (want && rc == SEMIPAR_OK) {
-      if (dalloc(&tmp, r->n) != hipSuccess) rc = SEMIPAR_E_OOM;
+      if (dalloc(&tmp, r->n) != hipSuccess) rc = oom(__LINE__);
       if (rc == SEMIPAR_OK) {
         k_emit_write<<<nb, NT, 0, r->stream>>>(r->X, nn, s, r->nxt, r->prv, r->id, fs, r->frz,
                                                blkoff, tot,
                                                r->bounded ? SEMIPAR_FLAG_ACTIVE : 0, tmp);
-        if (hipGetLastError() != hipSuccess) rc = SEMIPAR_E_HIP;
+        if (hipError_t e_ = hipGetLastError(); e_ != hipSuccess) rc = hip_fail(e_, "launch", __LINE__);
         int64_t off = 0;
         const hipMemcpyKind kind =
             mem == SEMIPAR_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
@@ -4368,6 +4350,7 @@ int region_emit_final_surfaces(semipar_region* r, semipar_point_rec* out[4], con
 }
 
 int region_loops(const semipar_region* r, semipar_loop* buf, int64_t cap, int64_t* n) {
+  spi::begin_call();
   if (!r || !n || cap < 0) return SEMIPAR_E_ARG;
   const int64_t total = r->llog_n;
   if (!buf) {
@@ -4391,6 +4374,7 @@ int region_loops(const semipar_region* r, semipar_loop* buf, int64_t cap, int64_
 }
 
 int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int64_t* n) {
+  spi::begin_call();
   if (!r || !n || cap < 0) return SEMIPAR_E_ARG;
   semipar_region* rr = const_cast<semipar_region*>(r);
   RCCHK(read_ctrl(rr));
@@ -4419,6 +4403,7 @@ int region_events(const semipar_region* r, semipar_event* buf, int64_t cap, int6
 }
 
 int region_candidates(const semipar_region* r, int64_t* ids, int64_t cap, int64_t* n) {
+  spi::begin_call();
   if (!r || !n || cap < 0) return SEMIPAR_E_ARG;
   semipar_region* rr = const_cast<semipar_region*>(r);
   if (r->n == 0 || !rr->cand) {
@@ -4486,6 +4471,11 @@ hipStream_t region_stream(const semipar_region* r) { return r ? r->stream : null
 
 void set_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
 
+void begin_call() {
+  g_last_error[0] = 0;
+  (void)hipGetLastError();
+}
+
 int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& cnt) {
   if (!r || r->n_sub <= 0 || !r->rid) return SEMIPAR_E_ARG;
   const int ns = r->n_sub;
@@ -4503,7 +4493,7 @@ int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& 
   if (dalloc(&blkcnt, 4 * (size_t)nb) != hipSuccess || dalloc(&blkoff, 4 * (size_t)nb) != hipSuccess ||
       dalloc(&tot, 4) != hipSuccess || dalloc(&pst, 4 * (size_t)ns) != hipSuccess ||
       dalloc(&dst, 4 * (size_t)ns) != hipSuccess)
-    rc = SEMIPAR_E_OOM;
+    rc = oom(__LINE__);
   if (rc == SEMIPAR_OK) {
     k_emit_count<<<nb, NT, 0, r->stream>>>(nn, r->fstep, r->frz, blkcnt);
     k_emit_scan<<<1, 1024, 0, r->stream>>>(blkcnt, nb, blkoff, tot);
@@ -4560,7 +4550,7 @@ int batch_stats(semipar_region* r, std::vector<int32_t>& steps, std::vector<int6
   unsigned long long* ps = nullptr;
   int32_t* sm = nullptr;
   int rc = SEMIPAR_OK;
-  if (dalloc(&ps, ns) != hipSuccess || dalloc(&sm, ns) != hipSuccess) rc = SEMIPAR_E_OOM;
+  if (dalloc(&ps, ns) != hipSuccess || dalloc(&sm, ns) != hipSuccess) rc = oom(__LINE__);
   if (rc == SEMIPAR_OK &&
       (hipMemsetAsync(ps, 0, sizeof(unsigned long long) * ns, r->stream) != hipSuccess ||
        hipMemsetAsync(sm, 0, sizeof(int32_t) * ns, r->stream) != hipSuccess))
@@ -4601,7 +4591,7 @@ int batch_events(semipar_region* r, std::vector<semipar_event>& ev, std::vector<
   int rc = SEMIPAR_OK;
   if (dalloc(&keys, npow) != hipSuccess || dalloc(&sorted, total) != hipSuccess ||
       dalloc(&cnt, ns) != hipSuccess)
-    rc = SEMIPAR_E_OOM;
+    rc = oom(__LINE__);
   std::vector<int32_t> hc((size_t)ns, 0);
   if (rc == SEMIPAR_OK) {
     const int nbp = blocks(npow);
@@ -4680,7 +4670,7 @@ int batch_features(semipar_region* r, float* feat) {
   if (dalloc(&acc, FEAT_STRIDE * (size_t)ns) != hipSuccess ||
       dalloc(&grid, (size_t)FEAT_CELLS * ns) != hipSuccess || dalloc(&np, ns) != hipSuccess ||
       dalloc(&df, 12 * (size_t)ns) != hipSuccess)
-    rc = SEMIPAR_E_OOM;
+    rc = oom(__LINE__);
   std::vector<int64_t> hn((size_t)ns);
   for (int q = 0; q < ns; ++q) hn[q] = r->sub_off[q + 1] - r->sub_off[q];
   if (rc == SEMIPAR_OK &&
@@ -4755,7 +4745,7 @@ int surface_features(const semipar_tiling* t, float* feat) {
       dalloc(&hkey, hcap) != hipSuccess || dalloc(&hval, hcap) != hipSuccess ||
       dalloc(&err, 1) != hipSuccess || dalloc(&acc, FEAT_STRIDE * (size_t)nr) != hipSuccess ||
       dalloc(&grid, (size_t)FEAT_CELLS * nr) != hipSuccess || dalloc(&df, 12 * (size_t)nr) != hipSuccess)
-    rc = SEMIPAR_E_OOM;
+    rc = oom(__LINE__);
   int32_t herr = 0;
   if (rc == SEMIPAR_OK &&
       (hipMemcpyAsync(dsrf, ptr.data(), sizeof(void*) * nr, hipMemcpyHostToDevice, st) != hipSuccess ||

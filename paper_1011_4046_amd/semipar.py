@@ -195,8 +195,9 @@ def last_error():
 
 def _check(rc, what):
     if rc != 0:
-        if rc == -4:
-            what = f"{what} [{lib().semipar_last_error().decode()}]"
+        msg = lib().semipar_last_error().decode()
+        if msg:
+            what = f"{what} [{msg}]"
         raise SemiparError(rc, what)
 
 

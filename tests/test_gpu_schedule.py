@@ -72,7 +72,8 @@ SIZES = [0, 300, 5000, 1200, 0, 20000, 800, 2500, 40, 9000, 150, 3000]
 
 
 @pytest.mark.parametrize("case", ["plain", "batched-heuristic", "batched-cost", "one-batch-f32",
-                                  "lanes", "work-packing", "precomputed-pencils"])
+                                  "lanes", "lanes-small-batches", "work-packing",
+                                  "precomputed-pencils"])
 def test_schedule_policies_equal_oracle_region_by_region(S, case):
     say(f"case: schedule_regions {case}, sizes {SIZES}, seed 200")
     parts, box = I.region_batch(SIZES, seed=200)
@@ -125,6 +126,12 @@ def test_schedule_policies_equal_oracle_region_by_region(S, case):
         res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=6000, use_graph=True,
                                  screen=S.SCREEN_F32, screen_split=2, lanes=2)
         assert res["stats"]["batches"] >= 4
+    elif case == "lanes-small-batches":
+        # many small batches on three lanes: one lane builds a batch (copies, fills) while
+        # another captures its step graph, which must not disturb the capture
+        res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=1500, use_graph=True,
+                                 screen=S.SCREEN_F32, lanes=3)
+        assert res["stats"]["batches"] >= 6
     elif case == "lanes":
         # batches evolved concurrently by three host threads on streams of their own
         res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=6000, use_graph=True,
