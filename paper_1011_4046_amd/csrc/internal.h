@@ -20,10 +20,13 @@ SP_HIDDEN int64_t region_points(const semipar_region* r);
 SP_HIDDEN hipStream_t region_stream(const semipar_region* r);
 
 // Batch of sub-regions (a region built with n_sub > 0), after region_evolve:
-// records of every sub-region into tmp (device, r->n records): sub-region q occupies
-// the slots of its input surface, its four streams in order, each in slot order;
-// cnt[4 q + f] = records of q on stream f.
-SP_HIDDEN int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& cnt);
+// records of every sub-region into dst (device memory): sub-region q occupies as many
+// records as its input surface had points, from base[q] on (base == nullptr: from its
+// first slot in the batch, so that dst holds r->n records), its four streams in order,
+// each in slot order; cnt[4 q + f] = records of q on stream f. Temporaries are
+// stream-ordered on the region's stream, so this waits for no other stream.
+SP_HIDDEN int batch_emit(semipar_region* r, semipar_point_rec* dst, std::vector<int64_t>& cnt,
+                         const int64_t* base = nullptr);
 
 // Per sub-region: slices advanced by its furthest point and its point-steps.
 SP_HIDDEN int batch_stats(semipar_region* r, std::vector<int32_t>& steps,

@@ -155,12 +155,6 @@ struct Runner {
   std::vector<std::vector<semipar_loop>> lp;   // per region
   semipar_sched_stats acc{};
   int32_t batch_id = 0;
-  semipar_point_rec* tmp = nullptr;
-  int64_t tmp_cap = 0;
-
-  ~Runner() {
-    if (tmp) (void)hipFree(tmp);
-  }
 
   void log_region(int32_t r, int32_t steps, int64_t psteps, int32_t batch, double ms) {
     if (p->region_steps) p->region_steps[r] = steps;
@@ -245,6 +239,8 @@ struct Runner {
     int rc = SEMIPAR_OK;
     std::string msg;    // the lane's error message when rc is not SEMIPAR_OK
     double cost = 0.0;  // predicted device time, for assigning batches to lanes
+    std::vector<int32_t> steps;  // per region: slices advanced (after harvest)
+    std::vector<int64_t> ps;     // per region: point-steps (after harvest)
   };
 
   int build_batch(Batch& b, void* stream) {
@@ -262,44 +258,60 @@ struct Runner {
     return rc;
   }
 
-  int finish_batch(Batch& b) {
-    int rc = b.rc;
+  // Results of an evolved batch, taken on its lane as soon as it has evolved, so that
+  // they overlap the other lanes' steps: records into the output (device output: written
+  // in place; host output: through the lane's device staging buffer), events and loop
+  // logs into the per-region lists, per-region step counts. Every device temporary is
+  // stream-ordered on the batch's stream, so nothing here waits for another lane.
+  int harvest(Batch& b, semipar_point_rec*& stage, int64_t& stage_cap) {
     semipar_region* reg = b.reg;
     const auto& regs = b.regs;
     int64_t total = 0;
     for (int64_t x : b.n) total += x;
-    if (rc == SEMIPAR_OK && p->out && total > 0) {
-      if (tmp_cap < total) {
-        if (tmp) (void)hipFree(tmp);
-        tmp = nullptr;
-        tmp_cap = 0;
-        if (hipMalloc(&tmp, sizeof(semipar_point_rec) * total) != hipSuccess) {
-          spi::set_error("schedule_regions: device allocation of the output staging failed");
-          rc = SEMIPAR_E_OOM;
-        } else {
-          tmp_cap = total;
+    int rc = SEMIPAR_OK;
+    if (p->out && total > 0) {
+      std::vector<int64_t> cnt;
+      if (p->out_mem == SEMIPAR_MEM_DEVICE) {
+        std::vector<int64_t> base(regs.size());
+        for (size_t i = 0; i < regs.size(); ++i) base[i] = slab[regs[i]].base;
+        rc = spi::batch_emit(reg, p->out, cnt, base.data());
+      } else {
+        if (stage_cap < total) {
+          if (stage) (void)hipFree(stage);
+          stage = nullptr;
+          stage_cap = 0;
+          if (hipMalloc(&stage, sizeof(semipar_point_rec) * total) != hipSuccess) {
+            spi::set_error("schedule_regions: device allocation of the output staging failed");
+            return SEMIPAR_E_OOM;
+          }
+          stage_cap = total;
+        }
+        rc = spi::batch_emit(reg, stage, cnt);
+        hipStream_t s = spi::region_stream(reg);
+        int64_t src = 0;
+        for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i) {
+          const int64_t nr = b.n[i];
+          if (nr > 0) {
+            const hipError_t e =
+                hipMemcpyAsync(p->out + slab[regs[i]].base, stage + src,
+                               sizeof(semipar_point_rec) * nr, hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) rc = hip_err(e, "record copy to the host");
+          }
+          src += nr;
+        }
+        if (rc == SEMIPAR_OK) {
+          const hipError_t e = hipStreamSynchronize(s);
+          if (e != hipSuccess) rc = hip_err(e, "record copy to the host");
         }
       }
-      std::vector<int64_t> cnt;
-      if (rc == SEMIPAR_OK) rc = spi::batch_emit(reg, tmp, cnt);
-      const hipMemcpyKind kind =
-          p->out_mem == SEMIPAR_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-      hipStream_t s = spi::region_stream(reg);
-      int64_t src = 0;
       for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i) {
         const int32_t r = regs[i];
-        const int64_t nr = b.n[i];
         int64_t off = slab[r].base;
         for (int f = 0; f < 4; ++f) {
           if (p->out_off) p->out_off[4 * r + f] = off;
           off += cnt[4 * i + f];
         }
-        if (nr > 0 && hipMemcpyAsync(p->out + slab[r].base, tmp + src,
-                                     sizeof(semipar_point_rec) * nr, kind, s) != hipSuccess)
-          rc = SEMIPAR_E_HIP;
-        src += nr;
       }
-      if (rc == SEMIPAR_OK && hipStreamSynchronize(s) != hipSuccess) rc = SEMIPAR_E_HIP;
     }
     if (rc == SEMIPAR_OK && p->events) {
       std::vector<semipar_event> e;
@@ -315,12 +327,16 @@ struct Runner {
       for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i)
         lp[regs[i]].assign(l.begin() + off[i], l.begin() + off[i + 1]);
     }
-    std::vector<int32_t> steps;
-    std::vector<int64_t> ps;
-    if (rc == SEMIPAR_OK) rc = spi::batch_stats(reg, steps, ps);
-    region_destroy(reg);
+    if (rc == SEMIPAR_OK) rc = spi::batch_stats(reg, b.steps, b.ps);
+    return rc;
+  }
+
+  // A harvested batch: totals, per-region log, and the batch region released (releasing
+  // device memory waits for the whole device, so this runs once all batches are done).
+  int finish_batch(Batch& b) {
+    if (b.reg) region_destroy(b.reg);
     b.reg = nullptr;
-    if (rc != SEMIPAR_OK) return rc;
+    if (b.rc != SEMIPAR_OK) return b.rc;
     const semipar_evolve_stats& es = b.es;
     acc.point_steps += es.point_steps;
     acc.steps += es.steps;
@@ -330,8 +346,8 @@ struct Runner {
     acc.loops += es.loops;
     acc.passed += es.passed;
     acc.batches += 1;
-    for (size_t i = 0; i < regs.size(); ++i)
-      log_region(regs[i], steps[i], ps[i], batch_id, es.elapsed_ms);
+    for (size_t i = 0; i < b.regs.size(); ++i)
+      log_region(b.regs[i], b.steps[i], b.ps[i], batch_id, es.elapsed_ms);
     batch_id++;
     return SEMIPAR_OK;
   }
@@ -341,16 +357,39 @@ struct Runner {
               std::chrono::steady_clock::time_point t0) {
     const int nr = tt->n_regions;
     int64_t ne = 0;
+    std::vector<int64_t> eoff((size_t)nr + 1, 0);
     for (int r = 0; r < nr; ++r) {
-      const int64_t m = (int64_t)ev[r].size();
-      if (pp->events) {
-        pp->events_off[r] = ne;
-        const int64_t fit = std::max<int64_t>(0, std::min(m, pp->events_cap - ne));
-        if (fit > 0) memcpy(pp->events + ne, ev[r].data(), sizeof(semipar_event) * fit);
-      }
-      ne += m;
+      eoff[r] = ne;
+      if (pp->events) pp->events_off[r] = ne;
+      ne += (int64_t)ev[r].size();
     }
-    if (pp->events) pp->events_off[nr] = ne;
+    eoff[nr] = ne;
+    if (pp->events) {
+      pp->events_off[nr] = ne;
+      // the copies into the caller's list, split over a few host threads by region
+      auto part = [&](int r0, int r1) {
+        for (int r = r0; r < r1; ++r) {
+          const int64_t fit =
+              std::max<int64_t>(0, std::min<int64_t>(eoff[r + 1], pp->events_cap) - eoff[r]);
+          if (fit > 0) memcpy(pp->events + eoff[r], ev[r].data(), sizeof(semipar_event) * fit);
+        }
+      };
+      const int nt = (int)std::min<int64_t>(8, std::max<int64_t>(1, ne / (1 << 16)));
+      if (nt <= 1) {
+        part(0, nr);
+      } else {
+        std::vector<std::thread> th;
+        int r0 = 0;
+        for (int k = 1; k <= nt; ++k) {
+          // region boundary nearest to k / nt of the events
+          int r1 = r0;
+          while (r1 < nr && (k == nt || eoff[r1] < ne * k / nt)) ++r1;
+          th.emplace_back(part, r0, r1);
+          r0 = r1;
+        }
+        for (auto& x : th) x.join();
+      }
+    }
     acc.events = ne;
     int64_t nl = 0;
     for (int r = 0; r < nr; ++r) {
@@ -442,8 +481,9 @@ struct Runner {
   // (k_dag_release); the host takes the regions that have become ready, packs them into
   // batches and hands those to idle lanes, longest predicted first. A region's
   // successors are released when its own batch has finished, not when a whole wave
-  // has. Results are collected after the last batch (in the order the batches were
-  // formed, which numbers them), since releasing device memory waits for the device.
+  // has. A batch's results are taken on its lane as soon as it has evolved (harvest);
+  // the batch regions are released, and the batches numbered in the order they were
+  // formed, after the last one, since releasing device memory waits for the device.
   int run_dynamic() {
     const int nr = t->n_regions;
     const int lanes = std::max(1, p->lanes);
@@ -475,6 +515,8 @@ struct Runner {
       return ae == hipErrorOutOfMemory ? SEMIPAR_E_OOM : SEMIPAR_E_HIP;
     }
     std::vector<hipStream_t> ls((size_t)lanes, nullptr);
+    std::vector<semipar_point_rec*> stage((size_t)lanes, nullptr);  // host output staging
+    std::vector<int64_t> stage_cap((size_t)lanes, 0);
     hipStream_t ms = nullptr;  // the queue's kernels and reads, in order
     hipEvent_t ready_ev = nullptr;
     std::deque<Batch> bs;
@@ -484,6 +526,8 @@ struct Runner {
           region_destroy(b.reg);
           b.reg = nullptr;
         }
+      for (semipar_point_rec* x : stage)
+        if (x) (void)hipFree(x);
       for (hipStream_t x : ls)
         if (x) (void)hipStreamDestroy(x);
       if (ms) (void)hipStreamDestroy(ms);
@@ -605,6 +649,7 @@ struct Runner {
               brc = build_batch(b, ls[l]);
               if (brc == SEMIPAR_OK) brc = region_evolve(b.reg, &e2, &b.es);
             }
+            if (brc == SEMIPAR_OK) brc = harvest(b, stage[l], stage_cap[l]);
             if (brc != SEMIPAR_OK) b.msg = semipar_last_error();
             {
               std::lock_guard<std::mutex> lk(mu);

@@ -4476,7 +4476,8 @@ void begin_call() {
   (void)hipGetLastError();
 }
 
-int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& cnt) {
+int batch_emit(semipar_region* r, semipar_point_rec* out, std::vector<int64_t>& cnt,
+               const int64_t* out_base) {
   if (!r || r->n_sub <= 0 || !r->rid) return SEMIPAR_E_ARG;
   const int ns = r->n_sub;
   cnt.assign(4 * (size_t)ns, 0);
@@ -4490,9 +4491,10 @@ int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& 
   int rc = SEMIPAR_OK;
   std::vector<int32_t> hp(4 * (size_t)ns, 0);
   int32_t th[4] = {0, 0, 0, 0};
-  if (dalloc(&blkcnt, 4 * (size_t)nb) != hipSuccess || dalloc(&blkoff, 4 * (size_t)nb) != hipSuccess ||
-      dalloc(&tot, 4) != hipSuccess || dalloc(&pst, 4 * (size_t)ns) != hipSuccess ||
-      dalloc(&dst, 4 * (size_t)ns) != hipSuccess)
+  hipStream_t st = r->stream;
+  if (salloc(&blkcnt, 4 * (size_t)nb, st) != hipSuccess ||
+      salloc(&blkoff, 4 * (size_t)nb, st) != hipSuccess || salloc(&tot, 4, st) != hipSuccess ||
+      salloc(&pst, 4 * (size_t)ns, st) != hipSuccess || salloc(&dst, 4 * (size_t)ns, st) != hipSuccess)
     rc = oom(__LINE__);
   if (rc == SEMIPAR_OK) {
     k_emit_count<<<nb, NT, 0, r->stream>>>(nn, r->fstep, r->frz, blkcnt);
@@ -4513,7 +4515,7 @@ int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& 
     for (int q = ns - 1; q >= 0; --q) {
       const int64_t nq = r->sub_off[q + 1] - r->sub_off[q];
       if (nq == 0) continue;
-      int64_t base = r->sub_off[q];
+      int64_t base = out_base ? out_base[q] : r->sub_off[q];
       for (int f = 0; f < 4; ++f) {
         const int64_t end = next >= 0 ? hp[4 * next + f] : th[f];
         cnt[4 * q + f] = end - hp[4 * q + f];
@@ -4527,16 +4529,16 @@ int batch_emit(semipar_region* r, semipar_point_rec* tmp, std::vector<int64_t>& 
       rc = SEMIPAR_E_HIP;
     if (rc == SEMIPAR_OK) {
       k_emit_sub_write<<<nb, NT, 0, r->stream>>>(r->X, nn, s, r->nxt, r->prv, r->id, r->fstep,
-                                                 r->frz, r->rid, blkoff, pst, dst, tmp);
+                                                 r->frz, r->rid, blkoff, pst, dst, out);
       if (hipGetLastError() != hipSuccess || hipStreamSynchronize(r->stream) != hipSuccess)
         rc = SEMIPAR_E_HIP;
     }
   }
-  dfree(blkcnt);
-  dfree(blkoff);
-  dfree(tot);
-  dfree(pst);
-  dfree(dst);
+  sfree(blkcnt, st);
+  sfree(blkoff, st);
+  sfree(tot, st);
+  sfree(pst, st);
+  sfree(dst, st);
   return rc;
 }
 
@@ -4550,7 +4552,8 @@ int batch_stats(semipar_region* r, std::vector<int32_t>& steps, std::vector<int6
   unsigned long long* ps = nullptr;
   int32_t* sm = nullptr;
   int rc = SEMIPAR_OK;
-  if (dalloc(&ps, ns) != hipSuccess || dalloc(&sm, ns) != hipSuccess) rc = oom(__LINE__);
+  if (salloc(&ps, ns, r->stream) != hipSuccess || salloc(&sm, ns, r->stream) != hipSuccess)
+    rc = oom(__LINE__);
   if (rc == SEMIPAR_OK &&
       (hipMemsetAsync(ps, 0, sizeof(unsigned long long) * ns, r->stream) != hipSuccess ||
        hipMemsetAsync(sm, 0, sizeof(int32_t) * ns, r->stream) != hipSuccess))
@@ -4568,8 +4571,8 @@ int batch_stats(semipar_region* r, std::vector<int32_t>& steps, std::vector<int6
       rc = SEMIPAR_E_HIP;
     for (int q = 0; q < ns; ++q) psteps[q] = (int64_t)hps[q];
   }
-  dfree(ps);
-  dfree(sm);
+  sfree(ps, r->stream);
+  sfree(sm, r->stream);
   return rc;
 }
 
@@ -4589,8 +4592,8 @@ int batch_events(semipar_region* r, std::vector<semipar_event>& ev, std::vector<
   int32_t* cnt = nullptr;
   semipar_event* sorted = nullptr;
   int rc = SEMIPAR_OK;
-  if (dalloc(&keys, npow) != hipSuccess || dalloc(&sorted, total) != hipSuccess ||
-      dalloc(&cnt, ns) != hipSuccess)
+  if (salloc(&keys, npow, r->stream) != hipSuccess ||
+      salloc(&sorted, total, r->stream) != hipSuccess || salloc(&cnt, ns, r->stream) != hipSuccess)
     rc = oom(__LINE__);
   std::vector<int32_t> hc((size_t)ns, 0);
   if (rc == SEMIPAR_OK) {
@@ -4619,9 +4622,9 @@ int batch_events(semipar_region* r, std::vector<semipar_event>& ev, std::vector<
     }
   }
   for (int q = 0; q < ns; ++q) off[q + 1] = off[q] + hc[q];
-  dfree(keys);
-  dfree(sorted);
-  dfree(cnt);
+  sfree(keys, r->stream);
+  sfree(sorted, r->stream);
+  sfree(cnt, r->stream);
   if (rc != SEMIPAR_OK) ev.clear();
   return rc;
 }
