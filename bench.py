@@ -395,12 +395,36 @@ def cpu_baseline_regions(parts, box, every=50, budget_s=20.0, coin=None):
                       f"{ps} point-steps in {tc:.1f} s"}
 
 
+def cached_region_batch(path, nt, workers):
+    """The batched workload's regions (seed 0), read from `path` when it holds them, else
+    generated and, when `path` is set, saved there (so that profiler passes over the same
+    workload generate it once, outside the profiler)."""
+    import numpy as np
+    from paper_1011_4046_amd import inputs as I
+    if path and os.path.exists(path):
+        with np.load(path) as z:
+            assert np.array_equal(z["nt"], np.asarray(nt)), "cached workload differs"
+            recs, cnt = z["recs"], z["counts"]
+            off = np.concatenate([[0], np.cumsum(cnt)])
+            parts = [(recs[off[r]:off[r + 1]].copy(), z["geoms"][r].copy())
+                     for r in range(len(cnt))]
+            return parts, float(z["box"])
+    parts, box = I.region_batch(nt, size=4.0, seed=0, slots=8, workers=workers)
+    if path:
+        np.savez(path, nt=np.asarray(nt), recs=np.concatenate([p[0] for p in parts]),
+                 counts=np.array([len(p[0]) for p in parts], np.int64),
+                 geoms=np.array([p[1] for p in parts], np.float64), box=box)
+    return parts, box
+
+
 def roofline_only(args):
     """The roofline schedules of the batched workload alone (no training, no timed
     schedules): what a profiler run of the kernels the roofline describes should see."""
     from paper_1011_4046_amd import inputs as I
     nt = I.lognormal_regions(args.regions, median=2e4, sigma=1.5, cap=2e5, p_empty=0.2, seed=0)
-    parts, box = I.region_batch(nt, size=4.0, seed=0, slots=8, workers=args.workers)
+    parts, box = cached_region_batch(args.inputs_cache, nt, args.workers)
+    if args.inputs_only:
+        return {"mode": "inputs-only", "regions": len(parts)}
     import torch
     from paper_1011_4046_amd import semipar as S
     torch.cuda.set_device(0)
@@ -514,6 +538,11 @@ def main():
                          "random resolution")
     ap.add_argument("--mixed-regions", type=int, default=160)
     ap.add_argument("--mixed-median", type=float, default=4000.0)
+    ap.add_argument("--inputs-cache", default="",
+                    help="file holding the batched workload (--roofline-only): read when "
+                         "present, written after generating it otherwise")
+    ap.add_argument("--inputs-only", action="store_true",
+                    help="with --roofline-only: generate (and cache) the workload, run nothing")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the eager one-lane roofline schedules of the batched workload "
                          "(for a profiler); prints their roofline")
