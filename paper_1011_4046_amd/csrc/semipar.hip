@@ -1187,6 +1187,315 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
   }  // chunks
 }
 
+// The same half-shell screen, one element per thread, with the box tests spread evenly
+// over the lanes of each wave. Every thread finds its element's five pencil ranges as
+// k_screen does (phase 1). The wave then numbers the (element, entry) pairs of its 64
+// elements in lane order (a scan of the per-element counts) and lane l takes pairs l,
+// l + 64, ...: a wave runs ceil(pairs / 64) rounds, where one thread per element runs,
+// for every pencil, as many rounds as its longest lane (about four times as many on the
+// batched workload). A lane finds the element of its pair by a binary search over the
+// wave's pair offsets and reads the element's box and ranges from the wave's LDS
+// records; consecutive lanes then read consecutive entries of one range.
+template <class T>
+struct alignas(16) ScreenOwner {
+  T lo[4];          // the element's box: low x, y, z; the cell edge
+  T hi[4];          // high x, y, z; the slack
+  int32_t k, nk, pk, salt;
+  int32_t rbp[5];   // per pencil: its first entry minus the pairs before it
+  int32_t pre[4];   // pairs before pencils 1..4
+  int32_t cell, msk;  // the element's cell (unsalted), 3 valid-cell bits per pencil
+  int32_t pad;
+};
+constexpr int SBUF_FLAT = 960;       // staged candidates per block (LDS shared with the records)
+constexpr int SBUF_FLAT_FLUSH = 480;
+
+template <int SCR>
+__global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
+    int n, const int2* __restrict__ sent, const void* __restrict__ sbox,
+    const void* __restrict__ ebox_slot, const int32_t* __restrict__ nxt,
+    const int32_t* __restrict__ prv, const int32_t* __restrict__ loc,
+    const int32_t* __restrict__ toff, int ntiles, const LargeBox* __restrict__ large, HashCfg hc,
+    sp::Period P, int2* __restrict__ cand, int cap, Ctrl* ctrl, const int32_t* __restrict__ rid,
+    const RCell* __restrict__ rcell) {
+  if (ctrl->done) return;
+  using T = typename std::conditional<SCR == 1, double, float>::type;
+  static_assert(sizeof(ScreenOwner<T>) % 16 == 0, "records are read as 16-byte vectors");
+  __shared__ int2 sbuf[SBUF_FLAT];
+  __shared__ ScreenOwner<T> s_own[NT];
+  __shared__ int s_cnt, s_base;
+  const Cells cs = ctrl->cells;
+  const int nl = ctrl->n_large;
+  const int n_norm = toff[ntiles];
+  const bool local = rcell != nullptr;
+  const int nchunk = (n_norm + nl + NT - 1) / NT;
+  const int cper = (nchunk + N_XCD - 1) / N_XCD;
+  const int xcd = (int)blockIdx.x % N_XCD;
+  const int bper = (int)gridDim.x / N_XCD;
+  const int lane = (int)(threadIdx.x & 63);
+  const int wbase = (int)threadIdx.x - lane;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  for (int c = (int)blockIdx.x / N_XCD; c < cper; c += bper) {
+  const int lid = xcd * cper + c;
+  if (lid >= nchunk) break;
+  const bool last = c + bper >= cper || lid + bper >= nchunk;
+  const int q = lid * NT + (int)threadIdx.x;
+  auto push = [&](int a, int b) {
+    const int i = atomicAdd(&s_cnt, 1);
+    if (i < SBUF_FLAT)
+      sbuf[i] = make_int2(a, b);
+    else
+      push_cand(ctrl, cand, cap, a, b);
+  };
+  int npairs = 0;
+  int k = -1;
+  bool own_large = false;
+  double wl[3], ex[3], tlo = 0.0, thi = 0.0;  // wrapped box (for large partners)
+  if (q < n_norm) {
+    // phase 1: the element, its grid and its five pencil ranges
+    const SBox<T> me = load_sbox<T>(sbox, q);
+    const int2 ent = entry_key_slot<SCR>(sent, me, q);
+    k = ent.y;
+    RCell C{};
+    uint32_t salt = 0;
+    int gnc = cs.nc;
+    if (local) {
+      C = rcell[rid[k]];
+      salt = C.salt;
+      gnc = C.nc;
+    }
+    const int32_t cc = (int32_t)((uint32_t)ent.x ^ salt);
+    const int nk = nxt[k], pk = prv[k];
+    const int cx = cc & 1023, cy = (cc >> 10) & 1023, cz = (cc >> 20) & 1023;
+    const T tl = SCR == 1 ? (T)hc.tol : (T)(local ? C.marg32 : cs.marg32);
+    const T hh = SCR == 1 ? (T)(local ? C.h : cs.h) : (T)(local ? C.h32 : cs.h32);
+    auto bucket = [&](int x, int y, int z) -> uint32_t {
+      return local ? (C.base + cell_index(gnc, x, y, z)) & hc.bmask
+                   : bucket_of(gnc, hc.bmask, x, y, z);
+    };
+    auto wrapc = [&](int v) { return v < 0 ? v + gnc : (v >= gnc ? v - gnc : v); };
+    // cells whose buckets are not consecutive (rare): tested here, one entry at a time
+    auto scan_cell = [&](int beg, int end, int32_t key, int dx, int dy, int dz) {
+      const T sx = (T)dx * hh, sy = (T)dy * hh, sz = (T)dz * hh;
+      for (int q2 = beg; q2 < end; ++q2) {
+        const SBox<T> b = load_sbox<T>(sbox, q2);
+        const int2 e = entry_key_slot<SCR>(sent, b, q2);
+        const int m = e.y;
+        if (e.x == key && m != nk && m != pk && box_overlap(me, b, sx, sy, sz, tl)) push(k, m);
+      }
+    };
+    int rb[N_PENCIL], len[N_PENCIL], msk = 0;
+#pragma unroll
+    for (int p = 0; p < N_PENCIL; ++p) {
+      rb[p] = 0;
+      len[p] = 0;
+      const int dx = p < 2 ? 0 : 1;
+      const int dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
+      int x = cx + dx, y = cy + dy;
+      if (local) {
+        if (x >= gnc || y < 0 || y >= gnc) continue;
+      } else {
+        x = wrapc(x);
+        y = wrapc(y);
+      }
+      bool kv[3];
+      uint32_t bk[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int dz = u - 1;
+        int z = cz + dz;
+        bool v = !(p == 0 && dz < 0);
+        if (local) {
+          v = v && z >= 0 && z < gnc;
+        } else {
+          z = wrapc(z);
+        }
+        kv[u] = v;
+        bk[u] = bucket(x, y, z);
+      }
+      const int first = kv[0] ? 0 : 1;
+      const int lst = kv[2] ? 2 : 1;
+      bool consec = true;
+      if (first == 0) consec = consec && bk[1] == bk[0] + 1;
+      if (lst == 2) consec = consec && bk[2] == bk[1] + 1;
+      if (consec) {
+        rb[p] = (p == 0) ? q + 1 : bucket_start(loc, toff, first == 0 ? bk[0] : bk[1]);
+        len[p] = max(0, bucket_start(loc, toff, (lst == 2 ? bk[2] : bk[1]) + 1) - rb[p]);
+        msk |= ((kv[0] ? 1 : 0) | 2 | (kv[2] ? 4 : 0)) << (3 * p);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          if (!kv[u]) continue;
+          int z = cz + u - 1;
+          if (!local) z = wrapc(z);
+          const int32_t key =
+              local ? (int32_t)(pack_cell(x, y, z) ^ salt) : (int32_t)pack_cell(x, y, z);
+          const int beg = (p == 0 && u == 1) ? q + 1 : bucket_start(loc, toff, bk[u]);
+          scan_cell(beg, bucket_start(loc, toff, bk[u] + 1), key, dx, dy, u - 1);
+        }
+      }
+    }
+    // the wave's LDS record of this element
+    ScreenOwner<T>& w = s_own[threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      w.lo[i] = me.v[i];
+      w.hi[i] = me.v[4 + i];
+    }
+    w.lo[3] = hh;
+    w.hi[3] = tl;
+    w.k = k;
+    w.nk = nk;
+    w.pk = pk;
+    w.salt = (int32_t)salt;
+    int acc = 0;
+#pragma unroll
+    for (int p = 0; p < N_PENCIL; ++p) {
+      if (p > 0) w.pre[p - 1] = acc;
+      w.rbp[p] = rb[p] - acc;
+      acc += len[p];
+    }
+    w.cell = (int32_t)pack_cell(cx, cy, cz);
+    w.msk = msk;
+    npairs = acc;
+    // the element's box in global coordinates (any periodic image) for the comparisons
+    // with large elements
+    const double gh = local ? C.h : cs.h;
+    const double go[3] = {local ? C.ox : 0.0, local ? C.oy : 0.0, local ? C.oz : 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      wl[i] = go[i] + ((double)(i == 0 ? cx : (i == 1 ? cy : cz)) * gh + (double)me.v[i]);
+      ex[i] = (double)me.v[4 + i] - (double)me.v[i];
+    }
+    if constexpr (SCR == 1) {
+      tlo = me.v[3];
+      thi = me.v[7];
+    } else {
+      const float4* eb = (const float4*)ebox_slot + (size_t)k * 2;
+      tlo = (double)eb[0].w + hc.tref;
+      thi = (double)eb[1].w + hc.tref;
+    }
+  } else if (q < n_norm + nl) {
+    own_large = true;
+    const LargeBox own = large[q - n_norm];
+    k = own.slot;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      wl[i] = own.wl[i];
+      ex[i] = own.ext[i];
+    }
+    tlo = own.tlo;
+    thi = own.thi;
+  }
+  // phase 2: the wave's pairs in lane order, two rounds of 64 per pass
+  int incl = npairs;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  const int off = incl - npairs;
+  const int total = __shfl(incl, 63, 64);
+  __syncthreads();  // the records are written
+  for (int base = 0; base < total; base += 128) {
+    int pia[2], oa[2], qa[2];
+    SBox<T> ba[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int p = base + 64 * u + lane;
+      // the element of pair p: the last lane whose first pair is at or before p
+      int o = 0, oo = 0;
+#pragma unroll
+      for (int st = 32; st > 0; st >>= 1) {
+        const int oc = __shfl(off, o + st, 64);
+        if (oc <= p) {
+          o += st;
+          oo = oc;
+        }
+      }
+      pia[u] = 0;
+      oa[u] = o;
+      qa[u] = -1;
+      if (p < total) {
+        const ScreenOwner<T>& w = s_own[wbase + o];
+        const int r = p - oo;
+        const int pi = (r >= w.pre[0]) + (r >= w.pre[1]) + (r >= w.pre[2]) + (r >= w.pre[3]);
+        pia[u] = pi;
+        qa[u] = w.rbp[pi] + r;
+        ba[u] = load_sbox<T>(sbox, qa[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (qa[u] < 0) continue;
+      const ScreenOwner<T>& w = s_own[wbase + oa[u]];
+      const int pi = pia[u];
+      const int dx = pi < 2 ? 0 : 1;
+      const int dy = pi == 0 ? 0 : (pi == 1 ? 1 : pi - 3);
+      const int32_t wc = w.cell;
+      int x = (wc & 1023) + dx, y = ((wc >> 10) & 1023) + dy;
+      if (!local) {
+        const int gnc = cs.nc;
+        x = x >= gnc ? x - gnc : x;
+        y = y < 0 ? y + gnc : (y >= gnc ? y - gnc : y);
+      }
+      const uint32_t c0 = pack_cell(x, y, (wc >> 20) & 1023);
+      const int mk = (w.msk >> (3 * pi)) & 7;
+      const int2 e = entry_key_slot<SCR>(sent, ba[u], qa[u]);
+      const uint32_t d = ((uint32_t)e.x ^ (uint32_t)w.salt) - c0;
+      int dz = 2;
+      if (d == 0u) dz = 0;
+      else if (d == (1u << 20)) dz = (mk & 4) ? 1 : 2;
+      else if (d == (uint32_t)(-(1 << 20))) dz = (mk & 1) ? -1 : 2;
+      const int m = e.y;
+      if (dz != 2 && m != w.nk && m != w.pk) {
+        SBox<T> me;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          me.v[i] = w.lo[i];
+          me.v[4 + i] = w.hi[i];
+        }
+        const T hh = w.lo[3];
+        if (box_overlap(me, ba[u], (T)dx * hh, (T)dy * hh, (T)dz * hh, w.hi[3])) push(w.k, m);
+      }
+    }
+  }
+  // tests against the large elements (two large ones: by the one of smaller slot)
+  if (k >= 0 && nl > 0) {
+    const int nk = nxt[k], pk = prv[k];
+    for (int a = 0; a < nl; ++a) {
+      const LargeBox lb = large[a];
+      const int m = lb.slot;
+      if (m == k) continue;
+      if (own_large && m < k) continue;
+      if (m == nk || m == pk) continue;
+      const double tt = hc.tol_t;
+      bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        ov = ov && wrap_overlap(wl[i], ex[i], lb.wl[i], lb.ext[i], P, hc.tolL);
+      if (ov) push(k, m);
+    }
+  }
+  __syncthreads();
+  // staged candidates go out in one reservation once half the buffer is used, and after
+  // the block's last chunk
+  const int staged = s_cnt;
+  if (staged >= SBUF_FLAT_FLUSH || last) {
+    const int cnt = min(staged, SBUF_FLAT);
+    if (threadIdx.x == 0 && cnt > 0) s_base = atomicAdd(&ctrl->n_cand, cnt);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += NT) {
+      const int idx = s_base + i;
+      if (idx < cap) cand[idx] = sbuf[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_cnt = 0;
+  }
+  __syncthreads();  // the buffer count and the records are free for the next chunk
+  }  // chunks
+}
+
 // The same half-shell screen, one thread per element, with the five pencil ranges read
 // from the element's PencilAux (written by k_scatter) instead of being looked up here:
 // a thread loads its entry and its 64-byte record, then scans its pencils. Pencils whose
@@ -3573,6 +3882,13 @@ void launch_screen_t(semipar_region* r, int n, int nb) {
 }
 
 template <int SCR>
+void launch_screen_flat_t(semipar_region* r, int n, int nb) {
+  k_screen_flat<SCR><<<xcd_grid(std::min(nb, SCREEN_GRID)), NT, 0, r->stream>>>(
+      n, r->sent, r->sbox, r->ebox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc,
+      r->P, r->cand, (int)r->cap_cand, r->ctrl, r->rid, r->rcell);
+}
+
+template <int SCR>
 void launch_screen_pre_t(semipar_region* r, int n, int nb) {
   k_screen_pre<SCR><<<xcd_grid(std::min(nb, SCREEN_GRID)), NT, 0, r->stream>>>(
       n, r->sent, r->sbox, r->ebox, r->saux, r->loc, r->toff, r->ntiles, r->large, r->hc, r->P,
@@ -3589,10 +3905,10 @@ void launch_screen(semipar_region* r, int n, int nb) {
   }
   const bool one = r->split == 1;
   if (r->screen == 1) {
-    if (one) launch_screen_t<1, 1>(r, n, nb);
+    if (one) launch_screen_flat_t<1>(r, n, nb);
     else launch_screen_t<1, N_PENCIL>(r, n, nb);
   } else {
-    if (one) launch_screen_t<2, 1>(r, n, nb);
+    if (one) launch_screen_flat_t<2>(r, n, nb);
     else launch_screen_t<2, N_PENCIL>(r, n, nb);
   }
 }
