@@ -170,13 +170,15 @@ def bench_batched(args):
     feat = S.region_features(rs)
     pred = cm.predict(feat)
     cfg = {"batch_frac": args.batch_frac, "screen_split": args.split,
-           "steps_per_sync": args.sync_steps, "lanes": args.lanes, "pack": args.pack}
+           "steps_per_sync": args.sync_steps, "lanes": args.lanes, "pack": args.pack,
+           "cell_factor": args.cell_factor}
     if args.tune:
         cfg = SC.autotune(rs, pred, screen=screen, cache=args.tune_cache or None, log=log)
         log(f"autotune: {cfg}")
     bp = SC.batch_points_for(rs, cfg)
     kw = dict(fast, batch_points=bp, screen_split=cfg["screen_split"],
-              steps_per_sync=cfg["steps_per_sync"], lanes=cfg["lanes"])
+              steps_per_sync=cfg["steps_per_sync"], lanes=cfg["lanes"],
+              cell_factor=cfg.get("cell_factor", 0.0))
     kw_learned = dict(kw, pack=cfg.get("pack", S.PACK_POINTS))
 
     for w in range(args.warmup):
@@ -266,6 +268,7 @@ def bench_batched(args):
                    "screen": args.screen, "graph": True, "batch_points": bp,
                    "screen_split": cfg["screen_split"], "steps_per_sync": cfg["steps_per_sync"],
                    "lanes": cfg["lanes"], "pack": cfg.get("pack", 0),
+                   "cell_factor": cfg.get("cell_factor", 0.0) or 1.15,
                    "p_intercommute": args.p,
                    "path": "batched + learned cost model (features, inference and schedule "
                            "inside the timed region)"},
@@ -282,12 +285,14 @@ def roofline_runs(S, rs, bp, cfg, screen, coin, screen_name):
     roofs = {}
     launch_config = (f"eager-1lane-bp{bp}-split{cfg['screen_split']}-sync{cfg['steps_per_sync']}"
                      f"-{screen_name}")
+    if cfg.get("cell_factor", 0.0):
+        launch_config += f"-cf{cfg['cell_factor']:g}"  # the default 1.15 goes unnamed
     for kname, kid in (("k_evolve", S.K_EVOLVE), ("k_screen", S.K_SCREEN)):
         rr = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=bp, cost=None, out=None,
                                 events=False, use_graph=False, screen=screen,
                                 screen_split=cfg["screen_split"],
                                 steps_per_sync=cfg["steps_per_sync"], timed_kernel=kid, lanes=1,
-                                **coin)
+                                cell_factor=cfg.get("cell_factor", 0.0), **coin)
         s2 = rr["stats"]
         ms, nl = s2["timed_kernel_ms"], max(s2["timed_kernel_launches"], 1)
         if kname == "k_evolve":
@@ -431,7 +436,7 @@ def roofline_only(args):
     rs = S.RegionSet.from_parts(parts, box, I.MATTER, device=True)
     screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
     cfg = {"batch_frac": args.batch_frac, "screen_split": args.split,
-           "steps_per_sync": args.sync_steps}
+           "steps_per_sync": args.sync_steps, "cell_factor": args.cell_factor}
     from paper_1011_4046_amd import scheduler as SC
     bp = SC.batch_points_for(rs, cfg)
     roof, other = roofline_runs(S, rs, bp, cfg, screen, dict(p=args.p, seed=args.seed),
@@ -517,6 +522,8 @@ def main():
     ap.add_argument("--split", type=int, default=1, help="screen threads per element (1 or 5)")
     ap.add_argument("--lanes", type=int, default=3, help="batches evolved concurrently")
     ap.add_argument("--sync-steps", type=int, default=32, help="lattice steps per host check")
+    ap.add_argument("--cell-factor", type=float, default=0.0,
+                    help="cell edge over the largest element extent (0: the library's 1.15)")
     ap.add_argument("--pack", type=int, default=0,
                     help="learned schedule: 0 = batches of equal points, 1 = of equal "
                          "predicted point-steps")

@@ -229,6 +229,12 @@ typedef struct semipar_evolve_params {
                              Results depend on (p, seed) only, never on batching or launch
                              order. Outside [0, 1] or NaN: SEMIPAR_E_ARG */
   uint64_t seed;          /* key of the crossings' draws (used when p < 1) */
+  double cell_factor;     /* edge of the next step's cells in units of this step's
+                             largest element extent (cell_size = 0 only); 0: the default,
+                             1.15. Any value in [1, 4] gives the same candidates and
+                             events (cells at least as wide as every element); smaller
+                             cells hold fewer entries but send more elements to the
+                             all-pairs path. Else SEMIPAR_E_ARG. Performance only */
 } semipar_evolve_params;
 
 /* most points of a sub-region evolved by persistent workgroups, and most crossings of

@@ -748,6 +748,8 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
   if (p->events && (!p->events_off || p->events_cap < 0)) return SEMIPAR_E_ARG;
   if (p->loops && (!p->loops_off || p->loops_cap < 0)) return SEMIPAR_E_ARG;
   if (p->evolve.loop_every < 0) return SEMIPAR_E_ARG;
+  const double cf = p->evolve.cell_factor;
+  if (!(cf == 0.0 || (cf >= 1.0 && cf <= 4.0))) return SEMIPAR_E_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   Runner R;
   R.t = t;

@@ -104,6 +104,12 @@ __device__ __forceinline__ int exit_face(const RegionGeom& G, const V4& P) {
 constexpr int32_t FS_ACTIVE = INT32_MAX;  // stop step of a point that still advances
 constexpr int32_t NO_ELEM = INT32_MIN;    // ecell of a point without an element this band
 
+// Default cell edge of the next step, in units of this step's largest element extent
+// (semipar_evolve_params.cell_factor overrides it): any value >= 1 gives the same
+// candidates; larger cells hold more entries, smaller ones send more elements to the
+// all-pairs path of large elements.
+constexpr double CELL_GROW = 1.15;
+
 struct Ctrl {
   int32_t step;        // lattice index of the current slice
   int32_t step_limit;  // a step is taken only while step < step_limit
@@ -2583,7 +2589,7 @@ __global__ __launch_bounds__(NT) void k_begin_min(Slices X, int n, const int32_t
 
 __global__ __launch_bounds__(1024) void k_begin_set(Ctrl* ctrl, int32_t step_limit, double t_end,
                                                     const uint64_t* __restrict__ blkred, int nblk,
-                                                    Cells cells, int set_cells) {
+                                                    Cells cells, int set_cells, double grow) {
   __shared__ uint64_t s_min[16], s_act[16];
   const int t = threadIdx.x;
   uint64_t mk = KEY_MAX, ak = 0;
@@ -2605,6 +2611,7 @@ __global__ __launch_bounds__(1024) void k_begin_set(Ctrl* ctrl, int32_t step_lim
     a += s_act[w];
   }
   if (set_cells) ctrl->cells = cells;
+  ctrl->grow = grow;
   ctrl->step_limit = step_limit;
   ctrl->t_end = t_end;
   ctrl->defer = 0;
@@ -4347,7 +4354,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
   c0.done = 1;
   c0.ext_key = 0;
   c0.box = d->box;
-  c0.grow = 1.15;
+  c0.grow = CELL_GROW;
   c0.tol = d->box * std::ldexp(1.0, -30);
   if (total > 0) {
     // gather all surfaces into one device record array
@@ -4423,6 +4430,8 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   if (p->screen != SEMIPAR_SCREEN_F64 && p->screen != SEMIPAR_SCREEN_F32) return SEMIPAR_E_ARG;
   const double p_ic = p->p == 0.0 ? 1.0 : p->p;
   if (!(p_ic > 0.0 && p_ic <= 1.0)) return SEMIPAR_E_ARG;
+  if (!(p->cell_factor == 0.0 || (p->cell_factor >= 1.0 && p->cell_factor <= 4.0)))
+    return SEMIPAR_E_ARG;
   if (r->broken) return SEMIPAR_E_STATE;
   semipar_evolve_stats zero{};
   if (st) *st = zero;
@@ -4485,7 +4494,9 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   }
   k_begin_min<<<blocks(n), NT, 0, r->stream>>>(r->X, n, stop_state(r), r->blkred, r->ctrl);
   // grid of the first step: the caller's cell size (kept fixed), else 1.25 x the
-  // initial element-size estimate, then adapted each step to the largest element
+  // initial element-size estimate, then adapted each step to the largest element (cell
+  // edge = grow x the previous step's largest extent)
+  const double grow = p->cell_factor > 0 ? p->cell_factor : CELL_GROW;
   Cells cells{};
   int set_cells = 0;
   if (p->cell_size > 0) {
@@ -4501,7 +4512,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     r->cells_fixed = false;
   }
   k_begin_set<<<1, 1024, 0, r->stream>>>(r->ctrl, seg_limit(before.step), p->t_end, r->blkred,
-                                         blocks(n), cells, set_cells);
+                                         blocks(n), cells, set_cells, grow);
   if (r->rcell) {
     // batch: every sub-region starts with cells fitting the largest initial element
     // (or the fixed size), then follows its own elements
@@ -4572,7 +4583,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
         checked = s;
         k_begin_min<<<blocks(n), NT, 0, r->stream>>>(r->X, n, stop_state(r), r->blkred, r->ctrl);
         k_begin_set<<<1, 1024, 0, r->stream>>>(r->ctrl, seg_limit(s), p->t_end, r->blkred,
-                                               blocks(n), Cells{}, 0);
+                                               blocks(n), Cells{}, 0, grow);
         HIPCHK(hipGetLastError());
         RCCHK(read_ctrl(r));
         if (!r->ctrl_h->done) continue;

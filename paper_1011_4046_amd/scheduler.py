@@ -81,6 +81,7 @@ TUNABLE = {
     "screen_split": [5, 1],
     "steps_per_sync": [64, 32, 128],
     "pack": [S.PACK_POINTS, S.PACK_WORK],         # equal points / equal predicted work
+    "cell_factor": [1.15, 1.0, 1.3, 1.6],         # cell edge / largest element extent
 }
 
 
@@ -111,7 +112,8 @@ def autotune(rs, cost=None, screen=S.SCREEN_F32, cache=None, max_steps=96, log=N
                                  out=None, events=False, use_graph=True, screen=screen,
                                  screen_split=cfg["screen_split"],
                                  steps_per_sync=cfg["steps_per_sync"], max_steps=max_steps,
-                                 lanes=cfg["lanes"], pack=cfg["pack"] if cost is not None else 0)
+                                 lanes=cfg["lanes"], pack=cfg["pack"] if cost is not None else 0,
+                                 cell_factor=cfg["cell_factor"])
         st = res["stats"]
         # time per point-step of the truncated schedule
         return st["makespan_ms"] / max(st["point_steps"], 1) * 1e6

@@ -69,7 +69,8 @@ class EvolveParams(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("cand_per_point", ctypes.c_double),
                 ("events_per_point", ctypes.c_double), ("timed_kernel", ctypes.c_int32),
                 ("screen_split", ctypes.c_int32), ("loop_every", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("p", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("persistent", ctypes.c_int32), ("p", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("cell_factor", ctypes.c_double)]
 
 
 class EvolveStats(ctypes.Structure):
@@ -273,14 +274,15 @@ class Region:
     def evolve(self, max_steps, t_end=float("inf"), screen=SCREEN_F64, intercommute=True,
                cell_size=0.0, steps_per_sync=0, use_graph=False, cand_per_point=0.0,
                events_per_point=0.0, timed_kernel=-1, screen_split=0, loop_every=0, p=1.0,
-               seed=0, persistent=0):
+               seed=0, persistent=0, cell_factor=0.0):
         """p: intercommutation probability in (0, 1]; seed: key of the crossings' draws;
-        persistent: evolve a batch of small regions by persistent workgroups."""
+        persistent: evolve a batch of small regions by persistent workgroups;
+        cell_factor: cell edge over the largest element extent (0: the default)."""
         prm = EvolveParams(int(max_steps), float(t_end), int(screen), int(bool(intercommute)),
                            float(cell_size), int(steps_per_sync), int(bool(use_graph)),
                            float(cand_per_point), float(events_per_point), int(timed_kernel),
                            int(screen_split), int(loop_every), int(persistent), float(p),
-                           int(seed))
+                           int(seed), float(cell_factor))
         st = EvolveStats()
         _check(lib().region_evolve(self.h, ctypes.byref(prm), ctypes.byref(st)), "region_evolve")
         return st.as_dict()
@@ -449,7 +451,7 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
                      screen=SCREEN_F64, intercommute=True, cell_size=0.0, steps_per_sync=0,
                      use_graph=False, cand_per_point=0.0, events_per_point=0.0,
                      screen_split=0, timed_kernel=-1, lanes=1, loop_every=0,
-                     pack=PACK_POINTS, p=1.0, seed=0, persistent=0):
+                     pack=PACK_POINTS, p=1.0, seed=0, persistent=0, cell_factor=0.0):
     """Run every region of rs; returns a dict with the stats, per-region logs, output
     records (out = "host": numpy; "device": torch uint8 CUDA tensor; None: not
     written), their offsets (4 per region + 1) and the events with offsets."""
@@ -470,7 +472,7 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
                             float(cell_size), int(steps_per_sync), int(bool(use_graph)),
                             float(cand_per_point), float(events_per_point), int(timed_kernel),
                             int(screen_split), int(loop_every), int(persistent), p_ic,
-                            int(seed))
+                            int(seed), float(cell_factor))
     total = int(rs.counts.sum())
     out_off = np.zeros(4 * nr + 1, dtype=np.int64)
     res = {}

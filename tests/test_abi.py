@@ -57,7 +57,8 @@ int main(void) {
   F(semipar_evolve_params, screen_split) F(semipar_evolve_params, loop_every)
   F(semipar_evolve_stats, timed_kernel_launches) F(semipar_evolve_stats, loop_points)
   F(semipar_evolve_stats, resolve_rounds) F(semipar_sched_params, pack)
-  F(semipar_evolve_params, p) F(semipar_evolve_params, seed) F(semipar_evolve_stats, passed)
+  F(semipar_evolve_params, p) F(semipar_evolve_params, seed) F(semipar_evolve_params, cell_factor)
+  F(semipar_evolve_stats, passed)
   F(semipar_loop, rep_id) F(semipar_loop, energy) F(semipar_loop, centre)
   F(semipar_tiling, surfaces) F(semipar_tiling, stream)
   F(semipar_sched_params, cost) F(semipar_sched_params, evolve) F(semipar_sched_params, out)

@@ -145,6 +145,28 @@ def test_schedule_policies_equal_oracle_region_by_region(S, case):
     check_against_oracle(res, parts, orc)
 
 
+@pytest.mark.parametrize("factor", [1.0, 1.3, 2.5, 4.0])
+def test_cell_factor_changes_nothing(S, factor):
+    """Cells of any edge from 1 to 4 times the largest element extent give the oracle's
+    results: the cell factor (which the autotuner searches) is performance only."""
+    say(f"case: schedule_regions BATCHED with cell factor {factor}, sizes {SIZES}, seed 200")
+    parts, box = I.region_batch(SIZES, seed=200)
+    orc = oracle_regions(parts, box, "sizes200")
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    res = S.schedule_regions(rs, S.SCHED_BATCHED, batch_points=6000, use_graph=True,
+                             screen=S.SCREEN_F32, lanes=2, cell_factor=factor)
+    check_against_oracle(res, parts, orc)
+
+
+def test_cell_factor_outside_its_range_is_refused(S):
+    parts, box = I.region_batch([400], seed=201)
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    for bad in (0.5, 4.5, -1.0, float("nan")):
+        with pytest.raises(S.SemiparError) as e:
+            S.schedule_regions(rs, S.SCHED_BATCHED, cell_factor=bad)
+        assert e.value.code == -1
+
+
 def test_schedule_device_resident_io_and_dependencies(S):
     """Device-resident input and output, and a dependency order: a region starts only
     in a later wave than all its predecessors; results unchanged."""
