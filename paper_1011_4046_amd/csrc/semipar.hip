@@ -340,6 +340,29 @@ __device__ __forceinline__ void write_frozen(semipar_point_rec* __restrict__ frz
   frz[k] = r;
 }
 
+// Runs of neighbouring lanes of a wave with the same bucket (lanes without one break
+// runs). head: this lane starts a run of `len` lanes; first: the lane starting the run
+// this lane is in. The lanes of a run share one atomic on their bucket's counter.
+struct LaneRun {
+  bool head;
+  int len, first;
+};
+__device__ __forceinline__ LaneRun lane_run(bool has, uint32_t b) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint32_t pb = __shfl_up(b, 1, 64);
+  const bool ph = __shfl_up(has ? 1 : 0, 1, 64) != 0;
+  LaneRun r;
+  r.head = has && (lane == 0 || !ph || pb != b);
+  const uint64_t heads = __ballot(r.head);
+  const uint64_t inmask = __ballot(has);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0..lane
+  const uint64_t after = (heads | ~inmask) & ~upto;  // run boundaries past this lane
+  r.len = (after ? __ffsll((unsigned long long)after) - 1 : 64) - lane;
+  const uint64_t hs = heads & upto;
+  r.first = hs ? 63 - __clzll((long long)hs) : 0;
+  return r;
+}
+
 // One step for every point: the diamond top X[n+1][k] (flat or first-order FRW) and,
 // when SCR != 0, the element of band n (k to next[k]): FP64 box, cell, bucket count.
 // BND: bounded region. Point k advances only when it is active, next[k] exists and is
@@ -355,7 +378,6 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
                                                sp::Period P, double hcoef, Ctrl* ctrl, HashCfg hc,
                                                void* __restrict__ ebox,
                                                int32_t* __restrict__ ecell,
-                                               int32_t* __restrict__ epos,
                                                int32_t* __restrict__ cnt,
                                                LargeBox* __restrict__ large,
                                                uint64_t* __restrict__ blkred,
@@ -533,27 +555,12 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
       ecell[k] = NO_ELEM;
     }
   }
-  // slots in bucket order: neighbouring lanes are neighbouring points of a string and
-  // often share a cell, so each run of lanes with one bucket reserves its places with a
-  // single atomic (the order of entries within a bucket is immaterial to the screen)
+  // bucket counts: neighbouring lanes are neighbouring points of a string and often share
+  // a cell, so each run of lanes with one bucket adds its size with a single atomic,
+  // whose result nobody waits for (k_scatter takes the places)
   if constexpr (SCR != 0) {
-    const int lane = (int)(threadIdx.x & 63);
-    const uint32_t pb = __shfl_up(hbk, 1, 64);
-    const bool ph = __shfl_up(hashed ? 1 : 0, 1, 64) != 0;
-    const bool head = hashed && (lane == 0 || !ph || pb != hbk);
-    const uint64_t heads = __ballot(head);
-    const uint64_t inmask = __ballot(hashed);
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0..lane
-    int base = 0;
-    if (head) {
-      const uint64_t after = (heads | ~inmask) & ~upto;  // run boundaries past this lane
-      const int end = after ? __ffsll((unsigned long long)after) - 1 : 64;
-      base = atomicAdd(&cnt[hbk], end - lane);
-    }
-    const uint64_t hs = heads & upto;
-    const int hl = hs ? 63 - __clzll((long long)hs) : 0;
-    base = __shfl(base, hl, 64);
-    if (hashed) epos[k] = base + (lane - hl);
+    const LaneRun lr = lane_run(hashed, hbk);
+    if (lr.head) atomicAdd(&cnt[hbk], lr.len);
   }
   // batch: largest element extent per sub-region (one atomic per wave when the wave
   // holds one sub-region)
@@ -607,7 +614,7 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
 
 constexpr int MAX_TILES = 2048;  // buckets <= 2^23
 
-// Per-tile exclusive scan of the bucket counts (counts are reset for the next step);
+// Per-tile exclusive scan of the bucket counts (k_scatter takes them back to zero);
 // tile totals go to tile_tot, which k_toff scans. (The last workgroup could scan them
 // instead, but making the totals visible to it takes a device-scope fence in every
 // workgroup, which writes back the L2: 12 times slower than a second launch.)
@@ -649,7 +656,6 @@ __global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     l4[i] = make_int4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
-    c4[i] = make_int4(0, 0, 0, 0);
   }
   if (t == 255) tile_tot[blockIdx.x] = sh[255];
 }
@@ -702,7 +708,7 @@ __device__ __forceinline__ void pencil_offsets(int p, int& dx, int& dy) {
 // the key is the packed local cell xor the sub-region's salt.
 template <int SCR>
 __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict__ ecell,
-                                                const int32_t* __restrict__ epos,
+                                                int32_t* __restrict__ cnt,
                                                 const int32_t* __restrict__ loc,
                                                 const int32_t* __restrict__ toff,
                                                 const void* __restrict__ ebox,
@@ -718,23 +724,38 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
   if (ctrl->done) return;
   const int nc = ctrl->cells.nc;
   const Cells cs = ctrl->cells;
-  for (int k = blockIdx.x * NT + threadIdx.x; k < n; k += gridDim.x * NT) {
+  const int nw = (n + 63) >> 6;
+  // the same trip count for every thread (wave-wide run detection below)
+  const int span = gridDim.x * NT;
+  const int iters = (n + span - 1) / span;
+  for (int it = 0; it < iters; ++it) {
+  const int k = it * span + blockIdx.x * NT + threadIdx.x;
   // no point of a cleared wave advanced this step, so none has an element
-  if (!wlive[__builtin_amdgcn_readfirstlane(k >> 6)]) continue;
-  const int32_t c = ecell[k];
-  if (c < 0) continue;
+  const int wv = __builtin_amdgcn_readfirstlane(k >> 6);
+  if (wv >= nw || !wlive[wv]) continue;
+  const int32_t c = k < n ? ecell[k] : -1;
+  const bool has = c >= 0;
   const int x = c & 1023, y = (c >> 10) & 1023, z = (c >> 20) & 1023;
-  uint32_t b;
+  uint32_t b = 0;
   int32_t key = c;
   RCell C{};
-  if (rcell) {
-    C = rcell[rid[k]];
-    b = (C.base + cell_index(C.nc, x, y, z)) & hc.bmask;
-    key = (int32_t)((uint32_t)c ^ C.salt);
-  } else {
-    b = bucket_of(nc, hc.bmask, x, y, z);
+  if (has) {
+    if (rcell) {
+      C = rcell[rid[k]];
+      b = (C.base + cell_index(C.nc, x, y, z)) & hc.bmask;
+      key = (int32_t)((uint32_t)c ^ C.salt);
+    } else {
+      b = bucket_of(nc, hc.bmask, x, y, z);
+    }
   }
-  const int pos = bucket_start(loc, toff, b) + epos[k];
+  // places in the bucket: each run of lanes with one bucket takes the top places left
+  // by one atomic decrement of its count (which so returns to zero for the next step)
+  const LaneRun lr = lane_run(has, b);
+  int base = 0;
+  if (lr.head) base = atomicSub(&cnt[b], lr.len) - lr.len;
+  base = __shfl(base, lr.first, 64) + ((int)(threadIdx.x & 63) - lr.first);
+  if (!has) continue;
+  const int pos = bucket_start(loc, toff, b) + base;
   if (saux) {
     // the five neighbour pencils' ranges of sorted entries (the screen's lookups, done
     // here where the element's grid and bucket offsets are already at hand)
@@ -3633,7 +3654,7 @@ struct semipar_region {
   // step buffers (configured per evolve parameters)
   int screen = -1;
   void* ebox = nullptr;
-  int32_t *ecell = nullptr, *epos = nullptr;
+  int32_t* ecell = nullptr;
   LargeBox* large = nullptr;
   HashCfg hc{};
   int32_t *cnt = nullptr, *loc = nullptr, *tile_tot = nullptr, *toff = nullptr;
@@ -3684,7 +3705,6 @@ namespace {
 void free_step_buffers(semipar_region* r) {
   dfree(r->ebox);
   dfree(r->ecell);
-  dfree(r->epos);
   dfree(r->large);
   dfree(r->cnt);
   dfree(r->loc);
@@ -3700,7 +3720,7 @@ void free_step_buffers(semipar_region* r) {
   dfree(r->saux);
   r->saux = nullptr;
   r->ebox = nullptr;
-  r->ecell = r->epos = r->cnt = r->loc = r->tile_tot = r->toff = r->used = nullptr;
+  r->ecell = r->cnt = r->loc = r->tile_tot = r->toff = r->used = nullptr;
   r->sent = nullptr;
   r->sbox = nullptr;
   r->large = nullptr;
@@ -3774,7 +3794,6 @@ int configure(semipar_region* r, const semipar_evolve_params* p) {
   // points that have stopped are never visited again: their cell must read NO_ELEM
   k_fill_i32<<<blocks(cap), NT, 0, r->stream>>>(r->ecell, (uint64_t)cap, NO_ELEM);
   HIPCHK(hipGetLastError());
-  HIPCHK(dalloc(&r->epos, cap));
   HIPCHK(dalloc(&r->large, cap));
   HIPCHK(dalloc(&r->cnt, r->hc.B));
   HIPCHK(dalloc(&r->loc, (size_t)r->hc.B + 1));
@@ -3855,7 +3874,7 @@ int grow_step_caps(semipar_region* r, int defer) {
 template <bool FRW, int SCR, bool BND>
 void launch_evolve_t(semipar_region* r, int n, int nb) {
   k_evolve<FRW, SCR, BND><<<nb, NT, 0, r->stream>>>(
-      r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell, r->epos,
+      r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell,
       r->cnt, r->large, r->blkred, (BND || r->removed) ? r->fstep : nullptr, r->face, r->frz,
       r->geom, r->geoms, r->rid, r->rcell, r->rext, r->wlive);
 }
@@ -3940,11 +3959,11 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
     k_toff<<<1, 1024, 0, s>>>(r->tile_tot, r->ntiles, r->toff, r->ctrl);
     PencilAux* saux = r->split == SPLIT_PRE ? r->saux : nullptr;
     if (r->screen == 1)
-      k_scatter<1><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
+      k_scatter<1><<<nbe, NT, 0, s>>>(n, r->ecell, r->cnt, r->loc, r->toff, r->ebox, r->sent,
                                       r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl, saux,
                                       r->nxt, r->prv);
     else
-      k_scatter<2><<<nbe, NT, 0, s>>>(n, r->ecell, r->epos, r->loc, r->toff, r->ebox, r->sent,
+      k_scatter<2><<<nbe, NT, 0, s>>>(n, r->ecell, r->cnt, r->loc, r->toff, r->ebox, r->sent,
                                       r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl, saux,
                                       r->nxt, r->prv);
     mark(r, SEMIPAR_K_SCATTER, 2 * i + 1);
