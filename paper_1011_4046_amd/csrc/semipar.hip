@@ -141,8 +141,11 @@ struct Ctrl {
   int32_t pb_step;    // persistent launch: the furthest slice any of its regions reached
 };
 
+// The last three slices of every point, one 32-byte vertex (x, y, z, t) per point per
+// slice: a gather through next[] then touches one 32-byte piece (two 16-byte loads), where
+// four separate coordinate arrays took four loads from four cache lines.
 struct Slices {
-  double* p[3][4];  // [slice mod 3][x, y, z, t]
+  double4* p[3];  // [slice mod 3][point]
 };
 
 struct EvCand {
@@ -190,13 +193,11 @@ constexpr double RCELL_W = 2.5;  // grid side in units of g
 constexpr int REXT_STRIDE = 16;
 
 __device__ __forceinline__ V4 ld(const Slices& X, int s, int k) {
-  return V4{X.p[s][0][k], X.p[s][1][k], X.p[s][2][k], X.p[s][3][k]};
+  const double4 v = X.p[s][k];
+  return V4{v.x, v.y, v.z, v.w};
 }
 __device__ __forceinline__ void st(const Slices& X, int s, int k, const V4& v) {
-  X.p[s][0][k] = v.x;
-  X.p[s][1][k] = v.y;
-  X.p[s][2][k] = v.z;
-  X.p[s][3][k] = v.t;
+  X.p[s][k] = make_double4(v.x, v.y, v.z, v.t);
 }
 
 __host__ __device__ __forceinline__ uint64_t order_key(double v) {
@@ -2584,7 +2585,7 @@ __global__ __launch_bounds__(NT) void k_begin_min(Slices X, int n, const int32_t
   uint64_t key = KEY_MAX;
   uint32_t act = 0;
   if (k < n && (!fstep || fstep[k] == FS_ACTIVE)) {
-    key = order_key(X.p[s % 3][3][k]);
+    key = order_key(X.p[s % 3][k].w);
     act = 1;
   }
   __shared__ uint64_t wmin[NT / 64];
@@ -4202,7 +4203,7 @@ void region_destroy(semipar_region* r) {
   drop_graph(r);
   free_step_buffers(r);
   for (int s = 0; s < 3; ++s)
-    for (int c = 0; c < 4; ++c) dfree(r->X.p[s][c]);
+    dfree(r->X.p[s]);
   dfree(r->nxt);
   dfree(r->prv);
   dfree(r->id);
@@ -4302,8 +4303,7 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
   }
   const int64_t cap = std::max<int64_t>(r->cap, 1);
   for (int s = 0; s < 3; ++s)
-    for (int c = 0; c < 4; ++c)
-      if (dalloc(&r->X.p[s][c], cap) != hipSuccess) return fail(oom(__LINE__));
+    if (dalloc(&r->X.p[s], cap) != hipSuccess) return fail(oom(__LINE__));
   if (dalloc(&r->nxt, cap) != hipSuccess || dalloc(&r->prv, cap) != hipSuccess ||
       dalloc(&r->id, cap) != hipSuccess || dalloc(&r->ctrl, 1) != hipSuccess ||
       dalloc(&r->blkred, 4 * (size_t)blocks(cap)) != hipSuccess ||
