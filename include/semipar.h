@@ -231,10 +231,11 @@ typedef struct semipar_evolve_params {
   uint64_t seed;          /* key of the crossings' draws (used when p < 1) */
   double cell_factor;     /* edge of the next step's cells in units of this step's
                              largest element extent (cell_size = 0 only); 0: the default,
-                             1.15. Any value in [1, 4] gives the same candidates and
-                             events (cells at least as wide as every element); smaller
-                             cells hold fewer entries but send more elements to the
-                             all-pairs path. Else SEMIPAR_E_ARG. Performance only */
+                             1.15. Any value in [1, 4] gives the same events; smaller
+                             cells hold fewer entries, and elements that outgrow the
+                             previous step's largest are screened apart (each walks the
+                             cells its box reaches). Else SEMIPAR_E_ARG. Performance
+                             only */
 } semipar_evolve_params;
 
 /* most points of a sub-region evolved by persistent workgroups, and most crossings of

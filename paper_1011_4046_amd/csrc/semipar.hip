@@ -664,6 +664,8 @@ __global__ __launch_bounds__(256) void k_scan(int32_t* __restrict__ cnt, int32_t
 constexpr int POINT_GRID = 2048;  // most workgroups of the grid-stride per-point kernels
 
 constexpr int SCREEN_GRID = 2560;  // most workgroups of the screen (a multiple of 8)
+constexpr int LARGE_GRID = 256;    // workgroups of k_screen_large (a wave per large element)
+constexpr int LARGE_CELLS = 4096;  // most cells a large element's wave visits one by one
 
 __device__ __forceinline__ int bucket_start(const int32_t* loc, const int32_t* s_toff, uint32_t b) {
   return loc[b] + s_toff[b >> TS_LOG];
@@ -893,6 +895,18 @@ __device__ __forceinline__ int2 entry_key_slot(const int2* __restrict__ sent,
                                                int q) {
   if constexpr (SCR == 2) return make_int2(__float_as_int(b.v[3]), __float_as_int(b.v[7]));
   else return sent[q];
+}
+
+// Key and slot of sorted entry q (FP32: from the box's fourth components).
+template <int SCR>
+__device__ __forceinline__ int2 sent_key_slot(const int2* __restrict__ sent, const void* sbox,
+                                              int q) {
+  if constexpr (SCR == 2) {
+    const float4* p = (const float4*)sbox + (size_t)q * 2;
+    return make_int2(__float_as_int(p[0].w), __float_as_int(p[1].w));
+  } else {
+    return sent[q];
+  }
 }
 
 constexpr int SBUF = 1024;       // candidates staged in LDS per block (more go straight to memory)
@@ -1278,7 +1292,7 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
   int npairs = 0;
   int k = -1;
   bool own_large = false;
-  double wl[3], ex[3], tlo = 0.0, thi = 0.0;  // wrapped box (for large partners)
+  double wl[3], ex[3], tlo = 0.0, thi = 0.0;  // a large element's wrapped box
   if (q < n_norm) {
     // phase 1: the element, its grid and its five pencil ranges
     const SBox<T> me = load_sbox<T>(sbox, q);
@@ -1386,23 +1400,6 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
     w.cell = (int32_t)pack_cell(cx, cy, cz);
     w.msk = msk;
     npairs = acc;
-    // the element's box in global coordinates (any periodic image) for the comparisons
-    // with large elements
-    const double gh = local ? C.h : cs.h;
-    const double go[3] = {local ? C.ox : 0.0, local ? C.oy : 0.0, local ? C.oz : 0.0};
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      wl[i] = go[i] + ((double)(i == 0 ? cx : (i == 1 ? cy : cz)) * gh + (double)me.v[i]);
-      ex[i] = (double)me.v[4 + i] - (double)me.v[i];
-    }
-    if constexpr (SCR == 1) {
-      tlo = me.v[3];
-      thi = me.v[7];
-    } else {
-      const float4* eb = (const float4*)ebox_slot + (size_t)k * 2;
-      tlo = (double)eb[0].w + hc.tref;
-      thi = (double)eb[1].w + hc.tref;
-    }
   } else if (q < n_norm + nl) {
     own_large = true;
     const LargeBox own = large[q - n_norm];
@@ -1488,8 +1485,9 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
       }
     }
   }
-  // tests against the large elements (two large ones: by the one of smaller slot)
-  if (k >= 0 && nl > 0) {
+  // two large elements: tested by the one of smaller slot (large against hashed ones:
+  // k_screen_large)
+  if (own_large && nl > 0) {
     const int nk = nxt[k], pk = prv[k];
     for (int a = 0; a < nl; ++a) {
       const LargeBox lb = large[a];
@@ -1522,6 +1520,119 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
   }
   __syncthreads();  // the buffer count and the records are free for the next chunk
   }  // chunks
+}
+
+// Large elements against the hashed ones, for the screen that leaves those pairs out
+// (k_screen_flat): one wave per large element walks the grid cells its box can reach
+// (every hashed element lies in the cell of its lower corner, clamped to the grid, and
+// spans less than a cell, so an overlapping one has its corner in [lo - h, hi] per
+// axis), a lane per cell, and tests that cell's entries in the frame of the element's
+// grid: the local grid of its sub-region (clamped cells) or the periodic box's (cells
+// wrapped). Spatial test with the large-element slack; the exact 4-D test follows in
+// k_confirm. Each (large, hashed) pair is seen once: the hashed element sits in one cell.
+template <int SCR>
+__global__ __launch_bounds__(NT) void k_screen_large(
+    const int2* __restrict__ sent, const void* __restrict__ sbox,
+    const int32_t* __restrict__ nxt, const int32_t* __restrict__ prv,
+    const int32_t* __restrict__ loc, const int32_t* __restrict__ toff,
+    int ntiles, const LargeBox* __restrict__ large, HashCfg hc, sp::Period P,
+    int2* __restrict__ cand, int cap, Ctrl* ctrl, const int32_t* __restrict__ rid,
+    const RCell* __restrict__ rcell) {
+  if (ctrl->done) return;
+  const int n_norm = toff[ntiles];
+  using T = typename std::conditional<SCR == 1, double, float>::type;
+  const int nl = ctrl->n_large;
+  const Cells cs = ctrl->cells;
+  const bool local = rcell != nullptr;
+  if (!local && cs.nc == 0) return;  // no grid: every element is large
+  const int lane = (int)(threadIdx.x & 63);
+  const int nwave = (int)(gridDim.x * (NT / 64));
+  for (int a = (int)(blockIdx.x * (NT / 64) + (threadIdx.x >> 6)); a < nl; a += nwave) {
+    const LargeBox L = large[a];
+    const int k = L.slot;
+    const int nk = nxt[k], pk = prv[k];
+    RCell C{};
+    int nc = cs.nc;
+    double h = cs.h, inv_h = cs.inv_h;
+    uint32_t salt = 0;
+    double lo[3];  // the element's lower corner in the grid's frame
+    if (local) {
+      C = rcell[rid[k]];
+      nc = C.nc;
+      h = C.h;
+      inv_h = C.inv_h;
+      salt = C.salt;
+      const double o[3] = {C.ox, C.oy, C.oz};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double d = L.wl[c] - o[c];
+        lo[c] = d - P.box * P.nearest(d);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lo[c] = L.wl[c];
+    }
+    // cell range per axis; a wrapped range of nc or more cells is the whole axis
+    int c0[3], cn[3];
+    int total = 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int a0 = (int)floor((lo[c] - h - hc.tolL) * inv_h);
+      int a1 = (int)floor((lo[c] + L.ext[c] + hc.tolL) * inv_h);
+      if (local) {
+        a0 = a0 < 0 ? 0 : (a0 > nc - 1 ? nc - 1 : a0);
+        a1 = a1 < 0 ? 0 : (a1 > nc - 1 ? nc - 1 : a1);
+      } else if (a1 - a0 + 1 >= nc) {
+        a0 = 0;
+        a1 = nc - 1;
+      }
+      c0[c] = a0;
+      cn[c] = a1 - a0 + 1;
+      total *= cn[c];
+    }
+    // entry q2 of cell cc against the element
+    auto test = [&](int q2, const int (&cc)[3], int32_t key, bool check_region) {
+      const SBox<T> e = load_sbox<T>(sbox, q2);
+      const int2 ks = entry_key_slot<SCR>(sent, e, q2);
+      const int m = ks.y;
+      if (ks.x != key || m == k || m == nk || m == pk) return;
+      if (check_region && rid[m] != rid[k]) return;
+      bool ov = true;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double elo = (double)cc[c] * h + (double)e.v[c];
+        const double eex = (double)e.v[4 + c] - (double)e.v[c];
+        if (local)
+          ov = ov && elo <= lo[c] + L.ext[c] + hc.tolL && lo[c] <= elo + eex + hc.tolL;
+        else
+          ov = ov && wrap_overlap(lo[c], L.ext[c], elo, eex, P, hc.tolL);
+      }
+      if (ov) push_cand(ctrl, cand, cap, k, m);
+    };
+    if (total <= LARGE_CELLS) {
+      for (int i = lane; i < total; i += 64) {
+        int cc[3] = {c0[0] + i % cn[0], c0[1] + (i / cn[0]) % cn[1], c0[2] + i / (cn[0] * cn[1])};
+        if (!local)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) cc[c] = ((cc[c] % nc) + nc) % nc;
+        const uint32_t b = local ? (C.base + cell_index(nc, cc[0], cc[1], cc[2])) & hc.bmask
+                                 : bucket_of(nc, hc.bmask, cc[0], cc[1], cc[2]);
+        const int32_t key = (int32_t)(pack_cell(cc[0], cc[1], cc[2]) ^ salt);
+        const int beg = bucket_start(loc, toff, b), end = bucket_start(loc, toff, b + 1);
+        for (int q2 = beg; q2 < end; ++q2) test(q2, cc, key, false);
+      }
+    } else {
+      // an element reaching more cells than there are worth visiting (cells much smaller
+      // than it, e.g. a fixed small cell size): every hashed entry of its region instead,
+      // its cell read from its key
+      for (int q2 = lane; q2 < n_norm; q2 += 64) {
+        const int2 ks = sent_key_slot<SCR>(sent, sbox, q2);
+        const uint32_t u = (uint32_t)ks.x ^ salt;
+        const int cc[3] = {(int)(u & 1023), (int)((u >> 10) & 1023), (int)((u >> 20) & 1023)};
+        test(q2, cc, ks.x, local);
+      }
+    }
+  }
 }
 
 // The same half-shell screen, one thread per element, with the five pencil ranges read
@@ -3913,6 +4024,9 @@ void launch_screen_flat_t(semipar_region* r, int n, int nb) {
   k_screen_flat<SCR><<<xcd_grid(std::min(nb, SCREEN_GRID)), NT, 0, r->stream>>>(
       n, r->sent, r->sbox, r->ebox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc,
       r->P, r->cand, (int)r->cap_cand, r->ctrl, r->rid, r->rcell);
+  k_screen_large<SCR><<<LARGE_GRID, NT, 0, r->stream>>>(
+      r->sent, r->sbox, r->nxt, r->prv, r->loc, r->toff, r->ntiles, r->large, r->hc, r->P,
+      r->cand, (int)r->cap_cand, r->ctrl, r->rid, r->rcell);
 }
 
 template <int SCR>
