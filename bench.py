@@ -93,6 +93,21 @@ def counted_traffic(kernel, launch_config):
     return None
 
 
+def table1(st):
+    """The six metrics of the paper's comparison table (Section "Performance"), with lanes
+    in the place of processors: total busy time of the lanes on batches ("CPU time"),
+    makespan ("elapsed time"), the lanes' summed lifetimes ("total real time"), their
+    time average ("average number of processors"), busy over held ("utilization") and
+    busy over elapsed ("degree of parallelism")."""
+    el = max(st["makespan_ms"], 1e-9)
+    held = max(st["lane_held_ms"], 1e-9)
+    return {"cpu_ms": round(st["lane_busy_ms"], 2), "elapsed_ms": round(st["makespan_ms"], 2),
+            "real_ms": round(st["lane_held_ms"], 2), "avg_lanes": round(held / el, 3),
+            "utilisation_pct": round(100.0 * st["lane_busy_ms"] / held, 2),
+            "parallelism": round(st["lane_busy_ms"] / el, 3),
+            "lanes_started": st["lanes_started"]}
+
+
 def make_inputs(args):
     from paper_1011_4046_amd import inputs as I
     t = time.perf_counter()
@@ -209,8 +224,19 @@ def bench_batched(args):
                          "parallelism": busy / max(st["makespan_ms"], 1e-9),
                          "lane_utilisation": busy / max(cfg["lanes"] * st["makespan_ms"], 1e-9),
                          "predict_ms": runs[0]["predict_ms"],
-                         "corr_log_pred_log_steps": round(corr, 4)}}
+                         "corr_log_pred_log_steps": round(corr, 4),
+                         "table1_held_pool": table1(st)}}
     del runs
+    # the same schedule under the paper's variable-size worker pool (lanes sleep, exit
+    # when nothing comes for lane_sleep_ms, are started again when batches wait
+    # lane_submit_ms): Table 1's six metrics, not part of the timed value
+    re_ = SC.learned_schedule(rs, cm, lane_sleep_ms=args.lane_sleep_ms,
+                              lane_submit_ms=args.lane_submit_ms, **kw_learned)
+    torch.cuda.synchronize()
+    extra["learned"]["table1_elastic_pool"] = dict(
+        table1(re_["stats"]), lane_sleep_ms=args.lane_sleep_ms,
+        lane_submit_ms=args.lane_submit_ms)
+    del re_
 
     # point-count heuristic, same batch size
     t = time.perf_counter()
@@ -522,6 +548,11 @@ def main():
     ap.add_argument("--split", type=int, default=1, help="screen threads per element (1 or 5)")
     ap.add_argument("--lanes", type=int, default=3, help="batches evolved concurrently")
     ap.add_argument("--sync-steps", type=int, default=32, help="lattice steps per host check")
+    ap.add_argument("--lane-sleep-ms", type=float, default=2.0,
+                    help="elastic worker pool leg: a lane exits after sleeping this long")
+    ap.add_argument("--lane-submit-ms", type=float, default=1.0,
+                    help="elastic worker pool leg: lanes are started again once batches have "
+                         "waited this long")
     ap.add_argument("--cell-factor", type=float, default=0.0,
                     help="cell edge over the largest element extent (0: the library's 1.15)")
     ap.add_argument("--pack", type=int, default=0,

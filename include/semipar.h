@@ -464,6 +464,14 @@ typedef struct semipar_sched_params {
                            (stats.loops is the total). NULL: not returned. */
   int64_t loops_cap;
   int64_t* loops_off;
+  double lane_sleep_ms;  /* BATCHED: 0: every lane is held for the whole call. > 0: the
+                            paper's variable-size worker pool (Section "Implementation"):
+                            a lane with nothing to do sleeps, is woken by new batches, and
+                            exits once it has slept this long; */
+  double lane_submit_ms; /* when batches have waited this long for lanes, the manager
+                            starts lanes again, up to `lanes` (the pool's job submission).
+                            Results do not depend on either; stats report the lanes'
+                            summed lifetimes (lane_held_ms) */
 } semipar_sched_params;
 
 typedef struct semipar_sched_stats {
@@ -482,6 +490,11 @@ typedef struct semipar_sched_stats {
   int64_t timed_kernel_launches; /* and the number of its launches that did work */
   int64_t loops;                 /* loops recorded and removed over all regions */
   int64_t passed;                /* crossings that passed through (p < 1) */
+  double lane_held_ms;   /* BATCHED: summed lifetimes of the lanes (from start to exit):
+                            the paper's "total real time" (Table 1) */
+  double lane_busy_ms;   /* summed wall time lanes spent on batches (build, evolve,
+                            results): its "total CPU time" */
+  int64_t lanes_started; /* lanes started, the first `lanes` included */
 } semipar_sched_stats;
 
 /* Run every region of the tiling on this GPU, in dependency order (paper: manager and

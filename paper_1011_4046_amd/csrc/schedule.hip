@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -622,54 +623,121 @@ struct Runner {
     std::vector<int32_t> live;
     if (rc == SEMIPAR_OK) rc = drain(live);
     if (rc == SEMIPAR_OK) dispatch(live);
-    std::vector<std::thread> th;
-    if (rc == SEMIPAR_OK)
-      for (int l = 0; l < lanes; ++l)
-        th.emplace_back([&, l]() {
-          for (;;) {
-            size_t i;
-            {
-              std::unique_lock<std::mutex> lk(mu);
-              cv_lane.wait(lk, [&] { return stop || !jobq.empty(); });
-              if (jobq.empty()) return;
-              i = jobq.back();
-              jobq.pop_back();
-              ++running;
-            }
-            Batch& b = bs[i];
-            int brc = build_batch(b, ls[l]);
-            if (brc == SEMIPAR_OK) brc = region_evolve(b.reg, &p->evolve, &b.es);
-            if (brc == SEMIPAR_E_OVERFLOW && p->evolve.persistent) {
-              // a step held more crossings than a persistent workgroup keeps: the
-              // batch runs again from its surfaces on the step kernels
-              region_destroy(b.reg);
-              b.reg = nullptr;
-              semipar_evolve_params e2 = p->evolve;
-              e2.persistent = 0;
-              brc = build_batch(b, ls[l]);
-              if (brc == SEMIPAR_OK) brc = region_evolve(b.reg, &e2, &b.es);
-            }
-            if (brc == SEMIPAR_OK) brc = harvest(b, stage[l], stage_cap[l]);
-            if (brc != SEMIPAR_OK) b.msg = semipar_last_error();
-            {
-              std::lock_guard<std::mutex> lk(mu);
-              b.rc = brc;
-              done.push_back(i);
-              --running;
-            }
+    // The worker pool (Section "Implementation"): lanes take batches from jobq. With
+    // lane_sleep_ms > 0 the pool is elastic as the paper's: a lane with nothing to do
+    // sleeps, is woken by new batches, and exits once it has slept lane_sleep_ms; when
+    // batches have waited lane_submit_ms for a lane, the manager starts lanes again (up to
+    // `lanes`, in free slots). Lifetimes and busy times are summed for the stats.
+    const double sleep_ms = p->lane_sleep_ms, submit_ms = p->lane_submit_ms;
+    const bool elastic = sleep_ms > 0.0;
+    const auto tb0 = std::chrono::steady_clock::now();
+    auto now_ms = [&]() {
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb0)
+          .count();
+    };
+    std::vector<std::thread> th((size_t)lanes);
+    std::vector<char> alive((size_t)lanes, 0);
+    int n_alive = 0;
+    double held_ms = 0.0, busy_ms = 0.0;
+    int64_t started = 0;
+    auto lane_body = [&](int l, double t_start) {
+      for (;;) {
+        size_t i;
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          auto ready = [&] { return stop || !jobq.empty(); };
+          bool got = true;
+          if (elastic)
+            got = cv_lane.wait_for(lk, std::chrono::duration<double, std::milli>(sleep_ms), ready);
+          else
+            cv_lane.wait(lk, ready);
+          if (!got || jobq.empty()) {
+            // slept with nothing to do, or the run is over: the lane exits (last use of mu)
+            alive[l] = 0;
+            --n_alive;
+            held_ms += now_ms() - t_start;
             cv_mgr.notify_one();
+            return;
           }
-        });
+          i = jobq.back();
+          jobq.pop_back();
+          ++running;
+        }
+        const double tb = now_ms();
+        Batch& b = bs[i];
+        int brc = build_batch(b, ls[l]);
+        if (brc == SEMIPAR_OK) brc = region_evolve(b.reg, &p->evolve, &b.es);
+        if (brc == SEMIPAR_E_OVERFLOW && p->evolve.persistent) {
+          // a step held more crossings than a persistent workgroup keeps: the
+          // batch runs again from its surfaces on the step kernels
+          region_destroy(b.reg);
+          b.reg = nullptr;
+          semipar_evolve_params e2 = p->evolve;
+          e2.persistent = 0;
+          brc = build_batch(b, ls[l]);
+          if (brc == SEMIPAR_OK) brc = region_evolve(b.reg, &e2, &b.es);
+        }
+        if (brc == SEMIPAR_OK) brc = harvest(b, stage[l], stage_cap[l]);
+        if (brc != SEMIPAR_OK) b.msg = semipar_last_error();
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          b.rc = brc;
+          done.push_back(i);
+          --running;
+          busy_ms += now_ms() - tb;
+        }
+        cv_mgr.notify_one();
+      }
+    };
+    auto start_lane = [&](int l) {  // with mu held; slot l's previous lane has returned
+      if (th[(size_t)l].joinable()) th[(size_t)l].join();
+      alive[(size_t)l] = 1;
+      ++n_alive;
+      ++started;
+      th[(size_t)l] = std::thread(lane_body, l, now_ms());
+    };
+    if (rc == SEMIPAR_OK) {
+      std::lock_guard<std::mutex> lk(mu);
+      for (int l = 0; l < lanes; ++l) start_lane(l);
+    }
+    double waiting_since = -1.0;  // batches waiting for a lane since then (elastic pool)
     cv_lane.notify_all();
     std::vector<int32_t> fin;
     while (rc == SEMIPAR_OK) {
       std::vector<size_t> got;
+      bool over = false;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_mgr.wait(lk, [&] { return !done.empty() || (running == 0 && jobq.empty()); });
+        auto ev = [&] { return !done.empty() || (running == 0 && jobq.empty()); };
+        if (elastic) {
+          cv_mgr.wait_for(lk, std::chrono::duration<double, std::milli>(
+                                  std::max(0.05, std::min(submit_ms, sleep_ms) / 4)), ev);
+          // batches waiting for more lanes than are idle: start lanes once that has
+          // lasted lane_submit_ms
+          const int idle = n_alive - running;
+          if ((int)jobq.size() > idle && n_alive < lanes) {
+            if (waiting_since < 0.0) waiting_since = now_ms();
+            if (now_ms() - waiting_since >= submit_ms) {
+              int want = (int)jobq.size() - idle;
+              for (int l = 0; l < lanes && want > 0; ++l)
+                if (!alive[(size_t)l]) {
+                  start_lane(l);
+                  --want;
+                }
+              waiting_since = -1.0;
+              cv_lane.notify_all();
+            }
+          } else {
+            waiting_since = -1.0;
+          }
+        } else {
+          cv_mgr.wait(lk, ev);
+        }
         got.swap(done);
+        over = got.empty() && running == 0 && jobq.empty();
       }
-      if (got.empty()) break;  // nothing running, nothing waiting: every ready region ran
+      if (over) break;  // nothing running, nothing waiting: every ready region ran
+      if (got.empty()) continue;
       fin.clear();
       for (size_t i : got) {
         if (bs[i].rc != SEMIPAR_OK && rc == SEMIPAR_OK) {
@@ -698,7 +766,11 @@ struct Runner {
       stop = true;
     }
     cv_lane.notify_all();
-    for (auto& x : th) x.join();
+    for (auto& x : th)
+      if (x.joinable()) x.join();
+    acc.lane_held_ms = held_ms;
+    acc.lane_busy_ms = busy_ms;
+    acc.lanes_started = started;
     if (rc == SEMIPAR_OK && consumed != nr) {
       spi::set_error("schedule_regions: the predecessor counts leave regions that never become ready");
       rc = SEMIPAR_E_ARG;
@@ -748,6 +820,7 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
   if (p->events && (!p->events_off || p->events_cap < 0)) return SEMIPAR_E_ARG;
   if (p->loops && (!p->loops_off || p->loops_cap < 0)) return SEMIPAR_E_ARG;
   if (p->evolve.loop_every < 0) return SEMIPAR_E_ARG;
+  if (!(p->lane_sleep_ms >= 0.0 && p->lane_submit_ms >= 0.0)) return SEMIPAR_E_ARG;
   const double cf = p->evolve.cell_factor;
   if (!(cf == 0.0 || (cf >= 1.0 && cf <= 4.0))) return SEMIPAR_E_ARG;
   const auto t0 = std::chrono::steady_clock::now();

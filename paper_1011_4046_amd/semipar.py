@@ -104,7 +104,8 @@ class SchedParams(ctypes.Structure):
                 ("region_point_steps", ctypes.c_void_p), ("region_batch", ctypes.c_void_p),
                 ("region_ms", ctypes.c_void_p), ("lanes", ctypes.c_int32),
                 ("pack", ctypes.c_int32), ("loops", ctypes.c_void_p),
-                ("loops_cap", ctypes.c_int64), ("loops_off", ctypes.c_void_p)]
+                ("loops_cap", ctypes.c_int64), ("loops_off", ctypes.c_void_p),
+                ("lane_sleep_ms", ctypes.c_double), ("lane_submit_ms", ctypes.c_double)]
 
 
 class SchedStats(ctypes.Structure):
@@ -113,7 +114,9 @@ class SchedStats(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("events", ctypes.c_int64),
                 ("makespan_ms", ctypes.c_double), ("evolve_ms", ctypes.c_double),
                 ("timed_kernel_ms", ctypes.c_double), ("timed_kernel_launches", ctypes.c_int64),
-                ("loops", ctypes.c_int64), ("passed", ctypes.c_int64)]
+                ("loops", ctypes.c_int64), ("passed", ctypes.c_int64),
+                ("lane_held_ms", ctypes.c_double), ("lane_busy_ms", ctypes.c_double),
+                ("lanes_started", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -451,7 +454,8 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
                      screen=SCREEN_F64, intercommute=True, cell_size=0.0, steps_per_sync=0,
                      use_graph=False, cand_per_point=0.0, events_per_point=0.0,
                      screen_split=0, timed_kernel=-1, lanes=1, loop_every=0,
-                     pack=PACK_POINTS, p=1.0, seed=0, persistent=0, cell_factor=0.0):
+                     pack=PACK_POINTS, p=1.0, seed=0, persistent=0, cell_factor=0.0,
+                     lane_sleep_ms=0.0, lane_submit_ms=0.0):
     """Run every region of rs; returns a dict with the stats, per-region logs, output
     records (out = "host": numpy; "device": torch uint8 CUDA tensor; None: not
     written), their offsets (4 per region + 1) and the events with offsets."""
@@ -463,6 +467,8 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
     p.batch_points = int(batch_points)
     p.lanes = int(lanes)
     p.pack = int(pack)
+    p.lane_sleep_ms = float(lane_sleep_ms)
+    p.lane_submit_ms = float(lane_submit_ms)
     cost_arr = None
     if cost is not None:
         cost_arr = np.ascontiguousarray(cost, dtype=np.float32)

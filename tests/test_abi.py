@@ -62,6 +62,8 @@ int main(void) {
   F(semipar_loop, rep_id) F(semipar_loop, energy) F(semipar_loop, centre)
   F(semipar_tiling, surfaces) F(semipar_tiling, stream)
   F(semipar_sched_params, cost) F(semipar_sched_params, evolve) F(semipar_sched_params, out)
+  F(semipar_sched_params, lane_sleep_ms) F(semipar_sched_params, lane_submit_ms)
+  F(semipar_sched_stats, lane_held_ms) F(semipar_sched_stats, lanes_started)
   F(semipar_sched_params, events_cap) F(semipar_sched_params, region_ms)
   F(semipar_sched_params, lanes) F(semipar_sched_params, loops)
   F(semipar_sched_params, loops_off)

@@ -41,20 +41,21 @@ def test_byte_model():
     assert bench.screen_bytes_per_element(False) == 72
 
 
-def profiled_source():
+def profiled(key):
     with open(os.path.join(ROOT, "profiles", "batched512_hbm_counters.txt")) as f:
         for line in f:
             if line.startswith("traffic-per-launch:"):
-                return dict(t.split("=", 1) for t in line.split()[1:])["source"]
+                return dict(t.split("=", 1) for t in line.split()[1:])[key]
     return None
 
 
 def test_traffic_only_for_the_profiled_source_and_configuration():
-    cfg = "bp5597978-split1-sync32-f32"
+    cfg = profiled("config")
+    assert cfg and cfg.startswith("eager-1lane-")
     for k in ("k_screen", "k_evolve"):
-        assert bench.counted_traffic(k, "bp1-split5-sync64-f64") is None
+        assert bench.counted_traffic(k, "eager-1lane-bp1-split5-sync64-f64") is None
     assert bench.counted_traffic("k_confirm", cfg) is None
-    if profiled_source() != bench.kernel_source_hash():
+    if profiled("source") != bench.kernel_source_hash():
         pytest.skip("the committed counter summary is for another kernel source: traffic is "
                     "reported as null until the kernels are profiled again")
     for k in ("k_screen", "k_evolve"):
