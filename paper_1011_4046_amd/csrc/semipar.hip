@@ -3736,6 +3736,9 @@ inline void sfree(void* p, hipStream_t s) {
 struct semipar_region {
   int64_t n = 0, cap = 0;
   bool bounded = false;
+  // buffers replaced by larger ones while the region is in use: released with it, since
+  // hipFree waits for the whole device (other lanes' batches included)
+  std::vector<void*> retired;
   RegionGeom geom{};
   int32_t n_sub = 0;
   RegionGeom* geoms = nullptr;  // batch: geometry of each sub-region
@@ -3948,10 +3951,10 @@ int ensure_log(semipar_region* r, int64_t need) {
       HIPCHK(hipMemcpyAsync(nr, r->log_rid, sizeof(int32_t) * r->ctrl_h->log_n,
                             hipMemcpyDeviceToDevice, r->stream));
     HIPCHK(hipStreamSynchronize(r->stream));
-    dfree(r->log_rid);
+    if (r->log_rid) r->retired.push_back(r->log_rid);
     r->log_rid = nr;
   }
-  dfree(r->log);
+  if (r->log) r->retired.push_back(r->log);
   r->log = nl;
   r->log_cap = nc;
   drop_graph(r);
@@ -3965,15 +3968,15 @@ int grow_step_caps(semipar_region* r, int defer) {
   HIPCHK(hipStreamSynchronize(r->stream));
   if (defer & 1) {
     if (r->cap_cand >= INT32_MAX / 4) return SEMIPAR_E_OVERFLOW;
-    dfree(r->cand);
+    r->retired.push_back(r->cand);
     r->cand = nullptr;
     r->cap_cand *= 2;
     HIPCHK(dalloc(&r->cand, r->cap_cand));
   }
   if (defer & 2) {
     if (r->cap_evt >= INT32_MAX / 4) return SEMIPAR_E_OVERFLOW;
-    dfree(r->ev);
-    dfree(r->evs);
+    r->retired.push_back(r->ev);
+    r->retired.push_back(r->evs);
     r->ev = nullptr;
     r->evs = nullptr;
     r->cap_evt *= 2;
@@ -4230,8 +4233,8 @@ int grow_loop_log(semipar_region* r, int64_t need) {
                           r->stream));
   }
   HIPCHK(hipStreamSynchronize(r->stream));
-  dfree(r->llog);
-  dfree(r->llog_rid);
+  if (r->llog) r->retired.push_back(r->llog);
+  if (r->llog_rid) r->retired.push_back(r->llog_rid);
   r->llog = nl;
   r->llog_rid = nr;
   r->llog_cap = nc;
@@ -4263,7 +4266,7 @@ int loop_check(semipar_region* r, int32_t s, int64_t* nl, int64_t* np) {
   const int32_t loops = r->lctr_h[0], pts = r->lctr_h[1];
   if (loops == 0) return SEMIPAR_OK;
   if (r->lacc_cap < loops) {
-    dfree(r->lacc);
+    if (r->lacc) r->retired.push_back(r->lacc);
     r->lacc = nullptr;
     r->lacc_cap = 0;
     const int64_t want = std::max<int64_t>(loops, 256);
@@ -4316,6 +4319,7 @@ void region_destroy(semipar_region* r) {
   if (!r) return;
   drop_graph(r);
   free_step_buffers(r);
+  for (void* q : r->retired) dfree(q);
   for (int s = 0; s < 3; ++s)
     dfree(r->X.p[s]);
   dfree(r->nxt);
