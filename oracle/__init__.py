@@ -106,6 +106,8 @@ def lib():
         L.orc_philox4x64.restype = None
         L.orc_coin.argtypes = [ctypes.c_uint64, i32, i64, i64]
         L.orc_coin.restype = dbl
+        L.orc_region_keys.argtypes = [P, dbl, i32, P, i64, P, P]
+        L.orc_region_keys.restype = None
         _lib = L
     return _lib
 
@@ -138,8 +140,9 @@ class OracleRegion:
 
     def evolve(self, max_steps, t_end=float("inf"), search=GRID, intercommute=True,
                loop_every=0, p=1.0, seed=0):
-        """p: intercommutation probability in (0, 1]; seed: key of the crossings'
-        random numbers (both apply to this call's steps)."""
+        """p: intercommutation probability in [0, 1] (0: every crossing passes
+        through); seed: key of the crossings' random numbers (both apply to this call's
+        steps)."""
         rc = lib().orc_set_coin(self.h, float(p), int(seed))
         if rc != 0:
             raise ValueError(f"oracle rejected p = {p} (code {rc})")
@@ -269,3 +272,71 @@ def coin(seed, step, id_a, id_b):
     """Uniform number in [0, 1) deciding whether crossing (id_a, id_b) of step
     `step` exchanges partners (it does when the number is below p)."""
     return lib().orc_coin(int(seed), int(step), int(id_a), int(id_b))
+
+
+# --------------------------------------------------------------------------------------
+# A periodic spacetime tiling run as one whole volume
+# --------------------------------------------------------------------------------------
+
+def region_keys(V, inv2g, K, P):
+    """(S, key) of spacetime points P (n x 4: x, y, z, t) in the periodic tiling with
+    lattice origin V, 1/(2 g) = inv2g and K = 4 L / (2 g): S the layer and key the past
+    vertex's position mod K (orc_region_keys)."""
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.float64).reshape(-1, 4))
+    Vv = np.ascontiguousarray(V, dtype=np.float64)
+    S = np.zeros(len(P), np.int32)
+    key = np.zeros(len(P), np.int32)
+    if len(P):
+        lib().orc_region_keys(_ptr(Vv), float(inv2g), int(K), _ptr(P), len(P), _ptr(S),
+                              _ptr(key))
+    return S, key
+
+
+def whole_volume_history(net, t_stop, p=0.0, seed=0, search=GRID):
+    """Run a whole-volume network one lattice step at a time until every point of the
+    newest slice has t > t_stop, keeping every slice.
+
+    Returns (X, ids, nxt, events): X[s, q] the vertex of the point in slot q on slice
+    s0 - 1 + s (s0 the step of the input records, so X[0] and X[1] are the initial
+    surface), nxt the next-neighbour slot of each slot at the start (with p = 0 links
+    never change) and the event log. With p = 0 every crossing is logged as passed."""
+    recs = np.ascontiguousarray(net["recs"], dtype=REC)
+    hc = {0: 0.0, 1: 2.0, 2: 1.0}[net["cosmology"]]
+    r = OracleRegion(recs, net["box"], net["cosmology"], hc)
+    try:
+        ids = recs["id"].copy()
+        slot = {int(v): q for q, v in enumerate(ids)}
+        nxt = np.array([slot[int(v)] for v in recs["next_id"]], dtype=np.int64)
+        X = [recs["x_prev"].copy(), recs["x"].copy()]
+        while X[-1][:, 3].min() <= t_stop:
+            r.evolve(1, search=search, intercommute=True, p=p, seed=seed)
+            cur = r.read()
+            if not np.array_equal(cur["id"], ids):
+                raise RuntimeError("slot order changed")
+            X.append(cur["x"].copy())
+        return np.stack(X), ids, nxt, r.events()
+    finally:
+        r.close()
+
+
+def diamond_owners(X, nxt, V, inv2g, K, region_of):
+    """Owner of every diamond of a whole-volume history in a periodic tiling (Section
+    "Semi-parallel cosmic string simulation": a diamond is built by the region holding
+    its earliest point). The diamond whose top is X[s, q] (s >= 2) has bottom
+    X[s - 2, next q]; owner[s, q] is the index that region_of (a dict (S, key) ->
+    region) gives that bottom's region, -1 outside the tiling or for s < 2."""
+    ns, n = X.shape[0], X.shape[1]
+    S, key = region_keys(V, inv2g, K, X.reshape(-1, 4))
+    S = S.reshape(ns, n)
+    key = key.reshape(ns, n)
+    code = S.astype(np.int64) * (1 << 32) + key
+    rk = np.array([s_ * (1 << 32) + k_ for (s_, k_) in region_of], dtype=np.int64)
+    rv = np.array(list(region_of.values()), dtype=np.int64)
+    order = np.argsort(rk)
+    rk, rv = rk[order], rv[order]
+    pos = np.minimum(np.searchsorted(rk, code), max(len(rk) - 1, 0))
+    lut = np.where((len(rk) > 0) & (rk[pos] == code), rv[pos], -1) if len(rk) else \
+        np.full((ns, n), -1, np.int64)
+    owner = np.full((ns, n), -1, np.int64)
+    owner[2:] = lut[:-2][:, nxt]
+    return owner, lut

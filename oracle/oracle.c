@@ -423,16 +423,44 @@ int orc_create_bounded(const orc_rec* recs, int64_t n, double box, int cosmology
 }
 
 /* Generator coordinates c = H^T (P - V) / (2 g) of a spacetime point (x, y, z, t). */
-void orc_region_coords(const orc_region* r, const double P[4], double c[4]) {
-  double dx = P[0] - r->V[0];
-  double dy = P[1] - r->V[1];
-  double dz = P[2] - r->V[2];
-  double dtau = r->sqrt3 * P[3] - r->V[3];
+static void gen_coords(const double V[4], double inv2g, const double P[4], double c[4]) {
+  double dx = P[0] - V[0];
+  double dy = P[1] - V[1];
+  double dz = P[2] - V[2];
+  double dtau = sqrt(3.0) * P[3] - V[3];
   double a = dx + dy, b = dz + dtau, cc = dx - dy, d = dtau - dz;
-  c[0] = (a + b) * r->inv2g;
-  c[1] = (cc + d) * r->inv2g;
-  c[2] = (d - cc) * r->inv2g;
-  c[3] = (b - a) * r->inv2g;
+  c[0] = (a + b) * inv2g;
+  c[1] = (cc + d) * inv2g;
+  c[2] = (d - cc) * inv2g;
+  c[3] = (b - a) * inv2g;
+}
+
+void orc_region_coords(const orc_region* r, const double P[4], double c[4]) {
+  gen_coords(r->V, r->inv2g, P, c);
+}
+
+/* Region of each of n spacetime points in a periodic tiling (Section "Geometry",
+ * subsection "Boundary conditions": the tiling repeats with the box). The region index
+ * is i = floor(c); its layer is S = i0 + i1 + i2 + i3 (regions of one layer share their
+ * starting time) and its past vertex lies at spatial position p g/2 with
+ * p = i0 h0 + i1 h1 + i2 h2 + i3 h3, h_m the generators' spatial directions (1,1,1),
+ * (1,-1,-1), (-1,1,-1), (-1,-1,1). A shift by the box L along one axis changes i by
+ * M (+-1, +-1, -+1, -+1) with K = 4 M = 4 L / (2 g), which leaves S and p mod K
+ * unchanged, so (S, key) with key = (px K + py) K + pz, p taken mod K, names the region
+ * up to the box's periodicity. */
+void orc_region_keys(const double V[4], double inv2g, int32_t K, const double* P, int64_t n,
+                     int32_t* S, int32_t* key) {
+  for (int64_t q = 0; q < n; ++q) {
+    double c[4];
+    gen_coords(V, inv2g, P + 4 * q, c);
+    int64_t i[4];
+    for (int m = 0; m < 4; ++m) i[m] = (int64_t)floor(c[m]);
+    int64_t p[3] = {i[0] + i[1] - i[2] - i[3], i[0] - i[1] + i[2] - i[3],
+                    i[0] - i[1] - i[2] + i[3]};
+    for (int m = 0; m < 3; ++m) p[m] = ((p[m] % K) + K) % K;
+    S[q] = (int32_t)(i[0] + i[1] + i[2] + i[3]);
+    key[q] = (int32_t)((p[0] * K + p[1]) * K + p[2]);
+  }
 }
 
 /* -1 when P lies in the region (floor(c) == idx); otherwise the first i with
@@ -1055,10 +1083,11 @@ void orc_stats(const orc_region* r, int64_t out[6]) {
   out[5] = r->n_passed_total;
 }
 
-/* Intercommutation probability p in (0, 1] and the generator's seed for later steps
- * (the default is p = 1: every accepted crossing exchanges partners). */
+/* Intercommutation probability p in [0, 1] and the generator's seed for later steps
+ * (the default is p = 1: every accepted crossing exchanges partners; p = 0: every
+ * crossing passes through, so the network's links never change). */
 int orc_set_coin(orc_region* r, double p, uint64_t seed) {
-  if (!r || !(p > 0.0 && p <= 1.0)) return ORC_E_ARG;
+  if (!r || !(p >= 0.0 && p <= 1.0)) return ORC_E_ARG;
   r->p_ic = p;
   r->seed = seed;
   return ORC_OK;

@@ -1,0 +1,153 @@
+"""The oracle's view of a periodic spacetime tiling run as one whole volume (CPU): the
+region names it gives points, and which region owns each diamond of the world sheet
+(Section "Geometry" and its subsections "Initial conditions" and "Boundary conditions";
+Section "Semi-parallel cosmic string simulation": a diamond is built by the region that
+holds its earliest point, and regions pass the diamonds on their final surfaces to their
+successors).
+
+Pins: names are unchanged by a shift of a whole box and tell the regions of a layer
+apart; every input of an owned diamond comes from the initial surface, from the owning
+region itself or from a region of an earlier layer (no information flows backwards
+across the null faces); only the first four layers read the initial surface, and the
+first of them reads nothing else; with intercommutation probability 0 every crossing is
+logged as passed and the positions are those of a run without the crossing search."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1011_4046_amd import inputs as I
+
+H = np.array([[1, 1, 1, 1], [1, -1, -1, 1], [-1, 1, -1, 1], [-1, -1, 1, 1]], dtype=np.float64)
+
+
+def region_centres(parts):
+    """One interior spacetime point (x, y, z, t) per region: generator coordinates
+    idx + 1/2 about the lattice origin."""
+    out = []
+    for _, geom in parts:
+        V, inv2g, idx = geom[:4], geom[4], geom[5:9]
+        g = 0.5 / inv2g
+        P = V + (0.5 * g) * ((idx + 0.5) @ H)
+        out.append([P[0], P[1], P[2], P[3] / np.sqrt(3.0)])
+    return np.array(out)
+
+
+@pytest.fixture(scope="module")
+def tiling():
+    net = I.vv_network(m=8, seed=1)
+    M, layers = 2, 8
+    parts, box, n_pred, succ, layer = I.tiling_regions(net, M=M, layers=layers)
+    V, inv2g = parts[0][1][:4], parts[0][1][4]
+    K = int(round(4 * box * inv2g))
+    S, key = O.region_keys(V, inv2g, K, region_centres(parts))
+    region_of = {(int(a), int(b)): r for r, (a, b) in enumerate(zip(S, key))}
+    g = 0.5 / inv2g
+    t_last = (V[3] + 0.5 * g * (layers - 1) + 2 * g) / np.sqrt(3.0)
+    X, ids, nxt, ev = O.whole_volume_history(net, t_last, p=0.0)
+    owner, lut = O.diamond_owners(X, nxt, V, inv2g, K, region_of)
+    return dict(net=net, parts=parts, box=box, layer=np.asarray(layer), V=V, inv2g=inv2g, K=K,
+                S=S, region_of=region_of, X=X, nxt=nxt, ev=ev, owner=owner, lut=lut,
+                layers=layers)
+
+
+def test_names_tell_regions_apart_and_follow_the_layers(tiling):
+    T = tiling
+    assert len(T["region_of"]) == len(T["parts"])
+    assert np.array_equal(T["S"], T["layer"])
+
+
+def test_names_do_not_change_under_a_whole_box_shift(tiling):
+    T = tiling
+    rng = np.random.default_rng(0)
+    P = rng.uniform(-T["box"], 2 * T["box"], (2000, 4))
+    P[:, 3] = rng.uniform(7.0, 14.0, 2000)
+    S0, k0 = O.region_keys(T["V"], T["inv2g"], T["K"], P)
+    for axis in range(3):
+        for sgn in (-1, 1, 3):
+            Q = P.copy()
+            Q[:, axis] += sgn * T["box"]
+            S1, k1 = O.region_keys(T["V"], T["inv2g"], T["K"], Q)
+            # the shifted coordinate is rounded again: allow the rare point that lies within
+            # rounding of a region face
+            same = (S1 == S0) & (k1 == k0)
+            assert same.mean() > 0.999
+
+
+def test_inputs_of_owned_diamonds_come_from_earlier_layers_or_the_owner(tiling):
+    T = tiling
+    X, nxt, own, layer = T["X"], T["nxt"], T["owner"], T["layer"]
+    ns, n = own.shape
+    produced = own.copy()          # region that built each vertex (-2: initial surface)
+    produced[:2] = -2
+    checked = 0
+    for s in range(2, ns):
+        q = np.nonzero(own[s] >= 0)[0]
+        r = own[s, q]
+        j = nxt[q]
+        for src in (produced[s - 1, q], produced[s - 1, j], produced[s - 2, j]):
+            ic = src == -2
+            same = src == r
+            earlier = (src >= 0) & (layer[np.maximum(src, 0)] < layer[r])
+            assert np.all(ic | same | earlier), f"slice {s}"
+            # an input outside the tiling would be a diamond nobody builds
+            assert not np.any(src == -1)
+        checked += len(q)
+    assert checked > 100000
+
+
+def test_only_the_first_four_layers_read_the_initial_surface(tiling):
+    T = tiling
+    own, nxt, layer = T["owner"], T["nxt"], T["layer"]
+    reads_ic = np.zeros(len(T["parts"]), bool)
+    reads_pred = np.zeros(len(T["parts"]), bool)
+    ns = own.shape[0]
+    for s in range(2, ns):
+        q = np.nonzero(own[s] >= 0)[0]
+        r = own[s, q]
+        j = nxt[q]
+        for (ss, pts) in ((s - 1, q), (s - 1, j), (s - 2, j)):
+            if ss <= 1:
+                reads_ic[r] = True
+            else:
+                src = own[ss, pts]
+                other = (src >= 0) & (src != r)
+                reads_pred[r[other]] = True
+    busy = np.zeros(len(T["parts"]), bool)
+    busy[own[own >= 0]] = True
+    assert np.all(layer[reads_ic] <= 3)
+    # each of the four families is present, the first with no predecessor input
+    for S in range(4):
+        assert reads_ic[(layer == S) & busy].any()
+    assert not reads_pred[layer == 0].any()
+    assert reads_pred[(layer >= 1) & (layer <= 3) & reads_ic].any()
+    assert busy[layer >= 4].any()
+
+
+def test_probability_zero_passes_every_crossing_and_keeps_the_positions(tiling):
+    T = tiling
+    ev = T["ev"]
+    assert len(ev) > 100 and np.all(ev["kind"] == 1)
+    net = T["net"]
+    steps = T["X"].shape[0] - 2
+    hc = 2.0
+    r = O.OracleRegion(net["recs"], net["box"], net["cosmology"], hc)
+    r.evolve(steps, intercommute=False)
+    rec = r.read()
+    r.close()
+    assert np.array_equal(rec["x"], T["X"][-1])
+    assert np.array_equal(rec["x_prev"], T["X"][-2])
+
+
+def test_owner_holds_the_earliest_of_the_diamonds_four_vertices(tiling):
+    T = tiling
+    X, nxt, own, lut = T["X"], T["nxt"], T["owner"], T["lut"]
+    ns, n = own.shape
+    q = np.arange(n)
+    j = nxt[q]
+    for s in range(2, ns, 7):
+        # the diamond with top X[s, q]: left X[s-1, q], right X[s-1, next q], bottom
+        # X[s-2, next q]; its earliest vertex by t decides the owner
+        cand = np.stack([lut[s, q], lut[s - 1, q], lut[s - 1, j], lut[s - 2, j]])
+        tt = np.stack([X[s, q, 3], X[s - 1, q, 3], X[s - 1, j, 3], X[s - 2, j, 3]])
+        first = cand[np.argmin(tt, axis=0), q]
+        assert np.array_equal(own[s], first)
