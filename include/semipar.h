@@ -506,6 +506,72 @@ typedef struct semipar_sched_stats {
 int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
                      semipar_sched_stats* st);
 
+/* ---- a tiling run with hand-off between regions ------------------------------------ */
+
+/* A periodic spacetime tiling run region by region, each region taking its input from
+ * its predecessors' output (Section "Geometry" and its subsections "Initial conditions"
+ * and "Boundary conditions"; Section "Semi-parallel cosmic string simulation": a diamond
+ * is built by the region that holds its earliest point, and a region passes on what
+ * overlaps its final surfaces; one GPU holds the whole world sheet in its memory, so
+ * "passing on" is a region writing vertices that later regions read).
+ *   n_regions, geoms  the regions (host). All share origin and inv2g; the box must hold
+ *              a whole number of region steps: K = 4 box inv2g a multiple of 4. A
+ *              region is named by its layer S = idx0 + idx1 + idx2 + idx3 and its past
+ *              vertex p = idx0 (1,1,1) + idx1 (1,-1,-1) + idx2 (-1,1,-1) + idx3 (-1,-1,1)
+ *              taken mod K (the names repeat with the box); two regions may not share a
+ *              name, and vertices whose region has no entry are outside the run.
+ *   n_pred, succ_off, succ  dependency lists as in semipar_tiling (required): every
+ *              region that can pass anything to r must come before it
+ *   ic, n_points, ic_mem  the initial surface of the whole volume (host or device):
+ *              records on one slice s0 >= 1 (x on s0, x_prev on s0 - 1), ids distinct,
+ *              every next_id and prev_id among the records and paired
+ *   hist, hist_slices  device memory for hist_slices x n_points x 4 doubles, the world
+ *              sheet: the vertex (x, y, z, t) of the point in record slot q on slice
+ *              s0 - 1 + s is at hist[4 (s n_points + q)]. The call fills it with
+ *              t = NaN (not built) and the two initial slices; on return it holds every
+ *              vertex a region of the tiling built. Too few slices: SEMIPAR_E_OVERFLOW.
+ *   stream     hipStream_t for all work (NULL: the library's own) */
+typedef struct semipar_handoff {
+  int32_t n_regions;
+  int32_t cosmology;
+  double box;
+  const semipar_region_geom* geoms;
+  const int32_t* n_pred;
+  const int32_t* succ_off;
+  const int32_t* succ;
+  const semipar_point_rec* ic;
+  int64_t n_points;
+  int32_t ic_mem;
+  int32_t reserved;
+  double* hist;
+  int64_t hist_slices;
+  void* stream;
+} semipar_handoff;
+
+/* Run every region of the tiling in dependency order with hand-off. Region R builds
+ * every diamond whose bottom lies in R, from inputs that R itself, its predecessors or
+ * the initial surface built. Point q's diamonds in R begin when its right neighbour's
+ * world line enters R -- the region that builds that entry vertex tells R (a start
+ * token) -- and end when that world line leaves R. Crossings between elements of one
+ * region are searched, confirmed and logged as in region_evolve, and pass through
+ * (kind 1; links never change), so every vertex equals that of one whole-volume run
+ * with intercommutation probability 0; crossings between elements of different regions
+ * are not searched.
+ *   p  used: batch_points (0: every ready region in one batch), cost (ordering only),
+ *      evolve (screen, intercommute, use_graph, steps_per_sync, cell_size, cell_factor,
+ *      cand_per_point, events_per_point, seed; max_steps caps the steps of each batch;
+ *      loop_every must be 0; p is ignored), events / events_cap / events_off,
+ *      region_steps, region_point_steps, region_batch, region_ms. out must be NULL (the
+ *      world sheet is the output); policy, pack, lanes and the lane_* fields are ignored.
+ *   st regions, empty_regions, batches, point_steps, steps, events, passed, makespan_ms,
+ *      evolve_ms.
+ * Errors: SEMIPAR_E_ARG, SEMIPAR_E_SURFACE (initial surface), SEMIPAR_E_OOM,
+ * SEMIPAR_E_HIP, SEMIPAR_E_OVERFLOW (hist_slices too few), SEMIPAR_E_STATE (a region
+ * received work after it had run, or a diamond lacked an input: the tiling's dependency
+ * lists or geometry do not match; semipar_last_error says which). */
+int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
+                     semipar_sched_stats* st);
+
 /* ---- the learned cost model --------------------------------------------------------- */
 #define SEMIPAR_MLP_IN 12
 #define SEMIPAR_MLP_HIDDEN 64

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsemipar.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("semipar.hip", "schedule.hip", "costmodel.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("semipar.hip", "schedule.hip", "handoff.hip", "costmodel.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")] + [
     os.path.join(INCLUDE, "semipar.h")]
 

@@ -1,0 +1,400 @@
+// handoff.hip -- a periodic spacetime tiling run region by region with hand-off.
+//
+// Paper, Section "Geometry": the 4-volume is cut into 4-cubes whose faces no signal
+// crosses backwards, so each region can run alone given what its predecessors passed
+// on; subsection "Initial conditions": the regions cut by the initial time take initial
+// data where they are cut and predecessor output elsewhere (four families), later ones
+// only predecessor output; subsection "Boundary conditions": a periodic volume is the
+// same tiling with its successor lists wrapped. Section "Semi-parallel cosmic string
+// simulation": a diamond is built by the region holding its earliest point, and a region
+// passes the diamonds overlapping its final surfaces to its successors.
+//
+// On one GPU the whole world sheet fits in device memory, so nothing is copied between
+// regions: every vertex is written once into a slice-major table by the region that
+// builds it, and read from there by every later diamond that needs it. What a region
+// does pass on is where its successors' work begins: when a vertex it builds is the first
+// vertex of a world line in another region, that region's diamond of the line's left
+// neighbour starts there (a start token). The manager here keeps the tokens per region
+// and runs the ready regions wave by wave as launch batches (one set of step kernels
+// over the points of many regions).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+#include "semipar.h"
+
+namespace {
+
+int fail_msg(int code, const char* msg) {
+  spi::set_error(msg);
+  return code;
+}
+
+int hip_msg(hipError_t e, const char* what) {
+  char msg[200];
+  snprintf(msg, sizeof(msg), "schedule_handoff: %s failed: %s", what, hipGetErrorString(e));
+  spi::set_error(msg);
+  return SEMIPAR_E_HIP;
+}
+
+// Device buffers of one call, released on every return path.
+struct Dev {
+  std::vector<void*> bufs;
+  hipStream_t own = nullptr;
+  ~Dev() {
+    for (void* p : bufs) (void)hipFree(p);
+    if (own) (void)hipStreamDestroy(own);
+    (void)hipGetLastError();
+  }
+  template <class T>
+  hipError_t alloc(T** p, size_t count) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * std::max<size_t>(count, 1));
+    if (e == hipSuccess) bufs.push_back(*p);
+    return e;
+  }
+};
+
+// Region name (S << 32 | key) from an index, as the step kernels name vertices.
+int64_t region_name(const int32_t idx[4], int K) {
+  const int64_t i0 = idx[0], i1 = idx[1], i2 = idx[2], i3 = idx[3];
+  int64_t p[3] = {i0 + i1 - i2 - i3, i0 - i1 + i2 - i3, i0 - i1 - i2 + i3};
+  for (int c = 0; c < 3; ++c) p[c] = ((p[c] % K) + K) % K;
+  const int64_t S = i0 + i1 + i2 + i3;
+  return (S << 32) | (int64_t)(uint32_t)((p[0] * K + p[1]) * K + p[2]);
+}
+
+}  // namespace
+
+int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
+                     semipar_sched_stats* st) {
+  spi::begin_call();
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!h || !p) return SEMIPAR_E_ARG;
+  const int nr = h->n_regions;
+  if (nr <= 0 || !h->geoms || !h->n_pred || !h->succ_off || !h->ic || h->n_points <= 0 ||
+      !h->hist || h->hist_slices < 2 || !(h->box > 0.0) || h->cosmology < 0 ||
+      h->cosmology > 2 || (h->ic_mem != SEMIPAR_MEM_HOST && h->ic_mem != SEMIPAR_MEM_DEVICE))
+    return SEMIPAR_E_ARG;
+  if (h->n_points >= ((int64_t)1 << 31) - 1 || h->hist_slices > INT32_MAX) return SEMIPAR_E_ARG;
+  if (p->out || p->evolve.loop_every != 0 || p->batch_points < 0 ||
+      (p->events && (!p->events_off || p->events_cap < 0)))
+    return SEMIPAR_E_ARG;
+  {
+    const double cf = p->evolve.cell_factor;
+    if (!(cf == 0.0 || (cf >= 1.0 && cf <= 4.0))) return SEMIPAR_E_ARG;
+  }
+  for (int r = 0; r < nr; ++r)
+    if (h->n_pred[r] < 0 || h->succ_off[r + 1] < h->succ_off[r]) return SEMIPAR_E_ARG;
+  if (h->succ_off[0] != 0) return SEMIPAR_E_ARG;
+  {
+    const int32_t m = h->succ_off[nr];
+    if (m > 0 && !h->succ) return SEMIPAR_E_ARG;
+    for (int32_t i = 0; i < m; ++i)
+      if (h->succ[i] < 0 || h->succ[i] >= nr) return SEMIPAR_E_ARG;
+  }
+  // one lattice origin and scale; the box a whole number of region steps
+  const semipar_region_geom& g0 = h->geoms[0];
+  if (!(g0.inv2g > 0.0)) return SEMIPAR_E_ARG;
+  for (int r = 1; r < nr; ++r) {
+    const semipar_region_geom& g = h->geoms[r];
+    if (g.inv2g != g0.inv2g) return SEMIPAR_E_ARG;
+    for (int q = 0; q < 4; ++q)
+      if (g.origin[q] != g0.origin[q]) return SEMIPAR_E_ARG;
+  }
+  const double Kd = 4.0 * h->box * g0.inv2g;
+  const int K = (int)std::llround(Kd);
+  if (K < 4 || K > 1024 || K % 4 != 0 || std::fabs(Kd - K) > 1e-9 * Kd)
+    return fail_msg(SEMIPAR_E_ARG, "schedule_handoff: the box is not a whole number of region steps");
+  // names -> region table
+  std::vector<int64_t> name((size_t)nr);
+  int32_t S_lo = INT32_MAX, S_hi = INT32_MIN;
+  for (int r = 0; r < nr; ++r) {
+    name[r] = region_name(h->geoms[r].idx, K);
+    const int32_t S = (int32_t)(name[r] >> 32);
+    S_lo = std::min(S_lo, S);
+    S_hi = std::max(S_hi, S);
+  }
+  const int64_t K3 = (int64_t)K * K * K;
+  const int64_t lut_n = ((int64_t)S_hi - S_lo + 1) * K3;
+  if (lut_n > ((int64_t)1 << 28)) return SEMIPAR_E_ARG;
+  std::vector<int32_t> lut((size_t)lut_n, -1);
+  for (int r = 0; r < nr; ++r) {
+    const int32_t S = (int32_t)(name[r] >> 32);
+    const int64_t key = (int64_t)(uint32_t)(name[r] & 0xffffffffll);
+    int32_t& e = lut[(size_t)((int64_t)(S - S_lo) * K3 + key)];
+    if (e >= 0) return fail_msg(SEMIPAR_E_ARG, "schedule_handoff: two regions with one name");
+    e = r;
+  }
+  Dev D;
+  hipStream_t stream = (hipStream_t)h->stream;
+  if (!stream) {
+    hipError_t e = hipStreamCreate(&D.own);
+    if (e != hipSuccess) return hip_msg(e, "hipStreamCreate");
+    stream = D.own;
+  }
+  // the initial surface on the host: links by slot
+  const int64_t n = h->n_points;
+  std::vector<semipar_point_rec> recs;
+  const semipar_point_rec* hrec = h->ic;
+  if (h->ic_mem == SEMIPAR_MEM_DEVICE) {
+    recs.resize((size_t)n);
+    hipError_t e = hipMemcpyAsync(recs.data(), h->ic, sizeof(semipar_point_rec) * n,
+                                  hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_msg(e, "copy of the initial surface");
+    hrec = recs.data();
+  }
+  const int32_t s0r = hrec[0].step;
+  if (s0r < 1) return SEMIPAR_E_SURFACE;
+  std::unordered_map<int64_t, int32_t> slot_of;
+  slot_of.reserve((size_t)n * 2);
+  for (int64_t q = 0; q < n; ++q) {
+    if (hrec[q].step != s0r) return SEMIPAR_E_SURFACE;
+    if (!slot_of.emplace(hrec[q].id, (int32_t)q).second) return SEMIPAR_E_SURFACE;
+  }
+  std::vector<int32_t> gnext((size_t)n), gprev((size_t)n);
+  std::vector<int64_t> gid((size_t)n);
+  for (int64_t q = 0; q < n; ++q) {
+    auto a = slot_of.find(hrec[q].next_id), b = slot_of.find(hrec[q].prev_id);
+    if (a == slot_of.end() || b == slot_of.end()) return SEMIPAR_E_SURFACE;
+    gnext[q] = a->second;
+    gprev[q] = b->second;
+    gid[q] = hrec[q].id;
+  }
+  for (int64_t q = 0; q < n; ++q)
+    if (gprev[gnext[q]] != q) return SEMIPAR_E_SURFACE;
+  slot_of.clear();
+  // device tables
+  int32_t *d_lut = nullptr, *d_gnext = nullptr, *d_gprev = nullptr, *d_gmap = nullptr;
+  int64_t* d_gid = nullptr;
+  semipar_point_rec* d_rec = nullptr;
+  if (D.alloc(&d_lut, lut.size()) != hipSuccess || D.alloc(&d_gnext, n) != hipSuccess ||
+      D.alloc(&d_gprev, n) != hipSuccess || D.alloc(&d_gmap, n) != hipSuccess ||
+      D.alloc(&d_gid, n) != hipSuccess || D.alloc(&d_rec, n) != hipSuccess)
+    return fail_msg(SEMIPAR_E_OOM, "schedule_handoff: device tables");
+  {
+    hipError_t e = hipMemcpyAsync(d_lut, lut.data(), sizeof(int32_t) * lut.size(),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_gnext, gnext.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_gprev, gprev.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_gid, gid.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d_gmap, 0xff, sizeof(int32_t) * n, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_rec, hrec, sizeof(semipar_point_rec) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_msg(e, "upload of the tiling tables");
+  }
+  spi::HandoffShared sh{};
+  sh.H = h->hist;
+  sh.n = n;
+  sh.s0 = s0r - 1;
+  sh.ns = (int32_t)h->hist_slices;
+  for (int q = 0; q < 4; ++q) sh.V[q] = g0.origin[q];
+  sh.inv2g = g0.inv2g;
+  sh.K = K;
+  sh.S_lo = S_lo;
+  sh.S_hi = S_hi;
+  sh.lut = d_lut;
+  sh.gnext = d_gnext;
+  sh.gprev = d_gprev;
+  sh.gid = d_gid;
+  sh.gmap = d_gmap;
+  sh.cosmology = h->cosmology;
+  sh.box = h->box;
+  // start tokens per region: (volume slot, first step)
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> work((size_t)nr);
+  std::vector<char> finished((size_t)nr, 0);
+  std::vector<spi::HandTok> tk;
+  auto route = [&](const std::vector<spi::HandTok>& v) -> int {
+    for (const spi::HandTok& t : v) {
+      if (t.region < 0 || t.region >= nr || t.slot < 0 || t.slot >= n)
+        return fail_msg(SEMIPAR_E_STATE, "schedule_handoff: a start token out of range");
+      if (finished[t.region])
+        return fail_msg(SEMIPAR_E_STATE,
+                        "schedule_handoff: a region received work after it had run (the "
+                        "dependency lists do not follow the geometry)");
+      work[t.region].emplace_back(t.slot, t.step);
+    }
+    return SEMIPAR_OK;
+  };
+  {
+    int rc = spi::handoff_ic(sh, d_rec, stream, tk);
+    if (rc != SEMIPAR_OK) return rc;
+    rc = route(tk);
+    if (rc != SEMIPAR_OK) return rc;
+  }
+  // per-region results
+  std::vector<std::vector<semipar_event>> ev_r((size_t)nr);
+  std::vector<int32_t> r_steps((size_t)nr, 0), r_batch((size_t)nr, -1);
+  std::vector<int64_t> r_psteps((size_t)nr, 0);
+  std::vector<double> r_ms((size_t)nr, 0.0);
+  std::vector<int32_t> pending((size_t)nr);
+  std::vector<int32_t> ready;
+  for (int r = 0; r < nr; ++r) {
+    pending[r] = h->n_pred[r];
+    if (pending[r] == 0) ready.push_back(r);
+  }
+  std::vector<char> in_batch((size_t)n, 0);
+  int64_t batches = 0, steps_sum = 0, psum = 0, nev = 0, npass = 0, empty = 0, done = 0;
+  double evolve_ms = 0.0, tk_ms = 0.0;
+  int64_t tk_n = 0;
+  semipar_evolve_params ep = p->evolve;
+  if (ep.max_steps <= 0) ep.max_steps = (int64_t)1 << 30;
+  ep.t_end = INFINITY;
+  ep.loop_every = 0;
+  ep.persistent = 0;
+  while (!ready.empty()) {
+    std::vector<int32_t> run, next;
+    auto release = [&](int32_t r) {
+      for (int32_t i = h->succ_off[r]; i < h->succ_off[r + 1]; ++i)
+        if (--pending[h->succ[i]] == 0) next.push_back(h->succ[i]);
+    };
+    for (int32_t r : ready) {
+      if (work[r].empty()) {
+        finished[r] = 1;
+        empty++;
+        done++;
+        release(r);
+      } else {
+        run.push_back(r);
+      }
+    }
+    // longest predicted first (else most start tokens first), cut into batches
+    std::stable_sort(run.begin(), run.end(), [&](int32_t a, int32_t b) {
+      if (p->cost) return p->cost[a] > p->cost[b];
+      return work[a].size() > work[b].size();
+    });
+    size_t i0 = 0;
+    while (i0 < run.size()) {
+      size_t i1 = i0;
+      int64_t pts = 0;
+      while (i1 < run.size() &&
+             (i1 == i0 || p->batch_points == 0 || pts + (int64_t)work[run[i1]].size() <= p->batch_points))
+        pts += (int64_t)work[run[i1++]].size();
+      std::vector<int32_t> regs(run.begin() + i0, run.begin() + i1);
+      i0 = i1;
+      std::vector<int32_t> slot, start;
+      std::vector<int64_t> sub_off(1, 0), names;
+      std::vector<semipar_region_geom> geoms;
+      slot.reserve((size_t)pts);
+      start.reserve((size_t)pts);
+      for (int32_t r : regs) {
+        auto& w = work[r];
+        std::sort(w.begin(), w.end());
+        int32_t last = -1;
+        for (const auto& e : w) {
+          if (e.first == last) {
+            if (e.second != start.back())
+              return fail_msg(SEMIPAR_E_STATE,
+                              "schedule_handoff: a point starts twice in one region");
+            continue;
+          }
+          if (in_batch[e.first])
+            return fail_msg(SEMIPAR_E_STATE,
+                            "schedule_handoff: a point works in two regions of one batch");
+          in_batch[e.first] = 1;
+          last = e.first;
+          slot.push_back(e.first);
+          start.push_back(e.second);
+        }
+        sub_off.push_back((int64_t)slot.size());
+        geoms.push_back(h->geoms[r]);
+        names.push_back(name[r]);
+      }
+      for (int32_t q : slot) in_batch[q] = 0;
+      semipar_region* R = nullptr;
+      int rc = spi::handoff_batch(sh, slot.data(), start.data(), sub_off, geoms.data(),
+                                  names.data(), stream, &R);
+      if (rc != SEMIPAR_OK) return rc;
+      semipar_evolve_stats es{};
+      rc = region_evolve(R, &ep, &es);
+      std::vector<semipar_event> evs;
+      std::vector<int64_t> eoff;
+      std::vector<int32_t> bsteps;
+      std::vector<int64_t> bps;
+      if (rc == SEMIPAR_OK && es.steps >= ep.max_steps)
+        rc = fail_msg(SEMIPAR_E_STATE, "schedule_handoff: a batch reached max_steps");
+      if (rc == SEMIPAR_OK) rc = spi::batch_events(R, evs, eoff);
+      if (rc == SEMIPAR_OK) rc = spi::batch_stats(R, bsteps, bps);
+      // its regions are done before their tokens go out: a token for one of them (or any
+      // earlier region) breaks the causal order
+      for (int32_t r : regs) finished[r] = 1;
+      if (rc == SEMIPAR_OK) rc = spi::handoff_tokens(R, tk);
+      region_destroy(R);
+      if (rc != SEMIPAR_OK) return rc;
+      rc = route(tk);
+      if (rc != SEMIPAR_OK) return rc;
+      for (size_t q = 0; q < regs.size(); ++q) {
+        const int32_t r = regs[q];
+        ev_r[r].assign(evs.begin() + eoff[q], evs.begin() + eoff[q + 1]);
+        for (const semipar_event& e : ev_r[r]) npass += e.kind == 1 ? 1 : 0;
+        nev += (int64_t)ev_r[r].size();
+        r_steps[r] = bsteps[q];
+        r_psteps[r] = bps[q];
+        r_batch[r] = (int32_t)batches;
+        r_ms[r] = es.elapsed_ms;
+        psum += bps[q];
+        work[r].clear();
+        work[r].shrink_to_fit();
+        done++;
+        release(r);
+      }
+      steps_sum += es.steps;
+      evolve_ms += es.elapsed_ms;
+      tk_ms += es.timed_kernel_ms;
+      tk_n += es.timed_kernel_launches;
+      batches++;
+    }
+    std::sort(next.begin(), next.end());
+    ready.swap(next);
+  }
+  if (done != nr)
+    return fail_msg(SEMIPAR_E_ARG, "schedule_handoff: the dependency lists leave regions never ready");
+  if (p->events) {
+    int64_t off = 0;
+    for (int r = 0; r < nr; ++r) {
+      p->events_off[r] = off;
+      for (const semipar_event& e : ev_r[r]) {
+        if (off < p->events_cap) p->events[off] = e;
+        off++;
+      }
+    }
+    p->events_off[nr] = off;
+  }
+  for (int r = 0; r < nr; ++r) {
+    if (p->region_steps) p->region_steps[r] = r_steps[r];
+    if (p->region_point_steps) p->region_point_steps[r] = r_psteps[r];
+    if (p->region_batch) p->region_batch[r] = r_batch[r];
+    if (p->region_ms) p->region_ms[r] = r_ms[r];
+  }
+  if (st) {
+    semipar_sched_stats z{};
+    *st = z;
+    st->regions = nr;
+    st->empty_regions = empty;
+    st->batches = batches;
+    st->point_steps = psum;
+    st->steps = steps_sum;
+    st->events = nev;
+    st->passed = npass;
+    st->evolve_ms = evolve_ms;
+    st->timed_kernel_ms = tk_ms;
+    st->timed_kernel_launches = tk_n;
+    st->makespan_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return SEMIPAR_OK;
+}

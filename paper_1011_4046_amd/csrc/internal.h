@@ -50,6 +50,52 @@ SP_HIDDEN int batch_features(semipar_region* r, float* feat);
 // is built, only an id table for the right neighbours (host, 12 n_regions).
 SP_HIDDEN int surface_features(const semipar_tiling* t, float* feat);
 
+// ---- hand-off tiling runs (schedule_handoff) ----------------------------------------
+
+// A start token: point `slot` (of the volume's initial surface) builds its diamonds in
+// region `region` from step `step` on, because its right neighbour's world line entered
+// that region at slice step - 1.
+struct HandTok {
+  int32_t slot;
+  int32_t step;
+  int32_t region;
+  int32_t pad;
+};
+
+// Device tables shared by every batch of a hand-off run (owned by its driver).
+struct HandoffShared {
+  double* H;        // world sheet: [slice - s0][slot] (x, y, z, t), t = NaN: not built
+  int64_t n;        // points of the volume
+  int32_t s0, ns;   // first slice held, slices held
+  double V[4];      // lattice origin (x, y, z, tau) shared by all regions
+  double inv2g;     // 1 / (2 g)
+  int32_t K, S_lo, S_hi;  // region names: layer S in [S_lo, S_hi], past vertex mod K
+  const int32_t* lut;     // [(S - S_lo) K^3 + key] -> region index, -1: none
+  const int32_t* gnext;   // per volume slot: right neighbour's slot
+  const int32_t* gprev;   // per volume slot: left neighbour's slot
+  const int64_t* gid;     // per volume slot: point id
+  int32_t* gmap;          // per volume slot: -1 between batches (the batch build's scratch)
+  int32_t cosmology;
+  double box;
+};
+
+// A batch of hand-off sub-regions: sub-region q's points are slot[sub_off[q] ..
+// sub_off[q+1]) (host, volume slots, ascending within a sub-region) with their start
+// steps; geoms and names (host, n_sub each) are the sub-regions' geometry and names.
+// The region evolves with region_evolve; crossings are logged and pass through.
+SP_HIDDEN int handoff_batch(const HandoffShared& sh, const int32_t* slot, const int32_t* start,
+                            const std::vector<int64_t>& sub_off, const semipar_region_geom* geoms,
+                            const int64_t* names, hipStream_t stream, semipar_region** out);
+
+// Fill the world sheet with t = NaN, write the initial surface's two slices (drec: n
+// records in device memory, volume slot order) and return the start tokens they give
+// (host copy, any order). Stream-ordered on st.
+SP_HIDDEN int handoff_ic(const HandoffShared& sh, const semipar_point_rec* drec, hipStream_t st,
+                         std::vector<HandTok>& tok);
+
+// The start tokens a hand-off batch wrote for other regions (host copy, any order).
+SP_HIDDEN int handoff_tokens(semipar_region* r, std::vector<HandTok>& out);
+
 // Record an error message for semipar_last_error.
 SP_HIDDEN void set_error(const char* msg);
 

@@ -124,7 +124,8 @@ struct Ctrl {
   int64_t n_points;
   int64_t last_cand;   // candidate appends of the last step taken (may exceed the buffer)
   int32_t err;
-  int32_t pad;
+  int32_t start_last;  // hand-off batch: the last step at which a point starts (else
+                       // INT32_MIN): the batch is not done before it
   uint64_t ext_key;    // init: order key of an element-size estimate
   Cells cells;         // grid of the current step
   double box;          // periodic length (for the grid choice)
@@ -139,6 +140,7 @@ struct Ctrl {
   // rounds of a group, and workgroups finished (all zero between steps)
   int32_t res_nlog, res_nacc, res_npass, res_iter, res_done;
   int32_t pb_step;    // persistent launch: the furthest slice any of its regions reached
+  int64_t tok_n;      // hand-off batch: start tokens written (may exceed the buffer)
 };
 
 // The last three slices of every point, one 32-byte vertex (x, y, z, t) per point per
@@ -191,6 +193,79 @@ constexpr double RCELL_W = 2.5;  // grid side in units of g
 // updates its entry each step, and neighbouring entries on one line would serialise the
 // atomics of different sub-regions.
 constexpr int REXT_STRIDE = 16;
+
+// ---- hand-off between the regions of a tiling -------------------------------------
+// A tiling run keeps the whole world sheet in device memory: the vertex of every point on
+// every slice, written once by the region that builds the diamond with that top and read
+// by every later region that needs it (Section "Semi-parallel cosmic string simulation":
+// a diamond is built by the region that holds its earliest point, and what overlaps a
+// region's final surfaces is passed on to its successors). A region's work list is a set
+// of start tokens: point q builds its diamonds in region R from step n on, because its
+// right neighbour's world line entered R at slice n - 1.
+using spi::HandTok;
+
+// Region names of the periodic tiling, the world sheet, and a hand-off batch's own
+// per-point tables (passed by value to the step kernel of such a batch).
+struct HistCfg {
+  double4* H;             // [slice - s0][slot]; t = NaN: not built
+  int64_t n;              // points of the volume
+  int32_t s0, ns;         // first slice held, slices held
+  double V[4];            // lattice origin (x, y, z, tau)
+  double inv2g, sqrt3;
+  int32_t K, S_lo, S_hi;  // names repeat with the box every K past-vertex steps
+  int32_t pad;
+  const int32_t* lut;     // [(S - S_lo) K^3 + key] -> region index, -1: not in the tiling
+  const int64_t* sname;   // per sub-region of the batch: its region's name
+  const int32_t* gnext;   // per volume slot: right neighbour's slot
+  const int32_t* gprev;   // per volume slot: left neighbour's slot
+  const int32_t* gsl;     // per local slot: volume slot
+  const int32_t* gnx;     // per local slot: volume slot of its right neighbour
+  const int32_t* start;   // per local slot: first step it builds a diamond here
+  HandTok* tok;           // tokens for other regions (capacity tok_cap)
+  int64_t tok_cap;
+};
+
+constexpr int32_t HERR_INPUT = 256;    // a diamond's input was never built
+constexpr int32_t HERR_START = 512;    // a start token whose diamond is not the region's
+constexpr int32_t HERR_SLICES = 1024;  // the world sheet holds too few slices
+constexpr int32_t HERR_SELF = 2048;    // a world line re-entered the region building it
+constexpr int32_t HERR_TOKENS = 4096;  // the token buffer overflowed
+constexpr int32_t HERR_MASK = HERR_INPUT | HERR_START | HERR_SLICES | HERR_SELF | HERR_TOKENS;
+
+// Name (S << 32 | key) of the region holding P: generator coordinates in the same
+// arithmetic as exit_face, index i = floor(c), layer S = sum i, past vertex p g/2 with
+// p = i0 h0 + i1 h1 + i2 h2 + i3 h3 (h_m the generators' spatial directions), key of
+// p mod K. A shift by the box changes i by K/4 (+-1, +-1, -+1, -+1), which keeps both.
+__device__ __forceinline__ int64_t hist_name(const HistCfg& h, const V4& P) {
+  const double dx = P.x - h.V[0];
+  const double dy = P.y - h.V[1];
+  const double dz = P.z - h.V[2];
+  const double dtau = h.sqrt3 * P.t - h.V[3];
+  const double a = dx + dy, b = dz + dtau, cc = dx - dy, d = dtau - dz;
+  const int i0 = (int)floor((a + b) * h.inv2g);
+  const int i1 = (int)floor((cc + d) * h.inv2g);
+  const int i2 = (int)floor((d - cc) * h.inv2g);
+  const int i3 = (int)floor((b - a) * h.inv2g);
+  const int K = h.K;
+  int px = (i0 + i1 - i2 - i3) % K, py = (i0 - i1 + i2 - i3) % K, pz = (i0 - i1 - i2 + i3) % K;
+  px += px < 0 ? K : 0;
+  py += py < 0 ? K : 0;
+  pz += pz < 0 ? K : 0;
+  const int S = i0 + i1 + i2 + i3;
+  return ((int64_t)S << 32) | (int64_t)(uint32_t)((px * K + py) * K + pz);
+}
+
+__device__ __forceinline__ int32_t hist_region(const HistCfg& h, int64_t name) {
+  const int S = (int)(name >> 32);
+  const int key = (int)(uint32_t)(name & 0xffffffffll);
+  if (S < h.S_lo || S > h.S_hi) return -1;
+  return h.lut[(int64_t)(S - h.S_lo) * h.K * h.K * h.K + key];
+}
+
+__device__ __forceinline__ V4 ldh(const HistCfg& h, int s, int g) {
+  const double4 v = h.H[(int64_t)(s - h.s0) * h.n + g];
+  return V4{v.x, v.y, v.z, v.w};
+}
 
 __device__ __forceinline__ V4 ld(const Slices& X, int s, int k) {
   const double4 v = X.p[s][k];
@@ -372,7 +447,14 @@ __device__ __forceinline__ LaneRun lane_run(bool has, uint32_t b) {
 // both k and next[k] advance; thread k re-derives next[k]'s decision from the same
 // inputs. All decisions read the state before the step (a stop written in this step
 // never satisfies "stopped before this step").
-template <bool FRW, int SCR, bool BND>
+// HIST (a hand-off batch of a tiling run): inputs come from the world sheet by volume
+// slot. Point k waits until its start step, then builds its diamond while the bottom
+// X[n-1][next k] lies in its region (the same test every step, also at its start, where
+// the token guarantees it) and stops for good at the first step where it does not. Each
+// new vertex goes to the world sheet and, with the slice it stands on, to this batch's
+// rings (for the elements); when it lies in another region than the point's previous
+// vertex, that region's diamond of the left neighbour built on it gets a start token.
+template <bool FRW, int SCR, bool BND, bool HIST = false>
 __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restrict__ nxt,
                                                const int32_t* __restrict__ prv,
                                                const int64_t* __restrict__ id, int n,
@@ -389,7 +471,7 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
                                                const int32_t* __restrict__ rid,
                                                const RCell* __restrict__ rcell,
                                                uint64_t* __restrict__ rext,
-                                               uint8_t* __restrict__ wlive) {
+                                               uint8_t* __restrict__ wlive, HistCfg hs) {
   if (ctrl->done) return;
   const int s = ctrl->step;
   const Cells cs = ctrl->cells;
@@ -420,13 +502,43 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   bool live_pt = k < n;
   if constexpr (BND) live_pt = live_pt && fstep[k] == FS_ACTIVE;
   else live_pt = live_pt && (!fstep || fstep[k] == FS_ACTIVE);
+  V4 L, R, B;
+  int64_t my_name = 0;
+  int g = 0;
   if (live_pt) {
     bool adv = true;
     int j = nxt[k];
     // geometry of k's region (links never leave a region, so also next[k]'s)
     RegionGeom G;
     if constexpr (BND) G = rid ? geoms[rid[k]] : G0;
-    if constexpr (BND) {
+    if constexpr (HIST) {
+      adv = false;
+      const int32_t s_start = hs.start[k];
+      if (s < s_start) {
+        still = true;  // not started yet: its wave stays live
+      } else if (s - hs.s0 >= hs.ns) {
+        atomicOr(&ctrl->err, HERR_SLICES);  // (nothing on slice s was ever written)
+        fstep[k] = s;
+      } else {
+        g = hs.gsl[k];
+        const int gj = hs.gnx[k];
+        my_name = hs.sname[rid[k]];
+        B = ldh(hs, s - 1, gj);
+        if (B.t == B.t && hist_name(hs, B) == my_name) {
+          L = ldh(hs, s, g);
+          R = ldh(hs, s, gj);
+          if (!(L.t == L.t && R.t == R.t)) {
+            atomicOr(&ctrl->err, HERR_INPUT);
+            fstep[k] = s;
+          } else {
+            adv = true;
+          }
+        } else {
+          if (s == s_start) atomicOr(&ctrl->err, HERR_START);
+          fstep[k] = s;
+        }
+      }
+    } else if constexpr (BND) {
       adv = false;
       {
         int f = -1;
@@ -450,18 +562,65 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
     if (adv) {
       nadv += 1;
       still = true;
-      const V4 L = ld(X, ic, k);
-      const V4 R = ld(X, ic, j);
-      const V4 B = ld(X, ip, j);
+      if constexpr (!HIST) {
+        L = ld(X, ic, k);
+        R = ld(X, ic, j);
+        B = ld(X, ip, j);
+      }
       const V4 T = sp::top<FRW>(L, R, B, P, hcoef);
       st(X, in, k, T);
+      if constexpr (HIST) {
+        st(X, ic, k, L);
+        if (s + 1 - hs.s0 < hs.ns) {
+          hs.H[(int64_t)(s + 1 - hs.s0) * hs.n + g] = make_double4(T.x, T.y, T.z, T.t);
+        } else {
+          atomicOr(&ctrl->err, HERR_SLICES);
+        }
+        // the diamond of k's left neighbour with bottom T belongs to T's region; its
+        // start there is announced when T is the first vertex of k's world line in it
+        const int64_t tn = hist_name(hs, T);
+        if (tn != hist_name(hs, L)) {
+          if (tn == my_name) {
+            atomicOr(&ctrl->err, HERR_SELF);
+          } else {
+            const int32_t dest = hist_region(hs, tn);
+            if (dest >= 0) {
+              const unsigned long long w =
+                  atomicAdd((unsigned long long*)&ctrl->tok_n, 1ull);
+              if ((int64_t)w < hs.tok_cap) {
+                HandTok tkn;
+                tkn.slot = hs.gprev[g];
+                tkn.step = s + 2;
+                tkn.region = dest;
+                tkn.pad = 0;
+                hs.tok[w] = tkn;
+              } else {
+                atomicOr(&ctrl->err, HERR_TOKENS);
+              }
+            }
+          }
+        }
+      }
       const uint64_t tk = order_key(T.t);
       tkey = tk < tkey ? tk : tkey;
       if constexpr (SCR != 0) {
-        const int jj = nxt[j];
+        const int jj = HIST ? -1 : nxt[j];  // (a hand-off batch reads next[j] by volume slot)
         bool jadv = true;
         V4 Rj, Bj;
-        if constexpr (BND) {
+        if constexpr (HIST) {
+          // next[k] builds its diamond in this region at this step: it is here, has
+          // started, has not stopped before, and its own bottom lies in the region
+          jadv = j >= 0 && hs.start[j] <= s && fstep[j] >= s;
+          if (jadv) {
+            const int gjj = hs.gnx[j];
+            Bj = ldh(hs, s - 1, gjj);
+            jadv = Bj.t == Bj.t && hist_name(hs, Bj) == my_name;
+            if (jadv) {
+              Rj = ldh(hs, s, gjj);
+              jadv = Rj.t == Rj.t;
+            }
+          }
+        } else if constexpr (BND) {
           jadv = fstep[j] == FS_ACTIVE && jj >= 0 && fstep[jj] >= s;
           if (jadv) {
             Bj = ld(X, ip, jj);
@@ -2378,7 +2537,10 @@ __global__ __launch_bounds__(RESOLVE_NT) void k_resolve(
     ctrl->steps_taken += 1;
     ctrl->point_steps += (int64_t)nadv;
     const double tmin = nadv ? from_key(m) : 0.0;
-    ctrl->done = (ctrl->step >= ctrl->step_limit || nadv == 0 || tmin >= ctrl->t_end) ? 1 : 0;
+    ctrl->done = (ctrl->step >= ctrl->step_limit || (nadv == 0 && ctrl->step > ctrl->start_last) ||
+                  tmin >= ctrl->t_end)
+                     ? 1
+                     : 0;
   }
   // a batch: every sub-region's grid for the next step (the events' LDS is free now)
   if (rcell) {
@@ -3171,6 +3333,104 @@ __device__ __forceinline__ semipar_point_rec current_record(const Slices& X, int
 }
 
 // Per block, the number of records of each of the 4 streams.
+// ---- hand-off batch build ---------------------------------------------------------
+// Per local slot k of the batch: its volume slot's right neighbour, id and start state;
+// gmap takes the local slot of every volume slot in the batch (reset by k_hand_unmap).
+__global__ __launch_bounds__(NT) void k_hand_init(int n, const int32_t* __restrict__ gsl,
+                                                  const int32_t* __restrict__ start,
+                                                  const int32_t* __restrict__ gnext,
+                                                  const int64_t* __restrict__ gid,
+                                                  int32_t* __restrict__ gnx, int64_t* id,
+                                                  int32_t* fstep, int32_t* face, int32_t* lev,
+                                                  int32_t* __restrict__ gmap) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const int g = gsl[k];
+  gnx[k] = gnext[g];
+  id[k] = gid[g];
+  fstep[k] = FS_ACTIVE;
+  face[k] = -1;
+  lev[k] = start[k] - 1;
+  gmap[g] = k;
+}
+
+// Local links (within one sub-region; others stay -1: their vertices are read from the
+// world sheet) and an element-size estimate from each point's first edge.
+__global__ __launch_bounds__(NT) void k_hand_links(int n, const int32_t* __restrict__ gsl,
+                                                   const int32_t* __restrict__ gnx,
+                                                   const int32_t* __restrict__ start,
+                                                   const int32_t* __restrict__ gprev,
+                                                   const int32_t* __restrict__ gmap,
+                                                   const int32_t* __restrict__ rid,
+                                                   int32_t* nxt, int32_t* prv, HistCfg hs,
+                                                   sp::Period P, Ctrl* ctrl) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  uint64_t key = 0;
+  if (k < n) {
+    const int g = gsl[k];
+    int a = gmap[gnx[k]];
+    int b = gmap[gprev[g]];
+    if (a >= 0 && rid[a] != rid[k]) a = -1;
+    if (b >= 0 && rid[b] != rid[k]) b = -1;
+    nxt[k] = a;
+    prv[k] = b;
+    const int s = start[k];
+    if (s - hs.s0 >= 0 && s - hs.s0 < hs.ns) {
+      const V4 L = ldh(hs, s, g), R = ldh(hs, s, gnx[k]);
+      if (L.t == L.t && R.t == R.t) {
+        double e = 0.0;
+        const double d[3] = {R.x - L.x, R.y - L.y, R.z - L.z};
+        for (int c = 0; c < 3; ++c) {
+          const double w = d[c] - P.box * P.nearest(d[c]);
+          e = fmax(e, fabs(w));
+        }
+        key = order_key(e);
+      }
+    }
+  }
+  key = wave_max_u64(key);
+  if ((threadIdx.x & 63) == 0 && key != 0) atomicMax((unsigned long long*)&ctrl->ext_key, key);
+}
+
+__global__ __launch_bounds__(NT) void k_hand_unmap(int n, const int32_t* __restrict__ gsl,
+                                                   int32_t* __restrict__ gmap) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k < n) gmap[gsl[k]] = -1;
+}
+
+// ---- hand-off run set-up ------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_hist_fill(double4* __restrict__ H, uint64_t m) {
+  const uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * NT;
+  for (uint64_t q = i; q < m; q += stride) H[q] = make_double4(0.0, 0.0, 0.0, __builtin_nan(""));
+}
+
+// The initial surface's two slices into the world sheet; start tokens of the first two
+// diamonds each point's left neighbour builds: their bottoms are the point's vertices on
+// the two initial slices, so they belong to those vertices' regions.
+__global__ __launch_bounds__(NT) void k_hist_ic(const semipar_point_rec* __restrict__ rec, int n,
+                                                HistCfg hs, HandTok* __restrict__ tok,
+                                                unsigned long long* __restrict__ ntok) {
+  const int j = blockIdx.x * NT + threadIdx.x;
+  if (j >= n) return;
+  const semipar_point_rec r = rec[j];
+  const V4 a{r.x_prev[0], r.x_prev[1], r.x_prev[2], r.x_prev[3]};
+  const V4 b{r.x[0], r.x[1], r.x[2], r.x[3]};
+  hs.H[j] = make_double4(a.x, a.y, a.z, a.t);
+  hs.H[hs.n + j] = make_double4(b.x, b.y, b.z, b.t);
+  const int64_t na = hist_name(hs, a), nb = hist_name(hs, b);
+  const int32_t da = hist_region(hs, na);
+  const int32_t db = nb != na ? hist_region(hs, nb) : -1;
+  if (da >= 0) {
+    const unsigned long long w = atomicAdd(ntok, 1ull);
+    tok[w] = HandTok{hs.gprev[j], hs.s0 + 1, da, 0};
+  }
+  if (db >= 0) {
+    const unsigned long long w = atomicAdd(ntok, 1ull);
+    tok[w] = HandTok{hs.gprev[j], hs.s0 + 2, db, 0};
+  }
+}
+
 __global__ __launch_bounds__(NT) void k_emit_count(int n, const int32_t* fstep,
                                                    const semipar_point_rec* frz,
                                                    int32_t* __restrict__ blkcnt) {
@@ -3310,12 +3570,17 @@ __global__ __launch_bounds__(NT) void k_sub_stats(int n, const int32_t* __restri
                                                   int32_t cur, int32_t step0,
                                                   const int32_t* __restrict__ rid,
                                                   unsigned long long* __restrict__ psteps,
-                                                  int32_t* __restrict__ smax) {
+                                                  int32_t* __restrict__ smax,
+                                                  const int32_t* __restrict__ start) {
   const int k = blockIdx.x * NT + threadIdx.x;
   const bool live = k < n;
   const int q = live ? (rid ? rid[k] : 0) : -1;
   int adv = 0;
-  if (live) adv = (fstep[k] == FS_ACTIVE ? cur : fstep[k]) - step0;
+  if (live) {
+    // a hand-off batch's points start at their own steps
+    adv = (fstep[k] == FS_ACTIVE ? cur : fstep[k]) - (start ? start[k] : step0);
+    adv = adv < 0 ? 0 : adv;
+  }
   if (wave_uniform(q, live)) {
     unsigned long long sum = (unsigned long long)adv;
     int mx = adv;
@@ -3813,6 +4078,13 @@ struct semipar_region {
   semipar_loop* llog = nullptr;  // loop log (completion order within a check)
   int32_t* llog_rid = nullptr;   // sub-region of each logged loop (batches; else 0)
   int64_t llog_n = 0, llog_cap = 0;
+  // hand-off batch of a tiling run: the world sheet and the tiling's names are the
+  // caller's; the per-point tables and the token buffer are the region's
+  bool hist = false;
+  HistCfg hcfg{};
+  int32_t *hgsl = nullptr, *hgnx = nullptr, *hstart = nullptr;
+  int64_t* hsname = nullptr;
+  HandTok* htok = nullptr;
 };
 
 namespace {
@@ -3961,6 +4233,25 @@ int ensure_log(semipar_region* r, int64_t need) {
   return SEMIPAR_OK;
 }
 
+// Hand-off batch: room for `need` start tokens (the written ones are kept).
+int ensure_tokens(semipar_region* r, int64_t need) {
+  if (r->hcfg.tok_cap >= need && r->htok) return SEMIPAR_OK;
+  const int64_t nc = std::max<int64_t>(need, std::max<int64_t>(2 * r->hcfg.tok_cap, 1 << 16));
+  HandTok* nt = nullptr;
+  HIPCHK(dalloc(&nt, (size_t)nc));
+  const int64_t have = std::min<int64_t>(r->ctrl_h->tok_n, r->hcfg.tok_cap);
+  if (r->htok && have > 0)
+    HIPCHK(hipMemcpyAsync(nt, r->htok, sizeof(HandTok) * have, hipMemcpyDeviceToDevice,
+                          r->stream));
+  HIPCHK(hipStreamSynchronize(r->stream));
+  if (r->htok) r->retired.push_back(r->htok);
+  r->htok = nt;
+  r->hcfg.tok = nt;
+  r->hcfg.tok_cap = nc;
+  drop_graph(r);  // the step launches carry the buffer
+  return SEMIPAR_OK;
+}
+
 // A deferred step reported that the candidate (bit 1) or event (bit 2) buffer was too
 // small: double it. The step is then taken again from the same state.
 int grow_step_caps(semipar_region* r, int defer) {
@@ -3986,29 +4277,32 @@ int grow_step_caps(semipar_region* r, int defer) {
   return SEMIPAR_OK;
 }
 
-template <bool FRW, int SCR, bool BND>
+template <bool FRW, int SCR, bool BND, bool HIST>
 void launch_evolve_t(semipar_region* r, int n, int nb) {
-  k_evolve<FRW, SCR, BND><<<nb, NT, 0, r->stream>>>(
+  k_evolve<FRW, SCR, BND, HIST><<<nb, NT, 0, r->stream>>>(
       r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell,
       r->cnt, r->large, r->blkred, (BND || r->removed) ? r->fstep : nullptr, r->face, r->frz,
-      r->geom, r->geoms, r->rid, r->rcell, r->rext, r->wlive);
+      r->geom, r->geoms, r->rid, r->rcell, r->rext, r->wlive, r->hcfg);
 }
 
-template <bool FRW, bool BND>
+template <bool FRW, bool BND, bool HIST>
 void launch_evolve_s(semipar_region* r, int scr, int n, int nb) {
-  if (scr == 0) launch_evolve_t<FRW, 0, BND>(r, n, nb);
-  else if (scr == 1) launch_evolve_t<FRW, 1, BND>(r, n, nb);
-  else launch_evolve_t<FRW, 2, BND>(r, n, nb);
+  if (scr == 0) launch_evolve_t<FRW, 0, BND, HIST>(r, n, nb);
+  else if (scr == 1) launch_evolve_t<FRW, 1, BND, HIST>(r, n, nb);
+  else launch_evolve_t<FRW, 2, BND, HIST>(r, n, nb);
 }
 
 // Diamond tops (+ element data when scr != 0) of one step.
 void launch_evolve(semipar_region* r, bool frw, int scr, bool bnd, int n, int nb) {
-  if (frw) {
-    if (bnd) launch_evolve_s<true, true>(r, scr, n, nb);
-    else launch_evolve_s<true, false>(r, scr, n, nb);
+  if (r->hist) {
+    if (frw) launch_evolve_s<true, true, true>(r, scr, n, nb);
+    else launch_evolve_s<false, true, true>(r, scr, n, nb);
+  } else if (frw) {
+    if (bnd) launch_evolve_s<true, true, false>(r, scr, n, nb);
+    else launch_evolve_s<true, false, false>(r, scr, n, nb);
   } else {
-    if (bnd) launch_evolve_s<false, true>(r, scr, n, nb);
-    else launch_evolve_s<false, false>(r, scr, n, nb);
+    if (bnd) launch_evolve_s<false, true, false>(r, scr, n, nb);
+    else launch_evolve_s<false, false, false>(r, scr, n, nb);
   }
 }
 
@@ -4353,6 +4647,11 @@ void region_destroy(semipar_region* r) {
   dfree(r->lacc);
   dfree(r->llog);
   dfree(r->llog_rid);
+  dfree(r->hgsl);
+  dfree(r->hgnx);
+  dfree(r->hstart);
+  dfree(r->hsname);
+  dfree(r->htok);
   if (r->lctr_h) (void)hipHostFree(r->lctr_h);
   if (r->ctrl_h) (void)hipHostFree(r->ctrl_h);
   if (r->ev0) (void)hipEventDestroy(r->ev0);
@@ -4565,8 +4864,10 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   spi::begin_call();
   if (!r || !p || p->max_steps < 0 || p->loop_every < 0) return SEMIPAR_E_ARG;
   if (p->screen != SEMIPAR_SCREEN_F64 && p->screen != SEMIPAR_SCREEN_F32) return SEMIPAR_E_ARG;
-  const double p_ic = p->p == 0.0 ? 1.0 : p->p;
-  if (!(p_ic > 0.0 && p_ic <= 1.0)) return SEMIPAR_E_ARG;
+  if (r->hist && p->loop_every != 0) return SEMIPAR_E_ARG;
+  // a hand-off batch passes every crossing through (links never change)
+  const double p_ic = r->hist ? 0.0 : (p->p == 0.0 ? 1.0 : p->p);
+  if (!(p_ic >= 0.0 && p_ic <= 1.0) || (!r->hist && p_ic == 0.0)) return SEMIPAR_E_ARG;
   if (!(p->cell_factor == 0.0 || (p->cell_factor >= 1.0 && p->cell_factor <= 4.0)))
     return SEMIPAR_E_ARG;
   if (r->broken) return SEMIPAR_E_STATE;
@@ -4602,7 +4903,8 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     r->p_ic = p_ic;
     r->seed = p->seed;
   }
-  if (p->persistent && persistent_ok(r, p)) return evolve_persistent(r, p, st, before, step_limit);
+  if (p->persistent && !r->hist && persistent_ok(r, p))
+    return evolve_persistent(r, p, st, before, step_limit);
   r->timed = (p->timed_kernel >= 0 && p->timed_kernel <= SEMIPAR_K_RESOLVE) ? p->timed_kernel : -1;
   if (r->timed >= 0) {
     rc = ensure_timing_events(r, K);
@@ -4663,6 +4965,11 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   for (;;) {
     rc = ensure_log(r, r->ctrl_h->log_n + 2 * r->cap_evt);
     if (rc != SEMIPAR_OK) return rc;
+    if (r->hist) {
+      // every point writes at most one token per step: room for a whole block
+      rc = ensure_tokens(r, r->ctrl_h->tok_n + (int64_t)K * r->n);
+      if (rc != SEMIPAR_OK) return rc;
+    }
     const int64_t taken0 = r->ctrl_h->steps_taken;
     // HIP events recorded inside a captured graph cannot be timed: a timed call
     // issues its steps eagerly.
@@ -4733,6 +5040,19 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, r->ev0, r->ev1));
   const Ctrl& a = *r->ctrl_h;
+  if (r->hist && (a.err & HERR_MASK)) {
+    r->broken = true;
+    char msg[256];
+    snprintf(msg, sizeof(msg),
+             "hand-off batch: %s%s%s%s%s",
+             (a.err & HERR_INPUT) ? "a diamond's input was never built; " : "",
+             (a.err & HERR_START) ? "a start token for a diamond of another region; " : "",
+             (a.err & HERR_SLICES) ? "the world sheet holds too few slices; " : "",
+             (a.err & HERR_SELF) ? "a world line re-entered its region; " : "",
+             (a.err & HERR_TOKENS) ? "token buffer overflow; " : "");
+    spi::set_error(msg);
+    return (a.err & HERR_SLICES) ? SEMIPAR_E_OVERFLOW : SEMIPAR_E_STATE;
+  }
   if (st) {
     st->steps = a.steps_taken - before.steps_taken;
     st->point_steps = a.point_steps - before.point_steps;
@@ -5006,6 +5326,209 @@ int batch_emit(semipar_region* r, semipar_point_rec* out, std::vector<int64_t>& 
   return rc;
 }
 
+int handoff_batch(const HandoffShared& sh, const int32_t* slot, const int32_t* start,
+                  const std::vector<int64_t>& sub_off, const semipar_region_geom* geoms,
+                  const int64_t* names, hipStream_t stream, semipar_region** out) {
+  *out = nullptr;
+  const int ns = (int)sub_off.size() - 1;
+  if (ns <= 0 || !sh.H || !sh.gmap) return SEMIPAR_E_ARG;
+  const int64_t total = sub_off[ns];
+  if (total <= 0 || total >= (int64_t)1 << 30) return SEMIPAR_E_ARG;
+  semipar_region* r = new (std::nothrow) semipar_region();
+  if (!r) return SEMIPAR_E_OOM;
+  auto fail = [&](int code) {
+    region_destroy(r);
+    return code;
+  };
+  r->n = total;
+  r->cap = total;
+  r->cosmology = sh.cosmology;
+  r->hcoef = sh.cosmology == SEMIPAR_MATTER ? 2.0 : (sh.cosmology == SEMIPAR_RADIATION ? 1.0 : 0.0);
+  r->box = sh.box;
+  r->bounded = true;
+  r->hist = true;
+  {
+    int ex = 0;
+    const double mant = std::frexp(sh.box, &ex);
+    r->P.box = sh.box;
+    r->P.pow2 = mant == 0.5 ? 1 : 0;
+    r->P.inv = r->P.pow2 ? std::ldexp(1.0, 1 - ex) : 1.0 / sh.box;
+  }
+  r->stream = stream;
+  if (!r->stream) {
+    if (hipStreamCreate(&r->stream) != hipSuccess) return fail(SEMIPAR_E_HIP);
+    r->own_stream = true;
+  }
+  const int64_t cap = total;
+  const int n = (int)total;
+  for (int q = 0; q < 3; ++q)
+    if (dalloc(&r->X.p[q], cap) != hipSuccess) return fail(oom(__LINE__));
+  if (dalloc(&r->nxt, cap) != hipSuccess || dalloc(&r->prv, cap) != hipSuccess ||
+      dalloc(&r->id, cap) != hipSuccess || dalloc(&r->ctrl, 1) != hipSuccess ||
+      dalloc(&r->blkred, 4 * (size_t)blocks(cap)) != hipSuccess ||
+      dalloc(&r->fstep, cap) != hipSuccess || dalloc(&r->face, cap) != hipSuccess ||
+      dalloc(&r->lev, cap) != hipSuccess || dalloc(&r->wlive, (cap + 63) / 64) != hipSuccess ||
+      dalloc(&r->geoms, ns) != hipSuccess || dalloc(&r->rid, cap) != hipSuccess ||
+      dalloc(&r->rcell, ns) != hipSuccess ||
+      dalloc(&r->rext, (size_t)ns * REXT_STRIDE) != hipSuccess ||
+      dalloc(&r->hgsl, cap) != hipSuccess || dalloc(&r->hgnx, cap) != hipSuccess ||
+      dalloc(&r->hstart, cap) != hipSuccess || dalloc(&r->hsname, ns) != hipSuccess)
+    return fail(oom(__LINE__));
+  if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
+    return fail(oom(__LINE__));
+  r->n_sub = ns;
+  r->sub_off = sub_off;
+  std::vector<RegionGeom> hg((size_t)ns);
+  for (int i = 0; i < ns; ++i) {
+    for (int q = 0; q < 4; ++q) {
+      hg[i].V[q] = geoms[i].origin[q];
+      hg[i].idx[q] = geoms[i].idx[q];
+    }
+    hg[i].inv2g = geoms[i].inv2g;
+    hg[i].sqrt3 = std::sqrt(3.0);
+  }
+  int32_t smin = INT32_MAX, smax = INT32_MIN;
+  for (int64_t k = 0; k < total; ++k) {
+    smin = std::min(smin, start[k]);
+    smax = std::max(smax, start[k]);
+  }
+  if (smin - 1 < sh.s0 || smin < 1) return fail(SEMIPAR_E_ARG);
+  r->step0 = smin;
+  Ctrl c0{};
+  c0.step = smin;
+  c0.start_last = smax;
+  c0.tmin_key = KEY_MAX;
+  c0.n_points = total;
+  c0.step_limit = smin;
+  c0.done = 1;
+  c0.box = sh.box;
+  c0.grow = CELL_GROW;
+  c0.tol = sh.box * std::ldexp(1.0, -30);
+  HistCfg& h = r->hcfg;
+  h.H = (double4*)sh.H;
+  h.n = sh.n;
+  h.s0 = sh.s0;
+  h.ns = sh.ns;
+  for (int q = 0; q < 4; ++q) h.V[q] = sh.V[q];
+  h.inv2g = sh.inv2g;
+  h.sqrt3 = std::sqrt(3.0);
+  h.K = sh.K;
+  h.S_lo = sh.S_lo;
+  h.S_hi = sh.S_hi;
+  h.lut = sh.lut;
+  h.sname = r->hsname;
+  h.gnext = sh.gnext;
+  h.gprev = sh.gprev;
+  h.gsl = r->hgsl;
+  h.gnx = r->hgnx;
+  h.start = r->hstart;
+  h.tok = nullptr;
+  h.tok_cap = 0;
+  int64_t* doff = nullptr;
+  hipStream_t st = r->stream;
+  int rc = SEMIPAR_OK;
+  if (salloc(&doff, (size_t)ns + 1, st) != hipSuccess) return fail(oom(__LINE__));
+  if (hipMemsetAsync(r->wlive, 1, (size_t)(cap + 63) / 64, st) != hipSuccess ||
+      hipMemsetAsync(r->rcell, 0, sizeof(RCell) * ns, st) != hipSuccess ||
+      hipMemsetAsync(r->rext, 0, sizeof(uint64_t) * ns * REXT_STRIDE, st) != hipSuccess ||
+      hipMemcpyAsync(r->geoms, hg.data(), sizeof(RegionGeom) * ns, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(r->hgsl, slot, sizeof(int32_t) * total, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(r->hstart, start, sizeof(int32_t) * total, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(r->hsname, names, sizeof(int64_t) * ns, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(doff, sub_off.data(), sizeof(int64_t) * ((size_t)ns + 1),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(r->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, st) != hipSuccess)
+    rc = SEMIPAR_E_HIP;
+  for (int q = 0; q < 3 && rc == SEMIPAR_OK; ++q)
+    if (hipMemsetAsync(r->X.p[q], 0, sizeof(double4) * cap, st) != hipSuccess) rc = SEMIPAR_E_HIP;
+  if (rc == SEMIPAR_OK) {
+    k_fill_rid<<<blocks(total), NT, 0, st>>>(r->rid, n, doff, ns);
+    k_hand_init<<<blocks(total), NT, 0, st>>>(n, r->hgsl, r->hstart, sh.gnext, sh.gid, r->hgnx,
+                                             r->id, r->fstep, r->face, r->lev, sh.gmap);
+    k_hand_links<<<blocks(total), NT, 0, st>>>(n, r->hgsl, r->hgnx, r->hstart, sh.gprev, sh.gmap,
+                                              r->rid, r->nxt, r->prv, r->hcfg, r->P, r->ctrl);
+    k_hand_unmap<<<blocks(total), NT, 0, st>>>(n, r->hgsl, sh.gmap);
+    if (hipError_t e_ = hipGetLastError(); e_ != hipSuccess) rc = hip_fail(e_, "launch", __LINE__);
+  }
+  // the host arrays are read before the call returns
+  if (rc == SEMIPAR_OK && read_ctrl(r) != SEMIPAR_OK) rc = SEMIPAR_E_HIP;
+  sfree(doff, st);
+  if (rc != SEMIPAR_OK) return fail(rc);
+  r->ext0 = from_key(r->ctrl_h->ext_key);
+  if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess)
+    return fail(SEMIPAR_E_HIP);
+  if (ensure_log(r, 1 << 16) != SEMIPAR_OK) return fail(oom(__LINE__));
+  *out = r;
+  return SEMIPAR_OK;
+}
+
+int handoff_ic(const HandoffShared& sh, const semipar_point_rec* drec, hipStream_t st,
+               std::vector<HandTok>& tok) {
+  tok.clear();
+  if (sh.n <= 0 || sh.ns < 2 || sh.n >= (int64_t)1 << 31) return SEMIPAR_E_ARG;
+  HistCfg h{};
+  h.H = (double4*)sh.H;
+  h.n = sh.n;
+  h.s0 = sh.s0;
+  h.ns = sh.ns;
+  for (int q = 0; q < 4; ++q) h.V[q] = sh.V[q];
+  h.inv2g = sh.inv2g;
+  h.sqrt3 = std::sqrt(3.0);
+  h.K = sh.K;
+  h.S_lo = sh.S_lo;
+  h.S_hi = sh.S_hi;
+  h.lut = sh.lut;
+  h.gnext = sh.gnext;
+  h.gprev = sh.gprev;
+  HandTok* dt = nullptr;
+  unsigned long long* dn = nullptr;
+  if (salloc(&dt, 2 * (size_t)sh.n, st) != hipSuccess || salloc(&dn, 1, st) != hipSuccess) {
+    sfree(dt, st);
+    sfree(dn, st);
+    return oom(__LINE__);
+  }
+  int rc = SEMIPAR_OK;
+  unsigned long long nt = 0;
+  const uint64_t cells = (uint64_t)sh.ns * (uint64_t)sh.n;
+  if (hipMemsetAsync(dn, 0, sizeof(unsigned long long), st) != hipSuccess) rc = SEMIPAR_E_HIP;
+  if (rc == SEMIPAR_OK) {
+    k_hist_fill<<<4096, NT, 0, st>>>((double4*)sh.H, cells);
+    k_hist_ic<<<blocks(sh.n), NT, 0, st>>>(drec, (int)sh.n, h, dt, dn);
+    if (hipError_t e_ = hipGetLastError(); e_ != hipSuccess) rc = hip_fail(e_, "launch", __LINE__);
+  }
+  if (rc == SEMIPAR_OK &&
+      (hipMemcpyAsync(&nt, dn, sizeof(nt), hipMemcpyDeviceToHost, st) != hipSuccess ||
+       hipStreamSynchronize(st) != hipSuccess))
+    rc = SEMIPAR_E_HIP;
+  if (rc == SEMIPAR_OK && nt > 0) {
+    tok.resize((size_t)nt);
+    if (hipMemcpyAsync(tok.data(), dt, sizeof(HandTok) * nt, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      rc = SEMIPAR_E_HIP;
+  }
+  sfree(dt, st);
+  sfree(dn, st);
+  return rc;
+}
+
+int handoff_tokens(semipar_region* r, std::vector<HandTok>& out) {
+  out.clear();
+  if (!r || !r->hist) return SEMIPAR_E_ARG;
+  RCCHK(read_ctrl(r));
+  const int64_t nt = std::min<int64_t>(r->ctrl_h->tok_n, r->hcfg.tok_cap);
+  if (nt <= 0) return SEMIPAR_OK;
+  out.resize((size_t)nt);
+  HIPCHK(hipMemcpyAsync(out.data(), r->htok, sizeof(HandTok) * nt, hipMemcpyDeviceToHost,
+                        r->stream));
+  HIPCHK(hipStreamSynchronize(r->stream));
+  return SEMIPAR_OK;
+}
+
 int batch_stats(semipar_region* r, std::vector<int32_t>& steps, std::vector<int64_t>& psteps) {
   if (!r || !r->bounded) return SEMIPAR_E_ARG;
   const int ns = r->n_sub > 0 ? r->n_sub : 1;  // a lone bounded region is one sub-region
@@ -5024,7 +5547,7 @@ int batch_stats(semipar_region* r, std::vector<int32_t>& steps, std::vector<int6
     rc = SEMIPAR_E_HIP;
   if (rc == SEMIPAR_OK) {
     k_sub_stats<<<blocks(r->n), NT, 0, r->stream>>>((int)r->n, r->fstep, r->ctrl_h->step, r->step0,
-                                                    r->rid, ps, sm);
+                                                    r->rid, ps, sm, r->hstart);
     std::vector<unsigned long long> hps((size_t)ns);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(hps.data(), ps, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost,

@@ -122,6 +122,16 @@ class SchedStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Handoff(ctypes.Structure):
+    _fields_ = [("n_regions", ctypes.c_int32), ("cosmology", ctypes.c_int32),
+                ("box", ctypes.c_double), ("geoms", ctypes.c_void_p),
+                ("n_pred", ctypes.c_void_p), ("succ_off", ctypes.c_void_p),
+                ("succ", ctypes.c_void_p), ("ic", ctypes.c_void_p),
+                ("n_points", ctypes.c_int64), ("ic_mem", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hist", ctypes.c_void_p),
+                ("hist_slices", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+
+
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
 PACK_POINTS, PACK_WORK = 0, 1
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
@@ -131,7 +141,8 @@ PERSISTENT_EVENTS = 160  # SEMIPAR_PERSISTENT_EVENTS
 # exported symbols declared in include/semipar.h
 SYMBOLS = ["region_init_from_surfaces", "region_evolve", "region_emit_final_surfaces",
            "region_events", "region_candidates", "region_loops", "region_destroy", "semipar_strerror", "semipar_version",
-           "semipar_last_error", "schedule_regions", "semipar_region_features",
+           "semipar_last_error", "schedule_regions", "schedule_handoff",
+           "semipar_region_features",
            "semipar_mlp_forward", "semipar_mlp_loss_grad", "semipar_mlp_loss_grad_noalloc",
            "semipar_mlp_adam_step",
            "semipar_mlp_train", "semipar_mlp_norm"]
@@ -172,6 +183,9 @@ def lib():
         L.schedule_regions.argtypes = [ctypes.POINTER(Tiling), ctypes.POINTER(SchedParams),
                                        ctypes.POINTER(SchedStats)]
         L.schedule_regions.restype = ctypes.c_int
+        L.schedule_handoff.argtypes = [ctypes.POINTER(Handoff), ctypes.POINTER(SchedParams),
+                                       ctypes.POINTER(SchedStats)]
+        L.schedule_handoff.restype = ctypes.c_int
         L.semipar_region_features.argtypes = [ctypes.POINTER(Tiling), P]
         L.semipar_region_features.restype = ctypes.c_int
         L.semipar_mlp_forward.argtypes = [P, P, P, ctypes.c_int64, P, P]
@@ -520,6 +534,73 @@ def schedule_regions(rs, policy=SCHED_BATCHED, batch_points=0, cost=None, out="h
         res["events"], res["events_off"] = ev[:st.events], ev_off
     if loop_every:
         res["loops"], res["loops_off"] = lp[:st.loops], lp_off
+    return res
+
+
+def schedule_handoff(ic, box, cosmology, geoms, n_pred, succ, hist, batch_points=0,
+                     cost=None, events=True, stream=None, max_steps=0, screen=SCREEN_F64,
+                     intercommute=True, cell_size=0.0, steps_per_sync=0, use_graph=False,
+                     cand_per_point=0.0, events_per_point=0.0, timed_kernel=-1, seed=0,
+                     cell_factor=0.0):
+    """Run a periodic tiling region by region with hand-off (schedule_handoff).
+
+    ic: the volume's initial surface (numpy records); geoms: per region (origin[4],
+    inv2g, idx[4]); n_pred, succ: predecessor counts and successor lists; hist: a CUDA
+    float64 tensor of shape (slices, n_points, 4), the world sheet (filled by the call).
+    Returns a dict with the stats, per-region logs and the events with offsets."""
+    import torch
+    L = lib()
+    ic = np.ascontiguousarray(ic, dtype=REC_DTYPE)
+    n = len(ic)
+    nr = len(geoms)
+    assert hist.is_cuda and hist.dtype == torch.float64 and hist.is_contiguous()
+    assert hist.dim() == 3 and hist.shape[1] == n and hist.shape[2] == 4
+    garr = (RegionGeom * max(nr, 1))()
+    for r, gm in enumerate(geoms):
+        garr[r] = _geom_struct(gm)
+    npred = np.ascontiguousarray(n_pred, dtype=np.int32)
+    off = np.zeros(nr + 1, dtype=np.int32)
+    off[1:] = np.cumsum([len(x) for x in succ])
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(x, np.int32) for x in succ])
+                                if off[-1] else np.zeros(1, np.int32))
+    h = Handoff()
+    h.n_regions, h.cosmology, h.box = nr, int(cosmology), float(box)
+    h.geoms = ctypes.addressof(garr)
+    h.n_pred, h.succ_off, h.succ = npred.ctypes.data, off.ctypes.data, flat.ctypes.data
+    h.ic, h.n_points, h.ic_mem = ic.ctypes.data, n, MEM_HOST
+    h.hist, h.hist_slices = hist.data_ptr(), int(hist.shape[0])
+    h.stream = stream if stream is not None else _current_stream()
+    p = SchedParams()
+    p.batch_points = int(batch_points)
+    cost_arr = None
+    if cost is not None:
+        cost_arr = np.ascontiguousarray(cost, dtype=np.float32)
+        assert len(cost_arr) == nr
+        p.cost = cost_arr.ctypes.data
+    p.evolve = EvolveParams(int(max_steps), float("inf"), int(screen), int(bool(intercommute)),
+                            float(cell_size), int(steps_per_sync), int(bool(use_graph)),
+                            float(cand_per_point), float(events_per_point), int(timed_kernel),
+                            0, 0, 0, 0.0, int(seed), float(cell_factor))
+    ev_off = np.zeros(nr + 1, dtype=np.int64)
+    ev_cap = max(n, 4096)
+    ev = np.zeros(ev_cap, dtype=EVENT_DTYPE) if events else None
+    if events:
+        p.events, p.events_cap, p.events_off = ev.ctypes.data, ev_cap, ev_off.ctypes.data
+    steps = np.zeros(max(nr, 1), dtype=np.int32)
+    psteps = np.zeros(max(nr, 1), dtype=np.int64)
+    batch = np.zeros(max(nr, 1), dtype=np.int32)
+    ms = np.zeros(max(nr, 1), dtype=np.float64)
+    p.region_steps, p.region_point_steps = steps.ctypes.data, psteps.ctypes.data
+    p.region_batch, p.region_ms = batch.ctypes.data, ms.ctypes.data
+    st = SchedStats()
+    _check(L.schedule_handoff(ctypes.byref(h), ctypes.byref(p), ctypes.byref(st)),
+           "schedule_handoff")
+    res = dict(stats=st.as_dict(), region_steps=steps[:nr], region_point_steps=psteps[:nr],
+               region_batch=batch[:nr], region_ms=ms[:nr])
+    if events:
+        if st.events > ev_cap:
+            raise SemiparError(-5, f"schedule_handoff: {st.events} events > buffer {ev_cap}")
+        res["events"], res["events_off"] = ev[:st.events], ev_off
     return res
 
 
