@@ -20,10 +20,15 @@ Also reported: the point-count heuristic (same pipeline, no model), the plain
 per-region path (one region at a time, FP64 screen, one host check per step, no
 graphs, no batching), the roofline of the dominant kernel and the oracle on the host.
 
---workload tiling: the learned-scheduling workload. The initial slice of a 32^3 VV
-network (seed 1) is cut into a periodic spacetime tiling of 16 layers x 256 regions
-(4096), run in dependency order; the cost model is trained on the seed-0 network in the
-same tiling. Same pipeline and report as the default.
+--workload tiling: a 32^3 matter-era VV network (seed 1, ~2.4e5 points, eta 8) in a
+periodic spacetime tiling of 16 layers x 256 regions (4096), run region by region in
+dependency order with hand-off (schedule_handoff): every region builds the diamonds
+whose earliest point it holds from what its predecessors and the initial surface built,
+searches the crossings of its own elements (they pass through: intercommutation
+probability 0, so that the run equals one whole-volume run), and starts its successors'
+work. One step = the whole tiling, world sheet resident in HBM. Reported against the
+plain per-region hand-off path (one region per launch sequence, FP64 screen, a host
+check every step, no graphs) and the oracle's whole-volume run on the host.
 
 --workload vv32: one whole-volume matter-era region (32^3 VV network, ~2.4e5 points,
 eta 8 -> 16), as before.
@@ -127,38 +132,127 @@ def make_inputs(args):
     return parts, box, train, tbox
 
 
-def make_tiling_inputs(args):
-    """Learned-scheduling workload: the initial slice of a 32^3 matter-era VV network
-    (seed 1) cut into a periodic spacetime tiling of 16 layers x 4 M^3 regions (M =
-    --split, 4 by default: 256 per layer), run in dependency order. Training logs come
-    from the seed-0 network in the same tiling."""
+def handoff_inputs(args, seed=1):
+    """Network, tiling geometry and dependency lists of the hand-off workload, and the
+    number of world-sheet slices its last layer needs."""
+    import numpy as np
     from paper_1011_4046_amd import inputs as I
     t = time.perf_counter()
-    out = []
-    for seed in (1, 0):
-        net = I.vv_network(m=args.m, seed=seed)
-        parts, box, n_pred, succ, _ = I.tiling_regions(net, M=args.split_m, layers=16)
-        out.append((parts, box, dict(n_pred=n_pred, succ=succ)))
-        log(f"tiling (seed {seed}): {len(parts)} regions, "
-            f"{sum(1 for p in parts if len(p[0]))} non-empty, "
-            f"{sum(len(p[0]) for p in parts)} points ({time.perf_counter() - t:.1f} s)")
-    return out
+    net = I.vv_network(m=args.m, seed=seed)
+    parts, box, n_pred, succ, _ = I.tiling_regions(net, M=args.split_m, layers=16)
+    geoms = [g for _, g in parts]
+    V, inv2g = geoms[0][:4], geoms[0][4]
+    g = 0.5 / inv2g
+    t_last = (V[3] + 0.5 * g * 15 + 2 * g) / np.sqrt(3.0)
+    # the initial slices are dt apart in t; in an expanding universe later slices of a
+    # moving string advance t by less, so twice that many slices, grown on overflow
+    rec = net["recs"][0]
+    dt = float(rec["x"][3] - rec["x_prev"][3])
+    slices = 2 * int(np.ceil((t_last - float(rec["x_prev"][3])) / dt)) + 8
+    log(f"hand-off tiling (seed {seed}): {len(net['recs'])} points, {len(geoms)} regions, "
+        f"{slices} slices ({time.perf_counter() - t:.1f} s)")
+    return net, box, geoms, n_pred, succ, slices
+
+
+def bench_handoff(args):
+    import numpy as np
+    import torch
+    from paper_1011_4046_amd import semipar as S
+    net, box, geoms, n_pred, succ, slices = handoff_inputs(args)
+    n = len(net["recs"])
+    torch.cuda.set_device(0)
+    screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
+    kw = dict(use_graph=True, screen=screen, steps_per_sync=args.sync_steps,
+              batch_points=0, cell_factor=args.cell_factor, screen_split=args.split)
+    hist = None
+    run = lambda **k: S.schedule_handoff(net["recs"], box, net["cosmology"], geoms, n_pred, succ,
+                                         hist, **k)
+    for _ in range(4):
+        hist = torch.empty((slices, n, 4), dtype=torch.float64, device="cuda")
+        try:
+            r = run(**kw)
+            break
+        except S.SemiparError as e:
+            if e.code != -5:
+                raise
+            log(f"world sheet of {slices} slices too short: doubled")
+            del hist
+            slices *= 2
+    log(f"first run: {r['stats']['batches']} batches, {r['stats']['makespan_ms']:.0f} ms")
+    for w in range(args.warmup):
+        r = run(**kw)
+        log(f"warmup {w}: {r['stats']['batches']} batches, {r['stats']['makespan_ms']:.0f} ms")
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        runs.append(run(**kw))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    point_steps = sum(r["stats"]["point_steps"] for r in runs)
+    value = point_steps / elapsed
+    st = runs[0]["stats"]
+    log(f"timed {args.steps} tilings: {elapsed * 1e3:.0f} ms, {point_steps} point-steps, "
+        f"{st['batches']} batches, {st['events']} crossings per tiling")
+    extra = {"handoff": {"batches": st["batches"], "empty_regions": st["empty_regions"],
+                         "makespan_ms": st["makespan_ms"], "evolve_ms": st["evolve_ms"],
+                         "crossings": st["events"]}}
+    if args.plain:
+        t = time.perf_counter()
+        rp = run(use_graph=False, screen=S.SCREEN_F64, steps_per_sync=1, batch_points=1)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        pv = rp["stats"]["point_steps"] / tp
+        assert rp["stats"]["point_steps"] == st["point_steps"]
+        extra["plain_per_region"] = {"point_steps_per_s": pv, "ms": tp * 1e3,
+                                     "batches": rp["stats"]["batches"],
+                                     "speedup_batched": value / pv, "steps_per_sync": 1}
+        log(f"plain per-region hand-off: {tp * 1e3:.0f} ms, speed-up {value / pv:.2f}x")
+    del hist
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_whole_volume(net)
+    return {
+        "value": value, "ms_per_step": elapsed * 1e3 / args.steps,
+        "config": {"workload": f"hand-off tiling: {args.m}^3 matter-era VV network (seed 1) in "
+                               f"a periodic spacetime tiling of 16 layers x "
+                               f"{4 * args.split_m ** 3} regions, run in dependency order, "
+                               f"crossings of each region's elements searched (pass through)",
+                   "regions": len(geoms), "points": n, "slices": slices,
+                   "point_steps_per_tiling": st["point_steps"], "screen": args.screen,
+                   "graph": True, "steps_per_sync": args.sync_steps,
+                   "path": "schedule_handoff: every ready region in one batch per wave, world "
+                           "sheet in HBM"},
+        "roofline": None, "cpu_baseline": cpu, **extra,
+    }
+
+
+def cpu_baseline_whole_volume(net, budget_s=20.0):
+    """The oracle's whole-volume run of the same network (crossing search on, every
+    crossing passing through), stepped for about budget_s seconds."""
+    import oracle as O
+    hc = {0: 0.0, 1: 2.0, 2: 1.0}[net["cosmology"]]
+    ro = O.OracleRegion(net["recs"], net["box"], net["cosmology"], hc)
+    t = time.perf_counter()
+    while time.perf_counter() - t < budget_s:
+        ro.evolve(1, p=0.0)
+    tc = time.perf_counter() - t
+    st = ro.stats()
+    ro.close()
+    log(f"cpu baseline: whole volume, {st['steps']} steps in {tc:.1f} s")
+    return {"value": st["point_steps"] / tc, "unit": "point-steps/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"the whole-volume run of the same network ({len(net['recs'])} points), "
+                      f"first {st['steps']} lattice steps ({st['point_steps']} point-steps in "
+                      f"{tc:.1f} s)"}
 
 
 def bench_batched(args):
-    if args.workload == "tiling":
-        (parts, box, dag), (train, tbox, dag_tr) = make_tiling_inputs(args)
-        per = 4 * args.split_m ** 3
-        desc = (f"learned scheduling: {args.m}^3 matter-era VV network (seed 1) cut at eta 8 "
-                f"into a periodic spacetime tiling of 16 layers x {per} regions "
-                f"({16 * per}), run in dependency order until every region's points stop; "
-                f"cost model trained on the seed-0 network in the same tiling")
-    else:
-        parts, box, train, tbox = make_inputs(args)   # before any GPU use (process pool)
-        dag, dag_tr = {}, {}
-        desc = ("512 independent matter-era regions (8x8x8 first layer, size 4), "
-                "lognormal points median 2e4 sigma 1.5 cap 2e5, 20% empty, "
-                "each run until all its points stop")
+    parts, box, train, tbox = make_inputs(args)   # before any GPU use (process pool)
+    dag, dag_tr = {}, {}
+    desc = ("512 independent matter-era regions (8x8x8 first layer, size 4), "
+            "lognormal points median 2e4 sigma 1.5 cap 2e5, 20% empty, "
+            "each run until all its points stop")
     import numpy as np
     import torch
     from paper_1011_4046_amd import inputs as I
@@ -595,7 +689,12 @@ def main():
     if args.roofline_only:
         print(json.dumps(roofline_only(args)), flush=True)
         return
-    res = bench_vv32(args) if args.workload == "vv32" else bench_batched(args)
+    if args.workload == "vv32":
+        res = bench_vv32(args)
+    elif args.workload == "tiling":
+        res = bench_handoff(args)
+    else:
+        res = bench_batched(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "point-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",

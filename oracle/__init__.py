@@ -319,24 +319,58 @@ def whole_volume_history(net, t_stop, p=0.0, seed=0, search=GRID):
         r.close()
 
 
+def vertex_homes(X, nxt, V, inv2g, K):
+    """Home region name (S << 32 | key) of every vertex of a whole-volume history.
+
+    A vertex's home is the region holding it, except where that region comes before the
+    home of a vertex its diamond was built from (the first-order expansion can leave an
+    edge slightly outside the light cone, so that a world line steps back across a face):
+    then it takes that later home. The vertices a diamond with top X[s, q] is built from
+    are X[s-1, q], X[s-1, next q] and X[s-2, next q]; the second initial slice X[1, q] is
+    taken as built from X[0, q] and X[0, next q]. "Later" is by layer S; two different
+    homes of the latest layer among those inputs cannot be ordered and raise ValueError.
+    With every edge inside or on the light cone (flat space) the homes are the regions."""
+    ns, n = X.shape[0], X.shape[1]
+    S, key = region_keys(V, inv2g, K, X.reshape(-1, 4))
+    own = ((S.astype(np.int64) << 32) | key.astype(np.int64)).reshape(ns, n)
+    home = own.copy()
+
+    def resolve(o, inputs):
+        m = inputs[0]
+        for x in inputs[1:]:
+            m = np.where((x >> 32) > (m >> 32), x, m)
+        later = (o >> 32) > (m >> 32)
+        for x in inputs:
+            if np.any(((x >> 32) == (m >> 32)) & (x != m) & ~later):
+                raise ValueError("inputs with two homes of one layer")
+        return np.where((o == m) | later, o, m)
+
+    if ns > 1:
+        home[1] = resolve(own[1], [home[0], home[0][nxt]])
+    for s in range(2, ns):
+        home[s] = resolve(own[s], [home[s - 1], home[s - 1][nxt], home[s - 2][nxt]])
+    return home, own
+
+
 def diamond_owners(X, nxt, V, inv2g, K, region_of):
     """Owner of every diamond of a whole-volume history in a periodic tiling (Section
     "Semi-parallel cosmic string simulation": a diamond is built by the region holding
-    its earliest point). The diamond whose top is X[s, q] (s >= 2) has bottom
+    its earliest point; vertex_homes gives the reading where a world line steps back
+    across a face). The diamond whose top is X[s, q] (s >= 2) has bottom
     X[s - 2, next q]; owner[s, q] is the index that region_of (a dict (S, key) ->
-    region) gives that bottom's region, -1 outside the tiling or for s < 2."""
+    region) gives that bottom's home, -1 outside the tiling or for s < 2. Also returns
+    the region index of every vertex's home."""
     ns, n = X.shape[0], X.shape[1]
-    S, key = region_keys(V, inv2g, K, X.reshape(-1, 4))
-    S = S.reshape(ns, n)
-    key = key.reshape(ns, n)
-    code = S.astype(np.int64) * (1 << 32) + key
+    home, _ = vertex_homes(X, nxt, V, inv2g, K)
     rk = np.array([s_ * (1 << 32) + k_ for (s_, k_) in region_of], dtype=np.int64)
     rv = np.array(list(region_of.values()), dtype=np.int64)
-    order = np.argsort(rk)
-    rk, rv = rk[order], rv[order]
-    pos = np.minimum(np.searchsorted(rk, code), max(len(rk) - 1, 0))
-    lut = np.where((len(rk) > 0) & (rk[pos] == code), rv[pos], -1) if len(rk) else \
-        np.full((ns, n), -1, np.int64)
+    if len(rk) == 0:
+        lut = np.full((ns, n), -1, np.int64)
+    else:
+        order = np.argsort(rk)
+        rk, rv = rk[order], rv[order]
+        pos = np.minimum(np.searchsorted(rk, home), len(rk) - 1)
+        lut = np.where(rk[pos] == home, rv[pos], -1)
     owner = np.full((ns, n), -1, np.int64)
     owner[2:] = lut[:-2][:, nxt]
     return owner, lut

@@ -176,8 +176,10 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
   slot_of.clear();
   // device tables
   int32_t *d_lut = nullptr, *d_gnext = nullptr, *d_gprev = nullptr, *d_gmap = nullptr;
-  int64_t* d_gid = nullptr;
+  int64_t *d_gid = nullptr, *d_home = nullptr;
   semipar_point_rec* d_rec = nullptr;
+  if (D.alloc(&d_home, (size_t)h->hist_slices * (size_t)n) != hipSuccess)
+    return fail_msg(SEMIPAR_E_OOM, "schedule_handoff: vertex homes");
   if (D.alloc(&d_lut, lut.size()) != hipSuccess || D.alloc(&d_gnext, n) != hipSuccess ||
       D.alloc(&d_gprev, n) != hipSuccess || D.alloc(&d_gmap, n) != hipSuccess ||
       D.alloc(&d_gid, n) != hipSuccess || D.alloc(&d_rec, n) != hipSuccess)
@@ -199,6 +201,7 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
   }
   spi::HandoffShared sh{};
   sh.H = h->hist;
+  sh.home = d_home;
   sh.n = n;
   sh.s0 = s0r - 1;
   sh.ns = (int32_t)h->hist_slices;

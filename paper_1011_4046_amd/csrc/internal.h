@@ -65,6 +65,7 @@ struct HandTok {
 // Device tables shared by every batch of a hand-off run (owned by its driver).
 struct HandoffShared {
   double* H;        // world sheet: [slice - s0][slot] (x, y, z, t), t = NaN: not built
+  int64_t* home;    // [slice - s0][slot]: name of each vertex's home region
   int64_t n;        // points of the volume
   int32_t s0, ns;   // first slice held, slices held
   double V[4];      // lattice origin (x, y, z, tau) shared by all regions

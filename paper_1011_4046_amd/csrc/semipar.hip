@@ -208,6 +208,7 @@ using spi::HandTok;
 // per-point tables (passed by value to the step kernel of such a batch).
 struct HistCfg {
   double4* H;             // [slice - s0][slot]; t = NaN: not built
+  int64_t* home;          // [slice - s0][slot]: name of the vertex's home (HOME_NONE: not built)
   int64_t n;              // points of the volume
   int32_t s0, ns;         // first slice held, slices held
   double V[4];            // lattice origin (x, y, z, tau)
@@ -230,7 +231,10 @@ constexpr int32_t HERR_START = 512;    // a start token whose diamond is not the
 constexpr int32_t HERR_SLICES = 1024;  // the world sheet holds too few slices
 constexpr int32_t HERR_SELF = 2048;    // a world line re-entered the region building it
 constexpr int32_t HERR_TOKENS = 4096;  // the token buffer overflowed
-constexpr int32_t HERR_MASK = HERR_INPUT | HERR_START | HERR_SLICES | HERR_SELF | HERR_TOKENS;
+constexpr int32_t HERR_TIE = 8192;     // a diamond's inputs have two homes of one layer
+constexpr int32_t HERR_MASK =
+    HERR_INPUT | HERR_START | HERR_SLICES | HERR_SELF | HERR_TOKENS | HERR_TIE;
+constexpr int64_t HOME_NONE = INT64_MIN;
 
 // Name (S << 32 | key) of the region holding P: generator coordinates in the same
 // arithmetic as exit_face, index i = floor(c), layer S = sum i, past vertex p g/2 with
@@ -260,6 +264,28 @@ __device__ __forceinline__ int32_t hist_region(const HistCfg& h, int64_t name) {
   const int key = (int)(uint32_t)(name & 0xffffffffll);
   if (S < h.S_lo || S > h.S_hi) return -1;
   return h.lut[(int64_t)(S - h.S_lo) * h.K * h.K * h.K + key];
+}
+
+// Home of a new vertex: the region holding it (name o), unless a vertex its diamond was
+// built from has a home of a later layer -- the first-order expansion can leave an edge
+// slightly outside the light cone, so that a world line steps back across a face --,
+// then that later home. Two different homes of the latest layer set *tie.
+__device__ __forceinline__ int64_t resolve_home(int64_t o, int64_t a, int64_t b, int64_t c,
+                                                bool* tie) {
+  int64_t m = a;
+  m = (b >> 32) > (m >> 32) ? b : m;
+  m = (c >> 32) > (m >> 32) ? c : m;
+  const bool later = (o >> 32) > (m >> 32);
+  if (!later) {
+    const int64_t Sm = m >> 32;
+    *tie = ((a >> 32) == Sm && a != m) || ((b >> 32) == Sm && b != m) ||
+           ((c >> 32) == Sm && c != m);
+  }
+  return (o == m || later) ? o : m;
+}
+
+__device__ __forceinline__ int64_t ldhome(const HistCfg& h, int s, int g) {
+  return h.home[(int64_t)(s - h.s0) * h.n + g];
 }
 
 __device__ __forceinline__ V4 ldh(const HistCfg& h, int s, int g) {
@@ -504,7 +530,7 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   else live_pt = live_pt && (!fstep || fstep[k] == FS_ACTIVE);
   V4 L, R, B;
   int64_t my_name = 0;
-  int g = 0;
+  int g = 0, gj = 0;
   if (live_pt) {
     bool adv = true;
     int j = nxt[k];
@@ -521,13 +547,13 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
         fstep[k] = s;
       } else {
         g = hs.gsl[k];
-        const int gj = hs.gnx[k];
+        gj = hs.gnx[k];
         my_name = hs.sname[rid[k]];
-        B = ldh(hs, s - 1, gj);
-        if (B.t == B.t && hist_name(hs, B) == my_name) {
+        if (ldhome(hs, s - 1, gj) == my_name) {
+          B = ldh(hs, s - 1, gj);
           L = ldh(hs, s, g);
           R = ldh(hs, s, gj);
-          if (!(L.t == L.t && R.t == R.t)) {
+          if (!(B.t == B.t && L.t == L.t && R.t == R.t)) {
             atomicOr(&ctrl->err, HERR_INPUT);
             fstep[k] = s;
           } else {
@@ -571,15 +597,21 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
       st(X, in, k, T);
       if constexpr (HIST) {
         st(X, ic, k, L);
+        // T's home, from the homes of L, R and B (B's is this region's)
+        const int64_t hl = ldhome(hs, s, g);
+        bool tie = false;
+        const int64_t tn = resolve_home(hist_name(hs, T), hl, ldhome(hs, s, gj), my_name, &tie);
+        if (tie) atomicOr(&ctrl->err, HERR_TIE);
         if (s + 1 - hs.s0 < hs.ns) {
-          hs.H[(int64_t)(s + 1 - hs.s0) * hs.n + g] = make_double4(T.x, T.y, T.z, T.t);
+          const int64_t at = (int64_t)(s + 1 - hs.s0) * hs.n + g;
+          hs.H[at] = make_double4(T.x, T.y, T.z, T.t);
+          hs.home[at] = tn;
         } else {
           atomicOr(&ctrl->err, HERR_SLICES);
         }
-        // the diamond of k's left neighbour with bottom T belongs to T's region; its
-        // start there is announced when T is the first vertex of k's world line in it
-        const int64_t tn = hist_name(hs, T);
-        if (tn != hist_name(hs, L)) {
+        // the diamond of k's left neighbour with bottom T belongs to T's home; its start
+        // there is announced when T is the first vertex of k's world line homed there
+        if (tn != hl) {
           if (tn == my_name) {
             atomicOr(&ctrl->err, HERR_SELF);
           } else {
@@ -613,11 +645,11 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
           jadv = j >= 0 && hs.start[j] <= s && fstep[j] >= s;
           if (jadv) {
             const int gjj = hs.gnx[j];
-            Bj = ldh(hs, s - 1, gjj);
-            jadv = Bj.t == Bj.t && hist_name(hs, Bj) == my_name;
+            jadv = ldhome(hs, s - 1, gjj) == my_name;
             if (jadv) {
+              Bj = ldh(hs, s - 1, gjj);
               Rj = ldh(hs, s, gjj);
-              jadv = Rj.t == Rj.t;
+              jadv = Bj.t == Bj.t && Rj.t == Rj.t;
             }
           }
         } else if constexpr (BND) {
@@ -3399,10 +3431,14 @@ __global__ __launch_bounds__(NT) void k_hand_unmap(int n, const int32_t* __restr
 }
 
 // ---- hand-off run set-up ------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_hist_fill(double4* __restrict__ H, uint64_t m) {
+__global__ __launch_bounds__(NT) void k_hist_fill(double4* __restrict__ H, int64_t* __restrict__ home,
+                                                  uint64_t m) {
   const uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * NT;
-  for (uint64_t q = i; q < m; q += stride) H[q] = make_double4(0.0, 0.0, 0.0, __builtin_nan(""));
+  for (uint64_t q = i; q < m; q += stride) {
+    H[q] = make_double4(0.0, 0.0, 0.0, __builtin_nan(""));
+    home[q] = HOME_NONE;
+  }
 }
 
 // The initial surface's two slices into the world sheet; start tokens of the first two
@@ -3410,7 +3446,8 @@ __global__ __launch_bounds__(NT) void k_hist_fill(double4* __restrict__ H, uint6
 // the two initial slices, so they belong to those vertices' regions.
 __global__ __launch_bounds__(NT) void k_hist_ic(const semipar_point_rec* __restrict__ rec, int n,
                                                 HistCfg hs, HandTok* __restrict__ tok,
-                                                unsigned long long* __restrict__ ntok) {
+                                                unsigned long long* __restrict__ ntok,
+                                                int32_t* __restrict__ err) {
   const int j = blockIdx.x * NT + threadIdx.x;
   if (j >= n) return;
   const semipar_point_rec r = rec[j];
@@ -3418,7 +3455,15 @@ __global__ __launch_bounds__(NT) void k_hist_ic(const semipar_point_rec* __restr
   const V4 b{r.x[0], r.x[1], r.x[2], r.x[3]};
   hs.H[j] = make_double4(a.x, a.y, a.z, a.t);
   hs.H[hs.n + j] = make_double4(b.x, b.y, b.z, b.t);
-  const int64_t na = hist_name(hs, a), nb = hist_name(hs, b);
+  // the second slice counts as built from the first slice's vertices of j and next j
+  const semipar_point_rec rn = rec[hs.gnext[j]];
+  const V4 an{rn.x_prev[0], rn.x_prev[1], rn.x_prev[2], rn.x_prev[3]};
+  const int64_t na = hist_name(hs, a);
+  bool tie = false;
+  const int64_t nb = resolve_home(hist_name(hs, b), na, hist_name(hs, an), na, &tie);
+  if (tie) atomicOr(err, HERR_TIE);
+  hs.home[j] = na;
+  hs.home[hs.n + j] = nb;
   const int32_t da = hist_region(hs, na);
   const int32_t db = nb != na ? hist_region(hs, nb) : -1;
   if (da >= 0) {
@@ -5044,12 +5089,13 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
     r->broken = true;
     char msg[256];
     snprintf(msg, sizeof(msg),
-             "hand-off batch: %s%s%s%s%s",
+             "hand-off batch: %s%s%s%s%s%s",
              (a.err & HERR_INPUT) ? "a diamond's input was never built; " : "",
              (a.err & HERR_START) ? "a start token for a diamond of another region; " : "",
              (a.err & HERR_SLICES) ? "the world sheet holds too few slices; " : "",
              (a.err & HERR_SELF) ? "a world line re-entered its region; " : "",
-             (a.err & HERR_TOKENS) ? "token buffer overflow; " : "");
+             (a.err & HERR_TOKENS) ? "token buffer overflow; " : "",
+             (a.err & HERR_TIE) ? "a diamond's inputs have two homes of one layer; " : "");
     spi::set_error(msg);
     return (a.err & HERR_SLICES) ? SEMIPAR_E_OVERFLOW : SEMIPAR_E_STATE;
   }
@@ -5406,6 +5452,7 @@ int handoff_batch(const HandoffShared& sh, const int32_t* slot, const int32_t* s
   c0.tol = sh.box * std::ldexp(1.0, -30);
   HistCfg& h = r->hcfg;
   h.H = (double4*)sh.H;
+  h.home = sh.home;
   h.n = sh.n;
   h.s0 = sh.s0;
   h.ns = sh.ns;
@@ -5472,6 +5519,7 @@ int handoff_ic(const HandoffShared& sh, const semipar_point_rec* drec, hipStream
   if (sh.n <= 0 || sh.ns < 2 || sh.n >= (int64_t)1 << 31) return SEMIPAR_E_ARG;
   HistCfg h{};
   h.H = (double4*)sh.H;
+  h.home = sh.home;
   h.n = sh.n;
   h.s0 = sh.s0;
   h.ns = sh.ns;
@@ -5486,24 +5534,35 @@ int handoff_ic(const HandoffShared& sh, const semipar_point_rec* drec, hipStream
   h.gprev = sh.gprev;
   HandTok* dt = nullptr;
   unsigned long long* dn = nullptr;
-  if (salloc(&dt, 2 * (size_t)sh.n, st) != hipSuccess || salloc(&dn, 1, st) != hipSuccess) {
+  int32_t* derr = nullptr;
+  if (salloc(&dt, 2 * (size_t)sh.n, st) != hipSuccess || salloc(&dn, 1, st) != hipSuccess ||
+      salloc(&derr, 1, st) != hipSuccess) {
     sfree(dt, st);
     sfree(dn, st);
+    sfree(derr, st);
     return oom(__LINE__);
   }
   int rc = SEMIPAR_OK;
   unsigned long long nt = 0;
+  int32_t herr = 0;
   const uint64_t cells = (uint64_t)sh.ns * (uint64_t)sh.n;
-  if (hipMemsetAsync(dn, 0, sizeof(unsigned long long), st) != hipSuccess) rc = SEMIPAR_E_HIP;
+  if (hipMemsetAsync(dn, 0, sizeof(unsigned long long), st) != hipSuccess ||
+      hipMemsetAsync(derr, 0, sizeof(int32_t), st) != hipSuccess)
+    rc = SEMIPAR_E_HIP;
   if (rc == SEMIPAR_OK) {
-    k_hist_fill<<<4096, NT, 0, st>>>((double4*)sh.H, cells);
-    k_hist_ic<<<blocks(sh.n), NT, 0, st>>>(drec, (int)sh.n, h, dt, dn);
+    k_hist_fill<<<4096, NT, 0, st>>>((double4*)sh.H, sh.home, cells);
+    k_hist_ic<<<blocks(sh.n), NT, 0, st>>>(drec, (int)sh.n, h, dt, dn, derr);
     if (hipError_t e_ = hipGetLastError(); e_ != hipSuccess) rc = hip_fail(e_, "launch", __LINE__);
   }
   if (rc == SEMIPAR_OK &&
       (hipMemcpyAsync(&nt, dn, sizeof(nt), hipMemcpyDeviceToHost, st) != hipSuccess ||
+       hipMemcpyAsync(&herr, derr, sizeof(herr), hipMemcpyDeviceToHost, st) != hipSuccess ||
        hipStreamSynchronize(st) != hipSuccess))
     rc = SEMIPAR_E_HIP;
+  if (rc == SEMIPAR_OK && herr != 0) {
+    spi::set_error("hand-off: initial surface vertices with two homes of one layer");
+    rc = SEMIPAR_E_STATE;
+  }
   if (rc == SEMIPAR_OK && nt > 0) {
     tok.resize((size_t)nt);
     if (hipMemcpyAsync(tok.data(), dt, sizeof(HandTok) * nt, hipMemcpyDeviceToHost, st) !=
@@ -5513,6 +5572,7 @@ int handoff_ic(const HandoffShared& sh, const semipar_point_rec* drec, hipStream
   }
   sfree(dt, st);
   sfree(dn, st);
+  sfree(derr, st);
   return rc;
 }
 

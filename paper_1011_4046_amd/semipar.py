@@ -541,7 +541,7 @@ def schedule_handoff(ic, box, cosmology, geoms, n_pred, succ, hist, batch_points
                      cost=None, events=True, stream=None, max_steps=0, screen=SCREEN_F64,
                      intercommute=True, cell_size=0.0, steps_per_sync=0, use_graph=False,
                      cand_per_point=0.0, events_per_point=0.0, timed_kernel=-1, seed=0,
-                     cell_factor=0.0):
+                     cell_factor=0.0, screen_split=0):
     """Run a periodic tiling region by region with hand-off (schedule_handoff).
 
     ic: the volume's initial surface (numpy records); geoms: per region (origin[4],
@@ -580,7 +580,7 @@ def schedule_handoff(ic, box, cosmology, geoms, n_pred, succ, hist, batch_points
     p.evolve = EvolveParams(int(max_steps), float("inf"), int(screen), int(bool(intercommute)),
                             float(cell_size), int(steps_per_sync), int(bool(use_graph)),
                             float(cand_per_point), float(events_per_point), int(timed_kernel),
-                            0, 0, 0, 0.0, int(seed), float(cell_factor))
+                            int(screen_split), 0, 0, 0.0, int(seed), float(cell_factor))
     ev_off = np.zeros(nr + 1, dtype=np.int64)
     ev_cap = max(n, 4096)
     ev = np.zeros(ev_cap, dtype=EVENT_DTYPE) if events else None

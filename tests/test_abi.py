@@ -53,6 +53,10 @@ int main(void) {
   Z(semipar_point_rec) Z(semipar_event) Z(semipar_surface) Z(semipar_region_geom)
   Z(semipar_region_desc) Z(semipar_evolve_params) Z(semipar_evolve_stats)
   Z(semipar_tiling) Z(semipar_sched_params) Z(semipar_sched_stats) Z(semipar_loop)
+  Z(semipar_handoff)
+  F(semipar_handoff, geoms) F(semipar_handoff, ic) F(semipar_handoff, n_points)
+  F(semipar_handoff, ic_mem) F(semipar_handoff, hist) F(semipar_handoff, hist_slices)
+  F(semipar_handoff, stream)
   F(semipar_region_desc, stream) F(semipar_region_desc, inv2g) F(semipar_region_desc, sub)
   F(semipar_evolve_params, screen_split) F(semipar_evolve_params, loop_every)
   F(semipar_evolve_stats, timed_kernel_launches) F(semipar_evolve_stats, loop_points)
@@ -97,12 +101,14 @@ def test_record_layouts_match_header(tmp_path):
     pairs = {"semipar_surface": S.Surface, "semipar_region_geom": S.RegionGeom,
              "semipar_region_desc": S.RegionDesc, "semipar_evolve_params": S.EvolveParams,
              "semipar_evolve_stats": S.EvolveStats, "semipar_tiling": S.Tiling,
-             "semipar_sched_params": S.SchedParams, "semipar_sched_stats": S.SchedStats}
+             "semipar_sched_params": S.SchedParams, "semipar_sched_stats": S.SchedStats,
+             "semipar_handoff": S.Handoff}
     for cname, py in pairs.items():
         assert c[cname] == ctypes.sizeof(py), cname
     fields = {"semipar_region_desc": S.RegionDesc, "semipar_evolve_params": S.EvolveParams,
               "semipar_evolve_stats": S.EvolveStats, "semipar_tiling": S.Tiling,
-              "semipar_sched_params": S.SchedParams, "semipar_sched_stats": S.SchedStats}
+              "semipar_sched_params": S.SchedParams, "semipar_sched_stats": S.SchedStats,
+              "semipar_handoff": S.Handoff}
     for key, off in c.items():
         if "." in key:
             cname, f = key.split(".")
@@ -174,6 +180,27 @@ def test_argument_errors_without_gpu():
     n = (ctypes.c_int64 * 4)()
     assert L.region_emit_final_surfaces(None, None, None, n, 0) == -1
     L.region_destroy(None)
+    # the hand-off run checks its tiling before touching the device
+    import numpy as np
+    from paper_1011_4046_amd import inputs as I
+    p = S.SchedParams()
+    assert L.schedule_handoff(None, ctypes.byref(p), None) == -1
+    geom, _ = I.region_geometry(4.0, 8.0)
+    g = (S.RegionGeom * 2)(S._geom_struct(geom), S._geom_struct(geom))
+    npred = np.zeros(2, np.int32)
+    off = np.zeros(3, np.int32)
+    rec = np.zeros(4, I.REC_DTYPE)
+    fake = np.zeros(8)
+    h = S.Handoff()
+    h.n_regions, h.cosmology, h.box = 2, I.MATTER, 16.0 * np.sqrt(2.0) / 4.0 * 1.01
+    h.geoms, h.n_pred, h.succ_off = ctypes.addressof(g), npred.ctypes.data, off.ctypes.data
+    h.ic, h.n_points, h.ic_mem = rec.ctypes.data, 4, S.MEM_HOST
+    h.hist, h.hist_slices = fake.ctypes.data, 2
+    assert L.schedule_handoff(ctypes.byref(h), ctypes.byref(p), None) == -1  # box
+    h.box = 4.0 / (2.0 * geom[4])
+    assert L.schedule_handoff(ctypes.byref(h), ctypes.byref(p), None) == -1  # one name twice
+    h.hist_slices = 1
+    assert L.schedule_handoff(ctypes.byref(h), ctypes.byref(p), None) == -1
     assert S.strerror(-2).startswith("inconsistent surface")
     assert "gfx950" in S.version()
 

@@ -151,3 +151,24 @@ def test_owner_holds_the_earliest_of_the_diamonds_four_vertices(tiling):
         tt = np.stack([X[s, q, 3], X[s - 1, q, 3], X[s - 1, j, 3], X[s - 2, j, 3]])
         first = cand[np.argmin(tt, axis=0), q]
         assert np.array_equal(own[s], first)
+
+
+def test_homes_never_run_backwards_and_are_the_regions_in_flat_space():
+    """Homes follow the layer order along every dependency of a diamond; in flat space
+    every edge is null, no world line steps back across a face, and every home is the
+    region holding the vertex."""
+    for cosmology in (I.FLAT, I.MATTER):
+        net = I.vv_network(m=8, seed=2, cosmology=cosmology)
+        parts, box, n_pred, succ, layer = I.tiling_regions(net, M=2, layers=8)
+        V, inv2g = parts[0][1][:4], parts[0][1][4]
+        K = int(round(4 * box * inv2g))
+        g = 0.5 / inv2g
+        t_last = (V[3] + 0.5 * g * 7 + 2 * g) / np.sqrt(3.0)
+        X, ids, nxt, _ = O.whole_volume_history(net, t_last, p=0.0)
+        home, own = O.vertex_homes(X, nxt, V, inv2g, K)
+        if cosmology == I.FLAT:
+            assert np.array_equal(home, own)
+        S = home >> 32
+        for s in range(2, X.shape[0]):
+            for src in (home[s - 1], home[s - 1][nxt], home[s - 2][nxt]):
+                assert np.all((home[s] == src) | (S[s] > (src >> 32)))
