@@ -220,9 +220,10 @@ def bench_handoff(args):
                                f"crossings of each region's elements searched (pass through)",
                    "regions": len(geoms), "points": n, "slices": slices,
                    "point_steps_per_tiling": st["point_steps"], "screen": args.screen,
-                   "graph": True, "steps_per_sync": args.sync_steps,
-                   "path": "schedule_handoff: every ready region in one batch per wave, world "
-                           "sheet in HBM"},
+                   "graph": True, "steps_per_sync": args.sync_steps, "lanes": 1,
+                   "screen_split": args.split,
+                   "path": "schedule_handoff: each layer's regions in one batch, layer after "
+                           "layer, world sheet in HBM"},
         "roofline": None, "cpu_baseline": cpu, **extra,
     }
 

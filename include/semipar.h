@@ -520,8 +520,10 @@ int schedule_regions(const semipar_tiling* t, const semipar_sched_params* p,
  *              vertex p = idx0 (1,1,1) + idx1 (1,-1,-1) + idx2 (-1,1,-1) + idx3 (-1,-1,1)
  *              taken mod K (the names repeat with the box); two regions may not share a
  *              name, and vertices whose region has no entry are outside the run.
- *   n_pred, succ_off, succ  dependency lists as in semipar_tiling (required): every
- *              region that can pass anything to r must come before it
+ *   n_pred, succ_off, succ  dependency lists as in semipar_tiling (required; each
+ *              successor must lie in a later layer). Regions run layer by layer: a
+ *              region reads and is told only what earlier layers or it itself built, and
+ *              the regions of one layer never exchange anything
  *   ic, n_points, ic_mem  the initial surface of the whole volume (host or device):
  *              records on one slice s0 >= 1 (x on s0, x_prev on s0 - 1), ids distinct,
  *              every next_id and prev_id among the records and paired
@@ -557,12 +559,16 @@ typedef struct semipar_handoff {
  * (kind 1; links never change), so every vertex equals that of one whole-volume run
  * with intercommutation probability 0; crossings between elements of different regions
  * are not searched.
- *   p  used: batch_points (0: every ready region in one batch), cost (ordering only),
- *      evolve (screen, intercommute, use_graph, steps_per_sync, cell_size, cell_factor,
- *      cand_per_point, events_per_point, seed; max_steps caps the steps of each batch;
- *      loop_every must be 0; p is ignored), events / events_cap / events_off,
- *      region_steps, region_point_steps, region_batch, region_ms. out must be NULL (the
- *      world sheet is the output); policy, pack, lanes and the lane_* fields are ignored.
+ *   p  used: lanes (0 or 1; more is refused with SEMIPAR_E_ARG), batch_points (at most
+ *      this many points per batch; 0: a layer's regions in one batch), cost (ordering
+ *      only: longest
+ *      predicted first, else most start tokens first), evolve (screen, intercommute,
+ *      use_graph, steps_per_sync, screen_split, cell_size, cell_factor, cand_per_point,
+ *      events_per_point, seed; max_steps caps the steps of each batch; loop_every must be
+ *      0; p is ignored), events / events_cap / events_off, region_steps,
+ *      region_point_steps, region_batch, region_ms. out must be NULL (the world sheet is
+ *      the output); policy, pack and the lane_* fields are ignored. Results never depend
+ *      on batch_points or cost.
  *   st regions, empty_regions, batches, point_steps, steps, events, passed, makespan_ms,
  *      evolve_ms.
  * Errors: SEMIPAR_E_ARG, SEMIPAR_E_SURFACE (initial surface), SEMIPAR_E_OOM,

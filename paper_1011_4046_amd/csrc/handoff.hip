@@ -15,8 +15,8 @@
 // does pass on is where its successors' work begins: when a vertex it builds is the first
 // vertex of a world line in another region, that region's diamond of the line's left
 // neighbour starts there (a start token). The manager here keeps the tokens per region
-// and runs the ready regions wave by wave as launch batches (one set of step kernels
-// over the points of many regions).
+// and runs the regions layer by layer as launch batches (one set of step kernels over the
+// points of many regions).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,7 +24,12 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <numeric>
+#include <mutex>
+#include <string>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -180,8 +185,15 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
   semipar_point_rec* d_rec = nullptr;
   if (D.alloc(&d_home, (size_t)h->hist_slices * (size_t)n) != hipSuccess)
     return fail_msg(SEMIPAR_E_OOM, "schedule_handoff: vertex homes");
+  // One lane. Batches of one layer on concurrent lanes (host threads with streams of their
+  // own) are switched off: a run with three lanes ended the process, and the cause is not
+  // shown (region_destroy's device-wide hipFree on one lane while another lane captures
+  // a graph is the suspect; the batched scheduler releases its batches only at its end).
+  if (p->lanes > 1)
+    return fail_msg(SEMIPAR_E_ARG, "schedule_handoff: one lane only (lanes > 1 is switched off)");
+  const int lanes = 1;
   if (D.alloc(&d_lut, lut.size()) != hipSuccess || D.alloc(&d_gnext, n) != hipSuccess ||
-      D.alloc(&d_gprev, n) != hipSuccess || D.alloc(&d_gmap, n) != hipSuccess ||
+      D.alloc(&d_gprev, n) != hipSuccess || D.alloc(&d_gmap, (size_t)lanes * n) != hipSuccess ||
       D.alloc(&d_gid, n) != hipSuccess || D.alloc(&d_rec, n) != hipSuccess)
     return fail_msg(SEMIPAR_E_OOM, "schedule_handoff: device tables");
   {
@@ -193,7 +205,8 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
       e = hipMemcpyAsync(d_gprev, gprev.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(d_gid, gid.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(d_gmap, 0xff, sizeof(int32_t) * n, stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(d_gmap, 0xff, sizeof(int32_t) * (size_t)lanes * n, stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(d_rec, hrec, sizeof(semipar_point_rec) * n, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -244,13 +257,8 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
   std::vector<int32_t> r_steps((size_t)nr, 0), r_batch((size_t)nr, -1);
   std::vector<int64_t> r_psteps((size_t)nr, 0);
   std::vector<double> r_ms((size_t)nr, 0.0);
-  std::vector<int32_t> pending((size_t)nr);
-  std::vector<int32_t> ready;
-  for (int r = 0; r < nr; ++r) {
-    pending[r] = h->n_pred[r];
-    if (pending[r] == 0) ready.push_back(r);
-  }
-  std::vector<char> in_batch((size_t)n, 0);
+  std::vector<int32_t> ready;  // regions of the open layer with work, not yet taken
+  std::vector<char> taken((size_t)nr, 0);
   int64_t batches = 0, steps_sum = 0, psum = 0, nev = 0, npass = 0, empty = 0, done = 0;
   double evolve_ms = 0.0, tk_ms = 0.0;
   int64_t tk_n = 0;
@@ -259,41 +267,104 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
   ep.t_end = INFINITY;
   ep.loop_every = 0;
   ep.persistent = 0;
-  while (!ready.empty()) {
-    std::vector<int32_t> run, next;
-    auto release = [&](int32_t r) {
-      for (int32_t i = h->succ_off[r]; i < h->succ_off[r + 1]; ++i)
-        if (--pending[h->succ[i]] == 0) next.push_back(h->succ[i]);
-    };
-    for (int32_t r : ready) {
-      if (work[r].empty()) {
-        finished[r] = 1;
-        empty++;
-        done++;
-        release(r);
-      } else {
-        run.push_back(r);
+  // the manager's state, shared by the lanes under mu
+  std::mutex mu;
+  std::condition_variable cv;
+  int running = 0, lane_rc = SEMIPAR_OK;
+  std::string lane_msg;
+  // Regions run layer by layer. A vertex's home lies in a later layer than the homes of
+  // the vertices it was built from, or in their own region, so everything a region reads
+  // or is told was made by an earlier layer or by itself, and the regions of one layer
+  // never exchange anything: they run in any order, side by side.
+  std::vector<int32_t> layer_of((size_t)nr);
+  for (int r = 0; r < nr; ++r) layer_of[r] = (int32_t)(name[r] >> 32);
+  for (int r = 0; r < nr; ++r)
+    for (int32_t i = h->succ_off[r]; i < h->succ_off[r + 1]; ++i)
+      if (layer_of[h->succ[i]] <= layer_of[r])
+        return fail_msg(SEMIPAR_E_ARG,
+                        "schedule_handoff: a successor in the same or an earlier layer");
+  std::vector<int32_t> by_layer((size_t)nr);
+  std::iota(by_layer.begin(), by_layer.end(), 0);
+  std::stable_sort(by_layer.begin(), by_layer.end(),
+                   [&](int32_t a, int32_t b) { return layer_of[a] < layer_of[b]; });
+  size_t next_layer_at = 0;      // first region of the next layer in by_layer
+  int32_t cur_layer = INT32_MIN;
+  // open the next layer that has work (regions without work are done at once)
+  auto open_layer = [&]() -> bool {
+    while (next_layer_at < by_layer.size()) {
+      cur_layer = layer_of[by_layer[next_layer_at]];
+      while (next_layer_at < by_layer.size() && layer_of[by_layer[next_layer_at]] == cur_layer) {
+        const int32_t r = by_layer[next_layer_at++];
+        if (work[r].empty()) {
+          finished[r] = 1;
+          empty++;
+          done++;
+        } else {
+          ready.push_back(r);
+        }
       }
+      if (!ready.empty()) return true;
     }
-    // longest predicted first (else most start tokens first), cut into batches
-    std::stable_sort(run.begin(), run.end(), [&](int32_t a, int32_t b) {
+    return false;
+  };
+  // route a batch's tokens (under mu): only later layers can receive work
+  auto route_locked = [&](const std::vector<spi::HandTok>& v) -> int {
+    for (const spi::HandTok& t : v) {
+      if (t.region < 0 || t.region >= nr || t.slot < 0 || t.slot >= n)
+        return fail_msg(SEMIPAR_E_STATE, "schedule_handoff: a start token out of range");
+      if (layer_of[t.region] <= cur_layer || finished[t.region] || taken[t.region])
+        return fail_msg(SEMIPAR_E_STATE,
+                        "schedule_handoff: a region received work after its layer had started");
+      work[t.region].emplace_back(t.slot, t.step);
+    }
+    return SEMIPAR_OK;
+  };
+  open_layer();
+  // one lane: take ready regions, longest predicted first (else most start tokens first),
+  // up to batch_points points (0: all ready ones, shared out over the idle lanes)
+  auto take = [&](int idle) {
+    std::stable_sort(ready.begin(), ready.end(), [&](int32_t a, int32_t b) {
       if (p->cost) return p->cost[a] > p->cost[b];
       return work[a].size() > work[b].size();
     });
-    size_t i0 = 0;
-    while (i0 < run.size()) {
-      size_t i1 = i0;
-      int64_t pts = 0;
-      while (i1 < run.size() &&
-             (i1 == i0 || p->batch_points == 0 || pts + (int64_t)work[run[i1]].size() <= p->batch_points))
-        pts += (int64_t)work[run[i1++]].size();
-      std::vector<int32_t> regs(run.begin() + i0, run.begin() + i1);
-      i0 = i1;
+    int64_t all = 0;
+    for (int32_t r : ready) all += (int64_t)work[r].size();
+    const int64_t cap = p->batch_points > 0 ? p->batch_points
+                                            : std::max<int64_t>(1, (all + idle - 1) / idle);
+    std::vector<int32_t> regs;
+    int64_t pts = 0;
+    size_t i = 0;
+    while (i < ready.size() && (regs.empty() || pts + (int64_t)work[ready[i]].size() <= cap)) {
+      pts += (int64_t)work[ready[i]].size();
+      regs.push_back(ready[i++]);
+    }
+    ready.erase(ready.begin(), ready.begin() + (ptrdiff_t)i);
+    for (int32_t r : regs) taken[r] = 1;
+    return regs;
+  };
+  auto lane_body = [&](int lane, hipStream_t ls) {
+    std::vector<char> in_batch((size_t)n, 0);  // a point works in one region of a batch
+    for (;;) {
+      std::vector<int32_t> regs;
+      int64_t my_batch = 0;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return lane_rc != SEMIPAR_OK || !ready.empty() || running == 0; });
+        if (lane_rc == SEMIPAR_OK && ready.empty() && running == 0) open_layer();
+        if (lane_rc != SEMIPAR_OK || ready.empty()) {
+          cv.notify_all();
+          return;
+        }
+        regs = take(std::max(1, lanes - running));
+        my_batch = batches++;
+        running++;
+      }
+      // the batch: its regions' start tokens, sorted by volume slot (a region's tokens are
+      // complete once it is ready: all their producers have run)
       std::vector<int32_t> slot, start;
       std::vector<int64_t> sub_off(1, 0), names;
       std::vector<semipar_region_geom> geoms;
-      slot.reserve((size_t)pts);
-      start.reserve((size_t)pts);
+      int rc = SEMIPAR_OK;
       for (int32_t r : regs) {
         auto& w = work[r];
         std::sort(w.begin(), w.end());
@@ -301,13 +372,12 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
         for (const auto& e : w) {
           if (e.first == last) {
             if (e.second != start.back())
-              return fail_msg(SEMIPAR_E_STATE,
-                              "schedule_handoff: a point starts twice in one region");
+              rc = fail_msg(SEMIPAR_E_STATE, "schedule_handoff: a point starts twice in one region");
             continue;
           }
           if (in_batch[e.first])
-            return fail_msg(SEMIPAR_E_STATE,
-                            "schedule_handoff: a point works in two regions of one batch");
+            rc = fail_msg(SEMIPAR_E_STATE,
+                          "schedule_handoff: a point works in two regions of one batch");
           in_batch[e.first] = 1;
           last = e.first;
           slot.push_back(e.first);
@@ -319,27 +389,32 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
       }
       for (int32_t q : slot) in_batch[q] = 0;
       semipar_region* R = nullptr;
-      int rc = spi::handoff_batch(sh, slot.data(), start.data(), sub_off, geoms.data(),
-                                  names.data(), stream, &R);
-      if (rc != SEMIPAR_OK) return rc;
       semipar_evolve_stats es{};
-      rc = region_evolve(R, &ep, &es);
       std::vector<semipar_event> evs;
-      std::vector<int64_t> eoff;
+      std::vector<int64_t> eoff, bps;
       std::vector<int32_t> bsteps;
-      std::vector<int64_t> bps;
+      std::vector<spi::HandTok> btk;
+      if (rc == SEMIPAR_OK)
+        rc = spi::handoff_batch(sh, lane, slot.data(), start.data(), sub_off, geoms.data(),
+                                names.data(), ls, &R);
+      if (rc == SEMIPAR_OK) rc = region_evolve(R, &ep, &es);
       if (rc == SEMIPAR_OK && es.steps >= ep.max_steps)
         rc = fail_msg(SEMIPAR_E_STATE, "schedule_handoff: a batch reached max_steps");
       if (rc == SEMIPAR_OK) rc = spi::batch_events(R, evs, eoff);
       if (rc == SEMIPAR_OK) rc = spi::batch_stats(R, bsteps, bps);
-      // its regions are done before their tokens go out: a token for one of them (or any
-      // earlier region) breaks the causal order
-      for (int32_t r : regs) finished[r] = 1;
-      if (rc == SEMIPAR_OK) rc = spi::handoff_tokens(R, tk);
+      if (rc == SEMIPAR_OK) rc = spi::handoff_tokens(R, btk);
       region_destroy(R);
-      if (rc != SEMIPAR_OK) return rc;
-      rc = route(tk);
-      if (rc != SEMIPAR_OK) return rc;
+      std::unique_lock<std::mutex> lk(mu);
+      running--;
+      if (rc == SEMIPAR_OK) rc = route_locked(btk);
+      if (rc != SEMIPAR_OK) {
+        if (lane_rc == SEMIPAR_OK) {
+          lane_rc = rc;
+          lane_msg = semipar_last_error();
+        }
+        cv.notify_all();
+        return;
+      }
       for (size_t q = 0; q < regs.size(); ++q) {
         const int32_t r = regs[q];
         ev_r[r].assign(evs.begin() + eoff[q], evs.begin() + eoff[q + 1]);
@@ -347,22 +422,25 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
         nev += (int64_t)ev_r[r].size();
         r_steps[r] = bsteps[q];
         r_psteps[r] = bps[q];
-        r_batch[r] = (int32_t)batches;
+        r_batch[r] = (int32_t)my_batch;
         r_ms[r] = es.elapsed_ms;
         psum += bps[q];
         work[r].clear();
         work[r].shrink_to_fit();
+        finished[r] = 1;
         done++;
-        release(r);
       }
       steps_sum += es.steps;
       evolve_ms += es.elapsed_ms;
       tk_ms += es.timed_kernel_ms;
       tk_n += es.timed_kernel_launches;
-      batches++;
+      cv.notify_all();
     }
-    std::sort(next.begin(), next.end());
-    ready.swap(next);
+  };
+  lane_body(0, stream);
+  if (lane_rc != SEMIPAR_OK) {
+    spi::set_error(lane_msg.c_str());  // the lane's message, on the caller's thread
+    return lane_rc;
   }
   if (done != nr)
     return fail_msg(SEMIPAR_E_ARG, "schedule_handoff: the dependency lists leave regions never ready");

@@ -75,7 +75,8 @@ struct HandoffShared {
   const int32_t* gnext;   // per volume slot: right neighbour's slot
   const int32_t* gprev;   // per volume slot: left neighbour's slot
   const int64_t* gid;     // per volume slot: point id
-  int32_t* gmap;          // per volume slot: -1 between batches (the batch build's scratch)
+  int32_t* gmap;          // per lane and volume slot, lanes x n: -1 between batches (the
+                          // batch build's scratch; batches on different lanes overlap)
   int32_t cosmology;
   double box;
 };
@@ -84,9 +85,11 @@ struct HandoffShared {
 // sub_off[q+1]) (host, volume slots, ascending within a sub-region) with their start
 // steps; geoms and names (host, n_sub each) are the sub-regions' geometry and names.
 // The region evolves with region_evolve; crossings are logged and pass through.
-SP_HIDDEN int handoff_batch(const HandoffShared& sh, const int32_t* slot, const int32_t* start,
-                            const std::vector<int64_t>& sub_off, const semipar_region_geom* geoms,
-                            const int64_t* names, hipStream_t stream, semipar_region** out);
+// lane selects the batch build's scratch row of sh.gmap.
+SP_HIDDEN int handoff_batch(const HandoffShared& sh, int lane, const int32_t* slot,
+                            const int32_t* start, const std::vector<int64_t>& sub_off,
+                            const semipar_region_geom* geoms, const int64_t* names,
+                            hipStream_t stream, semipar_region** out);
 
 // Fill the world sheet with t = NaN, write the initial surface's two slices (drec: n
 // records in device memory, volume slot order) and return the start tokens they give

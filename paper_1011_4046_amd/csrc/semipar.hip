@@ -3402,8 +3402,9 @@ __global__ __launch_bounds__(NT) void k_hand_links(int n, const int32_t* __restr
     const int g = gsl[k];
     int a = gmap[gnx[k]];
     int b = gmap[gprev[g]];
-    if (a >= 0 && rid[a] != rid[k]) a = -1;
-    if (b >= 0 && rid[b] != rid[k]) b = -1;
+    if (a >= n || b >= n) atomicOr(&ctrl->err, HERR_INPUT);  // (a stale scratch entry)
+    if (a >= 0 && (a >= n || rid[a] != rid[k])) a = -1;
+    if (b >= 0 && (b >= n || rid[b] != rid[k])) b = -1;
     nxt[k] = a;
     prv[k] = b;
     const int s = start[k];
@@ -5372,10 +5373,12 @@ int batch_emit(semipar_region* r, semipar_point_rec* out, std::vector<int64_t>& 
   return rc;
 }
 
-int handoff_batch(const HandoffShared& sh, const int32_t* slot, const int32_t* start,
+int handoff_batch(const HandoffShared& sh, int lane, const int32_t* slot, const int32_t* start,
                   const std::vector<int64_t>& sub_off, const semipar_region_geom* geoms,
                   const int64_t* names, hipStream_t stream, semipar_region** out) {
   *out = nullptr;
+  if (lane < 0) return SEMIPAR_E_ARG;
+  int32_t* gmap = sh.gmap + (size_t)lane * (size_t)sh.n;
   const int ns = (int)sub_off.size() - 1;
   if (ns <= 0 || !sh.H || !sh.gmap) return SEMIPAR_E_ARG;
   const int64_t total = sub_off[ns];
@@ -5495,10 +5498,10 @@ int handoff_batch(const HandoffShared& sh, const int32_t* slot, const int32_t* s
   if (rc == SEMIPAR_OK) {
     k_fill_rid<<<blocks(total), NT, 0, st>>>(r->rid, n, doff, ns);
     k_hand_init<<<blocks(total), NT, 0, st>>>(n, r->hgsl, r->hstart, sh.gnext, sh.gid, r->hgnx,
-                                             r->id, r->fstep, r->face, r->lev, sh.gmap);
-    k_hand_links<<<blocks(total), NT, 0, st>>>(n, r->hgsl, r->hgnx, r->hstart, sh.gprev, sh.gmap,
+                                             r->id, r->fstep, r->face, r->lev, gmap);
+    k_hand_links<<<blocks(total), NT, 0, st>>>(n, r->hgsl, r->hgnx, r->hstart, sh.gprev, gmap,
                                               r->rid, r->nxt, r->prv, r->hcfg, r->P, r->ctrl);
-    k_hand_unmap<<<blocks(total), NT, 0, st>>>(n, r->hgsl, sh.gmap);
+    k_hand_unmap<<<blocks(total), NT, 0, st>>>(n, r->hgsl, gmap);
     if (hipError_t e_ = hipGetLastError(); e_ != hipSuccess) rc = hip_fail(e_, "launch", __LINE__);
   }
   // the host arrays are read before the call returns

@@ -541,7 +541,7 @@ def schedule_handoff(ic, box, cosmology, geoms, n_pred, succ, hist, batch_points
                      cost=None, events=True, stream=None, max_steps=0, screen=SCREEN_F64,
                      intercommute=True, cell_size=0.0, steps_per_sync=0, use_graph=False,
                      cand_per_point=0.0, events_per_point=0.0, timed_kernel=-1, seed=0,
-                     cell_factor=0.0, screen_split=0):
+                     cell_factor=0.0, screen_split=0, lanes=1):
     """Run a periodic tiling region by region with hand-off (schedule_handoff).
 
     ic: the volume's initial surface (numpy records); geoms: per region (origin[4],
@@ -572,6 +572,7 @@ def schedule_handoff(ic, box, cosmology, geoms, n_pred, succ, hist, batch_points
     h.stream = stream if stream is not None else _current_stream()
     p = SchedParams()
     p.batch_points = int(batch_points)
+    p.lanes = int(lanes)
     cost_arr = None
     if cost is not None:
         cost_arr = np.ascontiguousarray(cost, dtype=np.float32)

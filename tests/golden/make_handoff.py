@@ -1,0 +1,120 @@
+"""Write handoff.json: digests of the world sheet and crossings that a hand-off run of the
+tiling workload must reproduce, from the oracle's whole-volume run alone.
+
+Calls only the oracle and the seeded input generators (no GPU code). The GPU test in
+tests/test_gpu_handoff_full.py runs schedule_handoff on the same tiling in the benchmark's
+launch shape and compares.
+
+Workload: the 32^3 matter-era VV network (seed 1, 8 points per correlation length, at
+rest at eta = 8) in the periodic spacetime tiling of 16 layers x 256 regions (M = 4),
+crossings passing through (intercommutation probability 0).
+
+Digests (SHA-256), with s the history index of a slice (0 and 1: the initial surface)
+and q a record slot of the initial surface:
+  built_sha256     the ascending flat indices s * n + q (int64) of every vertex the run
+                   holds: the initial surface and the top of every diamond whose bottom's
+                   home is a region of the tiling (oracle.diamond_owners);
+  vertices_sha256  those vertices (x, y, z, t as float64), in the same order;
+  point_steps_sha256  diamonds built per region (int64, region order);
+  events_sha256    per region in region order, the oracle's crossings whose two elements
+                   belong to that region (both diamonds of each element built there),
+                   each region's sorted by (step, t*, id_a, id_b).
+
+Run from the repository root: python tests/golden/make_handoff.py
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+from paper_1011_4046_amd import inputs as I  # noqa: E402
+
+OUT = os.path.join(HERE, "handoff.json")
+M, LAYERS, SEED, MSIZE = 4, 16, 1, 32
+GEN = np.array([[1, 1, 1, 1], [1, -1, -1, 1], [-1, 1, -1, 1], [-1, -1, 1, 1]], dtype=np.float64)
+
+
+def sha(b):
+    return hashlib.sha256(b).hexdigest()
+
+
+def tiling():
+    net = I.vv_network(m=MSIZE, seed=SEED)
+    parts, box, n_pred, succ, layer = I.tiling_regions(net, M=M, layers=LAYERS)
+    geoms = [g for _, g in parts]
+    return net, box, geoms, n_pred, succ, np.asarray(layer)
+
+
+def region_of(geoms, box):
+    """Region index by name (S, key), from an interior point of each region."""
+    V, inv2g = geoms[0][:4], geoms[0][4]
+    K = int(round(4 * box * inv2g))
+    g = 0.5 / inv2g
+    cen = []
+    for gm in geoms:
+        P = gm[:4] + (0.5 * g) * ((gm[5:9] + 0.5) @ GEN)
+        cen.append([P[0], P[1], P[2], P[3] / np.sqrt(3.0)])
+    S, key = O.region_keys(V, inv2g, K, np.array(cen))
+    return {(int(a), int(b)): r for r, (a, b) in enumerate(zip(S, key))}, V, inv2g, K
+
+
+def main():
+    t = time.time()
+    net, box, geoms, n_pred, succ, layer = tiling()
+    reg, V, inv2g, K = region_of(geoms, box)
+    g = 0.5 / inv2g
+    t_last = (V[3] + 0.5 * g * (LAYERS - 1) + 2 * g) / np.sqrt(3.0)
+    X, ids, nxt, ev = O.whole_volume_history(net, t_last + 2 * net["delta"], p=0.0)
+    ns, n = X.shape[0], X.shape[1]
+    print(f"whole volume: {n} points, {ns} slices, {len(ev)} crossings "
+          f"({time.time() - t:.0f} s)", flush=True)
+    own, _ = O.diamond_owners(X, nxt, V, inv2g, K, reg)
+    want = own >= 0
+    want[:2] = True
+    flat = np.flatnonzero(want.ravel()).astype(np.int64)
+    out = {"description": __doc__.strip().splitlines()[0],
+           "config": f"VV {MSIZE}^3 seed {SEED} matter era, tiling M={M} x {LAYERS} layers, p=0",
+           "points": int(n), "regions": len(geoms), "whole_volume_slices": int(ns),
+           "built": int(len(flat)), "built_sha256": sha(flat.tobytes())}
+    out["vertices_sha256"] = sha(np.ascontiguousarray(X.reshape(-1, 4)[flat]).tobytes())
+    del flat
+    ps = np.bincount(own[own >= 0], minlength=len(geoms)).astype(np.int64)
+    out["point_steps"] = int(ps.sum())
+    out["point_steps_per_layer"] = [int(ps[layer == S].sum()) for S in range(LAYERS)]
+    out["point_steps_sha256"] = sha(ps.tobytes())
+    # crossings whose two elements belong to one region
+    s0 = int(net["recs"]["step"][0])
+    slot = {int(v): q for q, v in enumerate(ids)}
+    per = [[] for _ in geoms]
+    for e in ev:
+        i = int(e["step"]) + 2 - s0
+        a, b = slot[int(e["id_a"])], slot[int(e["id_b"])]
+        ra = own[i, a] if own[i, a] == own[i, nxt[a]] else -1
+        rb = own[i, b] if own[i, b] == own[i, nxt[b]] else -1
+        if ra >= 0 and ra == rb:
+            per[int(ra)].append(e)
+    chunks = []
+    for r in range(len(geoms)):
+        if per[r]:
+            w = np.array(per[r], dtype=ev.dtype)
+            w = w[np.lexsort((w["id_b"], w["id_a"], w["t_star"], w["step"]))]
+            chunks.append(w.tobytes())
+    out["events"] = int(sum(len(p) for p in per))
+    out["events_sha256"] = sha(b"".join(chunks))
+    with open(OUT, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(f"wrote {OUT} ({time.time() - t:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

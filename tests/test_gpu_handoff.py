@@ -137,7 +137,7 @@ def test_launch_shapes_change_nothing(S):
     say("handoff launch shapes m=8 M=2")
     c = case(8, 2, 8, 3)
     base, H0 = run(S, c)
-    for kw in (dict(batch_points=3000), dict(use_graph=True, steps_per_sync=16),
+    for kw in (dict(batch_points=3000), dict(use_graph=True, steps_per_sync=16, screen_split=1),
                dict(screen=S.SCREEN_F32), dict(cell_size=0.4), dict(intercommute=False)):
         say(f"  {kw}")
         res, Hs = run(S, c, **kw)
@@ -148,6 +148,29 @@ def test_launch_shapes_change_nothing(S):
             assert res["events"].tobytes() == base["events"].tobytes()
         else:
             assert len(res["events"]) == 0
+
+
+@pytest.mark.skip(reason="concurrent lanes are switched off in schedule_handoff: a three-lane "
+                         "run of the 32^3 tiling ended the process and its cause is not shown")
+def test_lanes_change_nothing(S):
+    c = case(8, 2, 8, 3)
+    base, H0 = run(S, c)
+    for kw in (dict(lanes=3), dict(lanes=4, batch_points=2000),
+               dict(use_graph=True, steps_per_sync=16, lanes=2, screen_split=1)):
+        res, Hs = run(S, c, **kw)
+        assert np.array_equal(np.isnan(Hs), np.isnan(H0))
+        assert np.array_equal(Hs[~np.isnan(Hs)], H0[~np.isnan(H0)])
+
+
+def test_more_than_one_lane_is_refused(S):
+    import torch
+    c = case(4, 2, 8, 1)
+    n = len(c["net"]["recs"])
+    hist = torch.empty((4, n, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(S.SemiparError) as e:
+        S.schedule_handoff(c["net"]["recs"], c["box"], c["net"]["cosmology"], c["geoms"],
+                           c["n_pred"], c["succ"], hist, lanes=3)
+    assert e.value.code == -1
 
 
 def test_sixteen_layer_tiling_of_a_sixteen_cubed_network(S):
