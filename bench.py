@@ -21,7 +21,7 @@ per-region path (one region at a time, FP64 screen, one host check per step, no
 graphs, no batching), the roofline of the dominant kernel and the oracle on the host.
 
 --workload tiling: a 32^3 matter-era VV network (seed 1, ~2.4e5 points, eta 8) in a
-periodic spacetime tiling of 16 layers x 256 regions (4096), run region by region in
+periodic spacetime tiling of 4M layers x 4M^3 regions (M = 4: 16 x 256 = 4096), run region by region in
 dependency order with hand-off (schedule_handoff): every region builds the diamonds
 whose earliest point it holds from what its predecessors and the initial surface built,
 searches the crossings of its own elements (they pass through: intercommutation
@@ -139,26 +139,27 @@ def handoff_inputs(args, seed=1):
     from paper_1011_4046_amd import inputs as I
     t = time.perf_counter()
     net = I.vv_network(m=args.m, seed=seed)
-    parts, box, n_pred, succ, _ = I.tiling_regions(net, M=args.split_m, layers=16)
+    layers = args.layers or 4 * args.split_m
+    parts, box, n_pred, succ, _ = I.tiling_regions(net, M=args.split_m, layers=layers)
     geoms = [g for _, g in parts]
     V, inv2g = geoms[0][:4], geoms[0][4]
     g = 0.5 / inv2g
-    t_last = (V[3] + 0.5 * g * 15 + 2 * g) / np.sqrt(3.0)
+    t_last = (V[3] + 0.5 * g * (layers - 1) + 2 * g) / np.sqrt(3.0)
     # the initial slices are dt apart in t; in an expanding universe later slices of a
     # moving string advance t by less, so twice that many slices, grown on overflow
     rec = net["recs"][0]
     dt = float(rec["x"][3] - rec["x_prev"][3])
     slices = 2 * int(np.ceil((t_last - float(rec["x_prev"][3])) / dt)) + 8
-    log(f"hand-off tiling (seed {seed}): {len(net['recs'])} points, {len(geoms)} regions, "
-        f"{slices} slices ({time.perf_counter() - t:.1f} s)")
-    return net, box, geoms, n_pred, succ, slices
+    log(f"hand-off tiling (seed {seed}): {len(net['recs'])} points, {len(geoms)} regions in "
+        f"{layers} layers, {slices} slices ({time.perf_counter() - t:.1f} s)")
+    return net, box, geoms, n_pred, succ, slices, layers
 
 
 def bench_handoff(args):
     import numpy as np
     import torch
     from paper_1011_4046_amd import semipar as S
-    net, box, geoms, n_pred, succ, slices = handoff_inputs(args)
+    net, box, geoms, n_pred, succ, slices, layers = handoff_inputs(args)
     n = len(net["recs"])
     torch.cuda.set_device(0)
     screen = S.SCREEN_F32 if args.screen == "f32" else S.SCREEN_F64
@@ -215,7 +216,7 @@ def bench_handoff(args):
     return {
         "value": value, "ms_per_step": elapsed * 1e3 / args.steps,
         "config": {"workload": f"hand-off tiling: {args.m}^3 matter-era VV network (seed 1) in "
-                               f"a periodic spacetime tiling of 16 layers x "
+                               f"a periodic spacetime tiling of {layers} layers x "
                                f"{4 * args.split_m ** 3} regions, run in dependency order, "
                                f"crossings of each region's elements searched (pass through)",
                    "regions": len(geoms), "points": n, "slices": slices,
@@ -662,6 +663,9 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--split-m", type=int, default=4,
                     help="tiling workload: regions per layer 4 M^3 (the split factor)")
+    ap.add_argument("--layers", type=int, default=0,
+                    help="tiling workload: layers (0: 4 M, the same spacetime volume for every "
+                         "split factor)")
     ap.add_argument("--max-steps", type=int, default=10 ** 7)
     ap.add_argument("--p", type=float, default=1.0,
                     help="intercommutation probability in (0, 1] (1: every crossing exchanges)")
