@@ -32,11 +32,12 @@ def S():
     return semipar
 
 
-def case(m, M, layers, seed, cosmology=I.MATTER):
-    """The network, its tiling (geometry and dependency lists), the oracle's history and
-    the ownership of every diamond and element."""
+def case(m, M, layers, seed, cosmology=I.MATTER, lead=1.75):
+    """The network, its tiling (geometry and dependency lists; the initial slice `lead` g
+    above layer 0's past vertex), the oracle's history and the ownership of every diamond
+    and element."""
     net = I.vv_network(m=m, seed=seed, cosmology=cosmology)
-    parts, box, n_pred, succ, layer = I.tiling_regions(net, M=M, layers=layers)
+    parts, box, n_pred, succ, layer = I.tiling_regions(net, M=M, layers=layers, lead=lead)
     geoms = [g for _, g in parts]
     V, inv2g = geoms[0][:4], geoms[0][4]
     K = int(round(4 * box * inv2g))
@@ -115,14 +116,16 @@ def check_events(c, res):
     return total
 
 
-@pytest.mark.parametrize("m,M,layers,seed,cosmo", [
-    (4, 2, 8, 1, I.MATTER),
-    (8, 2, 8, 1, I.MATTER),
-    (8, 2, 8, 5, I.FLAT),
+@pytest.mark.parametrize("m,M,layers,seed,cosmo,lead", [
+    (4, 2, 8, 1, I.MATTER, 1.75),
+    (8, 2, 8, 1, I.MATTER, 1.75),
+    (8, 2, 8, 5, I.FLAT, 1.75),
+    (8, 2, 8, 4, I.RADIATION, 2.0),   # the initial slice through region vertices
+    (12, 3, 12, 6, I.MATTER, 1.3),
 ])
-def test_tiled_run_builds_the_whole_volume_world_sheet(S, m, M, layers, seed, cosmo):
-    say(f"handoff m={m} M={M} layers={layers} seed={seed} cosmology={cosmo}")
-    c = case(m, M, layers, seed, cosmo)
+def test_tiled_run_builds_the_whole_volume_world_sheet(S, m, M, layers, seed, cosmo, lead):
+    say(f"handoff m={m} M={M} layers={layers} seed={seed} cosmology={cosmo} lead={lead}")
+    c = case(m, M, layers, seed, cosmo, lead)
     res, Hs = run(S, c)
     check_world_sheet(c, res, Hs)
     n_ev = check_events(c, res)

@@ -172,3 +172,17 @@ def test_homes_never_run_backwards_and_are_the_regions_in_flat_space():
         for s in range(2, X.shape[0]):
             for src in (home[s - 1], home[s - 1][nxt], home[s - 2][nxt]):
                 assert np.all((home[s] == src) | (S[s] > (src >> 32)))
+
+
+def test_an_initial_slice_through_region_vertices_leaves_one_family_empty():
+    """Subsection "Initial conditions": of the four families of regions cut by the initial
+    time, one is trivial when the regions have vertices at that time. With the initial
+    slice 2 g above layer 0's past vertex, it passes through the future vertices of layer 0
+    and the past vertices of layer 4: the slice's vertices lie in layers 1..3 only."""
+    net = I.vv_network(m=8, seed=2)
+    for lead, layers_cut in ((1.75, {0, 1, 2, 3}), (2.0, {1, 2, 3})):
+        parts, box, n_pred, succ, layer = I.tiling_regions(net, M=2, layers=8, lead=lead)
+        V, inv2g = parts[0][1][:4], parts[0][1][4]
+        K = int(round(4 * box * inv2g))
+        S, _ = O.region_keys(V, inv2g, K, net["recs"]["x_prev"])
+        assert set(np.unique(S).tolist()) == layers_cut
