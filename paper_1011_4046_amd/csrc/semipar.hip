@@ -698,11 +698,14 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
             int ci[3];
             double lor[3], hir[3];
             if (local) {
-              // coordinates relative to the region's grid origin (minimum image)
+              // coordinates relative to the region's grid origin, in the periodic image
+              // nearest the grid's centre (a box of only twice the region's reach puts
+              // the far side of the grid more than half a box from its origin)
               const double o[3] = {C.ox, C.oy, C.oz};
+              const double half = 0.5 * (double)C.nc * C.h;
               for (int c = 0; c < 3; ++c) {
                 const double d = b.lo[c] - o[c];
-                const double sh = P.box * P.nearest(d);
+                const double sh = P.box * P.nearest(d - half);
                 const double dl = d - sh;
                 int q = (int)floor(dl * C.inv_h);
                 q = q < 0 ? 0 : (q > C.nc - 1 ? C.nc - 1 : q);
@@ -1754,10 +1757,11 @@ __global__ __launch_bounds__(NT) void k_screen_large(
       inv_h = C.inv_h;
       salt = C.salt;
       const double o[3] = {C.ox, C.oy, C.oz};
+      const double half = 0.5 * (double)nc * h;  // the image nearest the grid's centre
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double d = L.wl[c] - o[c];
-        lo[c] = d - P.box * P.nearest(d);
+        lo[c] = d - P.box * P.nearest(d - half);
       }
     } else {
 #pragma unroll
