@@ -43,15 +43,40 @@ class LearnedCost:
     """Cost model trained on logged (features, steps) pairs of earlier runs."""
 
     def __init__(self, seed=0):
+        self.seed = seed
         self.model = S.CostModel(init_params(seed))
         self.losses = None
+        self.val_losses = None
+        self.best_iter = None
 
-    def fit(self, feat, steps, iters=2000, lr=3e-3):
+    def fit(self, feat, steps, iters=2000, lr=3e-3, holdout=0.0, chunk=100):
+        """Train on log steps. holdout > 0: that share of the logged regions (seeded) is
+        kept out of training; every `chunk` iterations the loss on it is measured, and the
+        parameters with the lowest held-out loss are kept (early stopping)."""
         live = np.asarray(feat)[:, 0] > 0  # log1p(points) > 0: non-empty regions
         x = np.asarray(feat, np.float32)[live]
         y = np.log(np.maximum(np.asarray(steps, np.float64)[live], 1.0)).astype(np.float32)
-        self.model.set_norm_from(x)
-        self.losses = self.model.train(x, y, iters=iters, lr=lr)
+        n_val = int(round(holdout * len(x))) if holdout > 0 and len(x) >= 10 else 0
+        if n_val == 0:
+            self.model.set_norm_from(x)
+            self.losses = self.model.train(x, y, iters=iters, lr=lr)
+            return self
+        perm = np.random.default_rng(self.seed + 1).permutation(len(x))
+        va, tr = perm[:n_val], perm[n_val:]
+        self.model.set_norm_from(x[tr])
+        losses, vals = [], []
+        best, best_params, done = np.inf, None, 0
+        while done < iters:
+            k = min(chunk, iters - done)
+            losses.append(self.model.train(x[tr], y[tr], iters=k, lr=lr)[:k])
+            done += k
+            v = float(np.mean((self.model.forward(x[va]) - y[va]) ** 2))
+            vals.append(v)
+            if v < best:
+                best, best_params, self.best_iter = v, self.model.params.clone(), done
+        self.model.params.copy_(best_params)
+        self.losses = np.concatenate(losses)
+        self.val_losses = np.array(vals)
         return self
 
     def predict(self, feat):
