@@ -141,6 +141,7 @@ struct Ctrl {
   int32_t res_nlog, res_nacc, res_npass, res_iter, res_done;
   int32_t pb_step;    // persistent launch: the furthest slice any of its regions reached
   int64_t tok_n;      // hand-off batch: start tokens written (may exceed the buffer)
+  int32_t n_act;      // bounded region: entries of the list of advancing points
 };
 
 // The last three slices of every point, one 32-byte vertex (x, y, z, t) per point per
@@ -497,7 +498,8 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
                                                const int32_t* __restrict__ rid,
                                                const RCell* __restrict__ rcell,
                                                uint64_t* __restrict__ rext,
-                                               uint8_t* __restrict__ wlive, HistCfg hs) {
+                                               uint8_t* __restrict__ wlive, HistCfg hs,
+                                               const int32_t* __restrict__ act) {
   if (ctrl->done) return;
   const int s = ctrl->step;
   const Cells cs = ctrl->cells;
@@ -505,9 +507,12 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   const int ic = s % 3, ip = (s + 2) % 3, in = (s + 1) % 3;
   // grid-stride over the points in slot order (neighbouring lanes read neighbouring
   // slots, so the SoA loads stay coalesced), with the same trip count for every thread
-  // so that wave-wide operations stay uniform
+  // so that wave-wide operations stay uniform; a bounded region walks its list of the
+  // points that still advanced at the start of this block of steps (ascending slots)
+  const bool list = act != nullptr;
+  const int nn = list ? ctrl->n_act : n;
   const int span = gridDim.x * NT;
-  const int iters = (n + span - 1) / span;
+  const int iters = (nn + span - 1) / span;
   uint64_t tkey = KEY_MAX;
   uint64_t xkey = 0;
   uint32_t nadv = 0;
@@ -516,8 +521,9 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
   // a wave of 64 slots none of which still advances is skipped: its flag was cleared by
   // the step that stopped its last point, and stopped points never advance again
   const int wv = __builtin_amdgcn_readfirstlane(ii >> 6);
-  if (wv < nw && !wlive[wv]) continue;
-  const int k = ii < n ? ii : n;
+  if (!list && wv < nw && !wlive[wv]) continue;
+  if (list && ii - (ii & 63) >= nn) continue;  // (a whole wave past the list's end)
+  const int k = ii < nn ? (list ? act[ii] : ii) : n;
   uint64_t xk = 0;  // this point's element extent
   bool still = false;  // k advanced in this step (and so is still active)
   bool hashed = false;  // k's element goes to bucket hbk of the spatial hash
@@ -775,7 +781,7 @@ __global__ __launch_bounds__(NT) void k_evolve(Slices X, const int32_t* __restri
     }
   }
   xkey = xk > xkey ? xk : xkey;
-  {
+  if (!list) {
     const uint64_t any = __ballot(still);
     if ((threadIdx.x & 63) == 0 && wv < nw) wlive[wv] = any != 0ull ? 1 : 0;
   }
@@ -917,19 +923,25 @@ __global__ __launch_bounds__(NT) void k_scatter(int n, const int32_t* __restrict
                                                 const Ctrl* ctrl,
                                                 PencilAux* __restrict__ saux,
                                                 const int32_t* __restrict__ nxt,
-                                                const int32_t* __restrict__ prv) {
+                                                const int32_t* __restrict__ prv,
+                                                const int32_t* __restrict__ act) {
   if (ctrl->done) return;
   const int nc = ctrl->cells.nc;
   const Cells cs = ctrl->cells;
   const int nw = (n + 63) >> 6;
-  // the same trip count for every thread (wave-wide run detection below)
+  // the same trip count for every thread (wave-wide run detection below); a bounded
+  // region walks its list of advancing points, which holds every element of the step
+  const bool list = act != nullptr;
+  const int nn = list ? ctrl->n_act : n;
   const int span = gridDim.x * NT;
-  const int iters = (n + span - 1) / span;
+  const int iters = (nn + span - 1) / span;
   for (int it = 0; it < iters; ++it) {
-  const int k = it * span + blockIdx.x * NT + threadIdx.x;
+  const int ii = it * span + blockIdx.x * NT + threadIdx.x;
   // no point of a cleared wave advanced this step, so none has an element
-  const int wv = __builtin_amdgcn_readfirstlane(k >> 6);
-  if (wv >= nw || !wlive[wv]) continue;
+  const int wv = __builtin_amdgcn_readfirstlane(ii >> 6);
+  if (!list && (wv >= nw || !wlive[wv])) continue;
+  if (list && ii - (ii & 63) >= nn) continue;  // (a whole wave past the list's end)
+  const int k = ii < nn ? (list ? act[ii] : ii) : n;
   const int32_t c = k < n ? ecell[k] : -1;
   const bool has = c >= 0;
   const int x = c & 1023, y = (c >> 10) & 1023, z = (c >> 20) & 1023;
@@ -3369,6 +3381,69 @@ __device__ __forceinline__ semipar_point_rec current_record(const Slices& X, int
 }
 
 // Per block, the number of records of each of the 4 streams.
+// ---- the list of advancing points of a bounded region ----------------------------------
+// Rebuilt at the start of every block of steps (count per workgroup, scan, write), so that
+// the per-point kernels' waves hold only points that still advanced then; points that
+// stop inside the block stay listed and are passed over by their stop step.
+__global__ __launch_bounds__(NT) void k_act_count(int n, const int32_t* __restrict__ fstep,
+                                                  int32_t* __restrict__ blkcnt, const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const uint64_t m = __ballot(k < n && fstep[k] == FS_ACTIVE);
+  __shared__ int wc[NT / 64];
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < NT / 64; ++w) t += wc[w];
+    blkcnt[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of the per-workgroup counts in place (one workgroup); the total is the
+// list's length.
+__global__ __launch_bounds__(1024) void k_act_scan(int nblk, int32_t* __restrict__ blkcnt,
+                                                   Ctrl* ctrl) {
+  if (ctrl->done) return;
+  __shared__ int sc[1024];
+  const int t = threadIdx.x;
+  const int per = (nblk + 1023) / 1024;
+  const int b0 = t * per, b1 = b0 + per < nblk ? b0 + per : nblk;
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += blkcnt[b];
+  sc[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int add = t >= o ? sc[t - o] : 0;
+    __syncthreads();
+    sc[t] += add;
+    __syncthreads();
+  }
+  int run = sc[t] - sum;
+  for (int b = b0; b < b1; ++b) {
+    const int c = blkcnt[b];
+    blkcnt[b] = run;
+    run += c;
+  }
+  if (t == 1023) ctrl->n_act = sc[1023];
+}
+
+__global__ __launch_bounds__(NT) void k_act_write(int n, const int32_t* __restrict__ fstep,
+                                                  const int32_t* __restrict__ blkoff,
+                                                  int32_t* __restrict__ act, const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  const int k = blockIdx.x * NT + threadIdx.x;
+  const bool a = k < n && fstep[k] == FS_ACTIVE;
+  const uint64_t m = __ballot(a);
+  __shared__ int wc[NT / 64];
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  if (lane == 0) wc[w] = __popcll(m);
+  __syncthreads();
+  int base = blkoff[blockIdx.x];
+  for (int v = 0; v < w; ++v) base += wc[v];
+  if (a) act[base + __popcll(m & ((1ull << lane) - 1ull))] = k;
+}
+
 // ---- hand-off batch build ---------------------------------------------------------
 // Per local slot k of the batch: its volume slot's right neighbour, id and start state;
 // gmap takes the local slot of every volume slot in the batch (reset by k_hand_unmap).
@@ -4132,6 +4207,9 @@ struct semipar_region {
   // caller's; the per-point tables and the token buffer are the region's
   bool hist = false;
   HistCfg hcfg{};
+  // bounded region: the points still advancing at the start of each block of steps, in
+  // ascending slot order (the per-point kernels walk it), and its per-block counts
+  int32_t *act = nullptr, *actblk = nullptr;
   int32_t *hgsl = nullptr, *hgnx = nullptr, *hstart = nullptr;
   int64_t* hsname = nullptr;
   HandTok* htok = nullptr;
@@ -4332,7 +4410,7 @@ void launch_evolve_t(semipar_region* r, int n, int nb) {
   k_evolve<FRW, SCR, BND, HIST><<<nb, NT, 0, r->stream>>>(
       r->X, r->nxt, r->prv, r->id, n, r->P, r->hcoef, r->ctrl, r->hc, r->ebox, r->ecell,
       r->cnt, r->large, r->blkred, (BND || r->removed) ? r->fstep : nullptr, r->face, r->frz,
-      r->geom, r->geoms, r->rid, r->rcell, r->rext, r->wlive, r->hcfg);
+      r->geom, r->geoms, r->rid, r->rcell, r->rext, r->wlive, r->hcfg, r->act);
 }
 
 template <bool FRW, bool BND, bool HIST>
@@ -4403,6 +4481,16 @@ void launch_screen(semipar_region* r, int n, int nb) {
 
 // Issue one lattice step (all kernels) on the region's stream. i: index of the step in
 // its block (selects the timing-event pair when a kernel is timed).
+// Bounded region: rebuild the list of advancing points for the next block of steps.
+void issue_act(semipar_region* r) {
+  if (!r->act) return;
+  const int n = (int)r->n;
+  const int nb = blocks(n);
+  k_act_count<<<nb, NT, 0, r->stream>>>(n, r->fstep, r->actblk, r->ctrl);
+  k_act_scan<<<1, 1024, 0, r->stream>>>(nb, r->actblk, r->ctrl);
+  k_act_write<<<nb, NT, 0, r->stream>>>(n, r->fstep, r->actblk, r->act, r->ctrl);
+}
+
 void issue_step(semipar_region* r, bool intercommute, int i) {
   const int n = (int)r->n;
   const int nb = blocks(n);
@@ -4423,11 +4511,11 @@ void issue_step(semipar_region* r, bool intercommute, int i) {
     if (r->screen == 1)
       k_scatter<1><<<nbe, NT, 0, s>>>(n, r->ecell, r->cnt, r->loc, r->toff, r->ebox, r->sent,
                                       r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl, saux,
-                                      r->nxt, r->prv);
+                                      r->nxt, r->prv, r->act);
     else
       k_scatter<2><<<nbe, NT, 0, s>>>(n, r->ecell, r->cnt, r->loc, r->toff, r->ebox, r->sent,
                                       r->sbox, r->hc, r->rid, r->rcell, r->wlive, r->ctrl, saux,
-                                      r->nxt, r->prv);
+                                      r->nxt, r->prv, r->act);
     mark(r, SEMIPAR_K_SCATTER, 2 * i + 1);
     mark(r, SEMIPAR_K_SCREEN, 2 * i);
     launch_screen(r, n, nb);
@@ -4697,6 +4785,8 @@ void region_destroy(semipar_region* r) {
   dfree(r->lacc);
   dfree(r->llog);
   dfree(r->llog_rid);
+  dfree(r->act);
+  dfree(r->actblk);
   dfree(r->hgsl);
   dfree(r->hgnx);
   dfree(r->hstart);
@@ -4776,7 +4866,9 @@ int region_init_from_surfaces(const semipar_region_desc* d, const semipar_surfac
       dalloc(&r->blkred, 4 * (size_t)blocks(cap)) != hipSuccess ||
       dalloc(&r->fstep, cap) != hipSuccess || dalloc(&r->face, cap) != hipSuccess ||
       dalloc(&r->lev, cap) != hipSuccess || dalloc(&r->wlive, (cap + 63) / 64) != hipSuccess ||
-      (d->bounded && dalloc(&r->frz, cap) != hipSuccess))
+      (d->bounded && dalloc(&r->frz, cap) != hipSuccess) ||
+      (d->bounded && (dalloc(&r->act, cap) != hipSuccess ||
+                      dalloc(&r->actblk, (size_t)blocks(cap)) != hipSuccess)))
     return fail(oom(__LINE__));
   if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
     return fail(oom(__LINE__));
@@ -5028,6 +5120,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
         drop_graph(r);
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
+        issue_act(r);
         for (int i = 0; i < K; ++i) issue_step(r, ic, i);
         HIPCHK(hipStreamEndCapture(r->stream, &g));
         HIPCHK(hipGraphInstantiate(&r->gexec, g, nullptr, nullptr, 0));
@@ -5037,6 +5130,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
       }
       HIPCHK(hipGraphLaunch(r->gexec, r->stream));
     } else {
+      issue_act(r);
       for (int i = 0; i < K; ++i) issue_step(r, ic, i);
       HIPCHK(hipGetLastError());
     }
