@@ -3385,11 +3385,19 @@ __device__ __forceinline__ semipar_point_rec current_record(const Slices& X, int
 // Rebuilt at the start of every block of steps (count per workgroup, scan, write), so that
 // the per-point kernels' waves hold only points that still advanced then; points that
 // stop inside the block stay listed and are passed over by their stop step.
+// A hand-off batch (start != nullptr) lists only the points that start by the block's last
+// step (its step + horizon); later ones are listed by a later block.
+__device__ __forceinline__ bool act_listed(int k, int n, const int32_t* __restrict__ fstep,
+                                           const int32_t* __restrict__ start, int last) {
+  return k < n && fstep[k] == FS_ACTIVE && (!start || start[k] <= last);
+}
+
 __global__ __launch_bounds__(NT) void k_act_count(int n, const int32_t* __restrict__ fstep,
+                                                  const int32_t* __restrict__ start, int horizon,
                                                   int32_t* __restrict__ blkcnt, const Ctrl* ctrl) {
   if (ctrl->done) return;
   const int k = blockIdx.x * NT + threadIdx.x;
-  const uint64_t m = __ballot(k < n && fstep[k] == FS_ACTIVE);
+  const uint64_t m = __ballot(act_listed(k, n, fstep, start, ctrl->step + horizon));
   __shared__ int wc[NT / 64];
   if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(m);
   __syncthreads();
@@ -3429,11 +3437,12 @@ __global__ __launch_bounds__(1024) void k_act_scan(int nblk, int32_t* __restrict
 }
 
 __global__ __launch_bounds__(NT) void k_act_write(int n, const int32_t* __restrict__ fstep,
+                                                  const int32_t* __restrict__ start, int horizon,
                                                   const int32_t* __restrict__ blkoff,
                                                   int32_t* __restrict__ act, const Ctrl* ctrl) {
   if (ctrl->done) return;
   const int k = blockIdx.x * NT + threadIdx.x;
-  const bool a = k < n && fstep[k] == FS_ACTIVE;
+  const bool a = act_listed(k, n, fstep, start, ctrl->step + horizon);
   const uint64_t m = __ballot(a);
   __shared__ int wc[NT / 64];
   const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
@@ -4210,6 +4219,7 @@ struct semipar_region {
   // bounded region: the points still advancing at the start of each block of steps, in
   // ascending slot order (the per-point kernels walk it), and its per-block counts
   int32_t *act = nullptr, *actblk = nullptr;
+  int32_t act_last = INT32_MIN;  // eager blocks: the last step the current list covers
   int32_t *hgsl = nullptr, *hgnx = nullptr, *hstart = nullptr;
   int64_t* hsname = nullptr;
   HandTok* htok = nullptr;
@@ -4481,14 +4491,17 @@ void launch_screen(semipar_region* r, int n, int nb) {
 
 // Issue one lattice step (all kernels) on the region's stream. i: index of the step in
 // its block (selects the timing-event pair when a kernel is timed).
-// Bounded region: rebuild the list of advancing points for the next block of steps.
-void issue_act(semipar_region* r) {
+constexpr int ACT_EVERY = 32;  // eager blocks rebuild the list at most this often
+
+// Bounded region: rebuild the list of advancing points for the next K steps.
+void issue_act(semipar_region* r, int K) {
   if (!r->act) return;
   const int n = (int)r->n;
   const int nb = blocks(n);
-  k_act_count<<<nb, NT, 0, r->stream>>>(n, r->fstep, r->actblk, r->ctrl);
+  const int32_t* start = r->hist ? r->hstart : nullptr;
+  k_act_count<<<nb, NT, 0, r->stream>>>(n, r->fstep, start, K - 1, r->actblk, r->ctrl);
   k_act_scan<<<1, 1024, 0, r->stream>>>(nb, r->actblk, r->ctrl);
-  k_act_write<<<nb, NT, 0, r->stream>>>(n, r->fstep, r->actblk, r->act, r->ctrl);
+  k_act_write<<<nb, NT, 0, r->stream>>>(n, r->fstep, start, K - 1, r->actblk, r->act, r->ctrl);
 }
 
 void issue_step(semipar_region* r, bool intercommute, int i) {
@@ -5120,7 +5133,7 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
         drop_graph(r);
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
-        issue_act(r);
+        issue_act(r, K);
         for (int i = 0; i < K; ++i) issue_step(r, ic, i);
         HIPCHK(hipStreamEndCapture(r->stream, &g));
         HIPCHK(hipGraphInstantiate(&r->gexec, g, nullptr, nullptr, 0));
@@ -5129,8 +5142,16 @@ int region_evolve(semipar_region* r, const semipar_evolve_params* p, semipar_evo
         r->g_timed = r->timed;
       }
       HIPCHK(hipGraphLaunch(r->gexec, r->stream));
+      r->act_last = INT32_MIN;  // the graph rebuilds the list for its own block only
     } else {
-      issue_act(r);
+      // eager blocks rebuild the list only when this block runs past the steps it covers
+      // (at least ACT_EVERY of them), so that blocks of one step do not pay for it each step
+      const int32_t s = r->ctrl_h->step;
+      if (r->act && (int64_t)s + K - 1 > (int64_t)r->act_last) {
+        const int H = std::max(K, ACT_EVERY);
+        issue_act(r, H);
+        r->act_last = s + H - 1;
+      }
       for (int i = 0; i < K; ++i) issue_step(r, ic, i);
       HIPCHK(hipGetLastError());
     }
@@ -5519,7 +5540,8 @@ int handoff_batch(const HandoffShared& sh, int lane, const int32_t* slot, const 
       dalloc(&r->rcell, ns) != hipSuccess ||
       dalloc(&r->rext, (size_t)ns * REXT_STRIDE) != hipSuccess ||
       dalloc(&r->hgsl, cap) != hipSuccess || dalloc(&r->hgnx, cap) != hipSuccess ||
-      dalloc(&r->hstart, cap) != hipSuccess || dalloc(&r->hsname, ns) != hipSuccess)
+      dalloc(&r->hstart, cap) != hipSuccess || dalloc(&r->hsname, ns) != hipSuccess ||
+      dalloc(&r->act, cap) != hipSuccess || dalloc(&r->actblk, (size_t)blocks(cap)) != hipSuccess)
     return fail(oom(__LINE__));
   if (hipHostMalloc((void**)&r->ctrl_h, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
     return fail(oom(__LINE__));
