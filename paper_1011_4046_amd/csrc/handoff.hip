@@ -98,6 +98,13 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
     const double cf = p->evolve.cell_factor;
     if (!(cf == 0.0 || (cf >= 1.0 && cf <= 4.0))) return SEMIPAR_E_ARG;
   }
+  // One lane. Batches of one layer on concurrent lanes (host threads with streams of their
+  // own) are switched off: a run with three lanes ended the process, and the cause is not
+  // shown (region_destroy's device-wide hipFree on one lane while another lane captures
+  // a graph is the suspect; the batched scheduler releases its batches only at its end).
+  if (p->lanes > 1)
+    return fail_msg(SEMIPAR_E_ARG, "schedule_handoff: one lane only (lanes > 1 is switched off)");
+  const int lanes = 1;
   for (int r = 0; r < nr; ++r)
     if (h->n_pred[r] < 0 || h->succ_off[r + 1] < h->succ_off[r]) return SEMIPAR_E_ARG;
   if (h->succ_off[0] != 0) return SEMIPAR_E_ARG;
@@ -185,13 +192,6 @@ int schedule_handoff(const semipar_handoff* h, const semipar_sched_params* p,
   semipar_point_rec* d_rec = nullptr;
   if (D.alloc(&d_home, (size_t)h->hist_slices * (size_t)n) != hipSuccess)
     return fail_msg(SEMIPAR_E_OOM, "schedule_handoff: vertex homes");
-  // One lane. Batches of one layer on concurrent lanes (host threads with streams of their
-  // own) are switched off: a run with three lanes ended the process, and the cause is not
-  // shown (region_destroy's device-wide hipFree on one lane while another lane captures
-  // a graph is the suspect; the batched scheduler releases its batches only at its end).
-  if (p->lanes > 1)
-    return fail_msg(SEMIPAR_E_ARG, "schedule_handoff: one lane only (lanes > 1 is switched off)");
-  const int lanes = 1;
   if (D.alloc(&d_lut, lut.size()) != hipSuccess || D.alloc(&d_gnext, n) != hipSuccess ||
       D.alloc(&d_gprev, n) != hipSuccess || D.alloc(&d_gmap, (size_t)lanes * n) != hipSuccess ||
       D.alloc(&d_gid, n) != hipSuccess || D.alloc(&d_rec, n) != hipSuccess)
