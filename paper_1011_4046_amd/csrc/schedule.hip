@@ -25,6 +25,7 @@
 #include <cstring>
 #include <deque>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -148,12 +149,30 @@ struct DagDev {
   }
 };
 
+// A region's share of a list that a whole batch brought back from the device: the
+// batch's list stays as it came and each of its regions keeps where its part lies, so
+// that the entries are copied once, into the caller's list, when the schedule ends.
+template <class T>
+struct Part {
+  std::shared_ptr<const std::vector<T>> buf;
+  int64_t off = 0, n = 0;
+  const T* data() const { return buf ? buf->data() + off : nullptr; }
+  int64_t size() const { return n; }
+};
+
+template <class T>
+void share_out(std::vector<T>&& list, const std::vector<int64_t>& off,
+               const std::vector<int32_t>& regs, std::vector<Part<T>>& parts) {
+  auto buf = std::make_shared<const std::vector<T>>(std::move(list));
+  for (size_t i = 0; i < regs.size(); ++i) parts[regs[i]] = Part<T>{buf, off[i], off[i + 1] - off[i]};
+}
+
 struct Runner {
   const semipar_tiling* t;
   const semipar_sched_params* p;
   std::vector<Slab> slab;
-  std::vector<std::vector<semipar_event>> ev;  // per region
-  std::vector<std::vector<semipar_loop>> lp;   // per region
+  std::vector<Part<semipar_event>> ev;  // per region
+  std::vector<Part<semipar_loop>> lp;   // per region
   semipar_sched_stats acc{};
   int32_t batch_id = 0;
 
@@ -200,16 +219,18 @@ struct Runner {
       int64_t ne = 0;
       rc = region_events(reg, nullptr, 0, &ne);
       if (rc == SEMIPAR_OK) {
-        ev[r].resize((size_t)ne);
-        if (ne > 0) rc = region_events(reg, ev[r].data(), ne, &ne);
+        std::vector<semipar_event> e((size_t)ne);
+        if (ne > 0) rc = region_events(reg, e.data(), ne, &ne);
+        if (rc == SEMIPAR_OK) share_out(std::move(e), {0, ne}, {r}, ev);
       }
     }
     if (rc == SEMIPAR_OK && p->loops) {
       int64_t nl = 0;
       rc = region_loops(reg, nullptr, 0, &nl);
       if (rc == SEMIPAR_OK) {
-        lp[r].resize((size_t)nl);
-        if (nl > 0) rc = region_loops(reg, lp[r].data(), nl, &nl);
+        std::vector<semipar_loop> l((size_t)nl);
+        if (nl > 0) rc = region_loops(reg, l.data(), nl, &nl);
+        if (rc == SEMIPAR_OK) share_out(std::move(l), {0, nl}, {r}, lp);
       }
     }
     std::vector<int32_t> steps;
@@ -318,15 +339,13 @@ struct Runner {
       std::vector<semipar_event> e;
       std::vector<int64_t> off;
       rc = spi::batch_events(reg, e, off);
-      for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i)
-        ev[regs[i]].assign(e.begin() + off[i], e.begin() + off[i + 1]);
+      if (rc == SEMIPAR_OK) share_out(std::move(e), off, regs, ev);
     }
     if (rc == SEMIPAR_OK && p->loops) {
       std::vector<semipar_loop> l;
       std::vector<int64_t> off;
       rc = spi::batch_loops(reg, l, off);
-      for (size_t i = 0; i < regs.size() && rc == SEMIPAR_OK; ++i)
-        lp[regs[i]].assign(l.begin() + off[i], l.begin() + off[i + 1]);
+      if (rc == SEMIPAR_OK) share_out(std::move(l), off, regs, lp);
     }
     if (rc == SEMIPAR_OK) rc = spi::batch_stats(reg, b.steps, b.ps);
     return rc;
@@ -362,7 +381,7 @@ struct Runner {
     for (int r = 0; r < nr; ++r) {
       eoff[r] = ne;
       if (pp->events) pp->events_off[r] = ne;
-      ne += (int64_t)ev[r].size();
+      ne += ev[r].size();
     }
     eoff[nr] = ne;
     if (pp->events) {
@@ -394,7 +413,7 @@ struct Runner {
     acc.events = ne;
     int64_t nl = 0;
     for (int r = 0; r < nr; ++r) {
-      const int64_t m = (int64_t)lp[r].size();
+      const int64_t m = lp[r].size();
       if (pp->loops) {
         pp->loops_off[r] = nl;
         const int64_t fit = std::max<int64_t>(0, std::min(m, pp->loops_cap - nl));

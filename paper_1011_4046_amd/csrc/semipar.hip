@@ -1532,6 +1532,13 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
         if (e.x == key && m != nk && m != pk && box_overlap(me, b, sx, sy, sz, tl)) push(k, m);
       }
     };
+    // Cells one step up an axis (+x, +y, +z) hold entries whose low corner is at least
+    // one cell edge above this cell's origin, less the rounding of that corner (a few
+    // times the tolerance): an element whose high side plus the slack stays below the
+    // edge less a margin (1/256 of it plus eight tolerances, far above every rounding
+    // of these sums) cannot overlap any of them, and those cells are not read.
+    const T gate = hh - (hh * (T)0x1p-8 + (T)(8.0 * hc.tol));
+    const bool up[3] = {me.v[4] + tl >= gate, me.v[5] + tl >= gate, me.v[6] + tl >= gate};
     int rb[N_PENCIL], len[N_PENCIL], msk = 0;
 #pragma unroll
     for (int p = 0; p < N_PENCIL; ++p) {
@@ -1539,6 +1546,7 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
       len[p] = 0;
       const int dx = p < 2 ? 0 : 1;
       const int dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
+      if ((dx == 1 && !up[0]) || (dy == 1 && !up[1])) continue;
       int x = cx + dx, y = cy + dy;
       if (local) {
         if (x >= gnc || y < 0 || y >= gnc) continue;
@@ -1552,7 +1560,7 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
       for (int u = 0; u < 3; ++u) {
         const int dz = u - 1;
         int z = cz + dz;
-        bool v = !(p == 0 && dz < 0);
+        bool v = !(p == 0 && dz < 0) && (dz < 1 || up[2]);
         if (local) {
           v = v && z >= 0 && z < gnc;
         } else {
