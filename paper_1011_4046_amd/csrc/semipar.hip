@@ -1092,6 +1092,18 @@ __device__ __forceinline__ bool box_overlap(const SBox<T>& a, const SBox<T>& b, 
          b.v[1] + sy <= a.v[5] + tl && a.v[2] <= b.v[6] + sz + tl && b.v[2] + sz <= a.v[6] + tl;
 }
 
+// Which of the cells one step up an axis (+x, +y, +z) box a can reach. Such a cell holds
+// entries whose low corner is at least one cell edge hh above a's cell origin, less the
+// rounding of that corner (a few times the tolerance tol): when a's high side plus the
+// slack tl stays below the edge less a margin (1/256 of it plus eight tolerances, far
+// above every rounding of these sums), box_overlap fails for all of them.
+template <class T>
+__device__ __forceinline__ void reach_up(const SBox<T>& a, T hh, T tl, double tol, bool (&up)[3]) {
+  const T gate = hh - (hh * (T)0x1p-8 + (T)(8.0 * tol));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) up[i] = a.v[4 + i] + tl >= gate;
+}
+
 // The FP32 screen's sorted entries carry their cell key and slot in the fourth component
 // of the two float4 (lo.xyz, key) and (hi.xyz, slot), where the time range would be: one
 // 32-byte entry per element, read with two loads.
@@ -1273,6 +1285,8 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
       // Pencils whose buckets are not consecutive are scanned cell by cell right here.
       constexpr int NPT = (N_PENCIL + G - 1) / G;  // pencils per thread
       int rb[NPT], re[NPT], cen[NPT], msk[NPT];
+      bool up[3];  // cells one step up an axis that the element cannot reach are not read
+      reach_up(me, hh, tl, hc.tol, up);
 #pragma unroll
       for (int pi = 0; pi < NPT; ++pi) {
         const int p = g + pi * G;
@@ -1283,6 +1297,7 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
         if (p >= N_PENCIL) continue;
         const int dx = p == 0 ? 0 : (p == 1 ? 0 : 1);
         const int dy = p == 0 ? 0 : (p == 1 ? 1 : p - 3);
+        if ((dx == 1 && !up[0]) || (dy == 1 && !up[1])) continue;
         int x = cx + dx, y = cy + dy;
         if (local) {
           if (x >= gnc || y < 0 || y >= gnc) continue;
@@ -1298,7 +1313,7 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
         for (int u = 0; u < 3; ++u) {
           const int dz = u - 1;
           int z = cz + dz;
-          bool v = !(p == 0 && dz < 0);
+          bool v = !(p == 0 && dz < 0) && (dz < 1 || up[2]);
           if (local) {
             v = v && z >= 0 && z < gnc;
           } else {
@@ -1532,13 +1547,9 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
         if (e.x == key && m != nk && m != pk && box_overlap(me, b, sx, sy, sz, tl)) push(k, m);
       }
     };
-    // Cells one step up an axis (+x, +y, +z) hold entries whose low corner is at least
-    // one cell edge above this cell's origin, less the rounding of that corner (a few
-    // times the tolerance): an element whose high side plus the slack stays below the
-    // edge less a margin (1/256 of it plus eight tolerances, far above every rounding
-    // of these sums) cannot overlap any of them, and those cells are not read.
-    const T gate = hh - (hh * (T)0x1p-8 + (T)(8.0 * hc.tol));
-    const bool up[3] = {me.v[4] + tl >= gate, me.v[5] + tl >= gate, me.v[6] + tl >= gate};
+    // cells one step up an axis that the element cannot reach are not read
+    bool up[3];
+    reach_up(me, hh, tl, hc.tol, up);
     int rb[N_PENCIL], len[N_PENCIL], msk = 0;
 #pragma unroll
     for (int p = 0; p < N_PENCIL; ++p) {
