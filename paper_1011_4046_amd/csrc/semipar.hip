@@ -1416,12 +1416,14 @@ __global__ __launch_bounds__(NT, (SCR == 2 && G == 1) ? 5 : 1) void k_screen(int
     }
     if (g == 0 && nl > 0) {
       const int nk = nxt[k], pk = prv[k];
+      const int rk = rcell != nullptr ? rid[k] : 0;
       for (int a = 0; a < nl; ++a) {
         const LargeBox lb = large[a];
         const int m = lb.slot;
         if (m == k) continue;
         if (own_large && m < k) continue;
         if (m == nk || m == pk) continue;
+        if (rcell != nullptr && rid[m] != rk) continue;  // another sub-region of the batch
         const double tt = hc.tol_t;
         bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
 #pragma unroll
@@ -1714,12 +1716,14 @@ __global__ __launch_bounds__(NT, SCR == 2 ? 5 : 1) void k_screen_flat(
   // k_screen_large)
   if (own_large && nl > 0) {
     const int nk = nxt[k], pk = prv[k];
+    const int rk = local ? rid[k] : 0;
     for (int a = 0; a < nl; ++a) {
       const LargeBox lb = large[a];
       const int m = lb.slot;
       if (m == k) continue;
       if (own_large && m < k) continue;
       if (m == nk || m == pk) continue;
+      if (local && rid[m] != rk) continue;  // another sub-region of the batch
       const double tt = hc.tol_t;
       bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
 #pragma unroll
@@ -2033,12 +2037,14 @@ __global__ __launch_bounds__(NT, 5) void k_screen_pre(int n, const int2* __restr
       thi = own.thi;
     }
     if (nl > 0) {
+      const int rk = rcell != nullptr ? rid[k] : 0;
       for (int a = 0; a < nl; ++a) {
         const LargeBox lb = large[a];
         const int m = lb.slot;
         if (m == k) continue;
         if (own_large && m < k) continue;
         if (m == nk || m == pk) continue;
+        if (rcell != nullptr && rid[m] != rk) continue;  // another sub-region of the batch
         const double tt = hc.tol_t;
         bool ov = tlo <= lb.thi + tt && lb.tlo <= thi + tt;
 #pragma unroll
@@ -3514,16 +3520,36 @@ __global__ __launch_bounds__(NT) void k_hand_links(int n, const int32_t* __restr
     if (b >= 0 && (b >= n || rid[b] != rid[k])) b = -1;
     nxt[k] = a;
     prv[k] = b;
+    // element-size estimate (the first grids' cell edge follows it): the spatial box of
+    // the point's element of the band below its start slice, when both of that band's
+    // slices are built; else twice the distance to its neighbour on the start slice (an
+    // element also spans one step of motion: sized by the neighbour distance alone, most
+    // first elements would exceed the cells and take the large-element path)
     const int s = start[k];
     if (s - hs.s0 >= 0 && s - hs.s0 < hs.ns) {
       const V4 L = ldh(hs, s, g), R = ldh(hs, s, gnx[k]);
       if (L.t == L.t && R.t == R.t) {
-        double e = 0.0;
-        const double d[3] = {R.x - L.x, R.y - L.y, R.z - L.z};
-        for (int c = 0; c < 3; ++c) {
-          const double w = d[c] - P.box * P.nearest(d[c]);
-          e = fmax(e, fabs(w));
+        double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+        auto add = [&](const V4& V) {
+          const double d[3] = {V.x - L.x, V.y - L.y, V.z - L.z};
+          for (int c = 0; c < 3; ++c) {
+            const double w = d[c] - P.box * P.nearest(d[c]);
+            lo[c] = fmin(lo[c], w);
+            hi[c] = fmax(hi[c], w);
+          }
+        };
+        add(R);
+        bool below = false;
+        if (s - 1 - hs.s0 >= 0) {
+          const V4 B = ldh(hs, s - 1, g), Bj = ldh(hs, s - 1, gnx[k]);
+          if (B.t == B.t && Bj.t == Bj.t) {
+            add(B);
+            add(Bj);
+            below = true;
+          }
         }
+        double e = fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
+        if (!below) e *= 2.0;
         key = order_key(e);
       }
     }
