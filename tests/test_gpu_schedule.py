@@ -518,3 +518,43 @@ def test_links_between_regions_of_a_batch_are_cut(S):
         for r, (recs, geom_r) in enumerate(parts):
             want = C.features(recs, geom_r, box)
             assert np.allclose(f[r], want, rtol=1e-5, atol=1e-6), (device, r, f[r], want)
+
+
+def _twins(parts, shift=10 ** 9):
+    """Each region followed by its twin: the same geometry and positions, ids shifted."""
+    out = []
+    for recs, geom in parts:
+        twin = recs.copy()
+        for f in ("id", "next_id", "prev_id"):
+            twin[f] = np.where(recs[f] >= 0, recs[f] + shift, recs[f])
+        out += [(recs, geom), (twin, geom)]
+    return out
+
+
+def test_twin_regions_with_large_elements_do_not_meet_in_a_batch(S):
+    """Regions of one batch never pair elements of two regions, also on the screen's
+    path for elements larger than their cells (tested all against all): coarse strings
+    (one point per correlation length) in small regions, whose elements are larger than
+    a third of the local grid and so are all large, each batched with a twin at the
+    same place (same geometry and positions, other ids), so that every element of a
+    region overlaps its twin's copy. The regions are small (12-17 points, 10-23
+    point-steps each): each must end exactly as the oracle's run of it alone."""
+    say("case: twin coarse regions (size 1, 1 point per correlation length), one batch")
+    base, box = I.region_batch([300] * 4, size=1.0, seed=7, pts_per_xi=[1] * 4, slots=2)
+    parts = _twins(base)
+    assert sum(len(r) for r, _ in parts) >= 40
+    orc = oracle_regions(parts, box, "twins7")
+    rs = S.RegionSet.from_parts(parts, box, I.MATTER)
+    for policy in (S.SCHED_PLAIN, S.SCHED_BATCHED):
+        for screen in (S.SCREEN_F32, S.SCREEN_F64):
+            res = S.schedule_regions(rs, policy, batch_points=0, use_graph=True, screen=screen)
+            if policy == S.SCHED_BATCHED:
+                assert res["stats"]["batches"] == 1
+            check_against_oracle(res, parts, orc)
+            # a twin's events are its original's with the ids shifted
+            for r in range(0, len(parts), 2):
+                ea = res["events"][res["events_off"][r]:res["events_off"][r + 1]]
+                eb = res["events"][res["events_off"][r + 1]:res["events_off"][r + 2]]
+                assert len(ea) == len(eb)
+                assert np.array_equal(ea["id_a"] + 10 ** 9, eb["id_a"])
+                assert np.array_equal(ea["t_star"], eb["t_star"])
