@@ -531,23 +531,35 @@ def _twins(parts, shift=10 ** 9):
     return out
 
 
-def test_twin_regions_with_large_elements_do_not_meet_in_a_batch(S):
+@pytest.mark.parametrize("case", ["coarse", "tiny-cells"])
+def test_twin_regions_with_large_elements_do_not_meet_in_a_batch(S, case):
     """Regions of one batch never pair elements of two regions, also on the screen's
-    path for elements larger than their cells (tested all against all): coarse strings
-    (one point per correlation length) in small regions, whose elements are larger than
-    a third of the local grid and so are all large, each batched with a twin at the
-    same place (same geometry and positions, other ids), so that every element of a
-    region overlaps its twin's copy. The regions are small (12-17 points, 10-23
-    point-steps each): each must end exactly as the oracle's run of it alone."""
-    say("case: twin coarse regions (size 1, 1 point per correlation length), one batch")
-    base, box = I.region_batch([300] * 4, size=1.0, seed=7, pts_per_xi=[1] * 4, slots=2)
+    path for elements larger than their cells (tested all against all). Each region is
+    batched with a twin at the same place (same geometry and positions, other ids), so
+    that every element of a region overlaps its twin's copy; each must end exactly as
+    the oracle's run of it alone. coarse: strings of one point per correlation length in
+    small regions, whose elements exceed a third of the local grid and are all large
+    (12-17 points, 10-23 point-steps per region); tiny-cells: two regions of 1355 and
+    774 points with 24 and 4 crossings, under a fixed cell edge of 1e-3, which makes
+    every element large."""
+    if case == "coarse":
+        say("case: twin coarse regions (size 1, 1 point per correlation length), one batch")
+        base, box = I.region_batch([300] * 4, size=1.0, seed=7, pts_per_xi=[1] * 4, slots=2)
+        kw = {}
+    else:
+        say("case: twin regions (seed 33) with a fixed cell edge of 1e-3, one batch")
+        base, box = I.region_batch([1500, 800], seed=33, slots=2)
+        kw = dict(cell_size=1e-3)
     parts = _twins(base)
     assert sum(len(r) for r, _ in parts) >= 40
-    orc = oracle_regions(parts, box, "twins7")
+    orc = oracle_regions(parts, box, f"twins-{case}")
+    if case == "tiny-cells":
+        assert sum(len(o[1]) for o in orc) == 2 * (24 + 4)
     rs = S.RegionSet.from_parts(parts, box, I.MATTER)
     for policy in (S.SCHED_PLAIN, S.SCHED_BATCHED):
         for screen in (S.SCREEN_F32, S.SCREEN_F64):
-            res = S.schedule_regions(rs, policy, batch_points=0, use_graph=True, screen=screen)
+            res = S.schedule_regions(rs, policy, batch_points=0, use_graph=True, screen=screen,
+                                     **kw)
             if policy == S.SCHED_BATCHED:
                 assert res["stats"]["batches"] == 1
             check_against_oracle(res, parts, orc)
