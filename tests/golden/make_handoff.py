@@ -19,6 +19,10 @@ and q a record slot of the initial surface:
   events_sha256    per region in region order, the oracle's crossings whose two elements
                    belong to that region (both diamonds of each element built there),
                    each region's sorted by (step, t*, id_a, id_b).
+Counts (not compared by the tests): the whole-volume run's crossings whose two elements
+lie in the tiled volume (all four diamonds built by regions of the tiling), split into
+those of one region (the events above), those of two regions (each element within one),
+and those with an element whose two diamonds lie in two regions.
 
 Run from the repository root: python tests/golden/make_handoff.py
 """
@@ -95,6 +99,7 @@ def main():
     s0 = int(net["recs"]["step"][0])
     slot = {int(v): q for q, v in enumerate(ids)}
     per = [[] for _ in geoms]
+    n_two = n_split = 0
     for e in ev:
         i = int(e["step"]) + 2 - s0
         a, b = slot[int(e["id_a"])], slot[int(e["id_b"])]
@@ -102,6 +107,11 @@ def main():
         rb = own[i, b] if own[i, b] == own[i, nxt[b]] else -1
         if ra >= 0 and ra == rb:
             per[int(ra)].append(e)
+        elif min(own[i, a], own[i, nxt[a]], own[i, b], own[i, nxt[b]]) >= 0:
+            if ra >= 0 and rb >= 0:
+                n_two += 1
+            else:
+                n_split += 1
     chunks = []
     for r in range(len(geoms)):
         if per[r]:
@@ -110,6 +120,11 @@ def main():
             chunks.append(w.tobytes())
     out["events"] = int(sum(len(p) for p in per))
     out["events_sha256"] = sha(b"".join(chunks))
+    out["crossings_in_tiled_volume"] = out["events"] + n_two + n_split
+    out["crossings_two_regions"] = n_two
+    out["crossings_split_element"] = n_split
+    print(f"crossings in the tiled volume: {out['crossings_in_tiled_volume']}, of one region "
+          f"{out['events']}, of two regions {n_two}, with a split element {n_split}", flush=True)
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
